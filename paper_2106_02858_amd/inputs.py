@@ -1,0 +1,212 @@
+"""Seeded synthetic inputs for the CMCG Maxwell solver.
+
+This module only *generates problem data* -- meshes, material coefficients,
+source descriptions -- with numpy's PCG64 generator.  It contains none of the
+method's arithmetic (no DG operator, no time stepping, no CG), so both the
+HIP library and the CPU oracle may consume what it produces.
+
+Workloads (3-D stand-ins for the paper's 2-D experiments, Section 6):
+
+* ``cube_mesh(n)``: the unit cube split into n^3 cubes, each cut into the six
+  Kuhn tetrahedra (o, o+a e_p1, o+a(e_p1+e_p2), o+a(1,1,1)), one per
+  permutation p of the axes in lexicographic order.  Cube index
+  c = i + n (j + n k), x fastest; tet index = 6 c + permutation index.
+  The split is conforming under translation.
+* Face tags follow the library convention: local face f is opposite local
+  vertex f; tag 0 = interior, 1 = PEC, 2 = impedance (Silver-Mueller).
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+TAG_INTERIOR = 0
+TAG_PEC = 1
+TAG_IMPEDANCE = 2
+
+_PERMS = list(itertools.permutations(range(3)))  # lexicographic order
+
+
+def cube_mesh(n: int, boundary_tag: int = TAG_IMPEDANCE):
+    """Kuhn split of [0,1]^3 into 6 n^3 tetrahedra.
+
+    Returns (xyz [nv,3] float64, tet [K,4] int64, face_tag [K,4] int8).
+    """
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    nv1 = n + 1
+    ii, jj, kk = np.meshgrid(np.arange(nv1), np.arange(nv1), np.arange(nv1), indexing="ij")
+    # vertex index v = i + (n+1)(j + (n+1) k): x fastest
+    lat = np.stack([ii.transpose(2, 1, 0).ravel(), jj.transpose(2, 1, 0).ravel(),
+                    kk.transpose(2, 1, 0).ravel()], axis=1)
+    xyz = lat.astype(np.float64) / n
+
+    def vid(i, j, k):
+        return i + nv1 * (j + nv1 * k)
+
+    ci, cj, ck = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    ci = ci.transpose(2, 1, 0).ravel()
+    cj = cj.transpose(2, 1, 0).ravel()
+    ck = ck.transpose(2, 1, 0).ravel()
+    ncube = n ** 3
+    tet = np.empty((ncube, 6, 4), dtype=np.int64)
+    for p, perm in enumerate(_PERMS):
+        off = np.zeros((ncube, 3), dtype=np.int64)
+        corners = [off.copy()]
+        for ax in perm:
+            off = off.copy()
+            off[:, ax] += 1
+            corners.append(off)
+        for v in range(4):
+            tet[:, p, v] = vid(ci + corners[v][:, 0], cj + corners[v][:, 1], ck + corners[v][:, 2])
+    tet = tet.reshape(-1, 4)
+    tags = boundary_tags(lat, tet, n, boundary_tag)
+    return xyz, tet, tags
+
+
+def boundary_tags(lat: np.ndarray, tet: np.ndarray, n: int, boundary_tag: int) -> np.ndarray:
+    """Tag faces whose three vertices lie on one side of the cube's boundary."""
+    K = tet.shape[0]
+    tags = np.zeros((K, 4), dtype=np.int8)
+    for f in range(4):
+        others = [v for v in range(4) if v != f]
+        pts = lat[tet[:, others]]  # [K,3 verts,3 coords]
+        on = np.zeros(K, dtype=bool)
+        for ax in range(3):
+            c = pts[:, :, ax]
+            on |= np.all(c == 0, axis=1) | np.all(c == n, axis=1)
+        tags[on, f] = boundary_tag
+    return tags
+
+
+def tet_centroid_lattice4(lat_xyz_times_n: np.ndarray, tet: np.ndarray) -> np.ndarray:
+    """4 n * centroid as exact integers (sum of lattice coordinates)."""
+    return lat_xyz_times_n[tet].sum(axis=1)
+
+
+def gaussian_current(nodes: np.ndarray, centre, width: float, pol: int) -> np.ndarray:
+    """Nodal samples of j(x) = e_pol exp(-|x-centre|^2/width^2).
+
+    ``nodes`` is [K, Np, 3]; returns j_re [K, Np, 3] (j_im = 0).
+    """
+    d2 = np.sum((nodes - np.asarray(centre, dtype=np.float64)) ** 2, axis=-1)
+    j = np.zeros(nodes.shape, dtype=np.float64)
+    j[..., pol] = np.exp(-d2 / (width * width))
+    return j
+
+
+@dataclass
+class Workload:
+    """A seeded problem description (mesh + coefficients + source recipe)."""
+    name: str
+    n: int
+    q: int
+    omega: float
+    eps: np.ndarray          # [K]
+    mu: np.ndarray           # [K]
+    sigma: np.ndarray        # [K]
+    centre: np.ndarray       # [3]
+    width: float
+    pol: int
+    boundary_tag: int = TAG_IMPEDANCE
+    xyz: np.ndarray = field(default=None, repr=False)
+    tet: np.ndarray = field(default=None, repr=False)
+    tags: np.ndarray = field(default=None, repr=False)
+
+    @property
+    def K(self) -> int:
+        return self.tet.shape[0]
+
+
+def _mesh(n, boundary_tag):
+    return cube_mesh(n, boundary_tag)
+
+
+def plain_fp64(n: int = 6, q: int = 1, boundary_tag: int = TAG_IMPEDANCE) -> Workload:
+    """Unit cube, eps=mu=1, omega=2 pi, Gaussian e_z source width 0.1 at the centre.
+
+    n=6, q=1 is the 1296-tet plain FP64 configuration."""
+    xyz, tet, tags = _mesh(n, boundary_tag)
+    K = tet.shape[0]
+    return Workload("plain_fp64", n, q, 2 * math.pi, np.ones(K), np.ones(K), np.zeros(K),
+                    np.array([0.5, 0.5, 0.5]), 0.1, 2, boundary_tag, xyz, tet, tags)
+
+
+def large_single(n: int = 20, q: int = 3, seed: int = 2) -> Workload:
+    """eps per cube from {1,2,4} (seeded), omega = 4 pi, Gaussian width 0.05 at a
+    seeded point of [0.3,0.7]^3, e_z polarisation.  n=20, q=3 is the
+    48000-tet P3 FP32-vs-FP64 configuration."""
+    rng = np.random.default_rng(seed)
+    eps_cube = np.array([1.0, 2.0, 4.0])[rng.integers(0, 3, n ** 3)]
+    centre = rng.uniform(0.3, 0.7, 3)
+    xyz, tet, tags = _mesh(n, TAG_IMPEDANCE)
+    K = tet.shape[0]
+    eps = np.repeat(eps_cube, 6)
+    return Workload("large_single", n, q, 4 * math.pi, eps, np.ones(K), np.zeros(K),
+                    centre, 0.05, 2, TAG_IMPEDANCE, xyz, tet, tags)
+
+
+def batched_members(n: int = 12, q: int = 2, B: int = 64, seed: int = 3):
+    """Per-member (omega, centre, polarisation) for the batched configuration
+    (10368-tet P2 mesh at n=12, eps=mu=1, width 0.1)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(B):
+        omega = rng.uniform(2 * math.pi, 6 * math.pi)
+        centre = rng.uniform(0.2, 0.8, 3)
+        pol = int(rng.integers(0, 3))
+        out.append((omega, centre, pol))
+    xyz, tet, tags = _mesh(n, TAG_IMPEDANCE)
+    K = tet.shape[0]
+    members = [Workload(f"batched_{b}", n, q, om, np.ones(K), np.ones(K), np.zeros(K),
+                        c, 0.1, p, TAG_IMPEDANCE, xyz, tet, tags)
+               for b, (om, c, p) in enumerate(out)]
+    return members
+
+
+def serving_stream(n_requests: int = 2000, rate: float = 20.0, seed: int = 4,
+                   sizes=(8, 12, 16, 24), orders=(1, 2, 3)):
+    """Poisson arrival stream of request recipes (no meshes built here)."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    t = 0.0
+    for r in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        n = int(sizes[rng.integers(0, len(sizes))])
+        q = int(orders[rng.integers(0, len(orders))])
+        omega = rng.uniform(2 * math.pi, 8 * math.pi)
+        centre = rng.uniform(0.2, 0.8, 3)
+        pol = int(rng.integers(0, 3))
+        sub = int(rng.integers(0, 2 ** 31))
+        reqs.append(dict(id=r, arrival=t, n=n, q=q, omega=omega, centre=centre, pol=pol,
+                         width=0.1, subseed=sub))
+    return reqs
+
+
+def serving_request_workload(req) -> Workload:
+    rng = np.random.default_rng(req["subseed"])
+    n = req["n"]
+    eps_cube = np.array([1.0, 2.0, 4.0])[rng.integers(0, 3, n ** 3)]
+    xyz, tet, tags = _mesh(n, TAG_IMPEDANCE)
+    K = tet.shape[0]
+    return Workload(f"req_{req['id']}", n, req["q"], req["omega"], np.repeat(eps_cube, 6),
+                    np.ones(K), np.zeros(K), np.asarray(req["centre"]), req["width"],
+                    req["pol"], TAG_IMPEDANCE, xyz, tet, tags)
+
+
+def scatterer(n: int = 64, q: int = 2) -> Workload:
+    """Dielectric sphere eps=4 (radius 0.25 at the centre; a tet is inside when
+    its centroid is strictly inside), background eps=mu=1, omega = 8 pi,
+    Gaussian e_z source at (0.15,0.5,0.5) width 0.03."""
+    xyz, tet, tags = _mesh(n, TAG_IMPEDANCE)
+    lat = np.rint(xyz * n).astype(np.int64)
+    c4 = lat[tet].sum(axis=1)  # = 4 n centroid, exact
+    d = c4 - 2 * n  # 4n (centroid - 1/2)
+    inside = np.sum(d * d, axis=1) < (n * n)  # |4n(c-1/2)|^2 < (4n/4)^2
+    K = tet.shape[0]
+    eps = np.where(inside, 4.0, 1.0)
+    return Workload("scatterer", n, q, 8 * math.pi, eps, np.ones(K), np.zeros(K),
+                    np.array([0.15, 0.5, 0.5]), 0.03, 2, TAG_IMPEDANCE, xyz, tet, tags)
