@@ -1,0 +1,188 @@
+"""Benchmark: CMCG for time-harmonic Maxwell on one MI355X.
+
+Workload (default): unit cube 20^3 x 6 = 48000 tetrahedra, P3 (20 nodes), eps
+per cube from {1,2,4} (seed 2), mu = 1, omega = 4 pi, impedance boundary,
+Gaussian e_z current of width 0.05 at a seeded point of [0.3,0.7]^3.
+Fields are stepped in FP32 with the CG vectors, inner products, alpha/beta
+and the filter accumulator in FP64.
+
+One step = one complete CMCG solve from the zero guess (Algorithm 1, CG
+iterations until ||R||/||R0|| <= 1e-6, filter period), inputs resident in
+HBM.  value = DG dof-updates per second over the timed steps (6 Np K per
+time step, all periods).  Also reported: time-to-1e-6 of the FP32-field path
+and of the plain FP64 path on the same problem, the roofline of the dominant
+kernel (the fused RK4 stage kernel), and the FP64 CPU oracle on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=20)
+    ap.add_argument("--q", type=int, default=3)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 reference solve")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="RK steps of the CPU oracle sample")
+    ap.add_argument("--kernel-periods", type=int, default=3)
+    return ap.parse_args()
+
+
+def stage_bytes_per_element(q: int, esize: int) -> float:
+    """Algorithmic HBM bytes of one average RK4 stage launch per element:
+    16 field-vector passes per step (stage 1: 1 read + 2 writes; stages 2-3:
+    3 reads + 2 writes; stage 4: 2 reads + 1 write) -> 4 per launch, plus the
+    per-element geometry (40 values) and connectivity (4 int32)."""
+    Np = (q + 1) * (q + 2) * (q + 3) // 6
+    return 4 * 6 * Np * esize + 40 * esize + 16
+
+
+def cpu_baseline(w, steps: int):
+    """The FP64 oracle (as is) on a bounded sample: `steps` RK4 steps of the
+    full mesh without source, timed on the host cores."""
+    import numpy as np
+    import psutil
+
+    from oracle import dg, timestep
+    p = dg.make_problem(w.xyz, w.tet, w.tags, w.q, w.eps, w.mu, w.sigma, omega=w.omega)
+    M = timestep.n_steps(p)
+    dt = 2 * math.pi / w.omega / M
+    U = np.random.default_rng(0).standard_normal((p.K, 6, p.Np))
+    proc = psutil.Process()
+    c0 = proc.cpu_times()
+    t0 = time.perf_counter()
+    for m in range(steps):
+        U, _ = timestep.rk4_step(p, m * dt, U, dt, False) if w.q > 1 else timestep.rk2_step(p, m * dt, U, dt, False)
+    el = time.perf_counter() - t0
+    c1 = proc.cpu_times()
+    cores = (c1.user - c0.user + c1.system - c0.system) / el
+    ndof = p.K * 6 * p.Np
+    return {"value": ndof * steps / el, "unit": "dof-updates/s", "cores": round(cores, 2), "kind": "oracle",
+            "sample": f"{steps} RK{'4' if w.q > 1 else '2'} step(s) of the full {p.K}-tet P{w.q} mesh "
+                      f"({ndof} dofs), FP64 numpy oracle, {el:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2106_02858_amd import cmcg, inputs
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    w = inputs.large_single(n=a.n, q=a.q)
+    mesh = cmcg.cmcg_mesh_create(w.xyz, w.tet, w.tags)
+
+    def make(prec):
+        s = cmcg.cmcg_space_create(mesh, w.q, prec)
+        nodes = cmcg.cmcg_space_nodes(s)
+        j = inputs.gaussian_current(nodes, w.centre, w.width, w.pol)
+        jd = torch.tensor(j, dtype=torch.float64, device=dev)
+        p = cmcg.cmcg_problem_create_device(s, w.eps, w.mu, w.sigma, w.omega, jd)
+        return s, p
+
+    s32, p32 = make(cmcg.CMCG_FP32)
+    info = cmcg.cmcg_space_info(s32)
+    K, Np, ndof = info["K"], info["Np"], info["ndof"]
+    opts = cmcg.cmcg_options_default(tol=a.tol, max_iter=2000)
+    M, dt = cmcg.cmcg_problem_steps(p32, opts)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(a.warmup):
+        r = cmcg.cmcg_solve(p32, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dof_updates = 0.0
+    stats = []
+    for _ in range(a.steps):
+        r = cmcg.cmcg_solve(p32, opts)
+        st = cmcg.cmcg_result_stats(r)
+        stats.append(st)
+        dof_updates += st["dof_updates"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = dof_updates / elapsed
+
+    # dominant kernel: average stage-launch duration from HIP events around
+    # whole homogeneous periods (4 M stage launches each) on the same stream
+    U0 = torch.randn((K, 6, Np), dtype=torch.float64, device=dev) * 1e-3
+    UT = torch.empty_like(U0)
+    cmcg.cmcg_debug_period(p32, U0, UT, 1, False, opts=opts)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(a.kernel_periods):
+        cmcg.cmcg_debug_period(p32, U0, UT, 1, False, opts=opts)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    per_launch_s = ev0.elapsed_time(ev1) / 1e3 / (a.kernel_periods * 4 * M)
+    bpe = stage_bytes_per_element(w.q, 4)
+    achieved = bpe * K / per_launch_s / 1e9
+
+    out = {
+        "metric": "DG dof-updates/s; CMCG time-to-1e-6 residual vs FP64 plain; p50/p99 latency",
+        "value": value,
+        "unit": "dof-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": elapsed / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"unit cube {a.n}^3x6 = {K} tets, P{w.q}, eps per cube in {{1,2,4}} (seed 2), "
+                               f"mu=1, omega=4pi, impedance boundary, Gaussian e_z source width 0.05; "
+                               f"CMCG to rel. residual {a.tol:g} + filter period",
+                   "K": K, "q": w.q, "ndof": ndof, "steps_per_period": M, "fields": "fp32",
+                   "cg": "fp64"},
+        "cmcg": {"iters": stats[-1]["iters"], "periods": stats[-1]["periods"],
+                 "rel_res": stats[-1]["rel_res"], "seconds": stats[-1]["seconds"],
+                 "time_to_1e-6_fp32_s": stats[-1]["seconds_to_1e6"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_stage<float,{w.q}>", "avg_launch_us": per_launch_s * 1e6,
+                     "bytes_per_launch": bpe * K},
+    }
+    if not a.no_fp64:
+        s64, p64 = make(cmcg.CMCG_FP64)
+        r64 = cmcg.cmcg_solve(p64, opts)
+        st64 = cmcg.cmcg_result_stats(r64)
+        out["cmcg"]["time_to_1e-6_fp64_s"] = st64["seconds_to_1e6"]
+        out["cmcg"]["iters_fp64"] = st64["iters"]
+        # FP32-field result against the FP64 result (relative eps,mu norm via the library's inner product)
+        f32 = [torch.empty((K, 6, Np), dtype=torch.float64, device=dev) for _ in range(2)]
+        f64 = [torch.empty((K, 6, Np), dtype=torch.float64, device=dev) for _ in range(2)]
+        cmcg.cmcg_result_filtered_device(r, *f32)
+        cmcg.cmcg_result_filtered_device(r64, *f64)
+        d = [x - y for x, y in zip(f32, f64)]
+        num = sum(cmcg.cmcg_debug_dot(p64, x, x) for x in d)
+        den = sum(cmcg.cmcg_debug_dot(p64, x, x) for x in f64)
+        out["cmcg"]["fp32_vs_fp64_rel_l2"] = math.sqrt(num / den)
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

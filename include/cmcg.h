@@ -1,0 +1,221 @@
+/*
+ * cmcg.h -- C ABI of the MI355X (gfx950) controllability-CG solver for
+ * time-harmonic Maxwell's equations.
+ *
+ * Method (Chaumont-Frelet, Grote, Lanteri, Tang, "A controllability method
+ * for Maxwell's equations"):
+ *   Problem (Section 1, eq. (1.1)): find complex fields e, h with
+ *       i omega eps e + sigma e + curl h = j,   i omega mu h - curl e = 0,
+ *   e x n = 0 on the PEC boundary, an impedance (Silver-Mueller) condition
+ *   with data g on the rest.  The time-domain problem eq. (1.2) is driven by
+ *   Re(j e^{i omega t}); CMCG (Section 2.2, Algorithms 1-3) searches the
+ *   initial state U0 with P_psi U0 = U0 over one period T = 2 pi / omega by
+ *   conjugate gradients on J(U0) = 1/2 ||(I - P) U0 - G||^2_{eps,mu}, where
+ *   every gradient costs one forward and one backward (adjoint, P* = S P S)
+ *   period of an explicit upwind DG / Runge-Kutta scheme (Section 5.2-5.3),
+ *   and returns the filtered field F_psi U0 = (2/T) int_0^T U(t) e^{-i w t}
+ *   dt, computed on the fly during a last forward period (Section 5.4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Arrays are row-major and contiguous.  Indices are int64.
+ *  - Element map: x = v0 + xi1 (v1 - v0) + xi2 (v2 - v0) + xi3 (v3 - v0) on
+ *    the reference tetrahedron {xi >= 0, xi1 + xi2 + xi3 <= 1}; v0..v3 are
+ *    the element's vertices in the order given in tet[K][4].  Both
+ *    orientations are accepted.
+ *  - Local face f is opposite local vertex f.
+ *  - DG nodes of P_q (q = 1, 2, 3): xi = (i, j, k) / q with i + j + k <= q,
+ *    ordered with k slowest, then j, then i fastest.  Np = (q+1)(q+2)(q+3)/6
+ *    nodes per element, Nfp = (q+1)(q+2)/2 per face.  The nodes of face f are
+ *    the element nodes lying on it, in element node order.
+ *  - "Field" arrays at nodes: [K][Np][3] (x, y, z components).
+ *  - "Dof vectors" (debug entry points): [K][6][Np], components
+ *    (Ex, Ey, Ez, Hx, Hy, Hz) -- the library's internal layout.
+ *  - Time dependence e^{+i omega t}; field sign convention of eq. (1.2).
+ *  - Impedance faces use the dissipative Silver-Mueller condition
+ *    E x n - Z H_tau = G with Z = sqrt(mu/eps) of the adjacent element.
+ *
+ * Errors: every int-returning function returns CMCG_OK (0) on success,
+ * CMCG_NOT_CONVERGED (1) when a solve stopped at max_iter (its result is
+ * valid and flagged), or a negative CMCG_ERR_* code; cmcg_last_error()
+ * then describes the failure (thread-local).  No exception crosses the ABI.
+ * Handles are owned by the caller once returned and released with the
+ * matching *_destroy (NULL is accepted).  Input arrays are copied; the
+ * caller may free them after return.  A handle must not be used from two
+ * threads at once.
+ *
+ * Device: objects live on the HIP device that is current when they are
+ * created; later calls must be made with that device current.
+ */
+#ifndef CMCG_H
+#define CMCG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CMCG_OK = 0,
+    CMCG_NOT_CONVERGED = 1,
+    CMCG_ERR_ARG = -1,       /* invalid argument (NULL, size, range)          */
+    CMCG_ERR_MESH = -2,      /* degenerate / non-conforming / untagged mesh    */
+    CMCG_ERR_NOMEM = -3,     /* device memory exhausted or over budget         */
+    CMCG_ERR_DEVICE = -4,    /* a HIP runtime call failed                      */
+    CMCG_ERR_UNSTABLE = -5,  /* non-finite values appeared (step too large)    */
+    CMCG_ERR_BREAKDOWN = -6, /* CG breakdown: (D, A) <= 0 or not finite        */
+    CMCG_ERR_STATE = -7      /* call not valid in the object's current state   */
+};
+
+enum { CMCG_FP64 = 0, CMCG_FP32 = 1 };                   /* field precision  */
+enum { CMCG_TAG_INTERIOR = 0, CMCG_TAG_PEC = 1, CMCG_TAG_IMPEDANCE = 2 };
+enum { CMCG_SCHEME_AUTO = 0, CMCG_SCHEME_RK2 = 2, CMCG_SCHEME_RK4 = 4 };
+enum { CMCG_FLUX_UPWIND = 0, CMCG_FLUX_CENTRED = 1 };
+
+typedef struct cmcg_mesh cmcg_mesh;
+typedef struct cmcg_space cmcg_space;
+typedef struct cmcg_problem cmcg_problem;
+typedef struct cmcg_result cmcg_result;
+
+/* Solver options (Algorithm 3 and the time discretisation of Section 5.3). */
+typedef struct cmcg_options {
+    double tol;          /* stop when ||R_l|| <= tol ||R_0|| in the eps,mu norm */
+    int max_iter;        /* CG iteration cap (Algorithm 3's l_max)             */
+    int fixed_iters;     /* > 0: run exactly this many CG iterations, ignoring
+                            tol (parity testing at a fixed iteration count)     */
+    double cfl;          /* c_q of the CFL rule dt <= c_q min sqrt(mu eps) rho;
+                            <= 0 selects 0.20 / 0.16 / 0.12 for q = 1 / 2 / 3   */
+    int steps;           /* > 0: force M steps per period instead of the CFL M */
+    int scheme;          /* CMCG_SCHEME_*: AUTO = RK2 for q = 1, RK4 otherwise;
+                            RK2 pairs with the trapezoid filter, RK4 with the
+                            cubic-Hermite filter                                */
+    int flux;            /* CMCG_FLUX_UPWIND (the paper's) or _CENTRED (tests);
+                            impedance faces are always upwind                   */
+    int use_graph;       /* 1: replay each period from a captured hipGraph      */
+    int residual_refresh;/* > 0: every this many iterations replace R by the
+                            true gradient (costs two periods); 0 = never       */
+} cmcg_options;
+
+/* Fills *o with defaults: tol 1e-8, max_iter 1000, fixed_iters 0, cfl 0,
+ * steps 0, scheme AUTO, flux UPWIND, use_graph 1, residual_refresh 0. */
+void cmcg_options_default(cmcg_options* o);
+
+/* Solve statistics. */
+typedef struct cmcg_stats {
+    int iters;           /* CG iterations performed                            */
+    int periods;         /* periods simulated (2 per iteration + init + filter) */
+    int steps;           /* M, time steps per period                            */
+    int status;          /* CMCG_OK or CMCG_NOT_CONVERGED                       */
+    double dt;           /* T / M                                               */
+    double rel_res;      /* final ||R_l|| / ||R_0||                             */
+    double J0;           /* J(U0^(0)) = 1/2 ||G||^2 for a zero initial guess     */
+    double seconds;      /* wall time of the solve (inputs resident on device)  */
+    double seconds_to_1e6; /* wall time until ||R||/||R0|| <= 1e-6 (-1: never)  */
+    double dof_updates;  /* 6 Np K x steps executed over all periods            */
+} cmcg_stats;
+
+const char* cmcg_last_error(void);
+const char* cmcg_version(void);
+
+/* ---------------------------------------------------------------- mesh -- */
+/* Conforming tetrahedral mesh (Section 5.2: conforming simplicial mesh; each
+ * boundary face lies entirely on the PEC or the impedance part).
+ *   xyz[nv][3]   vertex coordinates
+ *   tet[K][4]    vertex indices (0-based)
+ *   face_tag     [K][4] (local face f opposite local vertex f): for boundary
+ *                faces CMCG_TAG_PEC or CMCG_TAG_IMPEDANCE; ignored on interior
+ *                faces.  NULL tags every boundary face impedance.
+ * Errors: CMCG_ERR_ARG (NULL, nv < 4, K < 1, index out of range),
+ * CMCG_ERR_MESH (zero volume, a face shared by more than two elements, an
+ * untagged boundary face). */
+int cmcg_mesh_create(int64_t nv, const double* xyz, int64_t K, const int64_t* tet,
+                     const int8_t* face_tag, cmcg_mesh** out);
+void cmcg_mesh_destroy(cmcg_mesh* m);
+int cmcg_mesh_info(const cmcg_mesh* m, int64_t* K, int64_t* n_boundary_faces,
+                   double* min_rho);
+
+/* --------------------------------------------------------------- space -- */
+/* Broken nodal space P_q(T_h)^6 on the mesh (Section 5.2), field precision
+ * CMCG_FP64 or CMCG_FP32 (time stepping in that precision; CG vectors,
+ * inner products, alpha/beta and the filter accumulator always FP64).
+ * Uploads geometry and connectivity to the current device.  The mesh may be
+ * destroyed afterwards. */
+int cmcg_space_create(const cmcg_mesh* m, int q, int precision, cmcg_space** out);
+void cmcg_space_destroy(cmcg_space* s);
+int cmcg_space_info(const cmcg_space* s, int* q, int* Np, int* Nfp, int64_t* K,
+                    int64_t* ndof);
+/* Physical coordinates of the DG nodes, xyz[K][Np][3] (host). */
+int cmcg_space_nodes(const cmcg_space* s, double* xyz);
+
+/* ------------------------------------------------------------- problem -- */
+/* Problem data (Section 1, eq. (1.1)):
+ *   eps[K], mu[K] > 0, sigma[K] >= 0 (NULL = 0): piecewise constant;
+ *   omega > 0;
+ *   j_re / j_im [K][Np][3]: nodal coefficients of j in the DG space (j_im
+ *   may be NULL = 0);
+ *   g_re / g_im [K][4][Nfp][3]: impedance boundary data at face nodes (read on
+ *   impedance faces only; NULL = 0).
+ * Host pointers.  The space may be destroyed afterwards. */
+int cmcg_problem_create(const cmcg_space* s, const double* eps, const double* mu,
+                        const double* sigma, double omega, const double* j_re,
+                        const double* j_im, const double* g_re, const double* g_im,
+                        cmcg_problem** out);
+/* Same, with j_re / j_im resident in device memory (ordered on `stream`). */
+int cmcg_problem_create_device(const cmcg_space* s, const double* eps, const double* mu,
+                               const double* sigma, double omega, const double* j_re_dev,
+                               const double* j_im_dev, hipStream_t stream,
+                               cmcg_problem** out);
+void cmcg_problem_destroy(cmcg_problem* p);
+/* Time steps per period M and dt = T / M that `o` selects for this problem
+ * (CFL rule of Section 5.3). */
+int cmcg_problem_steps(const cmcg_problem* p, const cmcg_options* o, int* M, double* dt);
+
+/* ---------------------------------------------------------------- solve -- */
+/* Algorithm 3 from the zero initial guess (or `u0_dev`, a device dof vector
+ * [K][6][Np] FP64, when not NULL), then the filter period.  Work is ordered
+ * on `stream` (NULL = the default stream); the call returns when the result
+ * is complete.  Returns CMCG_OK, CMCG_NOT_CONVERGED (result valid), or an
+ * error (no result). */
+int cmcg_solve(cmcg_problem* p, const cmcg_options* o, const double* u0_dev,
+               hipStream_t stream, cmcg_result** out);
+/* Filtered time-harmonic fields (complex amplitudes at the DG nodes),
+ * [K][Np][3] each, host pointers; any output may be NULL. */
+int cmcg_result_fields(const cmcg_result* r, double* e_re, double* e_im, double* h_re,
+                       double* h_im);
+/* Filtered field as device dof vectors [K][6][Np] FP64 (re, im). */
+int cmcg_result_filtered_device(const cmcg_result* r, double* f_re_dev, double* f_im_dev,
+                                hipStream_t stream);
+/* The periodic initial condition U0 reached by CG, device dof vector. */
+int cmcg_result_initial_device(const cmcg_result* r, double* u0_dev, hipStream_t stream);
+int cmcg_result_stats(const cmcg_result* r, cmcg_stats* st);
+/* ||R_l|| / ||R_0|| for l = 0..iters; copies min(cap, iters+1) values. */
+int cmcg_result_history(const cmcg_result* r, double* rel_res, int cap, int* n);
+void cmcg_result_destroy(cmcg_result* r);
+
+/* ---------------------------------------------------------- debug hooks -- */
+/* Per-kernel parity entry points.  Device dof vectors [K][6][Np] FP64 in and
+ * out (converted to / from the space's precision inside), ordered on
+ * `stream`, synchronous on return.
+ *
+ * cmcg_debug_rhs: out = Phi(t, U) = B U (+ Re(JJ e^{i omega t}) when
+ *   with_source), the semi-discrete right-hand side of Section 5.2.
+ * cmcg_debug_period: one period of M steps from U0 (Section 5.3): direction
+ *   +1 = forward P (P_psi when with_source), -1 = adjoint P* = S P S (never
+ *   with source).  f_re / f_im (may be NULL) receive the filtered field of
+ *   a forward period (trapezoid for RK2, Hermite for RK4).
+ * cmcg_debug_dot: (U, V)_{eps,mu} = V^T M U (Section 2.2), into *out (host),
+ *   with a fixed reduction order (bitwise reproducible). */
+int cmcg_debug_rhs(cmcg_problem* p, const cmcg_options* o, double t, int with_source,
+                   const double* u_dev, double* out_dev, hipStream_t stream);
+int cmcg_debug_period(cmcg_problem* p, const cmcg_options* o, int direction,
+                      int with_source, const double* u0_dev, double* ut_dev,
+                      double* f_re_dev, double* f_im_dev, hipStream_t stream);
+int cmcg_debug_dot(cmcg_problem* p, const double* u_dev, const double* v_dev, double* out,
+                   hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CMCG_H */

@@ -1,0 +1,306 @@
+"""Thin Python binding of libcmcg.so (include/cmcg.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Device arrays are torch tensors on the current HIP device (PyTorch supplies
+device memory and streams); host arrays are numpy arrays.  Functions keep the
+C names; the small classes only attach the matching *_destroy call to the
+handle's lifetime.  Importing this module fails loudly when the library has
+not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcmcg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2106_02858_amd.build`")
+
+_lib = C.CDLL(LIB_PATH)
+
+CMCG_OK = 0
+CMCG_NOT_CONVERGED = 1
+CMCG_ERR_ARG = -1
+CMCG_ERR_MESH = -2
+CMCG_ERR_NOMEM = -3
+CMCG_ERR_DEVICE = -4
+CMCG_ERR_UNSTABLE = -5
+CMCG_ERR_BREAKDOWN = -6
+CMCG_ERR_STATE = -7
+CMCG_FP64, CMCG_FP32 = 0, 1
+CMCG_TAG_INTERIOR, CMCG_TAG_PEC, CMCG_TAG_IMPEDANCE = 0, 1, 2
+CMCG_SCHEME_AUTO, CMCG_SCHEME_RK2, CMCG_SCHEME_RK4 = 0, 2, 4
+CMCG_FLUX_UPWIND, CMCG_FLUX_CENTRED = 0, 1
+
+EXPORTED = [
+    "cmcg_last_error", "cmcg_version", "cmcg_options_default",
+    "cmcg_mesh_create", "cmcg_mesh_destroy", "cmcg_mesh_info",
+    "cmcg_space_create", "cmcg_space_destroy", "cmcg_space_info", "cmcg_space_nodes",
+    "cmcg_problem_create", "cmcg_problem_create_device", "cmcg_problem_destroy", "cmcg_problem_steps",
+    "cmcg_solve", "cmcg_result_fields", "cmcg_result_filtered_device", "cmcg_result_initial_device",
+    "cmcg_result_stats", "cmcg_result_history", "cmcg_result_destroy",
+    "cmcg_debug_rhs", "cmcg_debug_period", "cmcg_debug_dot",
+]
+
+
+class cmcg_options(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("cfl", C.c_double),
+                ("steps", C.c_int), ("scheme", C.c_int), ("flux", C.c_int), ("use_graph", C.c_int),
+                ("residual_refresh", C.c_int)]
+
+
+class cmcg_stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("periods", C.c_int), ("steps", C.c_int), ("status", C.c_int),
+                ("dt", C.c_double), ("rel_res", C.c_double), ("J0", C.c_double), ("seconds", C.c_double),
+                ("seconds_to_1e6", C.c_double), ("dof_updates", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+P = C.c_void_p
+D = C.POINTER(C.c_double)
+_sig = {
+    "cmcg_last_error": (C.c_char_p, []),
+    "cmcg_version": (C.c_char_p, []),
+    "cmcg_options_default": (None, [C.POINTER(cmcg_options)]),
+    "cmcg_mesh_create": (C.c_int, [C.c_int64, P, C.c_int64, P, P, C.POINTER(P)]),
+    "cmcg_mesh_destroy": (None, [P]),
+    "cmcg_mesh_info": (C.c_int, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), D]),
+    "cmcg_space_create": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(P)]),
+    "cmcg_space_destroy": (None, [P]),
+    "cmcg_space_info": (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "cmcg_space_nodes": (C.c_int, [P, P]),
+    "cmcg_problem_create": (C.c_int, [P, P, P, P, C.c_double, P, P, P, P, C.POINTER(P)]),
+    "cmcg_problem_create_device": (C.c_int, [P, P, P, P, C.c_double, P, P, P, C.POINTER(P)]),
+    "cmcg_problem_destroy": (None, [P]),
+    "cmcg_problem_steps": (C.c_int, [P, C.POINTER(cmcg_options), C.POINTER(C.c_int), D]),
+    "cmcg_solve": (C.c_int, [P, C.POINTER(cmcg_options), P, P, C.POINTER(P)]),
+    "cmcg_result_fields": (C.c_int, [P, P, P, P, P]),
+    "cmcg_result_filtered_device": (C.c_int, [P, P, P, P]),
+    "cmcg_result_initial_device": (C.c_int, [P, P, P]),
+    "cmcg_result_stats": (C.c_int, [P, C.POINTER(cmcg_stats)]),
+    "cmcg_result_history": (C.c_int, [P, P, C.c_int, C.POINTER(C.c_int)]),
+    "cmcg_result_destroy": (None, [P]),
+    "cmcg_debug_rhs": (C.c_int, [P, C.POINTER(cmcg_options), C.c_double, C.c_int, P, P, P]),
+    "cmcg_debug_period": (C.c_int, [P, C.POINTER(cmcg_options), C.c_int, C.c_int, P, P, P, P, P]),
+    "cmcg_debug_dot": (C.c_int, [P, P, P, D, P]),
+}
+for _n, (_r, _a) in _sig.items():
+    _f = getattr(_lib, _n)
+    _f.restype = _r
+    _f.argtypes = _a
+
+
+class CmcgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"cmcg error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc, allow=(CMCG_OK,)):
+    if rc not in allow:
+        raise CmcgError(rc, _lib.cmcg_last_error().decode())
+    return rc
+
+
+def _ptr(a):
+    """Address of a contiguous numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags.c_contiguous
+        return a.ctypes.data
+    assert a.is_contiguous()
+    return a.data_ptr()
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def cmcg_version():
+    return _lib.cmcg_version().decode()
+
+
+def cmcg_last_error():
+    return _lib.cmcg_last_error().decode()
+
+
+def cmcg_options_default(**kw) -> cmcg_options:
+    o = cmcg_options()
+    _lib.cmcg_options_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class _Handle:
+    _destroy = None
+
+    def __init__(self, h, keep=()):
+        self.h = h
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "h", None) and self._destroy:
+            getattr(_lib, self._destroy)(self.h)
+            self.h = None
+
+
+class Mesh(_Handle):
+    _destroy = "cmcg_mesh_destroy"
+
+
+class Space(_Handle):
+    _destroy = "cmcg_space_destroy"
+
+    def info(self):
+        return cmcg_space_info(self)
+
+
+class Problem(_Handle):
+    _destroy = "cmcg_problem_destroy"
+
+
+class Result(_Handle):
+    _destroy = "cmcg_result_destroy"
+
+
+def cmcg_mesh_create(xyz, tet, face_tag=None) -> Mesh:
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tet = np.ascontiguousarray(tet, dtype=np.int64)
+    tags = None if face_tag is None else np.ascontiguousarray(face_tag, dtype=np.int8)
+    h = P()
+    _check(_lib.cmcg_mesh_create(xyz.shape[0], _ptr(xyz), tet.shape[0], _ptr(tet), _ptr(tags), C.byref(h)))
+    return Mesh(h)
+
+
+def cmcg_mesh_info(m: Mesh):
+    K, nb, rho = C.c_int64(), C.c_int64(), C.c_double()
+    _check(_lib.cmcg_mesh_info(m.h, C.byref(K), C.byref(nb), C.byref(rho)))
+    return dict(K=K.value, n_boundary=nb.value, min_rho=rho.value)
+
+
+def cmcg_space_create(m: Mesh, q: int, precision: int = CMCG_FP64) -> Space:
+    h = P()
+    _check(_lib.cmcg_space_create(m.h, q, precision, C.byref(h)))
+    return Space(h)
+
+
+def cmcg_space_info(s: Space):
+    q, Np, Nfp, K, nd = C.c_int(), C.c_int(), C.c_int(), C.c_int64(), C.c_int64()
+    _check(_lib.cmcg_space_info(s.h, C.byref(q), C.byref(Np), C.byref(Nfp), C.byref(K), C.byref(nd)))
+    return dict(q=q.value, Np=Np.value, Nfp=Nfp.value, K=K.value, ndof=nd.value)
+
+
+def cmcg_space_nodes(s: Space) -> np.ndarray:
+    i = cmcg_space_info(s)
+    out = np.empty((i["K"], i["Np"], 3))
+    _check(_lib.cmcg_space_nodes(s.h, _ptr(out)))
+    return out
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def cmcg_problem_create(s: Space, eps, mu, sigma=None, omega=2 * np.pi, j=None, g=None) -> Problem:
+    """j: complex [K,Np,3] nodal current density; g: complex [K,4,Nfp,3]."""
+    eps, mu, sigma = _f64(eps), _f64(mu), _f64(sigma)
+    jr = ji = gr = gi = None
+    if j is not None:
+        j = np.asarray(j)
+        jr = _f64(np.real(j))
+        ji = _f64(np.imag(j)) if np.iscomplexobj(j) else None
+    if g is not None:
+        g = np.asarray(g)
+        gr = _f64(np.real(g))
+        gi = _f64(np.imag(g)) if np.iscomplexobj(g) else None
+    h = P()
+    _check(_lib.cmcg_problem_create(s.h, _ptr(eps), _ptr(mu), _ptr(sigma), float(omega), _ptr(jr), _ptr(ji),
+                                    _ptr(gr), _ptr(gi), C.byref(h)))
+    return Problem(h, keep=(s,))
+
+
+def cmcg_problem_create_device(s: Space, eps, mu, sigma, omega, j_re_dev, j_im_dev=None, stream=None) -> Problem:
+    eps, mu, sigma = _f64(eps), _f64(mu), _f64(sigma)
+    h = P()
+    _check(_lib.cmcg_problem_create_device(s.h, _ptr(eps), _ptr(mu), _ptr(sigma), float(omega), _ptr(j_re_dev),
+                                           _ptr(j_im_dev), _stream(stream), C.byref(h)))
+    return Problem(h, keep=(s,))
+
+
+def cmcg_problem_steps(p: Problem, opts: cmcg_options | None = None):
+    o = opts or cmcg_options_default()
+    M, dt = C.c_int(), C.c_double()
+    _check(_lib.cmcg_problem_steps(p.h, C.byref(o), C.byref(M), C.byref(dt)))
+    return M.value, dt.value
+
+
+def cmcg_solve(p: Problem, opts: cmcg_options | None = None, u0_dev=None, stream=None) -> Result:
+    o = opts or cmcg_options_default()
+    h = P()
+    _check(_lib.cmcg_solve(p.h, C.byref(o), _ptr(u0_dev), _stream(stream), C.byref(h)),
+           allow=(CMCG_OK, CMCG_NOT_CONVERGED))
+    return Result(h, keep=(p,))
+
+
+def cmcg_result_fields(r: Result, K: int, Np: int):
+    out = [np.empty((K, Np, 3)) for _ in range(4)]
+    _check(_lib.cmcg_result_fields(r.h, *[_ptr(a) for a in out]))
+    e = out[0] + 1j * out[1]
+    h = out[2] + 1j * out[3]
+    return e, h
+
+
+def cmcg_result_filtered_device(r: Result, f_re, f_im, stream=None):
+    _check(_lib.cmcg_result_filtered_device(r.h, _ptr(f_re), _ptr(f_im), _stream(stream)))
+
+
+def cmcg_result_initial_device(r: Result, u0, stream=None):
+    _check(_lib.cmcg_result_initial_device(r.h, _ptr(u0), _stream(stream)))
+
+
+def cmcg_result_stats(r: Result) -> dict:
+    st = cmcg_stats()
+    _check(_lib.cmcg_result_stats(r.h, C.byref(st)))
+    return st.as_dict()
+
+
+def cmcg_result_history(r: Result) -> np.ndarray:
+    n = C.c_int()
+    _check(_lib.cmcg_result_history(r.h, None, 0, C.byref(n)))
+    out = np.empty(n.value)
+    _check(_lib.cmcg_result_history(r.h, _ptr(out), n.value, C.byref(n)))
+    return out
+
+
+def cmcg_debug_rhs(p: Problem, u_dev, out_dev, t: float = 0.0, with_source: bool = True,
+                   opts: cmcg_options | None = None, stream=None):
+    o = opts or cmcg_options_default()
+    _check(_lib.cmcg_debug_rhs(p.h, C.byref(o), float(t), int(with_source), _ptr(u_dev), _ptr(out_dev),
+                               _stream(stream)))
+
+
+def cmcg_debug_period(p: Problem, u0_dev, ut_dev, direction: int = 1, with_source: bool = False,
+                      f_re_dev=None, f_im_dev=None, opts: cmcg_options | None = None, stream=None):
+    o = opts or cmcg_options_default()
+    _check(_lib.cmcg_debug_period(p.h, C.byref(o), int(direction), int(with_source), _ptr(u0_dev), _ptr(ut_dev),
+                                  _ptr(f_re_dev), _ptr(f_im_dev), _stream(stream)))
+
+
+def cmcg_debug_dot(p: Problem, u_dev, v_dev, stream=None) -> float:
+    out = C.c_double()
+    _check(_lib.cmcg_debug_dot(p.h, _ptr(u_dev), _ptr(v_dev), C.byref(out), _stream(stream)))
+    return out.value

@@ -1,0 +1,70 @@
+// Kernel launch interface (kernels.hip) used by the host solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cmcg {
+
+// Stage kernel update modes (one Runge-Kutta stage of Section 5.3, fused with
+// the right-hand side Phi(t, Y) of Section 5.2):
+//   k = Phi(t_s, Y)
+//   RK2_S1: Ynext = U + cy k                      (U == Y)
+//   RK2_S2: U     = U + cu k
+//   RK4_S1: Ynext = U + cy k ; Acc = U + ca k     (U == Y)
+//   RK4_S2/S3: Ynext = U + cy k ; Acc += ca k
+//   RK4_S4: U     = Acc + cu k
+//   RHS:    Kout  = k
+// Optional filter accumulation (FP64): F += fa * U + fb * k (complex).
+enum StageMode { RK2_S1 = 0, RK2_S2, RK4_S1, RK4_S2, RK4_S3, RK4_S4, RHS };
+
+struct StageArgs {
+    const void* Y;      // stage input (Phi argument), [K][6][Np]
+    const void* U;      // base state
+    void* Ynext;
+    void* Acc;
+    void* Uout;
+    void* Kout;
+    const void* geo;    // [K][kGeo]
+    const int* conn;    // [K][4]: >= 0: nbr<<5 | nbr_face<<3 | perm; -1 PEC; -2 impedance
+    const void* Sre;    // source [K][6][Np] (nullable)
+    const void* Sim;
+    double* Fre;        // filter accumulators (nullable)
+    double* Fim;
+    int64_t K;
+    double cy, ca, cu;
+    double scos, ssin;  // Re(S e^{i w t}) = scos * Sre - ssin * Sim
+    int src_rows;       // 0 none, 3 E rows, 6 all rows
+    int mode;
+    double fa_re, fa_im, fb_re, fb_im;
+    int filter;
+};
+
+void upload_constants(int q, int precision, const double* D, const double* LIFT, const double* M,
+                      const int* fnode, const int* fperm);
+void launch_stage(int q, int precision, const StageArgs& a, hipStream_t s);
+
+// FP64 <-> field precision; flipH negates the magnetic rows (the S of P* = S P S).
+void launch_to_field(int precision, int Np, const double* X, void* U, int64_t n, int flipH,
+                     hipStream_t s);
+// Y = field(U) * (flipH ? S : I) - sub   (sub nullable)
+void launch_from_field(int precision, int Np, const void* U, double* Y, const double* sub,
+                       int64_t n, int flipH, hipStream_t s);
+void launch_copy_field(int precision, const void* src, void* dst, int64_t n, hipStream_t s);
+void launch_zero(void* p, size_t bytes, hipStream_t s);
+// z = a x + b y (FP64); y may alias z
+void launch_axpby(double a, const double* x, double b, const double* y, double* z, int64_t n,
+                  hipStream_t s);
+// F += w * field(U) (FP64 complex accumulation of a real field)
+void launch_filter_add(int precision, const void* U, double w_re, double w_im, double* Fre,
+                       double* Fim, int64_t n, hipStream_t s);
+// Deterministic M-weighted inner product (U, V)_{eps,mu}; result written to
+// out_dev[0] (device).  partial: scratch of dot_partials() doubles.
+int dot_partials();
+void launch_dot(int q, const double* U, const double* V, const double* wE, const double* wH,
+                int64_t K, double* partial, double* out_dev, hipStream_t s);
+// non-finite check: out_dev[0] = 1 if any entry of X is not finite
+void launch_nonfinite(const double* X, int64_t n, int* out_dev, hipStream_t s);
+
+}  // namespace cmcg

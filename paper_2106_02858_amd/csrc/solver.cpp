@@ -1,0 +1,955 @@
+// Host side of the CMCG Maxwell library: object lifetimes, the period driver
+// (Section 5.3 RK2 / RK4 over one period, hipGraph replay), the on-the-fly
+// filter weights (Section 5.4), the CMCG controller (Section 2.2, Algorithms
+// 1-3) and the extern "C" entry points declared in include/cmcg.h.
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "internal.h"
+#include "launch.h"
+
+namespace cmcg {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+std::shared_ptr<MeshData> build_mesh(int64_t nv, const double* xyz, int64_t K, const int64_t* tet,
+                                     const int8_t* face_tag);
+
+// ------------------------------------------------------------ device memory
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void alloc(size_t b) {
+        if (p && bytes == b) return;
+        release();
+        if (b == 0) return;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            fail(CMCG_ERR_NOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+        }
+        bytes = b;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T* as() const { return (T*)p; }
+};
+
+struct HostPinned {
+    double* p = nullptr;
+    HostPinned() {
+        if (hipHostMalloc((void**)&p, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(CMCG_ERR_NOMEM, "hipHostMalloc failed");
+        }
+    }
+    ~HostPinned() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
+// ----------------------------------------------------------- device constants
+namespace {
+std::mutex g_const_mu;
+bool g_const_done[64][kMaxQ + 1];
+}
+
+static void ensure_constants(int device, int q) {
+    std::lock_guard<std::mutex> lk(g_const_mu);
+    if (device < 0 || device >= 64) fail(CMCG_ERR_DEVICE, "device index out of range");
+    if (g_const_done[device][q]) return;
+    const RefElem& r = ref_elem(q);
+    upload_constants(q, 0, r.D.data(), r.LIFT.data(), r.M.data(), r.fnode.data(), r.fperm.data());
+    g_const_done[device][q] = true;
+}
+
+static int current_device() {
+    int d = 0;
+    CMCG_HIP(hipGetDevice(&d));
+    return d;
+}
+
+// ----------------------------------------------------------------- space
+struct SpaceData {
+    std::shared_ptr<MeshData> mesh;
+    int q = 1, Np = 4, Nfp = 3, precision = CMCG_FP64, device = 0;
+    int64_t K = 0, ndof = 0;
+    std::vector<int32_t> conn_h;
+    DevBuf conn;
+    size_t esize() const { return precision == CMCG_FP64 ? 8 : 4; }
+};
+
+}  // namespace cmcg
+
+struct cmcg_space {
+    std::shared_ptr<cmcg::SpaceData> d;
+};
+
+namespace cmcg {
+
+// time-stepping configuration of one solve
+struct StepCfg {
+    int M = 0;
+    int scheme = 2;
+    double dt = 0, T = 0;
+    double alpha = 1.0;  // flux parameter
+};
+
+// Hermite weights xi_ij = int_0^dt h_ij(s) e^{-i w s} ds by the power series
+// of the exponential (long double), h_ij the cubic Hermite basis on [0, dt].
+static void hermite_weights(double omega, double dt, std::complex<double> xi[4]) {
+    using LD = long double;
+    const LD th = (LD)omega * (LD)dt;
+    std::complex<LD> mu[4];
+    for (int k = 0; k < 4; ++k) {
+        std::complex<LD> s = 0, term = 1;  // (-i th)^n / n!
+        for (int n = 0; n < 60; ++n) {
+            s += term / (LD)(n + k + 1);
+            term *= std::complex<LD>(0, -th) / (LD)(n + 1);
+            if (std::abs(term) < 1e-40L) break;
+        }
+        mu[k] = s;
+    }
+    const LD h = dt;
+    xi[0] = std::complex<double>(h * (mu[0] - (LD)3 * mu[2] + (LD)2 * mu[3]));
+    xi[1] = std::complex<double>(h * ((LD)3 * mu[2] - (LD)2 * mu[3]));
+    xi[2] = std::complex<double>(h * h * (mu[1] - (LD)2 * mu[2] + mu[3]));
+    xi[3] = std::complex<double>(h * h * (mu[3] - mu[2]));
+}
+
+}  // namespace cmcg
+
+struct cmcg_problem {
+    std::shared_ptr<cmcg::SpaceData> sp;
+    double omega = 0;
+    std::vector<double> eps, mu, sigma;
+    bool has_j = false, has_g = false;
+    // device data
+    cmcg::DevBuf geo, wE, wH, Sre, Sim;
+    double geo_alpha = -1;
+    int src_rows = 0;
+    // work buffers
+    cmcg::DevBuf U, Y1, Y2, Acc, Fre, Fim, Kbuf;
+    cmcg::DevBuf v_u, v_r, v_d, v_a, v_w, v_gs, v_t;
+    cmcg::DevBuf partial, scal;
+    std::unique_ptr<cmcg::HostPinned> pinned;
+    hipStream_t cap_stream = nullptr;
+    std::map<int64_t, hipGraphExec_t> graphs;
+    ~cmcg_problem() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
+};
+
+struct cmcg_result {
+    std::shared_ptr<cmcg::SpaceData> sp;
+    cmcg::DevBuf Fre, Fim, U0;
+    cmcg_stats st{};
+    std::vector<double> history;
+};
+
+namespace cmcg {
+
+// ------------------------------------------------------------- problem setup
+static void build_geo(cmcg_problem* p, double alpha) {
+    const SpaceData& s = *p->sp;
+    const MeshData& m = *s.mesh;
+    const int64_t K = s.K;
+    std::vector<double> g(kGeo * K);
+    for (int64_t e = 0; e < K; ++e) {
+        double* o = &g[kGeo * e];
+        for (int i = 0; i < 9; ++i) o[i] = m.G[9 * e + i];
+        const double Zm = std::sqrt(p->mu[e] / p->eps[e]);
+        for (int f = 0; f < 4; ++f) {
+            double* q = o + 9 + 7 * f;
+            for (int k = 0; k < 3; ++k) q[k] = m.normal[12 * e + 3 * f + k];
+            const int64_t nb = m.nbr[4 * e + f];
+            const double Zp = nb >= 0 ? std::sqrt(p->mu[nb] / p->eps[nb]) : Zm;
+            const double Ym = 1.0 / Zm, Yp = 1.0 / Zp;
+            const double al = (nb < 0 && m.tag[4 * e + f] == CMCG_TAG_IMPEDANCE) ? 1.0 : alpha;
+            const double fs = m.area[4 * e + f] / m.vol[e];
+            q[3] = fs * al / (Zm + Zp);
+            q[4] = fs * Zp / (Zm + Zp);
+            q[5] = fs * al / (Ym + Yp);
+            q[6] = fs * Yp / (Ym + Yp);
+        }
+        o[37] = 1.0 / p->eps[e];
+        o[38] = 1.0 / p->mu[e];
+        o[39] = p->sigma[e] / p->eps[e];
+    }
+    p->geo.alloc(kGeo * K * s.esize());
+    if (s.precision == CMCG_FP64) {
+        CMCG_HIP(hipMemcpy(p->geo.p, g.data(), g.size() * 8, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> gf(g.begin(), g.end());
+        CMCG_HIP(hipMemcpy(p->geo.p, gf.data(), gf.size() * 4, hipMemcpyHostToDevice));
+    }
+    p->geo_alpha = alpha;
+}
+
+static void upload_field(const SpaceData& s, DevBuf& b, const std::vector<double>& v) {
+    b.alloc(v.size() * s.esize());
+    if (s.precision == CMCG_FP64) {
+        CMCG_HIP(hipMemcpy(b.p, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> f(v.begin(), v.end());
+        CMCG_HIP(hipMemcpy(b.p, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+    }
+}
+
+static cmcg_problem* make_problem(const cmcg_space* sh, const double* eps, const double* mu, const double* sigma,
+                                  double omega, const double* j_re, const double* j_im, const double* g_re,
+                                  const double* g_im) {
+    if (!sh || !sh->d) fail(CMCG_ERR_ARG, "problem: NULL space");
+    if (!eps || !mu) fail(CMCG_ERR_ARG, "problem: NULL eps or mu");
+    if (!(omega > 0) || !std::isfinite(omega)) fail(CMCG_ERR_ARG, "problem: omega must be positive");
+    auto sp = sh->d;
+    if (current_device() != sp->device) fail(CMCG_ERR_STATE, "problem: wrong current device");
+    const int64_t K = sp->K;
+    const int Np = sp->Np, Nfp = sp->Nfp;
+    std::unique_ptr<cmcg_problem> p(new cmcg_problem());
+    p->sp = sp;
+    p->omega = omega;
+    p->eps.assign(eps, eps + K);
+    p->mu.assign(mu, mu + K);
+    p->sigma.assign(K, 0.0);
+    if (sigma) p->sigma.assign(sigma, sigma + K);
+    for (int64_t e = 0; e < K; ++e) {
+        if (!(p->eps[e] > 0) || !(p->mu[e] > 0) || !std::isfinite(p->eps[e]) || !std::isfinite(p->mu[e]))
+            fail(CMCG_ERR_ARG, "problem: eps and mu must be positive and finite");
+        if (!(p->sigma[e] >= 0) || !std::isfinite(p->sigma[e]))
+            fail(CMCG_ERR_ARG, "problem: sigma must be non-negative and finite");
+    }
+    const MeshData& m = *sp->mesh;
+    // mass weights of the eps,mu inner product
+    std::vector<double> we(K), wh(K);
+    for (int64_t e = 0; e < K; ++e) {
+        we[e] = m.vol[e] * p->eps[e];
+        wh[e] = m.vol[e] * p->mu[e];
+    }
+    p->wE.alloc(K * 8);
+    p->wH.alloc(K * 8);
+    CMCG_HIP(hipMemcpy(p->wE.p, we.data(), K * 8, hipMemcpyHostToDevice));
+    CMCG_HIP(hipMemcpy(p->wH.p, wh.data(), K * 8, hipMemcpyHostToDevice));
+    // source vector S with Re(S e^{i w t}) = the forcing of Phi
+    p->has_j = j_re || j_im;
+    p->has_g = g_re || g_im;
+    if (p->has_j || p->has_g) {
+        std::vector<double> sr(sp->ndof, 0.0), si(sp->ndof, 0.0);
+        for (int64_t e = 0; e < K; ++e)
+            for (int c = 0; c < 3; ++c)
+                for (int i = 0; i < Np; ++i) {
+                    const int64_t src = (e * Np + i) * 3 + c;
+                    const int64_t dst = (e * 6 + c) * Np + i;
+                    if (j_re) sr[dst] = j_re[src] / p->eps[e];
+                    if (j_im) si[dst] = j_im[src] / p->eps[e];
+                }
+        if (p->has_g) {
+            // ghost E+ = n x G on impedance faces: flux_E = (n x G)/(2Z),
+            // flux_H = n x (n x G) / 2, lifted with the face scaling
+            const RefElem& r = ref_elem(sp->q);
+            for (int64_t e = 0; e < K; ++e) {
+                const double Z = std::sqrt(p->mu[e] / p->eps[e]);
+                for (int f = 0; f < 4; ++f) {
+                    if (m.nbr[4 * e + f] >= 0 || m.tag[4 * e + f] != CMCG_TAG_IMPEDANCE) continue;
+                    const double* n = &m.normal[12 * e + 3 * f];
+                    const double fs = m.area[4 * e + f] / m.vol[e];
+                    for (int k = 0; k < Nfp; ++k) {
+                        for (int part = 0; part < 2; ++part) {
+                            const double* gsrc = part == 0 ? g_re : g_im;
+                            if (!gsrc) continue;
+                            const double* G = &gsrc[((e * 4 + f) * Nfp + k) * 3];
+                            const double nG[3] = {n[1] * G[2] - n[2] * G[1], n[2] * G[0] - n[0] * G[2],
+                                                  n[0] * G[1] - n[1] * G[0]};
+                            const double nnG[3] = {n[1] * nG[2] - n[2] * nG[1], n[2] * nG[0] - n[0] * nG[2],
+                                                   n[0] * nG[1] - n[1] * nG[0]};
+                            std::vector<double>& S = part == 0 ? sr : si;
+                            for (int i = 0; i < Np; ++i) {
+                                const double L = r.LIFT[i * 4 * Nfp + f * Nfp + k] * fs;
+                                for (int c = 0; c < 3; ++c) {
+                                    S[(e * 6 + c) * Np + i] += L * nG[c] / (2 * Z) / p->eps[e];
+                                    S[(e * 6 + 3 + c) * Np + i] += L * nnG[c] / 2 / p->mu[e];
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        upload_field(*sp, p->Sre, sr);
+        upload_field(*sp, p->Sim, si);
+        p->src_rows = p->has_g ? 6 : 3;
+    }
+    build_geo(p.get(), 1.0);
+    p->pinned.reset(new HostPinned());
+    return p.release();
+}
+
+// -------------------------------------------------------------- time stepping
+static StepCfg step_config(const cmcg_problem* p, const cmcg_options* o) {
+    const SpaceData& s = *p->sp;
+    StepCfg c;
+    c.scheme = o->scheme == CMCG_SCHEME_AUTO ? (s.q == 1 ? 2 : 4) : o->scheme;
+    if (c.scheme != 2 && c.scheme != 4) fail(CMCG_ERR_ARG, "options: scheme must be AUTO, RK2 or RK4");
+    if (o->flux != CMCG_FLUX_UPWIND && o->flux != CMCG_FLUX_CENTRED) fail(CMCG_ERR_ARG, "options: bad flux");
+    c.alpha = o->flux == CMCG_FLUX_UPWIND ? 1.0 : 0.0;
+    c.T = 2.0 * M_PI / p->omega;
+    if (o->steps > 0) {
+        c.M = o->steps;
+    } else {
+        const double cq = o->cfl > 0 ? o->cfl : (s.q == 1 ? 0.20 : s.q == 2 ? 0.16 : 0.12);
+        const MeshData& m = *s.mesh;
+        double mn = HUGE_VAL;
+        for (int64_t e = 0; e < s.K; ++e) mn = std::fmin(mn, std::sqrt(p->mu[e] * p->eps[e]) * m.rho[e]);
+        const double dtmax = cq * mn;
+        long long M = (long long)std::ceil(c.T / dtmax);
+        if (M < 1) M = 1;
+        while (c.T / (double)M > dtmax) ++M;
+        while (M > 1 && c.T / (double)(M - 1) <= dtmax) --M;
+        if (M > 100000000LL) fail(CMCG_ERR_ARG, "options: more than 1e8 steps per period");
+        c.M = (int)M;
+    }
+    if (c.M < 3) fail(CMCG_ERR_ARG, "options: at least 3 steps per period are required");
+    c.dt = c.T / c.M;
+    return c;
+}
+
+static void ensure_work(cmcg_problem* p) {
+    const SpaceData& s = *p->sp;
+    const size_t fb = s.ndof * s.esize(), db = s.ndof * 8;
+    p->U.alloc(fb);
+    p->Y1.alloc(fb);
+    p->Y2.alloc(fb);
+    p->Acc.alloc(fb);
+    p->Fre.alloc(db);
+    p->Fim.alloc(db);
+    p->partial.alloc(dot_partials() * 8);
+    p->scal.alloc(64);
+}
+
+static StageArgs base_args(cmcg_problem* p) {
+    const SpaceData& s = *p->sp;
+    StageArgs a{};
+    a.geo = p->geo.p;
+    a.conn = s.conn.as<int>();
+    a.K = s.K;
+    a.Sre = p->Sre.p;
+    a.Sim = p->Sim.p;
+    a.Fre = p->Fre.as<double>();
+    a.Fim = p->Fim.as<double>();
+    return a;
+}
+
+// One period of M steps in place on p->U (field precision).  With `filt`,
+// F = (2/T) int U e^{-i w t} is accumulated into Fre / Fim (zeroed here).
+static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool filt, hipStream_t st) {
+    const SpaceData& s = *p->sp;
+    const int q = s.q, prec = s.precision;
+    const int M = c.M;
+    const double dt = c.dt;
+    const double two_pi = 2.0 * M_PI;
+    StageArgs a = base_args(p);
+    a.src_rows = (src && p->src_rows) ? p->src_rows : 0;
+    if (filt) {
+        launch_zero(p->Fre.p, p->Fre.bytes, st);
+        launch_zero(p->Fim.p, p->Fim.bytes, st);
+    }
+    std::complex<double> xi[4];
+    if (filt && c.scheme == 4) hermite_weights(p->omega, dt, xi);
+    const double twoT = 2.0 / c.T;
+    auto ph = [&](double m) { return std::complex<double>(std::cos(two_pi * m / M), -std::sin(two_pi * m / M)); };
+    auto set_src = [&](double mm) {
+        const double phase = two_pi * mm / M;
+        a.scos = std::cos(phase);
+        a.ssin = std::sin(phase);
+    };
+    for (int m = 0; m < M; ++m) {
+        a.filter = 0;
+        if (c.scheme == 2) {
+            // stage 1: k1 = Phi(t_m, U); Y1 = U + dt/2 k1
+            a.mode = RK2_S1;
+            a.Y = p->U.p;
+            a.U = p->U.p;
+            a.Ynext = p->Y1.p;
+            a.cy = 0.5 * dt;
+            set_src(m);
+            if (filt) {
+                // trapezoid: weight (1/M) e^{-i w t_m}, doubled for interior levels
+                std::complex<double> w = ph(m) * ((m == 0 ? 1.0 : 2.0) / M);
+                a.filter = 1;
+                a.fa_re = w.real();
+                a.fa_im = w.imag();
+                a.fb_re = a.fb_im = 0;
+            }
+            launch_stage(q, prec, a, st);
+            a.filter = 0;
+            // stage 2: k2 = Phi(t_m + dt/2, Y1); U += dt k2
+            a.mode = RK2_S2;
+            a.Y = p->Y1.p;
+            a.U = p->U.p;
+            a.Uout = p->U.p;
+            a.cu = dt;
+            set_src(m + 0.5);
+            launch_stage(q, prec, a, st);
+        } else {
+            a.mode = RK4_S1;
+            a.Y = p->U.p;
+            a.U = p->U.p;
+            a.Ynext = p->Y1.p;
+            a.Acc = p->Acc.p;
+            a.cy = 0.5 * dt;
+            a.ca = dt / 6.0;
+            set_src(m);
+            if (filt) {
+                // Hermite: U_m and Phi_m weights of the intervals [t_{m-1}, t_m], [t_m, t_{m+1}]
+                std::complex<double> wa = twoT * ph(m) * xi[0], wb = twoT * ph(m) * xi[2];
+                if (m >= 1) {
+                    wa += twoT * ph(m - 1) * xi[1];
+                    wb += twoT * ph(m - 1) * xi[3];
+                }
+                a.filter = 1;
+                a.fa_re = wa.real();
+                a.fa_im = wa.imag();
+                a.fb_re = wb.real();
+                a.fb_im = wb.imag();
+            }
+            launch_stage(q, prec, a, st);
+            a.filter = 0;
+            a.mode = RK4_S2;
+            a.Y = p->Y1.p;
+            a.Ynext = p->Y2.p;
+            a.cy = 0.5 * dt;
+            a.ca = dt / 3.0;
+            set_src(m + 0.5);
+            launch_stage(q, prec, a, st);
+            a.mode = RK4_S3;
+            a.Y = p->Y2.p;
+            a.Ynext = p->Y1.p;
+            a.cy = dt;
+            a.ca = dt / 3.0;
+            launch_stage(q, prec, a, st);
+            a.mode = RK4_S4;
+            a.Y = p->Y1.p;
+            a.Uout = p->U.p;
+            a.cu = dt / 6.0;
+            set_src(m + 1.0);
+            launch_stage(q, prec, a, st);
+        }
+    }
+    if (filt) {
+        if (c.scheme == 2) {
+            launch_filter_add(prec, p->U.p, 1.0 / M, 0.0, p->Fre.as<double>(), p->Fim.as<double>(), s.ndof, st);
+        } else {
+            // last level: Phi(t_M, U_M) and the weights of [t_{M-1}, t_M]
+            p->Kbuf.alloc(s.ndof * s.esize());
+            std::complex<double> wa = twoT * ph(M - 1) * xi[1], wb = twoT * ph(M - 1) * xi[3];
+            a.mode = RHS;
+            a.Y = p->U.p;
+            a.U = p->U.p;
+            a.Kout = p->Kbuf.p;
+            set_src(M);
+            a.filter = 1;
+            a.fa_re = wa.real();
+            a.fa_im = wa.imag();
+            a.fb_re = wb.real();
+            a.fb_im = wb.imag();
+            launch_stage(q, prec, a, st);
+        }
+    }
+}
+
+static void run_period(cmcg_problem* p, const StepCfg& c, bool src, bool filt, bool use_graph, hipStream_t st) {
+    if (!use_graph) {
+        enqueue_period(p, c, src, filt, st);
+        return;
+    }
+    const int64_t key = ((int64_t)c.M << 8) | (c.scheme << 4) | (src ? 2 : 0) | (filt ? 1 : 0);
+    auto it = p->graphs.find(key);
+    if (it == p->graphs.end()) {
+        if (!p->cap_stream) CMCG_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+        if (filt && c.scheme == 4) p->Kbuf.alloc(p->sp->ndof * p->sp->esize());
+        CMCG_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue_period(p, c, src, filt, p->cap_stream);
+        } catch (...) {
+            hipGraph_t g;
+            (void)hipStreamEndCapture(p->cap_stream, &g);
+            throw;
+        }
+        hipGraph_t g;
+        CMCG_HIP(hipStreamEndCapture(p->cap_stream, &g));
+        hipGraphExec_t ge;
+        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) fail(CMCG_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        it = p->graphs.emplace(key, ge).first;
+    }
+    CMCG_HIP(hipGraphLaunch(it->second, st));
+}
+
+// X (FP64 dof vector) -> propagate one period -> Y = S^d P S^d X - sub
+static void apply_period(cmcg_problem* p, const StepCfg& c, const cmcg_options* o, const double* X, double* Yo,
+                         const double* sub, int direction, bool src, bool filt, hipStream_t st) {
+    const SpaceData& s = *p->sp;
+    const int flip = direction < 0 ? 1 : 0;
+    if (X)
+        launch_to_field(s.precision, s.Np, X, p->U.p, s.ndof, flip, st);
+    else
+        launch_zero(p->U.p, p->U.bytes, st);
+    run_period(p, c, src && direction > 0, filt, o->use_graph != 0, st);
+    if (Yo) launch_from_field(s.precision, s.Np, p->U.p, Yo, sub, s.ndof, flip, st);
+}
+
+static double dot(cmcg_problem* p, const double* U, const double* V, hipStream_t st) {
+    const SpaceData& s = *p->sp;
+    launch_dot(s.q, U, V, p->wE.as<double>(), p->wH.as<double>(), s.K, p->partial.as<double>(), p->scal.as<double>(),
+               st);
+    CMCG_HIP(hipMemcpyAsync(p->pinned->p, p->scal.p, 8, hipMemcpyDeviceToHost, st));
+    CMCG_HIP(hipStreamSynchronize(st));
+    return p->pinned->p[0];
+}
+
+static void prepare(cmcg_problem* p, const StepCfg& c) {
+    if (current_device() != p->sp->device) fail(CMCG_ERR_STATE, "wrong current device");
+    ensure_constants(p->sp->device, p->sp->q);
+    if (p->geo_alpha != c.alpha) {
+        build_geo(p, c.alpha);
+        for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+        p->graphs.clear();
+    }
+    ensure_work(p);
+}
+
+static cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st) {
+    const StepCfg c = step_config(p, o);
+    prepare(p, c);
+    const SpaceData& s = *p->sp;
+    const int64_t n = s.ndof;
+    const size_t db = n * 8;
+    p->v_u.alloc(db);
+    p->v_r.alloc(db);
+    p->v_d.alloc(db);
+    p->v_a.alloc(db);
+    p->v_w.alloc(db);
+    p->v_gs.alloc(db);
+    double *U = p->v_u.as<double>(), *R = p->v_r.as<double>(), *D = p->v_d.as<double>(), *A = p->v_a.as<double>(),
+           *W = p->v_w.as<double>(), *Gs = p->v_gs.as<double>();
+    std::unique_ptr<cmcg_result> res(new cmcg_result());
+    res->sp = p->sp;
+    CMCG_HIP(hipStreamSynchronize(st));
+    const auto t0 = std::chrono::steady_clock::now();
+    auto secs = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+    int periods = 0;
+    // Algorithm 1: G = P_psi 0 (into W), G_T = P* G, G* = G - G_T
+    apply_period(p, c, o, nullptr, W, nullptr, +1, true, false, st);
+    apply_period(p, c, o, W, Gs, W, -1, false, false, st);  // Gs = P* G - G = -G*
+    launch_axpby(-1.0, Gs, 0.0, Gs, Gs, n, st);             // G* = G - P* G
+    periods += 2;
+    const double J0 = 0.5 * dot(p, W, W, st);
+    if (!std::isfinite(J0)) fail(CMCG_ERR_UNSTABLE, "solve: non-finite field after the first period");
+    auto gradient = [&](double* out) {
+        // Algorithm 2: W_T = P U - U, W_0 = P* W_T, J' = W_0 - W_T - G*
+        apply_period(p, c, o, U, W, U, +1, false, false, st);
+        apply_period(p, c, o, W, out, W, -1, false, false, st);
+        launch_axpby(1.0, out, -1.0, Gs, out, n, st);
+        periods += 2;
+    };
+    if (u0) {
+        CMCG_HIP(hipMemcpyAsync(U, u0, db, hipMemcpyDeviceToDevice, st));
+        gradient(R);
+    } else {
+        launch_zero(U, db, st);
+        launch_axpby(-1.0, Gs, 0.0, Gs, R, n, st);  // R0 = -G*
+    }
+    CMCG_HIP(hipMemcpyAsync(D, R, db, hipMemcpyDeviceToDevice, st));
+    double rr = dot(p, R, R, st);
+    const double rr0 = rr;
+    if (!std::isfinite(rr)) fail(CMCG_ERR_UNSTABLE, "solve: non-finite initial residual");
+    res->history.push_back(1.0);
+    double t6 = -1.0;
+    int it = 0;
+    const bool fixed = o->fixed_iters > 0;
+    const int limit = fixed ? o->fixed_iters : o->max_iter;
+    double rel = 1.0;
+    if (rr0 == 0.0) rel = 0.0;
+    while (it < limit) {
+        rel = rr0 > 0 ? std::sqrt(rr / rr0) : 0.0;
+        if (t6 < 0 && rel <= 1e-6) t6 = secs();
+        if (!fixed && rel <= o->tol) break;
+        if (rr0 == 0.0) break;
+        // A = (I - P*)(I - P) D = W_0 - W_T
+        apply_period(p, c, o, D, W, D, +1, false, false, st);
+        apply_period(p, c, o, W, A, W, -1, false, false, st);
+        periods += 2;
+        const double dA = dot(p, D, A, st);
+        if (!std::isfinite(dA)) fail(CMCG_ERR_UNSTABLE, "solve: non-finite values (time step too large?)");
+        if (!(dA > 0)) fail(CMCG_ERR_BREAKDOWN, "solve: CG breakdown, (D, A) <= 0");
+        const double alpha = rr / dA;
+        launch_axpby(-alpha, D, 1.0, U, U, n, st);
+        launch_axpby(-alpha, A, 1.0, R, R, n, st);
+        ++it;
+        if (o->residual_refresh > 0 && it % o->residual_refresh == 0) gradient(R);
+        const double rn = dot(p, R, R, st);
+        if (!std::isfinite(rn)) fail(CMCG_ERR_UNSTABLE, "solve: non-finite residual");
+        const double beta = rn / rr;
+        launch_axpby(1.0, R, beta, D, D, n, st);
+        rr = rn;
+        rel = rr0 > 0 ? std::sqrt(rr / rr0) : 0.0;
+        res->history.push_back(rel);
+    }
+    if (t6 < 0 && rel <= 1e-6) t6 = secs();
+    // final period with source and filter
+    apply_period(p, c, o, U, nullptr, nullptr, +1, true, true, st);
+    periods += 1;
+    res->Fre.alloc(db);
+    res->Fim.alloc(db);
+    res->U0.alloc(db);
+    CMCG_HIP(hipMemcpyAsync(res->Fre.p, p->Fre.p, db, hipMemcpyDeviceToDevice, st));
+    CMCG_HIP(hipMemcpyAsync(res->Fim.p, p->Fim.p, db, hipMemcpyDeviceToDevice, st));
+    CMCG_HIP(hipMemcpyAsync(res->U0.p, U, db, hipMemcpyDeviceToDevice, st));
+    CMCG_HIP(hipStreamSynchronize(st));
+    cmcg_stats& S = res->st;
+    S.iters = it;
+    S.periods = periods;
+    S.steps = c.M;
+    S.dt = c.dt;
+    S.rel_res = rel;
+    S.J0 = J0;
+    S.seconds = secs();
+    S.seconds_to_1e6 = t6;
+    S.dof_updates = (double)n * c.M * periods;
+    S.status = (!fixed && rel > o->tol) ? CMCG_NOT_CONVERGED : CMCG_OK;
+    return res.release();
+}
+
+}  // namespace cmcg
+
+// ======================================================================= ABI
+using namespace cmcg;
+
+#define CMCG_GUARD_BEGIN try {
+#define CMCG_GUARD_END                          \
+    }                                           \
+    catch (const Error& e) {                    \
+        set_last_error(e.msg);                  \
+        return e.code;                          \
+    }                                           \
+    catch (const std::bad_alloc&) {             \
+        set_last_error("host allocation failed"); \
+        return CMCG_ERR_NOMEM;                  \
+    }                                           \
+    catch (const std::exception& e) {           \
+        set_last_error(e.what());               \
+        return CMCG_ERR_ARG;                    \
+    }
+
+extern "C" {
+
+const char* cmcg_last_error(void) { return g_last_error.c_str(); }
+const char* cmcg_version(void) { return "cmcg-mi355x 0.1"; }
+
+void cmcg_options_default(cmcg_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-8;
+    o->max_iter = 1000;
+    o->scheme = CMCG_SCHEME_AUTO;
+    o->flux = CMCG_FLUX_UPWIND;
+    o->use_graph = 1;
+}
+
+int cmcg_mesh_create(int64_t nv, const double* xyz, int64_t K, const int64_t* tet, const int8_t* face_tag,
+                     cmcg_mesh** out) {
+    CMCG_GUARD_BEGIN
+    if (!out) fail(CMCG_ERR_ARG, "mesh: NULL output");
+    *out = nullptr;
+    auto d = build_mesh(nv, xyz, K, tet, face_tag);
+    *out = new cmcg_mesh{d};
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+void cmcg_mesh_destroy(cmcg_mesh* m) { delete m; }
+
+int cmcg_mesh_info(const cmcg_mesh* m, int64_t* K, int64_t* nb, double* min_rho) {
+    CMCG_GUARD_BEGIN
+    if (!m || !m->d) fail(CMCG_ERR_ARG, "mesh_info: NULL mesh");
+    if (K) *K = m->d->K;
+    if (nb) *nb = m->d->n_boundary;
+    if (min_rho) {
+        double r = HUGE_VAL;
+        for (double x : m->d->rho) r = std::fmin(r, x);
+        *min_rho = r;
+    }
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_space_create(const cmcg_mesh* m, int q, int precision, cmcg_space** out) {
+    CMCG_GUARD_BEGIN
+    if (!out) fail(CMCG_ERR_ARG, "space: NULL output");
+    *out = nullptr;
+    if (!m || !m->d) fail(CMCG_ERR_ARG, "space: NULL mesh");
+    if (q < 1 || q > kMaxQ) fail(CMCG_ERR_ARG, "space: q must be 1, 2 or 3");
+    if (precision != CMCG_FP64 && precision != CMCG_FP32) fail(CMCG_ERR_ARG, "space: bad precision");
+    auto s = std::make_shared<SpaceData>();
+    s->mesh = m->d;
+    s->q = q;
+    s->Np = np_of(q);
+    s->Nfp = nfp_of(q);
+    s->precision = precision;
+    s->device = current_device();
+    s->K = m->d->K;
+    s->ndof = s->K * 6 * s->Np;
+    const MeshData& md = *m->d;
+    s->conn_h.resize(4 * s->K);
+    for (int64_t i = 0; i < 4 * s->K; ++i) {
+        if (md.nbr[i] >= 0)
+            s->conn_h[i] = (int32_t)((md.nbr[i] << 5) | (md.nbr_face[i] << 3) | md.perm[i]);
+        else
+            s->conn_h[i] = md.tag[i] == CMCG_TAG_PEC ? -1 : -2;
+    }
+    (void)ref_elem(q);
+    ensure_constants(s->device, q);
+    s->conn.alloc(4 * s->K * sizeof(int32_t));
+    CMCG_HIP(hipMemcpy(s->conn.p, s->conn_h.data(), 4 * s->K * sizeof(int32_t), hipMemcpyHostToDevice));
+    *out = new cmcg_space{s};
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+void cmcg_space_destroy(cmcg_space* s) { delete s; }
+
+int cmcg_space_info(const cmcg_space* s, int* q, int* Np, int* Nfp, int64_t* K, int64_t* ndof) {
+    CMCG_GUARD_BEGIN
+    if (!s || !s->d) fail(CMCG_ERR_ARG, "space_info: NULL space");
+    if (q) *q = s->d->q;
+    if (Np) *Np = s->d->Np;
+    if (Nfp) *Nfp = s->d->Nfp;
+    if (K) *K = s->d->K;
+    if (ndof) *ndof = s->d->ndof;
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_space_nodes(const cmcg_space* s, double* xyz) {
+    CMCG_GUARD_BEGIN
+    if (!s || !s->d || !xyz) fail(CMCG_ERR_ARG, "space_nodes: NULL argument");
+    const SpaceData& sp = *s->d;
+    const MeshData& m = *sp.mesh;
+    const RefElem& r = ref_elem(sp.q);
+    for (int64_t e = 0; e < sp.K; ++e) {
+        const double* v0 = &m.xyz[3 * m.tet[4 * e]];
+        for (int i = 0; i < sp.Np; ++i)
+            for (int d = 0; d < 3; ++d) {
+                double x = v0[d];
+                for (int a = 0; a < 3; ++a) x += r.xi[3 * i + a] * (m.xyz[3 * m.tet[4 * e + a + 1] + d] - v0[d]);
+                xyz[(e * sp.Np + i) * 3 + d] = x;
+            }
+    }
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_problem_create(const cmcg_space* s, const double* eps, const double* mu, const double* sigma,
+                        double omega, const double* j_re, const double* j_im, const double* g_re,
+                        const double* g_im, cmcg_problem** out) {
+    CMCG_GUARD_BEGIN
+    if (!out) fail(CMCG_ERR_ARG, "problem: NULL output");
+    *out = nullptr;
+    *out = make_problem(s, eps, mu, sigma, omega, j_re, j_im, g_re, g_im);
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_problem_create_device(const cmcg_space* s, const double* eps, const double* mu, const double* sigma,
+                               double omega, const double* j_re_dev, const double* j_im_dev, hipStream_t stream,
+                               cmcg_problem** out) {
+    CMCG_GUARD_BEGIN
+    if (!out) fail(CMCG_ERR_ARG, "problem: NULL output");
+    *out = nullptr;
+    if (!s || !s->d) fail(CMCG_ERR_ARG, "problem: NULL space");
+    const size_t nb = (size_t)s->d->K * s->d->Np * 3 * 8;
+    std::vector<double> jr, ji;
+    if (j_re_dev) {
+        jr.resize(nb / 8);
+        CMCG_HIP(hipMemcpyAsync(jr.data(), j_re_dev, nb, hipMemcpyDeviceToHost, stream));
+    }
+    if (j_im_dev) {
+        ji.resize(nb / 8);
+        CMCG_HIP(hipMemcpyAsync(ji.data(), j_im_dev, nb, hipMemcpyDeviceToHost, stream));
+    }
+    CMCG_HIP(hipStreamSynchronize(stream));
+    *out = make_problem(s, eps, mu, sigma, omega, j_re_dev ? jr.data() : nullptr, j_im_dev ? ji.data() : nullptr,
+                        nullptr, nullptr);
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+void cmcg_problem_destroy(cmcg_problem* p) { delete p; }
+
+int cmcg_problem_steps(const cmcg_problem* p, const cmcg_options* o, int* M, double* dt) {
+    CMCG_GUARD_BEGIN
+    if (!p || !o) fail(CMCG_ERR_ARG, "problem_steps: NULL argument");
+    StepCfg c = step_config(p, o);
+    if (M) *M = c.M;
+    if (dt) *dt = c.dt;
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_solve(cmcg_problem* p, const cmcg_options* o, const double* u0_dev, hipStream_t stream,
+               cmcg_result** out) {
+    CMCG_GUARD_BEGIN
+    if (!out) fail(CMCG_ERR_ARG, "solve: NULL output");
+    *out = nullptr;
+    if (!p) fail(CMCG_ERR_ARG, "solve: NULL problem");
+    cmcg_options def;
+    cmcg_options_default(&def);
+    if (!o) o = &def;
+    if (o->max_iter < 0 || o->fixed_iters < 0) fail(CMCG_ERR_ARG, "solve: negative iteration count");
+    cmcg_result* r = solve(p, o, u0_dev, stream);
+    *out = r;
+    return r->st.status;
+    CMCG_GUARD_END
+}
+
+int cmcg_result_fields(const cmcg_result* r, double* e_re, double* e_im, double* h_re, double* h_im) {
+    CMCG_GUARD_BEGIN
+    if (!r || !r->sp) fail(CMCG_ERR_ARG, "result_fields: NULL result");
+    const SpaceData& s = *r->sp;
+    std::vector<double> fr(s.ndof), fi(s.ndof);
+    CMCG_HIP(hipMemcpy(fr.data(), r->Fre.p, s.ndof * 8, hipMemcpyDeviceToHost));
+    CMCG_HIP(hipMemcpy(fi.data(), r->Fim.p, s.ndof * 8, hipMemcpyDeviceToHost));
+    const int Np = s.Np;
+    for (int64_t e = 0; e < s.K; ++e)
+        for (int i = 0; i < Np; ++i)
+            for (int c = 0; c < 3; ++c) {
+                const int64_t o = (e * Np + i) * 3 + c;
+                if (e_re) e_re[o] = fr[(e * 6 + c) * Np + i];
+                if (e_im) e_im[o] = fi[(e * 6 + c) * Np + i];
+                if (h_re) h_re[o] = fr[(e * 6 + 3 + c) * Np + i];
+                if (h_im) h_im[o] = fi[(e * 6 + 3 + c) * Np + i];
+            }
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_result_filtered_device(const cmcg_result* r, double* f_re, double* f_im, hipStream_t stream) {
+    CMCG_GUARD_BEGIN
+    if (!r || !r->sp) fail(CMCG_ERR_ARG, "result: NULL result");
+    const size_t b = r->sp->ndof * 8;
+    if (f_re) CMCG_HIP(hipMemcpyAsync(f_re, r->Fre.p, b, hipMemcpyDeviceToDevice, stream));
+    if (f_im) CMCG_HIP(hipMemcpyAsync(f_im, r->Fim.p, b, hipMemcpyDeviceToDevice, stream));
+    CMCG_HIP(hipStreamSynchronize(stream));
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_result_initial_device(const cmcg_result* r, double* u0, hipStream_t stream) {
+    CMCG_GUARD_BEGIN
+    if (!r || !r->sp || !u0) fail(CMCG_ERR_ARG, "result: NULL argument");
+    CMCG_HIP(hipMemcpyAsync(u0, r->U0.p, r->sp->ndof * 8, hipMemcpyDeviceToDevice, stream));
+    CMCG_HIP(hipStreamSynchronize(stream));
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_result_stats(const cmcg_result* r, cmcg_stats* st) {
+    CMCG_GUARD_BEGIN
+    if (!r || !st) fail(CMCG_ERR_ARG, "result_stats: NULL argument");
+    *st = r->st;
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_result_history(const cmcg_result* r, double* rel, int cap, int* n) {
+    CMCG_GUARD_BEGIN
+    if (!r) fail(CMCG_ERR_ARG, "result_history: NULL result");
+    const int m = (int)r->history.size();
+    if (n) *n = m;
+    if (rel)
+        for (int i = 0; i < m && i < cap; ++i) rel[i] = r->history[i];
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+void cmcg_result_destroy(cmcg_result* r) { delete r; }
+
+int cmcg_debug_rhs(cmcg_problem* p, const cmcg_options* o, double t, int with_source, const double* u,
+                   double* out, hipStream_t stream) {
+    CMCG_GUARD_BEGIN
+    if (!p || !u || !out) fail(CMCG_ERR_ARG, "debug_rhs: NULL argument");
+    cmcg_options def;
+    cmcg_options_default(&def);
+    if (!o) o = &def;
+    StepCfg c = step_config(p, o);
+    prepare(p, c);
+    const SpaceData& s = *p->sp;
+    p->Kbuf.alloc(s.ndof * s.esize());
+    launch_to_field(s.precision, s.Np, u, p->U.p, s.ndof, 0, stream);
+    StageArgs a = base_args(p);
+    a.mode = RHS;
+    a.Y = p->U.p;
+    a.U = p->U.p;
+    a.Kout = p->Kbuf.p;
+    a.src_rows = (with_source && p->src_rows) ? p->src_rows : 0;
+    a.scos = std::cos(p->omega * t);
+    a.ssin = std::sin(p->omega * t);
+    launch_stage(s.q, s.precision, a, stream);
+    launch_from_field(s.precision, s.Np, p->Kbuf.p, out, nullptr, s.ndof, 0, stream);
+    CMCG_HIP(hipStreamSynchronize(stream));
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_debug_period(cmcg_problem* p, const cmcg_options* o, int direction, int with_source, const double* u0,
+                      double* ut, double* f_re, double* f_im, hipStream_t stream) {
+    CMCG_GUARD_BEGIN
+    if (!p || !u0 || !ut) fail(CMCG_ERR_ARG, "debug_period: NULL argument");
+    if (direction != 1 && direction != -1) fail(CMCG_ERR_ARG, "debug_period: direction must be +1 or -1");
+    if (direction < 0 && with_source) fail(CMCG_ERR_ARG, "debug_period: the adjoint period has no source");
+    if (direction < 0 && (f_re || f_im)) fail(CMCG_ERR_ARG, "debug_period: filter only on forward periods");
+    cmcg_options def;
+    cmcg_options_default(&def);
+    if (!o) o = &def;
+    StepCfg c = step_config(p, o);
+    prepare(p, c);
+    const bool filt = f_re || f_im;
+    apply_period(p, c, o, u0, ut, nullptr, direction, with_source != 0, filt, stream);
+    const size_t b = p->sp->ndof * 8;
+    if (f_re) CMCG_HIP(hipMemcpyAsync(f_re, p->Fre.p, b, hipMemcpyDeviceToDevice, stream));
+    if (f_im) CMCG_HIP(hipMemcpyAsync(f_im, p->Fim.p, b, hipMemcpyDeviceToDevice, stream));
+    CMCG_HIP(hipStreamSynchronize(stream));
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_debug_dot(cmcg_problem* p, const double* u, const double* v, double* out, hipStream_t stream) {
+    CMCG_GUARD_BEGIN
+    if (!p || !u || !v || !out) fail(CMCG_ERR_ARG, "debug_dot: NULL argument");
+    ensure_constants(p->sp->device, p->sp->q);
+    ensure_work(p);
+    *out = dot(p, u, v, stream);
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+}  // extern "C"
