@@ -29,6 +29,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,17 +112,30 @@ def main():
     M, dt = cmcg.cmcg_problem_steps(p32, opts)
     stream = torch.cuda.current_stream()
 
+    log(f"K={K} Np={Np} ndof={ndof} M={M}")
+    t_ref = [time.perf_counter()]
+
+    def progress(it, rel):
+        if it % 10 == 0:
+            log(f"  iter {it} rel {rel:.3e} t {time.perf_counter() - t_ref[0]:.1f}s")
+        return False
+
+    opts.set_progress(progress)
     for _ in range(a.warmup):
+        t_ref[0] = time.perf_counter()
         r = cmcg.cmcg_solve(p32, opts)
+        log(f"warmup solve: {cmcg.cmcg_result_stats(r)}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dof_updates = 0.0
     stats = []
     for _ in range(a.steps):
+        t_ref[0] = time.perf_counter()
         r = cmcg.cmcg_solve(p32, opts)
         st = cmcg.cmcg_result_stats(r)
         stats.append(st)
         dof_updates += st["dof_updates"]
+        log(f"timed solve: {st}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = dof_updates / elapsed
@@ -166,8 +183,10 @@ def main():
     }
     if not a.no_fp64:
         s64, p64 = make(cmcg.CMCG_FP64)
+        t_ref[0] = time.perf_counter()
         r64 = cmcg.cmcg_solve(p64, opts)
         st64 = cmcg.cmcg_result_stats(r64)
+        log(f"fp64 solve: {st64}")
         out["cmcg"]["time_to_1e-6_fp64_s"] = st64["seconds_to_1e6"]
         out["cmcg"]["iters_fp64"] = st64["iters"]
         # FP32-field result against the FP64 result (relative eps,mu norm via the library's inner product)
@@ -180,6 +199,7 @@ def main():
         den = sum(cmcg.cmcg_debug_dot(p64, x, x) for x in f64)
         out["cmcg"]["fp32_vs_fp64_rel_l2"] = math.sqrt(num / den)
     if not a.no_cpu:
+        log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
     print(json.dumps(out), flush=True)
 

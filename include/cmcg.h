@@ -95,11 +95,21 @@ typedef struct cmcg_options {
                             impedance faces are always upwind                   */
     int use_graph;       /* 1: replay each period from a captured hipGraph      */
     int residual_refresh;/* > 0: every this many iterations replace R by the
-                            true gradient (costs two periods); 0 = never       */
+                            true gradient (costs two periods); 0 = automatic:
+                            every 10 iterations with FP32 fields (their
+                            rounding breaks the exact adjointness CG relies on
+                            near 1e-6), never with FP64; < 0 = never           */
+    /* Optional progress report, called on the host after every CG iteration
+     * with the iteration count and ||R_l|| / ||R_0||; a non-zero return value
+     * stops the iteration (the result is then flagged NOT_CONVERGED).  NULL =
+     * no report. */
+    int (*progress)(void* ctx, int iter, double rel_res);
+    void* progress_ctx;
 } cmcg_options;
 
 /* Fills *o with defaults: tol 1e-8, max_iter 1000, fixed_iters 0, cfl 0,
- * steps 0, scheme AUTO, flux UPWIND, use_graph 1, residual_refresh 0. */
+ * steps 0, scheme AUTO, flux UPWIND, use_graph 1, residual_refresh 0,
+ * progress NULL. */
 void cmcg_options_default(cmcg_options* o);
 
 /* Solve statistics. */

@@ -47,10 +47,18 @@ EXPORTED = [
 ]
 
 
+PROGRESS_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_double)
+
+
 class cmcg_options(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("cfl", C.c_double),
                 ("steps", C.c_int), ("scheme", C.c_int), ("flux", C.c_int), ("use_graph", C.c_int),
-                ("residual_refresh", C.c_int)]
+                ("residual_refresh", C.c_int), ("progress", PROGRESS_FN), ("progress_ctx", C.c_void_p)]
+
+    def set_progress(self, fn):
+        """fn(iter, rel_res) -> bool (True stops the iteration)."""
+        self._cb = PROGRESS_FN(lambda ctx, it, rel: int(bool(fn(it, rel))))
+        self.progress = self._cb
 
 
 class cmcg_stats(C.Structure):
@@ -153,8 +161,12 @@ class _Handle:
         self._keep = keep
 
     def __del__(self):
-        if getattr(self, "h", None) and self._destroy:
-            getattr(_lib, self._destroy)(self.h)
+        h = getattr(self, "h", None)
+        if h and self._destroy and _lib is not None:
+            try:
+                getattr(_lib, self._destroy)(h)
+            except Exception:
+                pass
             self.h = None
 
 

@@ -586,8 +586,11 @@ static cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* 
     double t6 = -1.0;
     int it = 0;
     const bool fixed = o->fixed_iters > 0;
+    const int refresh =
+        o->residual_refresh > 0 ? o->residual_refresh : (o->residual_refresh == 0 && s.precision == CMCG_FP32 ? 10 : 0);
     const int limit = fixed ? o->fixed_iters : o->max_iter;
     double rel = 1.0;
+    bool stopped = false;
     if (rr0 == 0.0) rel = 0.0;
     while (it < limit) {
         rel = rr0 > 0 ? std::sqrt(rr / rr0) : 0.0;
@@ -605,7 +608,7 @@ static cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* 
         launch_axpby(-alpha, D, 1.0, U, U, n, st);
         launch_axpby(-alpha, A, 1.0, R, R, n, st);
         ++it;
-        if (o->residual_refresh > 0 && it % o->residual_refresh == 0) gradient(R);
+        if (refresh > 0 && it % refresh == 0) gradient(R);
         const double rn = dot(p, R, R, st);
         if (!std::isfinite(rn)) fail(CMCG_ERR_UNSTABLE, "solve: non-finite residual");
         const double beta = rn / rr;
@@ -613,6 +616,10 @@ static cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* 
         rr = rn;
         rel = rr0 > 0 ? std::sqrt(rr / rr0) : 0.0;
         res->history.push_back(rel);
+        if (o->progress && o->progress(o->progress_ctx, it, rel) != 0) {
+            stopped = true;
+            break;
+        }
     }
     if (t6 < 0 && rel <= 1e-6) t6 = secs();
     // final period with source and filter
@@ -635,7 +642,7 @@ static cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* 
     S.seconds = secs();
     S.seconds_to_1e6 = t6;
     S.dof_updates = (double)n * c.M * periods;
-    S.status = (!fixed && rel > o->tol) ? CMCG_NOT_CONVERGED : CMCG_OK;
+    S.status = (stopped || (!fixed && rel > o->tol)) ? CMCG_NOT_CONVERGED : CMCG_OK;
     return res.release();
 }
 
