@@ -225,6 +225,17 @@ int cmcg_debug_period(cmcg_problem* p, const cmcg_options* o, int direction,
 int cmcg_debug_dot(cmcg_problem* p, const double* u_dev, const double* v_dev, double* out,
                    hipStream_t stream);
 
+/* ------------------------------------------------------------- tuning -- */
+/* Stage-kernel implementation variant for (q, precision): 0 gathers each
+ * face's neighbour traces when it is processed, 1 requests them one face
+ * ahead (more registers, more latency hiding), 2 runs the volume and lift
+ * products on the matrix cores (FP32 fields, q = 2, 3; other combinations
+ * fall back to 0).  All compute the same Phi(t, Y) and stage update.  Process-wide; not thread-safe against
+ * concurrent solves.  Returns CMCG_ERR_ARG for an unknown q / precision /
+ * variant.  cmcg_tune_get_stage reports the current choice. */
+int cmcg_tune_stage(int q, int precision, int variant);
+int cmcg_tune_get_stage(int q, int precision, int* variant);
+
 #ifdef __cplusplus
 }
 #endif

@@ -43,7 +43,7 @@ EXPORTED = [
     "cmcg_problem_create", "cmcg_problem_create_device", "cmcg_problem_destroy", "cmcg_problem_steps",
     "cmcg_solve", "cmcg_result_fields", "cmcg_result_filtered_device", "cmcg_result_initial_device",
     "cmcg_result_stats", "cmcg_result_history", "cmcg_result_destroy",
-    "cmcg_debug_rhs", "cmcg_debug_period", "cmcg_debug_dot",
+    "cmcg_debug_rhs", "cmcg_debug_period", "cmcg_debug_dot", "cmcg_tune_stage", "cmcg_tune_get_stage",
 ]
 
 
@@ -98,6 +98,8 @@ _sig = {
     "cmcg_debug_rhs": (C.c_int, [P, C.POINTER(cmcg_options), C.c_double, C.c_int, P, P, P]),
     "cmcg_debug_period": (C.c_int, [P, C.POINTER(cmcg_options), C.c_int, C.c_int, P, P, P, P, P]),
     "cmcg_debug_dot": (C.c_int, [P, P, P, D, P]),
+    "cmcg_tune_stage": (C.c_int, [C.c_int, C.c_int, C.c_int]),
+    "cmcg_tune_get_stage": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
 }
 for _n, (_r, _a) in _sig.items():
     _f = getattr(_lib, _n)
@@ -316,3 +318,13 @@ def cmcg_debug_dot(p: Problem, u_dev, v_dev, stream=None) -> float:
     out = C.c_double()
     _check(_lib.cmcg_debug_dot(p.h, _ptr(u_dev), _ptr(v_dev), C.byref(out), _stream(stream)))
     return out.value
+
+
+def cmcg_tune_stage(q: int, precision: int, variant: int):
+    _check(_lib.cmcg_tune_stage(q, precision, variant))
+
+
+def cmcg_tune_get_stage(q: int, precision: int) -> int:
+    v = C.c_int()
+    _check(_lib.cmcg_tune_get_stage(q, precision, C.byref(v)))
+    return v.value

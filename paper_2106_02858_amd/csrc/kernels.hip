@@ -19,6 +19,8 @@
 //     accumulation run as one coalesced pass over the 10-element chunk.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 #include "launch.h"
 
@@ -55,117 +57,146 @@ template <> __device__ __forceinline__ const float* mats<float>() { return cMat3
 
 constexpr int EPW = 10;  // elements per 64-lane workgroup (60 active column lanes)
 
-template <typename T, int Q>
-__global__ __launch_bounds__(64) void k_stage(StageArgs a) {
+// Row access of NP contiguous values with the widest vector type the row
+// alignment allows (rows start at multiples of NP * sizeof(T) bytes).
+template <typename T, int NP> struct Row {
+    static constexpr int BYTES = NP * (int)sizeof(T);
+    static constexpr int VEC = (BYTES % 16 == 0) ? 16 : (BYTES % 8 == 0 ? 8 : (int)sizeof(T));
+    static constexpr int PER = VEC / (int)sizeof(T);
+    using V = typename std::conditional<VEC == 16, float4, typename std::conditional<VEC == 8, float2, T>::type>::type;
+    __device__ __forceinline__ static void load(const T* __restrict__ p, T (&r)[NP]) {
+        const V* q = reinterpret_cast<const V*>(p);
+#pragma unroll
+        for (int c = 0; c < NP / PER; ++c) {
+            V v = q[c];
+            const T* t = reinterpret_cast<const T*>(&v);
+#pragma unroll
+            for (int u = 0; u < PER; ++u) r[c * PER + u] = t[u];
+        }
+    }
+    __device__ __forceinline__ static void store(T* __restrict__ p, const T (&r)[NP]) {
+        V* q = reinterpret_cast<V*>(p);
+#pragma unroll
+        for (int c = 0; c < NP / PER; ++c) {
+            V v;
+            T* t = reinterpret_cast<T*>(&v);
+#pragma unroll
+            for (int u = 0; u < PER; ++u) t[u] = r[c * PER + u];
+            q[c] = v;
+        }
+    }
+};
+
+// Logical workgroup index with consecutive indices on one XCD: the hardware
+// hands workgroup b to XCD b % 8, so b -> (b % 8) * per + b / 8 keeps each
+// XCD on a contiguous element range (its face neighbours stay in that XCD's
+// L2).  The grid is a multiple of 8; indices past the element range exit.
+__device__ __forceinline__ int64_t xcd_block(int64_t per) {
+    const int64_t b = blockIdx.x;
+    return (b & 7) * per + (b >> 3);
+}
+
+// Neighbour traces of one face for the flux items a lane owns.  Item it of
+// face f is (element it % ne, face node it / ne), so consecutive lanes belong
+// to different elements (conflict-free LDS tile writes).  Interior faces read
+// the neighbour's stage input from global memory (cache-resident: the
+// neighbours are nearby in the element ordering); boundary items keep the
+// connectivity code and build their ghost state later.
+template <typename T, int Q, int RF> struct FaceGather {
+    T v[RF][6];
+    int code[RF];
+    __device__ __forceinline__ void issue(const StageArgs& a, const T* __restrict__ Y, int64_t e0, int ne, int f,
+                                          int lane, const int* fnode, const int* fperm) {
+        constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP;
+#pragma unroll
+        for (int r = 0; r < RF; ++r) {
+            const int it = lane + 64 * r;
+            code[r] = -3;
+            if (it < ne * NFP) {
+                const int k = it / ne;
+                const int fe = it - k * ne;
+                const int cd = a.conn[(e0 + fe) * 4 + f];
+                code[r] = cd;
+                if (cd >= 0) {
+                    const int64_t nb = cd >> 5;
+                    const int nn = fnode[((cd >> 3) & 3) * NFP + fperm[(cd & 7) * NFP + k]];
+                    const T* q = Y + nb * 6 * NP + nn;
+#pragma unroll
+                    for (int cc = 0; cc < 6; ++cc) v[r][cc] = q[cc * NP];
+                }
+            }
+        }
+    }
+};
+
+// PIPE: request the next face's neighbour traces (and, before the last face,
+// the update operands) one face ahead.  Without it every face gathers and
+// consumes in turn, which needs fewer registers.
+template <typename T, int Q, bool PIPE>
+__global__ __launch_bounds__(64) void k_stage(StageArgs a, int64_t per) {
     constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP, NF4 = 4 * NFP;
+    constexpr int RS = NP + 1;            // padded LDS row stride (bank spread)
     constexpr int MO = mat_off(Q);
     constexpr int LO = MO + 3 * NP * NP;  // LIFT [NP][NF4]
-    __shared__ T sY[EPW * 6 * NP];
-    __shared__ T sR[EPW * 6 * NP];
-    __shared__ T sF[NF4 * 64];
+    constexpr int RF = (EPW * NFP + 63) / 64;  // flux items per lane and face
+    __shared__ T sY[EPW * 6 * RS];
+    __shared__ T sF[NFP * 64];
     __shared__ T sG[EPW * kGeo];
 
+    const int64_t blk = xcd_block(per);
+    const int64_t e0 = blk * EPW;
+    if (e0 >= a.K) return;
     const T* __restrict__ Y = (const T*)a.Y;
     const int lane = threadIdx.x;
-    const int64_t e0 = (int64_t)blockIdx.x * EPW;
     const int ne = (int)((a.K - e0) < EPW ? (a.K - e0) : EPW);
-    const int nv = ne * 6 * NP;
     const int64_t base = e0 * 6 * NP;
-
-    for (int v = lane; v < nv; v += 64) sY[v] = Y[base + v];
-    const T* geo = (const T*)a.geo + e0 * kGeo;
-    for (int v = lane; v < ne * kGeo; v += 64) sG[v] = geo[v];
-    __syncthreads();
-
-    // ---- upwind flux at every face node: sF[face node][el * 6 + comp]
     const int* fnode = cFnode + fn_off(Q);
     const int* fperm = cFperm + fp_off(Q);
-    for (int it = lane; it < ne * NF4; it += 64) {
-        const int el = it / NF4;
-        const int r = it - el * NF4;
-        const int f = r / NFP;
-        const int k = r - f * NFP;
-        const int own = fnode[f * NFP + k];
-        T Em[3], Hm[3], Ep[3], Hp[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            Em[c] = sY[(el * 6 + c) * NP + own];
-            Hm[c] = sY[(el * 6 + 3 + c) * NP + own];
-        }
-        const int code = a.conn[(e0 + el) * 4 + f];
-        if (code >= 0) {
-            const int64_t nb = code >> 5;
-            const int f2 = (code >> 3) & 3;
-            const int p = code & 7;
-            const int nn = fnode[f2 * NFP + fperm[p * NFP + k]];
-            if (nb >= e0 && nb < e0 + ne) {
-                const int l = (int)(nb - e0);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    Ep[c] = sY[(l * 6 + c) * NP + nn];
-                    Hp[c] = sY[(l * 6 + 3 + c) * NP + nn];
-                }
-            } else {
-                const T* q = Y + nb * 6 * NP + nn;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    Ep[c] = q[c * NP];
-                    Hp[c] = q[(3 + c) * NP];
-                }
-            }
-        } else if (code == -1) {  // PEC ghost: E+ = -E-, H+ = H-
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                Ep[c] = -Em[c];
-                Hp[c] = Hm[c];
-            }
-        } else {  // impedance ghost (homogeneous part): zero exterior state
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                Ep[c] = T(0);
-                Hp[c] = T(0);
-            }
-        }
-        const T* g = &sG[el * kGeo + 9 + 7 * f];
-        const T n0 = g[0], n1 = g[1], n2 = g[2];
-        const T cE1 = g[3], cE2 = g[4], cH1 = g[5], cH2 = g[6];
-        const T dE0 = Ep[0] - Em[0], dE1 = Ep[1] - Em[1], dE2 = Ep[2] - Em[2];
-        const T dH0 = Hp[0] - Hm[0], dH1 = Hp[1] - Hm[1], dH2 = Hp[2] - Hm[2];
-        const T ndE = n0 * dE0 + n1 * dE1 + n2 * dE2;
-        const T ndH = n0 * dH0 + n1 * dH1 + n2 * dH2;
-        // n x dH, n x dE
-        const T xH0 = n1 * dH2 - n2 * dH1, xH1 = n2 * dH0 - n0 * dH2, xH2 = n0 * dH1 - n1 * dH0;
-        const T xE0 = n1 * dE2 - n2 * dE1, xE1 = n2 * dE0 - n0 * dE2, xE2 = n0 * dE1 - n1 * dE0;
-        T* o = &sF[(f * NFP + k) * 64 + el * 6];
-        o[0] = cE1 * (dE0 - ndE * n0) - cE2 * xH0;
-        o[1] = cE1 * (dE1 - ndE * n1) - cE2 * xH1;
-        o[2] = cE1 * (dE2 - ndE * n2) - cE2 * xH2;
-        o[3] = cH1 * (dH0 - ndH * n0) + cH2 * xE0;
-        o[4] = cH1 * (dH1 - ndH * n1) + cH2 * xE1;
-        o[5] = cH1 * (dH2 - ndH * n2) + cH2 * xE2;
-    }
 
-    // ---- volume term: lane = (element, component) column
+    // column ownership: lane = (element, component)
     const int el = lane / 6;
     const int c = lane - 6 * el;
     const bool act = el < ne;
     const int elc = act ? el : 0;
     const int row = elc * 6 + c;
+    const int64_t grow = base + (int64_t)row * NP;
+    const int mode = a.mode;
+    const bool needU = mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3;
+    const bool needA = mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4;
+
+    // neighbour traces of face 0 in flight during the staging and volume work
+    FaceGather<T, Q, RF> cur, nxt;
+    if (PIPE) cur.issue(a, Y, e0, ne, 0, lane, fnode, fperm);
+
+    for (int v = lane; v < ne * 6 * NP; v += 64) {
+        const int r = v / NP;
+        sY[r * RS + (v - r * NP)] = Y[base + v];
+    }
+    const T* geo = (const T*)a.geo + e0 * kGeo;
+    for (int v = lane; v < ne * kGeo; v += 64) sG[v] = geo[v];
+    __syncthreads();
+
+    // ---- volume term: D_a y per column, curl terms exchanged between lanes
     T y[NP];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) y[j] = sY[row * NP + j];
+    for (int j = 0; j < NP; ++j) y[j] = sY[row * RS + j];
     const T* gg = &sG[elc * kGeo];
     const int c3 = c < 3 ? c : c - 3;
     const int kp = c3 == 0 ? 2 : c3 - 1;  // (c3 + 2) % 3
     const int km = c3 == 2 ? 0 : c3 + 1;  // (c3 + 1) % 3
+    const int sb = elc * 6 + (c < 3 ? 3 : 0);
+    const int lane_p = sb + (c3 == 0 ? 2 : c3 - 1);  // sends +d_{m+1} V_{m+2} (m = c3)
+    const int lane_m = sb + (c3 == 2 ? 0 : c3 + 1);  // sends -d_{m+2} V_{m+1}
+    const T* Mt = mats<T>();
+    // this column's contributions to the curl of its field:
+    // pv = d_{c3+2} V_{c3} (to curl component c3+1), mv = -d_{c3+1} V_{c3} (to c3+2)
     T pv[NP], mv[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
         pv[i] = T(0);
         mv[i] = T(0);
     }
-    const T* Mt = mats<T>();
-#pragma unroll
+#pragma unroll 1
     for (int ax = 0; ax < 3; ++ax) {
         const T gp = gg[3 * ax + kp];
         const T gm = gg[3 * ax + km];
@@ -178,79 +209,446 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs a) {
             mv[i] = fma(-gm, d, mv[i]);
         }
     }
-    // curl component c3 of the other field: +d_{c3+1} V_{c3+2} from lane
-    // (c3+2), -d_{c3+2} V_{c3+1} from lane (c3+1)
-    const int sb = elc * 6 + (c < 3 ? 3 : 0);
-    const int lane_p = sb + (c3 == 0 ? 2 : c3 - 1);
-    const int lane_m = sb + (c3 == 2 ? 0 : c3 + 1);
-    T curl[NP];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) curl[i] = __shfl(pv[i], lane_p) + __shfl(mv[i], lane_m);
-    __syncthreads();  // flux tile complete
-
-    // ---- lift and scaling
-    T fl[NF4];
-#pragma unroll
-    for (int kk = 0; kk < NF4; ++kk) fl[kk] = sF[kk * 64 + lane];
-    const T inv = c < 3 ? gg[37] : gg[38];
+    // E rows take -curl H, H rows +curl E
     const T sgn = c < 3 ? T(-1) : T(1);
+    T acc[NP];
 #pragma unroll
-    for (int i = 0; i < NP; ++i) {
-        T s = T(0);
+    for (int i = 0; i < NP; ++i) acc[i] = sgn * (__shfl(pv[i], lane_p) + __shfl(mv[i], lane_m));
+
+    // ---- upwind flux and lift, one face at a time; the next face's
+    // neighbour traces (and before the last face the update operands) are
+    // requested before this face's work
+    T up[NP], ap[NP];
+#pragma unroll 1
+    for (int f = 0; f < 4; ++f) {
+        if (PIPE) {
+            if (f < 3) {
+                nxt.issue(a, Y, e0, ne, f + 1, lane, fnode, fperm);
+            } else if (act) {
+                if (needU) Row<T, NP>::load((const T*)a.U + grow, up);
+                if (needA) Row<T, NP>::load((const T*)a.Acc + grow, ap);
+            }
+        } else {
+            cur.issue(a, Y, e0, ne, f, lane, fnode, fperm);
+        }
 #pragma unroll
-        for (int kk = 0; kk < NF4; ++kk) s = fma(Mt[LO + i * NF4 + kk], fl[kk], s);
-        const T rv = inv * fma(sgn, curl[i], s);
-        if (act) sR[row * NP + i] = rv;
+        for (int r = 0; r < RF; ++r) {
+            const int it = lane + 64 * r;
+            if (it >= ne * NFP) continue;
+            const int k = it / ne;
+            const int fe = it - k * ne;
+            const int own = fnode[f * NFP + k];
+            T Em[3], Hm[3], Ep[3], Hp[3];
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                Em[cc] = sY[(fe * 6 + cc) * RS + own];
+                Hm[cc] = sY[(fe * 6 + 3 + cc) * RS + own];
+            }
+            const int code = cur.code[r];
+            if (code >= 0) {
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    Ep[cc] = cur.v[r][cc];
+                    Hp[cc] = cur.v[r][3 + cc];
+                }
+            } else if (code == -1) {  // PEC ghost: E+ = -E-, H+ = H-
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    Ep[cc] = -Em[cc];
+                    Hp[cc] = Hm[cc];
+                }
+            } else {  // impedance ghost (homogeneous part): zero exterior state
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    Ep[cc] = T(0);
+                    Hp[cc] = T(0);
+                }
+            }
+            const T* g = &sG[fe * kGeo + 9 + 7 * f];
+            const T n0 = g[0], n1 = g[1], n2 = g[2];
+            const T cE1 = g[3], cE2 = g[4], cH1 = g[5], cH2 = g[6];
+            const T dE0 = Ep[0] - Em[0], dE1 = Ep[1] - Em[1], dE2 = Ep[2] - Em[2];
+            const T dH0 = Hp[0] - Hm[0], dH1 = Hp[1] - Hm[1], dH2 = Hp[2] - Hm[2];
+            const T ndE = n0 * dE0 + n1 * dE1 + n2 * dE2;
+            const T ndH = n0 * dH0 + n1 * dH1 + n2 * dH2;
+            const T xH0 = n1 * dH2 - n2 * dH1, xH1 = n2 * dH0 - n0 * dH2, xH2 = n0 * dH1 - n1 * dH0;
+            const T xE0 = n1 * dE2 - n2 * dE1, xE1 = n2 * dE0 - n0 * dE2, xE2 = n0 * dE1 - n1 * dE0;
+            T* o = &sF[k * 64 + fe * 6];
+            o[0] = cE1 * (dE0 - ndE * n0) - cE2 * xH0;
+            o[1] = cE1 * (dE1 - ndE * n1) - cE2 * xH1;
+            o[2] = cE1 * (dE2 - ndE * n2) - cE2 * xH2;
+            o[3] = cH1 * (dH0 - ndH * n0) + cH2 * xE0;
+            o[4] = cH1 * (dH1 - ndH * n1) + cH2 * xE1;
+            o[5] = cH1 * (dH2 - ndH * n2) + cH2 * xE2;
+        }
+        __syncthreads();
+        T fl[NFP];
+#pragma unroll
+        for (int k = 0; k < NFP; ++k) fl[k] = sF[k * 64 + lane];
+        __syncthreads();  // the tile is rewritten by the next face
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            T s = acc[i];
+#pragma unroll
+            for (int k = 0; k < NFP; ++k) s = fma(Mt[LO + i * NF4 + f * NFP + k], fl[k], s);
+            acc[i] = s;
+        }
+        if (PIPE && f < 3) cur = nxt;
     }
+    if (!act) return;
+    if (!PIPE) {
+        if (needU) Row<T, NP>::load((const T*)a.U + grow, up);
+        if (needA) Row<T, NP>::load((const T*)a.Acc + grow, ap);
+    }
+
+    // ---- stage update on the lane's row
+    const T inv = c < 3 ? gg[37] : gg[38];
+    const T sig = c < 3 ? gg[39] : T(0);
+    T kv[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) kv[i] = fma(inv, acc[i], -sig * y[i]);
+    if (c < a.src_rows) {
+        T sr[NP], si[NP];
+        Row<T, NP>::load((const T*)a.Sre + grow, sr);
+        Row<T, NP>::load((const T*)a.Sim + grow, si);
+        const T scos = (T)a.scos, ssin = (T)a.ssin;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) kv[i] += scos * sr[i] - ssin * si[i];
+    }
+    const T cy = (T)a.cy, ca = (T)a.ca, cu = (T)a.cu;
+    T o1[NP], o2[NP];
+    switch (mode) {
+        case RK2_S1:
+#pragma unroll
+            for (int i = 0; i < NP; ++i) o1[i] = fma(cy, kv[i], y[i]);
+            Row<T, NP>::store((T*)a.Ynext + grow, o1);
+            break;
+        case RK2_S2:
+#pragma unroll
+            for (int i = 0; i < NP; ++i) o1[i] = fma(cu, kv[i], up[i]);
+            Row<T, NP>::store((T*)a.Uout + grow, o1);
+            break;
+        case RK4_S1:
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                o1[i] = fma(cy, kv[i], y[i]);
+                o2[i] = fma(ca, kv[i], y[i]);
+            }
+            Row<T, NP>::store((T*)a.Ynext + grow, o1);
+            Row<T, NP>::store((T*)a.Acc + grow, o2);
+            break;
+        case RK4_S2:
+        case RK4_S3:
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                o1[i] = fma(cy, kv[i], up[i]);
+                o2[i] = fma(ca, kv[i], ap[i]);
+            }
+            Row<T, NP>::store((T*)a.Ynext + grow, o1);
+            Row<T, NP>::store((T*)a.Acc + grow, o2);
+            break;
+        case RK4_S4:
+#pragma unroll
+            for (int i = 0; i < NP; ++i) o1[i] = fma(cu, kv[i], ap[i]);
+            Row<T, NP>::store((T*)a.Uout + grow, o1);
+            break;
+        default:
+            Row<T, NP>::store((T*)a.Kout + grow, kv);
+            break;
+    }
+    if (a.filter) {
+        // F += fa * U + fb * k on the lane's row (U is the stage input here)
+        double* fr = a.Fre + grow;
+        double* fi = a.Fim + grow;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const double ud = (double)y[i], kd = (double)kv[i];
+            fr[i] += a.fa_re * ud + a.fb_re * kd;
+            fi[i] += a.fa_im * ud + a.fb_im * kd;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 stage kernel on the matrix cores (q = 2, 3).
+//
+// Per 64-lane workgroup (10 elements, columns n = element * 6 + s):
+//   volume:  C[i][n] = sum_{a,j} D_a[i][j] W_a[j][n],  W_a = sgn (grad xi_a x V)_m,
+//            V = H for s < 3 (E rows, sgn = -1), V = E for s >= 3 (sgn = +1),
+//            m = s mod 3 -- i.e. curl V = sum_a D_a (grad xi_a x V) for an affine
+//            element, so the product already is the curl column;
+//   lift:    C[i][n] += sum_{f,k} LIFT[i][f Nfp + k] flux_f[k][n], face by face;
+// with v_mfma_f32_16x16x4f32: A = the reference matrices, held as register
+// fragments (lane l holds A[l % 16][l / 16] of each 16x4 block, read once from a
+// lane-ordered table), B = W or flux values from LDS, D[4 (l/16) + r][l % 16].
+// Rows i >= Np and padded K entries carry zero A fragments.
+template <int Q> struct MfmaDim {
+    static constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP;
+    static constexpr int MT = (NP + 15) / 16;        // 16-row output tiles
+    static constexpr int KSV = (3 * NP + 3) / 4;     // K steps of the volume product
+    static constexpr int KSF = (NFP + 3) / 4;        // K steps per face of the lift
+    static constexpr int NFRAG = MT * KSV + 4 * MT * KSF;
+};
+__host__ __device__ constexpr int frag_off(int q) {
+    return q <= 2 ? 0 : frag_off(q - 1) + 64 * MfmaDim<2>::NFRAG;
+}
+constexpr int kFragTotal = 64 * (MfmaDim<2>::NFRAG + MfmaDim<3>::NFRAG);
+__device__ float gFrag[kFragTotal];
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int Q>
+__global__ __launch_bounds__(64) void k_stage_mfma(StageArgs a, int64_t per) {
+    using T = float;
+    using MD = MfmaDim<Q>;
+    constexpr int NP = MD::NP, NFP = MD::NFP, MT = MD::MT, KSV = MD::KSV, KSF = MD::KSF;
+    constexpr int RS = NP + 1;
+    constexpr int KF = 4 * KSF;  // padded face rows of the flux tile
+    __shared__ T sY[EPW * 6 * RS];
+    __shared__ T sF[KF * 64];
+    __shared__ T sG[EPW * kGeo];
+
+    const int64_t blk = xcd_block(per);
+    const int64_t e0 = blk * EPW;
+    if (e0 >= a.K) return;  // uniform per workgroup
+    const T* __restrict__ Y = (const T*)a.Y;
+    const int lane = threadIdx.x;
+    const int ne = (int)((a.K - e0) < EPW ? (a.K - e0) : EPW);
+    const int64_t base = e0 * 6 * NP;
+    const int* fnode = cFnode + fn_off(Q);
+    const int* fperm = cFperm + fp_off(Q);
+
+    // matrix fragments (coalesced: fragment-major, lane-minor)
+    const float* fr = gFrag + frag_off(Q);
+    T afV[MT][KSV], afL[4][MT][KSF];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int ks = 0; ks < KSV; ++ks) afV[mt][ks] = fr[(mt * KSV + ks) * 64 + lane];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int ks = 0; ks < KSF; ++ks)
+                afL[f][mt][ks] = fr[(MT * KSV + (f * MT + mt) * KSF + ks) * 64 + lane];
+
+    for (int v = lane; v < ne * 6 * NP; v += 64) {
+        const int r = v / NP;
+        sY[r * RS + (v - r * NP)] = Y[base + v];
+    }
+    const T* geo = (const T*)a.geo + e0 * kGeo;
+    for (int v = lane; v < ne * kGeo; v += 64) sG[v] = geo[v];
+    for (int v = lane; v < KF * 64; v += 64) sF[v] = T(0);
     __syncthreads();
 
-    // ---- coalesced stage update
-    const T* __restrict__ Ub = (const T*)a.U;
-    const T* __restrict__ Sre = (const T*)a.Sre;
-    const T* __restrict__ Sim = (const T*)a.Sim;
+    const int q4 = lane >> 4;   // K row within a 4-row block / output row group
+    const int l16 = lane & 15;  // output column within a 16-column tile
+    v4f acc[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    // ---- volume product
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int n = nt * 16 + l16;
+        const bool ncol = n < 6 * ne;
+        const int e = ncol ? n / 6 : 0;
+        const int s = n - 6 * (n / 6);
+        const int m = s < 3 ? s : s - 3;
+        const int m1 = m == 2 ? 0 : m + 1, m2 = m == 0 ? 2 : m - 1;  // (m+1)%3, (m+2)%3
+        const int vb = e * 6 + (s < 3 ? 3 : 0);
+        const T sgn = s < 3 ? T(-1) : T(1);
+        const T* gE = &sG[e * kGeo];
+        const T* v1 = &sY[(vb + m1) * RS];
+        const T* v2 = &sY[(vb + m2) * RS];
+#pragma unroll
+        for (int ks = 0; ks < KSV; ++ks) {
+            const int k = ks * 4 + q4;
+            T b = T(0);
+            if (ncol && k < 3 * NP) {
+                const int ax = k / NP;
+                const int j = k - ax * NP;
+                b = sgn * (gE[3 * ax + m1] * v2[j] - gE[3 * ax + m2] * v1[j]);
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(afV[mt][ks], b, acc[mt][nt], 0, 0, 0);
+        }
+    }
+
+    // ---- upwind flux and lift, one face at a time
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        for (int it = lane; it < ne * NFP; it += 64) {
+            const int k = it / ne;
+            const int fe = it - k * ne;
+            const int own = fnode[f * NFP + k];
+            T Em[3], Hm[3], Ep[3], Hp[3];
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                Em[cc] = sY[(fe * 6 + cc) * RS + own];
+                Hm[cc] = sY[(fe * 6 + 3 + cc) * RS + own];
+            }
+            const int code = a.conn[(e0 + fe) * 4 + f];
+            if (code >= 0) {
+                const int64_t nb = code >> 5;
+                const int nn = fnode[((code >> 3) & 3) * NFP + fperm[(code & 7) * NFP + k]];
+                const T* q = Y + nb * 6 * NP + nn;
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    Ep[cc] = q[cc * NP];
+                    Hp[cc] = q[(3 + cc) * NP];
+                }
+            } else if (code == -1) {  // PEC ghost: E+ = -E-, H+ = H-
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    Ep[cc] = -Em[cc];
+                    Hp[cc] = Hm[cc];
+                }
+            } else {  // impedance ghost (homogeneous part): zero exterior state
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    Ep[cc] = T(0);
+                    Hp[cc] = T(0);
+                }
+            }
+            const T* g = &sG[fe * kGeo + 9 + 7 * f];
+            const T n0 = g[0], n1 = g[1], n2 = g[2];
+            const T cE1 = g[3], cE2 = g[4], cH1 = g[5], cH2 = g[6];
+            const T dE0 = Ep[0] - Em[0], dE1 = Ep[1] - Em[1], dE2 = Ep[2] - Em[2];
+            const T dH0 = Hp[0] - Hm[0], dH1 = Hp[1] - Hm[1], dH2 = Hp[2] - Hm[2];
+            const T ndE = n0 * dE0 + n1 * dE1 + n2 * dE2;
+            const T ndH = n0 * dH0 + n1 * dH1 + n2 * dH2;
+            const T xH0 = n1 * dH2 - n2 * dH1, xH1 = n2 * dH0 - n0 * dH2, xH2 = n0 * dH1 - n1 * dH0;
+            const T xE0 = n1 * dE2 - n2 * dE1, xE1 = n2 * dE0 - n0 * dE2, xE2 = n0 * dE1 - n1 * dE0;
+            T* o = &sF[k * 64 + fe * 6];
+            o[0] = cE1 * (dE0 - ndE * n0) - cE2 * xH0;
+            o[1] = cE1 * (dE1 - ndE * n1) - cE2 * xH1;
+            o[2] = cE1 * (dE2 - ndE * n2) - cE2 * xH2;
+            o[3] = cH1 * (dH0 - ndH * n0) + cH2 * xE0;
+            o[4] = cH1 * (dH1 - ndH * n1) + cH2 * xE1;
+            o[5] = cH1 * (dH2 - ndH * n2) + cH2 * xE2;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < KSF; ++ks) {
+            T b[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) b[nt] = sF[(ks * 4 + q4) * 64 + nt * 16 + l16];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(afL[f][mt][ks], b[nt], acc[mt][nt], 0, 0, 0);
+        }
+        __syncthreads();  // the tile is rewritten by the next face
+    }
+
+    // ---- stage update on the lane's output block (4 consecutive nodes of one column)
+    const int mode = a.mode;
     const T scos = (T)a.scos, ssin = (T)a.ssin;
     const T cy = (T)a.cy, ca = (T)a.ca, cu = (T)a.cu;
-    for (int v = lane; v < nv; v += 64) {
-        const int rw = v / NP;
-        const int comp = rw % 6;
-        const int e = rw / 6;
-        const T yv = sY[v];
-        T k = sR[v];
-        if (comp < 3) k = fma(-sG[e * kGeo + 39], yv, k);
-        const int64_t gi = base + v;
-        if (comp < a.src_rows) k += scos * Sre[gi] - ssin * Sim[gi];
-        T u = yv;
-        switch (a.mode) {
-            case RK2_S1:
-                ((T*)a.Ynext)[gi] = fma(cy, k, yv);
-                break;
-            case RK2_S2:
-                u = Ub[gi];
-                ((T*)a.Uout)[gi] = fma(cu, k, u);
-                break;
-            case RK4_S1:
-                ((T*)a.Ynext)[gi] = fma(cy, k, yv);
-                ((T*)a.Acc)[gi] = fma(ca, k, yv);
-                break;
-            case RK4_S2:
-            case RK4_S3: {
-                u = Ub[gi];
-                ((T*)a.Ynext)[gi] = fma(cy, k, u);
-                T* acc = (T*)a.Acc;
-                acc[gi] = fma(ca, k, acc[gi]);
-                break;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int n = nt * 16 + l16;
+        if (n >= 6 * ne) continue;
+        const int e = n / 6;
+        const int s = n - 6 * e;
+        const T inv = s < 3 ? sG[e * kGeo + 37] : sG[e * kGeo + 38];
+        const T sig = s < 3 ? sG[e * kGeo + 39] : T(0);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int i0 = mt * 16 + 4 * q4;
+            if (i0 >= NP) continue;
+            constexpr int W = (NP % 4 == 0) ? 4 : 2;  // NP = 20: float4 blocks; NP = 10: float2 pairs
+#pragma unroll
+            for (int h = 0; h < 4 / W; ++h) {
+                const int i = i0 + h * W;
+                if (i >= NP) continue;
+                const int64_t gi = base + (int64_t)n * NP + i;
+                T kv[W], yv[W];
+#pragma unroll
+                for (int u = 0; u < W; ++u) {
+                    yv[u] = sY[n * RS + i + u];
+                    kv[u] = fma(inv, acc[mt][nt][h * W + u], -sig * yv[u]);
+                }
+                using VW = typename std::conditional<W == 4, float4, float2>::type;
+                auto ld = [&](const void* p, T (&o)[W]) {
+                    VW v = *reinterpret_cast<const VW*>((const T*)p + gi);
+                    const T* t = reinterpret_cast<const T*>(&v);
+#pragma unroll
+                    for (int u = 0; u < W; ++u) o[u] = t[u];
+                };
+                auto st = [&](void* p, const T (&o)[W]) {
+                    VW v;
+                    T* t = reinterpret_cast<T*>(&v);
+#pragma unroll
+                    for (int u = 0; u < W; ++u) t[u] = o[u];
+                    *reinterpret_cast<VW*>((T*)p + gi) = v;
+                };
+                if (s < a.src_rows) {
+                    T sr[W], si[W];
+                    ld(a.Sre, sr);
+                    ld(a.Sim, si);
+#pragma unroll
+                    for (int u = 0; u < W; ++u) kv[u] += scos * sr[u] - ssin * si[u];
+                }
+                T o1[W], o2[W], up[W], ap[W];
+                switch (mode) {
+                    case RK2_S1:
+#pragma unroll
+                        for (int u = 0; u < W; ++u) o1[u] = fma(cy, kv[u], yv[u]);
+                        st(a.Ynext, o1);
+                        break;
+                    case RK2_S2:
+                        ld(a.U, up);
+#pragma unroll
+                        for (int u = 0; u < W; ++u) o1[u] = fma(cu, kv[u], up[u]);
+                        st(a.Uout, o1);
+                        break;
+                    case RK4_S1:
+#pragma unroll
+                        for (int u = 0; u < W; ++u) {
+                            o1[u] = fma(cy, kv[u], yv[u]);
+                            o2[u] = fma(ca, kv[u], yv[u]);
+                        }
+                        st(a.Ynext, o1);
+                        st(a.Acc, o2);
+                        break;
+                    case RK4_S2:
+                    case RK4_S3:
+                        ld(a.U, up);
+                        ld(a.Acc, ap);
+#pragma unroll
+                        for (int u = 0; u < W; ++u) {
+                            o1[u] = fma(cy, kv[u], up[u]);
+                            o2[u] = fma(ca, kv[u], ap[u]);
+                        }
+                        st(a.Ynext, o1);
+                        st(a.Acc, o2);
+                        break;
+                    case RK4_S4:
+                        ld(a.Acc, ap);
+#pragma unroll
+                        for (int u = 0; u < W; ++u) o1[u] = fma(cu, kv[u], ap[u]);
+                        st(a.Uout, o1);
+                        break;
+                    default:
+                        st(a.Kout, kv);
+                        break;
+                }
+                if (a.filter) {
+#pragma unroll
+                    for (int u = 0; u < W; ++u) {
+                        const double ud = (double)yv[u], kd = (double)kv[u];
+                        a.Fre[gi + u] += a.fa_re * ud + a.fb_re * kd;
+                        a.Fim[gi + u] += a.fa_im * ud + a.fb_im * kd;
+                    }
+                }
             }
-            case RK4_S4:
-                ((T*)a.Uout)[gi] = fma(cu, k, ((const T*)a.Acc)[gi]);
-                break;
-            default:
-                ((T*)a.Kout)[gi] = k;
-                break;
-        }
-        if (a.filter) {
-            const double ud = (double)u, kd = (double)k;
-            a.Fre[gi] += a.fa_re * ud + a.fb_re * kd;
-            a.Fim[gi] += a.fa_im * ud + a.fb_im * kd;
         }
     }
 }
@@ -359,6 +757,14 @@ __global__ void k_nonfinite(const double* X, int64_t n, int* flag) {
     }
 }
 
+// Stage-kernel variant per (q, precision): 0 = gather per face, 1 = gathers
+// pipelined one face ahead.  Chosen from measurements; overridable through
+// cmcg_tune_stage().
+// Defaults from the measured 48000-tet P3 / 10368-tet P2 periods: matrix
+// cores for FP32 P3 (64 us vs 75 us per stage), per-face gathers otherwise.
+int g_variant[kMaxQ + 1][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 2}};
+inline int stage_variant(int q, int precision) { return g_variant[q][precision]; }
+
 inline int grid_for(int64_t n, int threads = 256) {
     int64_t g = (n + threads - 1) / threads;
     if (g > 8192) g = 8192;
@@ -369,7 +775,18 @@ inline int grid_for(int64_t n, int threads = 256) {
 template <typename T, int Q>
 void stage_launch(const StageArgs& a, hipStream_t s) {
     const int64_t blocks = (a.K + EPW - 1) / EPW;
-    hipLaunchKernelGGL((k_stage<T, Q>), dim3((unsigned)blocks), dim3(64), 0, s, a);
+    const int64_t per = (blocks + 7) / 8;
+    const int v = stage_variant(Q, sizeof(T) == 8 ? CMCG_FP64 : CMCG_FP32);
+    if constexpr (sizeof(T) == 4 && Q >= 2) {
+        if (v == 2) {
+            hipLaunchKernelGGL((k_stage_mfma<Q>), dim3((unsigned)(8 * per)), dim3(64), 0, s, a, per);
+            return;
+        }
+    }
+    if (v == 1)
+        hipLaunchKernelGGL((k_stage<T, Q, true>), dim3((unsigned)(8 * per)), dim3(64), 0, s, a, per);
+    else
+        hipLaunchKernelGGL((k_stage<T, Q, false>), dim3((unsigned)(8 * per)), dim3(64), 0, s, a, per);
 }
 
 void check_launch() {
@@ -398,6 +815,34 @@ void upload_constants(int q, int precision, const double* D, const double* LIFT,
                                hipMemcpyHostToDevice));
     CMCG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cFperm), fperm, 6 * NFP * sizeof(int), fp_off(q) * sizeof(int),
                                hipMemcpyHostToDevice));
+    if (q >= 2) {
+        // lane-ordered A fragments of the matrix-core kernel: entry (frag, lane)
+        // = A[16 mt + lane % 16][4 ks + lane / 16] of the block the fragment names
+        const int MT = (NP + 15) / 16, KSV = (3 * NP + 3) / 4, KSF = (NFP + 3) / 4;
+        const int nfrag = MT * KSV + 4 * MT * KSF;
+        std::vector<float> fr(64 * nfrag, 0.f);
+        for (int l = 0; l < 64; ++l) {
+            const int i_in = l % 16, k_in = l / 16;
+            for (int mt = 0; mt < MT; ++mt) {
+                const int i = 16 * mt + i_in;
+                for (int ks = 0; ks < KSV; ++ks) {
+                    const int k = 4 * ks + k_in;  // k = a Np + j
+                    float v = 0.f;
+                    if (i < NP && k < 3 * NP) v = (float)D[((k / NP) * NP + i) * NP + k % NP];
+                    fr[(mt * KSV + ks) * 64 + l] = v;
+                }
+                for (int f = 0; f < 4; ++f)
+                    for (int ks = 0; ks < KSF; ++ks) {
+                        const int k = 4 * ks + k_in;
+                        float v = 0.f;
+                        if (i < NP && k < NFP) v = (float)LIFT[i * 4 * NFP + f * NFP + k];
+                        fr[(MT * KSV + (f * MT + mt) * KSF + ks) * 64 + l] = v;
+                    }
+            }
+        }
+        CMCG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(gFrag), fr.data(), fr.size() * sizeof(float),
+                                   frag_off(q) * sizeof(float), hipMemcpyHostToDevice));
+    }
 }
 
 void launch_stage(int q, int precision, const StageArgs& a, hipStream_t s) {
@@ -463,6 +908,9 @@ void launch_filter_add(int precision, const void* U, double wr, double wi, doubl
 }
 
 int dot_partials() { return kDotBlocks; }
+
+void set_stage_variant(int q, int precision, int variant) { g_variant[q][precision] = variant; }
+int get_stage_variant(int q, int precision) { return g_variant[q][precision]; }
 
 void launch_dot(int q, const double* U, const double* V, const double* wE, const double* wH, int64_t K,
                 double* partial, double* out_dev, hipStream_t s) {

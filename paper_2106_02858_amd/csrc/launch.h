@@ -44,6 +44,9 @@ struct StageArgs {
 void upload_constants(int q, int precision, const double* D, const double* LIFT, const double* M,
                       const int* fnode, const int* fperm);
 void launch_stage(int q, int precision, const StageArgs& a, hipStream_t s);
+void set_stage_variant(int q, int precision, int variant);
+int get_stage_variant(int q, int precision);
+constexpr int kStageVariants = 3;  // 2: matrix cores (FP32, q >= 2)
 
 // FP64 <-> field precision; flipH negates the magnetic rows (the S of P* = S P S).
 void launch_to_field(int precision, int Np, const double* X, void* U, int64_t n, int flipH,

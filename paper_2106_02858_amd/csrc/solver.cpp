@@ -959,4 +959,23 @@ int cmcg_debug_dot(cmcg_problem* p, const double* u, const double* v, double* ou
     CMCG_GUARD_END
 }
 
+int cmcg_tune_stage(int q, int precision, int variant) {
+    CMCG_GUARD_BEGIN
+    if (q < 1 || q > kMaxQ || (precision != CMCG_FP64 && precision != CMCG_FP32) || variant < 0 ||
+        variant >= kStageVariants)
+        fail(CMCG_ERR_ARG, "tune_stage: bad q, precision or variant");
+    set_stage_variant(q, precision, variant);
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_tune_get_stage(int q, int precision, int* variant) {
+    CMCG_GUARD_BEGIN
+    if (q < 1 || q > kMaxQ || (precision != CMCG_FP64 && precision != CMCG_FP32) || !variant)
+        fail(CMCG_ERR_ARG, "tune_get_stage: bad argument");
+    *variant = get_stage_variant(q, precision);
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
 }  // extern "C"

@@ -33,10 +33,23 @@ def test_nodes_match_oracle(lib, q):
     assert np.max(np.abs(lib.cmcg_space_nodes(s) - op.geo.x)) < 1e-15
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("q", [1, 2, 3])
-def test_rhs_parity(lib, q, precision):
-    print(f"rhs q={q} prec={precision}", flush=True)
+@pytest.fixture
+def variant(lib, request):
+    """Run a test under one stage-kernel variant, restoring the default."""
+    q, prec, v = request.param
+    old = lib.cmcg_tune_get_stage(q, prec)
+    lib.cmcg_tune_stage(q, prec, v)
+    yield request.param
+    lib.cmcg_tune_stage(q, prec, old)
+
+
+VARIANTS = [(q, p, v) for q in (1, 2, 3) for p in (0, 1) for v in (0, 1, 2)]
+
+
+@pytest.mark.parametrize("variant", VARIANTS, indirect=True, ids=lambda t: f"q{t[0]}-p{t[1]}-v{t[2]}")
+def test_rhs_parity(lib, variant):
+    q, precision, v = variant
+    print(f"rhs q={q} prec={precision} variant={v}", flush=True)
     op, s, lp = pair(lib, n=2, q=q, precision=precision, seed=q, g=True)
     U = np.random.default_rng(1).standard_normal((op.K, 6, op.Np))
     out = dev(np.zeros_like(U))
@@ -59,10 +72,10 @@ def test_rhs_centred_flux(lib, q, precision):
     assert np.max(np.abs(host(out) - ref)) / np.max(np.abs(ref)) < TOL[precision]
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("q", [1, 2, 3])
-def test_period_parity(lib, q, precision):
-    print(f"period q={q} prec={precision}", flush=True)
+@pytest.mark.parametrize("variant", VARIANTS, indirect=True, ids=lambda t: f"q{t[0]}-p{t[1]}-v{t[2]}")
+def test_period_parity(lib, variant):
+    q, precision, v = variant
+    print(f"period q={q} prec={precision} variant={v}", flush=True)
     op, s, lp = pair(lib, n=2 if q < 3 else 1, q=q, precision=precision, seed=10 + q, sigma=False, g=(q == 2))
     M = timestep.n_steps(op)
     sch = timestep.default_scheme(q)
