@@ -190,6 +190,18 @@ int cmcg_problem_steps(const cmcg_problem* p, const cmcg_options* o, int* M, dou
  * error (no result). */
 int cmcg_solve(cmcg_problem* p, const cmcg_options* o, const double* u0_dev,
                hipStream_t stream, cmcg_result** out);
+/* Batched solve: Algorithm 3 for n problems sharing one space (same mesh,
+ * order and field precision; each with its own omega, j, g and materials),
+ * advanced together -- one kernel launch per Runge-Kutta stage covers every
+ * member, members with shorter periods or a converged CG idle.  Each member
+ * stops on its own tolerance; its result equals the one cmcg_solve returns
+ * for it alone (same arithmetic and reduction order).  results[n] receives
+ * one result per member (owned by the caller).  Returns CMCG_OK when every
+ * member converged, CMCG_NOT_CONVERGED when some stopped at max_iter, or an
+ * error (then no results; CMCG_ERR_ARG when the problems do not share a
+ * space or a time scheme). */
+int cmcg_solve_batch(cmcg_problem* const* problems, int n, const cmcg_options* o,
+                     hipStream_t stream, cmcg_result** results);
 /* Filtered time-harmonic fields (complex amplitudes at the DG nodes),
  * [K][Np][3] each, host pointers; any output may be NULL. */
 int cmcg_result_fields(const cmcg_result* r, double* e_re, double* e_im, double* h_re,

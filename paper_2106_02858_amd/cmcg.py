@@ -41,7 +41,7 @@ EXPORTED = [
     "cmcg_mesh_create", "cmcg_mesh_destroy", "cmcg_mesh_info",
     "cmcg_space_create", "cmcg_space_destroy", "cmcg_space_info", "cmcg_space_nodes",
     "cmcg_problem_create", "cmcg_problem_create_device", "cmcg_problem_destroy", "cmcg_problem_steps",
-    "cmcg_solve", "cmcg_result_fields", "cmcg_result_filtered_device", "cmcg_result_initial_device",
+    "cmcg_solve", "cmcg_solve_batch", "cmcg_result_fields", "cmcg_result_filtered_device", "cmcg_result_initial_device",
     "cmcg_result_stats", "cmcg_result_history", "cmcg_result_destroy",
     "cmcg_debug_rhs", "cmcg_debug_period", "cmcg_debug_dot", "cmcg_tune_stage", "cmcg_tune_get_stage",
 ]
@@ -89,6 +89,7 @@ _sig = {
     "cmcg_problem_destroy": (None, [P]),
     "cmcg_problem_steps": (C.c_int, [P, C.POINTER(cmcg_options), C.POINTER(C.c_int), D]),
     "cmcg_solve": (C.c_int, [P, C.POINTER(cmcg_options), P, P, C.POINTER(P)]),
+    "cmcg_solve_batch": (C.c_int, [C.POINTER(P), C.c_int, C.POINTER(cmcg_options), P, C.POINTER(P)]),
     "cmcg_result_fields": (C.c_int, [P, P, P, P, P]),
     "cmcg_result_filtered_device": (C.c_int, [P, P, P, P]),
     "cmcg_result_initial_device": (C.c_int, [P, P, P]),
@@ -268,6 +269,15 @@ def cmcg_solve(p: Problem, opts: cmcg_options | None = None, u0_dev=None, stream
     _check(_lib.cmcg_solve(p.h, C.byref(o), _ptr(u0_dev), _stream(stream), C.byref(h)),
            allow=(CMCG_OK, CMCG_NOT_CONVERGED))
     return Result(h, keep=(p,))
+
+
+def cmcg_solve_batch(problems, opts: cmcg_options | None = None, stream=None):
+    o = opts or cmcg_options_default()
+    n = len(problems)
+    arr = (P * n)(*[p.h for p in problems])
+    res = (P * n)()
+    _check(_lib.cmcg_solve_batch(arr, n, C.byref(o), _stream(stream), res), allow=(CMCG_OK, CMCG_NOT_CONVERGED))
+    return [Result(P(res[b]), keep=(problems[b],)) for b in range(n)]
 
 
 def cmcg_result_fields(r: Result, K: int, Np: int):

@@ -96,6 +96,42 @@ __device__ __forceinline__ int64_t xcd_block(int64_t per) {
     return (b & 7) * per + (b >> 3);
 }
 
+// Arguments of this workgroup's member in a batched launch (grid.y = member):
+// field, source and filter pointers move by whole members, the stage scalars
+// come from the member table; returns false when the member is idle (CG
+// converged, or all of its steps in this period already taken).
+template <typename T>
+__device__ __forceinline__ bool member_args(const StageArgs& in, StageArgs& a) {
+    a = in;
+    if (!in.mtab) return true;
+    const int b = blockIdx.y;
+    if (!in.active[b]) return false;
+    if (in.step >= 0 && in.step >= in.msteps[b]) return false;
+    const double* p = in.mtab + (int64_t)b * kMemberParams;
+    a.cy = p[0];
+    a.ca = p[1];
+    a.cu = p[2];
+    a.scos = p[3];
+    a.ssin = p[4];
+    a.fa_re = p[5];
+    a.fa_im = p[6];
+    a.fb_re = p[7];
+    a.fb_im = p[8];
+    const int64_t fo = (int64_t)b * in.bstride;
+    if (in.Y) a.Y = (const T*)in.Y + fo;
+    if (in.U) a.U = (const T*)in.U + fo;
+    if (in.Ynext) a.Ynext = (T*)in.Ynext + fo;
+    if (in.Acc) a.Acc = (T*)in.Acc + fo;
+    if (in.Uout) a.Uout = (T*)in.Uout + fo;
+    if (in.Kout) a.Kout = (T*)in.Kout + fo;
+    if (in.Fre) a.Fre = in.Fre + fo;
+    if (in.Fim) a.Fim = in.Fim + fo;
+    a.geo = (const T*)in.geo + (int64_t)b * in.gstride;
+    if (in.Sre) a.Sre = (const T*)in.Sre + (int64_t)b * in.sstride;
+    if (in.Sim) a.Sim = (const T*)in.Sim + (int64_t)b * in.sstride;
+    return true;
+}
+
 // Neighbour traces of one face for the flux items a lane owns.  Item it of
 // face f is (element it % ne, face node it / ne), so consecutive lanes belong
 // to different elements (conflict-free LDS tile writes).  Interior faces read
@@ -133,7 +169,7 @@ template <typename T, int Q, int RF> struct FaceGather {
 // the update operands) one face ahead.  Without it every face gathers and
 // consumes in turn, which needs fewer registers.
 template <typename T, int Q, bool PIPE>
-__global__ __launch_bounds__(64) void k_stage(StageArgs a, int64_t per) {
+__global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP, NF4 = 4 * NFP;
     constexpr int RS = NP + 1;            // padded LDS row stride (bank spread)
     constexpr int MO = mat_off(Q);
@@ -143,6 +179,8 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs a, int64_t per) {
     __shared__ T sF[NFP * 64];
     __shared__ T sG[EPW * kGeo];
 
+    StageArgs a;
+    if (!member_args<T>(args, a)) return;  // uniform per workgroup
     const int64_t blk = xcd_block(per);
     const int64_t e0 = blk * EPW;
     if (e0 >= a.K) return;
@@ -398,7 +436,7 @@ __device__ float gFrag[kFragTotal];
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <int Q>
-__global__ __launch_bounds__(64) void k_stage_mfma(StageArgs a, int64_t per) {
+__global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) {
     using T = float;
     using MD = MfmaDim<Q>;
     constexpr int NP = MD::NP, NFP = MD::NFP, MT = MD::MT, KSV = MD::KSV, KSF = MD::KSF;
@@ -408,6 +446,8 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs a, int64_t per) {
     __shared__ T sF[KF * 64];
     __shared__ T sG[EPW * kGeo];
 
+    StageArgs a;
+    if (!member_args<T>(args, a)) return;  // uniform per workgroup
     const int64_t blk = xcd_block(per);
     const int64_t e0 = blk * EPW;
     if (e0 >= a.K) return;  // uniform per workgroup
@@ -750,6 +790,86 @@ __global__ __launch_bounds__(kDotThreads) void k_dot_final(const double* __restr
     if (threadIdx.x == 0) out[0] = sm[0];
 }
 
+// Batched dot: member b = blockIdx.y; per member the same block decomposition
+// and summation order as k_dot / k_dot_final (results equal the single dots).
+template <int Q>
+__global__ __launch_bounds__(kDotThreads) void k_dot_batch(const double* __restrict__ U, const double* __restrict__ V,
+                                                           const double* __restrict__ wE,
+                                                           const double* __restrict__ wH, int64_t wstride,
+                                                           int64_t K, double* __restrict__ partial) {
+    constexpr int NP = Dim<Q>::NP;
+    constexpr int MMO = mat_off(Q) + 3 * NP * NP + NP * 4 * Dim<Q>::NFP;
+    __shared__ double sm[kDotThreads];
+    const int64_t b = blockIdx.y;
+    const int64_t n = 6 * K * NP;
+    U += b * n;
+    V += b * n;
+    wE += b * wstride;
+    wH += b * wstride;
+    double acc = 0.0;
+    const int64_t rows = 6 * K;
+    for (int64_t r = blockIdx.x * (int64_t)kDotThreads + threadIdx.x; r < rows; r += (int64_t)gridDim.x * kDotThreads) {
+        const double* u = U + r * NP;
+        const double* v = V + r * NP;
+        double vv[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) vv[j] = v[j];
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            double mvv = 0.0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) mvv = fma(cMat64[MMO + i * NP + j], vv[j], mvv);
+            s = fma(u[i], mvv, s);
+        }
+        const int64_t e = r / 6;
+        acc = fma(s, (r - 6 * e) < 3 ? wE[e] : wH[e], acc);
+    }
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kDotThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[b * kDotBlocks + blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(kDotThreads) void k_dot_final_batch(const double* __restrict__ partial, int n,
+                                                                 double* __restrict__ out) {
+    __shared__ double sm[kDotThreads];
+    const int b = blockIdx.x;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += kDotThreads) acc += partial[(int64_t)b * kDotBlocks + i];
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kDotThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[b] = sm[0];
+}
+
+__global__ void k_axpby_batch(const double* __restrict__ a, const double* x, const double* __restrict__ c,
+                              const double* y, double* z, int64_t n, int B) {
+    const int64_t tot = n * B;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / n;
+        z[i] = a[b] * x[i] + c[b] * y[i];
+    }
+}
+
+template <typename T>
+__global__ void k_filter_add_batch(const T* __restrict__ U, const double* __restrict__ wr,
+                                   const double* __restrict__ wi, double* Fre, double* Fim, int64_t n, int B) {
+    const int64_t tot = n * B;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / n;
+        const double u = (double)U[i];
+        Fre[i] += wr[b] * u;
+        Fim[i] += wi[b] * u;
+    }
+}
+
 __global__ void k_nonfinite(const double* X, int64_t n, int* flag) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double x = X[i];
@@ -777,16 +897,17 @@ void stage_launch(const StageArgs& a, hipStream_t s) {
     const int64_t blocks = (a.K + EPW - 1) / EPW;
     const int64_t per = (blocks + 7) / 8;
     const int v = stage_variant(Q, sizeof(T) == 8 ? CMCG_FP64 : CMCG_FP32);
+    const dim3 grid((unsigned)(8 * per), (unsigned)(a.nmembers > 1 ? a.nmembers : 1));
     if constexpr (sizeof(T) == 4 && Q >= 2) {
         if (v == 2) {
-            hipLaunchKernelGGL((k_stage_mfma<Q>), dim3((unsigned)(8 * per)), dim3(64), 0, s, a, per);
+            hipLaunchKernelGGL((k_stage_mfma<Q>), grid, dim3(64), 0, s, a, per);
             return;
         }
     }
     if (v == 1)
-        hipLaunchKernelGGL((k_stage<T, Q, true>), dim3((unsigned)(8 * per)), dim3(64), 0, s, a, per);
+        hipLaunchKernelGGL((k_stage<T, Q, true>), grid, dim3(64), 0, s, a, per);
     else
-        hipLaunchKernelGGL((k_stage<T, Q, false>), dim3((unsigned)(8 * per)), dim3(64), 0, s, a, per);
+        hipLaunchKernelGGL((k_stage<T, Q, false>), grid, dim3(64), 0, s, a, per);
 }
 
 void check_launch() {
@@ -925,6 +1046,40 @@ void launch_dot(int q, const double* U, const double* V, const double* wE, const
         hipLaunchKernelGGL(k_dot<3>, dim3(blocks), dim3(kDotThreads), 0, s, U, V, wE, wH, K, partial);
     check_launch();
     hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kDotThreads), 0, s, partial, blocks, out_dev);
+    check_launch();
+}
+
+void launch_dot_batch(int q, const double* U, const double* V, const double* wE, const double* wH, int64_t wstride,
+                      int64_t K, int B, double* partial, double* out_dev, hipStream_t s) {
+    int64_t rows = 6 * K;
+    int blocks = (int)((rows + kDotThreads - 1) / kDotThreads);
+    if (blocks > kDotBlocks) blocks = kDotBlocks;
+    const dim3 grid(blocks, B);
+    if (q == 1)
+        hipLaunchKernelGGL(k_dot_batch<1>, grid, dim3(kDotThreads), 0, s, U, V, wE, wH, wstride, K, partial);
+    else if (q == 2)
+        hipLaunchKernelGGL(k_dot_batch<2>, grid, dim3(kDotThreads), 0, s, U, V, wE, wH, wstride, K, partial);
+    else
+        hipLaunchKernelGGL(k_dot_batch<3>, grid, dim3(kDotThreads), 0, s, U, V, wE, wH, wstride, K, partial);
+    check_launch();
+    hipLaunchKernelGGL(k_dot_final_batch, dim3(B), dim3(kDotThreads), 0, s, partial, blocks, out_dev);
+    check_launch();
+}
+
+void launch_axpby_batch(const double* a, const double* x, const double* c, const double* y, double* z, int64_t n,
+                        int B, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby_batch, dim3(grid_for(n * B)), dim3(256), 0, s, a, x, c, y, z, n, B);
+    check_launch();
+}
+
+void launch_filter_add_batch(int precision, const void* U, const double* w_re, const double* w_im, double* Fre,
+                             double* Fim, int64_t n, int B, hipStream_t s) {
+    if (precision == CMCG_FP64)
+        hipLaunchKernelGGL(k_filter_add_batch<double>, dim3(grid_for(n * B)), dim3(256), 0, s, (const double*)U,
+                           w_re, w_im, Fre, Fim, n, B);
+    else
+        hipLaunchKernelGGL(k_filter_add_batch<float>, dim3(grid_for(n * B)), dim3(256), 0, s, (const float*)U,
+                           w_re, w_im, Fre, Fim, n, B);
     check_launch();
 }
 

@@ -39,7 +39,18 @@ struct StageArgs {
     int mode;
     double fa_re, fa_im, fb_re, fb_im;
     int filter;
+    // batched launches (grid.y = member); mtab == nullptr for a single problem
+    int nmembers;           // members in the launch (>= 1)
+    const double* mtab;     // per-member stage scalars [member][kMemberParams]
+    const int* active;      // member still iterating (0: its workgroups exit)
+    const int* msteps;      // steps per period of each member
+    int step;               // time step of this launch; -1 skips the step check
+    int64_t bstride;        // field elements between consecutive members
+    int64_t gstride;        // geometry elements between members (0: shared)
+    int64_t sstride;        // source elements between members
 };
+// per-member scalars of a batched stage: cy, ca, cu, scos, ssin, fa_re, fa_im, fb_re, fb_im
+constexpr int kMemberParams = 9;
 
 void upload_constants(int q, int precision, const double* D, const double* LIFT, const double* M,
                       const int* fnode, const int* fperm);
@@ -67,6 +78,15 @@ void launch_filter_add(int precision, const void* U, double w_re, double w_im, d
 int dot_partials();
 void launch_dot(int q, const double* U, const double* V, const double* wE, const double* wH,
                 int64_t K, double* partial, double* out_dev, hipStream_t s);
+// Batched forms: members are consecutive blocks of n entries (K elements).
+void launch_dot_batch(int q, const double* U, const double* V, const double* wE, const double* wH,
+                      int64_t wstride, int64_t K, int B, double* partial, double* out_dev, hipStream_t s);
+// z_b = a_b x_b + c_b y_b with coefficient arrays a[B], c[B] in device memory
+void launch_axpby_batch(const double* a, const double* x, const double* c, const double* y, double* z,
+                        int64_t n, int B, hipStream_t s);
+// F_b += w_b field(U_b)
+void launch_filter_add_batch(int precision, const void* U, const double* w_re, const double* w_im,
+                             double* Fre, double* Fim, int64_t n, int B, hipStream_t s);
 // non-finite check: out_dev[0] = 1 if any entry of X is not finite
 void launch_nonfinite(const double* X, int64_t n, int* out_dev, hipStream_t s);
 

@@ -1,0 +1,121 @@
+// Host-side object definitions shared by the single-problem and batched
+// drivers (not part of the ABI).
+#pragma once
+
+#include <complex>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "launch.h"
+
+namespace cmcg {
+
+// Device buffer owned by a host object (hipMalloc / hipFree).
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void alloc(size_t b) {
+        if (p && bytes == b) return;
+        release();
+        if (b == 0) return;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            fail(CMCG_ERR_NOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+        }
+        bytes = b;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T* as() const { return (T*)p; }
+};
+
+// Small pinned host staging area for scalar read-backs.
+struct HostPinned {
+    double* p = nullptr;
+    explicit HostPinned(size_t n = 16) {
+        if (hipHostMalloc((void**)&p, n * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            fail(CMCG_ERR_NOMEM, "hipHostMalloc failed");
+        }
+    }
+    ~HostPinned() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
+struct SpaceData {
+    std::shared_ptr<MeshData> mesh;
+    int q = 1, Np = 4, Nfp = 3, precision = CMCG_FP64, device = 0;
+    int64_t K = 0, ndof = 0;
+    std::vector<int32_t> conn_h;
+    DevBuf conn;
+    size_t esize() const { return precision == CMCG_FP64 ? 8 : 4; }
+};
+
+// time-stepping configuration of one solve
+struct StepCfg {
+    int M = 0;
+    int scheme = 2;
+    double dt = 0, T = 0;
+    double alpha = 1.0;  // flux parameter
+};
+
+}  // namespace cmcg
+
+struct cmcg_space {
+    std::shared_ptr<cmcg::SpaceData> d;
+};
+
+struct cmcg_problem {
+    std::shared_ptr<cmcg::SpaceData> sp;
+    double omega = 0;
+    std::vector<double> eps, mu, sigma;
+    bool has_j = false, has_g = false;
+    // device data
+    cmcg::DevBuf geo, wE, wH, Sre, Sim;
+    double geo_alpha = -1;
+    int src_rows = 0;
+    // work buffers
+    cmcg::DevBuf U, Y1, Y2, Acc, Fre, Fim, Kbuf;
+    cmcg::DevBuf v_u, v_r, v_d, v_a, v_w, v_gs, v_t;
+    cmcg::DevBuf partial, scal;
+    std::unique_ptr<cmcg::HostPinned> pinned;
+    hipStream_t cap_stream = nullptr;
+    std::map<int64_t, hipGraphExec_t> graphs;
+    ~cmcg_problem() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
+};
+
+struct cmcg_result {
+    std::shared_ptr<cmcg::SpaceData> sp;
+    cmcg::DevBuf Fre, Fim, U0;
+    cmcg_stats st{};
+    std::vector<double> history;
+};
+
+namespace cmcg {
+// helpers defined in solver.cpp
+void ensure_constants(int device, int q);
+int current_device();
+StepCfg step_config(const cmcg_problem* p, const cmcg_options* o);
+void hermite_weights(double omega, double dt, std::complex<double> xi[4]);
+void build_geo(cmcg_problem* p, double alpha);
+void prepare(cmcg_problem* p, const StepCfg& c);
+cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st);
+void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipStream_t st, cmcg_result** out);
+}  // namespace cmcg

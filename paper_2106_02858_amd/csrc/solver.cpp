@@ -9,8 +9,7 @@
 #include <map>
 #include <mutex>
 
-#include "internal.h"
-#include "launch.h"
+#include "objects.h"
 
 namespace cmcg {
 
@@ -24,54 +23,13 @@ void set_last_error(const std::string& msg) { g_last_error = msg; }
 std::shared_ptr<MeshData> build_mesh(int64_t nv, const double* xyz, int64_t K, const int64_t* tet,
                                      const int8_t* face_tag);
 
-// ------------------------------------------------------------ device memory
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    DevBuf() = default;
-    DevBuf(const DevBuf&) = delete;
-    DevBuf& operator=(const DevBuf&) = delete;
-    ~DevBuf() { release(); }
-    void alloc(size_t b) {
-        if (p && bytes == b) return;
-        release();
-        if (b == 0) return;
-        hipError_t e = hipMalloc(&p, b);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-            fail(CMCG_ERR_NOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
-        }
-        bytes = b;
-    }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    template <typename T> T* as() const { return (T*)p; }
-};
-
-struct HostPinned {
-    double* p = nullptr;
-    HostPinned() {
-        if (hipHostMalloc((void**)&p, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-            (void)hipGetLastError();
-            fail(CMCG_ERR_NOMEM, "hipHostMalloc failed");
-        }
-    }
-    ~HostPinned() {
-        if (p) (void)hipHostFree(p);
-    }
-};
-
 // ----------------------------------------------------------- device constants
 namespace {
 std::mutex g_const_mu;
 bool g_const_done[64][kMaxQ + 1];
 }
 
-static void ensure_constants(int device, int q) {
+void ensure_constants(int device, int q) {
     std::lock_guard<std::mutex> lk(g_const_mu);
     if (device < 0 || device >= 64) fail(CMCG_ERR_DEVICE, "device index out of range");
     if (g_const_done[device][q]) return;
@@ -80,41 +38,15 @@ static void ensure_constants(int device, int q) {
     g_const_done[device][q] = true;
 }
 
-static int current_device() {
+int current_device() {
     int d = 0;
     CMCG_HIP(hipGetDevice(&d));
     return d;
 }
 
-// ----------------------------------------------------------------- space
-struct SpaceData {
-    std::shared_ptr<MeshData> mesh;
-    int q = 1, Np = 4, Nfp = 3, precision = CMCG_FP64, device = 0;
-    int64_t K = 0, ndof = 0;
-    std::vector<int32_t> conn_h;
-    DevBuf conn;
-    size_t esize() const { return precision == CMCG_FP64 ? 8 : 4; }
-};
-
-}  // namespace cmcg
-
-struct cmcg_space {
-    std::shared_ptr<cmcg::SpaceData> d;
-};
-
-namespace cmcg {
-
-// time-stepping configuration of one solve
-struct StepCfg {
-    int M = 0;
-    int scheme = 2;
-    double dt = 0, T = 0;
-    double alpha = 1.0;  // flux parameter
-};
-
 // Hermite weights xi_ij = int_0^dt h_ij(s) e^{-i w s} ds by the power series
 // of the exponential (long double), h_ij the cubic Hermite basis on [0, dt].
-static void hermite_weights(double omega, double dt, std::complex<double> xi[4]) {
+void hermite_weights(double omega, double dt, std::complex<double> xi[4]) {
     using LD = long double;
     const LD th = (LD)omega * (LD)dt;
     std::complex<LD> mu[4];
@@ -136,39 +68,10 @@ static void hermite_weights(double omega, double dt, std::complex<double> xi[4])
 
 }  // namespace cmcg
 
-struct cmcg_problem {
-    std::shared_ptr<cmcg::SpaceData> sp;
-    double omega = 0;
-    std::vector<double> eps, mu, sigma;
-    bool has_j = false, has_g = false;
-    // device data
-    cmcg::DevBuf geo, wE, wH, Sre, Sim;
-    double geo_alpha = -1;
-    int src_rows = 0;
-    // work buffers
-    cmcg::DevBuf U, Y1, Y2, Acc, Fre, Fim, Kbuf;
-    cmcg::DevBuf v_u, v_r, v_d, v_a, v_w, v_gs, v_t;
-    cmcg::DevBuf partial, scal;
-    std::unique_ptr<cmcg::HostPinned> pinned;
-    hipStream_t cap_stream = nullptr;
-    std::map<int64_t, hipGraphExec_t> graphs;
-    ~cmcg_problem() {
-        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
-        if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    }
-};
-
-struct cmcg_result {
-    std::shared_ptr<cmcg::SpaceData> sp;
-    cmcg::DevBuf Fre, Fim, U0;
-    cmcg_stats st{};
-    std::vector<double> history;
-};
-
 namespace cmcg {
 
 // ------------------------------------------------------------- problem setup
-static void build_geo(cmcg_problem* p, double alpha) {
+void build_geo(cmcg_problem* p, double alpha) {
     const SpaceData& s = *p->sp;
     const MeshData& m = *s.mesh;
     const int64_t K = s.K;
@@ -303,7 +206,7 @@ static cmcg_problem* make_problem(const cmcg_space* sh, const double* eps, const
 }
 
 // -------------------------------------------------------------- time stepping
-static StepCfg step_config(const cmcg_problem* p, const cmcg_options* o) {
+StepCfg step_config(const cmcg_problem* p, const cmcg_options* o) {
     const SpaceData& s = *p->sp;
     StepCfg c;
     c.scheme = o->scheme == CMCG_SCHEME_AUTO ? (s.q == 1 ? 2 : 4) : o->scheme;
@@ -526,7 +429,7 @@ static double dot(cmcg_problem* p, const double* U, const double* V, hipStream_t
     return p->pinned->p[0];
 }
 
-static void prepare(cmcg_problem* p, const StepCfg& c) {
+void prepare(cmcg_problem* p, const StepCfg& c) {
     if (current_device() != p->sp->device) fail(CMCG_ERR_STATE, "wrong current device");
     ensure_constants(p->sp->device, p->sp->q);
     if (p->geo_alpha != c.alpha) {
@@ -537,7 +440,7 @@ static void prepare(cmcg_problem* p, const StepCfg& c) {
     ensure_work(p);
 }
 
-static cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st) {
+cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st) {
     const StepCfg c = step_config(p, o);
     prepare(p, c);
     const SpaceData& s = *p->sp;
@@ -835,6 +738,31 @@ int cmcg_solve(cmcg_problem* p, const cmcg_options* o, const double* u0_dev, hip
     cmcg_result* r = solve(p, o, u0_dev, stream);
     *out = r;
     return r->st.status;
+    CMCG_GUARD_END
+}
+
+int cmcg_solve_batch(cmcg_problem* const* problems, int n, const cmcg_options* o, hipStream_t stream,
+                     cmcg_result** results) {
+    CMCG_GUARD_BEGIN
+    if (!results || !problems || n < 1) fail(CMCG_ERR_ARG, "solve_batch: NULL argument or empty batch");
+    for (int b = 0; b < n; ++b) results[b] = nullptr;
+    cmcg_options def;
+    cmcg_options_default(&def);
+    if (!o) o = &def;
+    if (o->max_iter < 0 || o->fixed_iters < 0) fail(CMCG_ERR_ARG, "solve_batch: negative iteration count");
+    try {
+        solve_batch(problems, n, o, stream, results);
+    } catch (...) {
+        for (int b = 0; b < n; ++b) {
+            delete results[b];
+            results[b] = nullptr;
+        }
+        throw;
+    }
+    int status = CMCG_OK;
+    for (int b = 0; b < n; ++b)
+        if (results[b]->st.status != CMCG_OK) status = CMCG_NOT_CONVERGED;
+    return status;
     CMCG_GUARD_END
 }
 
