@@ -45,6 +45,14 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=2, help="RK steps of the CPU oracle sample")
     ap.add_argument("--kernel-periods", type=int, default=3)
+    ap.add_argument("--workload", choices=["large_single", "batched", "serving"], default="large_single",
+                    help="large_single (default bench line), the 64-member batched configuration, or the "
+                         "Poisson request stream through the serving engine")
+    ap.add_argument("--members", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=60, help="serving: requests taken from the stream")
+    ap.add_argument("--rate", type=float, default=20.0, help="serving: Poisson arrival rate (req/s)")
+    ap.add_argument("--slots", type=int, default=8, help="serving: engine slots")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: engine memory budget")
     return ap.parse_args()
 
 
@@ -82,11 +90,92 @@ def cpu_baseline(w, steps: int):
                       f"({ndof} dofs), FP64 numpy oracle, {el:.1f} s"}
 
 
+def batched(a):
+    """64 independent solves on the 12^3 x 6 = 10368-tet P2 mesh (omega in
+    [2 pi, 6 pi], seeded centres and polarisations, eps = mu = 1), FP32 fields,
+    advanced by one batched CMCG; value = aggregate dof-updates/s."""
+    import torch
+
+    from paper_2106_02858_amd import cmcg, inputs
+    torch.cuda.set_device(0)
+    ws = inputs.batched_members(n=12 if a.n == 20 else a.n, q=2, B=a.members)
+    w0 = ws[0]
+    mesh = cmcg.cmcg_mesh_create(w0.xyz, w0.tet, w0.tags)
+    s = cmcg.cmcg_space_create(mesh, w0.q, cmcg.CMCG_FP32)
+    nodes = cmcg.cmcg_space_nodes(s)
+    probs = [cmcg.cmcg_problem_create(s, w.eps, w.mu, None, w.omega,
+                                      inputs.gaussian_current(nodes, w.centre, w.width, w.pol)) for w in ws]
+    info = cmcg.cmcg_space_info(s)
+    opts = cmcg.cmcg_options_default(tol=a.tol, max_iter=2000)
+    t_ref = [time.perf_counter()]
+
+    def progress(it, rel):
+        if it % 10 == 0:
+            log(f"  iter {it} worst rel {rel:.3e} t {time.perf_counter() - t_ref[0]:.1f}s")
+        return False
+
+    opts.set_progress(progress)
+    for _ in range(a.warmup):
+        t_ref[0] = time.perf_counter()
+        cmcg.cmcg_solve_batch(probs, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dof = 0.0
+    for _ in range(a.steps):
+        t_ref[0] = time.perf_counter()
+        res = cmcg.cmcg_solve_batch(probs, opts)
+        sts = [cmcg.cmcg_result_stats(r) for r in res]
+        dof += sum(st["dof_updates"] for st in sts)
+        log(f"batched solve: max iters {max(st['iters'] for st in sts)} seconds {sts[0]['seconds']:.2f}")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    Ms = [st["steps"] for st in sts]
+    out = {"metric": "DG dof-updates/s; CMCG time-to-1e-6 residual vs FP64 plain; p50/p99 latency",
+           "value": dof / el, "unit": "dof-updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": el / a.steps * 1e3, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"batched: {a.members} solves on the {info['K']}-tet P2 mesh, omega in [2pi,6pi], "
+                                  f"FP32 fields, CMCG to {a.tol:g} + filter", "members": a.members, "K": info["K"],
+                      "q": 2, "steps_per_period_min": min(Ms), "steps_per_period_max": max(Ms)},
+           "cmcg": {"iters_min": min(st["iters"] for st in sts), "iters_max": max(st["iters"] for st in sts),
+                    "time_to_1e-6_all_members_s": max(st["seconds_to_1e6"] for st in sts),
+                    "seconds": sts[0]["seconds"]}}
+    print(json.dumps(out), flush=True)
+
+
+def served(a):
+    """The request stream (n in {8,12,16,24}, q in {1,2,3}, omega in [2pi,8pi],
+    eps per cube in {1,2,4}, Poisson arrivals) through the serving engine."""
+    import torch
+
+    from paper_2106_02858_amd import cmcg, inputs, serving
+    torch.cuda.set_device(0)
+    reqs = inputs.serving_stream(n_requests=2000, rate=a.rate)[: a.requests]
+    out = serving.serve(reqs, budget_bytes=int(a.budget_gb * 2 ** 30), max_slots=a.slots, tol=a.tol,
+                        log=log)
+    res = {"metric": "DG dof-updates/s; CMCG time-to-1e-6 residual vs FP64 plain; p50/p99 latency",
+           "value": out["dof_updates_per_s"], "unit": "dof-updates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": out["elapsed"] * 1e3, "higher_is_better": True, "scaling": "strong",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"serving: first {a.requests} requests of the 2000-request Poisson stream at "
+                                  f"{a.rate:g} req/s (n in 8,12,16,24; q in 1,2,3), {a.slots} slots, "
+                                  f"{a.budget_gb:g} GB budget, CMCG to {a.tol:g}"},
+           "serving": {k: out[k] for k in ("completed", "elapsed", "throughput", "p50", "p99", "offered_rate",
+                                           "engine_steps")}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if a.workload == "batched":
+        batched(a)
+        return
+    if a.workload == "serving":
+        served(a)
+        return
     import numpy as np
     import torch
 

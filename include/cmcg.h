@@ -50,6 +50,7 @@
 #ifndef CMCG_H
 #define CMCG_H
 
+#include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime_api.h>
 
@@ -236,6 +237,40 @@ int cmcg_debug_period(cmcg_problem* p, const cmcg_options* o, int direction,
                       double* f_re_dev, double* f_im_dev, hipStream_t stream);
 int cmcg_debug_dot(cmcg_problem* p, const double* u_dev, const double* v_dev, double* out,
                    hipStream_t stream);
+
+/* ------------------------------------------------------------ serving -- */
+/* Continuous batching of independent solve requests (any mesh, order,
+ * frequency, source).  Each admitted problem occupies a slot with its own
+ * stream and runs exactly the launch sequence of cmcg_solve (Algorithms 1-3 +
+ * filter period), so its result equals the one cmcg_solve returns.
+ *
+ * cmcg_problem_footprint: device bytes a solve of p keeps resident (problem
+ *   data, field / filter / CG vectors, result) -- the admission cost.
+ * cmcg_engine_create: budget = device bytes the engine may hold for admitted
+ *   solves; max_slots = concurrent solves (1..1024).
+ * cmcg_engine_admit: starts a solve in a free slot; CMCG_ERR_NOMEM when no
+ *   slot is free or the footprint does not fit the remaining budget (the
+ *   caller keeps the request queued), CMCG_ERR_STATE when p is already held
+ *   by a slot.  p must stay alive until the slot is collected or cancelled.
+ * cmcg_engine_step: advances every running slot by one chunk of work (the
+ *   initial periods, one half of a CG iteration, or the filter period);
+ *   reports how many slots still run and how many wait for collection.
+ * cmcg_engine_poll: slot state 0 free, 1 running, 2 finished, 3 failed.
+ * cmcg_engine_collect: hands over the result of a finished slot and frees it
+ *   (returns the solve's status, or its error code for a failed slot).
+ * cmcg_engine_cancel: stops a slot and frees it.
+ * Not thread-safe; calls must come from one thread with the engine's device
+ * current. */
+typedef struct cmcg_engine cmcg_engine;
+int cmcg_problem_footprint(const cmcg_problem* p, size_t* bytes);
+int cmcg_engine_create(size_t hbm_budget, int max_slots, cmcg_engine** out);
+void cmcg_engine_destroy(cmcg_engine* e);
+int cmcg_engine_admit(cmcg_engine* e, cmcg_problem* p, const cmcg_options* o, int* slot);
+int cmcg_engine_step(cmcg_engine* e, int* n_running, int* n_finished);
+int cmcg_engine_poll(const cmcg_engine* e, int slot, int* state);
+int cmcg_engine_collect(cmcg_engine* e, int slot, cmcg_result** out);
+int cmcg_engine_cancel(cmcg_engine* e, int slot);
+int cmcg_engine_info(const cmcg_engine* e, size_t* used, int* n_running, int* n_finished);
 
 /* ------------------------------------------------------------- tuning -- */
 /* Stage-kernel implementation variant for (q, precision): 0 gathers each

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcmcg.so")
 
-SOURCES = ["refelem.cpp", "mesh.cpp", "solver.cpp", "batch.cpp", "kernels.hip"]
+SOURCES = ["refelem.cpp", "mesh.cpp", "solver.cpp", "batch.cpp", "engine.cpp", "kernels.hip"]
 ARCH = os.environ.get("CMCG_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{os.path.join(ROOT, 'include')}"]

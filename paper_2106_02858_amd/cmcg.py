@@ -44,6 +44,8 @@ EXPORTED = [
     "cmcg_solve", "cmcg_solve_batch", "cmcg_result_fields", "cmcg_result_filtered_device", "cmcg_result_initial_device",
     "cmcg_result_stats", "cmcg_result_history", "cmcg_result_destroy",
     "cmcg_debug_rhs", "cmcg_debug_period", "cmcg_debug_dot", "cmcg_tune_stage", "cmcg_tune_get_stage",
+    "cmcg_problem_footprint", "cmcg_engine_create", "cmcg_engine_destroy", "cmcg_engine_admit",
+    "cmcg_engine_step", "cmcg_engine_poll", "cmcg_engine_collect", "cmcg_engine_cancel", "cmcg_engine_info",
 ]
 
 
@@ -100,6 +102,15 @@ _sig = {
     "cmcg_debug_period": (C.c_int, [P, C.POINTER(cmcg_options), C.c_int, C.c_int, P, P, P, P, P]),
     "cmcg_debug_dot": (C.c_int, [P, P, P, D, P]),
     "cmcg_tune_stage": (C.c_int, [C.c_int, C.c_int, C.c_int]),
+    "cmcg_problem_footprint": (C.c_int, [P, C.POINTER(C.c_size_t)]),
+    "cmcg_engine_create": (C.c_int, [C.c_size_t, C.c_int, C.POINTER(P)]),
+    "cmcg_engine_destroy": (None, [P]),
+    "cmcg_engine_admit": (C.c_int, [P, P, C.POINTER(cmcg_options), C.POINTER(C.c_int)]),
+    "cmcg_engine_step": (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "cmcg_engine_poll": (C.c_int, [P, C.c_int, C.POINTER(C.c_int)]),
+    "cmcg_engine_collect": (C.c_int, [P, C.c_int, C.POINTER(P)]),
+    "cmcg_engine_cancel": (C.c_int, [P, C.c_int]),
+    "cmcg_engine_info": (C.c_int, [P, C.POINTER(C.c_size_t), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "cmcg_tune_get_stage": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
 }
 for _n, (_r, _a) in _sig.items():
@@ -338,3 +349,58 @@ def cmcg_tune_get_stage(q: int, precision: int) -> int:
     v = C.c_int()
     _check(_lib.cmcg_tune_get_stage(q, precision, C.byref(v)))
     return v.value
+
+
+class Engine(_Handle):
+    _destroy = "cmcg_engine_destroy"
+
+
+def cmcg_problem_footprint(p: Problem) -> int:
+    b = C.c_size_t()
+    _check(_lib.cmcg_problem_footprint(p.h, C.byref(b)))
+    return b.value
+
+
+def cmcg_engine_create(hbm_budget: int, max_slots: int) -> Engine:
+    h = P()
+    _check(_lib.cmcg_engine_create(int(hbm_budget), int(max_slots), C.byref(h)))
+    return Engine(h)
+
+
+def cmcg_engine_admit(e: Engine, p: Problem, opts: cmcg_options | None = None):
+    """Slot index, or None when the request does not fit now (keep it queued)."""
+    o = opts or cmcg_options_default()
+    slot = C.c_int(-1)
+    rc = _lib.cmcg_engine_admit(e.h, p.h, C.byref(o), C.byref(slot))
+    if rc == CMCG_ERR_NOMEM:
+        return None
+    _check(rc)
+    return slot.value
+
+
+def cmcg_engine_step(e: Engine):
+    r, f = C.c_int(), C.c_int()
+    _check(_lib.cmcg_engine_step(e.h, C.byref(r), C.byref(f)))
+    return r.value, f.value
+
+
+def cmcg_engine_poll(e: Engine, slot: int) -> int:
+    st = C.c_int()
+    _check(_lib.cmcg_engine_poll(e.h, slot, C.byref(st)))
+    return st.value
+
+
+def cmcg_engine_collect(e: Engine, slot: int, problem: Problem | None = None) -> Result:
+    h = P()
+    _check(_lib.cmcg_engine_collect(e.h, slot, C.byref(h)), allow=(CMCG_OK, CMCG_NOT_CONVERGED))
+    return Result(h, keep=(problem,) if problem is not None else ())
+
+
+def cmcg_engine_cancel(e: Engine, slot: int):
+    _check(_lib.cmcg_engine_cancel(e.h, slot))
+
+
+def cmcg_engine_info(e: Engine):
+    u, r, f = C.c_size_t(), C.c_int(), C.c_int()
+    _check(_lib.cmcg_engine_info(e.h, C.byref(u), C.byref(r), C.byref(f)))
+    return dict(used=u.value, running=r.value, finished=f.value)

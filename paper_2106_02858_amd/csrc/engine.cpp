@@ -1,0 +1,221 @@
+// Serving engine: continuous batching of independent CMCG solves.
+//
+// Requests (problems of any mesh, order and frequency) are admitted into
+// slots while their device working set fits the memory budget; each slot
+// owns a HIP stream and a CMCG state machine (CgRun).  cmcg_engine_step
+// visits the running slots in turn: it waits for the slot's in-flight chunk,
+// consumes its scalars and enqueues the next chunk, so while the host waits
+// for one slot the others' periods run on the device.  Finished solves stay
+// resident until collected, which frees the slot and its budget.  A slot runs
+// exactly the launch sequence of cmcg_solve, so a served result equals the
+// same problem solved alone.
+#include "objects.h"
+
+struct cmcg_engine {
+    struct Slot {
+        int state = 0;  // 0 free, 1 running, 2 finished, 3 failed
+        cmcg_problem* p = nullptr;
+        size_t bytes = 0;
+        hipStream_t st = nullptr;
+        std::unique_ptr<cmcg::CgRun> run;
+        std::unique_ptr<cmcg_result> result;
+        int err = 0;
+        std::string msg;
+    };
+    int device = 0;
+    size_t budget = 0, used = 0;
+    std::vector<Slot> slots;
+    ~cmcg_engine() {
+        for (auto& s : slots) {
+            if (s.st) {
+                (void)hipStreamSynchronize(s.st);
+                (void)hipStreamDestroy(s.st);
+            }
+        }
+    }
+};
+
+namespace cmcg {
+
+// Device bytes a solve of p keeps resident: the problem's own data
+// (geometry, source, mass weights) plus the solve's field, filter and CG
+// vectors and its result.
+size_t footprint(const cmcg_problem* p) {
+    const SpaceData& s = *p->sp;
+    const size_t n = s.ndof, es = s.esize(), K = s.K;
+    size_t b = K * kGeo * es + 2 * K * 8;  // geometry, mass weights
+    if (p->src_rows) b += 2 * n * es;      // source
+    b += 5 * n * es;                       // U, Y1, Y2, Acc, RHS buffer
+    b += 2 * n * 8;                        // filter accumulators
+    b += 6 * n * 8;                        // CG vectors
+    b += 3 * n * 8;                        // result
+    return b + (size_t)dot_partials() * 8 + 4096;
+}
+
+}  // namespace cmcg
+
+using namespace cmcg;
+
+#define ENGINE_GUARD_BEGIN try {
+#define ENGINE_GUARD_END          \
+    }                             \
+    catch (const Error& e) {      \
+        set_last_error(e.msg);    \
+        return e.code;            \
+    }                             \
+    catch (const std::exception& e) { \
+        set_last_error(e.what()); \
+        return CMCG_ERR_ARG;      \
+    }
+
+extern "C" {
+
+int cmcg_problem_footprint(const cmcg_problem* p, size_t* bytes) {
+    ENGINE_GUARD_BEGIN
+    if (!p || !bytes) fail(CMCG_ERR_ARG, "problem_footprint: NULL argument");
+    *bytes = footprint(p);
+    return CMCG_OK;
+    ENGINE_GUARD_END
+}
+
+int cmcg_engine_create(size_t hbm_budget, int max_slots, cmcg_engine** out) {
+    ENGINE_GUARD_BEGIN
+    if (!out) fail(CMCG_ERR_ARG, "engine_create: NULL output");
+    *out = nullptr;
+    if (max_slots < 1 || max_slots > 1024) fail(CMCG_ERR_ARG, "engine_create: max_slots must be 1..1024");
+    std::unique_ptr<cmcg_engine> e(new cmcg_engine());
+    e->device = current_device();
+    e->budget = hbm_budget;
+    e->slots.resize(max_slots);
+    for (auto& s : e->slots) CMCG_HIP(hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking));
+    *out = e.release();
+    return CMCG_OK;
+    ENGINE_GUARD_END
+}
+
+void cmcg_engine_destroy(cmcg_engine* e) { delete e; }
+
+int cmcg_engine_admit(cmcg_engine* e, cmcg_problem* p, const cmcg_options* o, int* slot) {
+    ENGINE_GUARD_BEGIN
+    if (!e || !p || !slot) fail(CMCG_ERR_ARG, "engine_admit: NULL argument");
+    *slot = -1;
+    if (current_device() != e->device) fail(CMCG_ERR_STATE, "engine_admit: wrong current device");
+    cmcg_options def;
+    cmcg_options_default(&def);
+    if (!o) o = &def;
+    int free_slot = -1;
+    for (int i = 0; i < (int)e->slots.size(); ++i) {
+        const auto& s = e->slots[i];
+        if (s.state != 0 && s.p == p) fail(CMCG_ERR_STATE, "engine_admit: problem already held by a slot");
+        if (s.state == 0 && free_slot < 0) free_slot = i;
+    }
+    if (free_slot < 0) fail(CMCG_ERR_NOMEM, "engine_admit: no free slot");
+    const size_t need = footprint(p);
+    if (e->used + need > e->budget) fail(CMCG_ERR_NOMEM, "engine_admit: over the memory budget");
+    auto& s = e->slots[free_slot];
+    s.run.reset(new CgRun());
+    s.run->start(p, o, nullptr, s.st);
+    s.state = 1;
+    s.p = p;
+    s.bytes = need;
+    s.err = 0;
+    s.msg.clear();
+    e->used += need;
+    *slot = free_slot;
+    return CMCG_OK;
+    ENGINE_GUARD_END
+}
+
+int cmcg_engine_step(cmcg_engine* e, int* n_running, int* n_finished) {
+    ENGINE_GUARD_BEGIN
+    if (!e) fail(CMCG_ERR_ARG, "engine_step: NULL engine");
+    int running = 0, finished = 0;
+    for (auto& s : e->slots) {
+        if (s.state != 1) continue;
+        try {
+            CMCG_HIP(hipStreamSynchronize(s.st));
+            s.run->complete();
+            if (s.run->done()) {
+                s.result = std::move(s.run->res);
+                s.run.reset();
+                s.state = 2;
+            }
+        } catch (const Error& err) {
+            (void)hipStreamSynchronize(s.st);
+            s.run.reset();
+            s.state = 3;
+            s.err = err.code;
+            s.msg = err.msg;
+        }
+    }
+    for (auto& s : e->slots) {
+        running += s.state == 1;
+        finished += s.state >= 2;
+    }
+    if (n_running) *n_running = running;
+    if (n_finished) *n_finished = finished;
+    return CMCG_OK;
+    ENGINE_GUARD_END
+}
+
+int cmcg_engine_poll(const cmcg_engine* e, int slot, int* state) {
+    ENGINE_GUARD_BEGIN
+    if (!e || !state || slot < 0 || slot >= (int)e->slots.size()) fail(CMCG_ERR_ARG, "engine_poll: bad argument");
+    *state = e->slots[slot].state;
+    return CMCG_OK;
+    ENGINE_GUARD_END
+}
+
+int cmcg_engine_collect(cmcg_engine* e, int slot, cmcg_result** out) {
+    ENGINE_GUARD_BEGIN
+    if (!e || !out || slot < 0 || slot >= (int)e->slots.size()) fail(CMCG_ERR_ARG, "engine_collect: bad argument");
+    *out = nullptr;
+    auto& s = e->slots[slot];
+    if (s.state != 2 && s.state != 3) fail(CMCG_ERR_STATE, "engine_collect: slot has no finished solve");
+    const int code = s.state == 3 ? s.err : CMCG_OK;
+    const std::string msg = s.msg;
+    cmcg_result* r = s.result.release();
+    e->used -= s.bytes;
+    s.state = 0;
+    s.p = nullptr;
+    s.bytes = 0;
+    s.result.reset();
+    s.run.reset();
+    if (code != CMCG_OK) fail(code, "engine_collect: the solve failed: " + msg);
+    *out = r;
+    return r->st.status;
+    ENGINE_GUARD_END
+}
+
+int cmcg_engine_cancel(cmcg_engine* e, int slot) {
+    ENGINE_GUARD_BEGIN
+    if (!e || slot < 0 || slot >= (int)e->slots.size()) fail(CMCG_ERR_ARG, "engine_cancel: bad argument");
+    auto& s = e->slots[slot];
+    if (s.state == 0) fail(CMCG_ERR_STATE, "engine_cancel: slot is free");
+    CMCG_HIP(hipStreamSynchronize(s.st));
+    e->used -= s.bytes;
+    s.run.reset();
+    s.result.reset();
+    s.state = 0;
+    s.p = nullptr;
+    s.bytes = 0;
+    return CMCG_OK;
+    ENGINE_GUARD_END
+}
+
+int cmcg_engine_info(const cmcg_engine* e, size_t* used, int* running, int* finished) {
+    ENGINE_GUARD_BEGIN
+    if (!e) fail(CMCG_ERR_ARG, "engine_info: NULL engine");
+    int r = 0, f = 0;
+    for (const auto& s : e->slots) {
+        r += s.state == 1;
+        f += s.state >= 2;
+    }
+    if (used) *used = e->used;
+    if (running) *running = r;
+    if (finished) *finished = f;
+    return CMCG_OK;
+    ENGINE_GUARD_END
+}
+
+}  // extern "C"

@@ -2,6 +2,7 @@
 // drivers (not part of the ABI).
 #pragma once
 
+#include <chrono>
 #include <complex>
 #include <map>
 #include <memory>
@@ -109,6 +110,34 @@ struct cmcg_result {
 };
 
 namespace cmcg {
+
+// One CMCG solve as a resumable sequence of asynchronous chunks (see
+// solver.cpp); cmcg_solve drives it to the end, the serving engine
+// interleaves many of them on separate streams.
+struct CgRun {
+    enum { kStart = 0, kAwaitDA, kAwaitRR, kFinal, kDone };
+    cmcg_problem* p = nullptr;
+    cmcg_options o{};
+    StepCfg c;
+    hipStream_t st = nullptr;
+    const double* u0 = nullptr;
+    std::unique_ptr<cmcg_result> res;
+    int phase = kDone;
+    int64_t n = 0;
+    int it = 0, periods = 0, refresh = 0, limit = 0;
+    bool fixed = false, stopped = false;
+    double rr = 0, rr0 = 0, rel = 1, t6 = -1, J0 = 0;
+    std::chrono::steady_clock::time_point t0;
+    void start(cmcg_problem* pr, const cmcg_options* opt, const double* u0_, hipStream_t s_);
+    void complete();
+    bool done() const { return phase == kDone; }
+    double secs() const;
+
+  private:
+    void decide();
+    void gradient(double* out);
+};
+
 // helpers defined in solver.cpp
 void ensure_constants(int device, int q);
 int current_device();

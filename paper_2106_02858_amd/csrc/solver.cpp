@@ -408,7 +408,7 @@ static void run_period(cmcg_problem* p, const StepCfg& c, bool src, bool filt, b
 }
 
 // X (FP64 dof vector) -> propagate one period -> Y = S^d P S^d X - sub
-static void apply_period(cmcg_problem* p, const StepCfg& c, const cmcg_options* o, const double* X, double* Yo,
+void apply_period(cmcg_problem* p, const StepCfg& c, const cmcg_options* o, const double* X, double* Yo,
                          const double* sub, int direction, bool src, bool filt, hipStream_t st) {
     const SpaceData& s = *p->sp;
     const int flip = direction < 0 ? 1 : 0;
@@ -420,7 +420,7 @@ static void apply_period(cmcg_problem* p, const StepCfg& c, const cmcg_options* 
     if (Yo) launch_from_field(s.precision, s.Np, p->U.p, Yo, sub, s.ndof, flip, st);
 }
 
-static double dot(cmcg_problem* p, const double* U, const double* V, hipStream_t st) {
+double dot(cmcg_problem* p, const double* U, const double* V, hipStream_t st) {
     const SpaceData& s = *p->sp;
     launch_dot(s.q, U, V, p->wE.as<double>(), p->wH.as<double>(), s.K, p->partial.as<double>(), p->scal.as<double>(),
                st);
@@ -440,11 +440,30 @@ void prepare(cmcg_problem* p, const StepCfg& c) {
     ensure_work(p);
 }
 
-cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st) {
-    const StepCfg c = step_config(p, o);
+// Inner product (U, V)_{eps,mu} into pinned slot k, ordered on the stream
+// (read after the stream has been synchronised).
+static void dot_async(cmcg_problem* p, const double* U, const double* V, int k, hipStream_t st) {
+    const SpaceData& s = *p->sp;
+    launch_dot(s.q, U, V, p->wE.as<double>(), p->wH.as<double>(), s.K, p->partial.as<double>(),
+               p->scal.as<double>() + k, st);
+    CMCG_HIP(hipMemcpyAsync(p->pinned->p + k, p->scal.as<double>() + k, 8, hipMemcpyDeviceToHost, st));
+}
+
+// --------------------------------------------------------- CMCG state machine
+// Algorithm 3 as a sequence of asynchronous chunks: start() enqueues
+// Algorithm 1 and the first inner products; every complete() (called once the
+// stream has drained) consumes the scalars of the last chunk and enqueues the
+// next one.  Chunks: [A] the two periods of (I-P*)(I-P) D and (D, A);
+// [B] the U, R updates (+ residual refresh) and (R, R); [F] the filter period.
+void CgRun::start(cmcg_problem* pr, const cmcg_options* opt, const double* u0_, hipStream_t s_) {
+    p = pr;
+    o = *opt;
+    st = s_;
+    u0 = u0_;
+    c = step_config(p, &o);
     prepare(p, c);
     const SpaceData& s = *p->sp;
-    const int64_t n = s.ndof;
+    n = s.ndof;
     const size_t db = n * 8;
     p->v_u.alloc(db);
     p->v_r.alloc(db);
@@ -452,28 +471,25 @@ cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hip
     p->v_a.alloc(db);
     p->v_w.alloc(db);
     p->v_gs.alloc(db);
-    double *U = p->v_u.as<double>(), *R = p->v_r.as<double>(), *D = p->v_d.as<double>(), *A = p->v_a.as<double>(),
-           *W = p->v_w.as<double>(), *Gs = p->v_gs.as<double>();
-    std::unique_ptr<cmcg_result> res(new cmcg_result());
+    res.reset(new cmcg_result());
     res->sp = p->sp;
+    res->Fre.alloc(db);
+    res->Fim.alloc(db);
+    res->U0.alloc(db);
+    fixed = o.fixed_iters > 0;
+    refresh = o.residual_refresh > 0 ? o.residual_refresh
+                                     : (o.residual_refresh == 0 && s.precision == CMCG_FP32 ? 10 : 0);
+    limit = fixed ? o.fixed_iters : o.max_iter;
     CMCG_HIP(hipStreamSynchronize(st));
-    const auto t0 = std::chrono::steady_clock::now();
-    auto secs = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
-    int periods = 0;
+    t0 = std::chrono::steady_clock::now();
+    double *U = p->v_u.as<double>(), *R = p->v_r.as<double>(), *D = p->v_d.as<double>(), *W = p->v_w.as<double>(),
+           *Gs = p->v_gs.as<double>();
     // Algorithm 1: G = P_psi 0 (into W), G_T = P* G, G* = G - G_T
-    apply_period(p, c, o, nullptr, W, nullptr, +1, true, false, st);
-    apply_period(p, c, o, W, Gs, W, -1, false, false, st);  // Gs = P* G - G = -G*
-    launch_axpby(-1.0, Gs, 0.0, Gs, Gs, n, st);             // G* = G - P* G
+    apply_period(p, c, &o, nullptr, W, nullptr, +1, true, false, st);
+    apply_period(p, c, &o, W, Gs, W, -1, false, false, st);  // Gs = P* G - G = -G*
+    launch_axpby(-1.0, Gs, 0.0, Gs, Gs, n, st);              // G* = G - P* G
     periods += 2;
-    const double J0 = 0.5 * dot(p, W, W, st);
-    if (!std::isfinite(J0)) fail(CMCG_ERR_UNSTABLE, "solve: non-finite field after the first period");
-    auto gradient = [&](double* out) {
-        // Algorithm 2: W_T = P U - U, W_0 = P* W_T, J' = W_0 - W_T - G*
-        apply_period(p, c, o, U, W, U, +1, false, false, st);
-        apply_period(p, c, o, W, out, W, -1, false, false, st);
-        launch_axpby(1.0, out, -1.0, Gs, out, n, st);
-        periods += 2;
-    };
+    dot_async(p, W, W, 0, st);
     if (u0) {
         CMCG_HIP(hipMemcpyAsync(U, u0, db, hipMemcpyDeviceToDevice, st));
         gradient(R);
@@ -482,71 +498,116 @@ cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hip
         launch_axpby(-1.0, Gs, 0.0, Gs, R, n, st);  // R0 = -G*
     }
     CMCG_HIP(hipMemcpyAsync(D, R, db, hipMemcpyDeviceToDevice, st));
-    double rr = dot(p, R, R, st);
-    const double rr0 = rr;
-    if (!std::isfinite(rr)) fail(CMCG_ERR_UNSTABLE, "solve: non-finite initial residual");
-    res->history.push_back(1.0);
-    double t6 = -1.0;
-    int it = 0;
-    const bool fixed = o->fixed_iters > 0;
-    const int refresh =
-        o->residual_refresh > 0 ? o->residual_refresh : (o->residual_refresh == 0 && s.precision == CMCG_FP32 ? 10 : 0);
-    const int limit = fixed ? o->fixed_iters : o->max_iter;
-    double rel = 1.0;
-    bool stopped = false;
-    if (rr0 == 0.0) rel = 0.0;
-    while (it < limit) {
-        rel = rr0 > 0 ? std::sqrt(rr / rr0) : 0.0;
-        if (t6 < 0 && rel <= 1e-6) t6 = secs();
-        if (!fixed && rel <= o->tol) break;
-        if (rr0 == 0.0) break;
-        // A = (I - P*)(I - P) D = W_0 - W_T
-        apply_period(p, c, o, D, W, D, +1, false, false, st);
-        apply_period(p, c, o, W, A, W, -1, false, false, st);
-        periods += 2;
-        const double dA = dot(p, D, A, st);
-        if (!std::isfinite(dA)) fail(CMCG_ERR_UNSTABLE, "solve: non-finite values (time step too large?)");
-        if (!(dA > 0)) fail(CMCG_ERR_BREAKDOWN, "solve: CG breakdown, (D, A) <= 0");
-        const double alpha = rr / dA;
-        launch_axpby(-alpha, D, 1.0, U, U, n, st);
-        launch_axpby(-alpha, A, 1.0, R, R, n, st);
-        ++it;
-        if (refresh > 0 && it % refresh == 0) gradient(R);
-        const double rn = dot(p, R, R, st);
-        if (!std::isfinite(rn)) fail(CMCG_ERR_UNSTABLE, "solve: non-finite residual");
-        const double beta = rn / rr;
-        launch_axpby(1.0, R, beta, D, D, n, st);
-        rr = rn;
-        rel = rr0 > 0 ? std::sqrt(rr / rr0) : 0.0;
-        res->history.push_back(rel);
-        if (o->progress && o->progress(o->progress_ctx, it, rel) != 0) {
-            stopped = true;
+    dot_async(p, R, R, 1, st);
+    phase = kStart;
+}
+
+double CgRun::secs() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void CgRun::gradient(double* out) {
+    // Algorithm 2: W_T = P U - U, W_0 = P* W_T, J' = W_0 - W_T - G*
+    double *U = p->v_u.as<double>(), *W = p->v_w.as<double>(), *Gs = p->v_gs.as<double>();
+    apply_period(p, c, &o, U, W, U, +1, false, false, st);
+    apply_period(p, c, &o, W, out, W, -1, false, false, st);
+    launch_axpby(1.0, out, -1.0, Gs, out, n, st);
+    periods += 2;
+}
+
+// convergence test, then the next chunk: [A] or [F]
+void CgRun::decide() {
+    rel = rr0 > 0 ? std::sqrt(rr / rr0) : 0.0;
+    if (t6 < 0 && rel <= 1e-6) t6 = secs();
+    const bool conv = !fixed && rel <= o.tol;
+    if (conv || rr0 == 0.0 || it >= limit || stopped) {
+        // final period with source and filter
+        double* U = p->v_u.as<double>();
+        apply_period(p, c, &o, U, nullptr, nullptr, +1, true, true, st);
+        periods += 1;
+        const size_t db = n * 8;
+        CMCG_HIP(hipMemcpyAsync(res->Fre.p, p->Fre.p, db, hipMemcpyDeviceToDevice, st));
+        CMCG_HIP(hipMemcpyAsync(res->Fim.p, p->Fim.p, db, hipMemcpyDeviceToDevice, st));
+        CMCG_HIP(hipMemcpyAsync(res->U0.p, U, db, hipMemcpyDeviceToDevice, st));
+        phase = kFinal;
+        return;
+    }
+    // A = (I - P*)(I - P) D = W_0 - W_T
+    double *D = p->v_d.as<double>(), *W = p->v_w.as<double>(), *A = p->v_a.as<double>();
+    apply_period(p, c, &o, D, W, D, +1, false, false, st);
+    apply_period(p, c, &o, W, A, W, -1, false, false, st);
+    periods += 2;
+    dot_async(p, D, A, 2, st);
+    phase = kAwaitDA;
+}
+
+void CgRun::complete() {
+    const double* pin = p->pinned->p;
+    double *U = p->v_u.as<double>(), *R = p->v_r.as<double>(), *D = p->v_d.as<double>(), *A = p->v_a.as<double>();
+    switch (phase) {
+        case kStart:
+            J0 = 0.5 * pin[0];
+            if (!std::isfinite(J0)) fail(CMCG_ERR_UNSTABLE, "solve: non-finite field after the first period");
+            rr = rr0 = pin[1];
+            if (!std::isfinite(rr)) fail(CMCG_ERR_UNSTABLE, "solve: non-finite initial residual");
+            res->history.push_back(1.0);
+            if (rr0 == 0.0) rel = 0.0;
+            decide();
+            break;
+        case kAwaitDA: {
+            const double dA = pin[2];
+            if (!std::isfinite(dA)) fail(CMCG_ERR_UNSTABLE, "solve: non-finite values (time step too large?)");
+            if (!(dA > 0)) fail(CMCG_ERR_BREAKDOWN, "solve: CG breakdown, (D, A) <= 0");
+            const double alpha = rr / dA;
+            launch_axpby(-alpha, D, 1.0, U, U, n, st);
+            launch_axpby(-alpha, A, 1.0, R, R, n, st);
+            ++it;
+            if (refresh > 0 && it % refresh == 0) gradient(R);
+            dot_async(p, R, R, 3, st);
+            phase = kAwaitRR;
             break;
         }
+        case kAwaitRR: {
+            const double rn = pin[3];
+            if (!std::isfinite(rn)) fail(CMCG_ERR_UNSTABLE, "solve: non-finite residual");
+            const double beta = rn / rr;
+            launch_axpby(1.0, R, beta, D, D, n, st);
+            rr = rn;
+            rel = rr0 > 0 ? std::sqrt(rr / rr0) : 0.0;
+            res->history.push_back(rel);
+            if (o.progress && o.progress(o.progress_ctx, it, rel) != 0) stopped = true;
+            decide();
+            break;
+        }
+        case kFinal: {
+            if (t6 < 0 && rel <= 1e-6) t6 = secs();
+            cmcg_stats& S = res->st;
+            S.iters = it;
+            S.periods = periods;
+            S.steps = c.M;
+            S.dt = c.dt;
+            S.rel_res = rel;
+            S.J0 = J0;
+            S.seconds = secs();
+            S.seconds_to_1e6 = t6;
+            S.dof_updates = (double)n * c.M * periods;
+            S.status = (stopped || (!fixed && rel > o.tol)) ? CMCG_NOT_CONVERGED : CMCG_OK;
+            phase = kDone;
+            break;
+        }
+        default:
+            fail(CMCG_ERR_STATE, "solve: no work pending");
     }
-    if (t6 < 0 && rel <= 1e-6) t6 = secs();
-    // final period with source and filter
-    apply_period(p, c, o, U, nullptr, nullptr, +1, true, true, st);
-    periods += 1;
-    res->Fre.alloc(db);
-    res->Fim.alloc(db);
-    res->U0.alloc(db);
-    CMCG_HIP(hipMemcpyAsync(res->Fre.p, p->Fre.p, db, hipMemcpyDeviceToDevice, st));
-    CMCG_HIP(hipMemcpyAsync(res->Fim.p, p->Fim.p, db, hipMemcpyDeviceToDevice, st));
-    CMCG_HIP(hipMemcpyAsync(res->U0.p, U, db, hipMemcpyDeviceToDevice, st));
-    CMCG_HIP(hipStreamSynchronize(st));
-    cmcg_stats& S = res->st;
-    S.iters = it;
-    S.periods = periods;
-    S.steps = c.M;
-    S.dt = c.dt;
-    S.rel_res = rel;
-    S.J0 = J0;
-    S.seconds = secs();
-    S.seconds_to_1e6 = t6;
-    S.dof_updates = (double)n * c.M * periods;
-    S.status = (stopped || (!fixed && rel > o->tol)) ? CMCG_NOT_CONVERGED : CMCG_OK;
-    return res.release();
+}
+
+cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st) {
+    CgRun run;
+    run.start(p, o, u0, st);
+    while (!run.done()) {
+        CMCG_HIP(hipStreamSynchronize(st));
+        run.complete();
+    }
+    return run.res.release();
 }
 
 }  // namespace cmcg

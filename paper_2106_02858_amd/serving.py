@@ -1,0 +1,115 @@
+"""Request-serving loop over the engine of the C ABI (continuous batching).
+
+Requests arrive on a wall clock (arrival times in seconds, e.g. a Poisson
+stream).  Arrived requests wait in a FIFO queue; the head is admitted into an
+engine slot as soon as a slot is free and its device footprint fits the
+budget; every engine step advances all running solves (their periods overlap
+on the device); finished solves are collected and their latency (result
+ready - arrival) recorded.  All numerical work runs in the HIP library; this
+loop only schedules.
+"""
+from __future__ import annotations
+
+import collections
+import time
+
+import numpy as np
+
+from . import cmcg, inputs
+
+
+class SpaceCache:
+    """Meshes and spaces shared by requests of the same (n, q)."""
+
+    def __init__(self, precision):
+        self.precision = precision
+        self.meshes = {}
+        self.spaces = {}
+
+    def get(self, n, q):
+        if n not in self.meshes:
+            xyz, tet, tags = inputs.cube_mesh(n)
+            self.meshes[n] = cmcg.cmcg_mesh_create(xyz, tet, tags)
+        key = (n, q)
+        if key not in self.spaces:
+            s = cmcg.cmcg_space_create(self.meshes[n], q, self.precision)
+            self.spaces[key] = (s, cmcg.cmcg_space_nodes(s))
+        return self.spaces[key]
+
+
+def build_problem(cache: SpaceCache, req):
+    w = inputs.serving_request_workload(req)
+    s, nodes = cache.get(w.n, w.q)
+    j = inputs.gaussian_current(nodes, w.centre, w.width, w.pol)
+    return cmcg.cmcg_problem_create(s, w.eps, w.mu, None, w.omega, j)
+
+
+def serve(requests, budget_bytes: int, max_slots: int, precision=cmcg.CMCG_FP32, tol: float = 1e-6,
+          max_iter: int = 2000, time_scale: float = 1.0, log=None, keep_results: bool = False):
+    """Serve `requests` (dicts with "arrival" and the recipe fields of
+    inputs.serving_stream).  time_scale > 1 compresses the arrival clock.
+    Returns a dict with latencies, throughput and per-request records."""
+    engine = cmcg.cmcg_engine_create(budget_bytes, max_slots)
+    cache = SpaceCache(precision)
+    opts = cmcg.cmcg_options_default(tol=tol, max_iter=max_iter)
+    pending = collections.deque(sorted(requests, key=lambda r: r["arrival"]))
+    queue = collections.deque()
+    slots = {}  # slot -> (request, problem, admit time)
+    records = []
+    results = {}
+    t0 = time.perf_counter()
+
+    def now():
+        return (time.perf_counter() - t0) * time_scale
+
+    steps = 0
+    while pending or queue or slots:
+        t = now()
+        while pending and pending[0]["arrival"] <= t:
+            queue.append(pending.popleft())
+        # FIFO admission while the head fits
+        while queue:
+            req = queue[0]
+            prob = req.get("_problem") or build_problem(cache, req)
+            req["_problem"] = prob
+            slot = cmcg.cmcg_engine_admit(engine, prob, opts)
+            if slot is None:
+                break
+            queue.popleft()
+            slots[slot] = (req, prob, now())
+        if not slots:
+            if pending:  # idle until the next arrival
+                wait = (pending[0]["arrival"] - now()) / time_scale
+                if wait > 0:
+                    time.sleep(min(wait, 0.05))
+            continue
+        cmcg.cmcg_engine_step(engine)
+        steps += 1
+        for slot in list(slots):
+            if cmcg.cmcg_engine_poll(engine, slot) >= 2:
+                req, prob, t_adm = slots.pop(slot)
+                res = cmcg.cmcg_engine_collect(engine, slot, prob)
+                t_done = now()
+                st = cmcg.cmcg_result_stats(res)
+                rec = dict(id=req["id"], n=req["n"], q=req["q"], omega=req["omega"], arrival=req["arrival"],
+                           admitted=t_adm, done=t_done, latency=t_done - req["arrival"], iters=st["iters"],
+                           rel_res=st["rel_res"], dof_updates=st["dof_updates"])
+                records.append(rec)
+                if keep_results:
+                    results[req["id"]] = res
+                req.pop("_problem", None)
+                if log:
+                    log(f"done {req['id']} n={req['n']} q={req['q']} iters={st['iters']} "
+                        f"latency={rec['latency']:.2f}s queue={len(queue)} running={len(slots)}")
+    elapsed = now()
+    lat = np.array([r["latency"] for r in records])
+    out = dict(completed=len(records), elapsed=elapsed, engine_steps=steps,
+               throughput=len(records) / elapsed if elapsed > 0 else 0.0,
+               dof_updates_per_s=sum(r["dof_updates"] for r in records) / elapsed if elapsed > 0 else 0.0,
+               p50=float(np.percentile(lat, 50)) if len(lat) else None,
+               p99=float(np.percentile(lat, 99)) if len(lat) else None,
+               offered_rate=(len(requests) / max(r["arrival"] for r in requests)) if requests else 0.0,
+               records=records)
+    if keep_results:
+        out["results"] = results
+    return out

@@ -1,0 +1,64 @@
+"""Serving engine: requests of different meshes, orders and frequencies are
+admitted by memory, overlap on the device, and each served result equals
+the same request solved alone (bit for bit: a slot runs the launch sequence
+of cmcg_solve)."""
+import numpy as np
+import pytest
+
+from paper_2106_02858_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def filtered(lib, r, K, Np):
+    import torch
+    fr = torch.zeros((K, 6, Np), dtype=torch.float64, device="cuda")
+    fi = torch.zeros_like(fr)
+    lib.cmcg_result_filtered_device(r, fr, fi)
+    return fr.cpu().numpy() + 1j * fi.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_served_results_equal_solo_solves(lib, precision):
+    from paper_2106_02858_amd import serving
+    reqs = inputs.serving_stream(n_requests=8, rate=200.0, seed=11, sizes=(1, 2), orders=(1, 2, 3))
+    out = serving.serve(reqs, budget_bytes=1 << 34, max_slots=3, precision=precision, tol=1e-7,
+                        keep_results=True)
+    assert out["completed"] == len(reqs)
+    assert max(len({r["n"] for r in out["records"]}), len({r["q"] for r in out["records"]})) > 1
+    cache = serving.SpaceCache(precision)
+    for rec in out["records"]:
+        req = next(r for r in reqs if r["id"] == rec["id"])
+        prob = serving.build_problem(cache, req)
+        alone = lib.cmcg_solve(prob, lib.cmcg_options_default(tol=1e-7, max_iter=2000))
+        s, _ = cache.get(req["n"], req["q"])
+        info = lib.cmcg_space_info(s)
+        a = filtered(lib, out["results"][rec["id"]], info["K"], info["Np"])
+        b = filtered(lib, alone, info["K"], info["Np"])
+        assert np.array_equal(a, b), rec
+        assert lib.cmcg_result_stats(alone)["iters"] == rec["iters"]
+    lat = [r["latency"] for r in out["records"]]
+    assert out["p50"] <= out["p99"] and min(lat) > 0
+
+
+def test_admission_by_budget_and_state(lib):
+    from paper_2106_02858_amd import serving
+    reqs = inputs.serving_stream(n_requests=2, rate=10.0, seed=3, sizes=(2,), orders=(2,))
+    cache = serving.SpaceCache(1)
+    p1, p2 = (serving.build_problem(cache, r) for r in reqs)
+    need = lib.cmcg_problem_footprint(p1)
+    e = lib.cmcg_engine_create(need + need // 2, 4)
+    s1 = lib.cmcg_engine_admit(e, p1)
+    assert s1 is not None
+    assert lib.cmcg_engine_admit(e, p2) is None           # over budget: stays queued
+    with pytest.raises(lib.CmcgError) as err:
+        lib.cmcg_engine_admit(e, p1)                        # already held by a slot
+    assert err.value.code == lib.CMCG_ERR_STATE
+    lib.cmcg_engine_cancel(e, s1)
+    assert lib.cmcg_engine_info(e)["used"] == 0
+    s2 = lib.cmcg_engine_admit(e, p2)
+    while lib.cmcg_engine_poll(e, s2) == 1:
+        lib.cmcg_engine_step(e)
+    r = lib.cmcg_engine_collect(e, s2, p2)
+    assert lib.cmcg_result_stats(r)["iters"] > 0
+    assert lib.cmcg_engine_poll(e, s2) == 0
