@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 reference solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=2, help="RK steps of the CPU oracle sample")
+    ap.add_argument("--cpu-steps", type=int, default=4, help="RK steps of the CPU oracle sample")
     ap.add_argument("--kernel-periods", type=int, default=3)
     ap.add_argument("--workload", choices=["large_single", "batched", "serving"], default="large_single",
                     help="large_single (default bench line), the 64-member batched configuration, or the "
@@ -56,13 +56,34 @@ def parse():
     return ap.parse_args()
 
 
+STAGE_KERNEL = {0: "k_stage<float,{q},false>", 1: "k_stage<float,{q},true>", 2: "k_stage_mfma<{q}>"}
+
+
 def stage_bytes_per_element(q: int, esize: int) -> float:
-    """Algorithmic HBM bytes of one average RK4 stage launch per element:
-    16 field-vector passes per step (stage 1: 1 read + 2 writes; stages 2-3:
-    3 reads + 2 writes; stage 4: 2 reads + 1 write) -> 4 per launch, plus the
-    per-element geometry (40 values) and connectivity (4 int32)."""
+    """Algorithmic HBM bytes of one average stage launch per element: the field
+    vectors each stage must read or write once, plus the element's geometry
+    (40 values) and connectivity (4 int32); neighbour traces are counted as
+    cache hits.  RK4 per dof and step: stage 1 reads Y, writes Y', Acc;
+    stages 2-3 read Y, U, Acc and write Y', Acc; stage 4 reads Y, Acc and
+    writes U -- FP64: 16 passes of 8 B; FP32 with the compensated state also
+    reads U and reads/writes the 2-byte low part in stage 4: 72 B.  RK2: FP64
+    5 passes of 8 B; FP32 5 passes of 4 B + 2 x 2 B."""
     Np = (q + 1) * (q + 2) * (q + 3) // 6
-    return 4 * 6 * Np * esize + 40 * esize + 16
+    if q >= 2:
+        per_dof = 72.0 / 4 if esize == 4 else 128.0 / 4
+    else:
+        per_dof = 24.0 / 2 if esize == 4 else 40.0 / 2
+    return 6 * Np * per_dof + 40 * esize + 16
+
+
+def bytes_per_dof_update(q: int, esize: int, members: int = 1) -> float:
+    """Algorithmic HBM bytes per dof-update (one dof advanced one full step):
+    the field passes of stage_bytes_per_element over the stages of a step,
+    geometry and connectivity shared by the members of a batched launch."""
+    Np = (q + 1) * (q + 2) * (q + 3) // 6
+    stages = 4 if q >= 2 else 2
+    field = stage_bytes_per_element(q, esize) - (40 * esize + 16)
+    return stages * (field + (40 * esize + 16) / members) / (6 * Np)
 
 
 def cpu_baseline(w, steps: int):
@@ -139,8 +160,16 @@ def batched(a):
                       "q": 2, "steps_per_period_min": min(Ms), "steps_per_period_max": max(Ms)},
            "cmcg": {"iters_min": min(st["iters"] for st in sts), "iters_max": max(st["iters"] for st in sts),
                     "time_to_1e-6_all_members_s": max(st["seconds_to_1e6"] for st in sts),
-                    "seconds": sts[0]["seconds"]}}
+                    "seconds": sts[0]["seconds"]},
+           "hbm_job": job_roofline(dof / el, bytes_per_dof_update(2, 4, a.members))}
     print(json.dumps(out), flush=True)
+
+
+def job_roofline(rate: float, bpd: float) -> dict:
+    """Whole-job HBM fraction: dof-updates/s x algorithmic bytes per dof-update
+    (CG vector work and idle members count as time, not as bytes)."""
+    gbs = rate * bpd / 1e9
+    return {"bytes_per_dof_update": bpd, "achieved_GBs": gbs, "peak_GBs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}
 
 
 def served(a):
@@ -162,6 +191,8 @@ def served(a):
                                   f"{a.budget_gb:g} GB budget, CMCG to {a.tol:g}"},
            "serving": {k: out[k] for k in ("completed", "elapsed", "throughput", "p50", "p99", "offered_rate",
                                            "engine_steps")}}
+    byts = sum(r["dof_updates"] * bytes_per_dof_update(r["q"], 4) for r in out["records"])
+    res["hbm_job"] = job_roofline(out["dof_updates_per_s"], byts / max(1.0, sum(r["dof_updates"] for r in out["records"])))
     print(json.dumps(res), flush=True)
 
 
@@ -267,7 +298,8 @@ def main():
                  "time_to_1e-6_fp32_s": stats[-1]["seconds_to_1e6"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"k_stage<float,{w.q}>", "avg_launch_us": per_launch_s * 1e6,
+                     "kernel": STAGE_KERNEL[cmcg.cmcg_tune_get_stage(w.q, cmcg.CMCG_FP32)].format(q=w.q),
+                     "avg_launch_us": per_launch_s * 1e6,
                      "bytes_per_launch": bpe * K},
     }
     if not a.no_fp64:

@@ -96,10 +96,12 @@ typedef struct cmcg_options {
                             impedance faces are always upwind                   */
     int use_graph;       /* 1: replay each period from a captured hipGraph      */
     int residual_refresh;/* > 0: every this many iterations replace R by the
-                            true gradient (costs two periods); 0 = automatic:
-                            every 10 iterations with FP32 fields (their
-                            rounding breaks the exact adjointness CG relies on
-                            near 1e-6), never with FP64; < 0 = never           */
+                            true gradient (costs two periods); <= 0 = never.
+                            FP32 fields keep the state compensated (FP32 +
+                            bfloat16 low part), which holds the rounding floor
+                            of the residual near 2e-7 on the 48000-tet P3
+                            problem, so the recursive residual needs no
+                            refresh at the usual tolerances                    */
     /* Optional progress report, called on the host after every CG iteration
      * with the iteration count and ||R_l|| / ||R_0||; a non-zero return value
      * stops the iteration (the result is then flagged NOT_CONVERGED).  NULL =
@@ -188,7 +190,10 @@ int cmcg_problem_steps(const cmcg_problem* p, const cmcg_options* o, int* M, dou
  * [K][6][Np] FP64, when not NULL), then the filter period.  Work is ordered
  * on `stream` (NULL = the default stream); the call returns when the result
  * is complete.  Returns CMCG_OK, CMCG_NOT_CONVERGED (result valid), or an
- * error (no result). */
+ * error (no result).  When the recursive residual grows past 100 times the
+ * smallest value it has reached (the rounding floor of FP32 fields lies above
+ * the tolerance), the iteration stops, the filter runs on the best iterate,
+ * and the status is CMCG_NOT_CONVERGED with rel_res the best value. */
 int cmcg_solve(cmcg_problem* p, const cmcg_options* o, const double* u0_dev,
                hipStream_t stream, cmcg_result** out);
 /* Batched solve: Algorithm 3 for n problems sharing one space (same mesh,

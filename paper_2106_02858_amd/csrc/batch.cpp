@@ -28,7 +28,8 @@ struct Batch {
     // device
     DevBuf geo, wE, wH, Sre, Sim;
     DevBuf U, Y1, Y2, Acc, Fre, Fim, Kbuf;
-    DevBuf vu, vr, vd, va, vw, vgs;
+    DevBuf Ulo;  // FP32 fields: bfloat16 low parts of U
+    DevBuf vu, vr, vd, va, vw, vgs, vbest;
     DevBuf partial, dots, coefA, coefC, active, msteps, mtab, fw_re, fw_im;
     std::unique_ptr<HostPinned> pin;
     hipStream_t cap = nullptr;
@@ -133,6 +134,7 @@ StageArgs batch_args(Batch& bt) {
     a.Sim = bt.Sim.p;
     a.Fre = bt.Fre.as<double>();
     a.Fim = bt.Fim.as<double>();
+    a.Ulo = bt.Ulo.p;
     a.nmembers = bt.B;
     a.active = bt.active.as<int>();
     a.msteps = bt.msteps.as<int>();
@@ -247,12 +249,14 @@ void batch_apply(Batch& bt, const cmcg_options* o, const double* X, double* Yo, 
     const SpaceData& s = *bt.sp;
     const int flip = direction < 0 ? 1 : 0;
     const int64_t N = bt.n() * bt.B;
-    if (X)
-        launch_to_field(s.precision, s.Np, X, bt.U.p, N, flip, st);
-    else
+    if (X) {
+        launch_to_field(s.precision, s.Np, X, bt.U.p, bt.Ulo.p, N, flip, st);
+    } else {
         launch_zero(bt.U.p, bt.U.bytes, st);
+        if (bt.Ulo.p) launch_zero(bt.Ulo.p, bt.Ulo.bytes, st);
+    }
     run_batch_period(bt, src && direction > 0, filt, o->use_graph != 0, st);
-    if (Yo) launch_from_field(s.precision, s.Np, bt.U.p, Yo, sub, N, flip, st);
+    if (Yo) launch_from_field(s.precision, s.Np, bt.U.p, bt.Ulo.p, Yo, sub, N, flip, st);
 }
 
 void batch_dots(Batch& bt, const double* U, const double* V, std::vector<double>& out, hipStream_t st) {
@@ -333,6 +337,7 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
     bt.Y1.alloc(bt.fb());
     bt.Y2.alloc(bt.fb());
     bt.Acc.alloc(bt.fb());
+    if (s.precision == CMCG_FP32) bt.Ulo.alloc((size_t)bt.n() * B * 2);
     bt.Kbuf.alloc(bt.fb());
     bt.Fre.alloc(bt.db());
     bt.Fim.alloc(bt.db());
@@ -355,6 +360,7 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
     bt.va.alloc(bt.db());
     bt.vw.alloc(bt.db());
     bt.vgs.alloc(bt.db());
+    if (o->fixed_iters <= 0) bt.vbest.alloc(bt.db());
     bt.partial.alloc((size_t)dot_partials() * B * 8);
     bt.dots.alloc(B * 8);
     bt.coefA.alloc(B * 8);
@@ -378,7 +384,8 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
     auto secs = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
     const std::vector<double> one(B, 1.0), zero(B, 0.0), mone(B, -1.0);
     std::vector<int> periods(B, 0), iters(B, 0);
-    std::vector<double> t6(B, -1.0), rel(B, 1.0), J0(B);
+    std::vector<double> t6(B, -1.0), rel(B, 1.0), J0(B), best(B, 1.0);
+    std::vector<int> diverged(B, 0);
     std::vector<std::vector<double>> hist(B, std::vector<double>{1.0});
     auto count_periods = [&](int k) {
         for (int b = 0; b < B; ++b)
@@ -398,8 +405,7 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
     }
     const bool fixed = o->fixed_iters > 0;
     const int limit = fixed ? o->fixed_iters : o->max_iter;
-    const int refresh =
-        o->residual_refresh > 0 ? o->residual_refresh : (o->residual_refresh == 0 && s.precision == CMCG_FP32 ? 10 : 0);
+    const int refresh = o->residual_refresh > 0 ? o->residual_refresh : 0;
     auto gradient = [&](double* outv) {
         batch_apply(bt, o, U, W, U, +1, false, false, st);
         batch_apply(bt, o, W, outv, W, -1, false, false, st);
@@ -407,6 +413,7 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
         count_periods(2);
     };
     launch_zero(U, bt.db(), st);
+    if (!fixed) launch_zero(bt.vbest.p, bt.db(), st);
     batch_axpby(bt, mone, Gs, zero, Gs, R, st);  // R0 = -G*
     CMCG_HIP(hipMemcpyAsync(D, R, bt.db(), hipMemcpyDeviceToDevice, st));
     std::vector<double> rr, rr0;
@@ -455,7 +462,8 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
         if (refresh > 0 && it % refresh == 0) gradient(R);
         std::vector<double> rn;
         batch_dots(bt, R, R, rn, st);
-        std::vector<double> beta(B, 0.0);
+        std::vector<double> beta(B, 0.0), keep_new(B, 0.0), keep_old(B, 1.0);
+        bool improved = false;
         for (int b = 0; b < B; ++b) {
             if (!act[b]) continue;
             if (!std::isfinite(rn[b])) fail(CMCG_ERR_UNSTABLE, "solve_batch: non-finite residual");
@@ -464,7 +472,18 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
             rel[b] = std::sqrt(rr[b] / rr0[b]);
             hist[b].push_back(rel[b]);
             if (t6[b] < 0 && rel[b] <= 1e-6) t6[b] = secs();
+            if (fixed) continue;
+            if (rel[b] < best[b]) {  // the best iterate so far is kept (cf. kDivergence)
+                best[b] = rel[b];
+                keep_new[b] = 1.0;
+                keep_old[b] = 0.0;
+                improved = true;
+            } else if (rel[b] > kDivergence * best[b]) {
+                diverged[b] = 1;
+                act[b] = 0;
+            }
         }
+        if (improved) batch_axpby(bt, keep_new, U, keep_old, bt.vbest.as<double>(), bt.vbest.as<double>(), st);
         batch_axpby(bt, one, R, beta, D, D, st);
         if (o->progress) {
             double worst = 0;
@@ -472,6 +491,19 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
                 if (act[b]) worst = std::max(worst, rel[b]);
             if (o->progress(o->progress_ctx, it, worst) != 0) break;
         }
+    }
+    // diverged members return to their best iterate
+    {
+        std::vector<double> take_best(B, 0.0), keep(B, 1.0);
+        bool anyd = false;
+        for (int b = 0; b < B; ++b)
+            if (diverged[b]) {
+                take_best[b] = 1.0;
+                keep[b] = 0.0;
+                rel[b] = best[b];
+                anyd = true;
+            }
+        if (anyd) batch_axpby(bt, take_best, bt.vbest.as<double>(), keep, U, U, st);
     }
     // filter period for every member
     std::fill(act.begin(), act.end(), 1);
@@ -499,7 +531,7 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
         S.seconds = total;
         S.seconds_to_1e6 = t6[b];
         S.dof_updates = (double)n * bt.cfg[b].M * periods[b];
-        S.status = (!fixed && rel[b] > o->tol) ? CMCG_NOT_CONVERGED : CMCG_OK;
+        S.status = (diverged[b] || (!fixed && rel[b] > o->tol)) ? CMCG_NOT_CONVERGED : CMCG_OK;
         r->history = hist[b];
         out[b] = r.release();
     }

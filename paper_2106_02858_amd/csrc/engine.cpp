@@ -46,8 +46,9 @@ size_t footprint(const cmcg_problem* p) {
     size_t b = K * kGeo * es + 2 * K * 8;  // geometry, mass weights
     if (p->src_rows) b += 2 * n * es;      // source
     b += 5 * n * es;                       // U, Y1, Y2, Acc, RHS buffer
+    if (s.precision == CMCG_FP32) b += 2 * n;  // bfloat16 low parts of U
     b += 2 * n * 8;                        // filter accumulators
-    b += 6 * n * 8;                        // CG vectors
+    b += 7 * n * 8;                        // CG vectors (with the best iterate)
     b += 3 * n * 8;                        // result
     return b + (size_t)dot_partials() * 8 + 4096;
 }

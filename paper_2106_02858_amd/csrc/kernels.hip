@@ -87,6 +87,55 @@ template <typename T, int NP> struct Row {
     }
 };
 
+// Low parts of a compensated FP32 state, stored as bfloat16 (8 more significant
+// bits than the FP32 high part; round to nearest even).
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint32_t h) { return __uint_as_float(h << 16); }
+
+// s + e == a + b exactly (Knuth's branch-free two-sum, any magnitudes).
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// NP bfloat16 low parts of one row (rows start at multiples of 2 NP bytes;
+// NP is even for every order, so 4-byte words always line up).
+template <int NP> struct RowH {
+    static_assert(NP % 2 == 0, "bfloat16 rows need an even node count");
+    static constexpr int PER = (2 * NP) % 8 == 0 ? 4 : 2;
+    using V = typename std::conditional<PER == 4, uint2, uint32_t>::type;
+    __device__ __forceinline__ static void load(const uint16_t* __restrict__ p, float (&r)[NP]) {
+        const V* q = reinterpret_cast<const V*>(p);
+#pragma unroll
+        for (int c = 0; c < NP / PER; ++c) {
+            V v = q[c];
+            const uint32_t* w = reinterpret_cast<const uint32_t*>(&v);
+#pragma unroll
+            for (int u = 0; u < PER / 2; ++u) {
+                r[c * PER + 2 * u] = from_bf16(w[u] & 0xffffu);
+                r[c * PER + 2 * u + 1] = from_bf16(w[u] >> 16);
+            }
+        }
+    }
+    __device__ __forceinline__ static void store(uint16_t* __restrict__ p, const float (&r)[NP]) {
+        V* q = reinterpret_cast<V*>(p);
+#pragma unroll
+        for (int c = 0; c < NP / PER; ++c) {
+            V v;
+            uint32_t* w = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+            for (int u = 0; u < PER / 2; ++u)
+                w[u] = (uint32_t)to_bf16(r[c * PER + 2 * u]) | ((uint32_t)to_bf16(r[c * PER + 2 * u + 1]) << 16);
+            q[c] = v;
+        }
+    }
+};
+
 // Logical workgroup index with consecutive indices on one XCD: the hardware
 // hands workgroup b to XCD b % 8, so b -> (b % 8) * per + b / 8 keeps each
 // XCD on a contiguous element range (its face neighbours stay in that XCD's
@@ -124,6 +173,7 @@ __device__ __forceinline__ bool member_args(const StageArgs& in, StageArgs& a) {
     if (in.Acc) a.Acc = (T*)in.Acc + fo;
     if (in.Uout) a.Uout = (T*)in.Uout + fo;
     if (in.Kout) a.Kout = (T*)in.Kout + fo;
+    if (in.Ulo) a.Ulo = (uint16_t*)in.Ulo + fo;
     if (in.Fre) a.Fre = in.Fre + fo;
     if (in.Fim) a.Fim = in.Fim + fo;
     a.geo = (const T*)in.geo + (int64_t)b * in.gstride;
@@ -199,7 +249,9 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     const int row = elc * 6 + c;
     const int64_t grow = base + (int64_t)row * NP;
     const int mode = a.mode;
-    const bool needU = mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3;
+    constexpr bool COMP = std::is_same<T, float>::value;  // compensated state U + Ulo
+    const bool needL = COMP && (mode == RK2_S2 || mode == RK4_S4);
+    const bool needU = mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || needL;
     const bool needA = mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4;
 
     // neighbour traces of face 0 in flight during the staging and volume work
@@ -257,6 +309,7 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     // neighbour traces (and before the last face the update operands) are
     // requested before this face's work
     T up[NP], ap[NP];
+    float lo[NP];
 #pragma unroll 1
     for (int f = 0; f < 4; ++f) {
         if (PIPE) {
@@ -265,6 +318,8 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
             } else if (act) {
                 if (needU) Row<T, NP>::load((const T*)a.U + grow, up);
                 if (needA) Row<T, NP>::load((const T*)a.Acc + grow, ap);
+                if constexpr (COMP)
+                    if (needL) RowH<NP>::load((const uint16_t*)a.Ulo + grow, lo);
             }
         } else {
             cur.issue(a, Y, e0, ne, f, lane, fnode, fperm);
@@ -337,6 +392,8 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     if (!PIPE) {
         if (needU) Row<T, NP>::load((const T*)a.U + grow, up);
         if (needA) Row<T, NP>::load((const T*)a.Acc + grow, ap);
+        if constexpr (COMP)
+            if (needL) RowH<NP>::load((const uint16_t*)a.Ulo + grow, lo);
     }
 
     // ---- stage update on the lane's row
@@ -362,15 +419,23 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
             Row<T, NP>::store((T*)a.Ynext + grow, o1);
             break;
         case RK2_S2:
+            if constexpr (COMP) {
+                float e[NP];
 #pragma unroll
-            for (int i = 0; i < NP; ++i) o1[i] = fma(cu, kv[i], up[i]);
-            Row<T, NP>::store((T*)a.Uout + grow, o1);
+                for (int i = 0; i < NP; ++i) two_sum(up[i], fma(cu, kv[i], lo[i]), o1[i], e[i]);
+                Row<T, NP>::store((T*)a.Uout + grow, o1);
+                RowH<NP>::store((uint16_t*)a.Ulo + grow, e);
+            } else {
+#pragma unroll
+                for (int i = 0; i < NP; ++i) o1[i] = fma(cu, kv[i], up[i]);
+                Row<T, NP>::store((T*)a.Uout + grow, o1);
+            }
             break;
         case RK4_S1:
 #pragma unroll
             for (int i = 0; i < NP; ++i) {
                 o1[i] = fma(cy, kv[i], y[i]);
-                o2[i] = fma(ca, kv[i], y[i]);
+                o2[i] = COMP ? ca * kv[i] : fma(ca, kv[i], y[i]);
             }
             Row<T, NP>::store((T*)a.Ynext + grow, o1);
             Row<T, NP>::store((T*)a.Acc + grow, o2);
@@ -386,9 +451,17 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
             Row<T, NP>::store((T*)a.Acc + grow, o2);
             break;
         case RK4_S4:
+            if constexpr (COMP) {
+                float e[NP];
 #pragma unroll
-            for (int i = 0; i < NP; ++i) o1[i] = fma(cu, kv[i], ap[i]);
-            Row<T, NP>::store((T*)a.Uout + grow, o1);
+                for (int i = 0; i < NP; ++i) two_sum(up[i], fma(cu, kv[i], ap[i]) + lo[i], o1[i], e[i]);
+                Row<T, NP>::store((T*)a.Uout + grow, o1);
+                RowH<NP>::store((uint16_t*)a.Ulo + grow, e);
+            } else {
+#pragma unroll
+                for (int i = 0; i < NP; ++i) o1[i] = fma(cu, kv[i], ap[i]);
+                Row<T, NP>::store((T*)a.Uout + grow, o1);
+            }
             break;
         default:
             Row<T, NP>::store((T*)a.Kout + grow, kv);
@@ -629,6 +702,25 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
                     for (int u = 0; u < W; ++u) t[u] = o[u];
                     *reinterpret_cast<VW*>((T*)p + gi) = v;
                 };
+                // bfloat16 low parts: W = 4 -> 8 bytes, W = 2 -> 4 bytes
+                using VH = typename std::conditional<W == 4, uint2, uint32_t>::type;
+                auto ld_lo = [&](T (&o)[W]) {
+                    VH v = *reinterpret_cast<const VH*>((const uint16_t*)a.Ulo + gi);
+                    const uint32_t* w = reinterpret_cast<const uint32_t*>(&v);
+#pragma unroll
+                    for (int u = 0; u < W / 2; ++u) {
+                        o[2 * u] = from_bf16(w[u] & 0xffffu);
+                        o[2 * u + 1] = from_bf16(w[u] >> 16);
+                    }
+                };
+                auto st_lo = [&](const T (&o)[W]) {
+                    VH v;
+                    uint32_t* w = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+                    for (int u = 0; u < W / 2; ++u)
+                        w[u] = (uint32_t)to_bf16(o[2 * u]) | ((uint32_t)to_bf16(o[2 * u + 1]) << 16);
+                    *reinterpret_cast<VH*>((uint16_t*)a.Ulo + gi) = v;
+                };
                 if (s < a.src_rows) {
                     T sr[W], si[W];
                     ld(a.Sre, sr);
@@ -636,7 +728,7 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
 #pragma unroll
                     for (int u = 0; u < W; ++u) kv[u] += scos * sr[u] - ssin * si[u];
                 }
-                T o1[W], o2[W], up[W], ap[W];
+                T o1[W], o2[W], up[W], ap[W], lo[W];
                 switch (mode) {
                     case RK2_S1:
 #pragma unroll
@@ -645,15 +737,17 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
                         break;
                     case RK2_S2:
                         ld(a.U, up);
+                        ld_lo(lo);
 #pragma unroll
-                        for (int u = 0; u < W; ++u) o1[u] = fma(cu, kv[u], up[u]);
+                        for (int u = 0; u < W; ++u) two_sum(up[u], fma(cu, kv[u], lo[u]), o1[u], o2[u]);
                         st(a.Uout, o1);
+                        st_lo(o2);
                         break;
                     case RK4_S1:
 #pragma unroll
                         for (int u = 0; u < W; ++u) {
                             o1[u] = fma(cy, kv[u], yv[u]);
-                            o2[u] = fma(ca, kv[u], yv[u]);
+                            o2[u] = ca * kv[u];
                         }
                         st(a.Ynext, o1);
                         st(a.Acc, o2);
@@ -671,10 +765,13 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
                         st(a.Acc, o2);
                         break;
                     case RK4_S4:
+                        ld(a.U, up);
                         ld(a.Acc, ap);
+                        ld_lo(lo);
 #pragma unroll
-                        for (int u = 0; u < W; ++u) o1[u] = fma(cu, kv[u], ap[u]);
+                        for (int u = 0; u < W; ++u) two_sum(up[u], fma(cu, kv[u], ap[u]) + lo[u], o1[u], o2[u]);
                         st(a.Uout, o1);
+                        st_lo(o2);
                         break;
                     default:
                         st(a.Kout, kv);
@@ -694,19 +791,25 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
 }
 
 template <typename T>
-__global__ void k_to_field(const double* __restrict__ X, T* __restrict__ U, int64_t n, int Np, int flipH) {
+__global__ void k_to_field(const double* __restrict__ X, T* __restrict__ U, uint16_t* __restrict__ Ulo, int64_t n,
+                           int Np, int flipH) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double x = X[i];
         if (flipH && ((i / Np) % 6) >= 3) x = -x;
-        U[i] = (T)x;
+        const T hi = (T)x;
+        U[i] = hi;
+        if constexpr (std::is_same<T, float>::value)
+            if (Ulo) Ulo[i] = to_bf16((float)(x - (double)hi));
     }
 }
 
 template <typename T>
-__global__ void k_from_field(const T* __restrict__ U, double* __restrict__ Yo, const double* __restrict__ sub,
-                             int64_t n, int Np, int flipH) {
+__global__ void k_from_field(const T* __restrict__ U, const uint16_t* __restrict__ Ulo, double* __restrict__ Yo,
+                             const double* __restrict__ sub, int64_t n, int Np, int flipH) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double x = (double)U[i];
+        if constexpr (std::is_same<T, float>::value)
+            if (Ulo) x += (double)from_bf16(Ulo[i]);
         if (flipH && ((i / Np) % 6) >= 3) x = -x;
         if (sub) x -= sub[i];
         Yo[i] = x;
@@ -979,22 +1082,25 @@ void launch_stage(int q, int precision, const StageArgs& a, hipStream_t s) {
     check_launch();
 }
 
-void launch_to_field(int precision, int Np, const double* X, void* U, int64_t n, int flipH, hipStream_t s) {
+void launch_to_field(int precision, int Np, const double* X, void* U, void* Ulo, int64_t n, int flipH,
+                     hipStream_t s) {
     if (precision == CMCG_FP64)
-        hipLaunchKernelGGL(k_to_field<double>, dim3(grid_for(n)), dim3(256), 0, s, X, (double*)U, n, Np, flipH);
+        hipLaunchKernelGGL(k_to_field<double>, dim3(grid_for(n)), dim3(256), 0, s, X, (double*)U, nullptr, n, Np,
+                           flipH);
     else
-        hipLaunchKernelGGL(k_to_field<float>, dim3(grid_for(n)), dim3(256), 0, s, X, (float*)U, n, Np, flipH);
+        hipLaunchKernelGGL(k_to_field<float>, dim3(grid_for(n)), dim3(256), 0, s, X, (float*)U, (uint16_t*)Ulo, n,
+                           Np, flipH);
     check_launch();
 }
 
-void launch_from_field(int precision, int Np, const void* U, double* Y, const double* sub, int64_t n, int flipH,
-                       hipStream_t s) {
+void launch_from_field(int precision, int Np, const void* U, const void* Ulo, double* Y, const double* sub,
+                       int64_t n, int flipH, hipStream_t s) {
     if (precision == CMCG_FP64)
-        hipLaunchKernelGGL(k_from_field<double>, dim3(grid_for(n)), dim3(256), 0, s, (const double*)U, Y, sub, n,
-                           Np, flipH);
+        hipLaunchKernelGGL(k_from_field<double>, dim3(grid_for(n)), dim3(256), 0, s, (const double*)U, nullptr, Y,
+                           sub, n, Np, flipH);
     else
-        hipLaunchKernelGGL(k_from_field<float>, dim3(grid_for(n)), dim3(256), 0, s, (const float*)U, Y, sub, n,
-                           Np, flipH);
+        hipLaunchKernelGGL(k_from_field<float>, dim3(grid_for(n)), dim3(256), 0, s, (const float*)U,
+                           (const uint16_t*)Ulo, Y, sub, n, Np, flipH);
     check_launch();
 }
 

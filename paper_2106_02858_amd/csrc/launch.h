@@ -17,6 +17,12 @@ namespace cmcg {
 //   RK4_S4: U     = Acc + cu k
 //   RHS:    Kout  = k
 // Optional filter accumulation (FP64): F += fa * U + fb * k (complex).
+//
+// FP32 fields carry the state as an unevaluated sum U + Ulo (Ulo in bfloat16,
+// |Ulo| <= half an FP32 ulp of U): Acc holds the increment only (RK4_S1:
+// Acc = ca k; RK4_S4: U + Ulo += Acc + cu k) and the last update of a step adds
+// its increment to U + Ulo with an exact two-sum, so rounding the state to
+// FP32 once per step does not accumulate over the period.
 enum StageMode { RK2_S1 = 0, RK2_S2, RK4_S1, RK4_S2, RK4_S3, RK4_S4, RHS };
 
 struct StageArgs {
@@ -26,6 +32,7 @@ struct StageArgs {
     void* Acc;
     void* Uout;
     void* Kout;
+    void* Ulo;          // FP32 fields: bfloat16 low parts of U (RK2_S2, RK4_S4 read and write it)
     const void* geo;    // [K][kGeo]
     const int* conn;    // [K][4]: >= 0: nbr<<5 | nbr_face<<3 | perm; -1 PEC; -2 impedance
     const void* Sre;    // source [K][6][Np] (nullable)
@@ -60,10 +67,11 @@ int get_stage_variant(int q, int precision);
 constexpr int kStageVariants = 3;  // 2: matrix cores (FP32, q >= 2)
 
 // FP64 <-> field precision; flipH negates the magnetic rows (the S of P* = S P S).
-void launch_to_field(int precision, int Np, const double* X, void* U, int64_t n, int flipH,
+// FP32: Ulo (nullable) receives / contributes the bfloat16 low part.
+void launch_to_field(int precision, int Np, const double* X, void* U, void* Ulo, int64_t n, int flipH,
                      hipStream_t s);
-// Y = field(U) * (flipH ? S : I) - sub   (sub nullable)
-void launch_from_field(int precision, int Np, const void* U, double* Y, const double* sub,
+// Y = field(U [+ Ulo]) * (flipH ? S : I) - sub   (sub, Ulo nullable)
+void launch_from_field(int precision, int Np, const void* U, const void* Ulo, double* Y, const double* sub,
                        int64_t n, int flipH, hipStream_t s);
 void launch_copy_field(int precision, const void* src, void* dst, int64_t n, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);

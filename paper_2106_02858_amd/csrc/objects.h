@@ -91,7 +91,8 @@ struct cmcg_problem {
     int src_rows = 0;
     // work buffers
     cmcg::DevBuf U, Y1, Y2, Acc, Fre, Fim, Kbuf;
-    cmcg::DevBuf v_u, v_r, v_d, v_a, v_w, v_gs, v_t;
+    cmcg::DevBuf Ulo;  // FP32 fields: bfloat16 low parts of U
+    cmcg::DevBuf v_u, v_r, v_d, v_a, v_w, v_gs, v_t, v_best;
     cmcg::DevBuf partial, scal;
     std::unique_ptr<cmcg::HostPinned> pinned;
     hipStream_t cap_stream = nullptr;
@@ -125,8 +126,8 @@ struct CgRun {
     int phase = kDone;
     int64_t n = 0;
     int it = 0, periods = 0, refresh = 0, limit = 0;
-    bool fixed = false, stopped = false;
-    double rr = 0, rr0 = 0, rel = 1, t6 = -1, J0 = 0;
+    bool fixed = false, stopped = false, diverged = false;
+    double rr = 0, rr0 = 0, rel = 1, t6 = -1, J0 = 0, best = 0;
     std::chrono::steady_clock::time_point t0;
     void start(cmcg_problem* pr, const cmcg_options* opt, const double* u0_, hipStream_t s_);
     void complete();
@@ -137,6 +138,11 @@ struct CgRun {
     void decide();
     void gradient(double* out);
 };
+
+// A solve whose recursive residual grows past this factor times the smallest
+// one seen has left the range its arithmetic resolves: it stops, returns the
+// best iterate and reports CMCG_NOT_CONVERGED.
+constexpr double kDivergence = 100.0;
 
 // helpers defined in solver.cpp
 void ensure_constants(int device, int q);

@@ -241,6 +241,7 @@ static void ensure_work(cmcg_problem* p) {
     p->Y1.alloc(fb);
     p->Y2.alloc(fb);
     p->Acc.alloc(fb);
+    if (s.precision == CMCG_FP32) p->Ulo.alloc(s.ndof * 2);
     p->Fre.alloc(db);
     p->Fim.alloc(db);
     p->partial.alloc(dot_partials() * 8);
@@ -257,6 +258,7 @@ static StageArgs base_args(cmcg_problem* p) {
     a.Sim = p->Sim.p;
     a.Fre = p->Fre.as<double>();
     a.Fim = p->Fim.as<double>();
+    a.Ulo = p->Ulo.p;
     return a;
 }
 
@@ -412,12 +414,14 @@ void apply_period(cmcg_problem* p, const StepCfg& c, const cmcg_options* o, cons
                          const double* sub, int direction, bool src, bool filt, hipStream_t st) {
     const SpaceData& s = *p->sp;
     const int flip = direction < 0 ? 1 : 0;
-    if (X)
-        launch_to_field(s.precision, s.Np, X, p->U.p, s.ndof, flip, st);
-    else
+    if (X) {
+        launch_to_field(s.precision, s.Np, X, p->U.p, p->Ulo.p, s.ndof, flip, st);
+    } else {
         launch_zero(p->U.p, p->U.bytes, st);
+        if (p->Ulo.p) launch_zero(p->Ulo.p, p->Ulo.bytes, st);
+    }
     run_period(p, c, src && direction > 0, filt, o->use_graph != 0, st);
-    if (Yo) launch_from_field(s.precision, s.Np, p->U.p, Yo, sub, s.ndof, flip, st);
+    if (Yo) launch_from_field(s.precision, s.Np, p->U.p, p->Ulo.p, Yo, sub, s.ndof, flip, st);
 }
 
 double dot(cmcg_problem* p, const double* U, const double* V, hipStream_t st) {
@@ -477,8 +481,7 @@ void CgRun::start(cmcg_problem* pr, const cmcg_options* opt, const double* u0_, 
     res->Fim.alloc(db);
     res->U0.alloc(db);
     fixed = o.fixed_iters > 0;
-    refresh = o.residual_refresh > 0 ? o.residual_refresh
-                                     : (o.residual_refresh == 0 && s.precision == CMCG_FP32 ? 10 : 0);
+    refresh = o.residual_refresh > 0 ? o.residual_refresh : 0;
     limit = fixed ? o.fixed_iters : o.max_iter;
     CMCG_HIP(hipStreamSynchronize(st));
     t0 = std::chrono::steady_clock::now();
@@ -498,6 +501,10 @@ void CgRun::start(cmcg_problem* pr, const cmcg_options* opt, const double* u0_, 
         launch_axpby(-1.0, Gs, 0.0, Gs, R, n, st);  // R0 = -G*
     }
     CMCG_HIP(hipMemcpyAsync(D, R, db, hipMemcpyDeviceToDevice, st));
+    if (!fixed) {
+        p->v_best.alloc(db);
+        CMCG_HIP(hipMemcpyAsync(p->v_best.p, U, db, hipMemcpyDeviceToDevice, st));
+    }
     dot_async(p, R, R, 1, st);
     phase = kStart;
 }
@@ -520,9 +527,13 @@ void CgRun::decide() {
     rel = rr0 > 0 ? std::sqrt(rr / rr0) : 0.0;
     if (t6 < 0 && rel <= 1e-6) t6 = secs();
     const bool conv = !fixed && rel <= o.tol;
-    if (conv || rr0 == 0.0 || it >= limit || stopped) {
+    if (conv || rr0 == 0.0 || it >= limit || stopped || diverged) {
         // final period with source and filter
         double* U = p->v_u.as<double>();
+        if (diverged) {
+            CMCG_HIP(hipMemcpyAsync(U, p->v_best.p, n * 8, hipMemcpyDeviceToDevice, st));
+            rel = best;
+        }
         apply_period(p, c, &o, U, nullptr, nullptr, +1, true, true, st);
         periods += 1;
         const size_t db = n * 8;
@@ -552,6 +563,7 @@ void CgRun::complete() {
             if (!std::isfinite(rr)) fail(CMCG_ERR_UNSTABLE, "solve: non-finite initial residual");
             res->history.push_back(1.0);
             if (rr0 == 0.0) rel = 0.0;
+            best = rel;
             decide();
             break;
         case kAwaitDA: {
@@ -575,6 +587,14 @@ void CgRun::complete() {
             rr = rn;
             rel = rr0 > 0 ? std::sqrt(rr / rr0) : 0.0;
             res->history.push_back(rel);
+            if (!fixed) {
+                if (rel < best) {
+                    best = rel;
+                    CMCG_HIP(hipMemcpyAsync(p->v_best.p, U, n * 8, hipMemcpyDeviceToDevice, st));
+                } else if (rel > kDivergence * best) {
+                    diverged = true;
+                }
+            }
             if (o.progress && o.progress(o.progress_ctx, it, rel) != 0) stopped = true;
             decide();
             break;
@@ -591,7 +611,7 @@ void CgRun::complete() {
             S.seconds = secs();
             S.seconds_to_1e6 = t6;
             S.dof_updates = (double)n * c.M * periods;
-            S.status = (stopped || (!fixed && rel > o.tol)) ? CMCG_NOT_CONVERGED : CMCG_OK;
+            S.status = (stopped || diverged || (!fixed && rel > o.tol)) ? CMCG_NOT_CONVERGED : CMCG_OK;
             phase = kDone;
             break;
         }
@@ -900,7 +920,7 @@ int cmcg_debug_rhs(cmcg_problem* p, const cmcg_options* o, double t, int with_so
     prepare(p, c);
     const SpaceData& s = *p->sp;
     p->Kbuf.alloc(s.ndof * s.esize());
-    launch_to_field(s.precision, s.Np, u, p->U.p, s.ndof, 0, stream);
+    launch_to_field(s.precision, s.Np, u, p->U.p, p->Ulo.p, s.ndof, 0, stream);
     StageArgs a = base_args(p);
     a.mode = RHS;
     a.Y = p->U.p;
@@ -910,7 +930,7 @@ int cmcg_debug_rhs(cmcg_problem* p, const cmcg_options* o, double t, int with_so
     a.scos = std::cos(p->omega * t);
     a.ssin = std::sin(p->omega * t);
     launch_stage(s.q, s.precision, a, stream);
-    launch_from_field(s.precision, s.Np, p->Kbuf.p, out, nullptr, s.ndof, 0, stream);
+    launch_from_field(s.precision, s.Np, p->Kbuf.p, nullptr, out, nullptr, s.ndof, 0, stream);
     CMCG_HIP(hipStreamSynchronize(stream));
     return CMCG_OK;
     CMCG_GUARD_END
