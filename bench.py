@@ -82,7 +82,8 @@ def measured_traffic(kernel: str, K: int):
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024
 
 
-STAGE_KERNEL = {0: "k_stage<float,{q},false>", 1: "k_stage<float,{q},true>", 2: "k_stage_mfma<{q}>"}
+STAGE_KERNEL = {0: "k_stage<float,{q},false>", 1: "k_stage<float,{q},true>", 2: "k_stage_mfma<{q},false>",
+                3: "k_stage_mfma<{q},true>"}
 
 
 def stage_bytes_per_element(q: int, esize: int) -> float:

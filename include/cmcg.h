@@ -282,8 +282,9 @@ int cmcg_engine_info(const cmcg_engine* e, size_t* used, int* n_running, int* n_
  * face's neighbour traces when it is processed, 1 requests them one face
  * ahead (more registers, more latency hiding), 2 runs the volume and lift
  * products on the matrix cores (FP32 fields, q = 2, 3; other combinations
- * fall back to 0).  All compute the same Phi(t, Y) and stage update.  Process-wide; not thread-safe against
- * concurrent solves.  Returns CMCG_ERR_ARG for an unknown q / precision /
+ * fall back to 0), 3 is 2 with the neighbour traces requested one face
+ * ahead.  All compute the same Phi(t, Y) and stage update.  Process-wide;
+ * not thread-safe against concurrent solves.  Returns CMCG_ERR_ARG for an unknown q / precision /
  * variant.  cmcg_tune_get_stage reports the current choice. */
 int cmcg_tune_stage(int q, int precision, int variant);
 int cmcg_tune_get_stage(int q, int precision, int* variant);

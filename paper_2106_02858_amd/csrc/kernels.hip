@@ -43,13 +43,18 @@ __host__ __device__ constexpr int mat_off(int q) { return q <= 1 ? 0 : mat_off(q
 constexpr int kMatTotal = mat_off(4);
 __host__ __device__ constexpr int fn_off(int q) { return q <= 1 ? 0 : fn_off(q - 1) + 4 * ((q) * (q + 1) / 2); }
 __host__ __device__ constexpr int fp_off(int q) { return q <= 1 ? 0 : fp_off(q - 1) + 6 * ((q) * (q + 1) / 2); }
+__host__ __device__ constexpr int nn_off(int q) { return q <= 1 ? 0 : nn_off(q - 1) + 24 * ((q) * (q + 1) / 2); }
 constexpr int kFnTotal = fn_off(4);
 constexpr int kFpTotal = fp_off(4);
+constexpr int kNnTotal = nn_off(4);
 
 __constant__ double cMat64[kMatTotal];
 __constant__ float cMat32[kMatTotal];
 __constant__ int cFnode[kFnTotal];
 __constant__ int cFperm[kFpTotal];
+// neighbour face node of face node k seen from the other side:
+// cNnode[nf][perm][k] = cFnode[nf][cFperm[perm][k]]
+__constant__ int cNnode[kNnTotal];
 
 template <typename T> __device__ __forceinline__ const T* mats();
 template <> __device__ __forceinline__ const double* mats<double>() { return cMat64; }
@@ -509,15 +514,56 @@ __device__ float gFrag[kFragTotal];
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <int Q>
+struct MfmaShared {
+    static constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP;
+    static constexpr int RS = NP + 1;
+    static constexpr int KF = 4 * MfmaDim<Q>::KSF;
+    float sY[EPW * 6 * RS];   // stage input, rows (element, component) padded to NP + 1
+    float sF[KF * 64];        // flux tile [face node][column], rows >= NFP stay zero
+    float sG[EPW * kGeo];     // geometry of the chunk
+    int sC[EPW * 4];          // connectivity codes of the chunk
+    int sT[28 * NFP];         // own face nodes [f][k], then neighbour face nodes [nf][perm][k]
+};
+
+// Neighbour traces of one face for the flux items a lane owns (item
+// it = lane + 64 r: face node it / ne of element it % ne).
+template <int Q, int RF> struct MfmaGather {
+    float v[RF][6];
+    int code[RF];
+    __device__ __forceinline__ void issue(const float* __restrict__ Y, const MfmaShared<Q>& sh, int ne, int f,
+                                          int lane) {
+        constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP;
+#pragma unroll
+        for (int r = 0; r < RF; ++r) {
+            const int it = lane + 64 * r;
+            code[r] = -3;
+            if (it < ne * NFP) {
+                const int k = it / ne;
+                const int fe = it - k * ne;
+                const int cd = sh.sC[fe * 4 + f];
+                code[r] = cd;
+                if (cd >= 0) {
+                    const int nn = sh.sT[4 * NFP + (((cd >> 3) & 3) * 6 + (cd & 7)) * NFP + k];
+                    const float* q = Y + (int64_t)(cd >> 5) * 6 * NP + nn;
+#pragma unroll
+                    for (int cc = 0; cc < 6; ++cc) v[r][cc] = q[cc * NP];
+                }
+            }
+        }
+    }
+};
+
+// PIPE: the next face's neighbour traces are requested before this face's
+// flux (more registers, the gather latency hides behind the lift).
+template <int Q, bool PIPE>
 __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) {
     using T = float;
     using MD = MfmaDim<Q>;
     constexpr int NP = MD::NP, NFP = MD::NFP, MT = MD::MT, KSV = MD::KSV, KSF = MD::KSF;
     constexpr int RS = NP + 1;
-    constexpr int KF = 4 * KSF;  // padded face rows of the flux tile
-    __shared__ T sY[EPW * 6 * RS];
-    __shared__ T sF[KF * 64];
-    __shared__ T sG[EPW * kGeo];
+    constexpr int KF = 4 * KSF;
+    constexpr int RF = (EPW * NFP + 63) / 64;
+    __shared__ MfmaShared<Q> sh;
 
     StageArgs a;
     if (!member_args<T>(args, a)) return;  // uniform per workgroup
@@ -528,8 +574,28 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
     const int lane = threadIdx.x;
     const int ne = (int)((a.K - e0) < EPW ? (a.K - e0) : EPW);
     const int64_t base = e0 * 6 * NP;
-    const int* fnode = cFnode + fn_off(Q);
-    const int* fperm = cFperm + fp_off(Q);
+    const int nv4 = ne * 6 * NP / 4;  // float4 groups of the chunk (6 NP is even, ne * 6 NP % 4 == 0 for NP even)
+
+    // ---- staging: chunk fields, geometry, connectivity, face-node tables
+    {
+        const float4* Y4 = reinterpret_cast<const float4*>(Y + base);
+        for (int v4 = lane; v4 < nv4; v4 += 64) {
+            const float4 x = Y4[v4];
+            const int v = 4 * v4;
+            sh.sY[v + v / NP] = x.x;
+            sh.sY[v + 1 + (v + 1) / NP] = x.y;
+            sh.sY[v + 2 + (v + 2) / NP] = x.z;
+            sh.sY[v + 3 + (v + 3) / NP] = x.w;
+        }
+        const float4* G4 = reinterpret_cast<const float4*>((const T*)a.geo + e0 * kGeo);
+        float4* sG4 = reinterpret_cast<float4*>(sh.sG);
+        for (int v4 = lane; v4 < ne * kGeo / 4; v4 += 64) sG4[v4] = G4[v4];
+        if (lane < ne * 4) sh.sC[lane] = a.conn[e0 * 4 + lane];
+        const int* tab = cFnode + fn_off(Q);
+        const int* ntab = cNnode + nn_off(Q);
+        for (int v = lane; v < 28 * NFP; v += 64) sh.sT[v] = v < 4 * NFP ? tab[v] : ntab[v - 4 * NFP];
+        for (int v = lane; v < KF * 64; v += 64) sh.sF[v] = T(0);
+    }
 
     // matrix fragments (coalesced: fragment-major, lane-minor)
     const float* fr = gFrag + frag_off(Q);
@@ -545,15 +611,11 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
 #pragma unroll
             for (int ks = 0; ks < KSF; ++ks)
                 afL[f][mt][ks] = fr[(MT * KSV + (f * MT + mt) * KSF + ks) * 64 + lane];
-
-    for (int v = lane; v < ne * 6 * NP; v += 64) {
-        const int r = v / NP;
-        sY[r * RS + (v - r * NP)] = Y[base + v];
-    }
-    const T* geo = (const T*)a.geo + e0 * kGeo;
-    for (int v = lane; v < ne * kGeo; v += 64) sG[v] = geo[v];
-    for (int v = lane; v < KF * 64; v += 64) sF[v] = T(0);
     __syncthreads();
+
+    // face 0's neighbour traces in flight during the volume product
+    MfmaGather<Q, RF> cur, nxt;
+    cur.issue(Y, sh, ne, 0, lane);
 
     const int q4 = lane >> 4;   // K row within a 4-row block / output row group
     const int l16 = lane & 15;  // output column within a 16-column tile
@@ -563,7 +625,7 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    // ---- volume product
+    // ---- volume product: B[k = a Np + j][n] = sgn (g_a[m1] V_m2(j) - g_a[m2] V_m1(j))
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         const int n = nt * 16 + l16;
@@ -574,17 +636,30 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
         const int m1 = m == 2 ? 0 : m + 1, m2 = m == 0 ? 2 : m - 1;  // (m+1)%3, (m+2)%3
         const int vb = e * 6 + (s < 3 ? 3 : 0);
         const T sgn = s < 3 ? T(-1) : T(1);
-        const T* gE = &sG[e * kGeo];
-        const T* v1 = &sY[(vb + m1) * RS];
-        const T* v2 = &sY[(vb + m2) * RS];
+        const T* gE = &sh.sG[e * kGeo];
+        T g1[3], g2[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            g1[ax] = sgn * gE[3 * ax + m1];
+            g2[ax] = sgn * gE[3 * ax + m2];
+        }
+        const T* v1 = &sh.sY[(vb + m1) * RS];
+        const T* v2 = &sh.sY[(vb + m2) * RS];
 #pragma unroll
         for (int ks = 0; ks < KSV; ++ks) {
             const int k = ks * 4 + q4;
             T b = T(0);
             if (ncol && k < 3 * NP) {
-                const int ax = k / NP;
+                // the axis is uniform over the 4-row block unless the block straddles Np
+                int ax;
+                if ((4 * ks) / NP == (4 * ks + 3) / NP)
+                    ax = (4 * ks) / NP;
+                else
+                    ax = k / NP;
                 const int j = k - ax * NP;
-                b = sgn * (gE[3 * ax + m1] * v2[j] - gE[3 * ax + m2] * v1[j]);
+                const T ga = ax == 0 ? g1[0] : (ax == 1 ? g1[1] : g1[2]);
+                const T gb = ax == 0 ? g2[0] : (ax == 1 ? g2[1] : g2[2]);
+                b = ga * v2[j] - gb * v1[j];
             }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
@@ -595,25 +670,26 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
     // ---- upwind flux and lift, one face at a time
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-        for (int it = lane; it < ne * NFP; it += 64) {
+        if (PIPE && f < 3) nxt.issue(Y, sh, ne, f + 1, lane);
+#pragma unroll
+        for (int r = 0; r < RF; ++r) {
+            const int it = lane + 64 * r;
+            if (it >= ne * NFP) continue;
             const int k = it / ne;
             const int fe = it - k * ne;
-            const int own = fnode[f * NFP + k];
+            const int own = sh.sT[f * NFP + k];
             T Em[3], Hm[3], Ep[3], Hp[3];
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) {
-                Em[cc] = sY[(fe * 6 + cc) * RS + own];
-                Hm[cc] = sY[(fe * 6 + 3 + cc) * RS + own];
+                Em[cc] = sh.sY[(fe * 6 + cc) * RS + own];
+                Hm[cc] = sh.sY[(fe * 6 + 3 + cc) * RS + own];
             }
-            const int code = a.conn[(e0 + fe) * 4 + f];
+            const int code = cur.code[r];
             if (code >= 0) {
-                const int64_t nb = code >> 5;
-                const int nn = fnode[((code >> 3) & 3) * NFP + fperm[(code & 7) * NFP + k]];
-                const T* q = Y + nb * 6 * NP + nn;
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc) {
-                    Ep[cc] = q[cc * NP];
-                    Hp[cc] = q[(3 + cc) * NP];
+                    Ep[cc] = cur.v[r][cc];
+                    Hp[cc] = cur.v[r][3 + cc];
                 }
             } else if (code == -1) {  // PEC ghost: E+ = -E-, H+ = H-
 #pragma unroll
@@ -628,7 +704,7 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
                     Hp[cc] = T(0);
                 }
             }
-            const T* g = &sG[fe * kGeo + 9 + 7 * f];
+            const T* g = &sh.sG[fe * kGeo + 9 + 7 * f];
             const T n0 = g[0], n1 = g[1], n2 = g[2];
             const T cE1 = g[3], cE2 = g[4], cH1 = g[5], cH2 = g[6];
             const T dE0 = Ep[0] - Em[0], dE1 = Ep[1] - Em[1], dE2 = Ep[2] - Em[2];
@@ -637,7 +713,7 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
             const T ndH = n0 * dH0 + n1 * dH1 + n2 * dH2;
             const T xH0 = n1 * dH2 - n2 * dH1, xH1 = n2 * dH0 - n0 * dH2, xH2 = n0 * dH1 - n1 * dH0;
             const T xE0 = n1 * dE2 - n2 * dE1, xE1 = n2 * dE0 - n0 * dE2, xE2 = n0 * dE1 - n1 * dE0;
-            T* o = &sF[k * 64 + fe * 6];
+            T* o = &sh.sF[k * 64 + fe * 6];
             o[0] = cE1 * (dE0 - ndE * n0) - cE2 * xH0;
             o[1] = cE1 * (dE1 - ndE * n1) - cE2 * xH1;
             o[2] = cE1 * (dE2 - ndE * n2) - cE2 * xH2;
@@ -650,7 +726,7 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
         for (int ks = 0; ks < KSF; ++ks) {
             T b[4];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) b[nt] = sF[(ks * 4 + q4) * 64 + nt * 16 + l16];
+            for (int nt = 0; nt < 4; ++nt) b[nt] = sh.sF[(ks * 4 + q4) * 64 + nt * 16 + l16];
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
@@ -658,133 +734,141 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(afL[f][mt][ks], b[nt], acc[mt][nt], 0, 0, 0);
         }
         __syncthreads();  // the tile is rewritten by the next face
+        if (f < 3) {
+            if (!PIPE) nxt.issue(Y, sh, ne, f + 1, lane);
+            cur = nxt;
+        }
     }
 
-    // ---- stage update on the lane's output block (4 consecutive nodes of one column)
-    const int mode = a.mode;
-    const T scos = (T)a.scos, ssin = (T)a.ssin;
-    const T cy = (T)a.cy, ca = (T)a.ca, cu = (T)a.cu;
+    // ---- scaled right-hand side (1/eps or 1/mu, conductivity) into the
+    // staging tile, in place: every value is read and written by one lane
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         const int n = nt * 16 + l16;
         if (n >= 6 * ne) continue;
         const int e = n / 6;
         const int s = n - 6 * e;
-        const T inv = s < 3 ? sG[e * kGeo + 37] : sG[e * kGeo + 38];
-        const T sig = s < 3 ? sG[e * kGeo + 39] : T(0);
+        const T inv = s < 3 ? sh.sG[e * kGeo + 37] : sh.sG[e * kGeo + 38];
+        const T sig = s < 3 ? sh.sG[e * kGeo + 39] : T(0);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const int i0 = mt * 16 + 4 * q4;
-            if (i0 >= NP) continue;
-            constexpr int W = (NP % 4 == 0) ? 4 : 2;  // NP = 20: float4 blocks; NP = 10: float2 pairs
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int h = 0; h < 4 / W; ++h) {
-                const int i = i0 + h * W;
-                if (i >= NP) continue;
-                const int64_t gi = base + (int64_t)n * NP + i;
-                T kv[W], yv[W];
-#pragma unroll
-                for (int u = 0; u < W; ++u) {
-                    yv[u] = sY[n * RS + i + u];
-                    kv[u] = fma(inv, acc[mt][nt][h * W + u], -sig * yv[u]);
+            for (int r = 0; r < 4; ++r) {
+                const int i = mt * 16 + 4 * q4 + r;
+                if (i < NP) {
+                    T* p = &sh.sY[n * RS + i];
+                    *p = fma(inv, acc[mt][nt][r], -sig * *p);
                 }
-                using VW = typename std::conditional<W == 4, float4, float2>::type;
-                auto ld = [&](const void* p, T (&o)[W]) {
-                    VW v = *reinterpret_cast<const VW*>((const T*)p + gi);
-                    const T* t = reinterpret_cast<const T*>(&v);
+            }
+    }
+    __syncthreads();
+
+    // ---- stage update: one coalesced pass over the chunk's contiguous rows
+    const int mode = a.mode;
+    const T scos = (T)a.scos, ssin = (T)a.ssin;
+    const T cy = (T)a.cy, ca = (T)a.ca, cu = (T)a.cu;
+    auto f4 = [](const void* p, int64_t o) { return reinterpret_cast<const float4*>((const T*)p + o); };
+    for (int v4 = lane; v4 < nv4; v4 += 64) {
+        const int v = 4 * v4;
+        const int64_t gi = base + v;
+        T kv[4];
 #pragma unroll
-                    for (int u = 0; u < W; ++u) o[u] = t[u];
-                };
-                auto st = [&](void* p, const T (&o)[W]) {
-                    VW v;
-                    T* t = reinterpret_cast<T*>(&v);
+        for (int u = 0; u < 4; ++u) kv[u] = sh.sY[v + u + (v + u) / NP];
+        if (a.src_rows > 0) {
+            const float4 sr = *f4(a.Sre, gi), si = *f4(a.Sim, gi);
+            const T srv[4] = {sr.x, sr.y, sr.z, sr.w}, siv[4] = {si.x, si.y, si.z, si.w};
 #pragma unroll
-                    for (int u = 0; u < W; ++u) t[u] = o[u];
-                    *reinterpret_cast<VW*>((T*)p + gi) = v;
-                };
-                // bfloat16 low parts: W = 4 -> 8 bytes, W = 2 -> 4 bytes
-                using VH = typename std::conditional<W == 4, uint2, uint32_t>::type;
-                auto ld_lo = [&](T (&o)[W]) {
-                    VH v = *reinterpret_cast<const VH*>((const uint16_t*)a.Ulo + gi);
-                    const uint32_t* w = reinterpret_cast<const uint32_t*>(&v);
+            for (int u = 0; u < 4; ++u) {
+                const int row = (v + u) / NP;
+                if (row - 6 * (row / 6) < a.src_rows) kv[u] += scos * srv[u] - ssin * siv[u];
+            }
+        }
+        T yv[4] = {0.f, 0.f, 0.f, 0.f};
+        if (mode == RK2_S1 || mode == RK4_S1 || a.filter) {
+            const float4 y = *f4(Y, gi);
+            yv[0] = y.x;
+            yv[1] = y.y;
+            yv[2] = y.z;
+            yv[3] = y.w;
+        }
+        auto st4 = [&](void* p, const T (&o)[4]) {
+            *reinterpret_cast<float4*>((T*)p + gi) = make_float4(o[0], o[1], o[2], o[3]);
+        };
+        auto ld4 = [&](const void* p, T (&o)[4]) {
+            const float4 x = *f4(p, gi);
+            o[0] = x.x;
+            o[1] = x.y;
+            o[2] = x.z;
+            o[3] = x.w;
+        };
+        auto ld_lo = [&](T (&o)[4]) {
+            const uint2 w = *reinterpret_cast<const uint2*>((const uint16_t*)a.Ulo + gi);
+            o[0] = from_bf16(w.x & 0xffffu);
+            o[1] = from_bf16(w.x >> 16);
+            o[2] = from_bf16(w.y & 0xffffu);
+            o[3] = from_bf16(w.y >> 16);
+        };
+        auto st_lo = [&](const T (&o)[4]) {
+            uint2 w;
+            w.x = (uint32_t)to_bf16(o[0]) | ((uint32_t)to_bf16(o[1]) << 16);
+            w.y = (uint32_t)to_bf16(o[2]) | ((uint32_t)to_bf16(o[3]) << 16);
+            *reinterpret_cast<uint2*>((uint16_t*)a.Ulo + gi) = w;
+        };
+        T o1[4], o2[4], up[4], ap[4], lo[4];
+        switch (mode) {
+            case RK2_S1:
 #pragma unroll
-                    for (int u = 0; u < W / 2; ++u) {
-                        o[2 * u] = from_bf16(w[u] & 0xffffu);
-                        o[2 * u + 1] = from_bf16(w[u] >> 16);
-                    }
-                };
-                auto st_lo = [&](const T (&o)[W]) {
-                    VH v;
-                    uint32_t* w = reinterpret_cast<uint32_t*>(&v);
+                for (int u = 0; u < 4; ++u) o1[u] = fma(cy, kv[u], yv[u]);
+                st4(a.Ynext, o1);
+                break;
+            case RK2_S2:
+                ld4(a.U, up);
+                ld_lo(lo);
 #pragma unroll
-                    for (int u = 0; u < W / 2; ++u)
-                        w[u] = (uint32_t)to_bf16(o[2 * u]) | ((uint32_t)to_bf16(o[2 * u + 1]) << 16);
-                    *reinterpret_cast<VH*>((uint16_t*)a.Ulo + gi) = v;
-                };
-                if (s < a.src_rows) {
-                    T sr[W], si[W];
-                    ld(a.Sre, sr);
-                    ld(a.Sim, si);
+                for (int u = 0; u < 4; ++u) two_sum(up[u], fma(cu, kv[u], lo[u]), o1[u], o2[u]);
+                st4(a.Uout, o1);
+                st_lo(o2);
+                break;
+            case RK4_S1:
 #pragma unroll
-                    for (int u = 0; u < W; ++u) kv[u] += scos * sr[u] - ssin * si[u];
+                for (int u = 0; u < 4; ++u) {
+                    o1[u] = fma(cy, kv[u], yv[u]);
+                    o2[u] = ca * kv[u];
                 }
-                T o1[W], o2[W], up[W], ap[W], lo[W];
-                switch (mode) {
-                    case RK2_S1:
+                st4(a.Ynext, o1);
+                st4(a.Acc, o2);
+                break;
+            case RK4_S2:
+            case RK4_S3:
+                ld4(a.U, up);
+                ld4(a.Acc, ap);
 #pragma unroll
-                        for (int u = 0; u < W; ++u) o1[u] = fma(cy, kv[u], yv[u]);
-                        st(a.Ynext, o1);
-                        break;
-                    case RK2_S2:
-                        ld(a.U, up);
-                        ld_lo(lo);
-#pragma unroll
-                        for (int u = 0; u < W; ++u) two_sum(up[u], fma(cu, kv[u], lo[u]), o1[u], o2[u]);
-                        st(a.Uout, o1);
-                        st_lo(o2);
-                        break;
-                    case RK4_S1:
-#pragma unroll
-                        for (int u = 0; u < W; ++u) {
-                            o1[u] = fma(cy, kv[u], yv[u]);
-                            o2[u] = ca * kv[u];
-                        }
-                        st(a.Ynext, o1);
-                        st(a.Acc, o2);
-                        break;
-                    case RK4_S2:
-                    case RK4_S3:
-                        ld(a.U, up);
-                        ld(a.Acc, ap);
-#pragma unroll
-                        for (int u = 0; u < W; ++u) {
-                            o1[u] = fma(cy, kv[u], up[u]);
-                            o2[u] = fma(ca, kv[u], ap[u]);
-                        }
-                        st(a.Ynext, o1);
-                        st(a.Acc, o2);
-                        break;
-                    case RK4_S4:
-                        ld(a.U, up);
-                        ld(a.Acc, ap);
-                        ld_lo(lo);
-#pragma unroll
-                        for (int u = 0; u < W; ++u) two_sum(up[u], fma(cu, kv[u], ap[u]) + lo[u], o1[u], o2[u]);
-                        st(a.Uout, o1);
-                        st_lo(o2);
-                        break;
-                    default:
-                        st(a.Kout, kv);
-                        break;
+                for (int u = 0; u < 4; ++u) {
+                    o1[u] = fma(cy, kv[u], up[u]);
+                    o2[u] = fma(ca, kv[u], ap[u]);
                 }
-                if (a.filter) {
+                st4(a.Ynext, o1);
+                st4(a.Acc, o2);
+                break;
+            case RK4_S4:
+                ld4(a.U, up);
+                ld4(a.Acc, ap);
+                ld_lo(lo);
 #pragma unroll
-                    for (int u = 0; u < W; ++u) {
-                        const double ud = (double)yv[u], kd = (double)kv[u];
-                        a.Fre[gi + u] += a.fa_re * ud + a.fb_re * kd;
-                        a.Fim[gi + u] += a.fa_im * ud + a.fb_im * kd;
-                    }
-                }
+                for (int u = 0; u < 4; ++u) two_sum(up[u], fma(cu, kv[u], ap[u]) + lo[u], o1[u], o2[u]);
+                st4(a.Uout, o1);
+                st_lo(o2);
+                break;
+            default:
+                st4(a.Kout, kv);
+                break;
+        }
+        if (a.filter) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double ud = (double)yv[u], kd = (double)kv[u];
+                a.Fre[gi + u] += a.fa_re * ud + a.fb_re * kd;
+                a.Fim[gi + u] += a.fa_im * ud + a.fb_im * kd;
             }
         }
     }
@@ -981,11 +1065,13 @@ __global__ void k_nonfinite(const double* X, int64_t n, int* flag) {
 }
 
 // Stage-kernel variant per (q, precision): 0 = gather per face, 1 = gathers
-// pipelined one face ahead.  Chosen from measurements; overridable through
-// cmcg_tune_stage().
-// Defaults from the measured 48000-tet P3 / 10368-tet P2 periods: matrix
-// cores for FP32 P3 (64 us vs 75 us per stage), per-face gathers otherwise.
-int g_variant[kMaxQ + 1][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 2}};
+// pipelined one face ahead, 2 / 3 = matrix cores (FP32, q >= 2) without /
+// with the one-face-ahead gathers.  Chosen from measurements; overridable
+// through cmcg_tune_stage().  Defaults from stage timings on 48000- and
+// 384000-tet meshes: FP32 P2 and P3 on the matrix cores with gathers one face
+// ahead (P3: 53 us vs 78 us, P2: 22.5 us vs 25.7 us per stage at 48000 tets),
+// per-face gathers otherwise.
+int g_variant[kMaxQ + 1][2] = {{0, 0}, {0, 0}, {0, 3}, {0, 3}};
 inline int stage_variant(int q, int precision) { return g_variant[q][precision]; }
 
 inline int grid_for(int64_t n, int threads = 256) {
@@ -1003,7 +1089,11 @@ void stage_launch(const StageArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)(8 * per), (unsigned)(a.nmembers > 1 ? a.nmembers : 1));
     if constexpr (sizeof(T) == 4 && Q >= 2) {
         if (v == 2) {
-            hipLaunchKernelGGL((k_stage_mfma<Q>), grid, dim3(64), 0, s, a, per);
+            hipLaunchKernelGGL((k_stage_mfma<Q, false>), grid, dim3(64), 0, s, a, per);
+            return;
+        }
+        if (v == 3) {
+            hipLaunchKernelGGL((k_stage_mfma<Q, true>), grid, dim3(64), 0, s, a, per);
             return;
         }
     }
@@ -1039,6 +1129,14 @@ void upload_constants(int q, int precision, const double* D, const double* LIFT,
                                hipMemcpyHostToDevice));
     CMCG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cFperm), fperm, 6 * NFP * sizeof(int), fp_off(q) * sizeof(int),
                                hipMemcpyHostToDevice));
+    {
+        std::vector<int> nn(24 * NFP);
+        for (int nf = 0; nf < 4; ++nf)
+            for (int pm = 0; pm < 6; ++pm)
+                for (int k = 0; k < NFP; ++k) nn[(nf * 6 + pm) * NFP + k] = fnode[nf * NFP + fperm[pm * NFP + k]];
+        CMCG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cNnode), nn.data(), nn.size() * sizeof(int), nn_off(q) * sizeof(int),
+                                   hipMemcpyHostToDevice));
+    }
     if (q >= 2) {
         // lane-ordered A fragments of the matrix-core kernel: entry (frag, lane)
         // = A[16 mt + lane % 16][4 ks + lane / 16] of the block the fragment names

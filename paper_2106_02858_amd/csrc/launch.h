@@ -64,7 +64,7 @@ void upload_constants(int q, int precision, const double* D, const double* LIFT,
 void launch_stage(int q, int precision, const StageArgs& a, hipStream_t s);
 void set_stage_variant(int q, int precision, int variant);
 int get_stage_variant(int q, int precision);
-constexpr int kStageVariants = 3;  // 2: matrix cores (FP32, q >= 2)
+constexpr int kStageVariants = 4;  // 2, 3: matrix cores (FP32, q >= 2; 3 gathers one face ahead)
 
 // FP64 <-> field precision; flipH negates the magnetic rows (the S of P* = S P S).
 // FP32: Ulo (nullable) receives / contributes the bfloat16 low part.
