@@ -518,28 +518,46 @@ struct MfmaShared {
     static constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP;
     static constexpr int RS = NP + 1;
     static constexpr int KF = 4 * MfmaDim<Q>::KSF;
+    static constexpr int FS = 65;  // flux tile row stride: the face nodes of one column fall in different banks
     float sY[EPW * 6 * RS];   // stage input, rows (element, component) padded to NP + 1
-    float sF[KF * 64];        // flux tile [face node][column], rows >= NFP stay zero
+    float sF[KF * FS];        // flux tile [face node][column], rows >= NFP stay zero
     float sG[EPW * kGeo];     // geometry of the chunk
     int sC[EPW * 4];          // connectivity codes of the chunk
-    int sT[28 * NFP];         // own face nodes [f][k], then neighbour face nodes [nf][perm][k]
+    uint8_t sT[28 * NFP];     // own face nodes [f][k], then neighbour face nodes [nf][perm][k]
 };
 
-// Neighbour traces of one face for the flux items a lane owns (item
-// it = lane + 64 r: face node it / ne of element it % ne).
-template <int Q, int RF> struct MfmaGather {
-    float v[RF][6];
-    int code[RF];
-    __device__ __forceinline__ void issue(const float* __restrict__ Y, const MfmaShared<Q>& sh, int ne, int f,
-                                          int lane) {
-        constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP;
+// Flux items of a lane: item it = lane + 64 r is face node k = it / ne of
+// element fe = it % ne (consecutive lanes on different elements); computed
+// once per chunk (the divisor is the compile-time chunk size for full chunks).
+template <int Q, int RF> struct MfmaItems {
+    int k[RF], fe[RF];
+    bool on[RF];
+    __device__ __forceinline__ void init(int ne, int lane) {
+        constexpr int NFP = Dim<Q>::NFP;
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
             const int it = lane + 64 * r;
+            on[r] = it < ne * NFP;
+            const int kk = ne == EPW ? it / EPW : it / ne;
+            k[r] = on[r] ? kk : 0;
+            fe[r] = on[r] ? it - kk * ne : 0;
+        }
+    }
+};
+
+// Neighbour traces of one face for the flux items a lane owns.
+template <int Q, int RF> struct MfmaGather {
+    float v[RF][6];
+    int code[RF];
+    __device__ __forceinline__ void issue(const float* __restrict__ Y, const MfmaShared<Q>& sh,
+                                          const MfmaItems<Q, RF>& itm, int f) {
+        constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP;
+#pragma unroll
+        for (int r = 0; r < RF; ++r) {
             code[r] = -3;
-            if (it < ne * NFP) {
-                const int k = it / ne;
-                const int fe = it - k * ne;
+            if (itm.on[r]) {
+                const int k = itm.k[r];
+                const int fe = itm.fe[r];
                 const int cd = sh.sC[fe * 4 + f];
                 code[r] = cd;
                 if (cd >= 0) {
@@ -553,10 +571,43 @@ template <int Q, int RF> struct MfmaGather {
     }
 };
 
+// Operands of the coalesced update pass (float4 groups v4 = lane + 64 t of
+// the chunk), all requested before the pass computes: r0 = U (stage 2-4
+// modes) or the stage input (stage-1 modes, filter), r1 = Acc, r2 = the
+// bfloat16 low parts.
+template <int Q> struct MfmaUpdateIn {
+    static constexpr int NIT = (EPW * 6 * Dim<Q>::NP / 4 + 63) / 64;
+    float4 r0[NIT], r1[NIT];
+    uint2 r2[NIT];
+    __device__ __forceinline__ void fetch(const StageArgs& a, int64_t base, int nv4, int lane) {
+        const int mode = a.mode;
+        const bool s1 = mode == RK2_S1 || mode == RK4_S1 || (mode == RHS && a.filter);
+        const bool needU = mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4;
+        const bool needA = mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4;
+        const bool needL = mode == RK2_S2 || mode == RK4_S4;
+        const float* src0 = needU ? (const float*)a.U : (const float*)a.Y;
+#pragma unroll
+        for (int t = 0; t < NIT; ++t) {
+            const int v4 = lane + 64 * t;
+            if (v4 >= nv4) continue;
+            const int64_t gi = base + 4 * v4;
+            if (s1 || needU) r0[t] = *reinterpret_cast<const float4*>(src0 + gi);
+            if (needA) r1[t] = *reinterpret_cast<const float4*>((const float*)a.Acc + gi);
+            if (needL) r2[t] = *reinterpret_cast<const uint2*>((const uint16_t*)a.Ulo + gi);
+        }
+    }
+};
+
 // PIPE: the next face's neighbour traces are requested before this face's
-// flux (more registers, the gather latency hides behind the lift).
+// flux (more registers, the gather latency hides behind the lift).  Register
+// allocation is held to 4 waves per SIMD (128 registers; the LDS tiles of
+// MfmaShared<3> stay under 10 KB so 16 workgroups fit a compute unit).
+// Requesting the update operands earlier (with the staging loads, or before
+// the last face) was measured slower: the registers cost occupancy (P2) or
+// spill (P3).
 template <int Q, bool PIPE>
-__global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_stage_mfma(StageArgs args,
+                                                                                             int64_t per) {
     using T = float;
     using MD = MfmaDim<Q>;
     constexpr int NP = MD::NP, NFP = MD::NFP, MT = MD::MT, KSV = MD::KSV, KSF = MD::KSF;
@@ -593,8 +644,8 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
         if (lane < ne * 4) sh.sC[lane] = a.conn[e0 * 4 + lane];
         const int* tab = cFnode + fn_off(Q);
         const int* ntab = cNnode + nn_off(Q);
-        for (int v = lane; v < 28 * NFP; v += 64) sh.sT[v] = v < 4 * NFP ? tab[v] : ntab[v - 4 * NFP];
-        for (int v = lane; v < KF * 64; v += 64) sh.sF[v] = T(0);
+        for (int v = lane; v < 28 * NFP; v += 64) sh.sT[v] = (uint8_t)(v < 4 * NFP ? tab[v] : ntab[v - 4 * NFP]);
+        for (int v = lane; v < KF * MfmaShared<Q>::FS; v += 64) sh.sF[v] = T(0);
     }
 
     // matrix fragments (coalesced: fragment-major, lane-minor)
@@ -614,8 +665,10 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
     __syncthreads();
 
     // face 0's neighbour traces in flight during the volume product
+    MfmaItems<Q, RF> itm;
+    itm.init(ne, lane);
     MfmaGather<Q, RF> cur, nxt;
-    cur.issue(Y, sh, ne, 0, lane);
+    cur.issue(Y, sh, itm, 0);
 
     const int q4 = lane >> 4;   // K row within a 4-row block / output row group
     const int l16 = lane & 15;  // output column within a 16-column tile
@@ -670,13 +723,12 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
     // ---- upwind flux and lift, one face at a time
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-        if (PIPE && f < 3) nxt.issue(Y, sh, ne, f + 1, lane);
+        if (PIPE && f < 3) nxt.issue(Y, sh, itm, f + 1);
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
-            const int it = lane + 64 * r;
-            if (it >= ne * NFP) continue;
-            const int k = it / ne;
-            const int fe = it - k * ne;
+            if (!itm.on[r]) continue;
+            const int k = itm.k[r];
+            const int fe = itm.fe[r];
             const int own = sh.sT[f * NFP + k];
             T Em[3], Hm[3], Ep[3], Hp[3];
 #pragma unroll
@@ -713,7 +765,7 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
             const T ndH = n0 * dH0 + n1 * dH1 + n2 * dH2;
             const T xH0 = n1 * dH2 - n2 * dH1, xH1 = n2 * dH0 - n0 * dH2, xH2 = n0 * dH1 - n1 * dH0;
             const T xE0 = n1 * dE2 - n2 * dE1, xE1 = n2 * dE0 - n0 * dE2, xE2 = n0 * dE1 - n1 * dE0;
-            T* o = &sh.sF[k * 64 + fe * 6];
+            T* o = &sh.sF[k * MfmaShared<Q>::FS + fe * 6];
             o[0] = cE1 * (dE0 - ndE * n0) - cE2 * xH0;
             o[1] = cE1 * (dE1 - ndE * n1) - cE2 * xH1;
             o[2] = cE1 * (dE2 - ndE * n2) - cE2 * xH2;
@@ -726,7 +778,7 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
         for (int ks = 0; ks < KSF; ++ks) {
             T b[4];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) b[nt] = sh.sF[(ks * 4 + q4) * 64 + nt * 16 + l16];
+            for (int nt = 0; nt < 4; ++nt) b[nt] = sh.sF[(ks * 4 + q4) * MfmaShared<Q>::FS + nt * 16 + l16];
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
@@ -735,7 +787,7 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
         }
         __syncthreads();  // the tile is rewritten by the next face
         if (f < 3) {
-            if (!PIPE) nxt.issue(Y, sh, ne, f + 1, lane);
+            if (!PIPE) nxt.issue(Y, sh, itm, f + 1);
             cur = nxt;
         }
     }
@@ -767,8 +819,13 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
     const int mode = a.mode;
     const T scos = (T)a.scos, ssin = (T)a.ssin;
     const T cy = (T)a.cy, ca = (T)a.ca, cu = (T)a.cu;
+    MfmaUpdateIn<Q> upd;
+    upd.fetch(a, base, nv4, lane);
     auto f4 = [](const void* p, int64_t o) { return reinterpret_cast<const float4*>((const T*)p + o); };
-    for (int v4 = lane; v4 < nv4; v4 += 64) {
+#pragma unroll
+    for (int t = 0; t < MfmaUpdateIn<Q>::NIT; ++t) {
+        const int v4 = lane + 64 * t;
+        if (v4 >= nv4) continue;
         const int v = 4 * v4;
         const int64_t gi = base + v;
         T kv[4];
@@ -783,30 +840,17 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
                 if (row - 6 * (row / 6) < a.src_rows) kv[u] += scos * srv[u] - ssin * siv[u];
             }
         }
-        T yv[4] = {0.f, 0.f, 0.f, 0.f};
-        if (mode == RK2_S1 || mode == RK4_S1 || a.filter) {
-            const float4 y = *f4(Y, gi);
-            yv[0] = y.x;
-            yv[1] = y.y;
-            yv[2] = y.z;
-            yv[3] = y.w;
+        const T x0[4] = {upd.r0[t].x, upd.r0[t].y, upd.r0[t].z, upd.r0[t].w};  // U, or Y in stage-1 modes
+        const T x1[4] = {upd.r1[t].x, upd.r1[t].y, upd.r1[t].z, upd.r1[t].w};  // Acc
+        T lo[4];
+        if (mode == RK2_S2 || mode == RK4_S4) {
+            lo[0] = from_bf16(upd.r2[t].x & 0xffffu);
+            lo[1] = from_bf16(upd.r2[t].x >> 16);
+            lo[2] = from_bf16(upd.r2[t].y & 0xffffu);
+            lo[3] = from_bf16(upd.r2[t].y >> 16);
         }
         auto st4 = [&](void* p, const T (&o)[4]) {
             *reinterpret_cast<float4*>((T*)p + gi) = make_float4(o[0], o[1], o[2], o[3]);
-        };
-        auto ld4 = [&](const void* p, T (&o)[4]) {
-            const float4 x = *f4(p, gi);
-            o[0] = x.x;
-            o[1] = x.y;
-            o[2] = x.z;
-            o[3] = x.w;
-        };
-        auto ld_lo = [&](T (&o)[4]) {
-            const uint2 w = *reinterpret_cast<const uint2*>((const uint16_t*)a.Ulo + gi);
-            o[0] = from_bf16(w.x & 0xffffu);
-            o[1] = from_bf16(w.x >> 16);
-            o[2] = from_bf16(w.y & 0xffffu);
-            o[3] = from_bf16(w.y >> 16);
         };
         auto st_lo = [&](const T (&o)[4]) {
             uint2 w;
@@ -814,25 +858,23 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
             w.y = (uint32_t)to_bf16(o[2]) | ((uint32_t)to_bf16(o[3]) << 16);
             *reinterpret_cast<uint2*>((uint16_t*)a.Ulo + gi) = w;
         };
-        T o1[4], o2[4], up[4], ap[4], lo[4];
+        T o1[4], o2[4];
         switch (mode) {
             case RK2_S1:
 #pragma unroll
-                for (int u = 0; u < 4; ++u) o1[u] = fma(cy, kv[u], yv[u]);
+                for (int u = 0; u < 4; ++u) o1[u] = fma(cy, kv[u], x0[u]);
                 st4(a.Ynext, o1);
                 break;
             case RK2_S2:
-                ld4(a.U, up);
-                ld_lo(lo);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) two_sum(up[u], fma(cu, kv[u], lo[u]), o1[u], o2[u]);
+                for (int u = 0; u < 4; ++u) two_sum(x0[u], fma(cu, kv[u], lo[u]), o1[u], o2[u]);
                 st4(a.Uout, o1);
                 st_lo(o2);
                 break;
             case RK4_S1:
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    o1[u] = fma(cy, kv[u], yv[u]);
+                    o1[u] = fma(cy, kv[u], x0[u]);
                     o2[u] = ca * kv[u];
                 }
                 st4(a.Ynext, o1);
@@ -840,22 +882,17 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
                 break;
             case RK4_S2:
             case RK4_S3:
-                ld4(a.U, up);
-                ld4(a.Acc, ap);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    o1[u] = fma(cy, kv[u], up[u]);
-                    o2[u] = fma(ca, kv[u], ap[u]);
+                    o1[u] = fma(cy, kv[u], x0[u]);
+                    o2[u] = fma(ca, kv[u], x1[u]);
                 }
                 st4(a.Ynext, o1);
                 st4(a.Acc, o2);
                 break;
             case RK4_S4:
-                ld4(a.U, up);
-                ld4(a.Acc, ap);
-                ld_lo(lo);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) two_sum(up[u], fma(cu, kv[u], ap[u]) + lo[u], o1[u], o2[u]);
+                for (int u = 0; u < 4; ++u) two_sum(x0[u], fma(cu, kv[u], x1[u]) + lo[u], o1[u], o2[u]);
                 st4(a.Uout, o1);
                 st_lo(o2);
                 break;
@@ -863,10 +900,10 @@ __global__ __launch_bounds__(64) void k_stage_mfma(StageArgs args, int64_t per) 
                 st4(a.Kout, kv);
                 break;
         }
-        if (a.filter) {
+        if (a.filter) {  // stage-1 and RHS modes: x0 is the stage input
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const double ud = (double)yv[u], kd = (double)kv[u];
+                const double ud = (double)x0[u], kd = (double)kv[u];
                 a.Fre[gi + u] += a.fa_re * ud + a.fb_re * kd;
                 a.Fim[gi + u] += a.fa_im * ud + a.fb_im * kd;
             }
