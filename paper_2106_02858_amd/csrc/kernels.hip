@@ -187,31 +187,105 @@ __device__ __forceinline__ bool member_args(const StageArgs& in, StageArgs& a) {
     return true;
 }
 
-// Neighbour traces of one face for the flux items a lane owns.  Item it of
-// face f is (element it % ne, face node it / ne), so consecutive lanes belong
-// to different elements (conflict-free LDS tile writes).  Interior faces read
-// the neighbour's stage input from global memory (cache-resident: the
-// neighbours are nearby in the element ordering); boundary items keep the
-// connectivity code and build their ghost state later.
-template <typename T, int Q, int RF> struct FaceGather {
-    T v[RF][6];
-    int code[RF];
-    __device__ __forceinline__ void issue(const StageArgs& a, const T* __restrict__ Y, int64_t e0, int ne, int f,
-                                          int lane, const int* fnode, const int* fperm) {
-        constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP;
+// One chunk's stage input and geometry (16-byte coalesced loads, all issued
+// before the first is consumed) and its connectivity codes; put() stores them
+// in LDS with the stage-input rows padded to NP + 1.
+template <typename T, int Q> struct ChunkIn {
+    static constexpr int NP = Dim<Q>::NP;
+    static constexpr int PV = 16 / (int)sizeof(T);  // values per load
+    static constexpr int NY = (EPW * 6 * NP / PV + 63) / 64, NG = (EPW * kGeo / PV + 63) / 64;
+    using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+    static_assert((6 * NP) % PV == 0 && kGeo % PV == 0, "rows must split into 16-byte groups");
+    V y[NY], g[NG];
+    int cd;
+    __device__ __forceinline__ void fetch(const T* __restrict__ Y, const T* __restrict__ geo,
+                                          const int* __restrict__ conn, int64_t e0, int ne, int lane) {
+        const V* Y4 = reinterpret_cast<const V*>(Y + e0 * 6 * NP);
+        const V* G4 = reinterpret_cast<const V*>(geo + e0 * kGeo);
+#pragma unroll
+        for (int i = 0; i < NY; ++i)
+            if (lane + 64 * i < ne * 6 * NP / PV) y[i] = Y4[lane + 64 * i];
+#pragma unroll
+        for (int i = 0; i < NG; ++i)
+            if (lane + 64 * i < ne * kGeo / PV) g[i] = G4[lane + 64 * i];
+        cd = lane < ne * 4 ? conn[e0 * 4 + lane] : -3;
+    }
+    __device__ __forceinline__ void put(T* sY, T* sG, int* sC, int ne, int lane) const {
+#pragma unroll
+        for (int i = 0; i < NY; ++i) {
+            const int g4 = lane + 64 * i;
+            if (g4 < ne * 6 * NP / PV) {
+                const T* t = reinterpret_cast<const T*>(&y[i]);
+#pragma unroll
+                for (int u = 0; u < PV; ++u) {
+                    const int v = PV * g4 + u;
+                    sY[v + v / NP] = t[u];
+                }
+            }
+        }
+        V* sG4 = reinterpret_cast<V*>(sG);
+#pragma unroll
+        for (int i = 0; i < NG; ++i)
+            if (lane + 64 * i < ne * kGeo / PV) sG4[lane + 64 * i] = g[i];
+        if (lane < ne * 4) sC[lane] = cd;
+    }
+};
+
+// Face-node tables in LDS (bytes): own face nodes [f][k], then the node of
+// the neighbour's face seen from this side [nf][perm][k].
+template <int Q> __device__ __forceinline__ void load_face_tables(uint8_t* sT, int lane) {
+    constexpr int NFP = Dim<Q>::NFP, N = 28 * NFP, IT = (N + 63) / 64;
+    const int* tab = cFnode + fn_off(Q);
+    const int* ntab = cNnode + nn_off(Q);
+    int t[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int v = lane + 64 * i;
+        t[i] = v < 4 * NFP ? tab[v] : (v < N ? ntab[v - 4 * NFP] : 0);
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i)
+        if (lane + 64 * i < N) sT[lane + 64 * i] = (uint8_t)t[i];
+}
+
+// Flux items of a lane: item it = lane + 64 r is face node k = it / ne of
+// element fe = it % ne (consecutive lanes on different elements); computed
+// once per chunk (the divisor is the compile-time chunk size for full chunks).
+template <int Q, int RF> struct FluxItems {
+    int k[RF], fe[RF];
+    bool on[RF];
+    __device__ __forceinline__ void init(int ne, int lane) {
+        constexpr int NFP = Dim<Q>::NFP;
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
             const int it = lane + 64 * r;
+            on[r] = it < ne * NFP;
+            const int kk = ne == EPW ? it / EPW : it / ne;
+            k[r] = on[r] ? kk : 0;
+            fe[r] = on[r] ? it - kk * ne : 0;
+        }
+    }
+};
+
+// Neighbour traces of one face for the flux items a lane owns: the
+// connectivity code and the neighbour's node come from LDS, so each item is
+// one round of global loads (cache-resident: neighbours are nearby in the
+// element ordering).  Boundary items keep the code and build a ghost later.
+template <typename T, int Q, int RF> struct TraceGather {
+    T v[RF][6];
+    int code[RF];
+    __device__ __forceinline__ void issue(const T* __restrict__ Y, const int* sC, const uint8_t* sT,
+                                          const FluxItems<Q, RF>& itm, int f) {
+        constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP;
+#pragma unroll
+        for (int r = 0; r < RF; ++r) {
             code[r] = -3;
-            if (it < ne * NFP) {
-                const int k = it / ne;
-                const int fe = it - k * ne;
-                const int cd = a.conn[(e0 + fe) * 4 + f];
+            if (itm.on[r]) {
+                const int cd = sC[itm.fe[r] * 4 + f];
                 code[r] = cd;
                 if (cd >= 0) {
-                    const int64_t nb = cd >> 5;
-                    const int nn = fnode[((cd >> 3) & 3) * NFP + fperm[(cd & 7) * NFP + k]];
-                    const T* q = Y + nb * 6 * NP + nn;
+                    const int nn = sT[4 * NFP + (((cd >> 3) & 3) * 6 + (cd & 7)) * NFP + itm.k[r]];
+                    const T* q = Y + (int64_t)(cd >> 5) * 6 * NP + nn;
 #pragma unroll
                     for (int cc = 0; cc < 6; ++cc) v[r][cc] = q[cc * NP];
                 }
@@ -230,9 +304,12 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     constexpr int MO = mat_off(Q);
     constexpr int LO = MO + 3 * NP * NP;  // LIFT [NP][NF4]
     constexpr int RF = (EPW * NFP + 63) / 64;  // flux items per lane and face
+    constexpr int FS = 65;                     // flux tile row stride (bank spread)
     __shared__ T sY[EPW * 6 * RS];
-    __shared__ T sF[NFP * 64];
+    __shared__ T sF[NFP * FS];
     __shared__ T sG[EPW * kGeo];
+    __shared__ int sC[EPW * 4];
+    __shared__ uint8_t sT[28 * NFP];
 
     StageArgs a;
     if (!member_args<T>(args, a)) return;  // uniform per workgroup
@@ -243,8 +320,6 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     const int lane = threadIdx.x;
     const int ne = (int)((a.K - e0) < EPW ? (a.K - e0) : EPW);
     const int64_t base = e0 * 6 * NP;
-    const int* fnode = cFnode + fn_off(Q);
-    const int* fperm = cFperm + fp_off(Q);
 
     // column ownership: lane = (element, component)
     const int el = lane / 6;
@@ -259,17 +334,18 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     const bool needU = mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || needL;
     const bool needA = mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4;
 
-    // neighbour traces of face 0 in flight during the staging and volume work
-    FaceGather<T, Q, RF> cur, nxt;
-    if (PIPE) cur.issue(a, Y, e0, ne, 0, lane, fnode, fperm);
-
-    for (int v = lane; v < ne * 6 * NP; v += 64) {
-        const int r = v / NP;
-        sY[r * RS + (v - r * NP)] = Y[base + v];
+    {
+        ChunkIn<T, Q> in;
+        in.fetch(Y, (const T*)a.geo, a.conn, e0, ne, lane);
+        load_face_tables<Q>(sT, lane);
+        in.put(sY, sG, sC, ne, lane);
     }
-    const T* geo = (const T*)a.geo + e0 * kGeo;
-    for (int v = lane; v < ne * kGeo; v += 64) sG[v] = geo[v];
     __syncthreads();
+    // neighbour traces of face 0 in flight during the volume work
+    FluxItems<Q, RF> itm;
+    itm.init(ne, lane);
+    TraceGather<T, Q, RF> cur, nxt;
+    if (PIPE) cur.issue(Y, sC, sT, itm, 0);
 
     // ---- volume term: D_a y per column, curl terms exchanged between lanes
     T y[NP];
@@ -319,7 +395,7 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     for (int f = 0; f < 4; ++f) {
         if (PIPE) {
             if (f < 3) {
-                nxt.issue(a, Y, e0, ne, f + 1, lane, fnode, fperm);
+                nxt.issue(Y, sC, sT, itm, f + 1);
             } else if (act) {
                 if (needU) Row<T, NP>::load((const T*)a.U + grow, up);
                 if (needA) Row<T, NP>::load((const T*)a.Acc + grow, ap);
@@ -327,15 +403,14 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
                     if (needL) RowH<NP>::load((const uint16_t*)a.Ulo + grow, lo);
             }
         } else {
-            cur.issue(a, Y, e0, ne, f, lane, fnode, fperm);
+            cur.issue(Y, sC, sT, itm, f);
         }
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
-            const int it = lane + 64 * r;
-            if (it >= ne * NFP) continue;
-            const int k = it / ne;
-            const int fe = it - k * ne;
-            const int own = fnode[f * NFP + k];
+            if (!itm.on[r]) continue;
+            const int k = itm.k[r];
+            const int fe = itm.fe[r];
+            const int own = sT[f * NFP + k];
             T Em[3], Hm[3], Ep[3], Hp[3];
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) {
@@ -371,7 +446,7 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
             const T ndH = n0 * dH0 + n1 * dH1 + n2 * dH2;
             const T xH0 = n1 * dH2 - n2 * dH1, xH1 = n2 * dH0 - n0 * dH2, xH2 = n0 * dH1 - n1 * dH0;
             const T xE0 = n1 * dE2 - n2 * dE1, xE1 = n2 * dE0 - n0 * dE2, xE2 = n0 * dE1 - n1 * dE0;
-            T* o = &sF[k * 64 + fe * 6];
+            T* o = &sF[k * FS + fe * 6];
             o[0] = cE1 * (dE0 - ndE * n0) - cE2 * xH0;
             o[1] = cE1 * (dE1 - ndE * n1) - cE2 * xH1;
             o[2] = cE1 * (dE2 - ndE * n2) - cE2 * xH2;
@@ -382,7 +457,7 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
         __syncthreads();
         T fl[NFP];
 #pragma unroll
-        for (int k = 0; k < NFP; ++k) fl[k] = sF[k * 64 + lane];
+        for (int k = 0; k < NFP; ++k) fl[k] = sF[k * FS + lane];
         __syncthreads();  // the tile is rewritten by the next face
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
@@ -526,51 +601,6 @@ struct MfmaShared {
     uint8_t sT[28 * NFP];     // own face nodes [f][k], then neighbour face nodes [nf][perm][k]
 };
 
-// Flux items of a lane: item it = lane + 64 r is face node k = it / ne of
-// element fe = it % ne (consecutive lanes on different elements); computed
-// once per chunk (the divisor is the compile-time chunk size for full chunks).
-template <int Q, int RF> struct MfmaItems {
-    int k[RF], fe[RF];
-    bool on[RF];
-    __device__ __forceinline__ void init(int ne, int lane) {
-        constexpr int NFP = Dim<Q>::NFP;
-#pragma unroll
-        for (int r = 0; r < RF; ++r) {
-            const int it = lane + 64 * r;
-            on[r] = it < ne * NFP;
-            const int kk = ne == EPW ? it / EPW : it / ne;
-            k[r] = on[r] ? kk : 0;
-            fe[r] = on[r] ? it - kk * ne : 0;
-        }
-    }
-};
-
-// Neighbour traces of one face for the flux items a lane owns.
-template <int Q, int RF> struct MfmaGather {
-    float v[RF][6];
-    int code[RF];
-    __device__ __forceinline__ void issue(const float* __restrict__ Y, const MfmaShared<Q>& sh,
-                                          const MfmaItems<Q, RF>& itm, int f) {
-        constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP;
-#pragma unroll
-        for (int r = 0; r < RF; ++r) {
-            code[r] = -3;
-            if (itm.on[r]) {
-                const int k = itm.k[r];
-                const int fe = itm.fe[r];
-                const int cd = sh.sC[fe * 4 + f];
-                code[r] = cd;
-                if (cd >= 0) {
-                    const int nn = sh.sT[4 * NFP + (((cd >> 3) & 3) * 6 + (cd & 7)) * NFP + k];
-                    const float* q = Y + (int64_t)(cd >> 5) * 6 * NP + nn;
-#pragma unroll
-                    for (int cc = 0; cc < 6; ++cc) v[r][cc] = q[cc * NP];
-                }
-            }
-        }
-    }
-};
-
 // Operands of the coalesced update pass (float4 groups v4 = lane + 64 t of
 // the chunk), all requested before the pass computes: r0 = U (stage 2-4
 // modes) or the stage input (stage-1 modes, filter), r1 = Acc, r2 = the
@@ -629,22 +659,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 
     // ---- staging: chunk fields, geometry, connectivity, face-node tables
     {
-        const float4* Y4 = reinterpret_cast<const float4*>(Y + base);
-        for (int v4 = lane; v4 < nv4; v4 += 64) {
-            const float4 x = Y4[v4];
-            const int v = 4 * v4;
-            sh.sY[v + v / NP] = x.x;
-            sh.sY[v + 1 + (v + 1) / NP] = x.y;
-            sh.sY[v + 2 + (v + 2) / NP] = x.z;
-            sh.sY[v + 3 + (v + 3) / NP] = x.w;
-        }
-        const float4* G4 = reinterpret_cast<const float4*>((const T*)a.geo + e0 * kGeo);
-        float4* sG4 = reinterpret_cast<float4*>(sh.sG);
-        for (int v4 = lane; v4 < ne * kGeo / 4; v4 += 64) sG4[v4] = G4[v4];
-        if (lane < ne * 4) sh.sC[lane] = a.conn[e0 * 4 + lane];
-        const int* tab = cFnode + fn_off(Q);
-        const int* ntab = cNnode + nn_off(Q);
-        for (int v = lane; v < 28 * NFP; v += 64) sh.sT[v] = (uint8_t)(v < 4 * NFP ? tab[v] : ntab[v - 4 * NFP]);
+        ChunkIn<T, Q> in;
+        in.fetch(Y, (const T*)a.geo, a.conn, e0, ne, lane);
+        in.put(sh.sY, sh.sG, sh.sC, ne, lane);
+        load_face_tables<Q>(sh.sT, lane);
         for (int v = lane; v < KF * MfmaShared<Q>::FS; v += 64) sh.sF[v] = T(0);
     }
 
@@ -665,10 +683,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     __syncthreads();
 
     // face 0's neighbour traces in flight during the volume product
-    MfmaItems<Q, RF> itm;
+    FluxItems<Q, RF> itm;
     itm.init(ne, lane);
-    MfmaGather<Q, RF> cur, nxt;
-    cur.issue(Y, sh, itm, 0);
+    TraceGather<T, Q, RF> cur, nxt;
+    cur.issue(Y, sh.sC, sh.sT, itm, 0);
 
     const int q4 = lane >> 4;   // K row within a 4-row block / output row group
     const int l16 = lane & 15;  // output column within a 16-column tile
@@ -723,7 +741,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     // ---- upwind flux and lift, one face at a time
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-        if (PIPE && f < 3) nxt.issue(Y, sh, itm, f + 1);
+        if (PIPE && f < 3) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1);
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
             if (!itm.on[r]) continue;
@@ -787,7 +805,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         }
         __syncthreads();  // the tile is rewritten by the next face
         if (f < 3) {
-            if (!PIPE) nxt.issue(Y, sh, itm, f + 1);
+            if (!PIPE) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1);
             cur = nxt;
         }
     }
