@@ -41,20 +41,18 @@ __host__ __device__ constexpr int mat_size(int q) {
 }
 __host__ __device__ constexpr int mat_off(int q) { return q <= 1 ? 0 : mat_off(q - 1) + mat_size(q - 1); }
 constexpr int kMatTotal = mat_off(4);
-__host__ __device__ constexpr int fn_off(int q) { return q <= 1 ? 0 : fn_off(q - 1) + 4 * ((q) * (q + 1) / 2); }
-__host__ __device__ constexpr int fp_off(int q) { return q <= 1 ? 0 : fp_off(q - 1) + 6 * ((q) * (q + 1) / 2); }
-__host__ __device__ constexpr int nn_off(int q) { return q <= 1 ? 0 : nn_off(q - 1) + 24 * ((q) * (q + 1) / 2); }
-constexpr int kFnTotal = fn_off(4);
-constexpr int kFpTotal = fp_off(4);
-constexpr int kNnTotal = nn_off(4);
+// face-node tables as packed bytes in 32-bit words: [fnode (4 Nfp) | nnode (24 Nfp)]
+__host__ __device__ constexpr int ft_words(int q) { return (28 * ((q + 1) * (q + 2) / 2) + 3) / 4; }
+__host__ __device__ constexpr int ft_off(int q) { return q <= 1 ? 0 : ft_off(q - 1) + ft_words(q - 1); }
+constexpr int kFtTotal = ft_off(4);
 
 __constant__ double cMat64[kMatTotal];
 __constant__ float cMat32[kMatTotal];
-__constant__ int cFnode[kFnTotal];
-__constant__ int cFperm[kFpTotal];
-// neighbour face node of face node k seen from the other side:
-// cNnode[nf][perm][k] = cFnode[nf][cFperm[perm][k]]
-__constant__ int cNnode[kNnTotal];
+// Per order q, one byte per entry packed into 32-bit words: the volume node of
+// face node k of face f ([f][k], 4 Nfp entries), then the volume node of the
+// neighbour's face node that sits at face node k of this side, for every
+// neighbour face nf and vertex permutation perm ([nf][perm][k], 24 Nfp).
+__constant__ uint32_t cFaceTab[kFtTotal];
 
 template <typename T> __device__ __forceinline__ const T* mats();
 template <> __device__ __forceinline__ const double* mats<double>() { return cMat64; }
@@ -196,12 +194,17 @@ template <typename T, int Q> struct ChunkIn {
     static constexpr int NY = (EPW * 6 * NP / PV + 63) / 64, NG = (EPW * kGeo / PV + 63) / 64;
     using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
     static_assert((6 * NP) % PV == 0 && kGeo % PV == 0, "rows must split into 16-byte groups");
+    static constexpr int NT = (ft_words(Q) + 63) / 64;  // face-table words per lane
     V y[NY], g[NG];
     int cd;
+    uint32_t tw[NT];
     __device__ __forceinline__ void fetch(const T* __restrict__ Y, const T* __restrict__ geo,
                                           const int* __restrict__ conn, int64_t e0, int ne, int lane) {
         const V* Y4 = reinterpret_cast<const V*>(Y + e0 * 6 * NP);
         const V* G4 = reinterpret_cast<const V*>(geo + e0 * kGeo);
+#pragma unroll
+        for (int i = 0; i < NT; ++i)
+            if (lane + 64 * i < ft_words(Q)) tw[i] = cFaceTab[ft_off(Q) + lane + 64 * i];
 #pragma unroll
         for (int i = 0; i < NY; ++i)
             if (lane + 64 * i < ne * 6 * NP / PV) y[i] = Y4[lane + 64 * i];
@@ -210,7 +213,11 @@ template <typename T, int Q> struct ChunkIn {
             if (lane + 64 * i < ne * kGeo / PV) g[i] = G4[lane + 64 * i];
         cd = lane < ne * 4 ? conn[e0 * 4 + lane] : -3;
     }
-    __device__ __forceinline__ void put(T* sY, T* sG, int* sC, int ne, int lane) const {
+    __device__ __forceinline__ void put(T* sY, T* sG, int* sC, uint8_t* sT, int ne, int lane) const {
+        uint32_t* sT4 = reinterpret_cast<uint32_t*>(sT);
+#pragma unroll
+        for (int i = 0; i < NT; ++i)
+            if (lane + 64 * i < ft_words(Q)) sT4[lane + 64 * i] = tw[i];
 #pragma unroll
         for (int i = 0; i < NY; ++i) {
             const int g4 = lane + 64 * i;
@@ -231,22 +238,9 @@ template <typename T, int Q> struct ChunkIn {
     }
 };
 
-// Face-node tables in LDS (bytes): own face nodes [f][k], then the node of
-// the neighbour's face seen from this side [nf][perm][k].
-template <int Q> __device__ __forceinline__ void load_face_tables(uint8_t* sT, int lane) {
-    constexpr int NFP = Dim<Q>::NFP, N = 28 * NFP, IT = (N + 63) / 64;
-    const int* tab = cFnode + fn_off(Q);
-    const int* ntab = cNnode + nn_off(Q);
-    int t[IT];
-#pragma unroll
-    for (int i = 0; i < IT; ++i) {
-        const int v = lane + 64 * i;
-        t[i] = v < 4 * NFP ? tab[v] : (v < N ? ntab[v - 4 * NFP] : 0);
-    }
-#pragma unroll
-    for (int i = 0; i < IT; ++i)
-        if (lane + 64 * i < N) sT[lane + 64 * i] = (uint8_t)t[i];
-}
+// The face-node tables reach LDS with the chunk (ChunkIn): own face nodes
+// [f][k], then the node of the neighbour's face seen from this side
+// [nf][perm][k], one byte each.
 
 // Flux items of a lane: item it = lane + 64 r is face node k = it / ne of
 // element fe = it % ne (consecutive lanes on different elements); computed
@@ -309,7 +303,7 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     __shared__ T sF[NFP * FS];
     __shared__ T sG[EPW * kGeo];
     __shared__ int sC[EPW * 4];
-    __shared__ uint8_t sT[28 * NFP];
+    __shared__ __align__(4) uint8_t sT[4 * ft_words(Q)];
 
     StageArgs a;
     if (!member_args<T>(args, a)) return;  // uniform per workgroup
@@ -337,8 +331,7 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     {
         ChunkIn<T, Q> in;
         in.fetch(Y, (const T*)a.geo, a.conn, e0, ne, lane);
-        load_face_tables<Q>(sT, lane);
-        in.put(sY, sG, sC, ne, lane);
+        in.put(sY, sG, sC, sT, ne, lane);
     }
     __syncthreads();
     // neighbour traces of face 0 in flight during the volume work
@@ -598,7 +591,7 @@ struct MfmaShared {
     float sF[KF * FS];        // flux tile [face node][column], rows >= NFP stay zero
     float sG[EPW * kGeo];     // geometry of the chunk
     int sC[EPW * 4];          // connectivity codes of the chunk
-    uint8_t sT[28 * NFP];     // own face nodes [f][k], then neighbour face nodes [nf][perm][k]
+    uint8_t sT[4 * ft_words(Q)];  // own face nodes [f][k], then neighbour face nodes [nf][perm][k]
 };
 
 // Operands of the coalesced update pass (float4 groups v4 = lane + 64 t of
@@ -661,9 +654,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     {
         ChunkIn<T, Q> in;
         in.fetch(Y, (const T*)a.geo, a.conn, e0, ne, lane);
-        in.put(sh.sY, sh.sG, sh.sC, ne, lane);
-        load_face_tables<Q>(sh.sT, lane);
         for (int v = lane; v < KF * MfmaShared<Q>::FS; v += 64) sh.sF[v] = T(0);
+        in.put(sh.sY, sh.sG, sh.sC, sh.sT, ne, lane);
     }
 
     // matrix fragments (coalesced: fragment-major, lane-minor)
@@ -1180,17 +1172,19 @@ void upload_constants(int q, int precision, const double* D, const double* LIFT,
                                hipMemcpyHostToDevice));
     CMCG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cMat32), bf.data(), n * sizeof(float), off * sizeof(float),
                                hipMemcpyHostToDevice));
-    CMCG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cFnode), fnode, 4 * NFP * sizeof(int), fn_off(q) * sizeof(int),
-                               hipMemcpyHostToDevice));
-    CMCG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cFperm), fperm, 6 * NFP * sizeof(int), fp_off(q) * sizeof(int),
-                               hipMemcpyHostToDevice));
     {
         std::vector<int> nn(24 * NFP);
         for (int nf = 0; nf < 4; ++nf)
             for (int pm = 0; pm < 6; ++pm)
                 for (int k = 0; k < NFP; ++k) nn[(nf * 6 + pm) * NFP + k] = fnode[nf * NFP + fperm[pm * NFP + k]];
-        CMCG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cNnode), nn.data(), nn.size() * sizeof(int), nn_off(q) * sizeof(int),
-                                   hipMemcpyHostToDevice));
+        std::vector<uint32_t> words(ft_words(q), 0u);
+        for (int i = 0; i < 28 * NFP; ++i) {
+            const int v = i < 4 * NFP ? fnode[i] : nn[i - 4 * NFP];
+            if (v < 0 || v > 255) fail(CMCG_ERR_ARG, "face-node table entry out of byte range");
+            words[i / 4] |= (uint32_t)v << (8 * (i % 4));
+        }
+        CMCG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(cFaceTab), words.data(), words.size() * sizeof(uint32_t),
+                                   ft_off(q) * sizeof(uint32_t), hipMemcpyHostToDevice));
     }
     if (q >= 2) {
         // lane-ordered A fragments of the matrix-core kernel: entry (frag, lane)
