@@ -262,27 +262,53 @@ template <int Q, int RF> struct FluxItems {
 };
 
 // Neighbour traces of one face for the flux items a lane owns: the
-// connectivity code and the neighbour's node come from LDS, so each item is
+// connectivity code and the neighbour's node come from LDS.  A neighbour in
+// the same chunk (about half of the interior faces of a cube-ordered mesh)
+// is read from the staged tile later (loc = its LDS offset); the others are
 // one round of global loads (cache-resident: neighbours are nearby in the
 // element ordering).  Boundary items keep the code and build a ghost later.
 template <typename T, int Q, int RF> struct TraceGather {
+    static constexpr int RS = Dim<Q>::NP + 1;  // staged row stride
     T v[RF][6];
-    int code[RF];
+    int code[RF], loc[RF];
     __device__ __forceinline__ void issue(const T* __restrict__ Y, const int* sC, const uint8_t* sT,
-                                          const FluxItems<Q, RF>& itm, int f) {
+                                          const FluxItems<Q, RF>& itm, int f, int64_t e0, int ne) {
         constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP;
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
             code[r] = -3;
+            loc[r] = -1;
             if (itm.on[r]) {
                 const int cd = sC[itm.fe[r] * 4 + f];
                 code[r] = cd;
                 if (cd >= 0) {
                     const int nn = sT[4 * NFP + (((cd >> 3) & 3) * 6 + (cd & 7)) * NFP + itm.k[r]];
-                    const T* q = Y + (int64_t)(cd >> 5) * 6 * NP + nn;
+                    const int64_t nb = cd >> 5;
+                    const int64_t d = nb - e0;
+                    if (d >= 0 && d < ne) {
+                        loc[r] = (int)d * 6 * RS + nn;
+                    } else {
+                        const T* q = Y + nb * 6 * NP + nn;
 #pragma unroll
-                    for (int cc = 0; cc < 6; ++cc) v[r][cc] = q[cc * NP];
+                        for (int cc = 0; cc < 6; ++cc) v[r][cc] = q[cc * NP];
+                    }
                 }
+            }
+        }
+    }
+    // neighbour values of item r (after issue; sY = the staged chunk)
+    __device__ __forceinline__ void values(const T* sY, int r, T (&Ep)[3], T (&Hp)[3]) const {
+        if (loc[r] >= 0) {
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                Ep[cc] = sY[loc[r] + cc * RS];
+                Hp[cc] = sY[loc[r] + (3 + cc) * RS];
+            }
+        } else {
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                Ep[cc] = v[r][cc];
+                Hp[cc] = v[r][3 + cc];
             }
         }
     }
@@ -338,7 +364,7 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     FluxItems<Q, RF> itm;
     itm.init(ne, lane);
     TraceGather<T, Q, RF> cur, nxt;
-    if (PIPE) cur.issue(Y, sC, sT, itm, 0);
+    if (PIPE) cur.issue(Y, sC, sT, itm, 0, e0, ne);
 
     // ---- volume term: D_a y per column, curl terms exchanged between lanes
     T y[NP];
@@ -388,7 +414,7 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     for (int f = 0; f < 4; ++f) {
         if (PIPE) {
             if (f < 3) {
-                nxt.issue(Y, sC, sT, itm, f + 1);
+                nxt.issue(Y, sC, sT, itm, f + 1, e0, ne);
             } else if (act) {
                 if (needU) Row<T, NP>::load((const T*)a.U + grow, up);
                 if (needA) Row<T, NP>::load((const T*)a.Acc + grow, ap);
@@ -396,7 +422,7 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
                     if (needL) RowH<NP>::load((const uint16_t*)a.Ulo + grow, lo);
             }
         } else {
-            cur.issue(Y, sC, sT, itm, f);
+            cur.issue(Y, sC, sT, itm, f, e0, ne);
         }
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
@@ -412,11 +438,7 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
             }
             const int code = cur.code[r];
             if (code >= 0) {
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    Ep[cc] = cur.v[r][cc];
-                    Hp[cc] = cur.v[r][3 + cc];
-                }
+                cur.values(sY, r, Ep, Hp);
             } else if (code == -1) {  // PEC ghost: E+ = -E-, H+ = H-
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc) {
@@ -678,7 +700,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     FluxItems<Q, RF> itm;
     itm.init(ne, lane);
     TraceGather<T, Q, RF> cur, nxt;
-    cur.issue(Y, sh.sC, sh.sT, itm, 0);
+    cur.issue(Y, sh.sC, sh.sT, itm, 0, e0, ne);
 
     const int q4 = lane >> 4;   // K row within a 4-row block / output row group
     const int l16 = lane & 15;  // output column within a 16-column tile
@@ -733,7 +755,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     // ---- upwind flux and lift, one face at a time
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-        if (PIPE && f < 3) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1);
+        if (PIPE && f < 3) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1, e0, ne);
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
             if (!itm.on[r]) continue;
@@ -748,11 +770,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
             }
             const int code = cur.code[r];
             if (code >= 0) {
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    Ep[cc] = cur.v[r][cc];
-                    Hp[cc] = cur.v[r][3 + cc];
-                }
+                cur.values(sh.sY, r, Ep, Hp);
             } else if (code == -1) {  // PEC ghost: E+ = -E-, H+ = H-
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc) {
@@ -797,7 +815,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         }
         __syncthreads();  // the tile is rewritten by the next face
         if (f < 3) {
-            if (!PIPE) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1);
+            if (!PIPE) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1, e0, ne);
             cur = nxt;
         }
     }
