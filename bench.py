@@ -45,10 +45,12 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=4, help="RK steps of the CPU oracle sample")
     ap.add_argument("--kernel-periods", type=int, default=3)
-    ap.add_argument("--workload", choices=["large_single", "batched", "serving"], default="large_single",
+    ap.add_argument("--workload", choices=["large_single", "batched", "serving", "scatterer"],
+                    default="large_single",
                     help="large_single (default bench line), the 64-member batched configuration, or the "
                          "Poisson request stream through the serving engine")
     ap.add_argument("--members", type=int, default=64)
+    ap.add_argument("--cg-iters", type=int, default=6, help="scatterer: CG iterations of the timed solve")
     ap.add_argument("--requests", type=int, default=60, help="serving: requests taken from the stream")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: Poisson arrival rate (req/s)")
     ap.add_argument("--slots", type=int, default=8, help="serving: engine slots")
@@ -199,6 +201,71 @@ def job_roofline(rate: float, bpd: float) -> dict:
     return {"bytes_per_dof_update": bpd, "achieved_GBs": gbs, "peak_GBs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}
 
 
+def scatterer(a):
+    """The 64^3 x 6 = 1572864-tet P2 dielectric-sphere scatterer (eps = 4 in
+    the sphere of radius 1/4, omega = 8 pi, source width 0.03 at
+    (0.15, 0.5, 0.5)), FP32 fields: a CMCG solve of --cg-iters iterations plus
+    the filter period (its working set is far beyond the on-die caches), and
+    the stage kernel's rate at this size."""
+    import torch
+
+    from paper_2106_02858_amd import cmcg, inputs
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    w = inputs.scatterer()
+    mesh = cmcg.cmcg_mesh_create(w.xyz, w.tet, w.tags)
+    s = cmcg.cmcg_space_create(mesh, w.q, cmcg.CMCG_FP32)
+    nodes = cmcg.cmcg_space_nodes(s)
+    jd = torch.tensor(inputs.gaussian_current(nodes, w.centre, w.width, w.pol), dtype=torch.float64, device=dev)
+    p = cmcg.cmcg_problem_create_device(s, w.eps, w.mu, w.sigma, w.omega, jd)
+    del jd, nodes
+    info = cmcg.cmcg_space_info(s)
+    K, Np = info["K"], info["Np"]
+    opts = cmcg.cmcg_options_default(fixed_iters=a.cg_iters)
+    M, dt = cmcg.cmcg_problem_steps(p, opts)
+    log(f"scatterer K={K} Np={Np} M={M}")
+    t_ref = [time.perf_counter()]
+
+    def progress(it, rel):
+        log(f"  iter {it} rel {rel:.3e} t {time.perf_counter() - t_ref[0]:.1f}s")
+        return False
+
+    opts.set_progress(progress)
+    U0 = torch.randn((K, 6, Np), dtype=torch.float64, device=dev) * 1e-3
+    UT = torch.empty_like(U0)
+    cmcg.cmcg_debug_period(p, U0, UT, 1, False, opts=opts)  # builds the period's graph
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = cmcg.cmcg_solve(p, opts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = cmcg.cmcg_result_stats(r)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    cmcg.cmcg_debug_period(p, U0, UT, 1, False, opts=opts)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    per_launch = ev0.elapsed_time(ev1) / 1e3 / (4 * M)
+    bpe = stage_bytes_per_element(w.q, 4)
+    achieved = bpe * K / per_launch / 1e9
+    kname = STAGE_KERNEL[cmcg.cmcg_tune_get_stage(w.q, cmcg.CMCG_FP32)].format(q=w.q)
+    out = {"metric": "DG dof-updates/s; CMCG time-to-1e-6 residual vs FP64 plain; p50/p99 latency",
+           "value": st["dof_updates"] / el, "unit": "dof-updates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": el * 1e3, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"scatterer: 64^3x6 = {K} tets, P2, eps = 4 in the sphere |x - c| < 1/4 "
+                                  f"(103392 tets), omega = 8 pi, source width 0.03 at (0.15,0.5,0.5); "
+                                  f"CMCG {a.cg_iters} iterations + filter period", "K": K, "q": w.q,
+                      "steps_per_period": M},
+           "cmcg": {"iters": st["iters"], "periods": st["periods"], "rel_res": st["rel_res"]},
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kname,
+                        "avg_launch_us": per_launch * 1e6, "bytes_per_launch": bpe * K},
+           "hbm_job": job_roofline(st["dof_updates"] / el, bytes_per_dof_update(w.q, 4))}
+    print(json.dumps(out), flush=True)
+
+
 def served(a):
     """The request stream (n in {8,12,16,24}, q in {1,2,3}, omega in [2pi,8pi],
     eps per cube in {1,2,4}, Poisson arrivals) through the serving engine."""
@@ -233,6 +300,9 @@ def main():
         return
     if a.workload == "serving":
         served(a)
+        return
+    if a.workload == "scatterer":
+        scatterer(a)
         return
     import numpy as np
     import torch
