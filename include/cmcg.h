@@ -257,9 +257,12 @@ int cmcg_debug_dot(cmcg_problem* p, const double* u_dev, const double* v_dev, do
  *   slot is free or the footprint does not fit the remaining budget (the
  *   caller keeps the request queued), CMCG_ERR_STATE when p is already held
  *   by a slot.  p must stay alive until the slot is collected or cancelled.
- * cmcg_engine_step: advances every running slot by one chunk of work (the
- *   initial periods, one half of a CG iteration, or the filter period);
- *   reports how many slots still run and how many wait for collection.
+ * cmcg_engine_step: advances every running slot whose chunk of work (the
+ *   initial periods, one half of a CG iteration, or the filter period) has
+ *   completed on its stream, enqueueing its next chunk; waits (polling) until
+ *   at least one slot has advanced, so slots of different sizes never wait
+ *   for one another; reports how many slots still run and how many wait for
+ *   collection.
  * cmcg_engine_poll: slot state 0 free, 1 running, 2 finished, 3 failed.
  * cmcg_engine_collect: hands over the result of a finished slot and frees it
  *   (returns the solve's status, or its error code for a failed slot).

@@ -9,6 +9,13 @@
 // resident until collected, which frees the slot and its budget.  A slot runs
 // exactly the launch sequence of cmcg_solve, so a served result equals the
 // same problem solved alone.
+//
+// cmcg_engine_step polls the slots' streams and advances every slot whose
+// chunk has completed, so a short solve is never held back by a long one on
+// another slot; it blocks (polling) only until at least one slot has
+// advanced.
+#include <thread>
+
 #include "objects.h"
 
 struct cmcg_engine {
@@ -131,23 +138,38 @@ int cmcg_engine_step(cmcg_engine* e, int* n_running, int* n_finished) {
     ENGINE_GUARD_BEGIN
     if (!e) fail(CMCG_ERR_ARG, "engine_step: NULL engine");
     int running = 0, finished = 0;
-    for (auto& s : e->slots) {
-        if (s.state != 1) continue;
-        try {
-            CMCG_HIP(hipStreamSynchronize(s.st));
-            s.run->complete();
-            if (s.run->done()) {
-                s.result = std::move(s.run->res);
+    for (int spins = 0;; ++spins) {
+        bool any = false, advanced = false;
+        for (auto& s : e->slots) {
+            if (s.state != 1) continue;
+            any = true;
+            try {
+                const hipError_t q = hipStreamQuery(s.st);
+                if (q == hipErrorNotReady) {
+                    (void)hipGetLastError();  // not an error: keep launch checks clean
+                    continue;
+                }
+                CMCG_HIP(q);
+                s.run->complete();
+                advanced = true;
+                if (s.run->done()) {
+                    s.result = std::move(s.run->res);
+                    s.run.reset();
+                    s.state = 2;
+                }
+            } catch (const Error& err) {
+                (void)hipGetLastError();
+                (void)hipStreamSynchronize(s.st);
                 s.run.reset();
-                s.state = 2;
+                s.state = 3;
+                s.err = err.code;
+                s.msg = err.msg;
+                advanced = true;
             }
-        } catch (const Error& err) {
-            (void)hipStreamSynchronize(s.st);
-            s.run.reset();
-            s.state = 3;
-            s.err = err.code;
-            s.msg = err.msg;
         }
+        if (!any || advanced) break;
+        // nothing completed yet: poll again shortly
+        if (spins > 64) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
     for (auto& s : e->slots) {
         running += s.state == 1;
