@@ -74,3 +74,29 @@ def test_options_defaults():
     from paper_2106_02858_amd import cmcg
     o = cmcg.cmcg_options_default()
     assert o.tol == 1e-8 and o.max_iter == 1000 and o.use_graph == 1 and o.fixed_iters == 0
+
+
+def test_mesh_edge_cases_host_only():
+    from paper_2106_02858_amd import cmcg
+    xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.float64)
+    tags = np.full((1, 4), cmcg.CMCG_TAG_IMPEDANCE, dtype=np.int8)
+    # a single tetrahedron: every face on the boundary
+    m = cmcg.cmcg_mesh_create(xyz, np.array([[0, 1, 2, 3]]), tags)
+    info = cmcg.cmcg_mesh_info(m)
+    assert info["K"] == 1 and info["n_boundary"] == 4
+    # the same tetrahedron with negative orientation is accepted (vertices reordered)
+    m2 = cmcg.cmcg_mesh_create(xyz, np.array([[1, 0, 2, 3]]), tags)
+    assert abs(cmcg.cmcg_mesh_info(m2)["min_rho"] - info["min_rho"]) < 1e-15
+    # empty mesh, too few vertices
+    with pytest.raises(cmcg.CmcgError) as e:
+        cmcg.cmcg_mesh_create(xyz, np.zeros((0, 4), dtype=np.int64), np.zeros((0, 4), dtype=np.int8))
+    assert e.value.code == cmcg.CMCG_ERR_ARG
+    with pytest.raises(cmcg.CmcgError) as e:
+        cmcg.cmcg_mesh_create(xyz[:3], np.array([[0, 1, 2, 2]]), tags)
+    assert e.value.code == cmcg.CMCG_ERR_ARG
+    # coplanar vertices: zero volume
+    flat = xyz.copy()
+    flat[3] = [1, 1, 0]
+    with pytest.raises(cmcg.CmcgError) as e:
+        cmcg.cmcg_mesh_create(flat, np.array([[0, 1, 2, 3]]), tags)
+    assert e.value.code == cmcg.CMCG_ERR_MESH

@@ -1,0 +1,143 @@
+"""Edge cases of the GPU path: every ragged chunk size (1..10 elements in
+the last 10-element chunk), a single-tetrahedron mesh, the zero-source
+problem (whose periodic solution is zero), argument and state errors."""
+import numpy as np
+import pytest
+
+from oracle import cmcg as ocmcg
+from oracle import dg
+from paper_2106_02858_amd import inputs
+from tests._pairs import lib_problem, rel_norm_c
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def first_elements(n_elem):
+    """The first n_elem tetrahedra of the 2^3 x 6 cube mesh, retagged."""
+    xyz, tet, tags = inputs.cube_mesh(2)
+    tet = tet[:n_elem]
+    used, inv = np.unique(tet.ravel(), return_inverse=True)
+    tet = inv.reshape(-1, 4)
+    xyz = xyz[used]
+    # faces without a partner inside the subset become impedance faces
+    keys = {}
+    for e in range(n_elem):
+        for f in range(4):
+            keys.setdefault(tuple(sorted(np.delete(tet[e], f))), []).append((e, f))
+    tags = np.zeros((n_elem, 4), dtype=np.int8)
+    for owners in keys.values():
+        if len(owners) == 1:
+            tags[owners[0]] = inputs.TAG_IMPEDANCE
+    return xyz, tet, tags
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_every_ragged_chunk_size(lib, q, precision):
+    tol = 1e-12 if precision == 0 else 1e-5
+    for n_elem in list(range(1, 11)) + [11, 19, 21]:
+        xyz, tet, tags = first_elements(n_elem)
+        rng = np.random.default_rng(n_elem)
+        K = tet.shape[0]
+        eps = rng.choice([1.0, 2.0, 4.0], K)
+        op = dg.make_problem(xyz, tet, tags, q, eps, np.ones(K), rng.uniform(0, 0.5, K), omega=3.0,
+                             j=rng.standard_normal((K, (q + 1) * (q + 2) * (q + 3) // 6, 3)))
+        s, lp = lib_problem(lib, op, precision, xyz, tet, tags)
+        U = rng.standard_normal((K, 6, op.Np))
+        out = dev(np.zeros_like(U))
+        lib.cmcg_debug_rhs(lp, dev(U), out, t=0.3, with_source=True)
+        ref = dg.phi(op, 0.3, U, with_source=True)
+        err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(np.abs(ref))
+        assert err < tol, (n_elem, err)
+
+
+def test_single_tetrahedron_cmcg(lib):
+    xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.float64)
+    tet = np.array([[0, 1, 2, 3]])
+    tags = np.full((1, 4), inputs.TAG_IMPEDANCE, dtype=np.int8)
+    j = inputs.gaussian_current(dg.make_problem(xyz, tet, tags, 2, np.ones(1), np.ones(1)).geo.x,
+                                (0.25, 0.25, 0.25), 0.5, 2)
+    op = dg.make_problem(xyz, tet, tags, 2, np.ones(1), np.ones(1), omega=2 * np.pi, j=j)
+    ref = ocmcg.solve(op, tol=1e-10, max_iter=200)
+    s, lp = lib_problem(lib, op, 0, xyz, tet, tags)
+    r = lib.cmcg_solve(lp, lib.cmcg_options_default(fixed_iters=ref.iters))
+    import torch
+    fr = torch.zeros((1, 6, op.Np), dtype=torch.float64, device="cuda")
+    fi = torch.zeros_like(fr)
+    lib.cmcg_result_filtered_device(r, fr, fi)
+    got = fr.cpu().numpy() + 1j * fi.cpu().numpy()
+    ref_f = ocmcg.solve(op, fixed_iters=ref.iters).F
+    assert rel_norm_c(op, got, ref_f) < 1e-11
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_zero_source_gives_zero_field(lib, precision):
+    xyz, tet, tags = inputs.cube_mesh(2)
+    m = lib.cmcg_mesh_create(xyz, tet, tags)
+    s = lib.cmcg_space_create(m, 2, precision)
+    K = tet.shape[0]
+    p = lib.cmcg_problem_create(s, np.ones(K), np.ones(K), None, 2 * np.pi, None)
+    r = lib.cmcg_solve(p, lib.cmcg_options_default(tol=1e-8))
+    st = lib.cmcg_result_stats(r)
+    assert st["iters"] == 0 and st["status"] == lib.CMCG_OK and st["rel_res"] == 0.0
+    import torch
+    fr = torch.ones((K, 6, 10), dtype=torch.float64, device="cuda")
+    fi = torch.ones_like(fr)
+    lib.cmcg_result_filtered_device(r, fr, fi)
+    assert float(fr.abs().max()) == 0.0 and float(fi.abs().max()) == 0.0
+
+
+def test_argument_errors(lib):
+    xyz, tet, tags = inputs.cube_mesh(1)
+    m = lib.cmcg_mesh_create(xyz, tet, tags)
+    for q, prec in ((0, 0), (4, 0), (2, 7)):
+        with pytest.raises(lib.CmcgError) as e:
+            lib.cmcg_space_create(m, q, prec)
+        assert e.value.code == lib.CMCG_ERR_ARG
+    s = lib.cmcg_space_create(m, 1, 0)
+    K = tet.shape[0]
+    for eps, mu, omega in ((np.ones(K), np.ones(K), 0.0), (np.ones(K), np.ones(K), -1.0),
+                           (np.zeros(K), np.ones(K), 1.0), (np.ones(K), -np.ones(K), 1.0)):
+        with pytest.raises(lib.CmcgError) as e:
+            lib.cmcg_problem_create(s, eps, mu, None, omega, None)
+        assert e.value.code == lib.CMCG_ERR_ARG
+    p = lib.cmcg_problem_create(s, np.ones(K), np.ones(K), None, 1.0, None)
+    for kw in (dict(steps=2), dict(scheme=3), dict(flux=5)):
+        with pytest.raises(lib.CmcgError) as e:
+            lib.cmcg_solve(p, lib.cmcg_options_default(**kw))
+        assert e.value.code == lib.CMCG_ERR_ARG, kw
+    with pytest.raises(lib.CmcgError) as e:
+        lib.cmcg_tune_stage(2, 1, 99)
+    assert e.value.code == lib.CMCG_ERR_ARG
+
+
+def test_engine_state_errors(lib):
+    xyz, tet, tags = inputs.cube_mesh(1)
+    m = lib.cmcg_mesh_create(xyz, tet, tags)
+    s = lib.cmcg_space_create(m, 1, 1)
+    K = tet.shape[0]
+    j = inputs.gaussian_current(lib.cmcg_space_nodes(s), (0.5, 0.5, 0.5), 0.3, 2)
+    p = lib.cmcg_problem_create(s, np.ones(K), np.ones(K), None, 2 * np.pi, j)
+    e = lib.cmcg_engine_create(1 << 30, 2)
+    with pytest.raises(lib.CmcgError) as err:
+        lib.cmcg_engine_cancel(e, 0)            # free slot
+    assert err.value.code == lib.CMCG_ERR_STATE
+    with pytest.raises(lib.CmcgError) as err:
+        lib.cmcg_engine_poll(e, 5)              # no such slot
+    assert err.value.code == lib.CMCG_ERR_ARG
+    slot = lib.cmcg_engine_admit(e, p)
+    with pytest.raises(lib.CmcgError) as err:
+        lib.cmcg_engine_collect(e, slot, p)     # still running
+    assert err.value.code == lib.CMCG_ERR_STATE
+    while lib.cmcg_engine_poll(e, slot) == 1:
+        lib.cmcg_engine_step(e)
+    r = lib.cmcg_engine_collect(e, slot, p)
+    assert lib.cmcg_result_stats(r)["status"] in (lib.CMCG_OK, lib.CMCG_NOT_CONVERGED)
+    with pytest.raises(lib.CmcgError) as err:
+        lib.cmcg_engine_create(1 << 20, 0)
+    assert err.value.code == lib.CMCG_ERR_ARG
