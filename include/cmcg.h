@@ -196,6 +196,22 @@ int cmcg_problem_steps(const cmcg_problem* p, const cmcg_options* o, int* M, dou
  * and the status is CMCG_NOT_CONVERGED with rel_res the best value. */
 int cmcg_solve(cmcg_problem* p, const cmcg_options* o, const double* u0_dev,
                hipStream_t stream, cmcg_result** out);
+
+/* Limiting-amplitude ("full wave", FW) iteration, the method Section 6
+ * compares CMCG against: time stepping with the source from u0_dev (NULL =
+ * zero, as in the paper's experiments), one period after another; the filter
+ * of each simulated period (Section 5.4) is the current time-harmonic
+ * approximation, so FW costs one period per iterate where CMCG costs two.
+ * Options: o->fixed_iters > 0 simulates exactly that many periods; otherwise
+ * it stops once the relative change of the filtered field between
+ * consecutive periods, ||F_l - F_(l-1)||_{eps,mu} / ||F_l||_{eps,mu}, is at
+ * most o->tol, or after o->max_iter periods (CMCG_NOT_CONVERGED).  The result
+ * holds the last period's filtered field, U0 = the state at the start of that
+ * period, the history of relative changes (1 for the first period) and stats
+ * with iters = periods = periods simulated.  Uses the problem's work buffers:
+ * not concurrently with another solve of the same problem. */
+int cmcg_fw_solve(cmcg_problem* p, const cmcg_options* o, const double* u0_dev,
+                  hipStream_t stream, cmcg_result** out);
 /* Batched solve: Algorithm 3 for n problems sharing one space (same mesh,
  * order and field precision; each with its own omega, j, g and materials),
  * advanced together -- one kernel launch per Runge-Kutta stage covers every

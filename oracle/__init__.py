@@ -14,6 +14,7 @@ timestep  RK2 / RK4, propagators P_psi, P, P* = S P S, filter accumulation
 filters   trapezoid and Hermite period filters
 cmcg      initialisation, gradient and CG algorithms of Section 2.2
 fs        frequency-domain solve and the discrete-periodic exact solve
+fw        limiting-amplitude (full wave) iteration of Section 6
 
 Parity status: every function is pinned by a test under tests/ against a
 closed form, an invariant, a brute-force computation or a library routine,

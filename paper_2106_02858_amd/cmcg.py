@@ -41,7 +41,7 @@ EXPORTED = [
     "cmcg_mesh_create", "cmcg_mesh_destroy", "cmcg_mesh_info",
     "cmcg_space_create", "cmcg_space_destroy", "cmcg_space_info", "cmcg_space_nodes",
     "cmcg_problem_create", "cmcg_problem_create_device", "cmcg_problem_destroy", "cmcg_problem_steps",
-    "cmcg_solve", "cmcg_solve_batch", "cmcg_result_fields", "cmcg_result_filtered_device", "cmcg_result_initial_device",
+    "cmcg_solve", "cmcg_fw_solve", "cmcg_solve_batch", "cmcg_result_fields", "cmcg_result_filtered_device", "cmcg_result_initial_device",
     "cmcg_result_stats", "cmcg_result_history", "cmcg_result_destroy",
     "cmcg_debug_rhs", "cmcg_debug_period", "cmcg_debug_dot", "cmcg_tune_stage", "cmcg_tune_get_stage",
     "cmcg_problem_footprint", "cmcg_engine_create", "cmcg_engine_destroy", "cmcg_engine_admit",
@@ -91,6 +91,7 @@ _sig = {
     "cmcg_problem_destroy": (None, [P]),
     "cmcg_problem_steps": (C.c_int, [P, C.POINTER(cmcg_options), C.POINTER(C.c_int), D]),
     "cmcg_solve": (C.c_int, [P, C.POINTER(cmcg_options), P, P, C.POINTER(P)]),
+    "cmcg_fw_solve": (C.c_int, [P, C.POINTER(cmcg_options), P, P, C.POINTER(P)]),
     "cmcg_solve_batch": (C.c_int, [C.POINTER(P), C.c_int, C.POINTER(cmcg_options), P, C.POINTER(P)]),
     "cmcg_result_fields": (C.c_int, [P, P, P, P, P]),
     "cmcg_result_filtered_device": (C.c_int, [P, P, P, P]),
@@ -278,6 +279,14 @@ def cmcg_solve(p: Problem, opts: cmcg_options | None = None, u0_dev=None, stream
     o = opts or cmcg_options_default()
     h = P()
     _check(_lib.cmcg_solve(p.h, C.byref(o), _ptr(u0_dev), _stream(stream), C.byref(h)),
+           allow=(CMCG_OK, CMCG_NOT_CONVERGED))
+    return Result(h, keep=(p,))
+
+
+def cmcg_fw_solve(p: Problem, opts: cmcg_options | None = None, u0_dev=None, stream=None) -> Result:
+    o = opts or cmcg_options_default()
+    h = P()
+    _check(_lib.cmcg_fw_solve(p.h, C.byref(o), _ptr(u0_dev), _stream(stream), C.byref(h)),
            allow=(CMCG_OK, CMCG_NOT_CONVERGED))
     return Result(h, keep=(p,))
 

@@ -152,5 +152,6 @@ void hermite_weights(double omega, double dt, std::complex<double> xi[4]);
 void build_geo(cmcg_problem* p, double alpha);
 void prepare(cmcg_problem* p, const StepCfg& c);
 cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st);
+cmcg_result* fw_solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st);
 void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipStream_t st, cmcg_result** out);
 }  // namespace cmcg

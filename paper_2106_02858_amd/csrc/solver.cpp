@@ -620,6 +620,83 @@ void CgRun::complete() {
     }
 }
 
+// Limiting-amplitude ("full wave") iteration of Section 6: periods with the
+// source from u0 (or zero), the filter of each period is the current
+// approximation; stop on the relative change of the filtered field between
+// consecutive periods.
+cmcg_result* fw_solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st) {
+    const StepCfg c = step_config(p, o);
+    prepare(p, c);
+    const SpaceData& s = *p->sp;
+    const int64_t n = s.ndof;
+    const size_t db = n * 8;
+    p->v_u.alloc(db);
+    p->v_w.alloc(db);
+    p->v_a.alloc(db);
+    p->v_d.alloc(db);
+    p->v_r.alloc(db);
+    std::unique_ptr<cmcg_result> res(new cmcg_result());
+    res->sp = p->sp;
+    res->Fre.alloc(db);
+    res->Fim.alloc(db);
+    res->U0.alloc(db);
+    double *U = p->v_u.as<double>(), *W = p->v_w.as<double>(), *Pre = p->v_a.as<double>(),
+           *Pim = p->v_d.as<double>(), *D = p->v_r.as<double>();
+    const double *Fre = p->Fre.as<double>(), *Fim = p->Fim.as<double>();
+    CMCG_HIP(hipStreamSynchronize(st));
+    const auto t0 = std::chrono::steady_clock::now();
+    if (u0)
+        CMCG_HIP(hipMemcpyAsync(U, u0, db, hipMemcpyDeviceToDevice, st));
+    else
+        launch_zero(U, db, st);
+    const bool fixed = o->fixed_iters > 0;
+    const int limit = fixed ? o->fixed_iters : o->max_iter;
+    double rel = 1.0;
+    int l = 0;
+    bool stopped = false;
+    for (; l < limit; ++l) {
+        CMCG_HIP(hipMemcpyAsync(res->U0.p, U, db, hipMemcpyDeviceToDevice, st));  // start of this period
+        apply_period(p, c, o, U, W, nullptr, +1, true, true, st);
+        if (l > 0) {
+            launch_axpby(1.0, Fre, -1.0, Pre, D, n, st);
+            double dd = dot(p, D, D, st);
+            launch_axpby(1.0, Fim, -1.0, Pim, D, n, st);
+            dd += dot(p, D, D, st);
+            const double ff = dot(p, Fre, Fre, st) + dot(p, Fim, Fim, st);
+            if (!std::isfinite(dd) || !std::isfinite(ff)) fail(CMCG_ERR_UNSTABLE, "fw_solve: non-finite field");
+            rel = ff > 0 ? std::sqrt(dd / ff) : 0.0;
+        }
+        res->history.push_back(l == 0 ? 1.0 : rel);
+        CMCG_HIP(hipMemcpyAsync(Pre, Fre, db, hipMemcpyDeviceToDevice, st));
+        CMCG_HIP(hipMemcpyAsync(Pim, Fim, db, hipMemcpyDeviceToDevice, st));
+        std::swap(U, W);
+        if (o->progress && o->progress(o->progress_ctx, l + 1, rel) != 0) {
+            stopped = true;
+            ++l;
+            break;
+        }
+        if (!fixed && l > 0 && rel <= o->tol) {
+            ++l;
+            break;
+        }
+    }
+    CMCG_HIP(hipMemcpyAsync(res->Fre.p, Fre, db, hipMemcpyDeviceToDevice, st));
+    CMCG_HIP(hipMemcpyAsync(res->Fim.p, Fim, db, hipMemcpyDeviceToDevice, st));
+    CMCG_HIP(hipStreamSynchronize(st));
+    cmcg_stats& S = res->st;
+    S.iters = l;
+    S.periods = l;
+    S.steps = c.M;
+    S.dt = c.dt;
+    S.rel_res = rel;
+    S.J0 = 0.0;
+    S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    S.seconds_to_1e6 = -1.0;
+    S.dof_updates = (double)n * c.M * l;
+    S.status = (stopped || (!fixed && (l < 2 || rel > o->tol))) ? CMCG_NOT_CONVERGED : CMCG_OK;
+    return res.release();
+}
+
 cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st) {
     CgRun run;
     run.start(p, o, u0, st);
@@ -817,6 +894,22 @@ int cmcg_solve(cmcg_problem* p, const cmcg_options* o, const double* u0_dev, hip
     if (!o) o = &def;
     if (o->max_iter < 0 || o->fixed_iters < 0) fail(CMCG_ERR_ARG, "solve: negative iteration count");
     cmcg_result* r = solve(p, o, u0_dev, stream);
+    *out = r;
+    return r->st.status;
+    CMCG_GUARD_END
+}
+
+int cmcg_fw_solve(cmcg_problem* p, const cmcg_options* o, const double* u0_dev, hipStream_t stream,
+                  cmcg_result** out) {
+    CMCG_GUARD_BEGIN
+    if (!out) fail(CMCG_ERR_ARG, "fw_solve: NULL output");
+    *out = nullptr;
+    if (!p) fail(CMCG_ERR_ARG, "fw_solve: NULL problem");
+    cmcg_options def;
+    cmcg_options_default(&def);
+    if (!o) o = &def;
+    if (o->max_iter < 0 || o->fixed_iters < 0) fail(CMCG_ERR_ARG, "fw_solve: negative period count");
+    cmcg_result* r = fw_solve(p, o, u0_dev, stream);
     *out = r;
     return r->st.status;
     CMCG_GUARD_END

@@ -1,0 +1,46 @@
+"""Pins of the FW (limiting amplitude) oracle: the state after l periods is
+the periodic orbit's initial state U* plus the homogeneous propagator applied
+l times to the initial difference, and the filtered field converges to the
+exactly periodic orbit's (impedance walls dissipate the transient)."""
+import numpy as np
+import pytest
+
+from oracle import dg, fs, fw, timestep
+from tests._problems import hetero_problem
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_fw_state_is_orbit_plus_decaying_transient(q):
+    p = hetero_problem(n=1, q=q, seed=3, tags=2, sigma=False)
+    M = timestep.n_steps(p)
+    scheme = timestep.default_scheme(q)
+    Uh, Fdp = fs.discrete_periodic(p, M, scheme)
+    Ustar = Uh.real
+    for l in (1, 3):
+        r = fw.solve(p, l, M=M, scheme=scheme)
+        trans = -Ustar
+        for _ in range(l):
+            trans = timestep.forward(p, trans, M, scheme, with_source=False)
+        scale = np.max(np.abs(Ustar))
+        assert np.max(np.abs(r.U_end - (Ustar + trans))) < 1e-11 * scale
+        # filter linearity: F(U0) = F(U*) + F_0(U0 - U*)
+        _, Ftr = timestep.forward(p, r.U0 - Ustar, M, scheme, with_source=False, filt=True)
+        assert np.max(np.abs(r.F - (Fdp + Ftr))) < 1e-10 * np.max(np.abs(Fdp))
+
+
+def test_fw_converges_to_periodic_orbit():
+    p = hetero_problem(n=1, q=1, seed=5, tags=2, sigma=False)
+    M = timestep.n_steps(p)
+    _, Fdp = fs.discrete_periodic(p, M, 2)
+    errs = []
+    for L in (2, 8, 32):
+        r = fw.solve(p, L, M=M, scheme=2)
+        errs.append(fw.rel_change(p, r.F, Fdp))
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-3 * errs[0]
+
+
+def test_fw_stops_on_tolerance():
+    p = hetero_problem(n=1, q=1, seed=5, tags=2, sigma=False)
+    r = fw.solve(p, 200, tol=1e-6)
+    assert r.periods < 200 and r.history[-1] <= 1e-6 and r.history[0] == 1.0
+    assert all(h > 1e-6 for h in r.history[1:-1])
