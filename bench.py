@@ -45,12 +45,14 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=4, help="RK steps of the CPU oracle sample")
     ap.add_argument("--kernel-periods", type=int, default=3)
-    ap.add_argument("--workload", choices=["large_single", "batched", "serving", "scatterer"],
+    ap.add_argument("--workload", choices=["large_single", "batched", "serving", "scatterer", "fw"],
                     default="large_single",
                     help="large_single (default bench line), the 64-member batched configuration, or the "
                          "Poisson request stream through the serving engine")
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--cg-iters", type=int, default=6, help="scatterer: CG iterations of the timed solve")
+    ap.add_argument("--fw-walls", choices=["impedance", "pec"], default="impedance",
+                    help="fw: walls of the comparison problem (pec: closed cavity)")
     ap.add_argument("--requests", type=int, default=60, help="serving: requests taken from the stream")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: Poisson arrival rate (req/s)")
     ap.add_argument("--slots", type=int, default=8, help="serving: engine slots")
@@ -266,6 +268,77 @@ def scatterer(a):
     print(json.dumps(out), flush=True)
 
 
+def fw_compare(a):
+    """CMCG against the limiting-amplitude (FW) iteration on the 48000-tet P3
+    problem with FP32 fields: CMCG to --tol, then FW for 1/8, 1/4, 1/2 and 1
+    times the periods CMCG used; each FW result is compared with the CMCG solution
+    (relative eps-mu norm of the filtered fields), cost in periods and time."""
+    import torch
+
+    from paper_2106_02858_amd import cmcg, inputs
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    w = inputs.large_single(n=a.n, q=a.q,
+                            boundary_tag=inputs.TAG_PEC if a.fw_walls == "pec" else inputs.TAG_IMPEDANCE)
+    mesh = cmcg.cmcg_mesh_create(w.xyz, w.tet, w.tags)
+    s = cmcg.cmcg_space_create(mesh, w.q, cmcg.CMCG_FP32)
+    nodes = cmcg.cmcg_space_nodes(s)
+    jd = torch.tensor(inputs.gaussian_current(nodes, w.centre, w.width, w.pol), dtype=torch.float64, device=dev)
+    p = cmcg.cmcg_problem_create_device(s, w.eps, w.mu, w.sigma, w.omega, jd)
+    info = cmcg.cmcg_space_info(s)
+    K, Np = info["K"], info["Np"]
+
+    def fields(r):
+        f = [torch.empty((K, 6, Np), dtype=torch.float64, device=dev) for _ in range(2)]
+        cmcg.cmcg_result_filtered_device(r, *f)
+        return f
+
+    t_ref = [time.perf_counter()]
+
+    def progress(it, rel):
+        if it % 20 == 0:
+            log(f"  cmcg iter {it} rel {rel:.3e} t {time.perf_counter() - t_ref[0]:.1f}s")
+        return False
+
+    oc = cmcg.cmcg_options_default(tol=a.tol, max_iter=2000)
+    oc.set_progress(progress)
+    rc = cmcg.cmcg_solve(p, oc)
+    stc = cmcg.cmcg_result_stats(rc)
+    Fc = fields(rc)
+    den = sum(cmcg.cmcg_debug_dot(p, x, x) for x in Fc)
+    log(f"cmcg: {stc['iters']} iterations, {stc['periods']} periods, {stc['seconds']:.2f} s")
+    rows = []
+    for frac in ((0.125, 0.25, 0.5, 1.0) if a.fw_walls == "impedance" else (0.5, 1.0, 2.0, 4.0)):
+        L = max(2, int(round(frac * stc["periods"])))
+        t0 = time.perf_counter()
+        of = cmcg.cmcg_options_default(fixed_iters=L)
+        t_ref[0] = time.perf_counter()
+
+        def fw_progress(it, rel):
+            if it % 200 == 0:
+                log(f"  fw period {it} change {rel:.3e} t {time.perf_counter() - t_ref[0]:.1f}s")
+            return False
+
+        of.set_progress(fw_progress)
+        rf = cmcg.cmcg_fw_solve(p, of)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        d = [x - y for x, y in zip(fields(rf), Fc)]
+        err = math.sqrt(sum(cmcg.cmcg_debug_dot(p, x, x) for x in d) / den)
+        last = float(cmcg.cmcg_result_history(rf)[-1])
+        rows.append({"periods": L, "seconds": el, "rel_diff_to_cmcg": err, "last_rel_change": last})
+        log(f"fw {L} periods: {el:.2f} s, rel. difference to CMCG {err:.3e}, last change {last:.3e}")
+    out = {"metric": "DG dof-updates/s; CMCG time-to-1e-6 residual vs FP64 plain; p50/p99 latency",
+           "value": stc["dof_updates"] / stc["seconds"], "unit": "dof-updates/s", "n_gpus": 1, "steps": 1,
+           "warmup": 0, "ms_per_step": stc["seconds"] * 1e3, "higher_is_better": True, "scaling": "strong",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"CMCG vs limiting amplitude (FW) on the 48000-tet P3 problem with "
+                                  f"{a.fw_walls} walls, FP32 fields, CMCG to {a.tol:g}"},
+           "cmcg": {"iters": stc["iters"], "periods": stc["periods"], "seconds": stc["seconds"]},
+           "fw": rows}
+    print(json.dumps(out), flush=True)
+
+
 def served(a):
     """The request stream (n in {8,12,16,24}, q in {1,2,3}, omega in [2pi,8pi],
     eps per cube in {1,2,4}, Poisson arrivals) through the serving engine."""
@@ -303,6 +376,9 @@ def main():
         return
     if a.workload == "scatterer":
         scatterer(a)
+        return
+    if a.workload == "fw":
+        fw_compare(a)
         return
     import numpy as np
     import torch

@@ -199,17 +199,18 @@ int cmcg_solve(cmcg_problem* p, const cmcg_options* o, const double* u0_dev,
 
 /* Limiting-amplitude ("full wave", FW) iteration, the method Section 6
  * compares CMCG against: time stepping with the source from u0_dev (NULL =
- * zero, as in the paper's experiments), one period after another; the filter
- * of each simulated period (Section 5.4) is the current time-harmonic
- * approximation, so FW costs one period per iterate where CMCG costs two.
- * Options: o->fixed_iters > 0 simulates exactly that many periods; otherwise
- * it stops once the relative change of the filtered field between
- * consecutive periods, ||F_l - F_(l-1)||_{eps,mu} / ||F_l||_{eps,mu}, is at
- * most o->tol, or after o->max_iter periods (CMCG_NOT_CONVERGED).  The result
- * holds the last period's filtered field, U0 = the state at the start of that
- * period, the history of relative changes (1 for the first period) and stats
- * with iters = periods = periods simulated.  Uses the problem's work buffers:
- * not concurrently with another solve of the same problem. */
+ * zero, as in the paper's experiments), one period after another, the state
+ * at a period start being the iterate U_0^(l); its time-harmonic
+ * approximation F_psi U_0^(l) (Section 5.4) comes from one final period with
+ * the filter.  Options: o->fixed_iters = L > 0 simulates exactly L periods
+ * (L - 1 plain ones, then the filtered one); otherwise the plain periods stop
+ * once the state changes by at most o->tol between period starts,
+ * ||U_0^(l) - U_0^(l-1)||_{eps,mu} / ||U_0^(l)||_{eps,mu}, or after
+ * o->max_iter - 1 of them (CMCG_NOT_CONVERGED).  The result holds the
+ * filtered field, U0 = the final iterate, the history of relative state
+ * changes (one per plain period) and stats with iters = plain periods and
+ * periods = plain periods + 1.  Uses the problem's work buffers: not
+ * concurrently with another solve of the same problem. */
 int cmcg_fw_solve(cmcg_problem* p, const cmcg_options* o, const double* u0_dev,
                   hipStream_t stream, cmcg_result** out);
 /* Batched solve: Algorithm 3 for n problems sharing one space (same mesh,

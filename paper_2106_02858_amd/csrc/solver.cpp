@@ -620,10 +620,10 @@ void CgRun::complete() {
     }
 }
 
-// Limiting-amplitude ("full wave") iteration of Section 6: periods with the
-// source from u0 (or zero), the filter of each period is the current
-// approximation; stop on the relative change of the filtered field between
-// consecutive periods.
+// Limiting-amplitude ("full wave") iteration of Section 6: plain periods with
+// the source from u0 (or zero), stopping on the relative change of the state
+// at the period starts; the approximation F_psi U_0^(l) comes from one final
+// period with the filter, so the filter's FP64 accumulation is paid once.
 cmcg_result* fw_solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st) {
     const StepCfg c = step_config(p, o);
     prepare(p, c);
@@ -632,17 +632,13 @@ cmcg_result* fw_solve(cmcg_problem* p, const cmcg_options* o, const double* u0, 
     const size_t db = n * 8;
     p->v_u.alloc(db);
     p->v_w.alloc(db);
-    p->v_a.alloc(db);
-    p->v_d.alloc(db);
     p->v_r.alloc(db);
     std::unique_ptr<cmcg_result> res(new cmcg_result());
     res->sp = p->sp;
     res->Fre.alloc(db);
     res->Fim.alloc(db);
     res->U0.alloc(db);
-    double *U = p->v_u.as<double>(), *W = p->v_w.as<double>(), *Pre = p->v_a.as<double>(),
-           *Pim = p->v_d.as<double>(), *D = p->v_r.as<double>();
-    const double *Fre = p->Fre.as<double>(), *Fim = p->Fim.as<double>();
+    double *U = p->v_u.as<double>(), *W = p->v_w.as<double>(), *D = p->v_r.as<double>();
     CMCG_HIP(hipStreamSynchronize(st));
     const auto t0 = std::chrono::steady_clock::now();
     if (u0)
@@ -652,48 +648,43 @@ cmcg_result* fw_solve(cmcg_problem* p, const cmcg_options* o, const double* u0, 
     const bool fixed = o->fixed_iters > 0;
     const int limit = fixed ? o->fixed_iters : o->max_iter;
     double rel = 1.0;
-    int l = 0;
-    bool stopped = false;
-    for (; l < limit; ++l) {
-        CMCG_HIP(hipMemcpyAsync(res->U0.p, U, db, hipMemcpyDeviceToDevice, st));  // start of this period
-        apply_period(p, c, o, U, W, nullptr, +1, true, true, st);
-        if (l > 0) {
-            launch_axpby(1.0, Fre, -1.0, Pre, D, n, st);
-            double dd = dot(p, D, D, st);
-            launch_axpby(1.0, Fim, -1.0, Pim, D, n, st);
-            dd += dot(p, D, D, st);
-            const double ff = dot(p, Fre, Fre, st) + dot(p, Fim, Fim, st);
-            if (!std::isfinite(dd) || !std::isfinite(ff)) fail(CMCG_ERR_UNSTABLE, "fw_solve: non-finite field");
-            rel = ff > 0 ? std::sqrt(dd / ff) : 0.0;
-        }
-        res->history.push_back(l == 0 ? 1.0 : rel);
-        CMCG_HIP(hipMemcpyAsync(Pre, Fre, db, hipMemcpyDeviceToDevice, st));
-        CMCG_HIP(hipMemcpyAsync(Pim, Fim, db, hipMemcpyDeviceToDevice, st));
+    int plain = 0;
+    bool stopped = false, converged = false;
+    while (plain < limit - 1) {
+        apply_period(p, c, o, U, W, nullptr, +1, true, false, st);
+        launch_axpby(1.0, W, -1.0, U, D, n, st);
+        const double dd = dot(p, D, D, st), ww = dot(p, W, W, st);
+        if (!std::isfinite(dd) || !std::isfinite(ww)) fail(CMCG_ERR_UNSTABLE, "fw_solve: non-finite field");
+        rel = ww > 0 ? std::sqrt(dd / ww) : 0.0;
+        res->history.push_back(rel);
         std::swap(U, W);
-        if (o->progress && o->progress(o->progress_ctx, l + 1, rel) != 0) {
+        ++plain;
+        if (o->progress && o->progress(o->progress_ctx, plain, rel) != 0) {
             stopped = true;
-            ++l;
             break;
         }
-        if (!fixed && l > 0 && rel <= o->tol) {
-            ++l;
+        if (!fixed && rel <= o->tol) {
+            converged = true;
             break;
         }
     }
-    CMCG_HIP(hipMemcpyAsync(res->Fre.p, Fre, db, hipMemcpyDeviceToDevice, st));
-    CMCG_HIP(hipMemcpyAsync(res->Fim.p, Fim, db, hipMemcpyDeviceToDevice, st));
+    // the iterate U_0^(plain) and its filtered field
+    CMCG_HIP(hipMemcpyAsync(res->U0.p, U, db, hipMemcpyDeviceToDevice, st));
+    apply_period(p, c, o, U, nullptr, nullptr, +1, true, true, st);
+    CMCG_HIP(hipMemcpyAsync(res->Fre.p, p->Fre.p, db, hipMemcpyDeviceToDevice, st));
+    CMCG_HIP(hipMemcpyAsync(res->Fim.p, p->Fim.p, db, hipMemcpyDeviceToDevice, st));
     CMCG_HIP(hipStreamSynchronize(st));
     cmcg_stats& S = res->st;
-    S.iters = l;
-    S.periods = l;
+    S.iters = plain;
+    S.periods = plain + 1;
     S.steps = c.M;
     S.dt = c.dt;
     S.rel_res = rel;
     S.J0 = 0.0;
     S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     S.seconds_to_1e6 = -1.0;
-    S.dof_updates = (double)n * c.M * l;
-    S.status = (stopped || (!fixed && (l < 2 || rel > o->tol))) ? CMCG_NOT_CONVERGED : CMCG_OK;
+    S.dof_updates = (double)n * c.M * (plain + 1);
+    S.status = (stopped || (!fixed && !converged)) ? CMCG_NOT_CONVERGED : CMCG_OK;
     return res.release();
 }
 

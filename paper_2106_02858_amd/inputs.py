@@ -135,18 +135,19 @@ def plain_fp64(n: int = 6, q: int = 1, boundary_tag: int = TAG_IMPEDANCE) -> Wor
                     np.array([0.5, 0.5, 0.5]), 0.1, 2, boundary_tag, xyz, tet, tags)
 
 
-def large_single(n: int = 20, q: int = 3, seed: int = 2) -> Workload:
+def large_single(n: int = 20, q: int = 3, seed: int = 2, boundary_tag: int = TAG_IMPEDANCE) -> Workload:
     """eps per cube from {1,2,4} (seeded), omega = 4 pi, Gaussian width 0.05 at a
     seeded point of [0.3,0.7]^3, e_z polarisation.  n=20, q=3 is the
-    48000-tet P3 FP32-vs-FP64 configuration."""
+    48000-tet P3 FP32-vs-FP64 configuration; boundary_tag = TAG_PEC makes the
+    same medium a closed cavity (no dissipation through the walls)."""
     rng = np.random.default_rng(seed)
     eps_cube = np.array([1.0, 2.0, 4.0])[rng.integers(0, 3, n ** 3)]
     centre = rng.uniform(0.3, 0.7, 3)
-    xyz, tet, tags = _mesh(n, TAG_IMPEDANCE)
+    xyz, tet, tags = _mesh(n, boundary_tag)
     K = tet.shape[0]
     eps = np.repeat(eps_cube, 6)
     return Workload("large_single", n, q, 4 * math.pi, eps, np.ones(K), np.zeros(K),
-                    centre, 0.05, 2, TAG_IMPEDANCE, xyz, tet, tags)
+                    centre, 0.05, 2, boundary_tag, xyz, tet, tags)
 
 
 def batched_members(n: int = 12, q: int = 2, B: int = 64, seed: int = 3):

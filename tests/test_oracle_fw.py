@@ -17,10 +17,12 @@ def test_fw_state_is_orbit_plus_decaying_transient(q):
     Uh, Fdp = fs.discrete_periodic(p, M, scheme)
     Ustar = Uh.real
     for l in (1, 3):
-        r = fw.solve(p, l, M=M, scheme=scheme)
+        r = fw.solve(p, l + 1, M=M, scheme=scheme)   # l plain periods + the filtered one
         trans = -Ustar
         for _ in range(l):
             trans = timestep.forward(p, trans, M, scheme, with_source=False)
+        assert np.max(np.abs(r.U0 - (Ustar + trans))) < 1e-11 * np.max(np.abs(Ustar))
+        trans = timestep.forward(p, trans, M, scheme, with_source=False)
         scale = np.max(np.abs(Ustar))
         assert np.max(np.abs(r.U_end - (Ustar + trans))) < 1e-11 * scale
         # filter linearity: F(U0) = F(U*) + F_0(U0 - U*)
@@ -42,5 +44,6 @@ def test_fw_converges_to_periodic_orbit():
 def test_fw_stops_on_tolerance():
     p = hetero_problem(n=1, q=1, seed=5, tags=2, sigma=False)
     r = fw.solve(p, 200, tol=1e-6)
-    assert r.periods < 200 and r.history[-1] <= 1e-6 and r.history[0] == 1.0
-    assert all(h > 1e-6 for h in r.history[1:-1])
+    assert r.periods < 200 and r.history[-1] <= 1e-6 and r.history[0] == 1.0  # first: from zero
+    assert all(h > 1e-6 for h in r.history[:-1])
+    assert r.periods == len(r.history) + 1
