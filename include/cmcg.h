@@ -180,6 +180,20 @@ int cmcg_problem_create_device(const cmcg_space* s, const double* eps, const dou
                                const double* sigma, double omega, const double* j_re_dev,
                                const double* j_im_dev, hipStream_t stream,
                                cmcg_problem** out);
+/* Several frequencies in one solve (the paper's concluding remarks): a
+ * current made of nh (1..8) harmonics of a base angular frequency omega0,
+ * J(t) = sum_h Re(j_h e^{i k[h] omega0 t}) with distinct integers k[h] >= 1,
+ * is periodic with T = 2 pi / omega0; cmcg_solve / cmcg_fw_solve then solve
+ * over that period and filter every harmonic at its own frequency k[h]
+ * omega0 (Section 5.4 weights), so one solve yields nh time-harmonic fields
+ * (cmcg_result_filtered_harmonic_device).  The time step follows the CFL rule
+ * for the period T; its accuracy at the highest harmonic is the caller's
+ * choice (o->steps forces M).  j_re / j_im: [nh][K][Np][3] host arrays
+ * (j_im may be NULL); no boundary data.  CMCG_ERR_ARG for nh out of range or
+ * repeated / non-positive k.  Not accepted by cmcg_solve_batch. */
+int cmcg_problem_create_harmonics(const cmcg_space* s, const double* eps, const double* mu,
+                                  const double* sigma, double omega0, int nh, const int* k,
+                                  const double* j_re, const double* j_im, cmcg_problem** out);
 void cmcg_problem_destroy(cmcg_problem* p);
 /* Time steps per period M and dt = T / M that `o` selects for this problem
  * (CFL rule of Section 5.3). */
@@ -229,9 +243,16 @@ int cmcg_solve_batch(cmcg_problem* const* problems, int n, const cmcg_options* o
  * [K][Np][3] each, host pointers; any output may be NULL. */
 int cmcg_result_fields(const cmcg_result* r, double* e_re, double* e_im, double* h_re,
                        double* h_im);
-/* Filtered field as device dof vectors [K][6][Np] FP64 (re, im). */
+/* Filtered field as device dof vectors [K][6][Np] FP64 (re, im); the first
+ * harmonic of a several-frequency result. */
 int cmcg_result_filtered_device(const cmcg_result* r, double* f_re_dev, double* f_im_dev,
                                 hipStream_t stream);
+/* Number of filtered harmonics in a result (1 for a single frequency), and
+ * the filtered field of harmonic h (0 <= h < nh) as device dof vectors;
+ * CMCG_ERR_ARG for h out of range. */
+int cmcg_result_harmonics(const cmcg_result* r, int* nh);
+int cmcg_result_filtered_harmonic_device(const cmcg_result* r, int h, double* f_re_dev,
+                                         double* f_im_dev, hipStream_t stream);
 /* The periodic initial condition U0 reached by CG, device dof vector. */
 int cmcg_result_initial_device(const cmcg_result* r, double* u0_dev, hipStream_t stream);
 int cmcg_result_stats(const cmcg_result* r, cmcg_stats* st);

@@ -41,6 +41,7 @@ EXPORTED = [
     "cmcg_mesh_create", "cmcg_mesh_destroy", "cmcg_mesh_info",
     "cmcg_space_create", "cmcg_space_destroy", "cmcg_space_info", "cmcg_space_nodes",
     "cmcg_problem_create", "cmcg_problem_create_device", "cmcg_problem_destroy", "cmcg_problem_steps",
+    "cmcg_problem_create_harmonics", "cmcg_result_harmonics", "cmcg_result_filtered_harmonic_device",
     "cmcg_solve", "cmcg_fw_solve", "cmcg_solve_batch", "cmcg_result_fields", "cmcg_result_filtered_device", "cmcg_result_initial_device",
     "cmcg_result_stats", "cmcg_result_history", "cmcg_result_destroy",
     "cmcg_debug_rhs", "cmcg_debug_period", "cmcg_debug_dot", "cmcg_tune_stage", "cmcg_tune_get_stage",
@@ -92,6 +93,9 @@ _sig = {
     "cmcg_problem_steps": (C.c_int, [P, C.POINTER(cmcg_options), C.POINTER(C.c_int), D]),
     "cmcg_solve": (C.c_int, [P, C.POINTER(cmcg_options), P, P, C.POINTER(P)]),
     "cmcg_fw_solve": (C.c_int, [P, C.POINTER(cmcg_options), P, P, C.POINTER(P)]),
+    "cmcg_problem_create_harmonics": (C.c_int, [P, P, P, P, C.c_double, C.c_int, P, P, P, C.POINTER(P)]),
+    "cmcg_result_harmonics": (C.c_int, [P, C.POINTER(C.c_int)]),
+    "cmcg_result_filtered_harmonic_device": (C.c_int, [P, C.c_int, P, P, P]),
     "cmcg_solve_batch": (C.c_int, [C.POINTER(P), C.c_int, C.POINTER(cmcg_options), P, C.POINTER(P)]),
     "cmcg_result_fields": (C.c_int, [P, P, P, P, P]),
     "cmcg_result_filtered_device": (C.c_int, [P, P, P, P]),
@@ -281,6 +285,29 @@ def cmcg_solve(p: Problem, opts: cmcg_options | None = None, u0_dev=None, stream
     _check(_lib.cmcg_solve(p.h, C.byref(o), _ptr(u0_dev), _stream(stream), C.byref(h)),
            allow=(CMCG_OK, CMCG_NOT_CONVERGED))
     return Result(h, keep=(p,))
+
+
+def cmcg_problem_create_harmonics(s: Space, eps, mu, sigma, omega0: float, ks, js) -> Problem:
+    """js: complex [nh, K, Np, 3] nodal currents of the harmonics k_h omega0."""
+    eps, mu, sigma = _f64(eps), _f64(mu), _f64(sigma)
+    js = np.asarray(js)
+    jr = _f64(np.real(js))
+    ji = _f64(np.imag(js)) if np.iscomplexobj(js) else None
+    karr = np.ascontiguousarray(np.asarray(ks, dtype=np.int32))
+    h = P()
+    _check(_lib.cmcg_problem_create_harmonics(s.h, _ptr(eps), _ptr(mu), _ptr(sigma), float(omega0), len(karr),
+                                              _ptr(karr), _ptr(jr), _ptr(ji), C.byref(h)))
+    return Problem(h, keep=(s,))
+
+
+def cmcg_result_harmonics(r: Result) -> int:
+    n = C.c_int()
+    _check(_lib.cmcg_result_harmonics(r.h, C.byref(n)))
+    return n.value
+
+
+def cmcg_result_filtered_harmonic_device(r: Result, h: int, f_re_dev, f_im_dev, stream=None):
+    _check(_lib.cmcg_result_filtered_harmonic_device(r.h, int(h), _ptr(f_re_dev), _ptr(f_im_dev), _stream(stream)))
 
 
 def cmcg_fw_solve(p: Problem, opts: cmcg_options | None = None, u0_dev=None, stream=None) -> Result:

@@ -135,6 +135,7 @@ StageArgs batch_args(Batch& bt) {
     a.Fre = bt.Fre.as<double>();
     a.Fim = bt.Fim.as<double>();
     a.Ulo = bt.Ulo.p;
+    a.nharm = 1;
     a.nmembers = bt.B;
     a.active = bt.active.as<int>();
     a.msteps = bt.msteps.as<int>();
@@ -299,6 +300,7 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
     for (int b = 0; b < B; ++b) {
         if (!probs[b]) fail(CMCG_ERR_ARG, "solve_batch: NULL problem");
         if (probs[b]->sp != bt.sp) fail(CMCG_ERR_ARG, "solve_batch: all problems must share one space");
+        if (probs[b]->nharm != 1) fail(CMCG_ERR_ARG, "solve_batch: several-frequency problems are solved singly");
         bt.P.push_back(probs[b]);
         bt.cfg.push_back(step_config(probs[b], o));
         if (bt.cfg[b].scheme != bt.cfg[0].scheme || bt.cfg[b].alpha != bt.cfg[0].alpha)

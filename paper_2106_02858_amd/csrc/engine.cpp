@@ -50,13 +50,14 @@ namespace cmcg {
 size_t footprint(const cmcg_problem* p) {
     const SpaceData& s = *p->sp;
     const size_t n = s.ndof, es = s.esize(), K = s.K;
+    const size_t H = p->nharm;
     size_t b = K * kGeo * es + 2 * K * 8;  // geometry, mass weights
-    if (p->src_rows) b += 2 * n * es;      // source
+    if (p->src_rows) b += 2 * n * es * H;  // source (per harmonic)
     b += 5 * n * es;                       // U, Y1, Y2, Acc, RHS buffer
     if (s.precision == CMCG_FP32) b += 2 * n;  // bfloat16 low parts of U
-    b += 2 * n * 8;                        // filter accumulators
+    b += 2 * n * 8 * H;                    // filter accumulators (per harmonic)
     b += 7 * n * 8;                        // CG vectors (with the best iterate)
-    b += 3 * n * 8;                        // result
+    b += (2 * H + 1) * n * 8;              // result: filtered fields, U0
     return b + (size_t)dot_partials() * 8 + 4096;
 }
 

@@ -317,7 +317,9 @@ template <typename T, int Q, int RF> struct TraceGather {
 // PIPE: request the next face's neighbour traces (and, before the last face,
 // the update operands) one face ahead.  Without it every face gathers and
 // consumes in turn, which needs fewer registers.
-template <typename T, int Q, bool PIPE>
+// MH: several-frequency problems (further source harmonics and filters);
+// the single-frequency instantiation carries none of that code.
+template <typename T, int Q, bool PIPE, bool MH>
 __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP, NF4 = 4 * NFP;
     constexpr int RS = NP + 1;            // padded LDS row stride (bank spread)
@@ -504,6 +506,14 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
         const T scos = (T)a.scos, ssin = (T)a.ssin;
 #pragma unroll
         for (int i = 0; i < NP; ++i) kv[i] += scos * sr[i] - ssin * si[i];
+#pragma unroll 1
+        for (int h = 1; MH && h < a.nharm; ++h) {  // further harmonics of a several-frequency source
+            Row<T, NP>::load((const T*)a.Sre + h * a.hstride + grow, sr);
+            Row<T, NP>::load((const T*)a.Sim + h * a.hstride + grow, si);
+            const T hc = (T)a.hcos[h], hs = (T)a.hsin[h];
+#pragma unroll
+            for (int i = 0; i < NP; ++i) kv[i] += hc * sr[i] - hs * si[i];
+        }
     }
     const T cy = (T)a.cy, ca = (T)a.ca, cu = (T)a.cu;
     T o1[NP], o2[NP];
@@ -571,6 +581,17 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
             const double ud = (double)y[i], kd = (double)kv[i];
             fr[i] += a.fa_re * ud + a.fb_re * kd;
             fi[i] += a.fa_im * ud + a.fb_im * kd;
+        }
+#pragma unroll 1
+        for (int h = 1; MH && h < a.nharm; ++h) {
+            double* hr = a.Fre + h * a.hstride + grow;
+            double* hi = a.Fim + h * a.hstride + grow;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                const double ud = (double)y[i], kd = (double)kv[i];
+                hr[i] += a.hfa_re[h] * ud + a.hfb_re[h] * kd;
+                hi[i] += a.hfa_im[h] * ud + a.hfb_im[h] * kd;
+            }
         }
     }
 }
@@ -650,7 +671,7 @@ template <int Q> struct MfmaUpdateIn {
 // Requesting the update operands earlier (with the staging loads, or before
 // the last face) was measured slower: the registers cost occupancy (P2) or
 // spill (P3).
-template <int Q, bool PIPE>
+template <int Q, bool PIPE, bool MH>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_stage_mfma(StageArgs args,
                                                                                              int64_t per) {
     using T = float;
@@ -867,6 +888,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                 const int row = (v + u) / NP;
                 if (row - 6 * (row / 6) < a.src_rows) kv[u] += scos * srv[u] - ssin * siv[u];
             }
+#pragma unroll 1
+            for (int h = 1; MH && h < a.nharm; ++h) {  // further harmonics of a several-frequency source
+                const float4 hr = *f4(a.Sre, h * a.hstride + gi), hi = *f4(a.Sim, h * a.hstride + gi);
+                const T hrv[4] = {hr.x, hr.y, hr.z, hr.w}, hiv[4] = {hi.x, hi.y, hi.z, hi.w};
+                const T hc = (T)a.hcos[h], hs = (T)a.hsin[h];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int row = (v + u) / NP;
+                    if (row - 6 * (row / 6) < a.src_rows) kv[u] += hc * hrv[u] - hs * hiv[u];
+                }
+            }
         }
         const T x0[4] = {upd.r0[t].x, upd.r0[t].y, upd.r0[t].z, upd.r0[t].w};  // U, or Y in stage-1 modes
         const T x1[4] = {upd.r1[t].x, upd.r1[t].y, upd.r1[t].z, upd.r1[t].w};  // Acc
@@ -935,6 +967,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                 a.Fre[gi + u] += a.fa_re * ud + a.fb_re * kd;
                 a.Fim[gi + u] += a.fa_im * ud + a.fb_im * kd;
             }
+#pragma unroll 1
+            for (int h = 1; MH && h < a.nharm; ++h)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double ud = (double)x0[u], kd = (double)kv[u];
+                    a.Fre[h * a.hstride + gi + u] += a.hfa_re[h] * ud + a.hfb_re[h] * kd;
+                    a.Fim[h * a.hstride + gi + u] += a.hfa_im[h] * ud + a.hfb_im[h] * kd;
+                }
         }
     }
 }
@@ -1146,26 +1186,34 @@ inline int grid_for(int64_t n, int threads = 256) {
     return (int)g;
 }
 
-template <typename T, int Q>
-void stage_launch(const StageArgs& a, hipStream_t s) {
+template <typename T, int Q, bool MH>
+void stage_launch_mh(const StageArgs& a, hipStream_t s) {
     const int64_t blocks = (a.K + EPW - 1) / EPW;
     const int64_t per = (blocks + 7) / 8;
     const int v = stage_variant(Q, sizeof(T) == 8 ? CMCG_FP64 : CMCG_FP32);
     const dim3 grid((unsigned)(8 * per), (unsigned)(a.nmembers > 1 ? a.nmembers : 1));
     if constexpr (sizeof(T) == 4 && Q >= 2) {
         if (v == 2) {
-            hipLaunchKernelGGL((k_stage_mfma<Q, false>), grid, dim3(64), 0, s, a, per);
+            hipLaunchKernelGGL((k_stage_mfma<Q, false, MH>), grid, dim3(64), 0, s, a, per);
             return;
         }
         if (v == 3) {
-            hipLaunchKernelGGL((k_stage_mfma<Q, true>), grid, dim3(64), 0, s, a, per);
+            hipLaunchKernelGGL((k_stage_mfma<Q, true, MH>), grid, dim3(64), 0, s, a, per);
             return;
         }
     }
     if (v == 1)
-        hipLaunchKernelGGL((k_stage<T, Q, true>), grid, dim3(64), 0, s, a, per);
+        hipLaunchKernelGGL((k_stage<T, Q, true, MH>), grid, dim3(64), 0, s, a, per);
     else
-        hipLaunchKernelGGL((k_stage<T, Q, false>), grid, dim3(64), 0, s, a, per);
+        hipLaunchKernelGGL((k_stage<T, Q, false, MH>), grid, dim3(64), 0, s, a, per);
+}
+
+template <typename T, int Q>
+void stage_launch(const StageArgs& a, hipStream_t s) {
+    if (a.nharm > 1)
+        stage_launch_mh<T, Q, true>(a, s);
+    else
+        stage_launch_mh<T, Q, false>(a, s);
 }
 
 void check_launch() {

@@ -55,7 +55,15 @@ struct StageArgs {
     int64_t bstride;        // field elements between consecutive members
     int64_t gstride;        // geometry elements between members (0: shared)
     int64_t sstride;        // source elements between members
+    // further harmonics h = 1 .. nharm - 1 of a several-frequency problem
+    // (single launches): source Re(S_h e^{i k_h w0 t}) = hcos[h] Sre_h -
+    // hsin[h] Sim_h, filter F_h += hfa[h] U + hfb[h] k; S_h and F_h sit
+    // hstride elements after S_(h-1) and F_(h-1)
+    int nharm;              // 1 for a single frequency
+    int64_t hstride;
+    double hcos[8], hsin[8], hfa_re[8], hfa_im[8], hfb_re[8], hfb_im[8];
 };
+constexpr int kMaxHarm = 8;
 // per-member scalars of a batched stage: cy, ca, cu, scos, ssin, fa_re, fa_im, fb_re, fb_im
 constexpr int kMemberParams = 9;
 

@@ -82,7 +82,9 @@ struct cmcg_space {
 
 struct cmcg_problem {
     std::shared_ptr<cmcg::SpaceData> sp;
-    double omega = 0;
+    double omega = 0;  // the (base) frequency: the period is 2 pi / omega
+    int nharm = 1;                 // harmonics of the source (several-frequency problems)
+    std::vector<int> kharm{1};     // harmonic h has frequency kharm[h] * omega
     std::vector<double> eps, mu, sigma;
     bool has_j = false, has_g = false;
     // device data
@@ -105,6 +107,7 @@ struct cmcg_problem {
 
 struct cmcg_result {
     std::shared_ptr<cmcg::SpaceData> sp;
+    int nharm = 1;                 // filtered fields stacked per harmonic in Fre, Fim
     cmcg::DevBuf Fre, Fim, U0;
     cmcg_stats st{};
     std::vector<double> history;

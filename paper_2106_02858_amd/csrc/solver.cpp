@@ -9,6 +9,8 @@
 #include <map>
 #include <mutex>
 
+#include <array>
+
 #include "objects.h"
 
 namespace cmcg {
@@ -117,9 +119,11 @@ static void upload_field(const SpaceData& s, DevBuf& b, const std::vector<double
     }
 }
 
+// j_re / j_im: [nh][K][Np][3] (harmonic h with frequency ks[h] omega; nh = 1,
+// ks = NULL for a single frequency); g only for a single frequency.
 static cmcg_problem* make_problem(const cmcg_space* sh, const double* eps, const double* mu, const double* sigma,
                                   double omega, const double* j_re, const double* j_im, const double* g_re,
-                                  const double* g_im) {
+                                  const double* g_im, int nh = 1, const int* ks = nullptr) {
     if (!sh || !sh->d) fail(CMCG_ERR_ARG, "problem: NULL space");
     if (!eps || !mu) fail(CMCG_ERR_ARG, "problem: NULL eps or mu");
     if (!(omega > 0) || !std::isfinite(omega)) fail(CMCG_ERR_ARG, "problem: omega must be positive");
@@ -127,9 +131,21 @@ static cmcg_problem* make_problem(const cmcg_space* sh, const double* eps, const
     if (current_device() != sp->device) fail(CMCG_ERR_STATE, "problem: wrong current device");
     const int64_t K = sp->K;
     const int Np = sp->Np, Nfp = sp->Nfp;
+    if (nh < 1 || nh > kMaxHarm) fail(CMCG_ERR_ARG, "problem: 1 to 8 harmonics");
     std::unique_ptr<cmcg_problem> p(new cmcg_problem());
     p->sp = sp;
     p->omega = omega;
+    p->nharm = nh;
+    p->kharm.assign(nh, 1);
+    if (ks) {
+        for (int h = 0; h < nh; ++h) {
+            if (ks[h] < 1) fail(CMCG_ERR_ARG, "problem: harmonic numbers must be positive");
+            for (int h2 = 0; h2 < h; ++h2)
+                if (ks[h2] == ks[h]) fail(CMCG_ERR_ARG, "problem: harmonic numbers must be distinct");
+            p->kharm[h] = ks[h];
+        }
+    }
+    if (nh > 1 && (g_re || g_im)) fail(CMCG_ERR_ARG, "problem: boundary data only for a single frequency");
     p->eps.assign(eps, eps + K);
     p->mu.assign(mu, mu + K);
     p->sigma.assign(K, 0.0);
@@ -155,15 +171,16 @@ static cmcg_problem* make_problem(const cmcg_space* sh, const double* eps, const
     p->has_j = j_re || j_im;
     p->has_g = g_re || g_im;
     if (p->has_j || p->has_g) {
-        std::vector<double> sr(sp->ndof, 0.0), si(sp->ndof, 0.0);
-        for (int64_t e = 0; e < K; ++e)
-            for (int c = 0; c < 3; ++c)
-                for (int i = 0; i < Np; ++i) {
-                    const int64_t src = (e * Np + i) * 3 + c;
-                    const int64_t dst = (e * 6 + c) * Np + i;
-                    if (j_re) sr[dst] = j_re[src] / p->eps[e];
-                    if (j_im) si[dst] = j_im[src] / p->eps[e];
-                }
+        std::vector<double> sr(sp->ndof * nh, 0.0), si(sp->ndof * nh, 0.0);
+        for (int h = 0; h < nh; ++h)
+            for (int64_t e = 0; e < K; ++e)
+                for (int c = 0; c < 3; ++c)
+                    for (int i = 0; i < Np; ++i) {
+                        const int64_t src = ((h * K + e) * Np + i) * 3 + c;
+                        const int64_t dst = h * sp->ndof + (e * 6 + c) * Np + i;
+                        if (j_re) sr[dst] = j_re[src] / p->eps[e];
+                        if (j_im) si[dst] = j_im[src] / p->eps[e];
+                    }
         if (p->has_g) {
             // ghost E+ = n x G on impedance faces: flux_E = (n x G)/(2Z),
             // flux_H = n x (n x G) / 2, lifted with the face scaling
@@ -242,8 +259,8 @@ static void ensure_work(cmcg_problem* p) {
     p->Y2.alloc(fb);
     p->Acc.alloc(fb);
     if (s.precision == CMCG_FP32) p->Ulo.alloc(s.ndof * 2);
-    p->Fre.alloc(db);
-    p->Fim.alloc(db);
+    p->Fre.alloc(db * p->nharm);
+    p->Fim.alloc(db * p->nharm);
     p->partial.alloc(dot_partials() * 8);
     p->scal.alloc(64);
 }
@@ -259,6 +276,8 @@ static StageArgs base_args(cmcg_problem* p) {
     a.Fre = p->Fre.as<double>();
     a.Fim = p->Fim.as<double>();
     a.Ulo = p->Ulo.p;
+    a.nharm = p->nharm;
+    a.hstride = s.ndof;
     return a;
 }
 
@@ -276,14 +295,29 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
         launch_zero(p->Fre.p, p->Fre.bytes, st);
         launch_zero(p->Fim.p, p->Fim.bytes, st);
     }
-    std::complex<double> xi[4];
-    if (filt && c.scheme == 4) hermite_weights(p->omega, dt, xi);
+    // harmonic h has frequency k_h omega (k = 1 for a single-frequency problem)
+    const int H = p->nharm;
+    std::vector<std::array<std::complex<double>, 4>> xi(H);
+    if (filt && c.scheme == 4)
+        for (int h = 0; h < H; ++h) hermite_weights(p->kharm[h] * p->omega, dt, xi[h].data());
     const double twoT = 2.0 / c.T;
-    auto ph = [&](double m) { return std::complex<double>(std::cos(two_pi * m / M), -std::sin(two_pi * m / M)); };
+    // e^{-i k_h omega t_m}
+    auto ph = [&](int h, double m) {
+        const double x = two_pi * p->kharm[h] * m / M;
+        return std::complex<double>(std::cos(x), -std::sin(x));
+    };
     auto set_src = [&](double mm) {
-        const double phase = two_pi * mm / M;
-        a.scos = std::cos(phase);
-        a.ssin = std::sin(phase);
+        for (int h = 0; h < H; ++h) {
+            const double phase = two_pi * p->kharm[h] * mm / M;
+            (h == 0 ? a.scos : a.hcos[h]) = std::cos(phase);
+            (h == 0 ? a.ssin : a.hsin[h]) = std::sin(phase);
+        }
+    };
+    auto set_filter = [&](int h, std::complex<double> wa, std::complex<double> wb) {
+        (h == 0 ? a.fa_re : a.hfa_re[h]) = wa.real();
+        (h == 0 ? a.fa_im : a.hfa_im[h]) = wa.imag();
+        (h == 0 ? a.fb_re : a.hfb_re[h]) = wb.real();
+        (h == 0 ? a.fb_im : a.hfb_im[h]) = wb.imag();
     };
     for (int m = 0; m < M; ++m) {
         a.filter = 0;
@@ -297,11 +331,8 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
             set_src(m);
             if (filt) {
                 // trapezoid: weight (1/M) e^{-i w t_m}, doubled for interior levels
-                std::complex<double> w = ph(m) * ((m == 0 ? 1.0 : 2.0) / M);
                 a.filter = 1;
-                a.fa_re = w.real();
-                a.fa_im = w.imag();
-                a.fb_re = a.fb_im = 0;
+                for (int h = 0; h < H; ++h) set_filter(h, ph(h, m) * ((m == 0 ? 1.0 : 2.0) / M), 0.0);
             }
             launch_stage(q, prec, a, st);
             a.filter = 0;
@@ -324,16 +355,15 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
             set_src(m);
             if (filt) {
                 // Hermite: U_m and Phi_m weights of the intervals [t_{m-1}, t_m], [t_m, t_{m+1}]
-                std::complex<double> wa = twoT * ph(m) * xi[0], wb = twoT * ph(m) * xi[2];
-                if (m >= 1) {
-                    wa += twoT * ph(m - 1) * xi[1];
-                    wb += twoT * ph(m - 1) * xi[3];
-                }
                 a.filter = 1;
-                a.fa_re = wa.real();
-                a.fa_im = wa.imag();
-                a.fb_re = wb.real();
-                a.fb_im = wb.imag();
+                for (int h = 0; h < H; ++h) {
+                    std::complex<double> wa = twoT * ph(h, m) * xi[h][0], wb = twoT * ph(h, m) * xi[h][2];
+                    if (m >= 1) {
+                        wa += twoT * ph(h, m - 1) * xi[h][1];
+                        wb += twoT * ph(h, m - 1) * xi[h][3];
+                    }
+                    set_filter(h, wa, wb);
+                }
             }
             launch_stage(q, prec, a, st);
             a.filter = 0;
@@ -360,21 +390,21 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
     }
     if (filt) {
         if (c.scheme == 2) {
-            launch_filter_add(prec, p->U.p, 1.0 / M, 0.0, p->Fre.as<double>(), p->Fim.as<double>(), s.ndof, st);
+            // last level t_M = T: e^{-i k_h w T} = 1
+            for (int h = 0; h < H; ++h)
+                launch_filter_add(prec, p->U.p, 1.0 / M, 0.0, p->Fre.as<double>() + h * s.ndof,
+                                  p->Fim.as<double>() + h * s.ndof, s.ndof, st);
         } else {
             // last level: Phi(t_M, U_M) and the weights of [t_{M-1}, t_M]
             p->Kbuf.alloc(s.ndof * s.esize());
-            std::complex<double> wa = twoT * ph(M - 1) * xi[1], wb = twoT * ph(M - 1) * xi[3];
             a.mode = RHS;
             a.Y = p->U.p;
             a.U = p->U.p;
             a.Kout = p->Kbuf.p;
             set_src(M);
             a.filter = 1;
-            a.fa_re = wa.real();
-            a.fa_im = wa.imag();
-            a.fb_re = wb.real();
-            a.fb_im = wb.imag();
+            for (int h = 0; h < H; ++h)
+                set_filter(h, twoT * ph(h, M - 1) * xi[h][1], twoT * ph(h, M - 1) * xi[h][3]);
             launch_stage(q, prec, a, st);
         }
     }
@@ -477,8 +507,9 @@ void CgRun::start(cmcg_problem* pr, const cmcg_options* opt, const double* u0_, 
     p->v_gs.alloc(db);
     res.reset(new cmcg_result());
     res->sp = p->sp;
-    res->Fre.alloc(db);
-    res->Fim.alloc(db);
+    res->nharm = p->nharm;
+    res->Fre.alloc(db * p->nharm);
+    res->Fim.alloc(db * p->nharm);
     res->U0.alloc(db);
     fixed = o.fixed_iters > 0;
     refresh = o.residual_refresh > 0 ? o.residual_refresh : 0;
@@ -537,8 +568,8 @@ void CgRun::decide() {
         apply_period(p, c, &o, U, nullptr, nullptr, +1, true, true, st);
         periods += 1;
         const size_t db = n * 8;
-        CMCG_HIP(hipMemcpyAsync(res->Fre.p, p->Fre.p, db, hipMemcpyDeviceToDevice, st));
-        CMCG_HIP(hipMemcpyAsync(res->Fim.p, p->Fim.p, db, hipMemcpyDeviceToDevice, st));
+        CMCG_HIP(hipMemcpyAsync(res->Fre.p, p->Fre.p, db * p->nharm, hipMemcpyDeviceToDevice, st));
+        CMCG_HIP(hipMemcpyAsync(res->Fim.p, p->Fim.p, db * p->nharm, hipMemcpyDeviceToDevice, st));
         CMCG_HIP(hipMemcpyAsync(res->U0.p, U, db, hipMemcpyDeviceToDevice, st));
         phase = kFinal;
         return;
@@ -635,8 +666,9 @@ cmcg_result* fw_solve(cmcg_problem* p, const cmcg_options* o, const double* u0, 
     p->v_r.alloc(db);
     std::unique_ptr<cmcg_result> res(new cmcg_result());
     res->sp = p->sp;
-    res->Fre.alloc(db);
-    res->Fim.alloc(db);
+    res->nharm = p->nharm;
+    res->Fre.alloc(db * p->nharm);
+    res->Fim.alloc(db * p->nharm);
     res->U0.alloc(db);
     double *U = p->v_u.as<double>(), *W = p->v_w.as<double>(), *D = p->v_r.as<double>();
     CMCG_HIP(hipStreamSynchronize(st));
@@ -671,8 +703,8 @@ cmcg_result* fw_solve(cmcg_problem* p, const cmcg_options* o, const double* u0, 
     // the iterate U_0^(plain) and its filtered field
     CMCG_HIP(hipMemcpyAsync(res->U0.p, U, db, hipMemcpyDeviceToDevice, st));
     apply_period(p, c, o, U, nullptr, nullptr, +1, true, true, st);
-    CMCG_HIP(hipMemcpyAsync(res->Fre.p, p->Fre.p, db, hipMemcpyDeviceToDevice, st));
-    CMCG_HIP(hipMemcpyAsync(res->Fim.p, p->Fim.p, db, hipMemcpyDeviceToDevice, st));
+    CMCG_HIP(hipMemcpyAsync(res->Fre.p, p->Fre.p, db * p->nharm, hipMemcpyDeviceToDevice, st));
+    CMCG_HIP(hipMemcpyAsync(res->Fim.p, p->Fim.p, db * p->nharm, hipMemcpyDeviceToDevice, st));
     CMCG_HIP(hipStreamSynchronize(st));
     cmcg_stats& S = res->st;
     S.iters = plain;
@@ -838,6 +870,18 @@ int cmcg_problem_create(const cmcg_space* s, const double* eps, const double* mu
     CMCG_GUARD_END
 }
 
+int cmcg_problem_create_harmonics(const cmcg_space* s, const double* eps, const double* mu, const double* sigma,
+                                  double omega0, int nh, const int* k, const double* j_re, const double* j_im,
+                                  cmcg_problem** out) {
+    CMCG_GUARD_BEGIN
+    if (!out) fail(CMCG_ERR_ARG, "problem_harmonics: NULL output");
+    *out = nullptr;
+    if (!k) fail(CMCG_ERR_ARG, "problem_harmonics: NULL harmonic numbers");
+    *out = make_problem(s, eps, mu, sigma, omega0, j_re, j_im, nullptr, nullptr, nh, k);
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
 int cmcg_problem_create_device(const cmcg_space* s, const double* eps, const double* mu, const double* sigma,
                                double omega, const double* j_re_dev, const double* j_im_dev, hipStream_t stream,
                                cmcg_problem** out) {
@@ -958,6 +1002,27 @@ int cmcg_result_filtered_device(const cmcg_result* r, double* f_re, double* f_im
     const size_t b = r->sp->ndof * 8;
     if (f_re) CMCG_HIP(hipMemcpyAsync(f_re, r->Fre.p, b, hipMemcpyDeviceToDevice, stream));
     if (f_im) CMCG_HIP(hipMemcpyAsync(f_im, r->Fim.p, b, hipMemcpyDeviceToDevice, stream));
+    CMCG_HIP(hipStreamSynchronize(stream));
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_result_harmonics(const cmcg_result* r, int* nh) {
+    CMCG_GUARD_BEGIN
+    if (!r || !nh) fail(CMCG_ERR_ARG, "result_harmonics: NULL argument");
+    *nh = r->nharm;
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_result_filtered_harmonic_device(const cmcg_result* r, int h, double* f_re, double* f_im,
+                                         hipStream_t stream) {
+    CMCG_GUARD_BEGIN
+    if (!r || !r->sp) fail(CMCG_ERR_ARG, "result: NULL result");
+    if (h < 0 || h >= r->nharm) fail(CMCG_ERR_ARG, "result: harmonic index out of range");
+    const size_t n = r->sp->ndof, b = n * 8;
+    if (f_re) CMCG_HIP(hipMemcpyAsync(f_re, r->Fre.as<double>() + h * n, b, hipMemcpyDeviceToDevice, stream));
+    if (f_im) CMCG_HIP(hipMemcpyAsync(f_im, r->Fim.as<double>() + h * n, b, hipMemcpyDeviceToDevice, stream));
     CMCG_HIP(hipStreamSynchronize(stream));
     return CMCG_OK;
     CMCG_GUARD_END

@@ -210,3 +210,17 @@ def test_cmcg_fp32_against_oracle(lib, q, n):
     print(f"fp32 q={q}: iters {st['iters']} err {err:.3e}", flush=True)
     assert st["rel_res"] <= 1e-6
     assert err < 1e-5
+
+
+@pytest.mark.parametrize("q,n", [(1, 2), (2, 2)])
+def test_cmcg_fixed_iterations_conductive_with_boundary_data(lib, q, n):
+    """Conductivity sigma > 0 on ~30% of the elements and impedance data g on
+    the walls (the problem statement's full right-hand side): CMCG iterates at
+    a fixed count, 1e-11 bounded by the oracle's own rounding spread."""
+    op, s, lp = pair(lib, n=n, q=q, seed=6, sigma=True, g=True, tags=2)
+    iters = 12
+    ref, spread = _oracle_self_spread(op, iters)
+    r = lib.cmcg_solve(lp, lib.cmcg_options_default(fixed_iters=iters))
+    err = rel_norm_c(op, _filtered(lib, r, op), ref.F)
+    print(f"conductive cmcg q={q}: {err:.2e} (oracle spread {spread:.2e})", flush=True)
+    assert err < max(1e-11, 10 * spread)
