@@ -366,7 +366,7 @@ def served(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "single-GPU implementation: --gpus must be 1"}))
         sys.exit(2)
     if a.workload == "batched":
         batched(a)
