@@ -15,6 +15,7 @@ filters   trapezoid and Hermite period filters
 cmcg      initialisation, gradient and CG algorithms of Section 2.2
 fs        frequency-domain solve and the discrete-periodic exact solve
 fw        limiting-amplitude (full wave) iteration of Section 6
+multifreq several harmonics of a base frequency in one CMCG solve
 
 Parity status: every function is pinned by a test under tests/ against a
 closed form, an invariant, a brute-force computation or a library routine,

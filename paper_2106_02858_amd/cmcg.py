@@ -148,8 +148,9 @@ def _ptr(a):
 
 
 def _stream(stream=None):
+    """A raw HIP stream handle, a torch stream, or None (torch's current stream)."""
     if stream is not None:
-        return stream
+        return getattr(stream, "cuda_stream", stream)
     import torch
     return torch.cuda.current_stream().cuda_stream
 

@@ -168,6 +168,16 @@ static cmcg_problem* make_problem(const cmcg_space* sh, const double* eps, const
     CMCG_HIP(hipMemcpy(p->wE.p, we.data(), K * 8, hipMemcpyHostToDevice));
     CMCG_HIP(hipMemcpy(p->wH.p, wh.data(), K * 8, hipMemcpyHostToDevice));
     // source vector S with Re(S e^{i w t}) = the forcing of Phi
+    const int64_t nj = (int64_t)nh * K * Np * 3;
+    for (const double* a : {j_re, j_im})
+        if (a)
+            for (int64_t i = 0; i < nj; ++i)
+                if (!std::isfinite(a[i])) fail(CMCG_ERR_ARG, "problem: non-finite current density");
+    const int64_t ng = K * 4 * (int64_t)Nfp * 3;
+    for (const double* a : {g_re, g_im})
+        if (a)
+            for (int64_t i = 0; i < ng; ++i)
+                if (!std::isfinite(a[i])) fail(CMCG_ERR_ARG, "problem: non-finite boundary data");
     p->has_j = j_re || j_im;
     p->has_g = g_re || g_im;
     if (p->has_j || p->has_g) {

@@ -141,3 +141,76 @@ def test_engine_state_errors(lib):
     with pytest.raises(lib.CmcgError) as err:
         lib.cmcg_engine_create(1 << 20, 0)
     assert err.value.code == lib.CMCG_ERR_ARG
+
+
+def _small_problem(lib, precision=1, q=1, omega=2 * np.pi):
+    xyz, tet, tags = inputs.cube_mesh(2)
+    m = lib.cmcg_mesh_create(xyz, tet, tags)
+    s = lib.cmcg_space_create(m, q, precision)
+    K = tet.shape[0]
+    j = inputs.gaussian_current(lib.cmcg_space_nodes(s), (0.5, 0.5, 0.5), 0.3, 2)
+    return lib.cmcg_problem_create(s, np.ones(K), np.ones(K), None, omega, j), s
+
+
+# Three steps over a period of 1000 time units: each step is thousands of
+# times the stability limit, so the FP32 fields overflow within the first
+# CG iteration.
+UNSTABLE = dict(steps=3, max_iter=50)
+SLOW = 2 * np.pi * 1e-3
+
+
+def test_unstable_step_is_reported(lib):
+    """A time step far above the stability limit (forced from the host: three
+    steps per period) grows without bound: the solve reports the instability
+    (non-finite values, or the CG breakdown they cause) instead of a result."""
+    p, _ = _small_problem(lib, precision=1, omega=SLOW)
+    with pytest.raises(lib.CmcgError) as e:
+        lib.cmcg_solve(p, lib.cmcg_options_default(**UNSTABLE))
+    assert e.value.code in (lib.CMCG_ERR_UNSTABLE, lib.CMCG_ERR_BREAKDOWN)
+
+
+def test_non_finite_current_is_rejected(lib):
+    xyz, tet, tags = inputs.cube_mesh(1)
+    m = lib.cmcg_mesh_create(xyz, tet, tags)
+    s = lib.cmcg_space_create(m, 1, 0)
+    K = tet.shape[0]
+    j = np.zeros((K, 4, 3))
+    j[2, 1, 0] = np.inf
+    with pytest.raises(lib.CmcgError) as e:
+        lib.cmcg_problem_create(s, np.ones(K), np.ones(K), None, 1.0, j)
+    assert e.value.code == lib.CMCG_ERR_ARG
+
+
+def test_engine_failed_slot_does_not_disturb_others(lib):
+    bad, _ = _small_problem(lib, precision=1, omega=SLOW)
+    good, _ = _small_problem(lib, precision=1)
+    e = lib.cmcg_engine_create(1 << 30, 4)
+    sb = lib.cmcg_engine_admit(e, bad, lib.cmcg_options_default(**UNSTABLE))
+    sg = lib.cmcg_engine_admit(e, good, lib.cmcg_options_default(tol=1e-6))
+    while lib.cmcg_engine_poll(e, sb) == 1 or lib.cmcg_engine_poll(e, sg) == 1:
+        lib.cmcg_engine_step(e)
+    assert lib.cmcg_engine_poll(e, sb) == 3
+    with pytest.raises(lib.CmcgError) as err:
+        lib.cmcg_engine_collect(e, sb, bad)
+    assert err.value.code in (lib.CMCG_ERR_UNSTABLE, lib.CMCG_ERR_BREAKDOWN)
+    r = lib.cmcg_engine_collect(e, sg, good)
+    alone = lib.cmcg_solve(good, lib.cmcg_options_default(tol=1e-6))
+    assert lib.cmcg_result_stats(r)["iters"] == lib.cmcg_result_stats(alone)["iters"]
+    assert lib.cmcg_engine_info(e)["used"] == 0
+
+
+def test_solve_on_a_caller_stream(lib):
+    import torch
+    p, s = _small_problem(lib, precision=0, q=2)
+    o = lib.cmcg_options_default(fixed_iters=5)
+    st = torch.cuda.Stream()
+    r1 = lib.cmcg_solve(p, o, stream=st)
+    r0 = lib.cmcg_solve(p, o)
+    info = lib.cmcg_space_info(s)
+    out = [torch.zeros((info["K"], 6, info["Np"]), dtype=torch.float64, device="cuda") for _ in range(4)]
+    lib.cmcg_result_filtered_device(r1, out[0], out[1], st)
+    st.synchronize()
+    lib.cmcg_result_filtered_device(r0, out[2], out[3])
+    torch.cuda.synchronize()
+    assert float(out[2].abs().max()) > 0
+    assert torch.equal(out[0], out[2]) and torch.equal(out[1], out[3])
