@@ -26,7 +26,7 @@ struct Batch {
     bool shared_geo = true;
     int src_rows = 0;
     // device
-    DevBuf geo, wE, wH, Sre, Sim;
+    DevBuf geo, wE, wH, Sre, Sim, smask;
     DevBuf U, Y1, Y2, Acc, Fre, Fim, Kbuf;
     DevBuf Ulo;  // FP32 fields: bfloat16 low parts of U
     DevBuf vu, vr, vd, va, vw, vgs, vbest;
@@ -132,6 +132,7 @@ StageArgs batch_args(Batch& bt) {
     a.K = bt.sp->K;
     a.Sre = bt.Sre.p;
     a.Sim = bt.Sim.p;
+    a.smask = bt.smask.as<uint32_t>();
     a.Fre = bt.Fre.as<double>();
     a.Fim = bt.Fim.as<double>();
     a.Ulo = bt.Ulo.p;
@@ -348,8 +349,13 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
         bt.Sim.alloc(bt.fb());
         launch_zero(bt.Sre.p, bt.Sre.bytes, st);
         launch_zero(bt.Sim.p, bt.Sim.bytes, st);
+        const int64_t mw = source_mask_words(K);
+        bt.smask.alloc((size_t)mw * 4 * B);
+        launch_zero(bt.smask.p, bt.smask.bytes, st);
         for (int b = 0; b < B; ++b) {
             if (!probs[b]->src_rows) continue;
+            CMCG_HIP(hipMemcpyAsync(bt.smask.as<uint32_t>() + b * mw, probs[b]->smask.p, mw * 4,
+                                    hipMemcpyDeviceToDevice, st));
             CMCG_HIP(hipMemcpyAsync((char*)bt.Sre.p + b * n * esz, probs[b]->Sre.p, n * esz, hipMemcpyDeviceToDevice,
                                     st));
             CMCG_HIP(hipMemcpyAsync((char*)bt.Sim.p + b * n * esz, probs[b]->Sim.p, n * esz, hipMemcpyDeviceToDevice,

@@ -52,7 +52,7 @@ size_t footprint(const cmcg_problem* p) {
     const size_t n = s.ndof, es = s.esize(), K = s.K;
     const size_t H = p->nharm;
     size_t b = K * kGeo * es + 2 * K * 8;  // geometry, mass weights
-    if (p->src_rows) b += 2 * n * es * H;  // source (per harmonic)
+    if (p->src_rows) b += 2 * n * es * H + p->smask.bytes;  // source (per harmonic) and its element mask
     b += 5 * n * es;                       // U, Y1, Y2, Acc, RHS buffer
     if (s.precision == CMCG_FP32) b += 2 * n;  // bfloat16 low parts of U
     b += 2 * n * 8 * H;                    // filter accumulators (per harmonic)

@@ -182,6 +182,7 @@ __device__ __forceinline__ bool member_args(const StageArgs& in, StageArgs& a) {
     a.geo = (const T*)in.geo + (int64_t)b * in.gstride;
     if (in.Sre) a.Sre = (const T*)in.Sre + (int64_t)b * in.sstride;
     if (in.Sim) a.Sim = (const T*)in.Sim + (int64_t)b * in.sstride;
+    if (in.smask) a.smask = in.smask + (int64_t)b * ((in.K + EPW - 1) / EPW);
     return true;
 }
 
@@ -499,7 +500,7 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     T kv[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) kv[i] = fma(inv, acc[i], -sig * y[i]);
-    if (c < a.src_rows) {
+    if (c < a.src_rows && (!a.smask || ((a.smask[blk] >> elc) & 1u))) {
         T sr[NP], si[NP];
         Row<T, NP>::load((const T*)a.Sre + grow, sr);
         Row<T, NP>::load((const T*)a.Sim + grow, si);
@@ -608,11 +609,15 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
 // with v_mfma_f32_16x16x4f32: A = the reference matrices, held as register
 // fragments (lane l holds A[l % 16][l / 16] of each 16x4 block, read once from a
 // lane-ordered table), B = W or flux values from LDS, D[4 (l/16) + r][l % 16].
-// Rows i >= Np and padded K entries carry zero A fragments.
+// The volume's K steps are axis-major: step ks covers axis a = ks / NJ and
+// nodes j = 4 (ks % NJ) + (0..3), so a lane meets the same nodes j = l/16 + 4 t
+// on every axis and reads them once.  Rows i >= Np and nodes j >= Np carry
+// zero A fragments.
 template <int Q> struct MfmaDim {
     static constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP;
     static constexpr int MT = (NP + 15) / 16;        // 16-row output tiles
-    static constexpr int KSV = (3 * NP + 3) / 4;     // K steps of the volume product
+    static constexpr int NJ = (NP + 3) / 4;          // K steps per axis of the volume product
+    static constexpr int KSV = 3 * NJ;               // K steps of the volume product
     static constexpr int KSF = (NFP + 3) / 4;        // K steps per face of the lift
     static constexpr int NFRAG = MT * KSV + 4 * MT * KSF;
 };
@@ -703,18 +708,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 
     // matrix fragments (coalesced: fragment-major, lane-minor)
     const float* fr = gFrag + frag_off(Q);
-    T afV[MT][KSV], afL[4][MT][KSF];
+    T afV[MT][KSV], afL[MT][KSF], afN[MT][KSF];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int ks = 0; ks < KSV; ++ks) afV[mt][ks] = fr[(mt * KSV + ks) * 64 + lane];
-#pragma unroll
-    for (int f = 0; f < 4; ++f)
+    // lift fragments of one face at a time, requested one face ahead
+    auto lift_frags = [&](int f, T (&d)[MT][KSF]) {
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int ks = 0; ks < KSF; ++ks)
-                afL[f][mt][ks] = fr[(MT * KSV + (f * MT + mt) * KSF + ks) * 64 + lane];
+            for (int ks = 0; ks < KSF; ++ks) d[mt][ks] = fr[(MT * KSV + (f * MT + mt) * KSF + ks) * 64 + lane];
+    };
+    lift_frags(0, afL);
     __syncthreads();
 
     // face 0's neighbour traces in flight during the volume product
@@ -731,12 +737,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    // ---- volume product: B[k = a Np + j][n] = sgn (g_a[m1] V_m2(j) - g_a[m2] V_m1(j))
+    // ---- volume product: B[(a, j)][n] = sgn (g_a[m1] V_m2(j) - g_a[m2] V_m1(j));
+    // padded columns read element 0 (their results are never stored)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         const int n = nt * 16 + l16;
-        const bool ncol = n < 6 * ne;
-        const int e = ncol ? n / 6 : 0;
+        const int e = n < 6 * ne ? n / 6 : 0;
         const int s = n - 6 * (n / 6);
         const int m = s < 3 ? s : s - 3;
         const int m1 = m == 2 ? 0 : m + 1, m2 = m == 0 ? 2 : m - 1;  // (m+1)%3, (m+2)%3
@@ -751,32 +757,31 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         }
         const T* v1 = &sh.sY[(vb + m1) * RS];
         const T* v2 = &sh.sY[(vb + m2) * RS];
+        constexpr int NJ = MD::NJ;
+        T r1[NJ], r2[NJ];
 #pragma unroll
-        for (int ks = 0; ks < KSV; ++ks) {
-            const int k = ks * 4 + q4;
-            T b = T(0);
-            if (ncol && k < 3 * NP) {
-                // the axis is uniform over the 4-row block unless the block straddles Np
-                int ax;
-                if ((4 * ks) / NP == (4 * ks + 3) / NP)
-                    ax = (4 * ks) / NP;
-                else
-                    ax = k / NP;
-                const int j = k - ax * NP;
-                const T ga = ax == 0 ? g1[0] : (ax == 1 ? g1[1] : g1[2]);
-                const T gb = ax == 0 ? g2[0] : (ax == 1 ? g2[1] : g2[2]);
-                b = ga * v2[j] - gb * v1[j];
-            }
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(afV[mt][ks], b, acc[mt][nt], 0, 0, 0);
+        for (int t = 0; t < NJ; ++t) {
+            const int j = q4 + 4 * t;
+            const bool in = NP % 4 == 0 || j < NP;  // j >= Np: zero fragment, zero operand
+            r1[t] = in ? v1[in ? j : 0] : T(0);
+            r2[t] = in ? v2[in ? j : 0] : T(0);
         }
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+            for (int t = 0; t < NJ; ++t) {
+                const T b = g1[ax] * r2[t] - g2[ax] * r1[t];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(afV[mt][ax * NJ + t], b, acc[mt][nt], 0, 0, 0);
+            }
     }
 
     // ---- upwind flux and lift, one face at a time
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
         if (PIPE && f < 3) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1, e0, ne);
+        if (f < 3) lift_frags(f + 1, afN);
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
             if (!itm.on[r]) continue;
@@ -832,12 +837,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
             for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(afL[f][mt][ks], b[nt], acc[mt][nt], 0, 0, 0);
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(afL[mt][ks], b[nt], acc[mt][nt], 0, 0, 0);
         }
         __syncthreads();  // the tile is rewritten by the next face
         if (f < 3) {
             if (!PIPE) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1, e0, ne);
             cur = nxt;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int ks = 0; ks < KSF; ++ks) afL[mt][ks] = afN[mt][ks];
         }
     }
 
@@ -868,6 +877,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     const int mode = a.mode;
     const T scos = (T)a.scos, ssin = (T)a.ssin;
     const T cy = (T)a.cy, ca = (T)a.ca, cu = (T)a.cu;
+    // elements whose source is zero (and H rows of an interior source) read none
+    const uint32_t sm = a.smask ? a.smask[blk] : 0xffffffffu;
+    auto takes_src = [&](int row) { return row - 6 * (row / 6) < a.src_rows && ((sm >> (row / 6)) & 1u); };
     MfmaUpdateIn<Q> upd;
     upd.fetch(a, base, nv4, lane);
     auto f4 = [](const void* p, int64_t o) { return reinterpret_cast<const float4*>((const T*)p + o); };
@@ -880,13 +892,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         T kv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) kv[u] = sh.sY[v + u + (v + u) / NP];
-        if (a.src_rows > 0) {
+        if (a.src_rows > 0 && (takes_src(v / NP) || takes_src((v + 3) / NP))) {
             const float4 sr = *f4(a.Sre, gi), si = *f4(a.Sim, gi);
             const T srv[4] = {sr.x, sr.y, sr.z, sr.w}, siv[4] = {si.x, si.y, si.z, si.w};
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int row = (v + u) / NP;
-                if (row - 6 * (row / 6) < a.src_rows) kv[u] += scos * srv[u] - ssin * siv[u];
+                if (takes_src(row)) kv[u] += scos * srv[u] - ssin * siv[u];
             }
 #pragma unroll 1
             for (int h = 1; MH && h < a.nharm; ++h) {  // further harmonics of a several-frequency source
@@ -896,7 +908,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int row = (v + u) / NP;
-                    if (row - 6 * (row / 6) < a.src_rows) kv[u] += hc * hrv[u] - hs * hiv[u];
+                    if (takes_src(row)) kv[u] += hc * hrv[u] - hs * hiv[u];
                 }
             }
         }
@@ -1014,6 +1026,25 @@ __global__ void k_copy(const T* __restrict__ s, T* __restrict__ d, int64_t n) {
 __global__ void k_zero(uint32_t* p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0u;
+}
+
+// One 64-lane workgroup per element block: bit e of mask[block] is set when
+// element e has a nonzero source value (either part, any row or harmonic).
+template <typename T>
+__global__ __launch_bounds__(64) void k_source_mask(const T* Sre, const T* Sim, int nharm, int64_t hstride,
+                                                    int64_t K, int np6, uint32_t* mask) {
+    const int64_t blk = blockIdx.x;
+    const int64_t e0 = blk * EPW;
+    const int ne = (int)((K - e0) < EPW ? (K - e0) : EPW);
+    const int n = ne * np6;
+    uint32_t bits = 0;
+    for (int h = 0; h < nharm; ++h)
+        for (int v = threadIdx.x; v < n; v += 64) {
+            const int64_t g = h * hstride + e0 * np6 + v;
+            if ((Sre && Sre[g] != T(0)) || (Sim && Sim[g] != T(0))) bits |= 1u << (v / np6);
+        }
+    for (int o = 32; o > 0; o >>= 1) bits |= (uint32_t)__shfl_xor((int)bits, o, 64);
+    if (threadIdx.x == 0) mask[blk] = bits;
 }
 
 __global__ void k_axpby(double a, const double* x, double b, const double* y, double* z, int64_t n) {
@@ -1255,7 +1286,7 @@ void upload_constants(int q, int precision, const double* D, const double* LIFT,
     if (q >= 2) {
         // lane-ordered A fragments of the matrix-core kernel: entry (frag, lane)
         // = A[16 mt + lane % 16][4 ks + lane / 16] of the block the fragment names
-        const int MT = (NP + 15) / 16, KSV = (3 * NP + 3) / 4, KSF = (NFP + 3) / 4;
+        const int MT = (NP + 15) / 16, NJ = (NP + 3) / 4, KSV = 3 * NJ, KSF = (NFP + 3) / 4;
         const int nfrag = MT * KSV + 4 * MT * KSF;
         std::vector<float> fr(64 * nfrag, 0.f);
         for (int l = 0; l < 64; ++l) {
@@ -1263,9 +1294,9 @@ void upload_constants(int q, int precision, const double* D, const double* LIFT,
             for (int mt = 0; mt < MT; ++mt) {
                 const int i = 16 * mt + i_in;
                 for (int ks = 0; ks < KSV; ++ks) {
-                    const int k = 4 * ks + k_in;  // k = a Np + j
+                    const int a = ks / NJ, j = 4 * (ks % NJ) + k_in;  // axis-major K order
                     float v = 0.f;
-                    if (i < NP && k < 3 * NP) v = (float)D[((k / NP) * NP + i) * NP + k % NP];
+                    if (i < NP && j < NP) v = (float)D[(a * NP + i) * NP + j];
                     fr[(mt * KSV + ks) * 64 + l] = v;
                 }
                 for (int f = 0; f < 4; ++f)
@@ -1328,6 +1359,21 @@ void launch_copy_field(int precision, const void* src, void* dst, int64_t n, hip
 void launch_zero(void* p, size_t bytes, hipStream_t s) {
     const int64_t n = (int64_t)(bytes / 4);
     hipLaunchKernelGGL(k_zero, dim3(grid_for(n)), dim3(256), 0, s, (uint32_t*)p, n);
+    check_launch();
+}
+
+int64_t source_mask_words(int64_t K) { return (K + EPW - 1) / EPW; }
+
+void launch_source_mask(int precision, int Np, const void* Sre, const void* Sim, int nharm, int64_t hstride,
+                        int64_t K, uint32_t* mask, hipStream_t s) {
+    const int64_t nb = source_mask_words(K);
+    if (nb == 0) return;
+    if (precision == CMCG_FP64)
+        hipLaunchKernelGGL(k_source_mask<double>, dim3((unsigned)nb), dim3(64), 0, s, (const double*)Sre,
+                           (const double*)Sim, nharm, hstride, K, 6 * Np, mask);
+    else
+        hipLaunchKernelGGL(k_source_mask<float>, dim3((unsigned)nb), dim3(64), 0, s, (const float*)Sre,
+                           (const float*)Sim, nharm, hstride, K, 6 * Np, mask);
     check_launch();
 }
 

@@ -37,6 +37,8 @@ struct StageArgs {
     const int* conn;    // [K][4]: >= 0: nbr<<5 | nbr_face<<3 | perm; -1 PEC; -2 impedance
     const void* Sre;    // source [K][6][Np] (nullable)
     const void* Sim;
+    const uint32_t* smask;  // per element block of the stage kernels: bit e set when element e of the
+                            // block has a nonzero source value (nullable: every element has)
     double* Fre;        // filter accumulators (nullable)
     double* Fim;
     int64_t K;
@@ -66,6 +68,13 @@ struct StageArgs {
 constexpr int kMaxHarm = 8;
 // per-member scalars of a batched stage: cy, ca, cu, scos, ssin, fa_re, fa_im, fb_re, fb_im
 constexpr int kMemberParams = 9;
+
+// Source element mask (StageArgs::smask) of a [nharm][K][6][Np] source: one
+// 32-bit word per element block; only exact zeros clear a bit, so skipping the
+// source of a cleared element changes no value.
+int64_t source_mask_words(int64_t K);
+void launch_source_mask(int precision, int Np, const void* Sre, const void* Sim, int nharm, int64_t hstride,
+                        int64_t K, uint32_t* mask, hipStream_t s);
 
 void upload_constants(int q, int precision, const double* D, const double* LIFT, const double* M,
                       const int* fnode, const int* fperm);

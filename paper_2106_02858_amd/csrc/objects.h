@@ -89,6 +89,7 @@ struct cmcg_problem {
     bool has_j = false, has_g = false;
     // device data
     cmcg::DevBuf geo, wE, wH, Sre, Sim;
+    cmcg::DevBuf smask;  // source element mask (StageArgs::smask)
     double geo_alpha = -1;
     int src_rows = 0;
     // work buffers

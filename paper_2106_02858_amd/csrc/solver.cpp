@@ -226,6 +226,9 @@ static cmcg_problem* make_problem(const cmcg_space* sh, const double* eps, const
         upload_field(*sp, p->Sre, sr);
         upload_field(*sp, p->Sim, si);
         p->src_rows = p->has_g ? 6 : 3;
+        p->smask.alloc(source_mask_words(K) * 4);
+        launch_source_mask(sp->precision, Np, p->Sre.p, p->Sim.p, nh, sp->ndof, K, p->smask.as<uint32_t>(), nullptr);
+        CMCG_HIP(hipStreamSynchronize(nullptr));
     }
     build_geo(p.get(), 1.0);
     p->pinned.reset(new HostPinned());
@@ -283,6 +286,7 @@ static StageArgs base_args(cmcg_problem* p) {
     a.K = s.K;
     a.Sre = p->Sre.p;
     a.Sim = p->Sim.p;
+    a.smask = p->smask.as<uint32_t>();
     a.Fre = p->Fre.as<double>();
     a.Fim = p->Fim.as<double>();
     a.Ulo = p->Ulo.p;

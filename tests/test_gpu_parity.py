@@ -11,7 +11,8 @@ import pytest
 
 from oracle import cmcg as ocmcg
 from oracle import dg, timestep
-from tests._pairs import pair, rel_norm, rel_norm_c, workload_pair
+from paper_2106_02858_amd import inputs
+from tests._pairs import lib_problem, pair, rel_norm, rel_norm_c, workload_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -60,6 +61,42 @@ def test_rhs_parity(lib, variant):
         ref = dg.phi(op, t, U, with_source=src)
         err = np.max(np.abs(host(out) - ref)) / np.max(np.abs(ref))
         assert err < TOL[precision], (t, src, err)
+
+
+LOCAL_SOURCE_ELEMENTS = (3, 4, 17, 45)  # 48 elements: blocks 0 and 4 mixed, 2 and 3 without source
+
+
+@pytest.mark.parametrize("variant", VARIANTS, indirect=True, ids=lambda t: f"q{t[0]}-p{t[1]}-v{t[2]}")
+def test_rhs_localised_source(lib, variant):
+    """A current confined to four elements: element blocks without any source
+    value skip the source arrays and blocks mix both kinds.  The right-hand
+    side still equals the oracle's, and its source part is exactly zero in
+    every element without current (and in every magnetic row)."""
+    q, precision, v = variant
+    print(f"localised source q={q} prec={precision} variant={v}", flush=True)
+    xyz, tet, tags = inputs.cube_mesh(2)
+    K = tet.shape[0]
+    rng = np.random.default_rng(40 + q)
+    Np = dg.make_problem(xyz, tet, tags, q, np.ones(K), np.ones(K)).geo.Np
+    j = np.zeros((K, Np, 3), complex)
+    for e in LOCAL_SOURCE_ELEMENTS:
+        j[e] = rng.standard_normal((Np, 3)) + 1j * rng.standard_normal((Np, 3))
+    eps = rng.choice([1.0, 2.0, 4.0], K)
+    op = dg.make_problem(xyz, tet, tags, q, eps, np.ones(K), j=j)
+    s, lp = lib_problem(lib, op, precision, xyz, tet, tags)
+    U = rng.standard_normal((K, 6, Np))
+    a, b = dev(np.zeros_like(U)), dev(np.zeros_like(U))
+    t = 0.37
+    lib.cmcg_debug_rhs(lp, dev(U), a, t=t, with_source=True)
+    lib.cmcg_debug_rhs(lp, dev(U), b, t=t, with_source=False)
+    ref = dg.phi(op, t, U, with_source=True)
+    assert np.max(np.abs(host(a) - ref)) / np.max(np.abs(ref)) < TOL[precision]
+    src, ref_src = host(a) - host(b), dg.source(op, t)
+    off = np.ones(K, bool)
+    off[list(LOCAL_SOURCE_ELEMENTS)] = False
+    assert np.all(src[off] == 0) and np.all(src[:, 3:] == 0)
+    # the difference of two right-hand sides carries their rounding (|B U| >> |J|)
+    assert np.max(np.abs(src - ref_src)) / np.max(np.abs(ref_src)) < (1e-11 if precision == 0 else 1e-4)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
