@@ -64,9 +64,9 @@ def parse():
 # 48000-tet P3 FP32 problem, with the scales a 1 GiB copy gives each counter;
 # valid only for the kernel source they were taken on (SHA-256 below).
 MEASURED_TRAFFIC = {
-    "kernels_sha256": "41421d6b8b2c88806364c1a944a15c69dd2ef7f8b022f849b24ede7b9a8da287",
-    "kernel": "k_stage_mfma<3,true>", "K": 48000,
-    "fetch_kib": 47573.06, "fetch_scale": 2.0000, "write_kib": 49721.90, "write_scale": 1.0000,
+    "kernels_sha256": "6d9e5d8b97d136e09a0f45d30a1ab49d9e6725940179ae5a45835b8deb10c39f",
+    "kernel": "k_stage_mfma<3,true,false>", "K": 48000,
+    "fetch_kib": 41866.43, "fetch_scale": 2.0000, "write_kib": 42260.93, "write_scale": 1.0000,
 }
 
 
@@ -86,8 +86,9 @@ def measured_traffic(kernel: str, K: int):
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024
 
 
-STAGE_KERNEL = {0: "k_stage<float,{q},false>", 1: "k_stage<float,{q},true>", 2: "k_stage_mfma<{q},false>",
-                3: "k_stage_mfma<{q},true>"}
+# single-frequency instantiations (the last template argument selects the several-frequency code)
+STAGE_KERNEL = {0: "k_stage<float,{q},false,false>", 1: "k_stage<float,{q},true,false>",
+                2: "k_stage_mfma<{q},false,false>", 3: "k_stage_mfma<{q},true,false>"}
 
 
 def stage_bytes_per_element(q: int, esize: int) -> float:
