@@ -108,11 +108,17 @@ typedef struct cmcg_options {
      * no report. */
     int (*progress)(void* ctx, int iter, double rel_res);
     void* progress_ctx;
+    /* Run-up (Section 6 mentions it as a way to accelerate CMCG): > 0 runs
+     * that many limiting-amplitude periods U <- P_psi U (time stepping with the
+     * source) from the initial guess before Algorithm 3 starts, which then
+     * starts from their end state; the periods count in stats.periods.  0 =
+     * none (the paper's zero initialisation); < 0 is CMCG_ERR_ARG. */
+    int runup;
 } cmcg_options;
 
 /* Fills *o with defaults: tol 1e-8, max_iter 1000, fixed_iters 0, cfl 0,
  * steps 0, scheme AUTO, flux UPWIND, use_graph 1, residual_refresh 0,
- * progress NULL. */
+ * progress NULL, runup 0. */
 void cmcg_options_default(cmcg_options* o);
 
 /* Solve statistics. */
@@ -127,6 +133,8 @@ typedef struct cmcg_stats {
     double seconds;      /* wall time of the solve (inputs resident on device)  */
     double seconds_to_1e6; /* wall time until ||R||/||R0|| <= 1e-6 (-1: never)  */
     double dof_updates;  /* 6 Np K x steps executed over all periods            */
+    double res0;         /* ||R_0|| in the eps,mu norm: the first residual, the
+                            scale of the stop rule (0 for the FW iteration)     */
 } cmcg_stats;
 
 const char* cmcg_last_error(void);

@@ -90,22 +90,27 @@ def functional(ops: Operators, U0, G):
 
 
 def solve(p: dg.Problem, tol: float = 1e-8, max_iter: int = 1000, u0=None, M=None,
-          scheme=None, fixed_iters: int | None = None, cfl=None, filt: bool = True) -> Result:
+          scheme=None, fixed_iters: int | None = None, cfl=None, filt: bool = True, runup: int = 0) -> Result:
     """Algorithm 3.  Stops when ||R_l|| <= tol ||R_0|| or after ``fixed_iters``
-    iterations when that is given (used for parity at a fixed count)."""
+    iterations when that is given (used for parity at a fixed count).
+
+    ``runup`` > 0: the run-up phase Section 6 mentions as an accelerator --
+    that many limiting-amplitude periods U <- P_psi U from the initial guess
+    (zero or u0) before the first residual; CG then starts from their state."""
     ops = Operators(p, M, scheme, cfl)
     G, Gstar = initialise(ops)
-    if u0 is None:
-        U = np.zeros((p.K, 6, p.Np))
+    U = np.zeros((p.K, 6, p.Np)) if u0 is None else np.array(u0, dtype=np.float64).reshape(p.K, 6, p.Np)
+    for _ in range(runup):
+        U = ops.P_psi(U)
+    if u0 is None and runup == 0:
         R = -Gstar
     else:
-        U = np.array(u0, dtype=np.float64).reshape(p.K, 6, p.Np)
         R = gradient(ops, U, Gstar)
     D = R.copy()
     rr = ops.ip(R, R)
     rr0 = rr
     hist = [1.0]
-    Jrec = [0.5 * ops.ip(G, G)] if u0 is None else []
+    Jrec = [0.5 * ops.ip(G, G)] if u0 is None and runup == 0 else []
     it = 0
     limit = max_iter if fixed_iters is None else fixed_iters
     while it < limit:

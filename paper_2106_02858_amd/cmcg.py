@@ -56,7 +56,8 @@ PROGRESS_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_double)
 class cmcg_options(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("cfl", C.c_double),
                 ("steps", C.c_int), ("scheme", C.c_int), ("flux", C.c_int), ("use_graph", C.c_int),
-                ("residual_refresh", C.c_int), ("progress", PROGRESS_FN), ("progress_ctx", C.c_void_p)]
+                ("residual_refresh", C.c_int), ("progress", PROGRESS_FN), ("progress_ctx", C.c_void_p),
+                ("runup", C.c_int)]
 
     def set_progress(self, fn):
         """fn(iter, rel_res) -> bool (True stops the iteration)."""
@@ -67,7 +68,7 @@ class cmcg_options(C.Structure):
 class cmcg_stats(C.Structure):
     _fields_ = [("iters", C.c_int), ("periods", C.c_int), ("steps", C.c_int), ("status", C.c_int),
                 ("dt", C.c_double), ("rel_res", C.c_double), ("J0", C.c_double), ("seconds", C.c_double),
-                ("seconds_to_1e6", C.c_double), ("dof_updates", C.c_double)]
+                ("seconds_to_1e6", C.c_double), ("dof_updates", C.c_double), ("res0", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -298,6 +298,7 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
     bt.B = B;
     bt.sp = probs[0] ? probs[0]->sp : nullptr;
     if (!bt.sp) fail(CMCG_ERR_ARG, "solve_batch: NULL problem");
+    if (o->runup < 0) fail(CMCG_ERR_ARG, "options: runup must be >= 0");
     for (int b = 0; b < B; ++b) {
         if (!probs[b]) fail(CMCG_ERR_ARG, "solve_batch: NULL problem");
         if (probs[b]->sp != bt.sp) fail(CMCG_ERR_ARG, "solve_batch: all problems must share one space");
@@ -421,8 +422,16 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
         count_periods(2);
     };
     launch_zero(U, bt.db(), st);
-    if (!fixed) launch_zero(bt.vbest.p, bt.db(), st);
-    batch_axpby(bt, mone, Gs, zero, Gs, R, st);  // R0 = -G*
+    if (o->runup > 0) {
+        // run-up: limiting-amplitude periods U <- P_psi U from zero
+        for (int l = 0; l < o->runup; ++l) batch_apply(bt, o, U, U, nullptr, +1, true, false, st);
+        count_periods(o->runup);
+    }
+    if (!fixed) CMCG_HIP(hipMemcpyAsync(bt.vbest.p, U, bt.db(), hipMemcpyDeviceToDevice, st));
+    if (o->runup > 0)
+        gradient(R);
+    else
+        batch_axpby(bt, mone, Gs, zero, Gs, R, st);  // R0 = -G*
     CMCG_HIP(hipMemcpyAsync(D, R, bt.db(), hipMemcpyDeviceToDevice, st));
     std::vector<double> rr, rr0;
     batch_dots(bt, R, R, rr, st);
@@ -536,6 +545,7 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
         S.dt = bt.cfg[b].dt;
         S.rel_res = rel[b];
         S.J0 = J0[b];
+        S.res0 = std::sqrt(rr0[b]);
         S.seconds = total;
         S.seconds_to_1e6 = t6[b];
         S.dof_updates = (double)n * bt.cfg[b].M * periods[b];

@@ -508,6 +508,7 @@ void CgRun::start(cmcg_problem* pr, const cmcg_options* opt, const double* u0_, 
     o = *opt;
     st = s_;
     u0 = u0_;
+    if (o.runup < 0) fail(CMCG_ERR_ARG, "options: runup must be >= 0");
     c = step_config(p, &o);
     prepare(p, c);
     const SpaceData& s = *p->sp;
@@ -538,11 +539,16 @@ void CgRun::start(cmcg_problem* pr, const cmcg_options* opt, const double* u0_, 
     launch_axpby(-1.0, Gs, 0.0, Gs, Gs, n, st);              // G* = G - P* G
     periods += 2;
     dot_async(p, W, W, 0, st);
-    if (u0) {
+    if (u0)
         CMCG_HIP(hipMemcpyAsync(U, u0, db, hipMemcpyDeviceToDevice, st));
+    else
+        launch_zero(U, db, st);
+    // run-up: limiting-amplitude periods U <- P_psi U from the initial guess
+    for (int l = 0; l < o.runup; ++l) apply_period(p, c, &o, U, U, nullptr, +1, true, false, st);
+    periods += o.runup;
+    if (u0 || o.runup > 0) {
         gradient(R);
     } else {
-        launch_zero(U, db, st);
         launch_axpby(-1.0, Gs, 0.0, Gs, R, n, st);  // R0 = -G*
     }
     CMCG_HIP(hipMemcpyAsync(D, R, db, hipMemcpyDeviceToDevice, st));
@@ -653,6 +659,7 @@ void CgRun::complete() {
             S.dt = c.dt;
             S.rel_res = rel;
             S.J0 = J0;
+            S.res0 = std::sqrt(rr0);
             S.seconds = secs();
             S.seconds_to_1e6 = t6;
             S.dof_updates = (double)n * c.M * periods;
