@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 reference solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default stage-kernel variant instead of autotuning it in the warm-up solve")
     ap.add_argument("--cpu-steps", type=int, default=4, help="RK steps of the CPU oracle sample")
     ap.add_argument("--kernel-periods", type=int, default=3)
     ap.add_argument("--workload", choices=["large_single", "batched", "serving", "scatterer", "fw"],
@@ -159,7 +161,7 @@ def batched(a):
     probs = [cmcg.cmcg_problem_create(s, w.eps, w.mu, None, w.omega,
                                       inputs.gaussian_current(nodes, w.centre, w.width, w.pol)) for w in ws]
     info = cmcg.cmcg_space_info(s)
-    opts = cmcg.cmcg_options_default(tol=a.tol, max_iter=2000)
+    opts = cmcg.cmcg_options_default(tol=a.tol, max_iter=2000, autotune=0 if a.no_autotune else 1)
     t_ref = [time.perf_counter()]
 
     def progress(it, rel):
@@ -189,7 +191,8 @@ def batched(a):
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"batched: {a.members} solves on the {info['K']}-tet P2 mesh, omega in [2pi,6pi], "
                                   f"FP32 fields, CMCG to {a.tol:g} + filter", "members": a.members, "K": info["K"],
-                      "q": 2, "steps_per_period_min": min(Ms), "steps_per_period_max": max(Ms)},
+                      "q": 2, "steps_per_period_min": min(Ms), "steps_per_period_max": max(Ms),
+                      "stage_variant": cmcg.cmcg_tune_get_stage(2, cmcg.CMCG_FP32), "autotuned": not a.no_autotune},
            "cmcg": {"iters_min": min(st["iters"] for st in sts), "iters_max": max(st["iters"] for st in sts),
                     "time_to_1e-6_all_members_s": max(st["seconds_to_1e6"] for st in sts),
                     "seconds": sts[0]["seconds"]},
@@ -224,7 +227,7 @@ def scatterer(a):
     del jd, nodes
     info = cmcg.cmcg_space_info(s)
     K, Np = info["K"], info["Np"]
-    opts = cmcg.cmcg_options_default(fixed_iters=a.cg_iters)
+    opts = cmcg.cmcg_options_default(fixed_iters=a.cg_iters, autotune=0 if a.no_autotune else 1)
     M, dt = cmcg.cmcg_problem_steps(p, opts)
     log(f"scatterer K={K} Np={Np} M={M}")
     t_ref = [time.perf_counter()]
@@ -234,6 +237,9 @@ def scatterer(a):
         return False
 
     opts.set_progress(progress)
+    if not a.no_autotune:  # outside the timed region (the solve reuses the cached choice)
+        v, us = cmcg.cmcg_autotune_stage(p, opts)
+        log(f"autotuned stage variant {v}: us per launch {[round(u, 1) for u in us]}")
     U0 = torch.randn((K, 6, Np), dtype=torch.float64, device=dev) * 1e-3
     UT = torch.empty_like(U0)
     cmcg.cmcg_debug_period(p, U0, UT, 1, False, opts=opts)  # builds the period's graph
@@ -260,7 +266,8 @@ def scatterer(a):
            "config": {"workload": f"scatterer: 64^3x6 = {K} tets, P2, eps = 4 in the sphere |x - c| < 1/4 "
                                   f"(103392 tets), omega = 8 pi, source width 0.03 at (0.15,0.5,0.5); "
                                   f"CMCG {a.cg_iters} iterations + filter period", "K": K, "q": w.q,
-                      "steps_per_period": M},
+                      "steps_per_period": M, "stage_variant": cmcg.cmcg_tune_get_stage(w.q, cmcg.CMCG_FP32),
+                      "autotuned": not a.no_autotune},
            "cmcg": {"iters": st["iters"], "periods": st["periods"], "rel_res": st["rel_res"]},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kname,
@@ -421,7 +428,7 @@ def main():
     s32, p32 = make(cmcg.CMCG_FP32)
     info = cmcg.cmcg_space_info(s32)
     K, Np, ndof = info["K"], info["Np"], info["ndof"]
-    opts = cmcg.cmcg_options_default(tol=a.tol, max_iter=2000)
+    opts = cmcg.cmcg_options_default(tol=a.tol, max_iter=2000, autotune=0 if a.no_autotune else 1)
     M, dt = cmcg.cmcg_problem_steps(p32, opts)
     stream = torch.cuda.current_stream()
 
@@ -486,7 +493,8 @@ def main():
                                f"mu=1, omega=4pi, impedance boundary, Gaussian e_z source width 0.05; "
                                f"CMCG to rel. residual {a.tol:g} + filter period",
                    "K": K, "q": w.q, "ndof": ndof, "steps_per_period": M, "fields": "fp32",
-                   "cg": "fp64"},
+                   "cg": "fp64", "stage_variant": cmcg.cmcg_tune_get_stage(w.q, cmcg.CMCG_FP32),
+                   "autotuned": not a.no_autotune},
         "cmcg": {"iters": stats[-1]["iters"], "periods": stats[-1]["periods"],
                  "rel_res": stats[-1]["rel_res"], "seconds": stats[-1]["seconds"],
                  "time_to_1e-6_fp32_s": stats[-1]["seconds_to_1e6"]},

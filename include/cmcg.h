@@ -114,11 +114,18 @@ typedef struct cmcg_options {
      * starts from their end state; the periods count in stats.periods.  0 =
      * none (the paper's zero initialisation); < 0 is CMCG_ERR_ARG. */
     int runup;
+    /* 1: before its first period the solve picks the stage-kernel variant with
+     * the autotuner (cmcg_autotune_stage; batched solves time the batched
+     * launch), once per (device, q, precision, K, members) in the process,
+     * and keeps it as the process-wide choice for (q, precision).  The
+     * serving engine ignores it (slots run concurrently; tune beforehand).
+     * 0 = keep the current choice. */
+    int autotune;
 } cmcg_options;
 
 /* Fills *o with defaults: tol 1e-8, max_iter 1000, fixed_iters 0, cfl 0,
  * steps 0, scheme AUTO, flux UPWIND, use_graph 1, residual_refresh 0,
- * progress NULL, runup 0. */
+ * progress NULL, runup 0, autotune 0. */
 void cmcg_options_default(cmcg_options* o);
 
 /* Solve statistics. */
@@ -337,6 +344,20 @@ int cmcg_engine_info(const cmcg_engine* e, size_t* used, int* n_running, int* n_
  * variant.  cmcg_tune_get_stage reports the current choice. */
 int cmcg_tune_stage(int q, int precision, int variant);
 int cmcg_tune_get_stage(int q, int precision, int* variant);
+
+/* Autotuner: times every stage-kernel variant that applies to p's (q,
+ * precision) on p's own launch shape -- up to 8 homogeneous time steps on
+ * its mesh and work buffers (o's scheme and step rule; o may be NULL), one
+ * warm-up run and the best of two timed runs (HIP events on `stream`) per
+ * variant -- keeps the fastest as the process-wide choice for (q, precision)
+ * (as cmcg_tune_stage does) and returns it in *variant.  us_per_launch
+ * (nullable, 4 entries) receives each variant's average stage-launch time in
+ * microseconds, 0 for variants that do not apply.  Overwrites p's work
+ * buffers, not its data; must not overlap a solve of p or any solve of the
+ * same (q, precision).  Errors: CMCG_ERR_ARG (NULL p or variant), device
+ * errors as CMCG_ERR_DEVICE. */
+int cmcg_autotune_stage(cmcg_problem* p, const cmcg_options* o, hipStream_t stream, int* variant,
+                        double* us_per_launch);
 
 #ifdef __cplusplus
 }

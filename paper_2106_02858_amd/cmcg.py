@@ -45,6 +45,7 @@ EXPORTED = [
     "cmcg_solve", "cmcg_fw_solve", "cmcg_solve_batch", "cmcg_result_fields", "cmcg_result_filtered_device", "cmcg_result_initial_device",
     "cmcg_result_stats", "cmcg_result_history", "cmcg_result_destroy",
     "cmcg_debug_rhs", "cmcg_debug_period", "cmcg_debug_dot", "cmcg_tune_stage", "cmcg_tune_get_stage",
+    "cmcg_autotune_stage",
     "cmcg_problem_footprint", "cmcg_engine_create", "cmcg_engine_destroy", "cmcg_engine_admit",
     "cmcg_engine_step", "cmcg_engine_poll", "cmcg_engine_collect", "cmcg_engine_cancel", "cmcg_engine_info",
 ]
@@ -57,7 +58,7 @@ class cmcg_options(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("cfl", C.c_double),
                 ("steps", C.c_int), ("scheme", C.c_int), ("flux", C.c_int), ("use_graph", C.c_int),
                 ("residual_refresh", C.c_int), ("progress", PROGRESS_FN), ("progress_ctx", C.c_void_p),
-                ("runup", C.c_int)]
+                ("runup", C.c_int), ("autotune", C.c_int)]
 
     def set_progress(self, fn):
         """fn(iter, rel_res) -> bool (True stops the iteration)."""
@@ -118,6 +119,8 @@ _sig = {
     "cmcg_engine_cancel": (C.c_int, [P, C.c_int]),
     "cmcg_engine_info": (C.c_int, [P, C.POINTER(C.c_size_t), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "cmcg_tune_get_stage": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
+    "cmcg_autotune_stage": (C.c_int, [P, C.POINTER(cmcg_options), C.c_void_p, C.POINTER(C.c_int),
+                                      C.POINTER(C.c_double)]),
 }
 for _n, (_r, _a) in _sig.items():
     _f = getattr(_lib, _n)
@@ -387,6 +390,15 @@ def cmcg_tune_get_stage(q: int, precision: int) -> int:
     v = C.c_int()
     _check(_lib.cmcg_tune_get_stage(q, precision, C.byref(v)))
     return v.value
+
+
+def cmcg_autotune_stage(p: Problem, opts: cmcg_options | None = None, stream=None):
+    """(chosen variant, [microseconds per stage launch of variants 0..3, 0 = not applicable])."""
+    o = opts or cmcg_options_default()
+    v = C.c_int()
+    us = (C.c_double * 4)()
+    _check(_lib.cmcg_autotune_stage(p.h, C.byref(o), _stream(stream), C.byref(v), us))
+    return v.value, list(us)
 
 
 class Engine(_Handle):

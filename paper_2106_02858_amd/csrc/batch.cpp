@@ -385,6 +385,25 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
     build_table(bt);
     std::vector<int> act(B, 1);
     set_active(bt, act, st);
+    if (o->autotune && !apply_tuned_variant(s.device, s.q, s.precision, K, B)) {
+        // time the stage variants on up to 8 homogeneous steps of the batched launch
+        double us[kStageVariants];
+        const int save = bt.Mmax, Mt = std::min(save, 8);
+        launch_zero(bt.U.p, bt.U.bytes, st);
+        if (bt.Ulo.p) launch_zero(bt.Ulo.p, bt.Ulo.bytes, st);
+        int v;
+        try {
+            v = time_stage_variants(s.q, s.precision, st, [&] {
+                bt.Mmax = Mt;
+                enqueue_batch_period(bt, false, false, st);
+                bt.Mmax = save;
+            }, Mt * bt.S, us);
+        } catch (...) {
+            bt.Mmax = save;
+            throw;
+        }
+        remember_tuned_variant(s.device, s.q, s.precision, K, B, v);
+    }
 
     double *U = bt.vu.as<double>(), *R = bt.vr.as<double>(), *D = bt.vd.as<double>(), *A = bt.va.as<double>(),
            *W = bt.vw.as<double>(), *Gs = bt.vgs.as<double>();

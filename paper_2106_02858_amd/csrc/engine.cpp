@@ -122,8 +122,10 @@ int cmcg_engine_admit(cmcg_engine* e, cmcg_problem* p, const cmcg_options* o, in
     const size_t need = footprint(p);
     if (e->used + need > e->budget) fail(CMCG_ERR_NOMEM, "engine_admit: over the memory budget");
     auto& s = e->slots[free_slot];
+    cmcg_options oe = *o;
+    oe.autotune = 0;  // the stage variant is process-wide and slots run concurrently
     s.run.reset(new CgRun());
-    s.run->start(p, o, nullptr, s.st);
+    s.run->start(p, &oe, nullptr, s.st);
     s.state = 1;
     s.p = p;
     s.bytes = need;

@@ -4,6 +4,7 @@
 
 #include <chrono>
 #include <complex>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -147,6 +148,17 @@ struct CgRun {
 // one seen has left the range its arithmetic resolves: it stops, returns the
 // best iterate and reports CMCG_NOT_CONVERGED.
 constexpr double kDivergence = 100.0;
+
+// Stage-variant autotuner (solver.cpp): runs `run` (which enqueues
+// `nlaunch` stage launches, the same ones each call) under every variant that
+// applies to (q, precision), keeps the fastest as the process-wide choice and
+// returns it; us[v] = average microseconds per launch, 0 where v does not apply.
+int time_stage_variants(int q, int precision, hipStream_t st, const std::function<void()>& run, int nlaunch,
+                        double* us);
+// Cached choice for (device, q, precision, K, members): applies it and returns
+// true, or returns false when that shape has not been tuned in this process.
+bool apply_tuned_variant(int device, int q, int precision, int64_t K, int members);
+void remember_tuned_variant(int device, int q, int precision, int64_t K, int members, int variant);
 
 // helpers defined in solver.cpp
 void ensure_constants(int device, int q);

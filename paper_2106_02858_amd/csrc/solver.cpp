@@ -10,6 +10,7 @@
 #include <mutex>
 
 #include <array>
+#include <tuple>
 
 #include "objects.h"
 
@@ -497,6 +498,98 @@ static void dot_async(cmcg_problem* p, const double* U, const double* V, int k, 
     CMCG_HIP(hipMemcpyAsync(p->pinned->p + k, p->scal.as<double>() + k, 8, hipMemcpyDeviceToHost, st));
 }
 
+// ----------------------------------------------------------------- autotuner
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int64_t, int>, int> g_tuned;
+
+bool variant_applies(int q, int precision, int v) { return v <= 1 || (precision == CMCG_FP32 && q >= 2); }
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    EventPair() {
+        CMCG_HIP(hipEventCreate(&a));
+        CMCG_HIP(hipEventCreate(&b));
+    }
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+}  // namespace
+
+int time_stage_variants(int q, int precision, hipStream_t st, const std::function<void()>& run, int nlaunch,
+                        double* us) {
+    EventPair ev;
+    const int old = get_stage_variant(q, precision);
+    int best = old;
+    double best_us = HUGE_VAL;
+    try {
+        for (int v = 0; v < kStageVariants; ++v) {
+            us[v] = 0.0;
+            if (!variant_applies(q, precision, v)) continue;
+            set_stage_variant(q, precision, v);
+            run();  // warm-up (first launches, caches)
+            float tmin = HUGE_VALF;
+            for (int rep = 0; rep < 2; ++rep) {
+                CMCG_HIP(hipEventRecord(ev.a, st));
+                run();
+                CMCG_HIP(hipEventRecord(ev.b, st));
+                CMCG_HIP(hipEventSynchronize(ev.b));
+                float ms = 0.f;
+                CMCG_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+                tmin = std::fmin(tmin, ms);
+            }
+            us[v] = 1e3 * tmin / nlaunch;
+            if (us[v] < best_us) {
+                best_us = us[v];
+                best = v;
+            }
+        }
+    } catch (...) {
+        set_stage_variant(q, precision, old);
+        throw;
+    }
+    set_stage_variant(q, precision, best);
+    return best;
+}
+
+bool apply_tuned_variant(int device, int q, int precision, int64_t K, int members) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(std::make_tuple(device, q, precision, K, members));
+    if (it == g_tuned.end()) return false;
+    set_stage_variant(q, precision, it->second);
+    return true;
+}
+
+void remember_tuned_variant(int device, int q, int precision, int64_t K, int members, int variant) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_tuple(device, q, precision, K, members)] = variant;
+}
+
+// Times the variants on up to 8 homogeneous steps of p's own mesh (its work
+// buffers, zeroed first).
+static int autotune_problem(cmcg_problem* p, const StepCfg& c, hipStream_t st, double* us) {
+    const SpaceData& s = *p->sp;
+    StepCfg ct = c;
+    ct.M = std::min(c.M, 8);
+    launch_zero(p->U.p, p->U.bytes, st);
+    if (p->Ulo.p) launch_zero(p->Ulo.p, p->Ulo.bytes, st);
+    const int nlaunch = ct.M * (c.scheme == 4 ? 4 : 2);
+    const int v = time_stage_variants(s.q, s.precision, st, [&] { enqueue_period(p, ct, false, false, st); },
+                                      nlaunch, us);
+    remember_tuned_variant(s.device, s.q, s.precision, s.K, 1, v);
+    return v;
+}
+
+static void maybe_autotune(cmcg_problem* p, const cmcg_options* o, const StepCfg& c, hipStream_t st) {
+    if (!o->autotune) return;
+    const SpaceData& s = *p->sp;
+    if (apply_tuned_variant(s.device, s.q, s.precision, s.K, 1)) return;
+    double us[kStageVariants];
+    autotune_problem(p, c, st, us);
+}
+
 // --------------------------------------------------------- CMCG state machine
 // Algorithm 3 as a sequence of asynchronous chunks: start() enqueues
 // Algorithm 1 and the first inner products; every complete() (called once the
@@ -511,6 +604,7 @@ void CgRun::start(cmcg_problem* pr, const cmcg_options* opt, const double* u0_, 
     if (o.runup < 0) fail(CMCG_ERR_ARG, "options: runup must be >= 0");
     c = step_config(p, &o);
     prepare(p, c);
+    maybe_autotune(p, &o, c, st);
     const SpaceData& s = *p->sp;
     n = s.ndof;
     const size_t db = n * 8;
@@ -679,6 +773,7 @@ void CgRun::complete() {
 cmcg_result* fw_solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st) {
     const StepCfg c = step_config(p, o);
     prepare(p, c);
+    maybe_autotune(p, o, c, st);
     const SpaceData& s = *p->sp;
     const int64_t n = s.ndof;
     const size_t db = n * 8;
@@ -1144,6 +1239,23 @@ int cmcg_tune_stage(int q, int precision, int variant) {
         variant >= kStageVariants)
         fail(CMCG_ERR_ARG, "tune_stage: bad q, precision or variant");
     set_stage_variant(q, precision, variant);
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_autotune_stage(cmcg_problem* p, const cmcg_options* o, hipStream_t stream, int* variant,
+                        double* us_per_launch) {
+    CMCG_GUARD_BEGIN
+    if (!p || !variant) fail(CMCG_ERR_ARG, "autotune_stage: NULL argument");
+    cmcg_options def;
+    cmcg_options_default(&def);
+    if (!o) o = &def;
+    const StepCfg c = step_config(p, o);
+    prepare(p, c);
+    double us[kStageVariants];
+    *variant = autotune_problem(p, c, stream, us);
+    if (us_per_launch)
+        for (int v = 0; v < kStageVariants; ++v) us_per_launch[v] = us[v];
     return CMCG_OK;
     CMCG_GUARD_END
 }
