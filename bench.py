@@ -52,6 +52,8 @@ def parse():
                     help="large_single (default bench line), the 64-member batched configuration, or the "
                          "Poisson request stream through the serving engine")
     ap.add_argument("--members", type=int, default=64)
+    ap.add_argument("--fp64-members", type=int, default=64,
+                    help="batched: members also solved one by one with plain FP64 fields (0: none)")
     ap.add_argument("--cg-iters", type=int, default=6, help="scatterer: CG iterations of the timed solve")
     ap.add_argument("--fw-walls", choices=["impedance", "pec"], default="impedance",
                     help="fw: walls of the comparison problem (pec: closed cavity)")
@@ -197,6 +199,26 @@ def batched(a):
                     "time_to_1e-6_all_members_s": max(st["seconds_to_1e6"] for st in sts),
                     "seconds": sts[0]["seconds"]},
            "hbm_job": job_roofline(dof / el, bytes_per_dof_update(2, 4, a.members))}
+    if a.fp64_members > 0:
+        # the plain FP64 form on the same problems: one solve after another
+        s64 = cmcg.cmcg_space_create(mesh, w0.q, cmcg.CMCG_FP64)
+        nodes64 = cmcg.cmcg_space_nodes(s64)
+        o64 = cmcg.cmcg_options_default(tol=a.tol, max_iter=2000, autotune=0 if a.no_autotune else 1)
+        t6, tall, it64 = [], [], []
+        for b, w in enumerate(ws[:a.fp64_members]):
+            p64 = cmcg.cmcg_problem_create(s64, w.eps, w.mu, None, w.omega,
+                                           inputs.gaussian_current(nodes64, w.centre, w.width, w.pol))
+            st = cmcg.cmcg_result_stats(cmcg.cmcg_solve(p64, o64))
+            t6.append(st["seconds_to_1e6"])
+            tall.append(st["seconds"])
+            it64.append(st["iters"])
+            if b % 16 == 15:
+                log(f"fp64 member {b + 1}: time-to-1e-6 so far {sum(t6):.2f} s")
+        out["fp64_plain"] = {"members": len(t6), "mode": "one plain FP64 solve after another",
+                             "time_to_1e-6_sum_s": sum(t6), "seconds_sum": sum(tall),
+                             "iters_min": min(it64), "iters_max": max(it64)}
+        log(f"fp64 plain, {len(t6)} members one by one: time-to-1e-6 {sum(t6):.2f} s "
+            f"(batched FP32: {out['cmcg']['time_to_1e-6_all_members_s']:.2f} s)")
     print(json.dumps(out), flush=True)
 
 
@@ -204,7 +226,34 @@ def job_roofline(rate: float, bpd: float) -> dict:
     """Whole-job HBM fraction: dof-updates/s x algorithmic bytes per dof-update
     (CG vector work and idle members count as time, not as bytes)."""
     gbs = rate * bpd / 1e9
-    return {"bytes_per_dof_update": bpd, "achieved_GBs": gbs, "peak_GBs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}
+    cp = stream_copy_gbs()
+    return {"bytes_per_dof_update": bpd, "achieved_GBs": gbs, "peak_GBs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS,
+            "copy_GBs": cp, "frac_of_copy": gbs / cp}
+
+
+_COPY_GBS = []
+
+
+def stream_copy_gbs(nbytes: int = 1 << 30) -> float:
+    """Bandwidth of a plain device-to-device copy of 1 GiB (read + write
+    bytes over the best of 5 timed copies): the practical HBM ceiling."""
+    if _COPY_GBS:
+        return _COPY_GBS[0]
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    best = float("inf")
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del x, y
+    _COPY_GBS.append(2 * nbytes / best / 1e9)
+    return _COPY_GBS[0]
 
 
 def scatterer(a):
@@ -271,7 +320,8 @@ def scatterer(a):
            "cmcg": {"iters": st["iters"], "periods": st["periods"], "rel_res": st["rel_res"]},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kname,
-                        "avg_launch_us": per_launch * 1e6, "bytes_per_launch": bpe * K},
+                        "avg_launch_us": per_launch * 1e6, "bytes_per_launch": bpe * K,
+                        "copy_GBs": stream_copy_gbs(), "frac_of_copy": achieved / stream_copy_gbs()},
            "hbm_job": job_roofline(st["dof_updates"] / el, bytes_per_dof_update(w.q, 4))}
     print(json.dumps(out), flush=True)
 
@@ -502,7 +552,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, K),
                      "kernel": kname,
                      "avg_launch_us": per_launch_s * 1e6,
-                     "bytes_per_launch": bpe * K},
+                     "bytes_per_launch": bpe * K,
+                     "copy_GBs": stream_copy_gbs(), "frac_of_copy": achieved / stream_copy_gbs()},
     }
     if not a.no_fp64:
         s64, p64 = make(cmcg.CMCG_FP64)
