@@ -1,5 +1,5 @@
-"""Period filters F U = (2/T) int_0^T U(t) e^{-i omega t} dt (eq. 2.x, filter
-definition in Section 2.1; quadratures of Section 5.4).
+"""Period filters F U = (2/T) int_0^T U(t) e^{-i omega t} dt (the filtering
+operator of Section 4.1; quadratures of Section 5.4).
 
 * trapezoid rule, paired with RK2 (eq. of the RK2 filter);
 * cubic-Hermite quadrature, paired with RK4: on [t_{m-1}, t_m] the field is
