@@ -155,9 +155,10 @@ const char* cmcg_version(void);
  *   face_tag     [K][4] (local face f opposite local vertex f): for boundary
  *                faces CMCG_TAG_PEC or CMCG_TAG_IMPEDANCE; ignored on interior
  *                faces.  NULL tags every boundary face impedance.
- * Errors: CMCG_ERR_ARG (NULL, nv < 4, K < 1, index out of range),
- * CMCG_ERR_MESH (zero volume, a face shared by more than two elements, an
- * untagged boundary face). */
+ * Errors: CMCG_ERR_ARG (NULL, nv < 4, K < 1, K >= 2^26 -- the neighbour
+ * index shares a 32-bit connectivity word with the face and permutation
+ * codes --, index out of range), CMCG_ERR_MESH (zero volume, a face shared by
+ * more than two elements, an untagged boundary face). */
 int cmcg_mesh_create(int64_t nv, const double* xyz, int64_t K, const int64_t* tet,
                      const int8_t* face_tag, cmcg_mesh** out);
 void cmcg_mesh_destroy(cmcg_mesh* m);

@@ -214,3 +214,112 @@ def test_solve_on_a_caller_stream(lib):
     torch.cuda.synchronize()
     assert float(out[2].abs().max()) > 0
     assert torch.equal(out[0], out[2]) and torch.equal(out[1], out[3])
+
+
+def _shuffled_mesh(n, seed):
+    """cube_mesh(n) with a random element order, random vertex numbering,
+    an orientation-preserving (even) permutation of every tetrahedron's
+    vertices and a random mix of PEC and impedance boundary faces: element
+    blocks then hold unrelated elements, so nearly every neighbour trace comes
+    from another block."""
+    xyz, tet, tags = inputs.cube_mesh(n)
+    rng = np.random.default_rng(seed)
+    K, nv = tet.shape[0], xyz.shape[0]
+    tags = tags.copy()
+    tags[(tags > 0) & (rng.random(tags.shape) < 0.4)] = inputs.TAG_PEC
+    order = rng.permutation(K)
+    tet, tags = tet[order], tags[order]
+    vnew = rng.permutation(nv)
+    xyz2 = np.empty_like(xyz)
+    xyz2[vnew] = xyz
+    tet = vnew[tet]
+    even = [p for p in __import__("itertools").permutations(range(4))
+            if sum(p[i] > p[j] for i in range(4) for j in range(i + 1, 4)) % 2 == 0]
+    pick = rng.integers(0, len(even), K)
+    sig = np.array(even)[pick]                      # new local vertex i = old local vertex sig[i]
+    tet = np.take_along_axis(tet, sig, axis=1)
+    tags = np.take_along_axis(tags, sig, axis=1)    # face i is opposite vertex i
+    return xyz2, np.ascontiguousarray(tet), np.ascontiguousarray(tags)
+
+
+@pytest.mark.parametrize("q,precision,v", [(1, 0, 0), (1, 1, 1), (2, 1, 3), (3, 1, 3), (3, 0, 1)])
+def test_rhs_on_shuffled_mesh(lib, q, precision, v):
+    print(f"shuffled mesh rhs q={q} prec={precision} variant={v}", flush=True)
+    old = lib.cmcg_tune_get_stage(q, precision)
+    lib.cmcg_tune_stage(q, precision, v)
+    try:
+        xyz, tet, tags = _shuffled_mesh(3, seed=50 + q)
+        K = tet.shape[0]
+        rng = np.random.default_rng(60 + q)
+        eps = rng.choice([1.0, 2.0, 4.0], K)
+        p0 = dg.make_problem(xyz, tet, tags, q, eps, np.ones(K))
+        j = inputs.gaussian_current(p0.geo.x, (0.4, 0.5, 0.6), 0.3, 2)
+        op = dg.make_problem(xyz, tet, tags, q, eps, np.ones(K), sigma=rng.uniform(0, 0.5, K), j=j)
+        s, lp = lib_problem(lib, op, precision, xyz, tet, tags)
+        import torch
+        U = rng.standard_normal((K, 6, op.Np))
+        out = torch.zeros((K, 6, op.Np), dtype=torch.float64, device="cuda")
+        lib.cmcg_debug_rhs(lp, torch.tensor(U, device="cuda"), out, t=0.21, with_source=True)
+        ref = dg.phi(op, 0.21, U, with_source=True)
+        err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(np.abs(ref))
+        print(f"  rel err {err:.2e}")
+        assert err < (1e-12 if precision == 0 else 1e-5)
+    finally:
+        lib.cmcg_tune_stage(q, precision, old)
+
+
+def test_cmcg_on_shuffled_mesh(lib):
+    xyz, tet, tags = _shuffled_mesh(2, seed=71)
+    K = tet.shape[0]
+    p0 = dg.make_problem(xyz, tet, tags, 1, np.ones(K), np.ones(K))
+    j = inputs.gaussian_current(p0.geo.x, (0.5, 0.5, 0.5), 0.3, 1)
+    op = dg.make_problem(xyz, tet, tags, 1, np.ones(K), np.ones(K), j=j)
+    s, lp = lib_problem(lib, op, 0, xyz, tet, tags)
+    ref = ocmcg.solve(op, fixed_iters=4)
+    r = lib.cmcg_solve(lp, lib.cmcg_options_default(fixed_iters=4))
+    import torch
+    fr = torch.zeros((K, 6, op.Np), dtype=torch.float64, device="cuda")
+    fi = torch.zeros_like(fr)
+    lib.cmcg_result_filtered_device(r, fr, fi)
+    assert rel_norm_c(op, fr.cpu().numpy() + 1j * fi.cpu().numpy(), ref.F) < 1e-11
+
+
+def test_concurrent_solves_from_two_threads(lib):
+    """Two host threads solve different problems (different orders and
+    precisions) at the same time, each on its own stream; each result equals
+    the same solve run alone."""
+    import threading
+    import torch
+    specs = [(1, 2), (0, 3), (1, 1)]
+    probs = [_small_problem(lib, precision=p, q=q) for p, q in specs]
+    o = lib.cmcg_options_default(fixed_iters=4)
+
+    def fields(r, s):
+        info = lib.cmcg_space_info(s)
+        f = [torch.zeros((info["K"], 6, info["Np"]), dtype=torch.float64, device="cuda") for _ in range(2)]
+        lib.cmcg_result_filtered_device(r, *f)
+        torch.cuda.synchronize()
+        return [x.cpu() for x in f]
+
+    alone = [fields(lib.cmcg_solve(p, o), s) for p, s in probs]
+    results, errors = [None] * len(probs), []
+
+    def work(i):
+        try:
+            torch.cuda.set_device(0)
+            st = torch.cuda.Stream()
+            for _ in range(2):
+                results[i] = lib.cmcg_solve(probs[i][0], o, stream=st)
+            st.synchronize()
+        except Exception as ex:  # reported below
+            errors.append(ex)
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(len(probs))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not errors and all(not t.is_alive() for t in threads)
+    for (p, s), r, a in zip(probs, results, alone):
+        b = fields(r, s)
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
