@@ -159,6 +159,20 @@ const char* cmcg_version(void);
  * index shares a 32-bit connectivity word with the face and permutation
  * codes --, index out of range), CMCG_ERR_MESH (zero volume, a face shared by
  * more than two elements, an untagged boundary face). */
+/* Element order for locality (host only, no device work): order[K] receives
+ * a permutation of 0..K-1 that sorts the element centroids along a Morton
+ * (Z-order) curve over their bounding cube, 21 bits per axis, ties kept in
+ * input order.  The stage kernels process elements in blocks of consecutive
+ * indices and read face neighbours through the caches, so a mesh whose
+ * elements are numbered without spatial locality runs slower (a randomly
+ * numbered 384000-tet cube: +15% P3, +17% P2 per stage); creating the mesh
+ * from tet[order[i]] (with face_tag[order[i]] and every per-element input
+ * permuted alike) restores the locality.  The library never reorders
+ * elements itself: its arrays keep the caller's element order.
+ * Errors: CMCG_ERR_ARG (NULL, nv < 1, K < 1, index out of range, non-finite
+ * coordinates). */
+int cmcg_mesh_locality_order(int64_t nv, const double* xyz, int64_t K, const int64_t* tet, int64_t* order);
+
 int cmcg_mesh_create(int64_t nv, const double* xyz, int64_t K, const int64_t* tet,
                      const int8_t* face_tag, cmcg_mesh** out);
 void cmcg_mesh_destroy(cmcg_mesh* m);

@@ -45,7 +45,7 @@ EXPORTED = [
     "cmcg_solve", "cmcg_fw_solve", "cmcg_solve_batch", "cmcg_result_fields", "cmcg_result_filtered_device", "cmcg_result_initial_device",
     "cmcg_result_stats", "cmcg_result_history", "cmcg_result_destroy",
     "cmcg_debug_rhs", "cmcg_debug_period", "cmcg_debug_dot", "cmcg_tune_stage", "cmcg_tune_get_stage",
-    "cmcg_autotune_stage",
+    "cmcg_autotune_stage", "cmcg_mesh_locality_order",
     "cmcg_problem_footprint", "cmcg_engine_create", "cmcg_engine_destroy", "cmcg_engine_admit",
     "cmcg_engine_step", "cmcg_engine_poll", "cmcg_engine_collect", "cmcg_engine_cancel", "cmcg_engine_info",
 ]
@@ -118,6 +118,7 @@ _sig = {
     "cmcg_engine_collect": (C.c_int, [P, C.c_int, C.POINTER(P)]),
     "cmcg_engine_cancel": (C.c_int, [P, C.c_int]),
     "cmcg_engine_info": (C.c_int, [P, C.POINTER(C.c_size_t), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "cmcg_mesh_locality_order": (C.c_int, [C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "cmcg_tune_get_stage": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
     "cmcg_autotune_stage": (C.c_int, [P, C.POINTER(cmcg_options), C.c_void_p, C.POINTER(C.c_int),
                                       C.POINTER(C.c_double)]),
@@ -390,6 +391,16 @@ def cmcg_tune_get_stage(q: int, precision: int) -> int:
     v = C.c_int()
     _check(_lib.cmcg_tune_get_stage(q, precision, C.byref(v)))
     return v.value
+
+
+def cmcg_mesh_locality_order(xyz, tet) -> np.ndarray:
+    """Permutation of the elements along a Morton curve of their centroids:
+    build the mesh from tet[order] (and permute every per-element input alike)."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tet = np.ascontiguousarray(tet, dtype=np.int64)
+    order = np.empty(tet.shape[0], dtype=np.int64)
+    _check(_lib.cmcg_mesh_locality_order(xyz.shape[0], _ptr(xyz), tet.shape[0], _ptr(tet), _ptr(order)))
+    return order
 
 
 def cmcg_autotune_stage(p: Problem, opts: cmcg_options | None = None, stream=None):

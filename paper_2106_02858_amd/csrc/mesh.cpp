@@ -7,7 +7,9 @@
 // one of the six triangle vertex permutations.  Normals and face areas come
 // from the gradients of the barycentric coordinates: n_f = -grad(lambda_f) /
 // |grad(lambda_f)|, area_f = 3 |K| |grad(lambda_f)|.
+#include <algorithm>
 #include <cmath>
+#include <numeric>
 #include <unordered_map>
 
 #include "internal.h"
@@ -36,6 +38,46 @@ void face_vertices(int f, int w[3]) {
 }
 
 }  // namespace
+
+// Spreads the low 21 bits of x to every third bit (Morton interleave).
+static uint64_t spread3(uint64_t x) {
+    x &= 0x1fffffull;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+
+void locality_order(int64_t nv, const double* xyz, int64_t K, const int64_t* tet, int64_t* order) {
+    if (!xyz || !tet || !order) fail(CMCG_ERR_ARG, "locality_order: NULL argument");
+    if (nv < 1 || K < 1) fail(CMCG_ERR_ARG, "locality_order: need nv >= 1 and K >= 1");
+    for (int64_t i = 0; i < 4 * K; ++i)
+        if (tet[i] < 0 || tet[i] >= nv) fail(CMCG_ERR_ARG, "locality_order: vertex index out of range");
+    double lo[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL}, hi[3] = {-HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+    std::vector<double> c(3 * K);
+    for (int64_t e = 0; e < K; ++e)
+        for (int d = 0; d < 3; ++d) {
+            double s = 0;
+            for (int v = 0; v < 4; ++v) s += xyz[3 * tet[4 * e + v] + d];
+            c[3 * e + d] = 0.25 * s;
+            if (!std::isfinite(c[3 * e + d])) fail(CMCG_ERR_ARG, "locality_order: non-finite coordinate");
+            lo[d] = std::fmin(lo[d], c[3 * e + d]);
+            hi[d] = std::fmax(hi[d], c[3 * e + d]);
+        }
+    // one scale for all axes keeps the curve's cells cubic
+    const double span = std::fmax(std::fmax(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]);
+    const double sc = span > 0 ? double((1 << 21) - 1) / span : 0.0;
+    std::vector<uint64_t> key(K);
+    for (int64_t e = 0; e < K; ++e) {
+        uint64_t k = 0;
+        for (int d = 0; d < 3; ++d) k |= spread3((uint64_t)((c[3 * e + d] - lo[d]) * sc)) << d;
+        key[e] = k;
+    }
+    std::iota(order, order + K, int64_t(0));
+    std::stable_sort(order, order + K, [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+}
 
 std::shared_ptr<MeshData> build_mesh(int64_t nv, const double* xyz, int64_t K, const int64_t* tet,
                                      const int8_t* face_tag) {

@@ -25,6 +25,7 @@ void set_last_error(const std::string& msg) { g_last_error = msg; }
 
 std::shared_ptr<MeshData> build_mesh(int64_t nv, const double* xyz, int64_t K, const int64_t* tet,
                                      const int8_t* face_tag);
+void locality_order(int64_t nv, const double* xyz, int64_t K, const int64_t* tet, int64_t* order);
 
 // ----------------------------------------------------------- device constants
 namespace {
@@ -894,6 +895,13 @@ int cmcg_mesh_create(int64_t nv, const double* xyz, int64_t K, const int64_t* te
 }
 
 void cmcg_mesh_destroy(cmcg_mesh* m) { delete m; }
+
+int cmcg_mesh_locality_order(int64_t nv, const double* xyz, int64_t K, const int64_t* tet, int64_t* order) {
+    CMCG_GUARD_BEGIN
+    locality_order(nv, xyz, K, tet, order);
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
 
 int cmcg_mesh_info(const cmcg_mesh* m, int64_t* K, int64_t* nb, double* min_rho) {
     CMCG_GUARD_BEGIN

@@ -323,3 +323,26 @@ def test_concurrent_solves_from_two_threads(lib):
     for (p, s), r, a in zip(probs, results, alone):
         b = fields(r, s)
         assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_locality_reordered_mesh_gives_the_same_fields(lib):
+    """Solving on the mesh renumbered by cmcg_mesh_locality_order (every
+    per-element input permuted alike) gives the same fields, permuted."""
+    import torch
+    xyz, tet, tags = _shuffled_mesh(2, seed=81)
+    K = tet.shape[0]
+    order = lib.cmcg_mesh_locality_order(xyz, tet)
+    rng = np.random.default_rng(82)
+    eps = rng.choice([1.0, 2.0, 4.0], K)
+    out = []
+    for perm in (np.arange(K), order):
+        m = lib.cmcg_mesh_create(xyz, np.ascontiguousarray(tet[perm]), np.ascontiguousarray(tags[perm]))
+        s = lib.cmcg_space_create(m, 2, 0)
+        j = inputs.gaussian_current(lib.cmcg_space_nodes(s), (0.4, 0.5, 0.5), 0.3, 0)
+        p = lib.cmcg_problem_create(s, eps[perm], np.ones(K), None, 2 * np.pi, j)
+        r = lib.cmcg_solve(p, lib.cmcg_options_default(fixed_iters=4))
+        f = [torch.zeros((K, 6, 10), dtype=torch.float64, device="cuda") for _ in range(2)]
+        lib.cmcg_result_filtered_device(r, *f)
+        out.append(f[0].cpu().numpy() + 1j * f[1].cpu().numpy())
+    a, b = out[0][order], out[1]
+    assert np.max(np.abs(a - b)) <= 1e-11 * np.max(np.abs(a))
