@@ -266,7 +266,8 @@ int cmcg_fw_solve(cmcg_problem* p, const cmcg_options* o, const double* u0_dev,
  * one result per member (owned by the caller).  Returns CMCG_OK when every
  * member converged, CMCG_NOT_CONVERGED when some stopped at max_iter, or an
  * error (then no results; CMCG_ERR_ARG when the problems do not share a
- * space or a time scheme). */
+ * space or a time scheme, or n > 65535: members are the launch's second grid
+ * dimension). */
 int cmcg_solve_batch(cmcg_problem* const* problems, int n, const cmcg_options* o,
                      hipStream_t stream, cmcg_result** results);
 /* Filtered time-harmonic fields (complex amplitudes at the DG nodes),

@@ -1078,6 +1078,7 @@ int cmcg_solve_batch(cmcg_problem* const* problems, int n, const cmcg_options* o
                      cmcg_result** results) {
     CMCG_GUARD_BEGIN
     if (!results || !problems || n < 1) fail(CMCG_ERR_ARG, "solve_batch: NULL argument or empty batch");
+    if (n > 65535) fail(CMCG_ERR_ARG, "solve_batch: at most 65535 problems per batch");
     for (int b = 0; b < n; ++b) results[b] = nullptr;
     cmcg_options def;
     cmcg_options_default(&def);

@@ -104,3 +104,10 @@ def test_batch_rejects_different_spaces(lib):
     with pytest.raises(lib.CmcgError) as e:
         lib.cmcg_solve_batch([p1[0], p2[0]])
     assert e.value.code == lib.CMCG_ERR_ARG
+
+
+def test_batch_rejects_more_members_than_the_grid_holds(lib):
+    s, p, _, _ = members(lib, 1, 1, 0, 1, seed=3)
+    with pytest.raises(lib.CmcgError) as e:
+        lib.cmcg_solve_batch([p[0]] * 65536)
+    assert e.value.code == lib.CMCG_ERR_ARG
