@@ -100,3 +100,14 @@ def test_mesh_edge_cases_host_only():
     with pytest.raises(cmcg.CmcgError) as e:
         cmcg.cmcg_mesh_create(flat, np.array([[0, 1, 2, 3]]), tags)
     assert e.value.code == cmcg.CMCG_ERR_MESH
+
+
+def test_c_program_links_against_the_library():
+    """The plain-C demo (built with the library) resolves libcmcg through its
+    rpath: the ABI is usable from C without Python."""
+    import subprocess
+    exe = os.path.join(os.path.dirname(__file__), "c_abi", "solve_demo")
+    if not os.path.exists(exe):
+        pytest.skip("library not built")
+    out = subprocess.run(["ldd", exe], capture_output=True, text=True).stdout
+    assert "libcmcg.so" in out and "not found" not in out
