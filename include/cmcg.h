@@ -355,9 +355,11 @@ int cmcg_engine_info(const cmcg_engine* e, size_t* used, int* n_running, int* n_
  * ahead (more registers, more latency hiding), 2 runs the volume and lift
  * products on the matrix cores (FP32 fields, q = 2, 3; other combinations
  * fall back to 0), 3 is 2 with the neighbour traces requested one face
- * ahead.  All compute the same Phi(t, Y) and stage update.  Process-wide;
+ * ahead, 4 is 3 with two waves per 10-element block, each computing one of
+ * the two 16-row output tiles (FP32, q = 3; q = 2 falls back to 3).  All compute the same Phi(t, Y) and stage update.  Process-wide;
  * not thread-safe against concurrent solves.  Returns CMCG_ERR_ARG for an unknown q / precision /
  * variant.  cmcg_tune_get_stage reports the current choice. */
+#define CMCG_STAGE_VARIANTS 5
 int cmcg_tune_stage(int q, int precision, int variant);
 int cmcg_tune_get_stage(int q, int precision, int* variant);
 
@@ -367,8 +369,8 @@ int cmcg_tune_get_stage(int q, int precision, int* variant);
  * warm-up run and the best of two timed runs (HIP events on `stream`) per
  * variant -- keeps the fastest as the process-wide choice for (q, precision)
  * (as cmcg_tune_stage does) and returns it in *variant.  us_per_launch
- * (nullable, 4 entries) receives each variant's average stage-launch time in
- * microseconds, 0 for variants that do not apply.  Overwrites p's work
+ * (nullable, CMCG_STAGE_VARIANTS entries) receives each variant's average
+ * stage-launch time in microseconds, 0 for variants that do not apply.  Overwrites p's work
  * buffers, not its data; must not overlap a solve of p or any solve of the
  * same (q, precision).  Errors: CMCG_ERR_ARG (NULL p or variant), device
  * errors as CMCG_ERR_DEVICE. */

@@ -23,6 +23,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 CMCG_OK = 0
+CMCG_STAGE_VARIANTS = 5  # include/cmcg.h
 CMCG_NOT_CONVERGED = 1
 CMCG_ERR_ARG = -1
 CMCG_ERR_MESH = -2
@@ -404,10 +405,10 @@ def cmcg_mesh_locality_order(xyz, tet) -> np.ndarray:
 
 
 def cmcg_autotune_stage(p: Problem, opts: cmcg_options | None = None, stream=None):
-    """(chosen variant, [microseconds per stage launch of variants 0..3, 0 = not applicable])."""
+    """(chosen variant, [microseconds per stage launch of every variant, 0 = not applicable])."""
     o = opts or cmcg_options_default()
     v = C.c_int()
-    us = (C.c_double * 4)()
+    us = (C.c_double * CMCG_STAGE_VARIANTS)()
     _check(_lib.cmcg_autotune_stage(p.h, C.byref(o), _stream(stream), C.byref(v), us))
     return v.value, list(us)
 

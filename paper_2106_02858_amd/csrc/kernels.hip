@@ -188,14 +188,15 @@ __device__ __forceinline__ bool member_args(const StageArgs& in, StageArgs& a) {
 
 // One chunk's stage input and geometry (16-byte coalesced loads, all issued
 // before the first is consumed) and its connectivity codes; put() stores them
-// in LDS with the stage-input rows padded to NP + 1.
-template <typename T, int Q> struct ChunkIn {
+// in LDS with the stage-input rows padded to NP + 1.  NTH threads share the
+// work (thread index `lane` < NTH).
+template <typename T, int Q, int NTH = 64> struct ChunkIn {
     static constexpr int NP = Dim<Q>::NP;
     static constexpr int PV = 16 / (int)sizeof(T);  // values per load
-    static constexpr int NY = (EPW * 6 * NP / PV + 63) / 64, NG = (EPW * kGeo / PV + 63) / 64;
+    static constexpr int NY = (EPW * 6 * NP / PV + NTH - 1) / NTH, NG = (EPW * kGeo / PV + NTH - 1) / NTH;
     using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
     static_assert((6 * NP) % PV == 0 && kGeo % PV == 0, "rows must split into 16-byte groups");
-    static constexpr int NT = (ft_words(Q) + 63) / 64;  // face-table words per lane
+    static constexpr int NT = (ft_words(Q) + NTH - 1) / NTH;  // face-table words per thread
     V y[NY], g[NG];
     int cd;
     uint32_t tw[NT];
@@ -205,23 +206,23 @@ template <typename T, int Q> struct ChunkIn {
         const V* G4 = reinterpret_cast<const V*>(geo + e0 * kGeo);
 #pragma unroll
         for (int i = 0; i < NT; ++i)
-            if (lane + 64 * i < ft_words(Q)) tw[i] = cFaceTab[ft_off(Q) + lane + 64 * i];
+            if (lane + NTH * i < ft_words(Q)) tw[i] = cFaceTab[ft_off(Q) + lane + NTH * i];
 #pragma unroll
         for (int i = 0; i < NY; ++i)
-            if (lane + 64 * i < ne * 6 * NP / PV) y[i] = Y4[lane + 64 * i];
+            if (lane + NTH * i < ne * 6 * NP / PV) y[i] = Y4[lane + NTH * i];
 #pragma unroll
         for (int i = 0; i < NG; ++i)
-            if (lane + 64 * i < ne * kGeo / PV) g[i] = G4[lane + 64 * i];
+            if (lane + NTH * i < ne * kGeo / PV) g[i] = G4[lane + NTH * i];
         cd = lane < ne * 4 ? conn[e0 * 4 + lane] : -3;
     }
     __device__ __forceinline__ void put(T* sY, T* sG, int* sC, uint8_t* sT, int ne, int lane) const {
         uint32_t* sT4 = reinterpret_cast<uint32_t*>(sT);
 #pragma unroll
         for (int i = 0; i < NT; ++i)
-            if (lane + 64 * i < ft_words(Q)) sT4[lane + 64 * i] = tw[i];
+            if (lane + NTH * i < ft_words(Q)) sT4[lane + NTH * i] = tw[i];
 #pragma unroll
         for (int i = 0; i < NY; ++i) {
-            const int g4 = lane + 64 * i;
+            const int g4 = lane + NTH * i;
             if (g4 < ne * 6 * NP / PV) {
                 const T* t = reinterpret_cast<const T*>(&y[i]);
 #pragma unroll
@@ -234,7 +235,7 @@ template <typename T, int Q> struct ChunkIn {
         V* sG4 = reinterpret_cast<V*>(sG);
 #pragma unroll
         for (int i = 0; i < NG; ++i)
-            if (lane + 64 * i < ne * kGeo / PV) sG4[lane + 64 * i] = g[i];
+            if (lane + NTH * i < ne * kGeo / PV) sG4[lane + NTH * i] = g[i];
         if (lane < ne * 4) sC[lane] = cd;
     }
 };
@@ -646,8 +647,8 @@ struct MfmaShared {
 // the chunk), all requested before the pass computes: r0 = U (stage 2-4
 // modes) or the stage input (stage-1 modes, filter), r1 = Acc, r2 = the
 // bfloat16 low parts.
-template <int Q> struct MfmaUpdateIn {
-    static constexpr int NIT = (EPW * 6 * Dim<Q>::NP / 4 + 63) / 64;
+template <int Q, int NTH = 64> struct MfmaUpdateIn {
+    static constexpr int NIT = (EPW * 6 * Dim<Q>::NP / 4 + NTH - 1) / NTH;
     float4 r0[NIT], r1[NIT];
     uint2 r2[NIT];
     __device__ __forceinline__ void fetch(const StageArgs& a, int64_t base, int nv4, int lane) {
@@ -659,7 +660,7 @@ template <int Q> struct MfmaUpdateIn {
         const float* src0 = needU ? (const float*)a.U : (const float*)a.Y;
 #pragma unroll
         for (int t = 0; t < NIT; ++t) {
-            const int v4 = lane + 64 * t;
+            const int v4 = lane + NTH * t;
             if (v4 >= nv4) continue;
             const int64_t gi = base + 4 * v4;
             if (s1 || needU) r0[t] = *reinterpret_cast<const float4*>(src0 + gi);
@@ -670,21 +671,29 @@ template <int Q> struct MfmaUpdateIn {
 };
 
 // PIPE: the next face's neighbour traces are requested before this face's
-// flux (more registers, the gather latency hides behind the lift).  Register
+// flux (more registers, the gather latency hides behind the lift).
+// W: waves per workgroup.  W = 2 (P3) gives each wave one of the two 16-row
+// output tiles: both waves build the same B operands, each runs half the
+// MFMAs, the flux items and the update pass are shared by 128 threads.  A
+// block's dependent chain gets shorter at 6 waves per SIMD (76 registers),
+// which pays where the launch ends in a partial round of workgroups.  Register
 // allocation is held to 4 waves per SIMD (128 registers; the LDS tiles of
 // MfmaShared<3> stay under 10 KB so 16 workgroups fit a compute unit).
 // Requesting the update operands earlier (with the staging loads, or before
 // the last face) was measured slower: the registers cost occupancy (P2) or
 // spill (P3).
-template <int Q, bool PIPE, bool MH>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_stage_mfma(StageArgs args,
-                                                                                             int64_t per) {
+template <int Q, bool PIPE, bool MH, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 : 6, 8))) void k_stage_mfma(
+    StageArgs args, int64_t per) {
     using T = float;
     using MD = MfmaDim<Q>;
     constexpr int NP = MD::NP, NFP = MD::NFP, MT = MD::MT, KSV = MD::KSV, KSF = MD::KSF;
     constexpr int RS = NP + 1;
     constexpr int KF = 4 * KSF;
-    constexpr int RF = (EPW * NFP + 63) / 64;
+    constexpr int NTH = 64 * W;                      // threads of the workgroup
+    constexpr int RF = (EPW * NFP + NTH - 1) / NTH;  // flux items per thread and face
+    constexpr int MW = W == 1 ? MT : 1;              // output row tiles of one wave
+    static_assert(W == 1 || (W == MT && RF == 1), "two waves split the two row tiles");
     __shared__ MfmaShared<Q> sh;
 
     StageArgs a;
@@ -693,47 +702,49 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     const int64_t e0 = blk * EPW;
     if (e0 >= a.K) return;  // uniform per workgroup
     const T* __restrict__ Y = (const T*)a.Y;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int mt0 = W == 1 ? 0 : tid >> 6;  // first output row tile of this wave
     const int ne = (int)((a.K - e0) < EPW ? (a.K - e0) : EPW);
     const int64_t base = e0 * 6 * NP;
     const int nv4 = ne * 6 * NP / 4;  // float4 groups of the chunk (6 NP is even, ne * 6 NP % 4 == 0 for NP even)
 
     // ---- staging: chunk fields, geometry, connectivity, face-node tables
     {
-        ChunkIn<T, Q> in;
-        in.fetch(Y, (const T*)a.geo, a.conn, e0, ne, lane);
-        for (int v = lane; v < KF * MfmaShared<Q>::FS; v += 64) sh.sF[v] = T(0);
-        in.put(sh.sY, sh.sG, sh.sC, sh.sT, ne, lane);
+        ChunkIn<T, Q, NTH> in;
+        in.fetch(Y, (const T*)a.geo, a.conn, e0, ne, tid);
+        for (int v = tid; v < KF * MfmaShared<Q>::FS; v += NTH) sh.sF[v] = T(0);
+        in.put(sh.sY, sh.sG, sh.sC, sh.sT, ne, tid);
     }
 
     // matrix fragments (coalesced: fragment-major, lane-minor)
     const float* fr = gFrag + frag_off(Q);
-    T afV[MT][KSV], afL[MT][KSF], afN[MT][KSF];
+    T afV[MW][KSV], afL[MW][KSF], afN[MW][KSF];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MW; ++mt)
 #pragma unroll
-        for (int ks = 0; ks < KSV; ++ks) afV[mt][ks] = fr[(mt * KSV + ks) * 64 + lane];
+        for (int ks = 0; ks < KSV; ++ks) afV[mt][ks] = fr[((mt + mt0) * KSV + ks) * 64 + lane];
     // lift fragments of one face at a time, requested one face ahead
-    auto lift_frags = [&](int f, T (&d)[MT][KSF]) {
+    auto lift_frags = [&](int f, T (&d)[MW][KSF]) {
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+        for (int mt = 0; mt < MW; ++mt)
 #pragma unroll
-            for (int ks = 0; ks < KSF; ++ks) d[mt][ks] = fr[(MT * KSV + (f * MT + mt) * KSF + ks) * 64 + lane];
+            for (int ks = 0; ks < KSF; ++ks) d[mt][ks] = fr[(MT * KSV + (f * MT + mt + mt0) * KSF + ks) * 64 + lane];
     };
     lift_frags(0, afL);
     __syncthreads();
 
     // face 0's neighbour traces in flight during the volume product
     FluxItems<Q, RF> itm;
-    itm.init(ne, lane);
+    itm.init(ne, tid);
     TraceGather<T, Q, RF> cur, nxt;
     cur.issue(Y, sh.sC, sh.sT, itm, 0, e0, ne);
 
     const int q4 = lane >> 4;   // K row within a 4-row block / output row group
     const int l16 = lane & 15;  // output column within a 16-column tile
-    v4f acc[MT][4];
+    v4f acc[MW][4];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MW; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = v4f{0.f, 0.f, 0.f, 0.f};
 
@@ -772,7 +783,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
             for (int t = 0; t < NJ; ++t) {
                 const T b = g1[ax] * r2[t] - g2[ax] * r1[t];
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
+                for (int mt = 0; mt < MW; ++mt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(afV[mt][ax * NJ + t], b, acc[mt][nt], 0, 0, 0);
             }
     }
@@ -836,7 +847,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
+                for (int mt = 0; mt < MW; ++mt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(afL[mt][ks], b[nt], acc[mt][nt], 0, 0, 0);
         }
         __syncthreads();  // the tile is rewritten by the next face
@@ -844,7 +855,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
             if (!PIPE) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1, e0, ne);
             cur = nxt;
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
+            for (int mt = 0; mt < MW; ++mt)
 #pragma unroll
                 for (int ks = 0; ks < KSF; ++ks) afL[mt][ks] = afN[mt][ks];
         }
@@ -861,10 +872,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         const T inv = s < 3 ? sh.sG[e * kGeo + 37] : sh.sG[e * kGeo + 38];
         const T sig = s < 3 ? sh.sG[e * kGeo + 39] : T(0);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+        for (int mt = 0; mt < MW; ++mt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = mt * 16 + 4 * q4 + r;
+                const int i = (mt + mt0) * 16 + 4 * q4 + r;
                 if (i < NP) {
                     T* p = &sh.sY[n * RS + i];
                     *p = fma(inv, acc[mt][nt][r], -sig * *p);
@@ -880,12 +891,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     // elements whose source is zero (and H rows of an interior source) read none
     const uint32_t sm = a.smask ? a.smask[blk] : 0xffffffffu;
     auto takes_src = [&](int row) { return row - 6 * (row / 6) < a.src_rows && ((sm >> (row / 6)) & 1u); };
-    MfmaUpdateIn<Q> upd;
-    upd.fetch(a, base, nv4, lane);
+    MfmaUpdateIn<Q, NTH> upd;
+    upd.fetch(a, base, nv4, tid);
     auto f4 = [](const void* p, int64_t o) { return reinterpret_cast<const float4*>((const T*)p + o); };
 #pragma unroll
-    for (int t = 0; t < MfmaUpdateIn<Q>::NIT; ++t) {
-        const int v4 = lane + 64 * t;
+    for (int t = 0; t < MfmaUpdateIn<Q, NTH>::NIT; ++t) {
+        const int v4 = tid + NTH * t;
         if (v4 >= nv4) continue;
         const int v = 4 * v4;
         const int64_t gi = base + v;
@@ -1202,12 +1213,14 @@ __global__ void k_nonfinite(const double* X, int64_t n, int* flag) {
 
 // Stage-kernel variant per (q, precision): 0 = gather per face, 1 = gathers
 // pipelined one face ahead, 2 / 3 = matrix cores (FP32, q >= 2) without /
-// with the one-face-ahead gathers.  Chosen from measurements; overridable
-// through cmcg_tune_stage().  Defaults from stage timings on 48000- and
-// 384000-tet meshes: FP32 P2 and P3 on the matrix cores with gathers one face
-// ahead (P3: 53 us vs 78 us, P2: 22.5 us vs 25.7 us per stage at 48000 tets),
-// per-face gathers otherwise.
-int g_variant[kMaxQ + 1][2] = {{0, 0}, {0, 0}, {0, 3}, {0, 3}};
+// with the one-face-ahead gathers, 4 = 3 with two waves per block (FP32, q =
+// 3).  Chosen from measurements; overridable through cmcg_tune_stage() and
+// the autotuner.  Defaults from stage timings on 48000- and 384000-tet
+// meshes: FP32 P2 on the matrix cores with gathers one face ahead (22.5 us
+// vs 25.7 us per stage at 48000 tets), FP32 P3 with two waves per block
+// (38.2 us vs 41.5 us at 48000 tets, 256 us vs 260 us at 384000), per-face
+// gathers otherwise.
+int g_variant[kMaxQ + 1][2] = {{0, 0}, {0, 0}, {0, 3}, {0, 4}};
 inline int stage_variant(int q, int precision) { return g_variant[q][precision]; }
 
 inline int grid_for(int64_t n, int threads = 256) {
@@ -1225,12 +1238,18 @@ void stage_launch_mh(const StageArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)(8 * per), (unsigned)(a.nmembers > 1 ? a.nmembers : 1));
     if constexpr (sizeof(T) == 4 && Q >= 2) {
         if (v == 2) {
-            hipLaunchKernelGGL((k_stage_mfma<Q, false, MH>), grid, dim3(64), 0, s, a, per);
+            hipLaunchKernelGGL((k_stage_mfma<Q, false, MH, 1>), grid, dim3(64), 0, s, a, per);
             return;
         }
-        if (v == 3) {
-            hipLaunchKernelGGL((k_stage_mfma<Q, true, MH>), grid, dim3(64), 0, s, a, per);
+        if (v == 3 || (v == 4 && Q != 3)) {
+            hipLaunchKernelGGL((k_stage_mfma<Q, true, MH, 1>), grid, dim3(64), 0, s, a, per);
             return;
+        }
+        if constexpr (Q == 3) {
+            if (v == 4) {
+                hipLaunchKernelGGL((k_stage_mfma<Q, true, MH, 2>), grid, dim3(128), 0, s, a, per);
+                return;
+            }
         }
     }
     if (v == 1)

@@ -33,7 +33,7 @@ def test_autotune_keeps_fastest_applicable_variant(lib, keep_variants, q, precis
     op, s, lp = pair(lib, n=3 if q < 3 else 2, q=q, precision=precision, seed=30 + q)
     v, us = lib.cmcg_autotune_stage(lp)
     print(f"  chosen {v}, us per launch {us}")
-    applies = [True, True, precision == 1 and q >= 2, precision == 1 and q >= 2]
+    applies = [True, True, precision == 1 and q >= 2, precision == 1 and q >= 2, precision == 1 and q == 3]
     assert all((u > 0) == a for u, a in zip(us, applies))
     assert us[v] == min(u for u in us if u > 0)
     assert lib.cmcg_tune_get_stage(q, precision) == v
