@@ -355,8 +355,8 @@ int cmcg_engine_info(const cmcg_engine* e, size_t* used, int* n_running, int* n_
  * ahead (more registers, more latency hiding), 2 runs the volume and lift
  * products on the matrix cores (FP32 fields, q = 2, 3; other combinations
  * fall back to 0), 3 is 2 with the neighbour traces requested one face
- * ahead, 4 is 3 with two waves per 10-element block, each computing one of
- * the two 16-row output tiles (FP32, q = 3; q = 2 falls back to 3).  All compute the same Phi(t, Y) and stage update.  Process-wide;
+ * ahead, 4 is 3 with two waves per 10-element block, each computing half of
+ * the output tiles (FP32, q = 2, 3).  All compute the same Phi(t, Y) and stage update.  Process-wide;
  * not thread-safe against concurrent solves.  Returns CMCG_ERR_ARG for an unknown q / precision /
  * variant.  cmcg_tune_get_stage reports the current choice. */
 #define CMCG_STAGE_VARIANTS 5

@@ -672,9 +672,10 @@ template <int Q, int NTH = 64> struct MfmaUpdateIn {
 
 // PIPE: the next face's neighbour traces are requested before this face's
 // flux (more registers, the gather latency hides behind the lift).
-// W: waves per workgroup.  W = 2 (P3) gives each wave one of the two 16-row
-// output tiles: both waves build the same B operands, each runs half the
-// MFMAs, the flux items and the update pass are shared by 128 threads.  A
+// W: waves per workgroup.  W = 2 gives each wave half the output tiles: P3
+// one of its two 16-row tiles (both waves build the same B operands), P2 two
+// of the four 16-column tiles (each wave builds only its own); each runs half
+// the MFMAs, the flux items and the update pass are shared by 128 threads.  A
 // block's dependent chain gets shorter at 6 waves per SIMD (76 registers),
 // which pays where the launch ends in a partial round of workgroups.  Register
 // allocation is held to 4 waves per SIMD (128 registers; the LDS tiles of
@@ -692,8 +693,12 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ?
     constexpr int KF = 4 * KSF;
     constexpr int NTH = 64 * W;                      // threads of the workgroup
     constexpr int RF = (EPW * NFP + NTH - 1) / NTH;  // flux items per thread and face
-    constexpr int MW = W == 1 ? MT : 1;              // output row tiles of one wave
-    static_assert(W == 1 || (W == MT && RF == 1), "two waves split the two row tiles");
+    // two waves split the output tiles: by rows when there are two row tiles
+    // (P3), by the four 16-column tiles otherwise (P2)
+    constexpr bool ROWS = W == 2 && MT == 2, COLS = W == 2 && MT == 1;
+    constexpr int MW = ROWS ? 1 : MT;   // output row tiles of one wave
+    constexpr int NW = COLS ? 2 : 4;    // output column tiles of one wave
+    static_assert(W == 1 || ((ROWS || COLS) && RF == 1), "two waves per block need one flux item per thread");
     __shared__ MfmaShared<Q> sh;
 
     StageArgs a;
@@ -704,7 +709,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ?
     const T* __restrict__ Y = (const T*)a.Y;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int mt0 = W == 1 ? 0 : tid >> 6;  // first output row tile of this wave
+    const int mt0 = ROWS ? tid >> 6 : 0;        // first output row tile of this wave
+    const int nt0 = COLS ? 2 * (tid >> 6) : 0;  // first output column tile of this wave
     const int ne = (int)((a.K - e0) < EPW ? (a.K - e0) : EPW);
     const int64_t base = e0 * 6 * NP;
     const int nv4 = ne * 6 * NP / 4;  // float4 groups of the chunk (6 NP is even, ne * 6 NP % 4 == 0 for NP even)
@@ -742,17 +748,17 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ?
 
     const int q4 = lane >> 4;   // K row within a 4-row block / output row group
     const int l16 = lane & 15;  // output column within a 16-column tile
-    v4f acc[MW][4];
+    v4f acc[MW][NW];
 #pragma unroll
     for (int mt = 0; mt < MW; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int nt = 0; nt < NW; ++nt) acc[mt][nt] = v4f{0.f, 0.f, 0.f, 0.f};
 
     // ---- volume product: B[(a, j)][n] = sgn (g_a[m1] V_m2(j) - g_a[m2] V_m1(j));
     // padded columns read element 0 (their results are never stored)
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        const int n = nt * 16 + l16;
+    for (int nt = 0; nt < NW; ++nt) {
+        const int n = (nt + nt0) * 16 + l16;
         const int e = n < 6 * ne ? n / 6 : 0;
         const int s = n - 6 * (n / 6);
         const int m = s < 3 ? s : s - 3;
@@ -841,11 +847,11 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ?
         __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < KSF; ++ks) {
-            T b[4];
+            T b[NW];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) b[nt] = sh.sF[(ks * 4 + q4) * MfmaShared<Q>::FS + nt * 16 + l16];
+            for (int nt = 0; nt < NW; ++nt) b[nt] = sh.sF[(ks * 4 + q4) * MfmaShared<Q>::FS + (nt + nt0) * 16 + l16];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt)
+            for (int nt = 0; nt < NW; ++nt)
 #pragma unroll
                 for (int mt = 0; mt < MW; ++mt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(afL[mt][ks], b[nt], acc[mt][nt], 0, 0, 0);
@@ -864,8 +870,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ?
     // ---- scaled right-hand side (1/eps or 1/mu, conductivity) into the
     // staging tile, in place: every value is read and written by one lane
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        const int n = nt * 16 + l16;
+    for (int nt = 0; nt < NW; ++nt) {
+        const int n = (nt + nt0) * 16 + l16;
         if (n >= 6 * ne) continue;
         const int e = n / 6;
         const int s = n - 6 * e;
@@ -1213,14 +1219,13 @@ __global__ void k_nonfinite(const double* X, int64_t n, int* flag) {
 
 // Stage-kernel variant per (q, precision): 0 = gather per face, 1 = gathers
 // pipelined one face ahead, 2 / 3 = matrix cores (FP32, q >= 2) without /
-// with the one-face-ahead gathers, 4 = 3 with two waves per block (FP32, q =
-// 3).  Chosen from measurements; overridable through cmcg_tune_stage() and
-// the autotuner.  Defaults from stage timings on 48000- and 384000-tet
-// meshes: FP32 P2 on the matrix cores with gathers one face ahead (22.5 us
-// vs 25.7 us per stage at 48000 tets), FP32 P3 with two waves per block
-// (38.2 us vs 41.5 us at 48000 tets, 256 us vs 260 us at 384000), per-face
-// gathers otherwise.
-int g_variant[kMaxQ + 1][2] = {{0, 0}, {0, 0}, {0, 3}, {0, 4}};
+// with the one-face-ahead gathers, 4 = 3 with two waves per block.  Chosen
+// from measurements; overridable through cmcg_tune_stage() and the
+// autotuner.  Defaults: FP32 P2 and P3 on the matrix cores with two waves per
+// block (P3: 38.2 us vs 41.5 us at 48000 tets, 256 vs 260 us at 384000; P2:
+// 8.6 vs 10.4 us at 10368 tets, 28.8 vs 31.0 us at 82944, but 126 vs 123 us
+// at 384000, where the autotuner keeps one wave), per-face gathers otherwise.
+int g_variant[kMaxQ + 1][2] = {{0, 0}, {0, 0}, {0, 4}, {0, 4}};
 inline int stage_variant(int q, int precision) { return g_variant[q][precision]; }
 
 inline int grid_for(int64_t n, int threads = 256) {
@@ -1241,15 +1246,13 @@ void stage_launch_mh(const StageArgs& a, hipStream_t s) {
             hipLaunchKernelGGL((k_stage_mfma<Q, false, MH, 1>), grid, dim3(64), 0, s, a, per);
             return;
         }
-        if (v == 3 || (v == 4 && Q != 3)) {
+        if (v == 3) {
             hipLaunchKernelGGL((k_stage_mfma<Q, true, MH, 1>), grid, dim3(64), 0, s, a, per);
             return;
         }
-        if constexpr (Q == 3) {
-            if (v == 4) {
-                hipLaunchKernelGGL((k_stage_mfma<Q, true, MH, 2>), grid, dim3(128), 0, s, a, per);
-                return;
-            }
+        if (v == 4) {
+            hipLaunchKernelGGL((k_stage_mfma<Q, true, MH, 2>), grid, dim3(128), 0, s, a, per);
+            return;
         }
     }
     if (v == 1)

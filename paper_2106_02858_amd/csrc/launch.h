@@ -82,7 +82,7 @@ void launch_stage(int q, int precision, const StageArgs& a, hipStream_t s);
 void set_stage_variant(int q, int precision, int variant);
 int get_stage_variant(int q, int precision);
 constexpr int kStageVariants = CMCG_STAGE_VARIANTS;  // 2, 3: matrix cores (FP32, q >= 2; 3 gathers one face
-                                                     // ahead); 4: as 3 with two waves per block (FP32, q = 3)
+                                                     // ahead); 4: as 3 with two waves per block (FP32, q >= 2)
 
 // FP64 <-> field precision; flipH negates the magnetic rows (the S of P* = S P S).
 // FP32: Ulo (nullable) receives / contributes the bfloat16 low part.

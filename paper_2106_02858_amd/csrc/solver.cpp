@@ -505,7 +505,7 @@ std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int64_t, int>, int> g_tuned;
 
 bool variant_applies(int q, int precision, int v) {
-    return v <= 1 || (precision == CMCG_FP32 && q >= 2 && (v <= 3 || q == 3));
+    return v <= 1 || (precision == CMCG_FP32 && q >= 2);
 }
 
 struct EventPair {

@@ -44,10 +44,10 @@ def variant(lib, request):
     lib.cmcg_tune_stage(q, prec, old)
 
 
-# 0, 1 run everywhere; the matrix-core variants 2, 3 exist for FP32 fields at q >= 2, 4 (two
-# waves per block) for FP32 at q = 3
+# 0, 1 run everywhere; the matrix-core variants 2, 3, 4 (4: two waves per block) exist for
+# FP32 fields at q >= 2
 VARIANTS = [(q, p, v) for q in (1, 2, 3) for p in (0, 1) for v in (0, 1)] + \
-    [(q, 1, v) for q in (2, 3) for v in (2, 3)] + [(3, 1, 4)]
+    [(q, 1, v) for q in (2, 3) for v in (2, 3, 4)]
 
 
 @pytest.mark.parametrize("variant", VARIANTS, indirect=True, ids=lambda t: f"q{t[0]}-p{t[1]}-v{t[2]}")
@@ -264,25 +264,27 @@ def test_cmcg_fixed_iterations_conductive_with_boundary_data(lib, q, n):
     assert err < max(1e-11, 10 * spread)
 
 
-def test_two_wave_blocks_equal_one_wave_blocks(lib):
-    """Variant 4 (two waves per 10-element block, one output row tile each)
+@pytest.mark.parametrize("q", [2, 3])
+def test_two_wave_blocks_equal_one_wave_blocks(lib, q):
+    """Variant 4 (two waves per 10-element block, half the output tiles each)
     does the same arithmetic as variant 3: right-hand side and a period agree
     bit for bit, also with a partial last block."""
     import torch
-    old = lib.cmcg_tune_get_stage(3, 1)
+    old = lib.cmcg_tune_get_stage(q, 1)
     try:
         xyz, tet, tags = inputs.cube_mesh(2)
         tet, tags = tet[:-3], np.full((tet.shape[0] - 3, 4), 2, dtype=np.int8)  # 45 elements: ragged
         K = tet.shape[0]
         m = lib.cmcg_mesh_create(xyz, tet, tags)
-        s = lib.cmcg_space_create(m, 3, 1)
+        s = lib.cmcg_space_create(m, q, 1)
+        Np = lib.cmcg_space_info(s)["Np"]
         j = inputs.gaussian_current(lib.cmcg_space_nodes(s), (0.5, 0.4, 0.5), 0.3, 1)
         p = lib.cmcg_problem_create(s, np.random.default_rng(3).choice([1.0, 2.0, 4.0], K), np.ones(K),
                                     np.full(K, 0.2), 2 * np.pi, j)
-        U = dev(np.random.default_rng(4).standard_normal((K, 6, 20)))
+        U = dev(np.random.default_rng(4).standard_normal((K, 6, Np)))
         outs = []
         for v in (3, 4):
-            lib.cmcg_tune_stage(3, 1, v)
+            lib.cmcg_tune_stage(q, 1, v)
             r, UT = torch.empty_like(U), torch.empty_like(U)
             lib.cmcg_debug_rhs(p, U, r, t=0.3, with_source=True)
             lib.cmcg_debug_period(p, U, UT, 1, True, opts=lib.cmcg_options_default(steps=12))
@@ -290,4 +292,4 @@ def test_two_wave_blocks_equal_one_wave_blocks(lib):
             outs.append((r.cpu(), UT.cpu()))
         assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
     finally:
-        lib.cmcg_tune_stage(3, 1, old)
+        lib.cmcg_tune_stage(q, 1, old)
