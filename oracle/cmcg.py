@@ -56,13 +56,13 @@ class Operators:
         return timestep.forward(self.p, U, self.M, self.scheme, True, filt=True)[1]
 
     def ip(self, U, V):
-        return float(dg.inner(self.p, U, V))
+        return float(timestep.ops_of(self.p).inner(self.p, U, V))
 
 
 def initialise(ops: Operators):
     """Algorithm 1: G = P_psi 0, G_T = P* G, G* = G - G_T."""
     p = ops.p
-    G = ops.P_psi(np.zeros((p.K, 6, p.Np)))
+    G = ops.P_psi(np.zeros((p.K, p.ncomp, p.Np)))
     GT = ops.P_star(G)
     return G, G - GT
 
@@ -99,7 +99,7 @@ def solve(p: dg.Problem, tol: float = 1e-8, max_iter: int = 1000, u0=None, M=Non
     (zero or u0) before the first residual; CG then starts from their state."""
     ops = Operators(p, M, scheme, cfl)
     G, Gstar = initialise(ops)
-    U = np.zeros((p.K, 6, p.Np)) if u0 is None else np.array(u0, dtype=np.float64).reshape(p.K, 6, p.Np)
+    U = np.zeros((p.K, p.ncomp, p.Np)) if u0 is None else np.array(u0, dtype=np.float64).reshape(p.K, p.ncomp, p.Np)
     for _ in range(runup):
         U = ops.P_psi(U)
     if u0 is None and runup == 0:

@@ -40,6 +40,9 @@ class Problem:
     g: np.ndarray | None      # complex [K, 4, Nfp, 3] impedance boundary data
     alpha: float = 1.0
 
+    dim = 3
+    ncomp = 6
+
     @property
     def K(self):
         return self.geo.K

@@ -18,18 +18,19 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from . import dg, timestep
+from .timestep import ops_of
 from .filters import hermite_xi
 
 
 def frequency_solve(p: dg.Problem, B: sp.csr_matrix | None = None) -> np.ndarray:
     if B is None:
-        B = dg.assemble_B(p)
-    M = dg.mass_matrix(p)
+        B = ops_of(p).assemble_B(p)
+    M = ops_of(p).mass_matrix(p)
     Kmat = -(M @ B)
-    JJ = dg.source_vector(p)
+    JJ = ops_of(p).source_vector(p)
     A = (1j * p.omega * M + Kmat).tocsc()
     U = spla.splu(A).solve(M @ JJ)
-    return U.reshape(p.K, 6, p.Np)
+    return U.reshape(p.K, p.ncomp, p.Np)
 
 
 def rk_forced_step(B, JJ, omega, dt, scheme):
@@ -49,13 +50,13 @@ def rk_forced_step(B, JJ, omega, dt, scheme):
 def discrete_periodic(p: dg.Problem, M: int, scheme: int, B: sp.csr_matrix | None = None):
     """Returns (U_hat, filtered) for the exactly periodic discrete orbit."""
     if B is None:
-        B = dg.assemble_B(p)
+        B = ops_of(p).assemble_B(p)
     B = B.tocsc().astype(np.complex128)
     n = B.shape[0]
     T = 2 * np.pi / p.omega
     dt = T / M
     z = np.exp(1j * p.omega * dt)
-    JJ = dg.source_vector(p)
+    JJ = ops_of(p).source_vector(p)
     S = rk_forced_step(B, JJ, p.omega, dt, scheme)
     # z - R(x) = c prod_k (x - r_k), x = dt B
     coef = timestep.step_matrix_poly(scheme)  # ascending
@@ -73,4 +74,4 @@ def discrete_periodic(p: dg.Problem, M: int, scheme: int, B: sp.csr_matrix | Non
     else:
         x00, x01, x10, x11 = hermite_xi(p.omega, dt)
         F = ((x00 + z * x01) * Uh + (x10 + z * x11) * (B @ Uh + JJ)) / dt
-    return Uh.reshape(p.K, 6, p.Np), F.reshape(p.K, 6, p.Np)
+    return Uh.reshape(p.K, p.ncomp, p.Np), F.reshape(p.K, p.ncomp, p.Np)

@@ -32,8 +32,8 @@ class FwResult:
 def rel_change(p: dg.Problem, F: np.ndarray, Fprev: np.ndarray) -> float:
     """||F - Fprev|| / ||F|| in the eps-mu norm (real or complex fields)."""
     d = F - Fprev
-    num = dg.inner(p, d.real, d.real) + dg.inner(p, np.imag(d), np.imag(d))
-    den = dg.inner(p, F.real, F.real) + dg.inner(p, np.imag(F), np.imag(F))
+    num = timestep.ops_of(p).inner(p, d.real, d.real) + timestep.ops_of(p).inner(p, np.imag(d), np.imag(d))
+    den = timestep.ops_of(p).inner(p, F.real, F.real) + timestep.ops_of(p).inner(p, np.imag(F), np.imag(F))
     return float(np.sqrt(num / den)) if den > 0 else 0.0
 
 
@@ -47,7 +47,7 @@ def solve(p: dg.Problem, periods: int, tol: float = 0.0, M: int | None = None, s
         M = timestep.n_steps(p)
     if scheme is None:
         scheme = timestep.default_scheme(p.geo.q)
-    U = np.zeros((p.K, 6, p.Np)) if u0 is None else np.array(u0, dtype=np.float64).reshape(p.K, 6, p.Np)
+    U = np.zeros((p.K, p.ncomp, p.Np)) if u0 is None else np.array(u0, dtype=np.float64).reshape(p.K, p.ncomp, p.Np)
     hist = []
     for _ in range(periods - 1):
         Un = timestep.forward(p, U, M, scheme, with_source=True)

@@ -13,7 +13,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import dg
+from . import dg, dg2d
 from . import filters
 
 # CFL constants c_q for 3-D tetrahedra.  The paper's 2-D values are
@@ -22,6 +22,14 @@ from . import filters
 # margin (limit >= 0.13); c_2 = 0.16 is a reading for P2 (limit ~0.20),
 # which the paper does not run.
 CFL = {1: 0.20, 2: 0.16, 3: 0.12}
+# 2-D triangles: the paper's c_1 = 0.24 and c_3 = 0.12, rho_K the diameter of
+# the inscribed circle; c_2 = 0.16 is a reading (the paper runs P1 and P3).
+CFL2D = {1: 0.24, 2: 0.16, 3: 0.12}
+
+
+def ops_of(p):
+    """The DG module of a problem: 3-D (dg) or 2-D transverse magnetic (dg2d)."""
+    return dg2d if getattr(p, "dim", 3) == 2 else dg
 
 
 def default_scheme(q: int) -> int:
@@ -30,7 +38,7 @@ def default_scheme(q: int) -> int:
 
 
 def n_steps(p: dg.Problem, cfl: float | None = None) -> int:
-    c = CFL[p.geo.q] if cfl is None else cfl
+    c = (CFL2D if getattr(p, "dim", 3) == 2 else CFL)[p.geo.q] if cfl is None else cfl
     T = 2 * np.pi / p.omega
     dtmax = c * np.min(np.sqrt(p.mu * p.eps) * p.geo.rho)
     M = int(np.ceil(T / dtmax))
@@ -42,16 +50,16 @@ def n_steps(p: dg.Problem, cfl: float | None = None) -> int:
 
 
 def rk2_step(p, t, U, dt, with_source):
-    k1 = dg.phi(p, t, U, with_source)
-    k2 = dg.phi(p, t + dt / 2, U + dt / 2 * k1, with_source)
+    k1 = ops_of(p).phi(p, t, U, with_source)
+    k2 = ops_of(p).phi(p, t + dt / 2, U + dt / 2 * k1, with_source)
     return U + dt * k2, k1
 
 
 def rk4_step(p, t, U, dt, with_source):
-    k1 = dg.phi(p, t, U, with_source)
-    k2 = dg.phi(p, t + dt / 2, U + dt / 2 * k1, with_source)
-    k3 = dg.phi(p, t + dt / 2, U + dt / 2 * k2, with_source)
-    k4 = dg.phi(p, t + dt, U + dt * k3, with_source)
+    k1 = ops_of(p).phi(p, t, U, with_source)
+    k2 = ops_of(p).phi(p, t + dt / 2, U + dt / 2 * k1, with_source)
+    k3 = ops_of(p).phi(p, t + dt / 2, U + dt / 2 * k2, with_source)
+    k4 = ops_of(p).phi(p, t + dt, U + dt * k3, with_source)
     return U + dt / 6 * (k1 + 2 * k2 + 2 * k3 + k4), k1
 
 
@@ -64,7 +72,7 @@ def forward(p: dg.Problem, U0: np.ndarray, M: int, scheme: int, with_source: boo
     T = 2 * np.pi / p.omega
     dt = T / M
     om = p.omega
-    U = np.array(U0, dtype=np.float64, copy=True).reshape(p.K, 6, p.Np)
+    U = np.array(U0, dtype=np.float64, copy=True).reshape(p.K, p.ncomp, p.Np)
     step = rk2_step if scheme == 2 else rk4_step
     Us, Phis = [U], []
     for m in range(M):
@@ -78,14 +86,15 @@ def forward(p: dg.Problem, U0: np.ndarray, M: int, scheme: int, with_source: boo
     if scheme == 2:
         F = filters.trapezoid(Us, om, M)
     else:
-        Phis.append(dg.phi(p, M * dt, U, with_source))
+        Phis.append(ops_of(p).phi(p, M * dt, U, with_source))
         F = filters.hermite(Us, Phis, om, M)
     return U, F
 
 
 def backward(p: dg.Problem, WT: np.ndarray, M: int, scheme: int) -> np.ndarray:
     """P* W_T = S P S W_T (homogeneous)."""
-    return dg.flip_H(forward(p, dg.flip_H(np.asarray(WT).reshape(p.K, 6, p.Np)), M, scheme, False))
+    flip = ops_of(p).flip_H
+    return flip(forward(p, flip(np.asarray(WT).reshape(p.K, p.ncomp, p.Np)), M, scheme, False))
 
 
 def step_matrix_poly(scheme: int):

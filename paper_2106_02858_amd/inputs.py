@@ -211,3 +211,160 @@ def scatterer(n: int = 64, q: int = 2) -> Workload:
     eps = np.where(inside, 4.0, 1.0)
     return Workload("scatterer", n, q, 8 * math.pi, eps, np.ones(K), np.zeros(K),
                     np.array([0.15, 0.5, 0.5]), 0.03, 2, TAG_IMPEDANCE, xyz, tet, tags)
+
+
+# ------------------------------------------------------------------ 2-D (TM)
+#
+# The paper's own experiments are two-dimensional (Section 6).  An "nx x ny
+# Cartesian mesh" of a rectangle is the grid of nx x ny cells, each divided
+# into four triangles by joining its corners to its barycentre.  Triangles are
+# counter-clockwise; local edge f is opposite local vertex f; the barycentre is
+# local vertex 0, so edge 0 is the cell side.  Cell c = i + nx j (x fastest)
+# holds triangles 4c .. 4c+3 for its bottom, right, top and left sides.
+
+SIDE_BOTTOM, SIDE_RIGHT, SIDE_TOP, SIDE_LEFT = range(4)
+
+
+def cartesian_triangles(nx: int, ny: int, x0: float = 0.0, y0: float = 0.0, lx: float = 1.0,
+                        ly: float = 1.0, side_tags=(TAG_IMPEDANCE,) * 4):
+    """Returns (xy [nv,2] float64, tri [4 nx ny, 3] int64, edge_tag [K,3] int8);
+    side_tags gives the tag of the bottom, right, top and left sides."""
+    if nx < 1 or ny < 1:
+        raise ValueError("nx, ny must be >= 1")
+    gi, gj = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), indexing="xy")
+    corners = np.stack([x0 + lx * gi.ravel() / nx, y0 + ly * gj.ravel() / ny], axis=1)
+    ci, cj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    ci, cj = ci.ravel(), cj.ravel()
+    centres = np.stack([x0 + lx * (ci + 0.5) / nx, y0 + ly * (cj + 0.5) / ny], axis=1)
+    xy = np.concatenate([corners, centres])
+    ncorner = corners.shape[0]
+
+    def vid(i, j):
+        return i + (nx + 1) * j
+
+    p0, p1, p2, p3 = vid(ci, cj), vid(ci + 1, cj), vid(ci + 1, cj + 1), vid(ci, cj + 1)
+    c = ncorner + np.arange(nx * ny)
+    tri = np.stack([np.stack([c, p0, p1], 1), np.stack([c, p1, p2], 1),
+                    np.stack([c, p2, p3], 1), np.stack([c, p3, p0], 1)], axis=1).reshape(-1, 3)
+    tags = np.zeros((tri.shape[0], 3), dtype=np.int8)
+    side = np.tile(np.arange(4), nx * ny)
+    on = np.stack([cj == 0, ci == nx - 1, cj == ny - 1, ci == 0], axis=1)  # [cells, side]
+    on = on.reshape(-1)
+    tags[on, 0] = np.asarray(side_tags, dtype=np.int8)[side[on]]
+    return xy, tri.astype(np.int64), tags
+
+
+@dataclass
+class Workload2D:
+    """A 2-D TM problem: mesh, coefficients and the recipe of its data.
+
+    source kinds: "constant" (j = 1), "gaussian" (j = exp(-|x-c|^2/s^2)),
+    "planewave" (impedance data of the plane wave exp(i omega d.x),
+    d = (cos theta, sin theta)), "none"."""
+    name: str
+    q: int
+    omega: float
+    eps: np.ndarray
+    mu: np.ndarray
+    sigma: np.ndarray
+    xy: np.ndarray = field(repr=False)
+    tri: np.ndarray = field(repr=False)
+    tags: np.ndarray = field(repr=False)
+    source: str = "none"
+    centre: np.ndarray = None
+    width: float = 0.0
+    theta: float = 0.0
+
+    @property
+    def K(self) -> int:
+        return self.tri.shape[0]
+
+
+def cavity2d(n: int = 32, q: int = 1, omega_r: float = 3 * math.sqrt(2) * math.pi,
+             delta: float = 1.0 / 8.0) -> Workload2D:
+    """Closed PEC cavity (0,1)^2 on an n x n Cartesian mesh, eps = mu = 1,
+    j = 1, omega = omega_r + sqrt(2) pi delta (the cavity experiment)."""
+    xy, tri, tags = cartesian_triangles(n, n, side_tags=(TAG_PEC,) * 4)
+    K = tri.shape[0]
+    om = omega_r + math.sqrt(2) * math.pi * delta
+    return Workload2D(f"cavity2d_n{n}_q{q}", q, om, np.ones(K), np.ones(K), np.zeros(K), xy, tri, tags,
+                      "constant")
+
+
+def planewave2d(n: int = 32, q: int = 1, omega: float = 10 * math.pi,
+                theta: float = math.pi / 4) -> Workload2D:
+    """Plane wave in (0,1)^2 with impedance walls on every side, eps = mu = 1,
+    j = 0, on an n x n Cartesian mesh (the free-space experiment)."""
+    xy, tri, tags = cartesian_triangles(n, n, side_tags=(TAG_IMPEDANCE,) * 4)
+    K = tri.shape[0]
+    return Workload2D(f"planewave2d_n{n}_q{q}", q, omega, np.ones(K), np.ones(K), np.zeros(K), xy, tri,
+                      tags, "planewave", theta=theta)
+
+
+def trap2d(n: int = 30, q: int = 3, omega: float = 10 * math.pi) -> Workload2D:
+    """Dipole in a trapping square: Omega = (-1,1)^2 with impedance walls,
+    eps = 4 in G = [-1/2,1/2]^2 (a triangle is inside when its centroid is),
+    else 1, mu = 1, j = exp(-|x-c|^2/s^2) with c = (1/4, 0), s = 0.05.  The
+    paper meshes this with GMSH (3636 triangles); the n x n Cartesian mesh of
+    (-1,1)^2 stands in for it (n = 30: 3600 triangles)."""
+    xy, tri, tags = cartesian_triangles(n, n, -1.0, -1.0, 2.0, 2.0)
+    K = tri.shape[0]
+    cen = xy[tri].mean(axis=1)
+    inside = np.all(np.abs(cen) < 0.5, axis=1)
+    return Workload2D(f"trap2d_n{n}_q{q}", q, omega, np.where(inside, 4.0, 1.0), np.ones(K), np.zeros(K),
+                      xy, tri, tags, "gaussian", centre=np.array([0.25, 0.0]), width=0.05)
+
+
+def current_2d(w: Workload2D, nodes: np.ndarray) -> np.ndarray | None:
+    """Nodal samples of the current density j at nodes [K, Np, 2] (real), or
+    None for sources without a current."""
+    if w.source == "constant":
+        return np.ones(nodes.shape[:2])
+    if w.source == "gaussian":
+        d2 = np.sum((nodes - w.centre) ** 2, axis=-1)
+        return np.exp(-d2 / (w.width * w.width))
+    return None
+
+
+SIDE_NORMALS = np.array([[0.0, -1.0], [1.0, 0.0], [0.0, 1.0], [-1.0, 0.0]])
+
+
+def planewave_boundary_data(w: Workload2D, face_points: np.ndarray, project: bool = True) -> np.ndarray:
+    """Impedance data G = e + Z h x n of the plane wave e = exp(i omega d.x),
+    h = (sin theta, -cos theta) e, Z = 1 (so G = e (1 + d.n)), on the wall
+    edges of a Cartesian mesh; [K, 3, Nfp] complex nodal values at the edge
+    nodes face_points [K, 3, Nfp, 2], zero off the impedance edges.
+
+    project=True returns the L2 projection of G onto polynomials of degree
+    Nfp - 1 on each edge (Gauss-Legendre, 16 points), so that the edge
+    integrals of the data against the edge basis are exact; project=False
+    samples G at the nodes.  The outward normal of a wall edge is that of its
+    cell side (triangle index mod 4)."""
+    d = np.array([math.cos(w.theta), math.sin(w.theta)])
+    K = w.K
+    assert face_points.shape[0] == K
+    out = np.zeros(face_points.shape[:3], dtype=np.complex128)
+    wall = np.nonzero(w.tags[:, 0] == TAG_IMPEDANCE)[0]
+    n = SIDE_NORMALS[wall % 4]
+    fac = (1.0 + n @ d)                                   # [nw]
+    pts = face_points[wall, 0]                            # [nw, Nfp, 2]
+    if not project:
+        out[wall, 0] = np.exp(1j * w.omega * (pts @ d)) * fac[:, None]
+        return out
+    A = w.xy[w.tri[wall, 1]]
+    B = w.xy[w.tri[wall, 2]]
+    sg, wg = np.polynomial.legendre.leggauss(16)
+    sg, wg = (sg + 1) / 2, wg / 2
+    L2 = np.sum((B - A) ** 2, axis=1)
+    s_nodes = np.einsum("wkc,wc->wk", pts - A[:, None, :], B - A) / L2[:, None]   # node positions on [0,1]
+    Nfp = pts.shape[1]
+    for i in range(len(wall)):
+        lag = np.ones((len(sg), Nfp))
+        for k in range(Nfp):
+            for l in range(Nfp):
+                if l != k:
+                    lag[:, k] *= (sg - s_nodes[i, l]) / (s_nodes[i, k] - s_nodes[i, l])
+        x = A[i] + sg[:, None] * (B[i] - A[i])
+        G = np.exp(1j * w.omega * (x @ d)) * fac[i]
+        out[wall[i], 0] = np.linalg.solve(lag.T @ (wg[:, None] * lag), lag.T @ (wg * G))
+    return out
