@@ -175,6 +175,33 @@ int cmcg_mesh_locality_order(int64_t nv, const double* xyz, int64_t K, const int
 
 int cmcg_mesh_create(int64_t nv, const double* xyz, int64_t K, const int64_t* tet,
                      const int8_t* face_tag, cmcg_mesh** out);
+/* Conforming triangle mesh of the 2-D transverse-magnetic setting (Section
+ * 5.1: fields independent of the third coordinate, e = E_3 and h = (H_1,
+ * H_2); Section 5.2: its DG scheme on triangles, edge sets interior / PEC /
+ * impedance).
+ *   xy[nv][2]     vertex coordinates
+ *   tri[K][3]     vertex indices (0-based), either orientation
+ *   edge_tag      [K][3] (local edge f opposite local vertex f): for boundary
+ *                 edges CMCG_TAG_PEC or CMCG_TAG_IMPEDANCE; NULL tags every
+ *                 boundary edge impedance.
+ * Spaces on such a mesh hold (e, h1, h2): dof vectors [K][3][Np] with Np =
+ * (q+1)(q+2)/2 equispaced nodes (i, j)/q, j slowest; the CFL constants
+ * default to the paper's c_1 = 0.24 and c_3 = 0.12 (c_2 = 0.16) with rho_K
+ * the diameter of the inscribed circle.  Layouts of the other calls on 2-D
+ * spaces: cmcg_space_nodes xy[K][Np][2]; problem current j[K][Np] (the e
+ * component; device form alike), impedance data g[K][3][Nfp] (the scalar G of
+ * e + Z h x n = G, h x n = h1 n2 - h2 n1, edge nodes from the edge's
+ * lower-numbered vertex); cmcg_result_fields e[K][Np], h[K][Np][2].  2-D
+ * problems are solved by cmcg_solve, cmcg_fw_solve and the serving engine,
+ * one frequency each; cmcg_solve_batch, several-harmonic problems and the
+ * stage autotuner return CMCG_ERR_ARG for them.
+ * Errors: CMCG_ERR_ARG (NULL, nv < 3, K < 1, K >= 2^26, index out of range),
+ * CMCG_ERR_MESH (zero area, an edge shared by more than two triangles, an
+ * untagged boundary edge). */
+int cmcg_mesh2d_create(int64_t nv, const double* xy, int64_t K, const int64_t* tri,
+                       const int8_t* edge_tag, cmcg_mesh** out);
+/* Dimension of a mesh: 3 (tetrahedra) or 2 (triangles). */
+int cmcg_mesh_dim(const cmcg_mesh* m, int* dim);
 void cmcg_mesh_destroy(cmcg_mesh* m);
 int cmcg_mesh_info(const cmcg_mesh* m, int64_t* K, int64_t* n_boundary_faces,
                    double* min_rho);

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libcmcg.so")
 C_DEMO_SRC = os.path.join(ROOT, "tests", "c_abi", "solve_demo.c")
 C_DEMO = os.path.join(ROOT, "tests", "c_abi", "solve_demo")
 
-SOURCES = ["refelem.cpp", "mesh.cpp", "solver.cpp", "batch.cpp", "engine.cpp", "kernels.hip"]
+SOURCES = ["refelem.cpp", "mesh.cpp", "solver.cpp", "batch.cpp", "engine.cpp", "kernels.hip", "kernels2d.hip"]
 ARCH = os.environ.get("CMCG_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{os.path.join(ROOT, 'include')}"]

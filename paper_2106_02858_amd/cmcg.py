@@ -39,7 +39,7 @@ CMCG_FLUX_UPWIND, CMCG_FLUX_CENTRED = 0, 1
 
 EXPORTED = [
     "cmcg_last_error", "cmcg_version", "cmcg_options_default",
-    "cmcg_mesh_create", "cmcg_mesh_destroy", "cmcg_mesh_info",
+    "cmcg_mesh_create", "cmcg_mesh2d_create", "cmcg_mesh_dim", "cmcg_mesh_destroy", "cmcg_mesh_info",
     "cmcg_space_create", "cmcg_space_destroy", "cmcg_space_info", "cmcg_space_nodes",
     "cmcg_problem_create", "cmcg_problem_create_device", "cmcg_problem_destroy", "cmcg_problem_steps",
     "cmcg_problem_create_harmonics", "cmcg_result_harmonics", "cmcg_result_filtered_harmonic_device",
@@ -84,6 +84,8 @@ _sig = {
     "cmcg_options_default": (None, [C.POINTER(cmcg_options)]),
     "cmcg_mesh_create": (C.c_int, [C.c_int64, P, C.c_int64, P, P, C.POINTER(P)]),
     "cmcg_mesh_destroy": (None, [P]),
+    "cmcg_mesh2d_create": (C.c_int, [C.c_int64, P, C.c_int64, P, P, C.POINTER(P)]),
+    "cmcg_mesh_dim": (C.c_int, [P, C.POINTER(C.c_int)]),
     "cmcg_mesh_info": (C.c_int, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), D]),
     "cmcg_space_create": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(P)]),
     "cmcg_space_destroy": (None, [P]),
@@ -224,6 +226,23 @@ def cmcg_mesh_create(xyz, tet, face_tag=None) -> Mesh:
     return Mesh(h)
 
 
+def cmcg_mesh2d_create(xy, tri, edge_tag=None) -> Mesh:
+    """Triangle mesh of the 2-D transverse-magnetic setting: xy [nv,2],
+    tri [K,3], edge_tag [K,3] (edge f opposite vertex f)."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int64)
+    tags = None if edge_tag is None else np.ascontiguousarray(edge_tag, dtype=np.int8)
+    h = P()
+    _check(_lib.cmcg_mesh2d_create(xy.shape[0], _ptr(xy), tri.shape[0], _ptr(tri), _ptr(tags), C.byref(h)))
+    return Mesh(h)
+
+
+def cmcg_mesh_dim(m: Mesh) -> int:
+    d = C.c_int()
+    _check(_lib.cmcg_mesh_dim(m.h, C.byref(d)))
+    return d.value
+
+
 def cmcg_mesh_info(m: Mesh):
     K, nb, rho = C.c_int64(), C.c_int64(), C.c_double()
     _check(_lib.cmcg_mesh_info(m.h, C.byref(K), C.byref(nb), C.byref(rho)))
@@ -233,18 +252,22 @@ def cmcg_mesh_info(m: Mesh):
 def cmcg_space_create(m: Mesh, q: int, precision: int = CMCG_FP64) -> Space:
     h = P()
     _check(_lib.cmcg_space_create(m.h, q, precision, C.byref(h)))
-    return Space(h)
+    s = Space(h)
+    s.dim = cmcg_mesh_dim(m)
+    return s
 
 
 def cmcg_space_info(s: Space):
     q, Np, Nfp, K, nd = C.c_int(), C.c_int(), C.c_int(), C.c_int64(), C.c_int64()
     _check(_lib.cmcg_space_info(s.h, C.byref(q), C.byref(Np), C.byref(Nfp), C.byref(K), C.byref(nd)))
-    return dict(q=q.value, Np=Np.value, Nfp=Nfp.value, K=K.value, ndof=nd.value)
+    dim = getattr(s, "dim", 3)
+    return dict(q=q.value, Np=Np.value, Nfp=Nfp.value, K=K.value, ndof=nd.value, dim=dim,
+                ncomp=3 if dim == 2 else 6)
 
 
 def cmcg_space_nodes(s: Space) -> np.ndarray:
     i = cmcg_space_info(s)
-    out = np.empty((i["K"], i["Np"], 3))
+    out = np.empty((i["K"], i["Np"], i["dim"]))
     _check(_lib.cmcg_space_nodes(s.h, _ptr(out)))
     return out
 
@@ -254,7 +277,8 @@ def _f64(a):
 
 
 def cmcg_problem_create(s: Space, eps, mu, sigma=None, omega=2 * np.pi, j=None, g=None) -> Problem:
-    """j: complex [K,Np,3] nodal current density; g: complex [K,4,Nfp,3]."""
+    """j: complex [K,Np,3] nodal current density; g: complex [K,4,Nfp,3].
+    2-D spaces: j [K,Np] (the e component), g [K,3,Nfp]."""
     eps, mu, sigma = _f64(eps), _f64(mu), _f64(sigma)
     jr = ji = gr = gi = None
     if j is not None:
@@ -334,8 +358,10 @@ def cmcg_solve_batch(problems, opts: cmcg_options | None = None, stream=None):
     return [Result(P(res[b]), keep=(problems[b],)) for b in range(n)]
 
 
-def cmcg_result_fields(r: Result, K: int, Np: int):
-    out = [np.empty((K, Np, 3)) for _ in range(4)]
+def cmcg_result_fields(r: Result, K: int, Np: int, dim: int = 3):
+    """(e, h) complex at the nodes: [K,Np,3] each, or in 2-D e [K,Np], h [K,Np,2]."""
+    shapes = [(K, Np, 3)] * 4 if dim == 3 else [(K, Np), (K, Np), (K, Np, 2), (K, Np, 2)]
+    out = [np.empty(sh) for sh in shapes]
     _check(_lib.cmcg_result_fields(r.h, *[_ptr(a) for a in out]))
     e = out[0] + 1j * out[1]
     h = out[2] + 1j * out[3]

@@ -298,6 +298,7 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
     bt.B = B;
     bt.sp = probs[0] ? probs[0]->sp : nullptr;
     if (!bt.sp) fail(CMCG_ERR_ARG, "solve_batch: NULL problem");
+    if (bt.sp->dim == 2) fail(CMCG_ERR_ARG, "solve_batch: 2-D problems are solved singly");
     if (o->runup < 0) fail(CMCG_ERR_ARG, "options: runup must be >= 0");
     for (int b = 0; b < B; ++b) {
         if (!probs[b]) fail(CMCG_ERR_ARG, "solve_batch: NULL problem");

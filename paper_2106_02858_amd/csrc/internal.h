@@ -47,8 +47,28 @@ const RefElem& ref_elem(int q);
 // j carries my face local vertex perm3[p][j]
 extern const int perm3[6][3];
 
+// Reference P_q triangle of the 2-D transverse-magnetic space (Section 5.1,
+// two-dimensional setting): nodes (i, j)/q with j slowest, edge f opposite
+// vertex f, edge nodes listed from the edge's lower-numbered vertex.
+inline int np2_of(int q) { return (q + 1) * (q + 2) / 2; }
+inline int nfp2_of(int q) { return q + 1; }
+struct RefElem2D {
+    int q, Np, Nfp;
+    std::vector<double> xi;      // [Np][2]
+    std::vector<double> M;       // [Np][Np] mass, unit-area element
+    std::vector<double> D;       // [2][Np][Np] d/dxi_a at nodes
+    std::vector<double> LIFT;    // [Np][3 Nfp] M^-1 E_f, unit-length edges
+    std::vector<int> fnode;      // [3][Nfp] element node of edge node k
+};
+const RefElem2D& ref_elem2d(int q);
+
 // ----------------------------------------------------------------- mesh
+// dim 3: tetrahedra, 4 faces; dim 2: triangles, 3 edges (the per-face arrays
+// then hold 3 entries per element, xyz 2 per vertex, G 4 per element, normal
+// 2 per face, area = edge length, vol = triangle area, rho = inscribed-circle
+// diameter, perm = 1 when the neighbour runs the edge the other way).
 struct MeshData {
+    int dim = 3;
     int64_t nv = 0, K = 0;
     std::vector<double> xyz;     // [nv][3]
     std::vector<int64_t> tet;    // [K][4]
@@ -68,6 +88,8 @@ struct MeshData {
 // Layout per element: G[9] | per face f: n[3], cE1, cE2, cH1, cH2 (28) |
 // 1/eps, 1/mu, sigma/eps  -> 40 values.
 constexpr int kGeo = 40;
+// 2-D: G[4] | per edge f: n[2], cE1, cE2, cH1, cH2 (18) | 1/eps, 1/mu, sigma/eps.
+constexpr int kGeo2 = 25;
 
 }  // namespace cmcg
 

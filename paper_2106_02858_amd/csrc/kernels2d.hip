@@ -1,0 +1,452 @@
+// Kernels of the 2-D transverse-magnetic path (Section 5.1, two-dimensional
+// setting; Section 5.2 DG scheme on triangles; Section 5.3 Runge-Kutta
+// stages): fields (e, h1, h2), dof layout [K][3][Np].
+//
+// Stage kernel: one 64-lane workgroup per block of 21 triangles, lane =
+// (triangle, component).  The block's stage input is staged in LDS with one
+// coalesced load; each lane differentiates its own component (D_a y with
+// uniform matrix operands from constant memory), and the curl terms are
+// exchanged between the three lanes of a triangle:
+//   e row:  -scurl h = -(d1 h2 - d2 h1),   h1 row: d2 e,   h2 row: -d1 e.
+// The upwind flux of the lane's component is formed at the Nfp nodes of each
+// edge (own traces from LDS, neighbour traces from the field) and lifted with
+// LIFT.  The Runge-Kutta update, the compensated FP32 state and the filter
+// accumulation follow the stage modes of launch.h, as in the 3-D kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "internal.h"
+#include "launch.h"
+
+namespace cmcg {
+
+namespace {
+
+template <int Q> struct Dim2 {
+    static constexpr int NP = (Q + 1) * (Q + 2) / 2;
+    static constexpr int NFP = Q + 1;
+    static constexpr int MAT = 2 * NP * NP + NP * 3 * NFP + NP * NP;  // D | LIFT | M
+};
+constexpr int mat2_off(int q) { return q <= 1 ? 0 : q == 2 ? Dim2<1>::MAT : Dim2<1>::MAT + Dim2<2>::MAT; }
+constexpr int kMat2Total = Dim2<1>::MAT + Dim2<2>::MAT + Dim2<3>::MAT;
+
+__constant__ double c2Mat64[kMat2Total];
+__constant__ float c2Mat32[kMat2Total];
+
+template <typename T> __device__ __forceinline__ const T* mats2();
+template <> __device__ __forceinline__ const double* mats2<double>() { return c2Mat64; }
+template <> __device__ __forceinline__ const float* mats2<float>() { return c2Mat32; }
+
+constexpr int EPB = 21;  // triangles per 64-lane workgroup (63 active lanes)
+
+// Element node of edge node k of edge f (nodes (i, j)/q, j slowest; edge 0 runs
+// from vertex 1 to vertex 2, edge 1 from 0 to 2, edge 2 from 0 to 1).
+template <int Q> __device__ __host__ constexpr int edge_node(int f, int k) {
+    // node (i, j) has index j (Q + 1) - j (j - 1) / 2 + i
+    return f == 0 ? k * (Q + 1) - k * (k - 1) / 2 + (Q - k) : f == 1 ? k * (Q + 1) - k * (k - 1) / 2 : k;
+}
+
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint32_t h) { return __uint_as_float(h << 16); }
+
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+template <typename T, int Q>
+__global__ __launch_bounds__(64) void k_stage2d(StageArgs a, int64_t per) {
+    constexpr int NP = Dim2<Q>::NP, NFP = Dim2<Q>::NFP, NF3 = 3 * NFP;
+    constexpr int MO = mat2_off(Q);
+    constexpr int LO = MO + 2 * NP * NP;  // LIFT [NP][3 NFP]
+    constexpr int ROWS = EPB * 3;
+    __shared__ T sY[ROWS * NP];
+    __shared__ T sG[EPB * kGeo2];
+    __shared__ int sC[EPB * 3];
+
+    const int64_t b = blockIdx.x;
+    const int64_t blk = (b & 7) * per + (b >> 3);  // consecutive blocks on one XCD
+    const int64_t e0 = blk * EPB;
+    if (e0 >= a.K) return;
+    const int lane = threadIdx.x;
+    const int ne = (int)((a.K - e0) < EPB ? (a.K - e0) : EPB);
+    const T* __restrict__ Y = (const T*)a.Y;
+    const T* __restrict__ geo = (const T*)a.geo;
+    {
+        const int nv = ne * 3 * NP;
+        const T* src = Y + e0 * 3 * NP;
+        for (int v = lane; v < nv; v += 64) sY[v] = src[v];
+        const int ng = ne * kGeo2;
+        for (int v = lane; v < ng; v += 64) sG[v] = geo[e0 * kGeo2 + v];
+        for (int v = lane; v < ne * 3; v += 64) sC[v] = a.conn[e0 * 3 + v];
+    }
+    __syncthreads();
+
+    const int el = lane / 3;
+    const int c = lane - 3 * el;
+    const bool act = el < ne;
+    const int elc = act ? el : 0;
+    const int row = elc * 3 + c;
+    const int64_t grow = (e0 * 3 + row) * NP;
+    const int mode = a.mode;
+    constexpr bool COMP = std::is_same<T, float>::value;
+    const bool needL = COMP && (mode == RK2_S2 || mode == RK4_S4);
+    const bool needU = mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || needL;
+    const bool needA = mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4;
+    const T* Mt = mats2<T>();
+    const T* gg = &sG[elc * kGeo2];
+
+    // ---- volume: physical derivatives of the lane's component
+    T y[NP], d1[NP], d2[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) y[j] = sY[row * NP + j];
+    const T g00 = gg[0], g01 = gg[1], g10 = gg[2], g11 = gg[3];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        T r0 = T(0), r1 = T(0);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            r0 = fma(Mt[MO + i * NP + j], y[j], r0);
+            r1 = fma(Mt[MO + NP * NP + i * NP + j], y[j], r1);
+        }
+        d1[i] = fma(g00, r0, g10 * r1);
+        d2[i] = fma(g01, r0, g11 * r1);
+    }
+    // curl exchange between the triangle's lanes (3 el: e, 3 el + 1: h1, 3 el + 2: h2)
+    const int base = 3 * elc;
+    const int srcA = c == 0 ? base + 2 : base;  // lane whose d1 is taken
+    const int srcB = c == 0 ? base + 1 : base;  // lane whose d2 is taken
+    const T sa = c == 1 ? T(0) : T(-1);
+    const T sb = c == 2 ? T(0) : T(1);
+    T acc[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const T A = __shfl(d1[i], srcA);
+        const T B = __shfl(d2[i], srcB);
+        acc[i] = sa * A + sb * B;
+    }
+
+    // ---- upwind flux of the lane's component on each edge, lifted
+#pragma unroll 1
+    for (int f = 0; f < 3; ++f) {
+        const int code = sC[elc * 3 + f];
+        const T* g = &gg[4 + 6 * f];
+        const T n0 = g[0], n1 = g[1];
+        const T cE1 = g[2], cE2 = g[3], cH1 = g[4], cH2 = g[5];
+        T fl[NFP];
+#pragma unroll
+        for (int k = 0; k < NFP; ++k) {
+            const int own = edge_node<Q>(f, k);
+            const T em = sY[(elc * 3) * NP + own];
+            const T h1m = sY[(elc * 3 + 1) * NP + own];
+            const T h2m = sY[(elc * 3 + 2) * NP + own];
+            T ep, h1p, h2p;
+            if (code >= 0) {
+                const int64_t nb = code >> 5;
+                const int nf = (code >> 3) & 3;
+                const int kk = (code & 7) ? NFP - 1 - k : k;
+                const int64_t o = nb * 3 * NP + edge_node<Q>(nf, kk);
+                ep = Y[o];
+                h1p = Y[o + NP];
+                h2p = Y[o + 2 * NP];
+            } else if (code == -1) {  // PEC ghost: e+ = -e-, h+ = h-
+                ep = -em;
+                h1p = h1m;
+                h2p = h2m;
+            } else {  // impedance ghost (homogeneous part): zero exterior state
+                ep = T(0);
+                h1p = T(0);
+                h2p = T(0);
+            }
+            const T de = ep - em, dh1 = h1p - h1m, dh2 = h2p - h2m;
+            if (c == 0) {
+                fl[k] = cE1 * de - cE2 * (n0 * dh2 - n1 * dh1);
+            } else {
+                const T ndh = n0 * dh1 + n1 * dh2;
+                fl[k] = c == 1 ? cH1 * (dh1 - ndh * n0) + cH2 * (n1 * de) : cH1 * (dh2 - ndh * n1) - cH2 * (n0 * de);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            T s = acc[i];
+#pragma unroll
+            for (int k = 0; k < NFP; ++k) s = fma(Mt[LO + i * NF3 + f * NFP + k], fl[k], s);
+            acc[i] = s;
+        }
+    }
+    if (!act) return;
+
+    // ---- stage update of the lane's row
+    const T inv = c == 0 ? gg[22] : gg[23];
+    const T sig = c == 0 ? gg[24] : T(0);
+    T kv[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) kv[i] = fma(inv, acc[i], -sig * y[i]);
+    if (c < a.src_rows) {
+        const T* sr = (const T*)a.Sre + grow;
+        const T* si = (const T*)a.Sim + grow;
+        const T scos = (T)a.scos, ssin = (T)a.ssin;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) kv[i] += scos * sr[i] - ssin * si[i];
+    }
+    T up[NP], ap[NP];
+    float lo[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        up[i] = needU ? ((const T*)a.U)[grow + i] : T(0);
+        ap[i] = needA ? ((const T*)a.Acc)[grow + i] : T(0);
+        lo[i] = needL ? from_bf16(((const uint16_t*)a.Ulo)[grow + i]) : 0.f;
+    }
+    const T cy = (T)a.cy, ca = (T)a.ca, cu = (T)a.cu;
+    T* Ynext = (T*)a.Ynext + grow;
+    T* Acc = (T*)a.Acc + grow;
+    T* Uout = (T*)a.Uout + grow;
+    switch (mode) {
+        case RK2_S1:
+#pragma unroll
+            for (int i = 0; i < NP; ++i) Ynext[i] = fma(cy, kv[i], y[i]);
+            break;
+        case RK2_S2:
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                if constexpr (COMP) {
+                    float s, e;
+                    two_sum(up[i], fma(cu, kv[i], lo[i]), s, e);
+                    Uout[i] = s;
+                    ((uint16_t*)a.Ulo)[grow + i] = to_bf16(e);
+                } else {
+                    Uout[i] = fma(cu, kv[i], up[i]);
+                }
+            }
+            break;
+        case RK4_S1:
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                Ynext[i] = fma(cy, kv[i], y[i]);
+                Acc[i] = COMP ? ca * kv[i] : fma(ca, kv[i], y[i]);
+            }
+            break;
+        case RK4_S2:
+        case RK4_S3:
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                Ynext[i] = fma(cy, kv[i], up[i]);
+                Acc[i] = fma(ca, kv[i], ap[i]);
+            }
+            break;
+        case RK4_S4:
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                if constexpr (COMP) {
+                    float s, e;
+                    two_sum(up[i], fma(cu, kv[i], ap[i]) + lo[i], s, e);
+                    Uout[i] = s;
+                    ((uint16_t*)a.Ulo)[grow + i] = to_bf16(e);
+                } else {
+                    Uout[i] = fma(cu, kv[i], ap[i]);
+                }
+            }
+            break;
+        default: {
+            T* Ko = (T*)a.Kout + grow;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) Ko[i] = kv[i];
+            break;
+        }
+    }
+    if (a.filter) {
+        double* fr = a.Fre + grow;
+        double* fi = a.Fim + grow;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const double ud = (double)y[i], kd = (double)kv[i];
+            fr[i] += a.fa_re * ud + a.fb_re * kd;
+            fi[i] += a.fa_im * ud + a.fb_im * kd;
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_to_field2d(const double* __restrict__ X, T* __restrict__ U, uint16_t* __restrict__ Ulo, int64_t n,
+                             int Np, int flipH) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double x = X[i];
+        if (flipH && ((i / Np) % 3) >= 1) x = -x;
+        const T hi = (T)x;
+        U[i] = hi;
+        if constexpr (std::is_same<T, float>::value)
+            if (Ulo) Ulo[i] = to_bf16((float)(x - (double)hi));
+    }
+}
+
+template <typename T>
+__global__ void k_from_field2d(const T* __restrict__ U, const uint16_t* __restrict__ Ulo, double* __restrict__ Yo,
+                               const double* __restrict__ sub, int64_t n, int Np, int flipH) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double x = (double)U[i];
+        if constexpr (std::is_same<T, float>::value)
+            if (Ulo) x += (double)from_bf16(Ulo[i]);
+        if (flipH && ((i / Np) % 3) >= 1) x = -x;
+        if (sub) x -= sub[i];
+        Yo[i] = x;
+    }
+}
+
+constexpr int kDot2Blocks = 1024;
+constexpr int kDot2Threads = 256;
+
+// (U, V)_{eps,mu} per block over rows r = 3 e + c (weight wE for c = 0, wH
+// otherwise), fixed decomposition; k_dot2d_final sums the partials in a
+// fixed order, so the result does not depend on scheduling.
+template <int Q>
+__global__ __launch_bounds__(kDot2Threads) void k_dot2d(const double* __restrict__ U, const double* __restrict__ V,
+                                                        const double* __restrict__ wE, const double* __restrict__ wH,
+                                                        int64_t K, double* __restrict__ partial) {
+    constexpr int NP = Dim2<Q>::NP;
+    constexpr int MMO = mat2_off(Q) + 2 * NP * NP + NP * 3 * Dim2<Q>::NFP;
+    __shared__ double sm[kDot2Threads];
+    double acc = 0.0;
+    const int64_t rows = 3 * K;
+    for (int64_t r = blockIdx.x * (int64_t)kDot2Threads + threadIdx.x; r < rows;
+         r += (int64_t)gridDim.x * kDot2Threads) {
+        const double* u = U + r * NP;
+        const double* v = V + r * NP;
+        double vv[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) vv[j] = v[j];
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            double mvv = 0.0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) mvv = fma(c2Mat64[MMO + i * NP + j], vv[j], mvv);
+            s = fma(u[i], mvv, s);
+        }
+        const int64_t e = r / 3;
+        acc = fma(s, (r - 3 * e) == 0 ? wE[e] : wH[e], acc);
+    }
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kDot2Threads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(kDot2Threads) void k_dot2d_final(const double* __restrict__ partial, int n,
+                                                              double* __restrict__ out) {
+    __shared__ double sm[kDot2Threads];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += kDot2Threads) acc += partial[i];
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kDot2Threads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sm[0];
+}
+
+unsigned grid2_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+void check2() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(CMCG_ERR_DEVICE, std::string("2-D kernel launch: ") + hipGetErrorString(e));
+}
+
+template <typename T, int Q>
+void stage2d(const StageArgs& a, hipStream_t s) {
+    const int64_t nb = (a.K + EPB - 1) / EPB;
+    const int64_t per = (nb + 7) / 8;
+    if (8 * per > 0x7fffffffLL) fail(CMCG_ERR_ARG, "stage2d: too many element blocks");
+    hipLaunchKernelGGL((k_stage2d<T, Q>), dim3((unsigned)(8 * per)), dim3(64), 0, s, a, per);
+}
+
+}  // namespace
+
+int64_t stage2d_blocks(int64_t K) { return (K + EPB - 1) / EPB; }
+
+void upload_constants2d(int q, const double* D, const double* LIFT, const double* M, const int* fnode) {
+    const int NP = np2_of(q), NFP = nfp2_of(q);
+    for (int f = 0; f < 3; ++f)
+        for (int k = 0; k < NFP; ++k) {
+            const int want = q == 1 ? edge_node<1>(f, k) : q == 2 ? edge_node<2>(f, k) : edge_node<3>(f, k);
+            if (fnode[f * NFP + k] != want) fail(CMCG_ERR_ARG, "2-D edge-node table does not match the kernels");
+        }
+    const int n = 2 * NP * NP + NP * 3 * NFP + NP * NP;
+    std::vector<double> buf(n);
+    std::copy(D, D + 2 * NP * NP, buf.begin());
+    std::copy(LIFT, LIFT + NP * 3 * NFP, buf.begin() + 2 * NP * NP);
+    std::copy(M, M + NP * NP, buf.begin() + 2 * NP * NP + 3 * NP * NFP);
+    std::vector<float> bf(buf.begin(), buf.end());
+    const size_t off = mat2_off(q);
+    CMCG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c2Mat64), buf.data(), n * sizeof(double), off * sizeof(double),
+                               hipMemcpyHostToDevice));
+    CMCG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c2Mat32), bf.data(), n * sizeof(float), off * sizeof(float),
+                               hipMemcpyHostToDevice));
+}
+
+void launch_stage2d(int q, int precision, const StageArgs& a, hipStream_t s) {
+    if (a.mtab) fail(CMCG_ERR_ARG, "stage2d: batched launches are not supported in 2-D");
+    if (precision == CMCG_FP64) {
+        if (q == 1) stage2d<double, 1>(a, s);
+        else if (q == 2) stage2d<double, 2>(a, s);
+        else stage2d<double, 3>(a, s);
+    } else {
+        if (q == 1) stage2d<float, 1>(a, s);
+        else if (q == 2) stage2d<float, 2>(a, s);
+        else stage2d<float, 3>(a, s);
+    }
+    check2();
+}
+
+void launch_to_field2d(int precision, int Np, const double* X, void* U, void* Ulo, int64_t n, int flipH,
+                       hipStream_t s) {
+    if (precision == CMCG_FP64)
+        hipLaunchKernelGGL(k_to_field2d<double>, dim3(grid2_for(n)), dim3(256), 0, s, X, (double*)U, nullptr, n, Np,
+                           flipH);
+    else
+        hipLaunchKernelGGL(k_to_field2d<float>, dim3(grid2_for(n)), dim3(256), 0, s, X, (float*)U, (uint16_t*)Ulo, n,
+                           Np, flipH);
+    check2();
+}
+
+void launch_from_field2d(int precision, int Np, const void* U, const void* Ulo, double* Y, const double* sub,
+                         int64_t n, int flipH, hipStream_t s) {
+    if (precision == CMCG_FP64)
+        hipLaunchKernelGGL(k_from_field2d<double>, dim3(grid2_for(n)), dim3(256), 0, s, (const double*)U, nullptr, Y,
+                           sub, n, Np, flipH);
+    else
+        hipLaunchKernelGGL(k_from_field2d<float>, dim3(grid2_for(n)), dim3(256), 0, s, (const float*)U,
+                           (const uint16_t*)Ulo, Y, sub, n, Np, flipH);
+    check2();
+}
+
+void launch_dot2d(int q, const double* U, const double* V, const double* wE, const double* wH, int64_t K,
+                  double* partial, double* out_dev, hipStream_t s) {
+    if (q == 1)
+        hipLaunchKernelGGL(k_dot2d<1>, dim3(kDot2Blocks), dim3(kDot2Threads), 0, s, U, V, wE, wH, K, partial);
+    else if (q == 2)
+        hipLaunchKernelGGL(k_dot2d<2>, dim3(kDot2Blocks), dim3(kDot2Threads), 0, s, U, V, wE, wH, K, partial);
+    else
+        hipLaunchKernelGGL(k_dot2d<3>, dim3(kDot2Blocks), dim3(kDot2Threads), 0, s, U, V, wE, wH, K, partial);
+    hipLaunchKernelGGL(k_dot2d_final, dim3(1), dim3(kDot2Threads), 0, s, partial, kDot2Blocks, out_dev);
+    check2();
+}
+
+}  // namespace cmcg

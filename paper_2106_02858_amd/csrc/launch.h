@@ -116,4 +116,18 @@ void launch_filter_add_batch(int precision, const void* U, const double* w_re, c
 // non-finite check: out_dev[0] = 1 if any entry of X is not finite
 void launch_nonfinite(const double* X, int64_t n, int* out_dev, hipStream_t s);
 
+// 2-D transverse-magnetic path (kernels2d.hip): fields (e, h1, h2), dof layout
+// [K][3][Np], geometry [K][kGeo2], connectivity [K][3] (perm bit: the
+// neighbour runs the edge the other way); the same stage modes and
+// compensated FP32 state as the 3-D kernels; single problems only.
+void upload_constants2d(int q, const double* D, const double* LIFT, const double* M, const int* fnode);
+void launch_stage2d(int q, int precision, const StageArgs& a, hipStream_t s);
+void launch_to_field2d(int precision, int Np, const double* X, void* U, void* Ulo, int64_t n, int flipH,
+                       hipStream_t s);
+void launch_from_field2d(int precision, int Np, const void* U, const void* Ulo, double* Y, const double* sub,
+                         int64_t n, int flipH, hipStream_t s);
+void launch_dot2d(int q, const double* U, const double* V, const double* wE, const double* wH, int64_t K,
+                  double* partial, double* out_dev, hipStream_t s);
+int64_t stage2d_blocks(int64_t K);
+
 }  // namespace cmcg

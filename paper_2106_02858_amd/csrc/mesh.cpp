@@ -204,4 +204,101 @@ std::shared_ptr<MeshData> build_mesh(int64_t nv, const double* xyz, int64_t K, c
     return m;
 }
 
+// Triangle meshes of the 2-D transverse-magnetic setting (Section 5.1): edges
+// matched through their sorted vertex pair; normals are the edge directions
+// turned a quarter turn away from the opposite vertex; rho_K = 4 |K| /
+// perimeter, the diameter of the inscribed circle.
+std::shared_ptr<MeshData> build_mesh2d(int64_t nv, const double* xy, int64_t K, const int64_t* tri,
+                                       const int8_t* edge_tag) {
+    if (!xy || !tri) fail(CMCG_ERR_ARG, "mesh2d: NULL coordinates or connectivity");
+    if (nv < 3 || K < 1) fail(CMCG_ERR_ARG, "mesh2d: need nv >= 3 and K >= 1");
+    if (K >= (int64_t(1) << 26)) fail(CMCG_ERR_ARG, "mesh2d: K must be below 2^26");
+    for (int64_t i = 0; i < 3 * K; ++i)
+        if (tri[i] < 0 || tri[i] >= nv) fail(CMCG_ERR_ARG, "mesh2d: vertex index out of range");
+    auto m = std::make_shared<MeshData>();
+    m->dim = 2;
+    m->nv = nv;
+    m->K = K;
+    m->xyz.assign(xy, xy + 2 * nv);
+    m->tet.assign(tri, tri + 3 * K);
+    m->tag.assign(3 * K, 0);
+    m->nbr.assign(3 * K, -1);
+    m->nbr_face.assign(3 * K, -1);
+    m->perm.assign(3 * K, 0);
+    m->G.resize(4 * K);
+    m->vol.resize(K);
+    m->normal.resize(6 * K);
+    m->area.resize(3 * K);
+    m->rho.resize(K);
+    for (int64_t e = 0; e < K; ++e) {
+        const double* v[3] = {&xy[2 * tri[3 * e]], &xy[2 * tri[3 * e + 1]], &xy[2 * tri[3 * e + 2]]};
+        const double J00 = v[1][0] - v[0][0], J01 = v[2][0] - v[0][0];
+        const double J10 = v[1][1] - v[0][1], J11 = v[2][1] - v[0][1];
+        const double det = J00 * J11 - J01 * J10;
+        const double scale = std::fmax(std::fmax(std::fabs(J00), std::fabs(J01)), std::fmax(std::fabs(J10), std::fabs(J11)));
+        if (!(std::fabs(det) > 1e-14 * scale * scale))
+            fail(CMCG_ERR_MESH, "mesh2d: degenerate triangle " + std::to_string(e));
+        // rows of the inverse Jacobian: grad xi_1, grad xi_2
+        m->G[4 * e + 0] = J11 / det;
+        m->G[4 * e + 1] = -J01 / det;
+        m->G[4 * e + 2] = -J10 / det;
+        m->G[4 * e + 3] = J00 / det;
+        m->vol[e] = 0.5 * std::fabs(det);
+        double per = 0;
+        for (int f = 0; f < 3; ++f) {
+            const int a = f == 0 ? 1 : 0, b = f == 2 ? 1 : 2;
+            const double tx = v[b][0] - v[a][0], ty = v[b][1] - v[a][1];
+            const double L = std::sqrt(tx * tx + ty * ty);
+            double nx = ty / L, ny = -tx / L;
+            if (nx * (v[f][0] - v[a][0]) + ny * (v[f][1] - v[a][1]) > 0) {
+                nx = -nx;
+                ny = -ny;
+            }
+            m->normal[6 * e + 2 * f] = nx;
+            m->normal[6 * e + 2 * f + 1] = ny;
+            m->area[3 * e + f] = L;
+            per += L;
+        }
+        m->rho[e] = 4.0 * m->vol[e] / per;
+    }
+    std::unordered_map<TriKey, int64_t, TriHash> open;
+    open.reserve(2 * K + 16);
+    for (int64_t e = 0; e < K; ++e)
+        for (int f = 0; f < 3; ++f) {
+            const int a = f == 0 ? 1 : 0, b = f == 2 ? 1 : 2;
+            const int64_t ga = tri[3 * e + a], gb = tri[3 * e + b];
+            if (ga == gb || tri[3 * e + f] == ga || tri[3 * e + f] == gb)
+                fail(CMCG_ERR_MESH, "mesh2d: repeated vertex in triangle " + std::to_string(e));
+            TriKey key{std::min(ga, gb), std::max(ga, gb), -1};
+            auto it = open.find(key);
+            if (it == open.end()) {
+                open.emplace(key, 3 * e + f);
+                continue;
+            }
+            const int64_t other = it->second;
+            if (other < 0) fail(CMCG_ERR_MESH, "mesh2d: edge shared by more than two triangles");
+            const int64_t e2 = other / 3;
+            const int f2 = (int)(other % 3);
+            it->second = -1;
+            const int a2 = f2 == 0 ? 1 : 0;
+            const int rev = tri[3 * e2 + a2] != ga ? 1 : 0;  // the neighbour starts the edge at my other end
+            m->nbr[3 * e + f] = e2;
+            m->nbr_face[3 * e + f] = (int8_t)f2;
+            m->perm[3 * e + f] = (int8_t)rev;
+            m->nbr[3 * e2 + f2] = e;
+            m->nbr_face[3 * e2 + f2] = (int8_t)f;
+            m->perm[3 * e2 + f2] = (int8_t)rev;
+        }
+    for (int64_t i = 0; i < 3 * K; ++i) {
+        if (m->nbr[i] >= 0) continue;
+        ++m->n_boundary;
+        const int t = edge_tag ? edge_tag[i] : CMCG_TAG_IMPEDANCE;
+        if (t != CMCG_TAG_PEC && t != CMCG_TAG_IMPEDANCE)
+            fail(CMCG_ERR_MESH, "mesh2d: boundary edge without PEC / impedance tag (element " +
+                                    std::to_string(i / 3) + ", edge " + std::to_string(i % 3) + ")");
+        m->tag[i] = (int8_t)t;
+    }
+    return m;
+}
+
 }  // namespace cmcg

@@ -60,6 +60,7 @@ struct HostPinned {
 
 struct SpaceData {
     std::shared_ptr<MeshData> mesh;
+    int dim = 3;  // 3: tetrahedra, fields [K][6][Np]; 2: triangles (TM), fields [K][3][Np]
     int q = 1, Np = 4, Nfp = 3, precision = CMCG_FP64, device = 0;
     int64_t K = 0, ndof = 0;
     std::vector<int32_t> conn_h;
@@ -161,7 +162,7 @@ bool apply_tuned_variant(int device, int q, int precision, int64_t K, int member
 void remember_tuned_variant(int device, int q, int precision, int64_t K, int members, int variant);
 
 // helpers defined in solver.cpp
-void ensure_constants(int device, int q);
+void ensure_constants(int device, int q, int dim = 3);
 int current_device();
 StepCfg step_config(const cmcg_problem* p, const cmcg_options* o);
 void hermite_weights(double omega, double dt, std::complex<double> xi[4]);

@@ -1,5 +1,6 @@
 // Reference P_q tetrahedron for the nodal DG space (Section 5.2, nodal basis
-// of P_q(T_h) lifted from triangles to tetrahedra).
+// of P_q(T_h) lifted from triangles to tetrahedra), and the P_q triangle of
+// the 2-D transverse-magnetic space (Section 5.1).
 //
 // Construction (long double): nodal basis from a Cartesian monomial
 // Vandermonde at the equispaced nodes; differentiation matrices from the
@@ -226,7 +227,115 @@ RefElem build(int q) {
     return r;
 }
 
+// Reference triangle: the same construction in two variables.  Edge f is
+// opposite vertex f; its nodes run from its lower-numbered vertex.
+RefElem2D build2d(int q) {
+    RefElem2D r;
+    r.q = q;
+    r.Np = np2_of(q);
+    r.Nfp = nfp2_of(q);
+    const int Np = r.Np, Nfp = r.Nfp;
+    std::vector<int> lab;  // (i, j), j slowest
+    for (int j = 0; j <= q; ++j)
+        for (int i = 0; i <= q - j; ++i) {
+            lab.push_back(i);
+            lab.push_back(j);
+        }
+    std::vector<LD> xi(2 * Np);
+    r.xi.resize(2 * Np);
+    for (int n = 0; n < 2 * Np; ++n) {
+        xi[n] = (LD)lab[n] / q;
+        r.xi[n] = (double)xi[n];
+    }
+    std::vector<int> ex;  // monomials x^a y^b, a + b <= q
+    for (int a = 0; a <= q; ++a)
+        for (int b = 0; b <= q - a; ++b) {
+            ex.push_back(a);
+            ex.push_back(b);
+        }
+    auto mono = [&](int m, LD x, LD y) { return std::pow(x, ex[2 * m]) * std::pow(y, ex[2 * m + 1]); };
+    std::vector<LD> V(Np * Np);
+    for (int n = 0; n < Np; ++n)
+        for (int m = 0; m < Np; ++m) V[n * Np + m] = mono(m, xi[2 * n], xi[2 * n + 1]);
+    const std::vector<LD> Vinv = invert(V, Np);
+    auto phi = [&](LD x, LD y, LD* out) {
+        for (int nn = 0; nn < Np; ++nn) {
+            LD t = 0;
+            for (int m = 0; m < Np; ++m) t += Vinv[m * Np + nn] * mono(m, x, y);
+            out[nn] = t;
+        }
+    };
+    r.D.assign(2 * Np * Np, 0);
+    for (int a = 0; a < 2; ++a)
+        for (int i = 0; i < Np; ++i)
+            for (int j = 0; j < Np; ++j) {
+                LD t = 0;
+                for (int m = 0; m < Np; ++m) {
+                    const int e = ex[2 * m + a];
+                    if (e == 0) continue;
+                    const LD x = xi[2 * i], y = xi[2 * i + 1];
+                    const LD d = a == 0 ? e * std::pow(x, e - 1) * std::pow(y, ex[2 * m + 1])
+                                        : e * std::pow(y, e - 1) * std::pow(x, ex[2 * m]);
+                    t += Vinv[m * Np + j] * d;
+                }
+                r.D[(a * Np + i) * Np + j] = (double)t;
+            }
+    // mass: 2 * int over the unit triangle (area 1/2), collapsed coordinates
+    std::vector<LD> gx, gw;
+    gauss01(q + 3, gx, gw);
+    std::vector<LD> M(Np * Np, 0), ph(Np);
+    for (size_t a = 0; a < gx.size(); ++a)
+        for (size_t b = 0; b < gx.size(); ++b) {
+            const LD u = gx[a], v = gx[b] * (1 - gx[a]);
+            const LD w = gw[a] * gw[b] * (1 - gx[a]) * 2;
+            phi(u, v, ph.data());
+            for (int i = 0; i < Np; ++i)
+                for (int j = 0; j < Np; ++j) M[i * Np + j] += w * ph[i] * ph[j];
+        }
+    r.M.resize(Np * Np);
+    for (int i = 0; i < Np * Np; ++i) r.M[i] = (double)M[i];
+    const std::vector<LD> Minv = invert(M, Np);
+    const LD V3[3][2] = {{0, 0}, {1, 0}, {0, 1}};
+    r.fnode.assign(3 * Nfp, -1);
+    r.LIFT.assign(Np * 3 * Nfp, 0);
+    for (int f = 0; f < 3; ++f) {
+        const int va = f == 0 ? 1 : 0, vb = f == 2 ? 1 : 2;
+        // edge nodes ordered by their distance from va
+        int cnt = 0;
+        for (int k = 0; k <= q; ++k)
+            for (int n = 0; n < Np; ++n) {
+                const int bl[3] = {q - lab[2 * n] - lab[2 * n + 1], lab[2 * n], lab[2 * n + 1]};
+                if (bl[f] == 0 && bl[vb] == k) r.fnode[f * Nfp + cnt++] = n;
+            }
+        if (cnt != Nfp) fail(CMCG_ERR_ARG, "edge node count");
+        // edge mass per unit length
+        std::vector<LD> E(Np * Np, 0);
+        for (size_t a = 0; a < gx.size(); ++a) {
+            const LD t = gx[a];
+            phi(V3[va][0] + t * (V3[vb][0] - V3[va][0]), V3[va][1] + t * (V3[vb][1] - V3[va][1]), ph.data());
+            for (int i = 0; i < Np; ++i)
+                for (int j = 0; j < Np; ++j) E[i * Np + j] += gw[a] * ph[i] * ph[j];
+        }
+        for (int i = 0; i < Np; ++i)
+            for (int k = 0; k < Nfp; ++k) {
+                LD t = 0;
+                const int col = r.fnode[f * Nfp + k];
+                for (int j = 0; j < Np; ++j) t += Minv[i * Np + j] * E[j * Np + col];
+                r.LIFT[i * 3 * Nfp + f * Nfp + k] = (double)t;
+            }
+    }
+    return r;
+}
+
 }  // namespace
+
+const RefElem2D& ref_elem2d(int q) {
+    static RefElem2D cache[kMaxQ + 1];
+    static std::once_flag once[kMaxQ + 1];
+    if (q < 1 || q > kMaxQ) fail(CMCG_ERR_ARG, "q must be 1, 2 or 3");
+    std::call_once(once[q], [q] { cache[q] = build2d(q); });
+    return cache[q];
+}
 
 const RefElem& ref_elem(int q) {
     static RefElem cache[kMaxQ + 1];

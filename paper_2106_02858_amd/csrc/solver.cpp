@@ -25,17 +25,27 @@ void set_last_error(const std::string& msg) { g_last_error = msg; }
 
 std::shared_ptr<MeshData> build_mesh(int64_t nv, const double* xyz, int64_t K, const int64_t* tet,
                                      const int8_t* face_tag);
+std::shared_ptr<MeshData> build_mesh2d(int64_t nv, const double* xy, int64_t K, const int64_t* tri,
+                                       const int8_t* edge_tag);
 void locality_order(int64_t nv, const double* xyz, int64_t K, const int64_t* tet, int64_t* order);
 
 // ----------------------------------------------------------- device constants
 namespace {
 std::mutex g_const_mu;
 bool g_const_done[64][kMaxQ + 1];
+bool g_const2_done[64][kMaxQ + 1];
 }
 
-void ensure_constants(int device, int q) {
+void ensure_constants(int device, int q, int dim) {
     std::lock_guard<std::mutex> lk(g_const_mu);
     if (device < 0 || device >= 64) fail(CMCG_ERR_DEVICE, "device index out of range");
+    if (dim == 2) {
+        if (g_const2_done[device][q]) return;
+        const RefElem2D& r = ref_elem2d(q);
+        upload_constants2d(q, r.D.data(), r.LIFT.data(), r.M.data(), r.fnode.data());
+        g_const2_done[device][q] = true;
+        return;
+    }
     if (g_const_done[device][q]) return;
     const RefElem& r = ref_elem(q);
     upload_constants(q, 0, r.D.data(), r.LIFT.data(), r.M.data(), r.fnode.data(), r.fperm.data());
@@ -75,11 +85,45 @@ void hermite_weights(double omega, double dt, std::complex<double> xi[4]) {
 namespace cmcg {
 
 // ------------------------------------------------------------- problem setup
+// 2-D: G[4] | per edge n[2], cE1, cE2, cH1, cH2 | 1/eps, 1/mu, sigma/eps
+static void build_geo2d(cmcg_problem* p, double alpha, std::vector<double>& g) {
+    const SpaceData& s = *p->sp;
+    const MeshData& m = *s.mesh;
+    const int64_t K = s.K;
+    g.assign(kGeo2 * K, 0.0);
+    for (int64_t e = 0; e < K; ++e) {
+        double* o = &g[kGeo2 * e];
+        for (int i = 0; i < 4; ++i) o[i] = m.G[4 * e + i];
+        const double Zm = std::sqrt(p->mu[e] / p->eps[e]);
+        for (int f = 0; f < 3; ++f) {
+            double* q = o + 4 + 6 * f;
+            q[0] = m.normal[6 * e + 2 * f];
+            q[1] = m.normal[6 * e + 2 * f + 1];
+            const int64_t nb = m.nbr[3 * e + f];
+            const double Zp = nb >= 0 ? std::sqrt(p->mu[nb] / p->eps[nb]) : Zm;
+            const double Ym = 1.0 / Zm, Yp = 1.0 / Zp;
+            const double al = (nb < 0 && m.tag[3 * e + f] == CMCG_TAG_IMPEDANCE) ? 1.0 : alpha;
+            const double fs = m.area[3 * e + f] / m.vol[e];
+            q[2] = fs * al / (Zm + Zp);
+            q[3] = fs * Zp / (Zm + Zp);
+            q[4] = fs * al / (Ym + Yp);
+            q[5] = fs * Yp / (Ym + Yp);
+        }
+        o[22] = 1.0 / p->eps[e];
+        o[23] = 1.0 / p->mu[e];
+        o[24] = p->sigma[e] / p->eps[e];
+    }
+}
+
 void build_geo(cmcg_problem* p, double alpha) {
     const SpaceData& s = *p->sp;
     const MeshData& m = *s.mesh;
     const int64_t K = s.K;
-    std::vector<double> g(kGeo * K);
+    std::vector<double> g;
+    if (s.dim == 2) {
+        build_geo2d(p, alpha, g);
+    } else {
+    g.assign(kGeo * K, 0.0);
     for (int64_t e = 0; e < K; ++e) {
         double* o = &g[kGeo * e];
         for (int i = 0; i < 9; ++i) o[i] = m.G[9 * e + i];
@@ -101,7 +145,8 @@ void build_geo(cmcg_problem* p, double alpha) {
         o[38] = 1.0 / p->mu[e];
         o[39] = p->sigma[e] / p->eps[e];
     }
-    p->geo.alloc(kGeo * K * s.esize());
+    }
+    p->geo.alloc(g.size() * s.esize());
     if (s.precision == CMCG_FP64) {
         CMCG_HIP(hipMemcpy(p->geo.p, g.data(), g.size() * 8, hipMemcpyHostToDevice));
     } else {
@@ -121,8 +166,66 @@ static void upload_field(const SpaceData& s, DevBuf& b, const std::vector<double
     }
 }
 
+// 2-D source: j [K][Np] on the e row; impedance data G [K][3][Nfp] through the
+// ghost e+ = G, h+ = 0 of the wall edges: flux_e = G / (2 Z), flux_h =
+// (n2 G, -n1 G) / 2, lifted with the edge scaling.
+static void build_source2d(cmcg_problem* p, const double* j_re, const double* j_im, const double* g_re,
+                           const double* g_im) {
+    const SpaceData& s = *p->sp;
+    const MeshData& m = *s.mesh;
+    const int64_t K = s.K;
+    const int Np = s.Np, Nfp = s.Nfp;
+    const int64_t nj = K * Np, ng = K * 3 * (int64_t)Nfp;
+    for (const double* a : {j_re, j_im})
+        if (a)
+            for (int64_t i = 0; i < nj; ++i)
+                if (!std::isfinite(a[i])) fail(CMCG_ERR_ARG, "problem: non-finite current density");
+    for (const double* a : {g_re, g_im})
+        if (a)
+            for (int64_t i = 0; i < ng; ++i)
+                if (!std::isfinite(a[i])) fail(CMCG_ERR_ARG, "problem: non-finite boundary data");
+    p->has_j = j_re || j_im;
+    p->has_g = g_re || g_im;
+    if (!p->has_j && !p->has_g) return;
+    std::vector<double> sr(s.ndof, 0.0), si(s.ndof, 0.0);
+    for (int64_t e = 0; e < K; ++e)
+        for (int i = 0; i < Np; ++i) {
+            if (j_re) sr[e * 3 * Np + i] = j_re[e * Np + i] / p->eps[e];
+            if (j_im) si[e * 3 * Np + i] = j_im[e * Np + i] / p->eps[e];
+        }
+    if (p->has_g) {
+        const RefElem2D& r = ref_elem2d(s.q);
+        for (int64_t e = 0; e < K; ++e) {
+            const double Z = std::sqrt(p->mu[e] / p->eps[e]);
+            for (int f = 0; f < 3; ++f) {
+                if (m.nbr[3 * e + f] >= 0 || m.tag[3 * e + f] != CMCG_TAG_IMPEDANCE) continue;
+                const double n1 = m.normal[6 * e + 2 * f], n2 = m.normal[6 * e + 2 * f + 1];
+                const double fs = m.area[3 * e + f] / m.vol[e];
+                for (int part = 0; part < 2; ++part) {
+                    const double* gsrc = part == 0 ? g_re : g_im;
+                    if (!gsrc) continue;
+                    std::vector<double>& S = part == 0 ? sr : si;
+                    for (int k = 0; k < Nfp; ++k) {
+                        const double G = gsrc[(e * 3 + f) * Nfp + k];
+                        for (int i = 0; i < Np; ++i) {
+                            const double L = r.LIFT[i * 3 * Nfp + f * Nfp + k] * fs;
+                            S[(e * 3) * Np + i] += L * G / (2 * Z) / p->eps[e];
+                            S[(e * 3 + 1) * Np + i] += L * (n2 * G) / 2 / p->mu[e];
+                            S[(e * 3 + 2) * Np + i] += L * (-n1 * G) / 2 / p->mu[e];
+                        }
+                    }
+                }
+            }
+        }
+    }
+    upload_field(s, p->Sre, sr);
+    upload_field(s, p->Sim, si);
+    p->src_rows = p->has_g ? 3 : 1;
+}
+
 // j_re / j_im: [nh][K][Np][3] (harmonic h with frequency ks[h] omega; nh = 1,
-// ks = NULL for a single frequency); g only for a single frequency.
+// ks = NULL for a single frequency); g only for a single frequency.  2-D
+// spaces: j [K][Np], g [K][3][Nfp], a single frequency.
 static cmcg_problem* make_problem(const cmcg_space* sh, const double* eps, const double* mu, const double* sigma,
                                   double omega, const double* j_re, const double* j_im, const double* g_re,
                                   const double* g_im, int nh = 1, const int* ks = nullptr) {
@@ -169,6 +272,13 @@ static cmcg_problem* make_problem(const cmcg_space* sh, const double* eps, const
     p->wH.alloc(K * 8);
     CMCG_HIP(hipMemcpy(p->wE.p, we.data(), K * 8, hipMemcpyHostToDevice));
     CMCG_HIP(hipMemcpy(p->wH.p, wh.data(), K * 8, hipMemcpyHostToDevice));
+    if (sp->dim == 2) {
+        if (nh != 1) fail(CMCG_ERR_ARG, "problem: several harmonics are not supported on 2-D spaces");
+        build_source2d(p.get(), j_re, j_im, g_re, g_im);
+        build_geo(p.get(), 1.0);
+        p->pinned.reset(new HostPinned());
+        return p.release();
+    }
     // source vector S with Re(S e^{i w t}) = the forcing of Phi
     const int64_t nj = (int64_t)nh * K * Np * 3;
     for (const double* a : {j_re, j_im})
@@ -249,7 +359,9 @@ StepCfg step_config(const cmcg_problem* p, const cmcg_options* o) {
     if (o->steps > 0) {
         c.M = o->steps;
     } else {
-        const double cq = o->cfl > 0 ? o->cfl : (s.q == 1 ? 0.20 : s.q == 2 ? 0.16 : 0.12);
+        // 3-D: c_1 = 0.20 (readings for tetrahedra); 2-D: the paper's c_1 = 0.24, c_3 = 0.12
+        const double c1 = s.dim == 2 ? 0.24 : 0.20;
+        const double cq = o->cfl > 0 ? o->cfl : (s.q == 1 ? c1 : s.q == 2 ? 0.16 : 0.12);
         const MeshData& m = *s.mesh;
         double mn = HUGE_VAL;
         for (int64_t e = 0; e < s.K; ++e) mn = std::fmin(mn, std::sqrt(p->mu[e] * p->eps[e]) * m.rho[e]);
@@ -278,6 +390,34 @@ static void ensure_work(cmcg_problem* p) {
     p->Fim.alloc(db * p->nharm);
     p->partial.alloc(dot_partials() * 8);
     p->scal.alloc(64);
+}
+
+// Dimension dispatch of the stage, field-conversion and inner-product kernels.
+static void stage_for(const SpaceData& s, const StageArgs& a, hipStream_t st) {
+    if (s.dim == 2)
+        launch_stage2d(s.q, s.precision, a, st);
+    else
+        launch_stage(s.q, s.precision, a, st);
+}
+static void to_field_for(const SpaceData& s, const double* X, void* U, void* Ulo, int flip, hipStream_t st) {
+    if (s.dim == 2)
+        launch_to_field2d(s.precision, s.Np, X, U, Ulo, s.ndof, flip, st);
+    else
+        launch_to_field(s.precision, s.Np, X, U, Ulo, s.ndof, flip, st);
+}
+static void from_field_for(const SpaceData& s, const void* U, const void* Ulo, double* Y, const double* sub, int flip,
+                           hipStream_t st) {
+    if (s.dim == 2)
+        launch_from_field2d(s.precision, s.Np, U, Ulo, Y, sub, s.ndof, flip, st);
+    else
+        launch_from_field(s.precision, s.Np, U, Ulo, Y, sub, s.ndof, flip, st);
+}
+static void dot_for(cmcg_problem* p, const double* U, const double* V, double* out_dev, hipStream_t st) {
+    const SpaceData& s = *p->sp;
+    if (s.dim == 2)
+        launch_dot2d(s.q, U, V, p->wE.as<double>(), p->wH.as<double>(), s.K, p->partial.as<double>(), out_dev, st);
+    else
+        launch_dot(s.q, U, V, p->wE.as<double>(), p->wH.as<double>(), s.K, p->partial.as<double>(), out_dev, st);
 }
 
 static StageArgs base_args(cmcg_problem* p) {
@@ -350,7 +490,7 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
                 a.filter = 1;
                 for (int h = 0; h < H; ++h) set_filter(h, ph(h, m) * ((m == 0 ? 1.0 : 2.0) / M), 0.0);
             }
-            launch_stage(q, prec, a, st);
+            stage_for(s, a, st);
             a.filter = 0;
             // stage 2: k2 = Phi(t_m + dt/2, Y1); U += dt k2
             a.mode = RK2_S2;
@@ -359,7 +499,7 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
             a.Uout = p->U.p;
             a.cu = dt;
             set_src(m + 0.5);
-            launch_stage(q, prec, a, st);
+            stage_for(s, a, st);
         } else {
             a.mode = RK4_S1;
             a.Y = p->U.p;
@@ -381,7 +521,7 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
                     set_filter(h, wa, wb);
                 }
             }
-            launch_stage(q, prec, a, st);
+            stage_for(s, a, st);
             a.filter = 0;
             a.mode = RK4_S2;
             a.Y = p->Y1.p;
@@ -389,19 +529,19 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
             a.cy = 0.5 * dt;
             a.ca = dt / 3.0;
             set_src(m + 0.5);
-            launch_stage(q, prec, a, st);
+            stage_for(s, a, st);
             a.mode = RK4_S3;
             a.Y = p->Y2.p;
             a.Ynext = p->Y1.p;
             a.cy = dt;
             a.ca = dt / 3.0;
-            launch_stage(q, prec, a, st);
+            stage_for(s, a, st);
             a.mode = RK4_S4;
             a.Y = p->Y1.p;
             a.Uout = p->U.p;
             a.cu = dt / 6.0;
             set_src(m + 1.0);
-            launch_stage(q, prec, a, st);
+            stage_for(s, a, st);
         }
     }
     if (filt) {
@@ -421,7 +561,7 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
             a.filter = 1;
             for (int h = 0; h < H; ++h)
                 set_filter(h, twoT * ph(h, M - 1) * xi[h][1], twoT * ph(h, M - 1) * xi[h][3]);
-            launch_stage(q, prec, a, st);
+            stage_for(s, a, st);
         }
     }
 }
@@ -461,19 +601,18 @@ void apply_period(cmcg_problem* p, const StepCfg& c, const cmcg_options* o, cons
     const SpaceData& s = *p->sp;
     const int flip = direction < 0 ? 1 : 0;
     if (X) {
-        launch_to_field(s.precision, s.Np, X, p->U.p, p->Ulo.p, s.ndof, flip, st);
+        to_field_for(s, X, p->U.p, p->Ulo.p, flip, st);
     } else {
         launch_zero(p->U.p, p->U.bytes, st);
         if (p->Ulo.p) launch_zero(p->Ulo.p, p->Ulo.bytes, st);
     }
     run_period(p, c, src && direction > 0, filt, o->use_graph != 0, st);
-    if (Yo) launch_from_field(s.precision, s.Np, p->U.p, p->Ulo.p, Yo, sub, s.ndof, flip, st);
+    if (Yo) from_field_for(s, p->U.p, p->Ulo.p, Yo, sub, flip, st);
 }
 
 double dot(cmcg_problem* p, const double* U, const double* V, hipStream_t st) {
     const SpaceData& s = *p->sp;
-    launch_dot(s.q, U, V, p->wE.as<double>(), p->wH.as<double>(), s.K, p->partial.as<double>(), p->scal.as<double>(),
-               st);
+    dot_for(p, U, V, p->scal.as<double>(), st);
     CMCG_HIP(hipMemcpyAsync(p->pinned->p, p->scal.p, 8, hipMemcpyDeviceToHost, st));
     CMCG_HIP(hipStreamSynchronize(st));
     return p->pinned->p[0];
@@ -481,7 +620,7 @@ double dot(cmcg_problem* p, const double* U, const double* V, hipStream_t st) {
 
 void prepare(cmcg_problem* p, const StepCfg& c) {
     if (current_device() != p->sp->device) fail(CMCG_ERR_STATE, "wrong current device");
-    ensure_constants(p->sp->device, p->sp->q);
+    ensure_constants(p->sp->device, p->sp->q, p->sp->dim);
     if (p->geo_alpha != c.alpha) {
         build_geo(p, c.alpha);
         for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -493,9 +632,7 @@ void prepare(cmcg_problem* p, const StepCfg& c) {
 // Inner product (U, V)_{eps,mu} into pinned slot k, ordered on the stream
 // (read after the stream has been synchronised).
 static void dot_async(cmcg_problem* p, const double* U, const double* V, int k, hipStream_t st) {
-    const SpaceData& s = *p->sp;
-    launch_dot(s.q, U, V, p->wE.as<double>(), p->wH.as<double>(), s.K, p->partial.as<double>(),
-               p->scal.as<double>() + k, st);
+    dot_for(p, U, V, p->scal.as<double>() + k, st);
     CMCG_HIP(hipMemcpyAsync(p->pinned->p + k, p->scal.as<double>() + k, 8, hipMemcpyDeviceToHost, st));
 }
 
@@ -588,6 +725,7 @@ static int autotune_problem(cmcg_problem* p, const StepCfg& c, hipStream_t st, d
 static void maybe_autotune(cmcg_problem* p, const cmcg_options* o, const StepCfg& c, hipStream_t st) {
     if (!o->autotune) return;
     const SpaceData& s = *p->sp;
+    if (s.dim == 2) return;  // one 2-D stage kernel
     if (apply_tuned_variant(s.device, s.q, s.precision, s.K, 1)) return;
     double us[kStageVariants];
     autotune_problem(p, c, st, us);
@@ -896,6 +1034,25 @@ int cmcg_mesh_create(int64_t nv, const double* xyz, int64_t K, const int64_t* te
     CMCG_GUARD_END
 }
 
+int cmcg_mesh2d_create(int64_t nv, const double* xy, int64_t K, const int64_t* tri, const int8_t* edge_tag,
+                       cmcg_mesh** out) {
+    CMCG_GUARD_BEGIN
+    if (!out) fail(CMCG_ERR_ARG, "mesh2d: NULL output");
+    *out = nullptr;
+    auto d = build_mesh2d(nv, xy, K, tri, edge_tag);
+    *out = new cmcg_mesh{d};
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_mesh_dim(const cmcg_mesh* m, int* dim) {
+    CMCG_GUARD_BEGIN
+    if (!m || !m->d || !dim) fail(CMCG_ERR_ARG, "mesh_dim: NULL argument");
+    *dim = m->d->dim;
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
 void cmcg_mesh_destroy(cmcg_mesh* m) { delete m; }
 
 int cmcg_mesh_locality_order(int64_t nv, const double* xyz, int64_t K, const int64_t* tet, int64_t* order) {
@@ -928,25 +1085,26 @@ int cmcg_space_create(const cmcg_mesh* m, int q, int precision, cmcg_space** out
     if (precision != CMCG_FP64 && precision != CMCG_FP32) fail(CMCG_ERR_ARG, "space: bad precision");
     auto s = std::make_shared<SpaceData>();
     s->mesh = m->d;
+    s->dim = m->d->dim;
+    const int nf = s->dim == 2 ? 3 : 4;
     s->q = q;
-    s->Np = np_of(q);
-    s->Nfp = nfp_of(q);
+    s->Np = s->dim == 2 ? np2_of(q) : np_of(q);
+    s->Nfp = s->dim == 2 ? nfp2_of(q) : nfp_of(q);
     s->precision = precision;
     s->device = current_device();
     s->K = m->d->K;
-    s->ndof = s->K * 6 * s->Np;
+    s->ndof = s->K * (s->dim == 2 ? 3 : 6) * s->Np;
     const MeshData& md = *m->d;
-    s->conn_h.resize(4 * s->K);
-    for (int64_t i = 0; i < 4 * s->K; ++i) {
+    s->conn_h.resize(nf * s->K);
+    for (int64_t i = 0; i < nf * s->K; ++i) {
         if (md.nbr[i] >= 0)
             s->conn_h[i] = (int32_t)((md.nbr[i] << 5) | (md.nbr_face[i] << 3) | md.perm[i]);
         else
             s->conn_h[i] = md.tag[i] == CMCG_TAG_PEC ? -1 : -2;
     }
-    (void)ref_elem(q);
-    ensure_constants(s->device, q);
-    s->conn.alloc(4 * s->K * sizeof(int32_t));
-    CMCG_HIP(hipMemcpy(s->conn.p, s->conn_h.data(), 4 * s->K * sizeof(int32_t), hipMemcpyHostToDevice));
+    ensure_constants(s->device, q, s->dim);
+    s->conn.alloc(nf * s->K * sizeof(int32_t));
+    CMCG_HIP(hipMemcpy(s->conn.p, s->conn_h.data(), nf * s->K * sizeof(int32_t), hipMemcpyHostToDevice));
     *out = new cmcg_space{s};
     return CMCG_OK;
     CMCG_GUARD_END
@@ -971,6 +1129,20 @@ int cmcg_space_nodes(const cmcg_space* s, double* xyz) {
     if (!s || !s->d || !xyz) fail(CMCG_ERR_ARG, "space_nodes: NULL argument");
     const SpaceData& sp = *s->d;
     const MeshData& m = *sp.mesh;
+    if (sp.dim == 2) {
+        const RefElem2D& r2 = ref_elem2d(sp.q);
+        for (int64_t e = 0; e < sp.K; ++e) {
+            const double* v0 = &m.xyz[2 * m.tet[3 * e]];
+            for (int i = 0; i < sp.Np; ++i)
+                for (int d = 0; d < 2; ++d) {
+                    double x = v0[d];
+                    for (int a = 0; a < 2; ++a)
+                        x += r2.xi[2 * i + a] * (m.xyz[2 * m.tet[3 * e + a + 1] + d] - v0[d]);
+                    xyz[(e * sp.Np + i) * 2 + d] = x;
+                }
+        }
+        return CMCG_OK;
+    }
     const RefElem& r = ref_elem(sp.q);
     for (int64_t e = 0; e < sp.K; ++e) {
         const double* v0 = &m.xyz[3 * m.tet[4 * e]];
@@ -1015,7 +1187,7 @@ int cmcg_problem_create_device(const cmcg_space* s, const double* eps, const dou
     if (!out) fail(CMCG_ERR_ARG, "problem: NULL output");
     *out = nullptr;
     if (!s || !s->d) fail(CMCG_ERR_ARG, "problem: NULL space");
-    const size_t nb = (size_t)s->d->K * s->d->Np * 3 * 8;
+    const size_t nb = (size_t)s->d->K * s->d->Np * (s->d->dim == 2 ? 1 : 3) * 8;
     std::vector<double> jr, ji;
     if (j_re_dev) {
         jr.resize(nb / 8);
@@ -1110,6 +1282,18 @@ int cmcg_result_fields(const cmcg_result* r, double* e_re, double* e_im, double*
     CMCG_HIP(hipMemcpy(fr.data(), r->Fre.p, s.ndof * 8, hipMemcpyDeviceToHost));
     CMCG_HIP(hipMemcpy(fi.data(), r->Fim.p, s.ndof * 8, hipMemcpyDeviceToHost));
     const int Np = s.Np;
+    if (s.dim == 2) {  // e [K][Np], h [K][Np][2]
+        for (int64_t e = 0; e < s.K; ++e)
+            for (int i = 0; i < Np; ++i) {
+                if (e_re) e_re[e * Np + i] = fr[(e * 3) * Np + i];
+                if (e_im) e_im[e * Np + i] = fi[(e * 3) * Np + i];
+                for (int c = 0; c < 2; ++c) {
+                    if (h_re) h_re[(e * Np + i) * 2 + c] = fr[(e * 3 + 1 + c) * Np + i];
+                    if (h_im) h_im[(e * Np + i) * 2 + c] = fi[(e * 3 + 1 + c) * Np + i];
+                }
+            }
+        return CMCG_OK;
+    }
     for (int64_t e = 0; e < s.K; ++e)
         for (int i = 0; i < Np; ++i)
             for (int c = 0; c < 3; ++c) {
@@ -1196,7 +1380,7 @@ int cmcg_debug_rhs(cmcg_problem* p, const cmcg_options* o, double t, int with_so
     prepare(p, c);
     const SpaceData& s = *p->sp;
     p->Kbuf.alloc(s.ndof * s.esize());
-    launch_to_field(s.precision, s.Np, u, p->U.p, p->Ulo.p, s.ndof, 0, stream);
+    to_field_for(s, u, p->U.p, p->Ulo.p, 0, stream);
     StageArgs a = base_args(p);
     a.mode = RHS;
     a.Y = p->U.p;
@@ -1205,8 +1389,8 @@ int cmcg_debug_rhs(cmcg_problem* p, const cmcg_options* o, double t, int with_so
     a.src_rows = (with_source && p->src_rows) ? p->src_rows : 0;
     a.scos = std::cos(p->omega * t);
     a.ssin = std::sin(p->omega * t);
-    launch_stage(s.q, s.precision, a, stream);
-    launch_from_field(s.precision, s.Np, p->Kbuf.p, nullptr, out, nullptr, s.ndof, 0, stream);
+    stage_for(s, a, stream);
+    from_field_for(s, p->Kbuf.p, nullptr, out, nullptr, 0, stream);
     CMCG_HIP(hipStreamSynchronize(stream));
     return CMCG_OK;
     CMCG_GUARD_END
@@ -1237,7 +1421,7 @@ int cmcg_debug_period(cmcg_problem* p, const cmcg_options* o, int direction, int
 int cmcg_debug_dot(cmcg_problem* p, const double* u, const double* v, double* out, hipStream_t stream) {
     CMCG_GUARD_BEGIN
     if (!p || !u || !v || !out) fail(CMCG_ERR_ARG, "debug_dot: NULL argument");
-    ensure_constants(p->sp->device, p->sp->q);
+    ensure_constants(p->sp->device, p->sp->q, p->sp->dim);
     ensure_work(p);
     *out = dot(p, u, v, stream);
     return CMCG_OK;
@@ -1258,6 +1442,7 @@ int cmcg_autotune_stage(cmcg_problem* p, const cmcg_options* o, hipStream_t stre
                         double* us_per_launch) {
     CMCG_GUARD_BEGIN
     if (!p || !variant) fail(CMCG_ERR_ARG, "autotune_stage: NULL argument");
+    if (p->sp->dim == 2) fail(CMCG_ERR_ARG, "autotune_stage: 2-D spaces have one stage kernel");
     cmcg_options def;
     cmcg_options_default(&def);
     if (!o) o = &def;

@@ -1,0 +1,219 @@
+"""GPU parity of the 2-D transverse-magnetic path (triangles, fields e, h1,
+h2) against the 2-D oracle, through the C-ABI.
+
+Tolerances as for the 3-D path: FP64 right-hand side and period 1e-12, CMCG
+at a fixed iteration count 1e-11; FP32 fields 1e-5.  The meshes hold 64 and
+100 triangles: several 21-triangle workgroups and a ragged last one.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import cmcg as ocmcg
+from oracle import dg2d, exact2d, fs, fw as ofw, timestep
+from paper_2106_02858_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5}
+P, I = inputs.TAG_PEC, inputs.TAG_IMPEDANCE
+
+
+def dev(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def pair2d(lib, n=4, q=2, precision=0, seed=0, walls=(P, I, P, I), sigma=True, g=True, omega=3 * math.pi,
+           source=True):
+    """Seeded heterogeneous 2-D problem for the oracle and the library."""
+    xy, tri, tags = inputs.cartesian_triangles(n, n, side_tags=walls)
+    K = tri.shape[0]
+    rng = np.random.default_rng(seed)
+    eps = rng.choice([1.0, 2.0, 4.0], K)
+    mu = rng.choice([1.0, 1.5], K)
+    sg = rng.uniform(0.0, 0.5, K) if sigma else None
+    p0 = dg2d.make_problem(xy, tri, tags, q, eps, mu)
+    Np, Nfp = p0.Np, p0.geo.Nfp
+    j = (rng.standard_normal((K, Np)) + 1j * rng.standard_normal((K, Np))) if source else None
+    gg = None
+    if g and source:
+        gg = np.zeros((K, 3, Nfp), complex)
+        wall = p0.geo.tag == inputs.TAG_IMPEDANCE
+        gg[wall] = rng.standard_normal((wall.sum(), Nfp)) + 1j * rng.standard_normal((wall.sum(), Nfp))
+    op = dg2d.make_problem(xy, tri, tags, q, eps, mu, sg, omega=omega, j=j, g=gg)
+    m = lib.cmcg_mesh2d_create(xy, tri, tags)
+    s = lib.cmcg_space_create(m, q, precision)
+    lp = lib.cmcg_problem_create(s, eps, mu, sg, omega, j, gg)
+    return op, s, lp
+
+
+def rel_norm(op, a, b):
+    return dg2d.norm(op, a - b) / dg2d.norm(op, b)
+
+
+def rel_norm_c(op, a, b):
+    d = a - b
+    num = np.sqrt(abs(dg2d.inner(op, d.real, d.real)) + abs(dg2d.inner(op, d.imag, d.imag)))
+    den = np.sqrt(abs(dg2d.inner(op, b.real, b.real)) + abs(dg2d.inner(op, b.imag, b.imag)))
+    return num / den
+
+
+def filtered(lib, r, op):
+    fr, fi = dev(np.zeros((op.K, 3, op.Np))), dev(np.zeros((op.K, 3, op.Np)))
+    lib.cmcg_result_filtered_device(r, fr, fi)
+    return host(fr) + 1j * host(fi)
+
+
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_space_nodes_and_layout(lib, q):
+    op, s, lp = pair2d(lib, q=q)
+    info = lib.cmcg_space_info(s)
+    assert info["dim"] == 2 and info["Np"] == op.Np and info["Nfp"] == q + 1
+    assert info["ndof"] == op.K * 3 * op.Np
+    assert np.max(np.abs(lib.cmcg_space_nodes(s) - op.geo.x)) < 1e-15
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_rhs_parity(lib, q, precision):
+    print(f"2-D rhs q={q} prec={precision}", flush=True)
+    op, s, lp = pair2d(lib, q=q, precision=precision, seed=q)
+    U = np.random.default_rng(1).standard_normal((op.K, 3, op.Np))
+    out = dev(np.zeros_like(U))
+    for t, src in ((0.0, False), (0.123, True)):
+        lib.cmcg_debug_rhs(lp, dev(U), out, t=t, with_source=src)
+        ref = dg2d.phi(op, t, U, with_source=src)
+        err = np.max(np.abs(host(out) - ref)) / np.max(np.abs(ref))
+        assert err < TOL[precision], (t, src, err)
+
+
+@pytest.mark.parametrize("walls", [(P,) * 4, (I,) * 4])
+@pytest.mark.parametrize("q", [1, 3])
+def test_rhs_centred_flux_and_walls(lib, q, walls):
+    op, s, lp = pair2d(lib, n=5, q=q, seed=7, walls=walls)
+    op.alpha = 0.0
+    U = np.random.default_rng(2).standard_normal((op.K, 3, op.Np))
+    out = dev(np.zeros_like(U))
+    lib.cmcg_debug_rhs(lp, dev(U), out, t=0.0, with_source=False,
+                       opts=lib.cmcg_options_default(flux=lib.CMCG_FLUX_CENTRED))
+    ref = dg2d.apply_B(op, U)
+    assert np.max(np.abs(host(out) - ref)) / np.max(np.abs(ref)) < 1e-12
+
+
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_dot_parity_and_determinism(lib, q):
+    op, s, lp = pair2d(lib, n=5, q=q, seed=4)
+    rng = np.random.default_rng(5)
+    U = rng.standard_normal((op.K, 3, op.Np))
+    V = rng.standard_normal((op.K, 3, op.Np))
+    a = lib.cmcg_debug_dot(lp, dev(U), dev(V))
+    b = lib.cmcg_debug_dot(lp, dev(U), dev(V))
+    assert a == b
+    assert abs(a - dg2d.inner(op, U, V)) <= 1e-13 * dg2d.norm(op, U) * dg2d.norm(op, V)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_period_parity(lib, q, precision):
+    print(f"2-D period q={q} prec={precision}", flush=True)
+    op, s, lp = pair2d(lib, n=4 if q < 3 else 3, q=q, precision=precision, seed=10 + q)
+    M = timestep.n_steps(op)
+    sch = timestep.default_scheme(q)
+    assert lib.cmcg_problem_steps(lp)[0] == M
+    U0 = np.random.default_rng(3).standard_normal((op.K, 3, op.Np))
+    ut = dev(np.zeros_like(U0))
+    fr, fi = dev(np.zeros_like(U0)), dev(np.zeros_like(U0))
+    for use_graph in (0, 1):
+        o = lib.cmcg_options_default(use_graph=use_graph)
+        lib.cmcg_debug_period(lp, dev(U0), ut, 1, True, fr, fi, opts=o)
+        refU, refF = timestep.forward(op, U0, M, sch, True, filt=True)
+        assert rel_norm(op, host(ut), refU) < TOL[precision]
+        assert rel_norm_c(op, host(fr) + 1j * host(fi), refF) < TOL[precision]
+        lib.cmcg_debug_period(lp, dev(U0), ut, -1, False, opts=o)
+        assert rel_norm(op, host(ut), timestep.backward(op, U0, M, sch)) < TOL[precision]
+
+
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_cmcg_fixed_iterations_fp64(lib, q):
+    print(f"2-D cmcg q={q}", flush=True)
+    op, s, lp = pair2d(lib, n=4 if q < 3 else 3, q=q, seed=20 + q, walls=(I,) * 4, sigma=False)
+    ref = ocmcg.solve(op, tol=1e-8, max_iter=300)
+    r = lib.cmcg_solve(lp, lib.cmcg_options_default(fixed_iters=ref.iters))
+    st = lib.cmcg_result_stats(r)
+    assert st["iters"] == ref.iters and st["steps"] == ref.M
+    assert rel_norm_c(op, filtered(lib, r, op), ref.F) < 1e-11
+    assert np.allclose(lib.cmcg_result_history(r), ref.history, rtol=1e-6, atol=1e-12)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cmcg_converges_to_the_discrete_periodic_orbit(lib, precision):
+    op, s, lp = pair2d(lib, n=4, q=2, precision=precision, seed=31, walls=(P, P, I, I))
+    M = timestep.n_steps(op)
+    _, F = fs.discrete_periodic(op, M, timestep.default_scheme(op.geo.q))
+    tol = 1e-9 if precision == 0 else 1e-6
+    r = lib.cmcg_solve(lp, lib.cmcg_options_default(tol=tol, max_iter=600))
+    assert lib.cmcg_result_stats(r)["status"] == lib.CMCG_OK
+    assert rel_norm_c(op, filtered(lib, r, op), F) < (1e-7 if precision == 0 else 1e-4)
+
+
+def test_fw_fixed_periods(lib):
+    op, s, lp = pair2d(lib, n=4, q=1, seed=41, walls=(I,) * 4)
+    ref = ofw.solve(op, periods=12)
+    r = lib.cmcg_fw_solve(lp, lib.cmcg_options_default(fixed_iters=12))
+    assert rel_norm_c(op, filtered(lib, r, op), ref.F) < 1e-12
+
+
+def test_result_fields_layout(lib):
+    op, s, lp = pair2d(lib, n=3, q=2, seed=5, walls=(I,) * 4)
+    r = lib.cmcg_solve(lp, lib.cmcg_options_default(fixed_iters=3))
+    F = filtered(lib, r, op)
+    e, h = lib.cmcg_result_fields(r, op.K, op.Np, dim=2)
+    assert np.array_equal(e, F[:, 0]) and np.array_equal(h, np.transpose(F[:, 1:3], (0, 2, 1)))
+
+
+def test_unsupported_2d_calls_are_rejected(lib):
+    op, s, lp = pair2d(lib, n=2, q=1)
+    with pytest.raises(lib.CmcgError):
+        lib.cmcg_solve_batch([lp, lp])
+    with pytest.raises(lib.CmcgError):
+        lib.cmcg_autotune_stage(lp)
+    with pytest.raises(lib.CmcgError):
+        lib.cmcg_problem_create_harmonics(s, op.eps, op.mu, None, op.omega, [1, 2],
+                                          np.zeros((2, op.K, op.Np)))
+
+
+@pytest.mark.parametrize("delta", [0.125, 0.015625])
+def test_paper_cavity_p1_32x32(lib, delta):
+    """The cavity experiment at its printed size (P1, 32 x 32 Cartesian mesh,
+    4096 triangles, j = 1, omega = 3 sqrt(2) pi + sqrt(2) pi delta): CMCG on
+    the GPU converges to the exactly periodic discrete orbit.  Its error
+    against the exact solution adds the RK2 time-discretisation error (M = 146
+    steps per period at c_1 = 0.24) to that of the frequency-domain upwind
+    system: 0.0074 against 0.0052 at delta = 1/8."""
+    w = inputs.cavity2d(32, 1, 3 * math.sqrt(2) * math.pi, delta)
+    p0 = dg2d.make_problem(w.xy, w.tri, w.tags, 1, w.eps, w.mu, omega=w.omega)
+    j = inputs.current_2d(w, p0.geo.x)
+    op = dg2d.make_problem(w.xy, w.tri, w.tags, 1, w.eps, w.mu, omega=w.omega, j=j)
+    m = lib.cmcg_mesh2d_create(w.xy, w.tri, w.tags)
+    s = lib.cmcg_space_create(m, 1, lib.CMCG_FP64)
+    lp = lib.cmcg_problem_create(s, w.eps, w.mu, None, w.omega, j)
+    r = lib.cmcg_solve(lp, lib.cmcg_options_default(tol=1e-10, max_iter=4000))
+    st = lib.cmcg_result_stats(r)
+    print(f"cavity 32x32 P1 delta={delta}: {st['iters']} iterations, M = {st['steps']}", flush=True)
+    assert st["status"] == lib.CMCG_OK and st["steps"] == timestep.n_steps(op)
+    F = filtered(lib, r, op)
+    _, Fd = fs.discrete_periodic(op, st["steps"], 2)
+    assert rel_norm_c(op, F, Fd) < 1e-8
+    err, ref = exact2d.energy_error(op.geo, w.xy, w.tri, w.eps, w.mu, F, lambda x: exact2d.cavity(w.omega, x),
+                                    nq=6)
+    U_fs = fs.frequency_solve(op)
+    err_fs, _ = exact2d.energy_error(op.geo, w.xy, w.tri, w.eps, w.mu, U_fs,
+                                     lambda x: exact2d.cavity(w.omega, x), nq=6)
+    print(f"  error vs exact: CMCG {err / ref:.5f}, frequency-domain upwind system {err_fs / ref:.5f}", flush=True)
+    assert err_fs < err < 2.5 * err_fs
