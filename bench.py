@@ -47,10 +47,12 @@ def parse():
                     help="keep the default stage-kernel variant instead of autotuning it in the warm-up solve")
     ap.add_argument("--cpu-steps", type=int, default=4, help="RK steps of the CPU oracle sample")
     ap.add_argument("--kernel-periods", type=int, default=3)
-    ap.add_argument("--workload", choices=["large_single", "batched", "serving", "scatterer", "fw"],
+    ap.add_argument("--workload", choices=["large_single", "batched", "serving", "scatterer", "fw", "trap2d"],
                     default="large_single",
                     help="large_single (default bench line), the 64-member batched configuration, or the "
                          "Poisson request stream through the serving engine")
+    ap.add_argument("--trap", choices=["square", "disk"], default="disk", help="trap2d: shape of the trap")
+    ap.add_argument("--n2d", type=int, default=75, help="trap2d: cells per side of the Cartesian mesh")
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--fp64-members", type=int, default=64,
                     help="batched: members also solved one by one with plain FP64 fields (0: none)")
@@ -329,6 +331,117 @@ def scatterer(a):
     print(json.dumps(out), flush=True)
 
 
+def stage2d_bytes_per_element(q: int, esize: int) -> float:
+    """Algorithmic HBM bytes of one average 2-D stage launch per triangle: the
+    field passes of stage_bytes_per_element over 3 components, the geometry
+    (25 values) and connectivity (3 int32)."""
+    Np = (q + 1) * (q + 2) // 2
+    if q >= 2:
+        per_dof = 72.0 / 4 if esize == 4 else 128.0 / 4
+    else:
+        per_dof = 24.0 / 2 if esize == 4 else 40.0 / 2
+    return 3 * Np * per_dof + 25 * esize + 12
+
+
+def cpu_baseline_2d(w, steps: int):
+    """The 2-D FP64 oracle (as is) on a bounded sample: `steps` RK steps of
+    the full mesh without source, timed on the host cores."""
+    import numpy as np
+    import psutil
+
+    from oracle import dg2d, timestep
+    p = dg2d.make_problem(w.xy, w.tri, w.tags, w.q, w.eps, w.mu, w.sigma, omega=w.omega)
+    M = timestep.n_steps(p)
+    dt = 2 * math.pi / w.omega / M
+    U = np.random.default_rng(0).standard_normal((p.K, 3, p.Np))
+    proc = psutil.Process()
+    c0 = proc.cpu_times()
+    t0 = time.perf_counter()
+    for m in range(steps):
+        U, _ = timestep.rk4_step(p, m * dt, U, dt, False) if w.q > 1 else timestep.rk2_step(p, m * dt, U, dt, False)
+    el = time.perf_counter() - t0
+    c1 = proc.cpu_times()
+    ndof = p.K * 3 * p.Np
+    return {"value": ndof * steps / el, "unit": "dof-updates/s", "cores": round((c1.user - c0.user + c1.system -
+                                                                               c0.system) / el, 2),
+            "kind": "oracle", "sample": f"{steps} RK{'4' if w.q > 1 else '2'} step(s) of the full {p.K}-triangle "
+                                        f"P{w.q} mesh ({ndof} dofs), FP64 numpy 2-D oracle, {el:.1f} s"}
+
+
+def trap2d_bench(a):
+    """The paper's own 2-D workload (dipole in a trapping body, Section 6),
+    transverse-magnetic fields on triangles, P3: CMCG to --tol with FP32
+    fields, timed, beside the plain FP64 solve; the 2-D stage kernel's
+    launch time over a period (HIP events on the solve's stream)."""
+    import numpy as np
+    import torch
+
+    from paper_2106_02858_amd import cmcg, inputs
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    w = inputs.trap2d(a.n2d, 3, a.trap)
+    mesh = cmcg.cmcg_mesh2d_create(w.xy, w.tri, w.tags)
+
+    def make(prec):
+        s = cmcg.cmcg_space_create(mesh, w.q, prec)
+        j = inputs.current_2d(w, cmcg.cmcg_space_nodes(s))
+        return s, cmcg.cmcg_problem_create(s, w.eps, w.mu, None, w.omega, j)
+
+    res = {}
+    for prec in (cmcg.CMCG_FP32, cmcg.CMCG_FP64):
+        s, p = make(prec)
+        info = cmcg.cmcg_space_info(s)
+        K, Np = info["K"], info["Np"]
+        opts = cmcg.cmcg_options_default(tol=a.tol, max_iter=3000)
+        M, dt = cmcg.cmcg_problem_steps(p, opts)
+        U0 = torch.randn((K, 3, Np), dtype=torch.float64, device=dev) * 1e-3
+        UT = torch.empty_like(U0)
+        cmcg.cmcg_debug_period(p, U0, UT, 1, False, opts=opts)  # builds the period's graph (untimed)
+        for _ in range(a.warmup):
+            cmcg.cmcg_solve(p, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            r = cmcg.cmcg_solve(p, opts)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / a.steps
+        st = cmcg.cmcg_result_stats(r)
+        stream = torch.cuda.current_stream()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(a.kernel_periods):
+            cmcg.cmcg_debug_period(p, U0, UT, 1, False, opts=opts)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        per_launch = ev0.elapsed_time(ev1) / 1e3 / (a.kernel_periods * 4 * M)
+        res[prec] = dict(el=el, st=st, K=K, Np=Np, M=M, per_launch=per_launch,
+                         rate=st["dof_updates"] / st["seconds"] if st["seconds"] > 0 else 0.0)
+        log(f"2-D trap prec={prec} K={K} M={M}: {st['iters']} iters, {el:.3f} s, stage launch "
+            f"{per_launch * 1e6:.2f} us (includes the field conversions of the period)")
+    f32, f64 = res[cmcg.CMCG_FP32], res[cmcg.CMCG_FP64]
+    K = f32["K"]
+    bpe = stage2d_bytes_per_element(3, 4)
+    achieved = bpe * K / f32["per_launch"] / 1e9
+    out = {"metric": "DG dof-updates/s; CMCG time-to-1e-6 residual vs FP64 plain; p50/p99 latency",
+           "value": f32["st"]["dof_updates"] / f32["el"], "unit": "dof-updates/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": f32["el"] * 1e3, "higher_is_better": True, "scaling": "strong",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"2-D TM dipole in a trapping {a.trap} (Section 6): (-1,1)^2 Cartesian "
+                                  f"{a.n2d}x{a.n2d} mesh, {K} triangles, P3, eps = 4 in the trap, impedance walls, "
+                                  f"omega = {w.omega / math.pi:.0f} pi, Gaussian j (s = 0.05); CMCG to {a.tol:g}",
+                      "K": K, "q": 3, "steps_per_period": f32["M"]},
+           "cmcg": {"iters": f32["st"]["iters"], "periods": f32["st"]["periods"], "rel_res": f32["st"]["rel_res"],
+                    "seconds": f32["el"], "fp64_iters": f64["st"]["iters"], "fp64_seconds": f64["el"],
+                    "speedup_vs_fp64": f64["el"] / f32["el"]},
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_stage2d<float,3>",
+                        "avg_launch_us": f32["per_launch"] * 1e6, "bytes_per_launch": bpe * K,
+                        "fp64_avg_launch_us": f64["per_launch"] * 1e6}}
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_2d(w, max(a.cpu_steps, 20))
+    print(json.dumps(out), flush=True)
+
+
 def fw_compare(a):
     """CMCG against the limiting-amplitude (FW) iteration on the 48000-tet P3
     problem with FP32 fields: CMCG to --tol, then FW for 1/8, 1/4, 1/2 and 1
@@ -461,6 +574,9 @@ def main():
         return
     if a.workload == "scatterer":
         scatterer(a)
+        return
+    if a.workload == "trap2d":
+        trap2d_bench(a)
         return
     if a.workload == "fw":
         fw_compare(a)

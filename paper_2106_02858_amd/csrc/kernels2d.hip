@@ -105,6 +105,49 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs a, int64_t per) {
     const T* Mt = mats2<T>();
     const T* gg = &sG[elc * kGeo2];
 
+    // ---- FP32 fields: every global load of the stage is requested here,
+    // before the volume work (neighbour traces of the three edges, update
+    // operands, source rows); the kernel is latency-bound at the paper's
+    // sizes.  FP64 fields gather per edge and load the update operands after
+    // the lift, which keeps P3 within half the register file.
+    constexpr bool EARLY = std::is_same<T, float>::value;
+    T nv[3][NFP][3];
+    auto gather = [&](int f, T (&tr)[NFP][3]) {
+        const int code = sC[elc * 3 + f];
+#pragma unroll
+        for (int k = 0; k < NFP; ++k) {
+            if (code >= 0) {
+                const int64_t nb = code >> 5;
+                const int nf = (code >> 3) & 3;
+                const int kk = (code & 7) ? NFP - 1 - k : k;
+                const int64_t o = nb * 3 * NP + edge_node<Q>(nf, kk);
+                tr[k][0] = Y[o];
+                tr[k][1] = Y[o + NP];
+                tr[k][2] = Y[o + 2 * NP];
+            } else {
+                tr[k][0] = tr[k][1] = tr[k][2] = T(0);
+            }
+        }
+    };
+    T up[NP], ap[NP], sr[NP], si[NP];
+    float lo[NP];
+    const bool src = act && c < a.src_rows;
+    auto operands = [&]() {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            up[i] = (act && needU) ? ((const T*)a.U)[grow + i] : T(0);
+            ap[i] = (act && needA) ? ((const T*)a.Acc)[grow + i] : T(0);
+            lo[i] = (act && needL) ? from_bf16(((const uint16_t*)a.Ulo)[grow + i]) : 0.f;
+            sr[i] = src ? ((const T*)a.Sre)[grow + i] : T(0);
+            si[i] = src ? ((const T*)a.Sim)[grow + i] : T(0);
+        }
+    };
+    if constexpr (EARLY) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) gather(f, nv[f]);
+        operands();
+    }
+
     // ---- volume: physical derivatives of the lane's component
     T y[NP], d1[NP], d2[NP];
 #pragma unroll
@@ -136,8 +179,7 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs a, int64_t per) {
     }
 
     // ---- upwind flux of the lane's component on each edge, lifted
-#pragma unroll 1
-    for (int f = 0; f < 3; ++f) {
+    auto face = [&](int f, const T (&tr)[NFP][3]) {
         const int code = sC[elc * 3 + f];
         const T* g = &gg[4 + 6 * f];
         const T n0 = g[0], n1 = g[1];
@@ -149,24 +191,12 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs a, int64_t per) {
             const T em = sY[(elc * 3) * NP + own];
             const T h1m = sY[(elc * 3 + 1) * NP + own];
             const T h2m = sY[(elc * 3 + 2) * NP + own];
-            T ep, h1p, h2p;
-            if (code >= 0) {
-                const int64_t nb = code >> 5;
-                const int nf = (code >> 3) & 3;
-                const int kk = (code & 7) ? NFP - 1 - k : k;
-                const int64_t o = nb * 3 * NP + edge_node<Q>(nf, kk);
-                ep = Y[o];
-                h1p = Y[o + NP];
-                h2p = Y[o + 2 * NP];
-            } else if (code == -1) {  // PEC ghost: e+ = -e-, h+ = h-
+            T ep = tr[k][0], h1p = tr[k][1], h2p = tr[k][2];
+            if (code == -1) {  // PEC ghost: e+ = -e-, h+ = h-
                 ep = -em;
                 h1p = h1m;
                 h2p = h2m;
-            } else {  // impedance ghost (homogeneous part): zero exterior state
-                ep = T(0);
-                h1p = T(0);
-                h2p = T(0);
-            }
+            }  // impedance ghost (homogeneous part): zero exterior state, as gathered
             const T de = ep - em, dh1 = h1p - h1m, dh2 = h2p - h2m;
             if (c == 0) {
                 fl[k] = cE1 * de - cE2 * (n0 * dh2 - n1 * dh1);
@@ -177,13 +207,25 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs a, int64_t per) {
         }
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
-            T s = acc[i];
+            T t = acc[i];
 #pragma unroll
-            for (int k = 0; k < NFP; ++k) s = fma(Mt[LO + i * NF3 + f * NFP + k], fl[k], s);
-            acc[i] = s;
+            for (int k = 0; k < NFP; ++k) t = fma(Mt[LO + i * NF3 + f * NFP + k], fl[k], t);
+            acc[i] = t;
+        }
+    };
+    if constexpr (EARLY) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) face(f, nv[f]);
+    } else {
+#pragma unroll 1
+        for (int f = 0; f < 3; ++f) {
+            T tr[NFP][3];
+            gather(f, tr);
+            face(f, tr);
         }
     }
     if (!act) return;
+    if constexpr (!EARLY) operands();
 
     // ---- stage update of the lane's row
     const T inv = c == 0 ? gg[22] : gg[23];
@@ -191,20 +233,10 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs a, int64_t per) {
     T kv[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) kv[i] = fma(inv, acc[i], -sig * y[i]);
-    if (c < a.src_rows) {
-        const T* sr = (const T*)a.Sre + grow;
-        const T* si = (const T*)a.Sim + grow;
+    if (src) {
         const T scos = (T)a.scos, ssin = (T)a.ssin;
 #pragma unroll
         for (int i = 0; i < NP; ++i) kv[i] += scos * sr[i] - ssin * si[i];
-    }
-    T up[NP], ap[NP];
-    float lo[NP];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-        up[i] = needU ? ((const T*)a.U)[grow + i] : T(0);
-        ap[i] = needA ? ((const T*)a.Acc)[grow + i] : T(0);
-        lo[i] = needL ? from_bf16(((const uint16_t*)a.Ulo)[grow + i]) : 0.f;
     }
     const T cy = (T)a.cy, ca = (T)a.ca, cu = (T)a.cu;
     T* Ynext = (T*)a.Ynext + grow;

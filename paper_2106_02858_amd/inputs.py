@@ -301,18 +301,28 @@ def planewave2d(n: int = 32, q: int = 1, omega: float = 10 * math.pi,
                       tags, "planewave", theta=theta)
 
 
-def trap2d(n: int = 30, q: int = 3, omega: float = 10 * math.pi) -> Workload2D:
-    """Dipole in a trapping square: Omega = (-1,1)^2 with impedance walls,
-    eps = 4 in G = [-1/2,1/2]^2 (a triangle is inside when its centroid is),
-    else 1, mu = 1, j = exp(-|x-c|^2/s^2) with c = (1/4, 0), s = 0.05.  The
-    paper meshes this with GMSH (3636 triangles); the n x n Cartesian mesh of
-    (-1,1)^2 stands in for it (n = 30: 3600 triangles)."""
+def trap2d(n: int = 30, q: int = 3, shape: str = "square") -> Workload2D:
+    """Dipole in a trapping body G inside Omega = (-1,1)^2 with impedance
+    walls: eps = 4 in G (a triangle is inside when its centroid is), else 1,
+    mu = 1, j = exp(-|x-c|^2/s^2) with s = 0.05.
+      shape "square": G = [-1/2,1/2]^2, c = (1/4, 0), omega = 10 pi;
+      shape "disk":   G = {|x| < 1/2}, c = (sqrt2/4, 1/2 - sqrt2/4), omega = 20 pi.
+    The paper meshes these with GMSH (3636 and 22294 triangles); the n x n
+    Cartesian mesh of (-1,1)^2 stands in for them (n = 30: 3600 triangles,
+    n = 75: 22500)."""
     xy, tri, tags = cartesian_triangles(n, n, -1.0, -1.0, 2.0, 2.0)
     K = tri.shape[0]
     cen = xy[tri].mean(axis=1)
-    inside = np.all(np.abs(cen) < 0.5, axis=1)
-    return Workload2D(f"trap2d_n{n}_q{q}", q, omega, np.where(inside, 4.0, 1.0), np.ones(K), np.zeros(K),
-                      xy, tri, tags, "gaussian", centre=np.array([0.25, 0.0]), width=0.05)
+    if shape == "square":
+        inside = np.all(np.abs(cen) < 0.5, axis=1)
+        c, om = np.array([0.25, 0.0]), 10 * math.pi
+    elif shape == "disk":
+        inside = np.sum(cen * cen, axis=1) < 0.25
+        c, om = np.array([math.sqrt(2) / 4, 0.5 - math.sqrt(2) / 4]), 20 * math.pi
+    else:
+        raise ValueError("shape must be 'square' or 'disk'")
+    return Workload2D(f"trap2d_{shape}_n{n}_q{q}", q, om, np.where(inside, 4.0, 1.0), np.ones(K), np.zeros(K),
+                      xy, tri, tags, "gaussian", centre=c, width=0.05)
 
 
 def current_2d(w: Workload2D, nodes: np.ndarray) -> np.ndarray | None:

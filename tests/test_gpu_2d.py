@@ -217,3 +217,26 @@ def test_paper_cavity_p1_32x32(lib, delta):
                                      lambda x: exact2d.cavity(w.omega, x), nq=6)
     print(f"  error vs exact: CMCG {err / ref:.5f}, frequency-domain upwind system {err_fs / ref:.5f}", flush=True)
     assert err_fs < err < 2.5 * err_fs
+
+
+def test_serving_engine_mixes_2d_and_3d_requests(lib):
+    """A 2-D and a 3-D request share one engine (overlapping on their own
+    streams); each served result equals the same problem solved alone."""
+    from tests._pairs import pair
+    op2, s2, lp2 = pair2d(lib, n=6, q=2, seed=51, walls=(I,) * 4)
+    op3, s3, lp3 = pair(lib, n=2, q=2, seed=52, tags=inputs.TAG_IMPEDANCE)
+    o = lib.cmcg_options_default(tol=1e-8, max_iter=500)
+    e = lib.cmcg_engine_create(1 << 32, 4)
+    slots = {lib.cmcg_engine_admit(e, lp2, o): (lp2, op2, 3), lib.cmcg_engine_admit(e, lp3, o): (lp3, op3, 6)}
+    assert None not in slots
+    while any(lib.cmcg_engine_poll(e, s) == 1 for s in slots):
+        lib.cmcg_engine_step(e)
+    for slot, (lp, op, nc) in slots.items():
+        served = lib.cmcg_engine_collect(e, slot, lp)
+        alone = lib.cmcg_solve(lp, o)
+        import torch
+        bufs = [torch.zeros((op.K, nc, op.Np), dtype=torch.float64, device="cuda") for _ in range(4)]
+        lib.cmcg_result_filtered_device(served, bufs[0], bufs[1])
+        lib.cmcg_result_filtered_device(alone, bufs[2], bufs[3])
+        assert torch.equal(bufs[0], bufs[2]) and torch.equal(bufs[1], bufs[3])
+        assert lib.cmcg_result_stats(served)["iters"] == lib.cmcg_result_stats(alone)["iters"]
