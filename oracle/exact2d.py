@@ -92,3 +92,44 @@ def energy_error(geo, xy, tri, eps, mu, U_h: np.ndarray, exact, nq: int = 8):
     err = np.sum(wt[..., None] * coef * np.abs(ex - uh) ** 2)
     ref = np.sum(wt[..., None] * coef * np.abs(ex) ** 2)
     return float(np.sqrt(err)), float(np.sqrt(ref))
+
+
+def waveguide(omega: float, theta: float, pts: np.ndarray, modes: int = 50, robin: bool = True):
+    """(e, h1, h2) of the half-open waveguide (0,4) x (0,1): PEC at y = 0, 1 and
+    x = 0, impedance wall at x = 4 with data from xi = exp(i omega d.x),
+    d = (cos theta, sin theta); eps = mu = Z = 1, j = 0.
+
+    e = sum_n e_n(x) sin(n pi y), -e_n'' + kappa_n^2 e_n = 0, kappa_n^2 =
+    n^2 pi^2 - omega^2, e_n(0) = 0, so e_n = A_n sinh(kappa_n x).  At x = 4 the
+    impedance condition e + Z h x n = G reads e + d_x e / (i omega) = G; with
+    ``robin`` the data xi is the Robin data of d_x e + i omega e (G = xi /
+    (i omega)), else G = xi.  g_n are the sine coefficients of the data on the
+    wall (Gauss-Legendre, 8 points per mode and at least 200, so that the
+    highest mode is resolved); the series stops at ``modes`` terms."""
+    x, y = pts[:, 0], pts[:, 1]
+    sg, wg = np.polynomial.legendre.leggauss(max(200, 8 * modes))
+    sg, wg = (sg + 1) / 2, wg / 2
+    wall = np.exp(1j * omega * (4.0 * np.cos(theta) + sg * np.sin(theta)))
+    e = np.zeros(len(x), dtype=np.complex128)
+    dxe = np.zeros_like(e)
+    dye = np.zeros_like(e)
+    for n in range(1, modes + 1):
+        gn = 2.0 * np.sum(wg * wall * np.sin(n * np.pi * sg))
+        k = np.sqrt(complex((n * np.pi) ** 2 - omega ** 2))
+        if k.real < 0:
+            k = -k
+        # d_x e_n(4) + i omega e_n(4) = g_n (Robin), or e_n(4) + d_x e_n(4) / (i omega) = g_n
+        if not robin:
+            gn = gn * 1j * omega
+        if abs(k) < 1e-12:  # cut-off mode (n pi = omega): e_n is linear in x
+            en = gn * x / (1 + 4j * omega)
+            den_d = gn * np.ones_like(x) / (1 + 4j * omega)
+        else:  # sinh(k x) / (k cosh 4k + i omega sinh 4k), scaled by e^{-4k}
+            den = k * (1 + np.exp(-8 * k)) + 1j * omega * (1 - np.exp(-8 * k))
+            en = gn * (np.exp(k * (x - 4)) - np.exp(-k * (x + 4))) / den
+            den_d = gn * k * (np.exp(k * (x - 4)) + np.exp(-k * (x + 4))) / den
+        sy, cy = np.sin(n * np.pi * y), np.cos(n * np.pi * y)
+        e += en * sy
+        dxe += den_d * sy
+        dye += en * (n * np.pi) * cy
+    return e, dye / (1j * omega), -dxe / (1j * omega)

@@ -325,6 +325,18 @@ def trap2d(n: int = 30, q: int = 3, shape: str = "square") -> Workload2D:
                       xy, tri, tags, "gaussian", centre=c, width=0.05)
 
 
+def waveguide2d(nx: int = 64, q: int = 1, omega: float = 2 * math.pi, theta: float = math.pi / 6) -> Workload2D:
+    """Half-open waveguide (0,4) x (0,1) on an nx x nx/4 Cartesian mesh: PEC on
+    the bottom, top and left sides, impedance wall on the right with the data
+    of the plane wave exp(i omega d.x), d = (cos theta, sin theta); eps = mu =
+    1, j = 0 (the waveguide experiment)."""
+    xy, tri, tags = cartesian_triangles(nx, nx // 4, 0.0, 0.0, 4.0, 1.0,
+                                        side_tags=(TAG_PEC, TAG_IMPEDANCE, TAG_PEC, TAG_PEC))
+    K = tri.shape[0]
+    return Workload2D(f"waveguide2d_n{nx}_q{q}", q, omega, np.ones(K), np.ones(K), np.zeros(K), xy, tri, tags,
+                      "wallwave", theta=theta)
+
+
 def current_2d(w: Workload2D, nodes: np.ndarray) -> np.ndarray | None:
     """Nodal samples of the current density j at nodes [K, Np, 2] (real), or
     None for sources without a current."""
@@ -339,27 +351,19 @@ def current_2d(w: Workload2D, nodes: np.ndarray) -> np.ndarray | None:
 SIDE_NORMALS = np.array([[0.0, -1.0], [1.0, 0.0], [0.0, 1.0], [-1.0, 0.0]])
 
 
-def planewave_boundary_data(w: Workload2D, face_points: np.ndarray, project: bool = True) -> np.ndarray:
-    """Impedance data G = e + Z h x n of the plane wave e = exp(i omega d.x),
-    h = (sin theta, -cos theta) e, Z = 1 (so G = e (1 + d.n)), on the wall
-    edges of a Cartesian mesh; [K, 3, Nfp] complex nodal values at the edge
-    nodes face_points [K, 3, Nfp, 2], zero off the impedance edges.
-
-    project=True returns the L2 projection of G onto polynomials of degree
-    Nfp - 1 on each edge (Gauss-Legendre, 16 points), so that the edge
-    integrals of the data against the edge basis are exact; project=False
-    samples G at the nodes.  The outward normal of a wall edge is that of its
-    cell side (triangle index mod 4)."""
-    d = np.array([math.cos(w.theta), math.sin(w.theta)])
-    K = w.K
-    assert face_points.shape[0] == K
+def _wall_data(w: Workload2D, face_points: np.ndarray, fn, project: bool) -> np.ndarray:
+    """fn(points [..., 2], outward normal [2]) on the impedance edges (edge 0
+    of wall cells; the normal is that of the cell side), sampled at the edge
+    nodes or L2-projected onto polynomials of degree Nfp - 1 on each edge
+    (Gauss-Legendre, 16 points): [K, 3, Nfp] complex, zero elsewhere."""
+    assert face_points.shape[0] == w.K
     out = np.zeros(face_points.shape[:3], dtype=np.complex128)
     wall = np.nonzero(w.tags[:, 0] == TAG_IMPEDANCE)[0]
-    n = SIDE_NORMALS[wall % 4]
-    fac = (1.0 + n @ d)                                   # [nw]
     pts = face_points[wall, 0]                            # [nw, Nfp, 2]
+    Nfp = pts.shape[1]
     if not project:
-        out[wall, 0] = np.exp(1j * w.omega * (pts @ d)) * fac[:, None]
+        for i, e in enumerate(wall):
+            out[e, 0] = fn(pts[i], SIDE_NORMALS[e % 4])
         return out
     A = w.xy[w.tri[wall, 1]]
     B = w.xy[w.tri[wall, 2]]
@@ -367,14 +371,32 @@ def planewave_boundary_data(w: Workload2D, face_points: np.ndarray, project: boo
     sg, wg = (sg + 1) / 2, wg / 2
     L2 = np.sum((B - A) ** 2, axis=1)
     s_nodes = np.einsum("wkc,wc->wk", pts - A[:, None, :], B - A) / L2[:, None]   # node positions on [0,1]
-    Nfp = pts.shape[1]
-    for i in range(len(wall)):
+    for i, e in enumerate(wall):
         lag = np.ones((len(sg), Nfp))
         for k in range(Nfp):
             for l in range(Nfp):
                 if l != k:
                     lag[:, k] *= (sg - s_nodes[i, l]) / (s_nodes[i, k] - s_nodes[i, l])
-        x = A[i] + sg[:, None] * (B[i] - A[i])
-        G = np.exp(1j * w.omega * (x @ d)) * fac[i]
-        out[wall[i], 0] = np.linalg.solve(lag.T @ (wg[:, None] * lag), lag.T @ (wg * G))
+        G = fn(A[i] + sg[:, None] * (B[i] - A[i]), SIDE_NORMALS[e % 4])
+        out[e, 0] = np.linalg.solve(lag.T @ (wg[:, None] * lag), lag.T @ (wg * G))
     return out
+
+
+def planewave_boundary_data(w: Workload2D, face_points: np.ndarray, project: bool = True) -> np.ndarray:
+    """Impedance data G = e + Z h x n of the plane wave e = exp(i omega d.x),
+    h = (sin theta, -cos theta) e, Z = 1 (so G = e (1 + d.n)), on the wall
+    edges of a Cartesian mesh; [K, 3, Nfp] complex nodal values at the edge
+    nodes face_points [K, 3, Nfp, 2], zero off the impedance edges.
+    project=True returns the L2 projection on each edge (exact edge integrals
+    of the data against the edge basis), project=False samples the nodes."""
+    d = np.array([math.cos(w.theta), math.sin(w.theta)])
+    return _wall_data(w, face_points, lambda x, n: np.exp(1j * w.omega * (x @ d)) * (1.0 + n @ d), project)
+
+
+def waveguide_boundary_data(w: Workload2D, face_points: np.ndarray, project: bool = True) -> np.ndarray:
+    """Impedance data of the waveguide's right wall: the printed data xi =
+    exp(i omega d.x) is read as the Robin data of d_n e + i omega e, so the
+    first-order data is G = xi / (i omega) (see planewave_boundary_data for
+    the layout and `project`)."""
+    d = np.array([math.cos(w.theta), math.sin(w.theta)])
+    return _wall_data(w, face_points, lambda x, n: np.exp(1j * w.omega * (x @ d)) / (1j * w.omega), project)
