@@ -47,11 +47,15 @@ def parse():
                     help="keep the default stage-kernel variant instead of autotuning it in the warm-up solve")
     ap.add_argument("--cpu-steps", type=int, default=4, help="RK steps of the CPU oracle sample")
     ap.add_argument("--kernel-periods", type=int, default=3)
-    ap.add_argument("--workload", choices=["large_single", "batched", "serving", "scatterer", "fw", "trap2d"],
+    ap.add_argument("--workload", choices=["large_single", "batched", "serving", "scatterer", "fw", "trap2d",
+                                           "curves2d"],
                     default="large_single",
                     help="large_single (default bench line), the 64-member batched configuration, or the "
                          "Poisson request stream through the serving engine")
     ap.add_argument("--trap", choices=["square", "disk"], default="disk", help="trap2d: shape of the trap")
+    ap.add_argument("--exp", choices=["cavity", "cavity_near", "planewave", "waveguide", "trap"], default="cavity",
+                    help="curves2d: which 2-D experiment")
+    ap.add_argument("--max-periods", type=int, default=1024, help="curves2d: longest run in simulated periods")
     ap.add_argument("--n2d", type=int, default=75, help="trap2d: cells per side of the Cartesian mesh")
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--fp64-members", type=int, default=64,
@@ -442,6 +446,89 @@ def trap2d_bench(a):
     print(json.dumps(out), flush=True)
 
 
+def curves2d(a):
+    """CMCG against the limiting-amplitude iteration (FW) on the paper's 2-D
+    experiments (Section 6), FP64 fields: error of the filtered field after a
+    given number of simulated periods, relative to the CMCG solution at
+    1e-10 (eps-mu norm; Section 6 measures the trapping-medium case the same
+    way).  CMCG after k iterations has simulated 2 k + 3 periods (two for
+    Algorithm 1, two per iteration, one filter period); FW after L periods
+    has simulated L."""
+    import torch
+
+    from paper_2106_02858_amd import cmcg, inputs
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    exps = {
+        "cavity": lambda: inputs.cavity2d(32, 1, 3 * math.sqrt(2) * math.pi, 1 / 8),
+        "cavity_near": lambda: inputs.cavity2d(32, 1, 3 * math.sqrt(2) * math.pi, 1 / 64),
+        "planewave": lambda: inputs.planewave2d(32, 1, 10 * math.pi),
+        "waveguide": lambda: inputs.waveguide2d(32, 3, 6 * math.pi),
+        "trap": lambda: inputs.trap2d(30, 3, "square"),
+    }
+    w = exps[a.exp]()
+    mesh = cmcg.cmcg_mesh2d_create(w.xy, w.tri, w.tags)
+    s = cmcg.cmcg_space_create(mesh, w.q, cmcg.CMCG_FP64)
+    info = cmcg.cmcg_space_info(s)
+    K, Np = info["K"], info["Np"]
+    nodes = cmcg.cmcg_space_nodes(s)
+    g = None
+    if w.source in ("planewave", "wallwave"):
+        import numpy as np
+        # edge nodes in the library's node order (edge f opposite vertex f, from its lower vertex)
+        q = w.q
+        lab = [(i, j) for j in range(q + 1) for i in range(q + 1 - j)]
+        idx = {l: n for n, l in enumerate(lab)}
+        edges = [[idx[(q - k, k)] for k in range(q + 1)], [idx[(0, k)] for k in range(q + 1)],
+                 [idx[(k, 0)] for k in range(q + 1)]]
+        fp = nodes[:, np.array(edges)]
+        fn = inputs.planewave_boundary_data if w.source == "planewave" else inputs.waveguide_boundary_data
+        g = fn(w, fp)
+    p = cmcg.cmcg_problem_create(s, w.eps, w.mu, None, w.omega, inputs.current_2d(w, nodes), g)
+    M, _ = cmcg.cmcg_problem_steps(p)
+
+    def field(r):
+        fr = torch.zeros((K, 3, Np), dtype=torch.float64, device=dev)
+        fi = torch.zeros_like(fr)
+        cmcg.cmcg_result_filtered_device(r, fr, fi)
+        return fr, fi
+
+    t0 = time.perf_counter()
+    ref = cmcg.cmcg_solve(p, cmcg.cmcg_options_default(tol=1e-10, max_iter=4000))
+    st = cmcg.cmcg_result_stats(ref)
+    Rr, Ri = field(ref)
+    den = cmcg.cmcg_debug_dot(p, Rr, Rr) + cmcg.cmcg_debug_dot(p, Ri, Ri)
+    log(f"{a.exp}: K={K} q={w.q} M={M}; reference CMCG {st['iters']} iterations ({st['status']}) "
+        f"{time.perf_counter() - t0:.1f}s")
+
+    def err(r):
+        fr, fi = field(r)
+        dr, di = fr - Rr, fi - Ri
+        return math.sqrt((cmcg.cmcg_debug_dot(p, dr, dr) + cmcg.cmcg_debug_dot(p, di, di)) / den)
+
+    cm, fw = [], []
+    k = 1
+    while 2 * k + 3 <= a.max_periods and k <= st["iters"]:
+        cm.append([2 * k + 3, err(cmcg.cmcg_solve(p, cmcg.cmcg_options_default(fixed_iters=k)))])
+        k *= 2
+    L = 2
+    while L <= a.max_periods:
+        fw.append([L, err(cmcg.cmcg_fw_solve(p, cmcg.cmcg_options_default(fixed_iters=L)))])
+        L *= 2
+    for (pc, e1) in cm:
+        log(f"  CMCG {pc:5d} periods: {e1:.3e}")
+    for (pf, e2) in fw:
+        log(f"  FW   {pf:5d} periods: {e2:.3e}")
+    out = {"metric": "relative error of the filtered field against the CMCG solution at 1e-10 vs simulated periods",
+           "value": None, "unit": "curves", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": (time.perf_counter() - t0) * 1e3, "higher_is_better": False, "scaling": "strong",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"2-D {a.exp} ({w.name}), {K} triangles, P{w.q}, {M} steps per period",
+                      "reference_iters": st["iters"], "reference_periods": st["periods"]},
+           "curves": {"cmcg": cm, "fw": fw}}
+    print(json.dumps(out), flush=True)
+
+
 def fw_compare(a):
     """CMCG against the limiting-amplitude (FW) iteration on the 48000-tet P3
     problem with FP32 fields: CMCG to --tol, then FW for 1/8, 1/4, 1/2 and 1
@@ -574,6 +661,9 @@ def main():
         return
     if a.workload == "scatterer":
         scatterer(a)
+        return
+    if a.workload == "curves2d":
+        curves2d(a)
         return
     if a.workload == "trap2d":
         trap2d_bench(a)
