@@ -240,3 +240,45 @@ def test_serving_engine_mixes_2d_and_3d_requests(lib):
         lib.cmcg_result_filtered_device(alone, bufs[2], bufs[3])
         assert torch.equal(bufs[0], bufs[2]) and torch.equal(bufs[1], bufs[3])
         assert lib.cmcg_result_stats(served)["iters"] == lib.cmcg_result_stats(alone)["iters"]
+
+
+@pytest.fixture(scope="module")
+def trap_disk_reference():
+    """Oracle right-hand side and one period of the benchmarked 2-D
+    configuration, computed once for both precisions."""
+    w = inputs.trap2d(75, 3, "disk")
+    p0 = dg2d.make_problem(w.xy, w.tri, w.tags, 3, w.eps, w.mu, omega=w.omega)
+    j = inputs.current_2d(w, p0.geo.x)
+    op = dg2d.make_problem(w.xy, w.tri, w.tags, 3, w.eps, w.mu, omega=w.omega, j=j)
+    U = np.random.default_rng(9).standard_normal((op.K, 3, op.Np))
+    t = 0.41 * 2 * math.pi / w.omega
+    M = timestep.n_steps(op)
+    print(f"oracle for the full-size trap disk (K={op.K}, {M} RK4 steps)", flush=True)
+    refU, refF = timestep.forward(op, 1e-2 * U, M, 4, True, filt=True)
+    return w, op, U, t, dg2d.phi(op, t, U), M, refU, refF
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_trap_disk(lib, precision, trap_disk_reference):
+    """The benchmarked 2-D configuration at full size (22500 triangles, P3,
+    Gaussian current, impedance walls): one right-hand side at every element,
+    and one whole period with source and filter, against the oracle."""
+    w, op, U, t, ref, M, refU, refF = trap_disk_reference
+    print(f"full-size trap disk K={w.K} precision={precision}", flush=True)
+    m = lib.cmcg_mesh2d_create(w.xy, w.tri, w.tags)
+    s = lib.cmcg_space_create(m, 3, precision)
+    nodes = lib.cmcg_space_nodes(s)
+    assert np.max(np.abs(nodes - op.geo.x)) < 1e-15
+    lp = lib.cmcg_problem_create(s, w.eps, w.mu, None, w.omega, inputs.current_2d(w, nodes))
+    out = dev(np.zeros_like(U))
+    lib.cmcg_debug_rhs(lp, dev(U), out, t=t, with_source=True)
+    err = np.max(np.abs(host(out) - ref)) / np.max(np.abs(ref))
+    print(f"  rhs max rel err {err:.2e}", flush=True)
+    assert err < TOL[precision]
+    assert lib.cmcg_problem_steps(lp)[0] == M
+    ut = dev(np.zeros_like(U))
+    fr, fi = dev(np.zeros_like(U)), dev(np.zeros_like(U))
+    lib.cmcg_debug_period(lp, dev(1e-2 * U), ut, 1, True, fr, fi)
+    e1, e2 = rel_norm(op, host(ut), refU), rel_norm_c(op, host(fr) + 1j * host(fi), refF)
+    print(f"  period ({M} RK4 steps): state {e1:.2e}, filtered {e2:.2e}", flush=True)
+    assert e1 < TOL[precision] and e2 < TOL[precision]
