@@ -4,9 +4,10 @@
 //
 // Stage kernel: one 64-lane workgroup per block of 21 triangles, lane =
 // (triangle, component).  The block's stage input is staged in LDS with one
-// coalesced load; each lane differentiates its own component (D_a y with
-// uniform matrix operands from constant memory), and the curl terms are
-// exchanged between the three lanes of a triangle:
+// coalesced load, together with the order's D and LIFT (read afterwards as
+// LDS broadcasts, which shortens the chain of scalar-cache loads a lone wave
+// otherwise waits on); each lane differentiates its own component, and the
+// curl terms are exchanged between the three lanes of a triangle:
 //   e row:  -scurl h = -(d1 h2 - d2 h1),   h1 row: d2 e,   h2 row: -d1 e.
 // The upwind flux of the lane's component is formed at the Nfp nodes of each
 // edge (own traces from LDS, neighbour traces from the field) and lifted with
@@ -66,12 +67,14 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
 template <typename T, int Q>
 __global__ __launch_bounds__(64) void k_stage2d(StageArgs a, int64_t per) {
     constexpr int NP = Dim2<Q>::NP, NFP = Dim2<Q>::NFP, NF3 = 3 * NFP;
-    constexpr int MO = mat2_off(Q);
-    constexpr int LO = MO + 2 * NP * NP;  // LIFT [NP][3 NFP]
+    constexpr int MO = 0;                 // D [2][NP][NP] in sM
+    constexpr int LO = 2 * NP * NP;       // LIFT [NP][3 NFP] in sM
+    constexpr int NM = 2 * NP * NP + NP * NF3;
     constexpr int ROWS = EPB * 3;
     __shared__ T sY[ROWS * NP];
     __shared__ T sG[EPB * kGeo2];
     __shared__ int sC[EPB * 3];
+    __shared__ T sM[NM];  // the order's D and LIFT, read as LDS broadcasts
 
     const int64_t b = blockIdx.x;
     const int64_t blk = (b & 7) * per + (b >> 3);  // consecutive blocks on one XCD
@@ -88,6 +91,8 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs a, int64_t per) {
         const int ng = ne * kGeo2;
         for (int v = lane; v < ng; v += 64) sG[v] = geo[e0 * kGeo2 + v];
         for (int v = lane; v < ne * 3; v += 64) sC[v] = a.conn[e0 * 3 + v];
+        const T* gm = mats2<T>() + mat2_off(Q);
+        for (int v = lane; v < NM; v += 64) sM[v] = gm[v];
     }
     __syncthreads();
 
@@ -102,7 +107,7 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs a, int64_t per) {
     const bool needL = COMP && (mode == RK2_S2 || mode == RK4_S4);
     const bool needU = mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || needL;
     const bool needA = mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4;
-    const T* Mt = mats2<T>();
+    const T* Mt = sM;
     const T* gg = &sG[elc * kGeo2];
 
     // ---- FP32 fields: every global load of the stage is requested here,
