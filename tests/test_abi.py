@@ -111,3 +111,44 @@ def test_c_program_links_against_the_library():
         pytest.skip("library not built")
     out = subprocess.run(["ldd", exe], capture_output=True, text=True).stdout
     assert "libcmcg.so" in out and "not found" not in out
+
+
+def test_mesh2d_validation_host_only():
+    """2-D triangle meshes: counts, inscribed-circle diameters, orientation
+    independence and the error paths (host only, no device work)."""
+    from paper_2106_02858_amd import cmcg, inputs
+    xy, tri, tags = inputs.cartesian_triangles(3, 2, side_tags=(1, 2, 1, 2))
+    m = cmcg.cmcg_mesh2d_create(xy, tri, tags)
+    assert cmcg.cmcg_mesh_dim(m) == 2
+    info = cmcg.cmcg_mesh_info(m)
+    assert info["K"] == 24 and info["n_boundary"] == 2 * (3 + 2)
+    h = min(1 / 3, 1 / 2)   # cells 1/3 x 1/2: the smallest inscribed circle sits in the flattest triangles
+    assert 0 < info["min_rho"] < h
+    # clockwise triangles are accepted (normals are oriented by the opposite vertex)
+    cw = tri[:, [0, 2, 1]]
+    cw_tags = tags[:, [0, 2, 1]]
+    assert cmcg.cmcg_mesh_info(cmcg.cmcg_mesh2d_create(xy, cw, cw_tags))["min_rho"] == info["min_rho"]
+    bad = tri.copy()
+    bad[0, 1] = bad[0, 0]
+    with pytest.raises(cmcg.CmcgError) as e:
+        cmcg.cmcg_mesh2d_create(xy, bad, tags)
+    assert e.value.code == cmcg.CMCG_ERR_MESH
+    bad = tri.copy()
+    bad[2, 2] = xy.shape[0]
+    with pytest.raises(cmcg.CmcgError) as e:
+        cmcg.cmcg_mesh2d_create(xy, bad, tags)
+    assert e.value.code == cmcg.CMCG_ERR_ARG
+    t2 = tags.copy()
+    b = np.argwhere(tags > 0)[0]
+    t2[b[0], b[1]] = 0
+    with pytest.raises(cmcg.CmcgError) as e:
+        cmcg.cmcg_mesh2d_create(xy, tri, t2)
+    assert e.value.code == cmcg.CMCG_ERR_MESH
+    with pytest.raises(cmcg.CmcgError) as e:   # an edge shared by three triangles
+        cmcg.cmcg_mesh2d_create(xy, np.concatenate([tri, tri[:1]]), np.concatenate([tags, tags[:1]]))
+    assert e.value.code == cmcg.CMCG_ERR_MESH
+    flat = xy.copy()
+    flat[:, 1] = 0.0                                 # every triangle degenerate
+    with pytest.raises(cmcg.CmcgError) as e:
+        cmcg.cmcg_mesh2d_create(flat, tri, tags)
+    assert e.value.code == cmcg.CMCG_ERR_MESH
