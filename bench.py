@@ -57,6 +57,7 @@ def parse():
                     help="curves2d: which 2-D experiment")
     ap.add_argument("--max-periods", type=int, default=1024, help="curves2d: longest run in simulated periods")
     ap.add_argument("--n2d", type=int, default=75, help="trap2d: cells per side of the Cartesian mesh")
+    ap.add_argument("--members2d", type=int, default=1, help="trap2d: dipole positions solved in one batch")
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--fp64-members", type=int, default=64,
                     help="batched: members also solved one by one with plain FP64 fields (0: none)")
@@ -372,6 +373,66 @@ def cpu_baseline_2d(w, steps: int):
                                         f"P{w.q} mesh ({ndof} dofs), FP64 numpy 2-D oracle, {el:.1f} s"}
 
 
+def trap2d_batch(a):
+    """--members2d B solves of the 2-D dipole-in-trap problem advanced by one
+    batched CMCG (grid.y = member): the dipole at B seeded points of the trap,
+    FP32 fields, shared mesh and media; value = aggregate dof-updates/s."""
+    import numpy as np
+    import torch
+
+    from paper_2106_02858_amd import cmcg, inputs
+    torch.cuda.set_device(0)
+    w = inputs.trap2d(a.n2d, 3, a.trap)
+    mesh = cmcg.cmcg_mesh2d_create(w.xy, w.tri, w.tags)
+    s = cmcg.cmcg_space_create(mesh, w.q, cmcg.CMCG_FP32)
+    nodes = cmcg.cmcg_space_nodes(s)
+    info = cmcg.cmcg_space_info(s)
+    K, Np = info["K"], info["Np"]
+    rng = np.random.default_rng(12)
+    probs = []
+    for _ in range(a.members2d):
+        r, t = 0.4 * math.sqrt(rng.uniform()), rng.uniform(0, 2 * math.pi)   # inside |x| < 0.4
+        w.centre = np.array([r * math.cos(t), r * math.sin(t)])
+        probs.append(cmcg.cmcg_problem_create(s, w.eps, w.mu, None, w.omega, inputs.current_2d(w, nodes)))
+    opts = cmcg.cmcg_options_default(tol=a.tol, max_iter=3000)
+    M, _ = cmcg.cmcg_problem_steps(probs[0], opts)
+    for _ in range(a.warmup):
+        cmcg.cmcg_solve_batch(probs, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        res = cmcg.cmcg_solve_batch(probs, opts)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / a.steps
+    sts = [cmcg.cmcg_result_stats(r) for r in res]
+    dof = sum(st["dof_updates"] for st in sts)
+    log(f"2-D trap batch of {a.members2d}: K={K} M={M}, iterations {min(st['iters'] for st in sts)}-"
+        f"{max(st['iters'] for st in sts)}, {el:.3f} s")
+    bpd = bytes_per_dof_update_2d(3, 4, a.members2d)
+    out = {"metric": "DG dof-updates/s; CMCG time-to-1e-6 residual vs FP64 plain; p50/p99 latency",
+           "value": dof / el, "unit": "dof-updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": el * 1e3, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"2-D TM dipole in a trapping {a.trap}: {a.members2d} dipole positions (seed 12) "
+                                  f"batched on the {K}-triangle P3 mesh, omega = {w.omega / math.pi:.0f} pi; "
+                                  f"CMCG to {a.tol:g}", "K": K, "q": 3, "members": a.members2d,
+                      "steps_per_period": M},
+           "cmcg": {"iters_min": min(st["iters"] for st in sts), "iters_max": max(st["iters"] for st in sts),
+                    "all_converged": all(st["status"] == cmcg.CMCG_OK for st in sts), "seconds": el},
+           "hbm_job": job_roofline(dof / el, bpd)}
+    print(json.dumps(out), flush=True)
+
+
+def bytes_per_dof_update_2d(q: int, esize: int, members: int = 1) -> float:
+    """Algorithmic HBM bytes per 2-D dof-update: the field passes of
+    stage2d_bytes_per_element over the stages of a step, geometry and
+    connectivity shared by the members of a batched launch."""
+    Np = (q + 1) * (q + 2) // 2
+    stages = 4 if q >= 2 else 2
+    field = stage2d_bytes_per_element(q, esize) - (25 * esize + 12)
+    return stages * (field + (25 * esize + 12) / members) / (3 * Np)
+
+
 def trap2d_bench(a):
     """The paper's own 2-D workload (dipole in a trapping body, Section 6),
     transverse-magnetic fields on triangles, P3: CMCG to --tol with FP32
@@ -666,7 +727,10 @@ def main():
         curves2d(a)
         return
     if a.workload == "trap2d":
-        trap2d_bench(a)
+        if a.members2d > 1:
+            trap2d_batch(a)
+        else:
+            trap2d_bench(a)
         return
     if a.workload == "fw":
         fw_compare(a)

@@ -141,13 +141,13 @@ StageArgs batch_args(Batch& bt) {
     a.active = bt.active.as<int>();
     a.msteps = bt.msteps.as<int>();
     a.bstride = bt.n();
-    a.gstride = bt.shared_geo ? 0 : (int64_t)kGeo * bt.sp->K;
+    a.gstride = bt.shared_geo ? 0 : (int64_t)geo_values(*bt.sp) * bt.sp->K;
     a.sstride = bt.n();
     return a;
 }
 
 void enqueue_batch_period(Batch& bt, bool src, bool filt, hipStream_t st) {
-    const int q = bt.sp->q, prec = bt.sp->precision, S = bt.S, B = bt.B;
+    const int prec = bt.sp->precision, S = bt.S, B = bt.B;
     StageArgs a = batch_args(bt);
     a.src_rows = src ? bt.src_rows : 0;
     if (filt) {
@@ -165,14 +165,14 @@ void enqueue_batch_period(Batch& bt, bool src, bool filt, hipStream_t st) {
             a.Ynext = bt.Y1.p;
             a.mtab = row(m, 0);
             a.filter = filt ? 1 : 0;
-            launch_stage(q, prec, a, st);
+            stage_dim(*bt.sp, a, st);
             a.filter = 0;
             a.mode = RK2_S2;
             a.Y = bt.Y1.p;
             a.U = bt.U.p;
             a.Uout = bt.U.p;
             a.mtab = row(m, 1);
-            launch_stage(q, prec, a, st);
+            stage_dim(*bt.sp, a, st);
         } else {
             a.mode = RK4_S1;
             a.Y = bt.U.p;
@@ -181,23 +181,23 @@ void enqueue_batch_period(Batch& bt, bool src, bool filt, hipStream_t st) {
             a.Acc = bt.Acc.p;
             a.mtab = row(m, 0);
             a.filter = filt ? 1 : 0;
-            launch_stage(q, prec, a, st);
+            stage_dim(*bt.sp, a, st);
             a.filter = 0;
             a.mode = RK4_S2;
             a.Y = bt.Y1.p;
             a.Ynext = bt.Y2.p;
             a.mtab = row(m, 1);
-            launch_stage(q, prec, a, st);
+            stage_dim(*bt.sp, a, st);
             a.mode = RK4_S3;
             a.Y = bt.Y2.p;
             a.Ynext = bt.Y1.p;
             a.mtab = row(m, 2);
-            launch_stage(q, prec, a, st);
+            stage_dim(*bt.sp, a, st);
             a.mode = RK4_S4;
             a.Y = bt.Y1.p;
             a.Uout = bt.U.p;
             a.mtab = row(m, 3);
-            launch_stage(q, prec, a, st);
+            stage_dim(*bt.sp, a, st);
         }
     }
     if (filt) {
@@ -212,7 +212,7 @@ void enqueue_batch_period(Batch& bt, bool src, bool filt, hipStream_t st) {
             a.Kout = bt.Kbuf.p;
             a.mtab = row(bt.Mmax, 0);
             a.filter = 1;
-            launch_stage(q, prec, a, st);
+            stage_dim(*bt.sp, a, st);
         }
     }
 }
@@ -252,19 +252,23 @@ void batch_apply(Batch& bt, const cmcg_options* o, const double* X, double* Yo, 
     const int flip = direction < 0 ? 1 : 0;
     const int64_t N = bt.n() * bt.B;
     if (X) {
-        launch_to_field(s.precision, s.Np, X, bt.U.p, bt.Ulo.p, N, flip, st);
+        to_field_dim(s, X, bt.U.p, bt.Ulo.p, N, flip, st);
     } else {
         launch_zero(bt.U.p, bt.U.bytes, st);
         if (bt.Ulo.p) launch_zero(bt.Ulo.p, bt.Ulo.bytes, st);
     }
     run_batch_period(bt, src && direction > 0, filt, o->use_graph != 0, st);
-    if (Yo) launch_from_field(s.precision, s.Np, bt.U.p, bt.Ulo.p, Yo, sub, N, flip, st);
+    if (Yo) from_field_dim(s, bt.U.p, bt.Ulo.p, Yo, sub, N, flip, st);
 }
 
 void batch_dots(Batch& bt, const double* U, const double* V, std::vector<double>& out, hipStream_t st) {
     const SpaceData& s = *bt.sp;
-    launch_dot_batch(s.q, U, V, bt.wE.as<double>(), bt.wH.as<double>(), bt.shared_geo ? 0 : s.K, s.K, bt.B,
-                     bt.partial.as<double>(), bt.dots.as<double>(), st);
+    if (s.dim == 2)
+        launch_dot_batch2d(s.q, U, V, bt.wE.as<double>(), bt.wH.as<double>(), bt.shared_geo ? 0 : s.K, s.K, bt.B,
+                           bt.partial.as<double>(), bt.dots.as<double>(), st);
+    else
+        launch_dot_batch(s.q, U, V, bt.wE.as<double>(), bt.wH.as<double>(), bt.shared_geo ? 0 : s.K, s.K, bt.B,
+                         bt.partial.as<double>(), bt.dots.as<double>(), st);
     CMCG_HIP(hipMemcpyAsync(bt.pin->p, bt.dots.p, bt.B * 8, hipMemcpyDeviceToHost, st));
     CMCG_HIP(hipStreamSynchronize(st));
     out.assign(bt.pin->p, bt.pin->p + bt.B);
@@ -298,7 +302,6 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
     bt.B = B;
     bt.sp = probs[0] ? probs[0]->sp : nullptr;
     if (!bt.sp) fail(CMCG_ERR_ARG, "solve_batch: NULL problem");
-    if (bt.sp->dim == 2) fail(CMCG_ERR_ARG, "solve_batch: 2-D problems are solved singly");
     if (o->runup < 0) fail(CMCG_ERR_ARG, "options: runup must be >= 0");
     for (int b = 0; b < B; ++b) {
         if (!probs[b]) fail(CMCG_ERR_ARG, "solve_batch: NULL problem");
@@ -319,20 +322,21 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
     const SpaceData& s = *bt.sp;
     const int64_t n = s.ndof, K = s.K;
     const size_t esz = s.esize();
+    const int kG = geo_values(s);
     // shared or per-member geometry and mass weights
     if (bt.shared_geo) {
-        bt.geo.alloc(kGeo * K * esz);
+        bt.geo.alloc(kG * K * esz);
         bt.wE.alloc(K * 8);
         bt.wH.alloc(K * 8);
-        CMCG_HIP(hipMemcpyAsync(bt.geo.p, probs[0]->geo.p, kGeo * K * esz, hipMemcpyDeviceToDevice, st));
+        CMCG_HIP(hipMemcpyAsync(bt.geo.p, probs[0]->geo.p, kG * K * esz, hipMemcpyDeviceToDevice, st));
         CMCG_HIP(hipMemcpyAsync(bt.wE.p, probs[0]->wE.p, K * 8, hipMemcpyDeviceToDevice, st));
         CMCG_HIP(hipMemcpyAsync(bt.wH.p, probs[0]->wH.p, K * 8, hipMemcpyDeviceToDevice, st));
     } else {
-        bt.geo.alloc(kGeo * K * esz * B);
+        bt.geo.alloc(kG * K * esz * B);
         bt.wE.alloc(K * 8 * B);
         bt.wH.alloc(K * 8 * B);
         for (int b = 0; b < B; ++b) {
-            CMCG_HIP(hipMemcpyAsync((char*)bt.geo.p + b * kGeo * K * esz, probs[b]->geo.p, kGeo * K * esz,
+            CMCG_HIP(hipMemcpyAsync((char*)bt.geo.p + b * kG * K * esz, probs[b]->geo.p, kG * K * esz,
                                     hipMemcpyDeviceToDevice, st));
             CMCG_HIP(hipMemcpyAsync(bt.wE.as<double>() + b * K, probs[b]->wE.p, K * 8, hipMemcpyDeviceToDevice, st));
             CMCG_HIP(hipMemcpyAsync(bt.wH.as<double>() + b * K, probs[b]->wH.p, K * 8, hipMemcpyDeviceToDevice, st));
@@ -351,13 +355,16 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
         bt.Sim.alloc(bt.fb());
         launch_zero(bt.Sre.p, bt.Sre.bytes, st);
         launch_zero(bt.Sim.p, bt.Sim.bytes, st);
-        const int64_t mw = source_mask_words(K);
-        bt.smask.alloc((size_t)mw * 4 * B);
-        launch_zero(bt.smask.p, bt.smask.bytes, st);
+        const int64_t mw = s.dim == 2 ? 0 : source_mask_words(K);  // 2-D stages read every source row
+        if (mw) {
+            bt.smask.alloc((size_t)mw * 4 * B);
+            launch_zero(bt.smask.p, bt.smask.bytes, st);
+        }
         for (int b = 0; b < B; ++b) {
             if (!probs[b]->src_rows) continue;
-            CMCG_HIP(hipMemcpyAsync(bt.smask.as<uint32_t>() + b * mw, probs[b]->smask.p, mw * 4,
-                                    hipMemcpyDeviceToDevice, st));
+            if (mw)
+                CMCG_HIP(hipMemcpyAsync(bt.smask.as<uint32_t>() + b * mw, probs[b]->smask.p, mw * 4,
+                                        hipMemcpyDeviceToDevice, st));
             CMCG_HIP(hipMemcpyAsync((char*)bt.Sre.p + b * n * esz, probs[b]->Sre.p, n * esz, hipMemcpyDeviceToDevice,
                                     st));
             CMCG_HIP(hipMemcpyAsync((char*)bt.Sim.p + b * n * esz, probs[b]->Sim.p, n * esz, hipMemcpyDeviceToDevice,
@@ -386,7 +393,7 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
     build_table(bt);
     std::vector<int> act(B, 1);
     set_active(bt, act, st);
-    if (o->autotune && !apply_tuned_variant(s.device, s.q, s.precision, K, B)) {
+    if (o->autotune && s.dim == 3 && !apply_tuned_variant(s.device, s.q, s.precision, K, B)) {
         // time the stage variants on up to 8 homogeneous steps of the batched launch
         double us[kStageVariants];
         const int save = bt.Mmax, Mt = std::min(save, 8);

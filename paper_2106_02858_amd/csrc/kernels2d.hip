@@ -43,6 +43,7 @@ template <> __device__ __forceinline__ const double* mats2<double>() { return c2
 template <> __device__ __forceinline__ const float* mats2<float>() { return c2Mat32; }
 
 constexpr int EPB = 21;  // triangles per 64-lane workgroup (63 active lanes)
+constexpr int64_t kEarlyBlocks = 2048;
 
 // Element node of edge node k of edge f (nodes (i, j)/q, j slowest; edge 0 runs
 // from vertex 1 to vertex 2, edge 1 from 0 to 2, edge 2 from 0 to 1).
@@ -64,8 +65,46 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
     e = (a - (s - bb)) + (b - bb);
 }
 
-template <typename T, int Q>
-__global__ __launch_bounds__(64) void k_stage2d(StageArgs a, int64_t per) {
+// Arguments of this workgroup's member in a batched launch (grid.y = member):
+// field, geometry and source pointers move by whole members, the stage
+// scalars come from the member table; false when the member is idle (its CG
+// has converged, or its period has fewer steps than this launch's).
+template <typename T>
+__device__ __forceinline__ bool member_args2d(const StageArgs& in, StageArgs& a) {
+    a = in;
+    a.smask = nullptr;
+    if (!in.mtab) return true;
+    const int b = blockIdx.y;
+    if (!in.active[b]) return false;
+    if (in.step >= 0 && in.step >= in.msteps[b]) return false;
+    const double* p = in.mtab + (int64_t)b * kMemberParams;
+    a.cy = p[0];
+    a.ca = p[1];
+    a.cu = p[2];
+    a.scos = p[3];
+    a.ssin = p[4];
+    a.fa_re = p[5];
+    a.fa_im = p[6];
+    a.fb_re = p[7];
+    a.fb_im = p[8];
+    const int64_t fo = (int64_t)b * in.bstride;
+    if (in.Y) a.Y = (const T*)in.Y + fo;
+    if (in.U) a.U = (const T*)in.U + fo;
+    if (in.Ynext) a.Ynext = (T*)in.Ynext + fo;
+    if (in.Acc) a.Acc = (T*)in.Acc + fo;
+    if (in.Uout) a.Uout = (T*)in.Uout + fo;
+    if (in.Kout) a.Kout = (T*)in.Kout + fo;
+    if (in.Ulo) a.Ulo = (uint16_t*)in.Ulo + fo;
+    if (in.Fre) a.Fre = in.Fre + fo;
+    if (in.Fim) a.Fim = in.Fim + fo;
+    a.geo = (const T*)in.geo + (int64_t)b * in.gstride;
+    if (in.Sre) a.Sre = (const T*)in.Sre + (int64_t)b * in.sstride;
+    if (in.Sim) a.Sim = (const T*)in.Sim + (int64_t)b * in.sstride;
+    return true;
+}
+
+template <typename T, int Q, bool EARLY>
+__global__ __launch_bounds__(64) void k_stage2d(StageArgs args, int64_t per) {
     constexpr int NP = Dim2<Q>::NP, NFP = Dim2<Q>::NFP, NF3 = 3 * NFP;
     constexpr int MO = 0;                 // D [2][NP][NP] in sM
     constexpr int LO = 2 * NP * NP;       // LIFT [NP][3 NFP] in sM
@@ -76,6 +115,8 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs a, int64_t per) {
     __shared__ int sC[EPB * 3];
     __shared__ T sM[NM];  // the order's D and LIFT, read as LDS broadcasts
 
+    StageArgs a;
+    if (!member_args2d<T>(args, a)) return;  // uniform per workgroup
     const int64_t b = blockIdx.x;
     const int64_t blk = (b & 7) * per + (b >> 3);  // consecutive blocks on one XCD
     const int64_t e0 = blk * EPB;
@@ -110,12 +151,12 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs a, int64_t per) {
     const T* Mt = sM;
     const T* gg = &sG[elc * kGeo2];
 
-    // ---- FP32 fields: every global load of the stage is requested here,
-    // before the volume work (neighbour traces of the three edges, update
-    // operands, source rows); the kernel is latency-bound at the paper's
-    // sizes.  FP64 fields gather per edge and load the update operands after
-    // the lift, which keeps P3 within half the register file.
-    constexpr bool EARLY = std::is_same<T, float>::value;
+    // ---- EARLY: every global load of the stage is requested here, before the
+    // volume work (neighbour traces of the three edges, update operands,
+    // source rows): for launches of about one wave per SIMD, where each wave's
+    // chain of dependent loads sets the time.  Otherwise the traces are
+    // gathered per edge and the update operands loaded after the lift, which
+    // keeps the registers (and so the occupancy) of large launches in check.
     T nv[3][NFP][3];
     auto gather = [&](int f, T (&tr)[NFP][3]) {
         const int code = sC[elc * 3 + f];
@@ -380,6 +421,67 @@ __global__ __launch_bounds__(kDot2Threads) void k_dot2d(const double* __restrict
     if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
 }
 
+// Batched form: member b = blockIdx.y, the same block decomposition and
+// summation order per member (a member's inner product equals its single one).
+template <int Q>
+__global__ __launch_bounds__(kDot2Threads) void k_dot2d_batch(const double* __restrict__ U,
+                                                              const double* __restrict__ V,
+                                                              const double* __restrict__ wE,
+                                                              const double* __restrict__ wH, int64_t wstride,
+                                                              int64_t K, double* __restrict__ partial) {
+    constexpr int NP = Dim2<Q>::NP;
+    constexpr int MMO = mat2_off(Q) + 2 * NP * NP + NP * 3 * Dim2<Q>::NFP;
+    __shared__ double sm[kDot2Threads];
+    const int64_t bm = blockIdx.y;
+    const int64_t n = 3 * K * NP;
+    U += bm * n;
+    V += bm * n;
+    wE += bm * wstride;
+    wH += bm * wstride;
+    double acc = 0.0;
+    const int64_t rows = 3 * K;
+    for (int64_t r = blockIdx.x * (int64_t)kDot2Threads + threadIdx.x; r < rows;
+         r += (int64_t)gridDim.x * kDot2Threads) {
+        const double* u = U + r * NP;
+        const double* v = V + r * NP;
+        double vv[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) vv[j] = v[j];
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            double mvv = 0.0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) mvv = fma(c2Mat64[MMO + i * NP + j], vv[j], mvv);
+            s = fma(u[i], mvv, s);
+        }
+        const int64_t e = r / 3;
+        acc = fma(s, (r - 3 * e) == 0 ? wE[e] : wH[e], acc);
+    }
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kDot2Threads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[bm * kDot2Blocks + blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(kDot2Threads) void k_dot2d_final_batch(const double* __restrict__ partial, int n,
+                                                                    double* __restrict__ out) {
+    __shared__ double sm[kDot2Threads];
+    const int bm = blockIdx.x;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += kDot2Threads) acc += partial[(int64_t)bm * kDot2Blocks + i];
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kDot2Threads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[bm] = sm[0];
+}
+
 __global__ __launch_bounds__(kDot2Threads) void k_dot2d_final(const double* __restrict__ partial, int n,
                                                               double* __restrict__ out) {
     __shared__ double sm[kDot2Threads];
@@ -411,7 +513,18 @@ void stage2d(const StageArgs& a, hipStream_t s) {
     const int64_t nb = (a.K + EPB - 1) / EPB;
     const int64_t per = (nb + 7) / 8;
     if (8 * per > 0x7fffffffLL) fail(CMCG_ERR_ARG, "stage2d: too many element blocks");
-    hipLaunchKernelGGL((k_stage2d<T, Q>), dim3((unsigned)(8 * per)), dim3(64), 0, s, a, per);
+    if (a.mtab && (a.nmembers < 1 || a.nmembers > 65535)) fail(CMCG_ERR_ARG, "stage2d: 1 to 65535 members");
+    const dim3 grid((unsigned)(8 * per), (unsigned)(a.mtab ? a.nmembers : 1));
+    // early loads pay off while the launch has at most about two single-wave
+    // workgroups per SIMD (1024 SIMDs); FP64 always takes the lean form
+    const int64_t total = nb * (a.mtab ? a.nmembers : 1);
+    if constexpr (std::is_same<T, float>::value) {
+        if (total <= kEarlyBlocks) {
+            hipLaunchKernelGGL((k_stage2d<T, Q, true>), grid, dim3(64), 0, s, a, per);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_stage2d<T, Q, false>), grid, dim3(64), 0, s, a, per);
 }
 
 }  // namespace
@@ -439,7 +552,6 @@ void upload_constants2d(int q, const double* D, const double* LIFT, const double
 }
 
 void launch_stage2d(int q, int precision, const StageArgs& a, hipStream_t s) {
-    if (a.mtab) fail(CMCG_ERR_ARG, "stage2d: batched launches are not supported in 2-D");
     if (precision == CMCG_FP64) {
         if (q == 1) stage2d<double, 1>(a, s);
         else if (q == 2) stage2d<double, 2>(a, s);
@@ -471,6 +583,20 @@ void launch_from_field2d(int precision, int Np, const void* U, const void* Ulo, 
     else
         hipLaunchKernelGGL(k_from_field2d<float>, dim3(grid2_for(n)), dim3(256), 0, s, (const float*)U,
                            (const uint16_t*)Ulo, Y, sub, n, Np, flipH);
+    check2();
+}
+
+void launch_dot_batch2d(int q, const double* U, const double* V, const double* wE, const double* wH,
+                        int64_t wstride, int64_t K, int B, double* partial, double* out_dev, hipStream_t s) {
+    const dim3 grid(kDot2Blocks, (unsigned)B);
+    if (q == 1)
+        hipLaunchKernelGGL(k_dot2d_batch<1>, grid, dim3(kDot2Threads), 0, s, U, V, wE, wH, wstride, K, partial);
+    else if (q == 2)
+        hipLaunchKernelGGL(k_dot2d_batch<2>, grid, dim3(kDot2Threads), 0, s, U, V, wE, wH, wstride, K, partial);
+    else
+        hipLaunchKernelGGL(k_dot2d_batch<3>, grid, dim3(kDot2Threads), 0, s, U, V, wE, wH, wstride, K, partial);
+    hipLaunchKernelGGL(k_dot2d_final_batch, dim3((unsigned)B), dim3(kDot2Threads), 0, s, partial, kDot2Blocks,
+                       out_dev);
     check2();
 }
 

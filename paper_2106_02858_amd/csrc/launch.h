@@ -119,7 +119,8 @@ void launch_nonfinite(const double* X, int64_t n, int* out_dev, hipStream_t s);
 // 2-D transverse-magnetic path (kernels2d.hip): fields (e, h1, h2), dof layout
 // [K][3][Np], geometry [K][kGeo2], connectivity [K][3] (perm bit: the
 // neighbour runs the edge the other way); the same stage modes and
-// compensated FP32 state as the 3-D kernels; single problems only.
+// compensated FP32 state as the 3-D kernels; batched launches (grid.y =
+// member, StageArgs::mtab non-null) as in 3-D, without the source mask.
 void upload_constants2d(int q, const double* D, const double* LIFT, const double* M, const int* fnode);
 void launch_stage2d(int q, int precision, const StageArgs& a, hipStream_t s);
 void launch_to_field2d(int precision, int Np, const double* X, void* U, void* Ulo, int64_t n, int flipH,
@@ -128,6 +129,8 @@ void launch_from_field2d(int precision, int Np, const void* U, const void* Ulo, 
                          int64_t n, int flipH, hipStream_t s);
 void launch_dot2d(int q, const double* U, const double* V, const double* wE, const double* wH, int64_t K,
                   double* partial, double* out_dev, hipStream_t s);
+void launch_dot_batch2d(int q, const double* U, const double* V, const double* wE, const double* wH,
+                        int64_t wstride, int64_t K, int B, double* partial, double* out_dev, hipStream_t s);
 int64_t stage2d_blocks(int64_t K);
 
 }  // namespace cmcg

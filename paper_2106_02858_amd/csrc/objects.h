@@ -68,6 +68,30 @@ struct SpaceData {
     size_t esize() const { return precision == CMCG_FP64 ? 8 : 4; }
 };
 
+// Dimension dispatch (SpaceData::dim) of the stage and field-conversion
+// kernels, and the per-element geometry size.
+inline int geo_values(const SpaceData& s) { return s.dim == 2 ? kGeo2 : kGeo; }
+inline void stage_dim(const SpaceData& s, const StageArgs& a, hipStream_t st) {
+    if (s.dim == 2)
+        launch_stage2d(s.q, s.precision, a, st);
+    else
+        launch_stage(s.q, s.precision, a, st);
+}
+inline void to_field_dim(const SpaceData& s, const double* X, void* U, void* Ulo, int64_t n, int flip,
+                         hipStream_t st) {
+    if (s.dim == 2)
+        launch_to_field2d(s.precision, s.Np, X, U, Ulo, n, flip, st);
+    else
+        launch_to_field(s.precision, s.Np, X, U, Ulo, n, flip, st);
+}
+inline void from_field_dim(const SpaceData& s, const void* U, const void* Ulo, double* Y, const double* sub,
+                           int64_t n, int flip, hipStream_t st) {
+    if (s.dim == 2)
+        launch_from_field2d(s.precision, s.Np, U, Ulo, Y, sub, n, flip, st);
+    else
+        launch_from_field(s.precision, s.Np, U, Ulo, Y, sub, n, flip, st);
+}
+
 // time-stepping configuration of one solve
 struct StepCfg {
     int M = 0;
