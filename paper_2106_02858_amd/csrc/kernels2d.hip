@@ -157,8 +157,12 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs args, int64_t per) {
     // chain of dependent loads sets the time.  Otherwise the traces are
     // gathered per edge and the update operands loaded after the lift, which
     // keeps the registers (and so the occupancy) of large launches in check.
-    T nv[3][NFP][3];
-    auto gather = [&](int f, T (&tr)[NFP][3]) {
+    // Each lane gathers its own component of the neighbour's edge trace; the
+    // triangle's three lanes then exchange them (lanes 3 el + c), so every
+    // trace value is loaded once.
+    const int base = 3 * elc;
+    T nv[3][NFP];
+    auto gather = [&](int f, T (&own)[NFP]) {
         const int code = sC[elc * 3 + f];
 #pragma unroll
         for (int k = 0; k < NFP; ++k) {
@@ -166,13 +170,18 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs args, int64_t per) {
                 const int64_t nb = code >> 5;
                 const int nf = (code >> 3) & 3;
                 const int kk = (code & 7) ? NFP - 1 - k : k;
-                const int64_t o = nb * 3 * NP + edge_node<Q>(nf, kk);
-                tr[k][0] = Y[o];
-                tr[k][1] = Y[o + NP];
-                tr[k][2] = Y[o + 2 * NP];
+                own[k] = Y[nb * 3 * NP + c * NP + edge_node<Q>(nf, kk)];
             } else {
-                tr[k][0] = tr[k][1] = tr[k][2] = T(0);
+                own[k] = T(0);
             }
+        }
+    };
+    auto expand = [&](const T (&own)[NFP], T (&tr)[NFP][3]) {
+#pragma unroll
+        for (int k = 0; k < NFP; ++k) {
+            tr[k][0] = __shfl(own[k], base);
+            tr[k][1] = __shfl(own[k], base + 1);
+            tr[k][2] = __shfl(own[k], base + 2);
         }
     };
     T up[NP], ap[NP], sr[NP], si[NP];
@@ -211,7 +220,6 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs args, int64_t per) {
         d2[i] = fma(g01, r0, g11 * r1);
     }
     // curl exchange between the triangle's lanes (3 el: e, 3 el + 1: h1, 3 el + 2: h2)
-    const int base = 3 * elc;
     const int srcA = c == 0 ? base + 2 : base;  // lane whose d1 is taken
     const int srcB = c == 0 ? base + 1 : base;  // lane whose d2 is taken
     const T sa = c == 1 ? T(0) : T(-1);
@@ -261,12 +269,17 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs args, int64_t per) {
     };
     if constexpr (EARLY) {
 #pragma unroll
-        for (int f = 0; f < 3; ++f) face(f, nv[f]);
+        for (int f = 0; f < 3; ++f) {
+            T tr[NFP][3];
+            expand(nv[f], tr);
+            face(f, tr);
+        }
     } else {
 #pragma unroll 1
         for (int f = 0; f < 3; ++f) {
-            T tr[NFP][3];
-            gather(f, tr);
+            T own[NFP], tr[NFP][3];
+            gather(f, own);
+            expand(own, tr);
             face(f, tr);
         }
     }
