@@ -59,6 +59,69 @@ __device__ __forceinline__ uint16_t to_bf16(float x) {
 }
 __device__ __forceinline__ float from_bf16(uint32_t h) { return __uint_as_float(h << 16); }
 
+// NP contiguous values of one row: 8-byte accesses for FP32 rows that start on
+// 8-byte boundaries (rows start at multiples of 4 NP bytes: P2 and P3), single
+// accesses otherwise; bfloat16 rows likewise in 4-byte pairs.
+template <typename T, int NP> struct Row2 {
+    static constexpr bool V2 = sizeof(T) == 4 && (NP * 4) % 8 == 0;
+    __device__ __forceinline__ static void load(const T* __restrict__ p, T (&r)[NP]) {
+        if constexpr (V2) {
+            const float2* q = reinterpret_cast<const float2*>(p);
+#pragma unroll
+            for (int c = 0; c < NP / 2; ++c) {
+                const float2 v = q[c];
+                r[2 * c] = v.x;
+                r[2 * c + 1] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NP; ++i) r[i] = p[i];
+        }
+    }
+    __device__ __forceinline__ static void store(T* __restrict__ p, const T (&r)[NP]) {
+        if constexpr (V2) {
+            float2* q = reinterpret_cast<float2*>(p);
+#pragma unroll
+            for (int c = 0; c < NP / 2; ++c) q[c] = make_float2(r[2 * c], r[2 * c + 1]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < NP; ++i) p[i] = r[i];
+        }
+    }
+};
+template <int NP> struct RowLo2 {
+    static constexpr bool V2 = (NP * 2) % 4 == 0;
+    __device__ __forceinline__ static void load(const uint16_t* __restrict__ p, float (&r)[NP]);
+    __device__ __forceinline__ static void store(uint16_t* __restrict__ p, const float (&r)[NP]);
+};
+template <int NP>
+__device__ __forceinline__ void RowLo2<NP>::load(const uint16_t* __restrict__ p, float (&r)[NP]) {
+    if constexpr (V2) {
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+#pragma unroll
+        for (int c = 0; c < NP / 2; ++c) {
+            const uint32_t w = q[c];
+            r[2 * c] = __uint_as_float(w << 16);
+            r[2 * c + 1] = __uint_as_float(w & 0xffff0000u);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) r[i] = __uint_as_float((uint32_t)p[i] << 16);
+    }
+}
+
+template <int NP>
+__device__ __forceinline__ void RowLo2<NP>::store(uint16_t* __restrict__ p, const float (&r)[NP]) {
+    if constexpr (V2) {
+        uint32_t* q = reinterpret_cast<uint32_t*>(p);
+#pragma unroll
+        for (int c = 0; c < NP / 2; ++c) q[c] = (uint32_t)to_bf16(r[2 * c]) | ((uint32_t)to_bf16(r[2 * c + 1]) << 16);
+    } else {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) p[i] = to_bf16(r[i]);
+    }
+}
+
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
     s = a + b;
     const float bb = s - a;
@@ -190,11 +253,15 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs args, int64_t per) {
     auto operands = [&]() {
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
-            up[i] = (act && needU) ? ((const T*)a.U)[grow + i] : T(0);
-            ap[i] = (act && needA) ? ((const T*)a.Acc)[grow + i] : T(0);
-            lo[i] = (act && needL) ? from_bf16(((const uint16_t*)a.Ulo)[grow + i]) : 0.f;
-            sr[i] = src ? ((const T*)a.Sre)[grow + i] : T(0);
-            si[i] = src ? ((const T*)a.Sim)[grow + i] : T(0);
+            up[i] = ap[i] = sr[i] = si[i] = T(0);
+            lo[i] = 0.f;
+        }
+        if (act && needU) Row2<T, NP>::load((const T*)a.U + grow, up);
+        if (act && needA) Row2<T, NP>::load((const T*)a.Acc + grow, ap);
+        if (act && needL) RowLo2<NP>::load((const uint16_t*)a.Ulo + grow, lo);
+        if (src) {
+            Row2<T, NP>::load((const T*)a.Sre + grow, sr);
+            Row2<T, NP>::load((const T*)a.Sim + grow, si);
         }
     };
     if constexpr (EARLY) {
@@ -298,61 +365,58 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs args, int64_t per) {
         for (int i = 0; i < NP; ++i) kv[i] += scos * sr[i] - ssin * si[i];
     }
     const T cy = (T)a.cy, ca = (T)a.ca, cu = (T)a.cu;
-    T* Ynext = (T*)a.Ynext + grow;
-    T* Acc = (T*)a.Acc + grow;
-    T* Uout = (T*)a.Uout + grow;
+    T o1[NP], o2[NP];
+    float lo2[NP];
     switch (mode) {
         case RK2_S1:
 #pragma unroll
-            for (int i = 0; i < NP; ++i) Ynext[i] = fma(cy, kv[i], y[i]);
+            for (int i = 0; i < NP; ++i) o1[i] = fma(cy, kv[i], y[i]);
+            Row2<T, NP>::store((T*)a.Ynext + grow, o1);
             break;
         case RK2_S2:
 #pragma unroll
             for (int i = 0; i < NP; ++i) {
-                if constexpr (COMP) {
-                    float s, e;
-                    two_sum(up[i], fma(cu, kv[i], lo[i]), s, e);
-                    Uout[i] = s;
-                    ((uint16_t*)a.Ulo)[grow + i] = to_bf16(e);
-                } else {
-                    Uout[i] = fma(cu, kv[i], up[i]);
-                }
+                if constexpr (COMP)
+                    two_sum(up[i], fma(cu, kv[i], lo[i]), o1[i], lo2[i]);
+                else
+                    o1[i] = fma(cu, kv[i], up[i]);
             }
+            Row2<T, NP>::store((T*)a.Uout + grow, o1);
+            if constexpr (COMP) RowLo2<NP>::store((uint16_t*)a.Ulo + grow, lo2);
             break;
         case RK4_S1:
 #pragma unroll
             for (int i = 0; i < NP; ++i) {
-                Ynext[i] = fma(cy, kv[i], y[i]);
-                Acc[i] = COMP ? ca * kv[i] : fma(ca, kv[i], y[i]);
+                o1[i] = fma(cy, kv[i], y[i]);
+                o2[i] = COMP ? ca * kv[i] : fma(ca, kv[i], y[i]);
             }
+            Row2<T, NP>::store((T*)a.Ynext + grow, o1);
+            Row2<T, NP>::store((T*)a.Acc + grow, o2);
             break;
         case RK4_S2:
         case RK4_S3:
 #pragma unroll
             for (int i = 0; i < NP; ++i) {
-                Ynext[i] = fma(cy, kv[i], up[i]);
-                Acc[i] = fma(ca, kv[i], ap[i]);
+                o1[i] = fma(cy, kv[i], up[i]);
+                o2[i] = fma(ca, kv[i], ap[i]);
             }
+            Row2<T, NP>::store((T*)a.Ynext + grow, o1);
+            Row2<T, NP>::store((T*)a.Acc + grow, o2);
             break;
         case RK4_S4:
 #pragma unroll
             for (int i = 0; i < NP; ++i) {
-                if constexpr (COMP) {
-                    float s, e;
-                    two_sum(up[i], fma(cu, kv[i], ap[i]) + lo[i], s, e);
-                    Uout[i] = s;
-                    ((uint16_t*)a.Ulo)[grow + i] = to_bf16(e);
-                } else {
-                    Uout[i] = fma(cu, kv[i], ap[i]);
-                }
+                if constexpr (COMP)
+                    two_sum(up[i], fma(cu, kv[i], ap[i]) + lo[i], o1[i], lo2[i]);
+                else
+                    o1[i] = fma(cu, kv[i], ap[i]);
             }
+            Row2<T, NP>::store((T*)a.Uout + grow, o1);
+            if constexpr (COMP) RowLo2<NP>::store((uint16_t*)a.Ulo + grow, lo2);
             break;
-        default: {
-            T* Ko = (T*)a.Kout + grow;
-#pragma unroll
-            for (int i = 0; i < NP; ++i) Ko[i] = kv[i];
+        default:
+            Row2<T, NP>::store((T*)a.Kout + grow, kv);
             break;
-        }
     }
     if (a.filter) {
         double* fr = a.Fre + grow;

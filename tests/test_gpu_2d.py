@@ -317,3 +317,24 @@ def test_batched_members_equal_single_solves(lib, q, precision):
         if precision == 0:
             ref = ocmcg.solve(op, fixed_iters=6)
             assert rel_norm_c(op, filtered(lib, res[b], op), ref.F) < 1e-11
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("walls", [(P,) * 4, (I,) * 4])
+def test_single_cell_mesh(lib, walls, precision):
+    """One Cartesian cell (4 triangles, one partly filled workgroup): right-hand
+    side and a period with source and filter against the oracle."""
+    op, s, lp = pair2d(lib, n=1, q=2, precision=precision, seed=70, walls=walls)
+    assert op.K == 4
+    U = np.random.default_rng(71).standard_normal((op.K, 3, op.Np))
+    out = dev(np.zeros_like(U))
+    lib.cmcg_debug_rhs(lp, dev(U), out, t=0.2, with_source=True)
+    ref = dg2d.phi(op, 0.2, U)
+    assert np.max(np.abs(host(out) - ref)) / np.max(np.abs(ref)) < TOL[precision]
+    M = timestep.n_steps(op)
+    ut = dev(np.zeros_like(U))
+    fr, fi = dev(np.zeros_like(U)), dev(np.zeros_like(U))
+    lib.cmcg_debug_period(lp, dev(U), ut, 1, True, fr, fi)
+    refU, refF = timestep.forward(op, U, M, 4, True, filt=True)
+    assert rel_norm(op, host(ut), refU) < TOL[precision]
+    assert rel_norm_c(op, host(fr) + 1j * host(fi), refF) < TOL[precision]
