@@ -173,7 +173,7 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs args, int64_t per) {
     constexpr int LO = 2 * NP * NP;       // LIFT [NP][3 NFP] in sM
     constexpr int NM = 2 * NP * NP + NP * NF3;
     constexpr int ROWS = EPB * 3;
-    __shared__ T sY[ROWS * NP];
+    __shared__ __align__(16) T sY[ROWS * NP];
     __shared__ T sG[EPB * kGeo2];
     __shared__ int sC[EPB * 3];
     __shared__ T sM[NM];  // the order's D and LIFT, read as LDS broadcasts
@@ -191,7 +191,13 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs args, int64_t per) {
     {
         const int nv = ne * 3 * NP;
         const T* src = Y + e0 * 3 * NP;
-        for (int v = lane; v < nv; v += 64) sY[v] = src[v];
+        if constexpr (Row2<T, NP>::V2) {  // the chunk starts on an 8-byte boundary and holds whole pairs
+            const float2* s2 = reinterpret_cast<const float2*>(src);
+            float2* d2 = reinterpret_cast<float2*>(sY);
+            for (int v = lane; v < nv / 2; v += 64) d2[v] = s2[v];
+        } else {
+            for (int v = lane; v < nv; v += 64) sY[v] = src[v];
+        }
         const int ng = ne * kGeo2;
         for (int v = lane; v < ng; v += 64) sG[v] = geo[e0 * kGeo2 + v];
         for (int v = lane; v < ne * 3; v += 64) sC[v] = a.conn[e0 * 3 + v];
