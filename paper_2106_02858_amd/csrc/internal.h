@@ -88,8 +88,10 @@ struct MeshData {
 // Layout per element: G[9] | per face f: n[3], cE1, cE2, cH1, cH2 (28) |
 // 1/eps, 1/mu, sigma/eps  -> 40 values.
 constexpr int kGeo = 40;
-// 2-D: G[4] | per edge f: n[2], cE1, cE2, cH1, cH2 (18) | 1/eps, 1/mu, sigma/eps.
-constexpr int kGeo2 = 25;
+// 2-D: G[4] | per edge f: n[2], cE1, cE2, cH1, cH2 (18) | 1/eps, 1/mu, sigma/eps,
+// padded to 28 values so that every element's record starts on a 16-byte
+// boundary (the stage kernel stages it with 16-byte loads).
+constexpr int kGeo2 = 28;
 
 }  // namespace cmcg
 

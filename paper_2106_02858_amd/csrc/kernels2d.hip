@@ -174,7 +174,7 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs args, int64_t per) {
     constexpr int NM = 2 * NP * NP + NP * NF3;
     constexpr int ROWS = EPB * 3;
     __shared__ __align__(16) T sY[ROWS * NP];
-    __shared__ T sG[EPB * kGeo2];
+    __shared__ __align__(16) T sG[EPB * kGeo2];
     __shared__ int sC[EPB * 3];
     __shared__ T sM[NM];  // the order's D and LIFT, read as LDS broadcasts
 
@@ -199,7 +199,15 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs args, int64_t per) {
             for (int v = lane; v < nv; v += 64) sY[v] = src[v];
         }
         const int ng = ne * kGeo2;
-        for (int v = lane; v < ng; v += 64) sG[v] = geo[e0 * kGeo2 + v];
+        if constexpr (sizeof(T) == 4) {  // records of 28 values: 7 x 16 bytes each
+            const float4* g4 = reinterpret_cast<const float4*>(geo + e0 * kGeo2);
+            float4* d4 = reinterpret_cast<float4*>(sG);
+            for (int v = lane; v < ng / 4; v += 64) d4[v] = g4[v];
+        } else {  // 14 x 16 bytes
+            const double2* g2 = reinterpret_cast<const double2*>(geo + e0 * kGeo2);
+            double2* d2 = reinterpret_cast<double2*>(sG);
+            for (int v = lane; v < ng / 2; v += 64) d2[v] = g2[v];
+        }
         for (int v = lane; v < ne * 3; v += 64) sC[v] = a.conn[e0 * 3 + v];
         const T* gm = mats2<T>() + mat2_off(Q);
         for (int v = lane; v < NM; v += 64) sM[v] = gm[v];
