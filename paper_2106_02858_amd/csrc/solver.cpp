@@ -392,26 +392,7 @@ static void ensure_work(cmcg_problem* p) {
     p->scal.alloc(64);
 }
 
-// Dimension dispatch of the stage, field-conversion and inner-product kernels.
-static void stage_for(const SpaceData& s, const StageArgs& a, hipStream_t st) {
-    if (s.dim == 2)
-        launch_stage2d(s.q, s.precision, a, st);
-    else
-        launch_stage(s.q, s.precision, a, st);
-}
-static void to_field_for(const SpaceData& s, const double* X, void* U, void* Ulo, int flip, hipStream_t st) {
-    if (s.dim == 2)
-        launch_to_field2d(s.precision, s.Np, X, U, Ulo, s.ndof, flip, st);
-    else
-        launch_to_field(s.precision, s.Np, X, U, Ulo, s.ndof, flip, st);
-}
-static void from_field_for(const SpaceData& s, const void* U, const void* Ulo, double* Y, const double* sub, int flip,
-                           hipStream_t st) {
-    if (s.dim == 2)
-        launch_from_field2d(s.precision, s.Np, U, Ulo, Y, sub, s.ndof, flip, st);
-    else
-        launch_from_field(s.precision, s.Np, U, Ulo, Y, sub, s.ndof, flip, st);
-}
+// Inner product dispatch by dimension (stage and field conversions: objects.h).
 static void dot_for(cmcg_problem* p, const double* U, const double* V, double* out_dev, hipStream_t st) {
     const SpaceData& s = *p->sp;
     if (s.dim == 2)
@@ -441,7 +422,7 @@ static StageArgs base_args(cmcg_problem* p) {
 // F = (2/T) int U e^{-i w t} is accumulated into Fre / Fim (zeroed here).
 static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool filt, hipStream_t st) {
     const SpaceData& s = *p->sp;
-    const int q = s.q, prec = s.precision;
+    const int prec = s.precision;
     const int M = c.M;
     const double dt = c.dt;
     const double two_pi = 2.0 * M_PI;
@@ -490,7 +471,7 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
                 a.filter = 1;
                 for (int h = 0; h < H; ++h) set_filter(h, ph(h, m) * ((m == 0 ? 1.0 : 2.0) / M), 0.0);
             }
-            stage_for(s, a, st);
+            stage_dim(s, a, st);
             a.filter = 0;
             // stage 2: k2 = Phi(t_m + dt/2, Y1); U += dt k2
             a.mode = RK2_S2;
@@ -499,7 +480,7 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
             a.Uout = p->U.p;
             a.cu = dt;
             set_src(m + 0.5);
-            stage_for(s, a, st);
+            stage_dim(s, a, st);
         } else {
             a.mode = RK4_S1;
             a.Y = p->U.p;
@@ -521,7 +502,7 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
                     set_filter(h, wa, wb);
                 }
             }
-            stage_for(s, a, st);
+            stage_dim(s, a, st);
             a.filter = 0;
             a.mode = RK4_S2;
             a.Y = p->Y1.p;
@@ -529,19 +510,19 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
             a.cy = 0.5 * dt;
             a.ca = dt / 3.0;
             set_src(m + 0.5);
-            stage_for(s, a, st);
+            stage_dim(s, a, st);
             a.mode = RK4_S3;
             a.Y = p->Y2.p;
             a.Ynext = p->Y1.p;
             a.cy = dt;
             a.ca = dt / 3.0;
-            stage_for(s, a, st);
+            stage_dim(s, a, st);
             a.mode = RK4_S4;
             a.Y = p->Y1.p;
             a.Uout = p->U.p;
             a.cu = dt / 6.0;
             set_src(m + 1.0);
-            stage_for(s, a, st);
+            stage_dim(s, a, st);
         }
     }
     if (filt) {
@@ -561,7 +542,7 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
             a.filter = 1;
             for (int h = 0; h < H; ++h)
                 set_filter(h, twoT * ph(h, M - 1) * xi[h][1], twoT * ph(h, M - 1) * xi[h][3]);
-            stage_for(s, a, st);
+            stage_dim(s, a, st);
         }
     }
 }
@@ -601,17 +582,16 @@ void apply_period(cmcg_problem* p, const StepCfg& c, const cmcg_options* o, cons
     const SpaceData& s = *p->sp;
     const int flip = direction < 0 ? 1 : 0;
     if (X) {
-        to_field_for(s, X, p->U.p, p->Ulo.p, flip, st);
+        to_field_dim(s, X, p->U.p, p->Ulo.p, s.ndof, flip, st);
     } else {
         launch_zero(p->U.p, p->U.bytes, st);
         if (p->Ulo.p) launch_zero(p->Ulo.p, p->Ulo.bytes, st);
     }
     run_period(p, c, src && direction > 0, filt, o->use_graph != 0, st);
-    if (Yo) from_field_for(s, p->U.p, p->Ulo.p, Yo, sub, flip, st);
+    if (Yo) from_field_dim(s, p->U.p, p->Ulo.p, Yo, sub, s.ndof, flip, st);
 }
 
 double dot(cmcg_problem* p, const double* U, const double* V, hipStream_t st) {
-    const SpaceData& s = *p->sp;
     dot_for(p, U, V, p->scal.as<double>(), st);
     CMCG_HIP(hipMemcpyAsync(p->pinned->p, p->scal.p, 8, hipMemcpyDeviceToHost, st));
     CMCG_HIP(hipStreamSynchronize(st));
@@ -1380,7 +1360,7 @@ int cmcg_debug_rhs(cmcg_problem* p, const cmcg_options* o, double t, int with_so
     prepare(p, c);
     const SpaceData& s = *p->sp;
     p->Kbuf.alloc(s.ndof * s.esize());
-    to_field_for(s, u, p->U.p, p->Ulo.p, 0, stream);
+    to_field_dim(s, u, p->U.p, p->Ulo.p, s.ndof, 0, stream);
     StageArgs a = base_args(p);
     a.mode = RHS;
     a.Y = p->U.p;
@@ -1389,8 +1369,8 @@ int cmcg_debug_rhs(cmcg_problem* p, const cmcg_options* o, double t, int with_so
     a.src_rows = (with_source && p->src_rows) ? p->src_rows : 0;
     a.scos = std::cos(p->omega * t);
     a.ssin = std::sin(p->omega * t);
-    stage_for(s, a, stream);
-    from_field_for(s, p->Kbuf.p, nullptr, out, nullptr, 0, stream);
+    stage_dim(s, a, stream);
+    from_field_dim(s, p->Kbuf.p, nullptr, out, nullptr, s.ndof, 0, stream);
     CMCG_HIP(hipStreamSynchronize(stream));
     return CMCG_OK;
     CMCG_GUARD_END
