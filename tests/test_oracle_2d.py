@@ -261,3 +261,24 @@ def test_cmcg_2d_converges_to_the_discrete_periodic_orbit(q, n, tag):
     Uh, F = fs.discrete_periodic(p, M, timestep.default_scheme(q))
     assert np.max(np.abs(r.F - F)) < 1e-8 * np.max(np.abs(F))
     assert np.max(np.abs(r.U0 - Uh.real)) < 1e-8 * np.max(np.abs(Uh))
+
+
+def test_frequency_domain_converges_to_the_exact_cavity_solution():
+    """Away from resonance (omega = 1.5 sqrt(2) pi) the frequency-domain upwind
+    system converges to the exact cavity solution at rate 2 for P1 (q + 1);
+    P2 and P3 are limited by the corner singularity of the solution (a
+    constant source in a square with e = 0 on the walls) but stay ahead."""
+    def err(q, n):
+        w = inputs.cavity2d(n, q, math.sqrt(2) * math.pi, 0.5)
+        p0 = dg2d.make_problem(w.xy, w.tri, w.tags, q, w.eps, w.mu, omega=w.omega)
+        p = dg2d.make_problem(w.xy, w.tri, w.tags, q, w.eps, w.mu, omega=w.omega, j=inputs.current_2d(w, p0.geo.x))
+        U = fs.frequency_solve(p)
+        e, r = exact2d.energy_error(p.geo, w.xy, w.tri, w.eps, w.mu, U,
+                                    lambda x: exact2d.cavity(w.omega, x, modes=300), nq=8)
+        return e / r
+    e1 = [err(1, n) for n in (4, 8, 16)]
+    rates = [math.log2(e1[i] / e1[i + 1]) for i in range(2)]
+    assert all(1.9 < r < 2.2 for r in rates), rates
+    e2 = [err(2, n) for n in (2, 4)]
+    assert math.log2(e2[0] / e2[1]) > 2.5
+    assert err(3, 4) < e2[1] < e1[1]
