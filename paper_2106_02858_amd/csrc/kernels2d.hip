@@ -59,17 +59,19 @@ __device__ __forceinline__ uint16_t to_bf16(float x) {
 }
 __device__ __forceinline__ float from_bf16(uint32_t h) { return __uint_as_float(h << 16); }
 
-// NP contiguous values of one row: 8-byte accesses for FP32 rows that start on
-// 8-byte boundaries (rows start at multiples of 4 NP bytes: P2 and P3), single
-// accesses otherwise; bfloat16 rows likewise in 4-byte pairs.
+// NP contiguous values of one row in pairs: 8-byte accesses for FP32 rows,
+// 16-byte for FP64 rows, when rows start on such boundaries (they start at
+// multiples of NP sizeof(T) bytes: P2 and P3), single accesses otherwise;
+// bfloat16 rows likewise in 4-byte pairs.
 template <typename T, int NP> struct Row2 {
-    static constexpr bool V2 = sizeof(T) == 4 && (NP * 4) % 8 == 0;
+    static constexpr bool V2 = NP % 2 == 0;
+    using P2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
     __device__ __forceinline__ static void load(const T* __restrict__ p, T (&r)[NP]) {
         if constexpr (V2) {
-            const float2* q = reinterpret_cast<const float2*>(p);
+            const P2* q = reinterpret_cast<const P2*>(p);
 #pragma unroll
             for (int c = 0; c < NP / 2; ++c) {
-                const float2 v = q[c];
+                const P2 v = q[c];
                 r[2 * c] = v.x;
                 r[2 * c + 1] = v.y;
             }
@@ -80,9 +82,14 @@ template <typename T, int NP> struct Row2 {
     }
     __device__ __forceinline__ static void store(T* __restrict__ p, const T (&r)[NP]) {
         if constexpr (V2) {
-            float2* q = reinterpret_cast<float2*>(p);
+            P2* q = reinterpret_cast<P2*>(p);
 #pragma unroll
-            for (int c = 0; c < NP / 2; ++c) q[c] = make_float2(r[2 * c], r[2 * c + 1]);
+            for (int c = 0; c < NP / 2; ++c) {
+                P2 v;
+                v.x = r[2 * c];
+                v.y = r[2 * c + 1];
+                q[c] = v;
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < NP; ++i) p[i] = r[i];
@@ -191,9 +198,10 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs args, int64_t per) {
     {
         const int nv = ne * 3 * NP;
         const T* src = Y + e0 * 3 * NP;
-        if constexpr (Row2<T, NP>::V2) {  // the chunk starts on an 8-byte boundary and holds whole pairs
-            const float2* s2 = reinterpret_cast<const float2*>(src);
-            float2* d2 = reinterpret_cast<float2*>(sY);
+        if constexpr (Row2<T, NP>::V2) {  // the chunk starts on a pair boundary and holds whole pairs
+            using P2 = typename Row2<T, NP>::P2;
+            const P2* s2 = reinterpret_cast<const P2*>(src);
+            P2* d2 = reinterpret_cast<P2*>(sY);
             for (int v = lane; v < nv / 2; v += 64) d2[v] = s2[v];
         } else {
             for (int v = lane; v < nv; v += 64) sY[v] = src[v];
