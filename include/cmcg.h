@@ -193,8 +193,8 @@ int cmcg_mesh_create(int64_t nv, const double* xyz, int64_t K, const int64_t* te
  * e + Z h x n = G, h x n = h1 n2 - h2 n1, edge nodes from the edge's
  * lower-numbered vertex); cmcg_result_fields e[K][Np], h[K][Np][2].  2-D
  * problems are solved by cmcg_solve, cmcg_fw_solve, cmcg_solve_batch and the
- * serving engine, one frequency each; several-harmonic problems and the stage
- * autotuner return CMCG_ERR_ARG for them.
+ * serving engine; cmcg_problem_create_harmonics takes j[nh][K][Np] on a 2-D
+ * space; the stage autotuner returns CMCG_ERR_ARG for them.
  * Errors: CMCG_ERR_ARG (NULL, nv < 3, K < 1, K >= 2^26, index out of range),
  * CMCG_ERR_MESH (zero area, an edge shared by more than two triangles, an
  * untagged boundary edge). */

@@ -17,14 +17,15 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import cmcg, dg, timestep
+from .timestep import ops_of
 from .filters import hermite_xi
 
 
 @dataclass
 class MultiProblem:
-    base: dg.Problem          # mesh and media, omega = omega0, no source
+    base: dg.Problem          # mesh and media, omega = omega0, no source (3-D or 2-D TM)
     ks: list                  # harmonic numbers k_h
-    harm: list                # dg.Problem per harmonic: omega = k_h omega0, its j_h
+    harm: list                # problem per harmonic: omega = k_h omega0, its j_h
 
     @property
     def omega0(self):
@@ -32,16 +33,16 @@ class MultiProblem:
 
 
 def make(base: dg.Problem, ks, js) -> MultiProblem:
-    harm = [dg.Problem(base.geo, base.ref, base.eps, base.mu, base.sigma, k * base.omega, np.asarray(j), None,
+    harm = [type(base)(base.geo, base.ref, base.eps, base.mu, base.sigma, k * base.omega, np.asarray(j), None,
                        base.alpha) for k, j in zip(ks, js)]
     return MultiProblem(base, list(ks), harm)
 
 
 def phi(mp: MultiProblem, t: float, U: np.ndarray, with_source: bool) -> np.ndarray:
-    r = dg.apply_B(mp.base, U)
+    r = ops_of(mp.base).apply_B(mp.base, U)
     if with_source:
         for ph in mp.harm:
-            r = r + dg.source(ph, t)
+            r = r + ops_of(ph).source(ph, t)
     return r
 
 
@@ -50,7 +51,7 @@ def forward(mp: MultiProblem, U0, M: int, scheme: int, with_source: bool, filt: 
     filtered field of every harmonic (trapezoid for RK2, Hermite for RK4)."""
     T = 2 * np.pi / mp.omega0
     dt = T / M
-    U = np.array(U0, dtype=np.float64, copy=True).reshape(mp.base.K, 6, mp.base.Np)
+    U = np.array(U0, dtype=np.float64, copy=True).reshape(mp.base.K, mp.base.ncomp, mp.base.Np)
     Us, Phis = [U], []
     for m in range(M):
         t = m * dt
@@ -103,7 +104,7 @@ def solve(mp: MultiProblem, tol: float = 1e-8, max_iter: int = 1000, M: int | No
     G = P_psi 0 (Algorithm 1) and the final filtered period only."""
     ops = cmcg.Operators(mp.base, M, scheme)
     M, scheme = ops.M, ops.scheme
-    G = forward(mp, np.zeros((mp.base.K, 6, mp.base.Np)), M, scheme, True)
+    G = forward(mp, np.zeros((mp.base.K, mp.base.ncomp, mp.base.Np)), M, scheme, True)
     Gstar = G - ops.P_star(G)
     U = np.zeros_like(G)
     R = -Gstar

@@ -385,6 +385,17 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs args, int64_t per) {
         const T scos = (T)a.scos, ssin = (T)a.ssin;
 #pragma unroll
         for (int i = 0; i < NP; ++i) kv[i] += scos * sr[i] - ssin * si[i];
+        // further harmonics of a several-frequency source (single launches only,
+        // so the kernel arguments hold this problem's tables; they are indexed
+        // there, not in the local copy, which would go to scratch)
+#pragma unroll 1
+        for (int h = 1; h < args.nharm; ++h) {
+            Row2<T, NP>::load((const T*)args.Sre + h * args.hstride + grow, sr);
+            Row2<T, NP>::load((const T*)args.Sim + h * args.hstride + grow, si);
+            const T hc = (T)args.hcos[h], hs = (T)args.hsin[h];
+#pragma unroll
+            for (int i = 0; i < NP; ++i) kv[i] += hc * sr[i] - hs * si[i];
+        }
     }
     const T cy = (T)a.cy, ca = (T)a.ca, cu = (T)a.cu;
     T o1[NP], o2[NP];
@@ -448,6 +459,17 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs args, int64_t per) {
             const double ud = (double)y[i], kd = (double)kv[i];
             fr[i] += a.fa_re * ud + a.fb_re * kd;
             fi[i] += a.fa_im * ud + a.fb_im * kd;
+        }
+#pragma unroll 1
+        for (int h = 1; h < args.nharm; ++h) {  // each harmonic filtered at its own frequency
+            double* hr = args.Fre + h * args.hstride + grow;
+            double* hi = args.Fim + h * args.hstride + grow;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                const double ud = (double)y[i], kd = (double)kv[i];
+                hr[i] += args.hfa_re[h] * ud + args.hfb_re[h] * kd;
+                hi[i] += args.hfa_im[h] * ud + args.hfb_im[h] * kd;
+            }
         }
     }
 }

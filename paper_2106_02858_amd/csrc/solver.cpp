@@ -166,16 +166,17 @@ static void upload_field(const SpaceData& s, DevBuf& b, const std::vector<double
     }
 }
 
-// 2-D source: j [K][Np] on the e row; impedance data G [K][3][Nfp] through the
-// ghost e+ = G, h+ = 0 of the wall edges: flux_e = G / (2 Z), flux_h =
-// (n2 G, -n1 G) / 2, lifted with the edge scaling.
+// 2-D source: j [nh][K][Np] on the e row (harmonic h at hstride = ndof);
+// impedance data G [K][3][Nfp] (one frequency) through the ghost e+ = G, h+ = 0
+// of the wall edges: flux_e = G / (2 Z), flux_h = (n2 G, -n1 G) / 2, lifted
+// with the edge scaling.
 static void build_source2d(cmcg_problem* p, const double* j_re, const double* j_im, const double* g_re,
-                           const double* g_im) {
+                           const double* g_im, int nh) {
     const SpaceData& s = *p->sp;
     const MeshData& m = *s.mesh;
     const int64_t K = s.K;
     const int Np = s.Np, Nfp = s.Nfp;
-    const int64_t nj = K * Np, ng = K * 3 * (int64_t)Nfp;
+    const int64_t nj = nh * K * Np, ng = K * 3 * (int64_t)Nfp;
     for (const double* a : {j_re, j_im})
         if (a)
             for (int64_t i = 0; i < nj; ++i)
@@ -187,12 +188,14 @@ static void build_source2d(cmcg_problem* p, const double* j_re, const double* j_
     p->has_j = j_re || j_im;
     p->has_g = g_re || g_im;
     if (!p->has_j && !p->has_g) return;
-    std::vector<double> sr(s.ndof, 0.0), si(s.ndof, 0.0);
-    for (int64_t e = 0; e < K; ++e)
-        for (int i = 0; i < Np; ++i) {
-            if (j_re) sr[e * 3 * Np + i] = j_re[e * Np + i] / p->eps[e];
-            if (j_im) si[e * 3 * Np + i] = j_im[e * Np + i] / p->eps[e];
-        }
+    std::vector<double> sr(s.ndof * nh, 0.0), si(s.ndof * nh, 0.0);
+    for (int h = 0; h < nh; ++h)
+        for (int64_t e = 0; e < K; ++e)
+            for (int i = 0; i < Np; ++i) {
+                const int64_t src = (h * K + e) * Np + i, dst = h * s.ndof + e * 3 * Np + i;
+                if (j_re) sr[dst] = j_re[src] / p->eps[e];
+                if (j_im) si[dst] = j_im[src] / p->eps[e];
+            }
     if (p->has_g) {
         const RefElem2D& r = ref_elem2d(s.q);
         for (int64_t e = 0; e < K; ++e) {
@@ -273,8 +276,7 @@ static cmcg_problem* make_problem(const cmcg_space* sh, const double* eps, const
     CMCG_HIP(hipMemcpy(p->wE.p, we.data(), K * 8, hipMemcpyHostToDevice));
     CMCG_HIP(hipMemcpy(p->wH.p, wh.data(), K * 8, hipMemcpyHostToDevice));
     if (sp->dim == 2) {
-        if (nh != 1) fail(CMCG_ERR_ARG, "problem: several harmonics are not supported on 2-D spaces");
-        build_source2d(p.get(), j_re, j_im, g_re, g_im);
+        build_source2d(p.get(), j_re, j_im, g_re, g_im, nh);
         build_geo(p.get(), 1.0);
         p->pinned.reset(new HostPinned());
         return p.release();

@@ -179,11 +179,8 @@ def test_result_fields_layout(lib):
 
 def test_unsupported_2d_calls_are_rejected(lib):
     op, s, lp = pair2d(lib, n=2, q=1)
-    with pytest.raises(lib.CmcgError):
+    with pytest.raises(lib.CmcgError):   # one 2-D stage kernel per precision: nothing to tune
         lib.cmcg_autotune_stage(lp)
-    with pytest.raises(lib.CmcgError):
-        lib.cmcg_problem_create_harmonics(s, op.eps, op.mu, None, op.omega, [1, 2],
-                                          np.zeros((2, op.K, op.Np)))
 
 
 @pytest.mark.parametrize("delta", [0.125, 0.015625])
@@ -338,3 +335,36 @@ def test_single_cell_mesh(lib, walls, precision):
     refU, refF = timestep.forward(op, U, M, 4, True, filt=True)
     assert rel_norm(op, host(ut), refU) < TOL[precision]
     assert rel_norm_c(op, host(fr) + 1j * host(fi), refF) < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("q", [1, 2])
+def test_several_harmonics(lib, q, precision):
+    """A three-harmonic current (k = 1, 2, 3 times omega0) on a 2-D problem:
+    CMCG at a fixed iteration count over the base period, each harmonic
+    filtered at its own frequency, against the oracle."""
+    from oracle import multifreq
+    xy, tri, tags = inputs.cartesian_triangles(4, 4, side_tags=(P, I, I, I))
+    K = tri.shape[0]
+    eps = np.random.default_rng(13).choice([1.0, 2.0], K)
+    omega0 = 1.5 * np.pi
+    base = dg2d.make_problem(xy, tri, tags, q, eps, np.ones(K), omega=omega0)
+    ks = [1, 2, 3]
+    js = [np.exp(-np.sum((base.geo.x - c) ** 2, axis=-1) / 0.1) * (1 + 0.5j * h)
+          for h, c in enumerate(((0.4, 0.5), (0.6, 0.4), (0.5, 0.6)))]
+    mp = multifreq.make(base, ks, js)
+    m = lib.cmcg_mesh2d_create(xy, tri, tags)
+    s = lib.cmcg_space_create(m, q, precision)
+    lp = lib.cmcg_problem_create_harmonics(s, eps, np.ones(K), None, omega0, ks, np.stack(js))
+    M0 = 6 * ((lib.cmcg_problem_steps(lp, lib.cmcg_options_default())[0] + 5) // 6)
+    ref = multifreq.solve(mp, M=M0, fixed_iters=8)
+    r = lib.cmcg_solve(lp, lib.cmcg_options_default(fixed_iters=8, steps=M0))
+    assert lib.cmcg_result_harmonics(r) == 3
+    import torch
+    for h in range(3):
+        fr = torch.zeros((K, 3, base.Np), dtype=torch.float64, device="cuda")
+        fi = torch.zeros_like(fr)
+        lib.cmcg_result_filtered_harmonic_device(r, h, fr, fi)
+        err = rel_norm_c(base, fr.cpu().numpy() + 1j * fi.cpu().numpy(), ref.Fs[h])
+        print(f"  2-D harmonic k={ks[h]} q={q} prec={precision}: {err:.2e}", flush=True)
+        assert err < (1e-11 if precision == 0 else 1e-5)
