@@ -509,10 +509,12 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
 #pragma unroll
         for (int i = 0; i < NP; ++i) kv[i] += scos * sr[i] - ssin * si[i];
 #pragma unroll 1
-        for (int h = 1; MH && h < a.nharm; ++h) {  // further harmonics of a several-frequency source
-            Row<T, NP>::load((const T*)a.Sre + h * a.hstride + grow, sr);
-            Row<T, NP>::load((const T*)a.Sim + h * a.hstride + grow, si);
-            const T hc = (T)a.hcos[h], hs = (T)a.hsin[h];
+        // further harmonics of a several-frequency source (single launches, so the
+        // kernel arguments hold the tables; indexing the local copy put it in scratch)
+        for (int h = 1; MH && h < a.nharm; ++h) {
+            Row<T, NP>::load((const T*)args.Sre + h * args.hstride + grow, sr);
+            Row<T, NP>::load((const T*)args.Sim + h * args.hstride + grow, si);
+            const T hc = (T)args.hcos[h], hs = (T)args.hsin[h];
 #pragma unroll
             for (int i = 0; i < NP; ++i) kv[i] += hc * sr[i] - hs * si[i];
         }
@@ -586,13 +588,13 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
         }
 #pragma unroll 1
         for (int h = 1; MH && h < a.nharm; ++h) {
-            double* hr = a.Fre + h * a.hstride + grow;
-            double* hi = a.Fim + h * a.hstride + grow;
+            double* hr = args.Fre + h * args.hstride + grow;
+            double* hi = args.Fim + h * args.hstride + grow;
 #pragma unroll
             for (int i = 0; i < NP; ++i) {
                 const double ud = (double)y[i], kd = (double)kv[i];
-                hr[i] += a.hfa_re[h] * ud + a.hfb_re[h] * kd;
-                hi[i] += a.hfa_im[h] * ud + a.hfb_im[h] * kd;
+                hr[i] += args.hfa_re[h] * ud + args.hfb_re[h] * kd;
+                hi[i] += args.hfa_im[h] * ud + args.hfb_im[h] * kd;
             }
         }
     }
@@ -918,10 +920,11 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ?
                 if (takes_src(row)) kv[u] += scos * srv[u] - ssin * siv[u];
             }
 #pragma unroll 1
-            for (int h = 1; MH && h < a.nharm; ++h) {  // further harmonics of a several-frequency source
-                const float4 hr = *f4(a.Sre, h * a.hstride + gi), hi = *f4(a.Sim, h * a.hstride + gi);
+            // further harmonics (tables read from the kernel arguments, as in k_stage)
+            for (int h = 1; MH && h < a.nharm; ++h) {
+                const float4 hr = *f4(args.Sre, h * args.hstride + gi), hi = *f4(args.Sim, h * args.hstride + gi);
                 const T hrv[4] = {hr.x, hr.y, hr.z, hr.w}, hiv[4] = {hi.x, hi.y, hi.z, hi.w};
-                const T hc = (T)a.hcos[h], hs = (T)a.hsin[h];
+                const T hc = (T)args.hcos[h], hs = (T)args.hsin[h];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int row = (v + u) / NP;
@@ -1001,8 +1004,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ?
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const double ud = (double)x0[u], kd = (double)kv[u];
-                    a.Fre[h * a.hstride + gi + u] += a.hfa_re[h] * ud + a.hfb_re[h] * kd;
-                    a.Fim[h * a.hstride + gi + u] += a.hfa_im[h] * ud + a.hfb_im[h] * kd;
+                    args.Fre[h * args.hstride + gi + u] += args.hfa_re[h] * ud + args.hfb_re[h] * kd;
+                    args.Fim[h * args.hstride + gi + u] += args.hfa_im[h] * ud + args.hfb_im[h] * kd;
                 }
         }
     }
