@@ -6,6 +6,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -35,15 +36,36 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def _scratch_kernels(remarks: str):
+    """Stage kernels that the compiler's resource-usage remarks show using
+    per-lane scratch memory (a spill, or a dynamically indexed local array)."""
+    bad, name = [], None
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and name and "k_stage" in name and int(m.group(1)) > 0:
+            bad.append(f"{name} ({m.group(1)} B/lane)")
+    return bad
+
+
 def _compile(src: str) -> str:
     out = os.path.join(OBJ, os.path.basename(src) + ".o")
     cmd = [hipcc()] + COMMON
     if src.endswith(".hip"):
-        cmd += DEVICE + ["-x", "hip"]
+        cmd += DEVICE + ["-x", "hip", "-Rpass-analysis=kernel-resource-usage"]
     cmd += ["-c", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if src.endswith(".hip"):
+        # the stage kernels are latency-bound: scratch traffic in them has cost
+        # up to 2.4x, so the build refuses it
+        bad = _scratch_kernels(r.stderr)
+        if bad:
+            raise RuntimeError(f"stage kernels use scratch memory in {src}: " + ", ".join(bad))
     return out
 
 
