@@ -650,8 +650,6 @@ void stage2d(const StageArgs& a, hipStream_t s) {
 
 }  // namespace
 
-int64_t stage2d_blocks(int64_t K) { return (K + EPB - 1) / EPB; }
-
 void upload_constants2d(int q, const double* D, const double* LIFT, const double* M, const int* fnode) {
     const int NP = np2_of(q), NFP = nfp2_of(q);
     for (int f = 0; f < 3; ++f)

@@ -131,6 +131,5 @@ void launch_dot2d(int q, const double* U, const double* V, const double* wE, con
                   double* partial, double* out_dev, hipStream_t s);
 void launch_dot_batch2d(int q, const double* U, const double* V, const double* wE, const double* wH,
                         int64_t wstride, int64_t K, int B, double* partial, double* out_dev, hipStream_t s);
-int64_t stage2d_blocks(int64_t K);
 
 }  // namespace cmcg
