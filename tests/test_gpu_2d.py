@@ -368,3 +368,29 @@ def test_several_harmonics(lib, q, precision):
         err = rel_norm_c(base, fr.cpu().numpy() + 1j * fi.cpu().numpy(), ref.Fs[h])
         print(f"  2-D harmonic k={ks[h]} q={q} prec={precision}: {err:.2e}", flush=True)
         assert err < (1e-11 if precision == 0 else 1e-5)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_lean_form_equals_single_early_form(lib, precision):
+    """A batch above the early-load threshold (30 members x 77 workgroups) runs
+    the lean stage form while each single solve of the same 1600-triangle
+    problem runs the early-load form: the two forms do the same arithmetic in
+    the same order, so the members still equal their single solves bit for
+    bit."""
+    xy, tri, tags = inputs.cartesian_triangles(20, 20, side_tags=(I, I, P, I))
+    K = tri.shape[0]
+    m = lib.cmcg_mesh2d_create(xy, tri, tags)
+    s = lib.cmcg_space_create(m, 3, precision)
+    nodes = lib.cmcg_space_nodes(s)
+    rng = np.random.default_rng(80)
+    lps = []
+    for b in range(30):
+        c = rng.uniform(0.2, 0.8, 2)
+        j = np.exp(-np.sum((nodes - c) ** 2, axis=-1) / 0.02)
+        lps.append(lib.cmcg_problem_create(s, np.ones(K), np.ones(K), None, 4 * math.pi, j))
+    o = lib.cmcg_options_default(fixed_iters=3)
+    res = lib.cmcg_solve_batch(lps, o)
+    op = dg2d.make_problem(xy, tri, tags, 3, np.ones(K), np.ones(K))
+    for b in (0, 13, 29):
+        single = lib.cmcg_solve(lps[b], o)
+        assert np.array_equal(filtered(lib, res[b], op), filtered(lib, single, op)), b
