@@ -83,12 +83,20 @@ MEASURED_TRAFFIC = {
 }
 
 
-def measured_traffic(kernel: str, K: int):
+# The same for the 2-D stage kernel on the 22500-triangle disk trap (P3, FP32).
+MEASURED_TRAFFIC_2D = {
+    "kernels_sha256": "2cfab2a02241355bb5ef28a6732137553b93d1adb24d0d1f204160b9cff12150",
+    "kernel": "k_stage2d<float,3,true>", "K": 22500,
+    "fetch_kib": 5064.65, "fetch_scale": 2.0000, "write_kib": 4944.12, "write_scale": 1.0000,
+}
+
+
+def measured_traffic(kernel: str, K: int, table=None, source: str = "kernels.hip"):
     """HBM bytes per launch from the committed counter runs, or None when the
     kernel source or the workload differs from the one measured."""
     import hashlib
-    t = MEASURED_TRAFFIC
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2106_02858_amd", "csrc", "kernels.hip")
+    t = MEASURED_TRAFFIC if table is None else table
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2106_02858_amd", "csrc", source)
     try:
         with open(src, "rb") as f:
             digest = hashlib.sha256(f.read()).hexdigest()
@@ -499,7 +507,9 @@ def trap2d_bench(a):
                     "seconds": f32["el"], "fp64_iters": f64["st"]["iters"], "fp64_seconds": f64["el"],
                     "speedup_vs_fp64": f64["el"] / f32["el"]},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_stage2d<float,3>",
+                        "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": measured_traffic("k_stage2d<float,3,true>", K, MEASURED_TRAFFIC_2D, "kernels2d.hip"),
+                        "kernel": "k_stage2d<float,3,true>",
                         "avg_launch_us": f32["per_launch"] * 1e6, "bytes_per_launch": bpe * K,
                         "fp64_avg_launch_us": f64["per_launch"] * 1e6}}
     if not a.no_cpu:

@@ -1,9 +1,11 @@
 """Counter workload for HBM-traffic measurement of the stage kernel.
 
     python -m paper_2106_02858_amd.counters [--n 20 --q 3 --periods 2]
+    python -m paper_2106_02858_amd.counters --trap2d      # the 2-D disk trap instead
 
 Runs whole homogeneous periods (4 M stage launches each) of the large
-single-solve problem (48000 tets, P3, FP32 fields), then a plain elementwise
+single-solve problem (48000 tets, P3, FP32 fields) -- or, with --trap2d, of
+the 2-D dipole-in-trap problem (22500 triangles, P3, FP32) -- then a plain elementwise
 copy of known size (read 4 B, write 4 B per float; 1 GiB each way) that
 calibrates what FETCH_SIZE / WRITE_SIZE report per byte moved.  Under
 `rocprofv3 --pmc FETCH_SIZE` (then WRITE_SIZE) the per-dispatch averages of
@@ -22,12 +24,30 @@ def main() -> int:
     ap.add_argument("--periods", type=int, default=2)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--copies", type=int, default=4)
+    ap.add_argument("--trap2d", action="store_true")
     a = ap.parse_args()
     import torch
 
     from . import cmcg, inputs
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if a.trap2d:
+        w = inputs.trap2d(75, 3, "disk")
+        mesh = cmcg.cmcg_mesh2d_create(w.xy, w.tri, w.tags)
+        s = cmcg.cmcg_space_create(mesh, 3, cmcg.CMCG_FP32)
+        p = cmcg.cmcg_problem_create(s, w.eps, w.mu, None, w.omega,
+                                     inputs.current_2d(w, cmcg.cmcg_space_nodes(s)))
+        info = cmcg.cmcg_space_info(s)
+        K, Np = info["K"], info["Np"]
+        M, _ = cmcg.cmcg_problem_steps(p)
+        print(f"2-D stage kernel: K={K} Np={Np} M={M}, {a.periods} periods = {4 * M * a.periods} launches",
+              flush=True)
+        U0 = torch.randn((K, 3, Np), dtype=torch.float64, device=dev) * 1e-3
+        UT = torch.empty_like(U0)
+        for _ in range(a.periods):
+            cmcg.cmcg_debug_period(p, U0, UT, 1, False)
+        torch.cuda.synchronize()
+        return copy_calibration(a, dev)
     w = inputs.large_single(n=a.n, q=a.q)
     mesh = cmcg.cmcg_mesh_create(w.xyz, w.tet, w.tags)
     s = cmcg.cmcg_space_create(mesh, w.q, cmcg.CMCG_FP32)
@@ -44,6 +64,13 @@ def main() -> int:
     for _ in range(a.periods):
         cmcg.cmcg_debug_period(p, U0, UT, 1, False, opts=opts)
     torch.cuda.synchronize()
+    return copy_calibration(a, dev)
+
+
+def copy_calibration(a, dev) -> int:
+    """Plain elementwise copies of known size (torch.neg: read and write
+    copy_mib MiB each): what FETCH_SIZE / WRITE_SIZE report per byte moved."""
+    import torch
     n = a.copy_mib * (1 << 20) // 4
     x = torch.ones(n, dtype=torch.float32, device=dev)
     y = torch.empty_like(x)
