@@ -6,10 +6,16 @@ device memory and streams); host arrays are numpy arrays.  Functions keep the
 C names; the small classes only attach the matching *_destroy call to the
 handle's lifetime.  Importing this module fails loudly when the library has
 not been built.
+
+A program that also uses torch on the device initialises torch first (for
+instance torch.cuda.set_device(0)): the HIP runtime that is loaded first
+serves both, and torch cannot start on one the library loaded before it.
+Without torch, host arrays and the default stream suffice.
 """
 from __future__ import annotations
 
 import ctypes as C
+import sys
 import os
 
 import numpy as np
@@ -156,11 +162,17 @@ def _ptr(a):
 
 
 def _stream(stream=None):
-    """A raw HIP stream handle, a torch stream, or None (torch's current stream)."""
+    """A raw HIP stream handle, a torch stream, or None: torch's current
+    stream when torch has already initialised the device, else the default
+    stream.  (Initialising torch here, after the library has started the HIP
+    runtime on its own, would fail: the device runtime is set up by whichever
+    comes first.)"""
     if stream is not None:
         return getattr(stream, "cuda_stream", stream)
-    import torch
-    return torch.cuda.current_stream().cuda_stream
+    torch = sys.modules.get("torch")
+    if torch is not None and torch.cuda.is_initialized():
+        return torch.cuda.current_stream().cuda_stream
+    return None
 
 
 def cmcg_version():

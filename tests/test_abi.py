@@ -152,3 +152,16 @@ def test_mesh2d_validation_host_only():
     with pytest.raises(cmcg.CmcgError) as e:
         cmcg.cmcg_mesh2d_create(flat, tri, tags)
     assert e.value.code == cmcg.CMCG_ERR_MESH
+
+
+def test_default_stream_does_not_start_torch():
+    """With no stream given and torch not yet on the device, the binding uses
+    the default stream and leaves torch alone (starting torch after the library
+    has loaded its own HIP runtime fails); in a fresh interpreter."""
+    import subprocess
+    import sys
+    code = ("import sys; from paper_2106_02858_amd import cmcg; "
+            "assert cmcg._stream(None) is None; assert 'torch' not in sys.modules; print('ok')")
+    root = __import__("os").path.dirname(__import__("os").path.dirname(__import__("os").path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root, timeout=120)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", r.stderr
