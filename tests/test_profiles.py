@@ -1,0 +1,78 @@
+"""The committed rocprofv3 summaries agree with what bench.py reports from them.
+
+* every command a summary gives runs committed files only (the repository's
+  bench.py or a module of the package), with the program directly after
+  ``--`` and counter passes that stay within one run's hardware limits;
+* the traffic summaries hold the same per-dispatch FETCH_SIZE / WRITE_SIZE
+  means, kernel name and source SHA-256 as the tables bench.py scales into
+  ``roofline.traffic``, so a re-taken counter run cannot be reported from a
+  stale table or the reverse.
+"""
+from __future__ import annotations
+
+import os
+import re
+
+import pytest
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def _summaries():
+    return sorted(f for f in os.listdir(PROFILES) if f.endswith((".md", ".txt")))
+
+
+def _commands(text: str):
+    cmds, inside = [], False
+    for line in text.splitlines():
+        if line.startswith("```"):
+            inside = not inside
+            continue
+        if inside and line.startswith("rocprofv3"):
+            cmds.append(line.split())
+    return cmds
+
+
+@pytest.mark.parametrize("name", _summaries())
+def test_profile_commands_run_committed_files(name):
+    text = open(os.path.join(PROFILES, name)).read()
+    assert "round" not in name.lower()
+    cmds = _commands(text)
+    assert cmds, f"{name} gives no rocprofv3 command"
+    for argv in cmds:
+        prog = argv[argv.index("--") + 1:]
+        assert prog[0] in ("python", "python3"), argv
+        if prog[1] == "-m":
+            path = os.path.join(ROOT, *prog[2].split(".")) + ".py"
+        else:
+            path = os.path.join(ROOT, prog[1])
+        assert os.path.isfile(path), f"{name}: {path} is not in the repository"
+        assert "_work" not in " ".join(argv)
+        if "--pmc" in argv:
+            # counters go in runs of their own, without trace domains
+            assert not {"--kernel-trace", "--stats", "-s", "--sys-trace", "-r",
+                        "--runtime-trace"} & set(argv), argv
+            counters = argv[argv.index("--pmc") + 1:argv.index("-d")]
+            sq = [c for c in counters if c.startswith("SQ_")]
+            tcc = [c for c in counters if c.startswith("TCC_") or c in ("FETCH_SIZE", "WRITE_SIZE")]
+            assert len(sq) <= 8 and len(tcc) <= 2, argv
+
+
+def _traffic_table(text: str):
+    sha = re.search(r"\b([0-9a-f]{64})\b", text).group(1)
+    row = re.search(r"^\| `(k_stage[^`]*)` \| (\d+) \| ([\d.]+) \| ([\d.]+) \|", text, re.M)
+    return sha, row.group(1), float(row.group(3)), float(row.group(4))
+
+
+@pytest.mark.parametrize("name,table", [
+    ("k_stage_mfma_q3_large_single_traffic.md", bench.MEASURED_TRAFFIC),
+    ("k_stage2d_p3_trap_disk_traffic.md", bench.MEASURED_TRAFFIC_2D),
+])
+def test_traffic_summary_matches_bench_table(name, table):
+    sha, kernel, fetch, write = _traffic_table(open(os.path.join(PROFILES, name)).read())
+    assert sha == table["kernels_sha256"]
+    assert kernel == table["kernel"]
+    assert fetch == table["fetch_kib"] and write == table["write_kib"]
