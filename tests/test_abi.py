@@ -152,6 +152,14 @@ def test_mesh2d_validation_host_only():
     with pytest.raises(cmcg.CmcgError) as e:
         cmcg.cmcg_mesh2d_create(flat, tri, tags)
     assert e.value.code == cmcg.CMCG_ERR_MESH
+    with pytest.raises(cmcg.CmcgError) as e:         # no triangles
+        cmcg.cmcg_mesh2d_create(xy, tri[:0], tags[:0])
+    assert e.value.code == cmcg.CMCG_ERR_ARG
+    nan = xy.copy()
+    nan[tri[0, 2], 1] = np.nan                       # a non-finite vertex
+    with pytest.raises(cmcg.CmcgError) as e:
+        cmcg.cmcg_mesh2d_create(nan, tri, tags)
+    assert e.value.code == cmcg.CMCG_ERR_MESH
 
 
 def test_default_stream_does_not_start_torch():
