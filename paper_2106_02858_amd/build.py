@@ -16,9 +16,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcmcg.so")
-# plain-C program that uses the C-ABI without Python (run by a GPU test)
-C_DEMO_SRC = os.path.join(ROOT, "tests", "c_abi", "solve_demo.c")
-C_DEMO = os.path.join(ROOT, "tests", "c_abi", "solve_demo")
+# plain-C programs that use the C-ABI without Python (run by GPU tests): the
+# 3-D solve and the 2-D transverse-magnetic solve
+C_DEMOS = [os.path.join(ROOT, "tests", "c_abi", name) for name in ("solve_demo", "solve_demo2d")]
 
 SOURCES = ["refelem.cpp", "mesh.cpp", "solver.cpp", "batch.cpp", "engine.cpp", "kernels.hip", "kernels2d.hip"]
 ARCH = os.environ.get("CMCG_OFFLOAD_ARCH", "gfx950")
@@ -79,11 +79,13 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
-    if os.path.exists(C_DEMO_SRC):
+    for exe in C_DEMOS:
+        if not os.path.exists(exe + ".c"):
+            continue
         rocm = os.path.dirname(os.path.dirname(os.path.realpath(hipcc())))
         cmd = [shutil.which("gcc") or "gcc", "-std=c11", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__",
-               f"-I{os.path.join(ROOT, 'include')}", f"-I{os.path.join(rocm, 'include')}", C_DEMO_SRC,
-               "-o", C_DEMO, f"-L{HERE}", "-lcmcg", f"-L{os.path.join(rocm, 'lib')}", "-lamdhip64", "-lm",
+               f"-I{os.path.join(ROOT, 'include')}", f"-I{os.path.join(rocm, 'include')}", exe + ".c",
+               "-o", exe, f"-L{HERE}", "-lcmcg", f"-L{os.path.join(rocm, 'lib')}", "-lamdhip64", "-lm",
                "-Wl,-rpath,$ORIGIN/../../paper_2106_02858_amd", f"-Wl,-rpath,{os.path.join(rocm, 'lib')}"]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
