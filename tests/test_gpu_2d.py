@@ -93,6 +93,53 @@ def test_rhs_parity(lib, q, precision):
         assert err < TOL[precision], (t, src, err)
 
 
+def strip_mesh(K):
+    """K triangles (p_t, p_t+1, p_t+2) over the zigzag p_k = (k // 2, k % 2):
+    any triangle count, orientations alternating, every unmatched edge a wall
+    (PEC on even triangles, impedance on odd ones)."""
+    k = np.arange(K + 2)
+    xy = np.stack([k // 2, k % 2], axis=1).astype(np.float64)
+    tri = np.stack([k[:K], k[1:K + 1], k[2:K + 2]], axis=1).astype(np.int64)
+    owners = {}
+    for e in range(K):
+        for f in range(3):
+            owners.setdefault(tuple(sorted(np.delete(tri[e], f))), []).append((e, f))
+    tags = np.zeros((K, 3), dtype=np.int8)
+    for own in owners.values():
+        if len(own) == 1:
+            e, f = own[0]
+            tags[e, f] = P if e % 2 == 0 else I
+    return xy, tri, tags
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("q", [1, 3])
+def test_rhs_every_ragged_wave(lib, q, precision):
+    """Every remainder of K modulo the 21 triangles one 64-lane wave holds (and
+    one past two full waves), on strips with mixed orientation and both wall
+    kinds: right-hand side with current and wall data against the oracle."""
+    for K in list(range(1, 22)) + [41, 42, 43]:
+        xy, tri, tags = strip_mesh(K)
+        rng = np.random.default_rng(100 + K)
+        eps, mu = rng.choice([1.0, 2.0, 4.0], K), rng.choice([1.0, 1.5], K)
+        sg = rng.uniform(0.0, 0.5, K)
+        p0 = dg2d.make_problem(xy, tri, tags, q, eps, mu)
+        Np, Nfp = p0.Np, p0.geo.Nfp
+        j = rng.standard_normal((K, Np)) + 1j * rng.standard_normal((K, Np))
+        gg = np.zeros((K, 3, Nfp), complex)
+        wall = p0.geo.tag == I
+        gg[wall] = rng.standard_normal((wall.sum(), Nfp)) + 1j * rng.standard_normal((wall.sum(), Nfp))
+        op = dg2d.make_problem(xy, tri, tags, q, eps, mu, sg, omega=2.5, j=j, g=gg)
+        s = lib.cmcg_space_create(lib.cmcg_mesh2d_create(xy, tri, tags), q, precision)
+        lp = lib.cmcg_problem_create(s, eps, mu, sg, 2.5, j, gg)
+        U = rng.standard_normal((K, 3, Np))
+        out = dev(np.zeros_like(U))
+        lib.cmcg_debug_rhs(lp, dev(U), out, t=0.4, with_source=True)
+        ref = dg2d.phi(op, 0.4, U, with_source=True)
+        err = np.max(np.abs(host(out) - ref)) / np.max(np.abs(ref))
+        assert err < TOL[precision], (K, err)
+
+
 @pytest.mark.parametrize("walls", [(P,) * 4, (I,) * 4])
 @pytest.mark.parametrize("q", [1, 3])
 def test_rhs_centred_flux_and_walls(lib, q, walls):
