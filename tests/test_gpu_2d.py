@@ -140,6 +140,25 @@ def test_rhs_every_ragged_wave(lib, q, precision):
         assert err < TOL[precision], (K, err)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("walls", [(P,) * 4, (I,) * 4])
+def test_zero_source_gives_zero_field(lib, walls, precision):
+    """No current and no wall data: the periodic solution is zero; CMCG stops
+    before its first iteration and the filtered fields are exact zeros."""
+    xy, tri, tags = inputs.cartesian_triangles(3, 3, side_tags=walls)
+    K = tri.shape[0]
+    s = lib.cmcg_space_create(lib.cmcg_mesh2d_create(xy, tri, tags), 2, precision)
+    p = lib.cmcg_problem_create(s, np.ones(K), np.ones(K), None, 2 * np.pi, None)
+    r = lib.cmcg_solve(p, lib.cmcg_options_default(tol=1e-8))
+    st = lib.cmcg_result_stats(r)
+    assert st["iters"] == 0 and st["status"] == lib.CMCG_OK and st["rel_res"] == 0.0
+    import torch
+    fr = torch.ones((K, 3, 6), dtype=torch.float64, device="cuda")
+    fi = torch.ones_like(fr)
+    lib.cmcg_result_filtered_device(r, fr, fi)
+    assert float(fr.abs().max()) == 0.0 and float(fi.abs().max()) == 0.0
+
+
 @pytest.mark.parametrize("walls", [(P,) * 4, (I,) * 4])
 @pytest.mark.parametrize("q", [1, 3])
 def test_rhs_centred_flux_and_walls(lib, q, walls):
