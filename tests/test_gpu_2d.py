@@ -228,6 +228,22 @@ def test_cmcg_converges_to_the_discrete_periodic_orbit(lib, precision):
     assert rel_norm_c(op, filtered(lib, r, op), F) < (1e-7 if precision == 0 else 1e-4)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solves_are_reproducible_bit_for_bit(lib, precision):
+    """The same problem solved twice from graphs and once eagerly: identical
+    iteration counts, residual histories and filtered fields, bit for bit (no
+    atomics; the inner products reduce in a fixed order)."""
+    op, s, lp = pair2d(lib, n=5, q=3, precision=precision, seed=61, walls=(P, I, P, I))
+    runs = []
+    for use_graph in (1, 1, 0):
+        r = lib.cmcg_solve(lp, lib.cmcg_options_default(tol=1e-6, max_iter=300, use_graph=use_graph))
+        runs.append((lib.cmcg_result_stats(r)["iters"], np.asarray(lib.cmcg_result_history(r)),
+                     filtered(lib, r, op)))
+    for it, hist, F in runs[1:]:
+        assert it == runs[0][0]
+        assert np.array_equal(hist, runs[0][1]) and np.array_equal(F, runs[0][2])
+
+
 def test_fw_fixed_periods(lib):
     op, s, lp = pair2d(lib, n=4, q=1, seed=41, walls=(I,) * 4)
     ref = ofw.solve(op, periods=12)
