@@ -293,3 +293,21 @@ def test_two_wave_blocks_equal_one_wave_blocks(lib, q):
         assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
     finally:
         lib.cmcg_tune_stage(q, 1, old)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solves_are_reproducible_bit_for_bit(lib, precision):
+    """The same problem solved twice from graphs and once eagerly: identical
+    iteration counts, residual histories and filtered fields, bit for bit (no
+    atomics; the inner products reduce in a fixed order)."""
+    op, s, lp = pair(lib, n=2, q=3, precision=precision, seed=71)
+    runs = []
+    for use_graph in (1, 1, 0):
+        r = lib.cmcg_solve(lp, lib.cmcg_options_default(tol=1e-6, max_iter=300, use_graph=use_graph))
+        fr, fi = dev(np.zeros((op.K, 6, op.Np))), dev(np.zeros((op.K, 6, op.Np)))
+        lib.cmcg_result_filtered_device(r, fr, fi)
+        runs.append((lib.cmcg_result_stats(r)["iters"], np.asarray(lib.cmcg_result_history(r)),
+                     host(fr), host(fi)))
+    for it, hist, fr, fi in runs[1:]:
+        assert it == runs[0][0] and np.array_equal(hist, runs[0][1])
+        assert np.array_equal(fr, runs[0][2]) and np.array_equal(fi, runs[0][3])
