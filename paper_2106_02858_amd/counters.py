@@ -2,10 +2,12 @@
 
     python -m paper_2106_02858_amd.counters [--n 20 --q 3 --periods 2]
     python -m paper_2106_02858_amd.counters --trap2d      # the 2-D disk trap instead
+    python -m paper_2106_02858_amd.counters --fp64        # FP64 fields (either problem)
 
 Runs whole homogeneous periods (4 M stage launches each) of the large
 single-solve problem (48000 tets, P3, FP32 fields) -- or, with --trap2d, of
-the 2-D dipole-in-trap problem (22500 triangles, P3, FP32) -- then a plain elementwise
+the 2-D dipole-in-trap problem (22500 triangles, P3, FP32); --fp64 takes FP64
+fields instead -- then a plain elementwise
 copy of known size (read 4 B, write 4 B per float; 1 GiB each way) that
 calibrates what FETCH_SIZE / WRITE_SIZE report per byte moved.  Under
 `rocprofv3 --pmc FETCH_SIZE` (then WRITE_SIZE) the per-dispatch averages of
@@ -25,6 +27,7 @@ def main() -> int:
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--trap2d", action="store_true")
+    ap.add_argument("--fp64", action="store_true")
     a = ap.parse_args()
     import torch
 
@@ -34,7 +37,7 @@ def main() -> int:
     if a.trap2d:
         w = inputs.trap2d(75, 3, "disk")
         mesh = cmcg.cmcg_mesh2d_create(w.xy, w.tri, w.tags)
-        s = cmcg.cmcg_space_create(mesh, 3, cmcg.CMCG_FP32)
+        s = cmcg.cmcg_space_create(mesh, 3, cmcg.CMCG_FP64 if a.fp64 else cmcg.CMCG_FP32)
         p = cmcg.cmcg_problem_create(s, w.eps, w.mu, None, w.omega,
                                      inputs.current_2d(w, cmcg.cmcg_space_nodes(s)))
         info = cmcg.cmcg_space_info(s)
@@ -50,7 +53,7 @@ def main() -> int:
         return copy_calibration(a, dev)
     w = inputs.large_single(n=a.n, q=a.q)
     mesh = cmcg.cmcg_mesh_create(w.xyz, w.tet, w.tags)
-    s = cmcg.cmcg_space_create(mesh, w.q, cmcg.CMCG_FP32)
+    s = cmcg.cmcg_space_create(mesh, w.q, cmcg.CMCG_FP64 if a.fp64 else cmcg.CMCG_FP32)
     nodes = cmcg.cmcg_space_nodes(s)
     j = torch.tensor(inputs.gaussian_current(nodes, w.centre, w.width, w.pol), dtype=torch.float64, device=dev)
     p = cmcg.cmcg_problem_create_device(s, w.eps, w.mu, w.sigma, w.omega, j)
