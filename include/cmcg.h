@@ -12,7 +12,7 @@
  *   initial state U0 with P_psi U0 = U0 over one period T = 2 pi / omega by
  *   conjugate gradients on J(U0) = 1/2 ||(I - P) U0 - G||^2_{eps,mu}, where
  *   every gradient costs one forward and one backward (adjoint, P* = S P S)
- *   period of an explicit upwind DG / Runge-Kutta scheme (Section 5.2-5.3),
+ *   period of an explicit upwind DG / Runge-Kutta scheme (Sections 5.2.2 and 5.3),
  *   and returns the filtered field F_psi U0 = (2/T) int_0^T U(t) e^{-i w t}
  *   dt, computed on the fly during a last forward period (Section 5.4).
  *
@@ -67,7 +67,9 @@ enum {
     CMCG_ERR_DEVICE = -4,    /* a HIP runtime call failed                      */
     CMCG_ERR_UNSTABLE = -5,  /* non-finite values appeared (step too large)    */
     CMCG_ERR_BREAKDOWN = -6, /* CG breakdown: (D, A) <= 0 or not finite        */
-    CMCG_ERR_STATE = -7      /* call not valid in the object's current state   */
+    CMCG_ERR_STATE = -7,     /* call not valid in the object's current state   */
+    CMCG_ERR_TOO_LARGE = -8  /* serving: the request's footprint exceeds the
+                                engine's whole budget (never admissible)        */
 };
 
 enum { CMCG_FP64 = 0, CMCG_FP32 = 1 };                   /* field precision  */
@@ -148,7 +150,7 @@ const char* cmcg_last_error(void);
 const char* cmcg_version(void);
 
 /* ---------------------------------------------------------------- mesh -- */
-/* Conforming tetrahedral mesh (Section 5.2: conforming simplicial mesh; each
+/* Conforming tetrahedral mesh (Section 5.2.2: conforming simplicial mesh; each
  * boundary face lies entirely on the PEC or the impedance part).
  *   xyz[nv][3]   vertex coordinates
  *   tet[K][4]    vertex indices (0-based)
@@ -177,7 +179,7 @@ int cmcg_mesh_create(int64_t nv, const double* xyz, int64_t K, const int64_t* te
                      const int8_t* face_tag, cmcg_mesh** out);
 /* Conforming triangle mesh of the 2-D transverse-magnetic setting (Section
  * 5.1: fields independent of the third coordinate, e = E_3 and h = (H_1,
- * H_2); Section 5.2: its DG scheme on triangles, edge sets interior / PEC /
+ * H_2); Section 5.2.2: its DG scheme on triangles, edge sets interior / PEC /
  * impedance).
  *   xy[nv][2]     vertex coordinates
  *   tri[K][3]     vertex indices (0-based), either orientation
@@ -207,7 +209,7 @@ int cmcg_mesh_info(const cmcg_mesh* m, int64_t* K, int64_t* n_boundary_faces,
                    double* min_rho);
 
 /* --------------------------------------------------------------- space -- */
-/* Broken nodal space P_q(T_h)^6 on the mesh (Section 5.2), field precision
+/* Broken nodal space P_q(T_h)^6 on the mesh (Section 5.2.2), field precision
  * CMCG_FP64 or CMCG_FP32 (time stepping in that precision; CG vectors,
  * inner products, alpha/beta and the filter accumulator always FP64).
  * Uploads geometry and connectivity to the current device.  The mesh may be
@@ -232,11 +234,16 @@ int cmcg_problem_create(const cmcg_space* s, const double* eps, const double* mu
                         const double* sigma, double omega, const double* j_re,
                         const double* j_im, const double* g_re, const double* g_im,
                         cmcg_problem** out);
-/* Same, with j_re / j_im resident in device memory (ordered on `stream`). */
+/* Same, with j_re / j_im ([K][Np][3]) and g_re / g_im ([K][4][Nfp][3];
+ * 2-D spaces: j [K][Np], g [K][3][Nfp]) resident in device memory; each may
+ * be NULL (= 0).  Read in order on `stream`, which is synchronised before
+ * return; the caller may free them afterwards.  eps, mu, sigma are host
+ * arrays.  Errors as cmcg_problem_create, CMCG_ERR_DEVICE when a copy
+ * fails. */
 int cmcg_problem_create_device(const cmcg_space* s, const double* eps, const double* mu,
                                const double* sigma, double omega, const double* j_re_dev,
-                               const double* j_im_dev, hipStream_t stream,
-                               cmcg_problem** out);
+                               const double* j_im_dev, const double* g_re_dev,
+                               const double* g_im_dev, hipStream_t stream, cmcg_problem** out);
 /* Several frequencies in one solve (the paper's concluding remarks): a
  * current made of nh (1..8) harmonics of a base angular frequency omega0,
  * J(t) = sum_h Re(j_h e^{i k[h] omega0 t}) with distinct integers k[h] >= 1,
@@ -324,11 +331,19 @@ void cmcg_result_destroy(cmcg_result* r);
  * `stream`, synchronous on return.
  *
  * cmcg_debug_rhs: out = Phi(t, U) = B U (+ Re(JJ e^{i omega t}) when
- *   with_source), the semi-discrete right-hand side of Section 5.2.
+ *   with_source), the semi-discrete right-hand side of Section 5.2.2.
  * cmcg_debug_period: one period of M steps from U0 (Section 5.3): direction
  *   +1 = forward P (P_psi when with_source), -1 = adjoint P* = S P S (never
  *   with source).  f_re / f_im (may be NULL) receive the filtered field of
  *   a forward period (trapezoid for RK2, Hermite for RK4).
+ * cmcg_debug_step: one time step (Section 5.3: RK2 for q = 1, classical RK4
+ *   otherwise, or o->scheme) from t_m = m dt to t_{m+1}, dt = T / M with M
+ *   the step count `o` selects (0 <= m < M, else CMCG_ERR_ARG): direction +1
+ *   applies the forward step (with the source Re(JJ e^{i omega t}) at the
+ *   stage times when with_source), -1 the adjoint step S R S (never with
+ *   source).  This is exactly the launch sequence that a period repeats M
+ *   times: FP32 spaces round the input to FP32 (+ bfloat16 low part) and
+ *   return the compensated state.
  * cmcg_debug_dot: (U, V)_{eps,mu} = V^T M U (Section 2.2), into *out (host),
  *   with a fixed reduction order (bitwise reproducible). */
 int cmcg_debug_rhs(cmcg_problem* p, const cmcg_options* o, double t, int with_source,
@@ -336,6 +351,8 @@ int cmcg_debug_rhs(cmcg_problem* p, const cmcg_options* o, double t, int with_so
 int cmcg_debug_period(cmcg_problem* p, const cmcg_options* o, int direction,
                       int with_source, const double* u0_dev, double* ut_dev,
                       double* f_re_dev, double* f_im_dev, hipStream_t stream);
+int cmcg_debug_step(cmcg_problem* p, const cmcg_options* o, int m, int direction, int with_source,
+                    const double* u_dev, double* out_dev, hipStream_t stream);
 int cmcg_debug_dot(cmcg_problem* p, const double* u_dev, const double* v_dev, double* out,
                    hipStream_t stream);
 
@@ -350,9 +367,12 @@ int cmcg_debug_dot(cmcg_problem* p, const double* u_dev, const double* v_dev, do
  * cmcg_engine_create: budget = device bytes the engine may hold for admitted
  *   solves; max_slots = concurrent solves (1..1024).
  * cmcg_engine_admit: starts a solve in a free slot; CMCG_ERR_NOMEM when no
- *   slot is free or the footprint does not fit the remaining budget (the
- *   caller keeps the request queued), CMCG_ERR_STATE when p is already held
- *   by a slot.  p must stay alive until the slot is collected or cancelled.
+ *   slot is free, the footprint does not fit the remaining budget or a device
+ *   allocation for the solve failed (the caller keeps the request queued; if
+ *   the engine holds no other solve, waiting will not help),
+ *   CMCG_ERR_TOO_LARGE when the footprint exceeds the whole budget (the
+ *   request can never be admitted), CMCG_ERR_STATE when p is already held by
+ *   a slot.  p must stay alive until the slot is collected or cancelled.
  * cmcg_engine_step: advances every running slot whose chunk of work (the
  *   initial periods, one half of a CG iteration, or the filter period) has
  *   completed on its stream, enqueueing its next chunk; waits (polling) until

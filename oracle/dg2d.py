@@ -1,5 +1,5 @@
 """Upwind nodal DG semi-discretisation of the 2-D transverse-magnetic system
-(Section 5.1, two-dimensional setting; Section 5.2, DG discretisation).
+(Section 5.2.1, two-dimensional setting; Section 5.2.2, DG discretisation).
 
 Fields: e (the out-of-plane electric component) and h = (h1, h2).  With
 scurl h = d1 h2 - d2 h1 and vcurl e = (d2 e, -d1 e) the system is
@@ -150,7 +150,7 @@ def source(p: Problem2D, t: float) -> np.ndarray:
 
 
 def phi(p: Problem2D, t: float, U: np.ndarray, with_source: bool = True) -> np.ndarray:
-    """Phi(t, U) of the semi-discrete ODE system (Section 5.2)."""
+    """Phi(t, U) of the semi-discrete ODE system (Section 5.2.2)."""
     r = apply_B(p, U)
     if with_source:
         r = r + source(p, t)

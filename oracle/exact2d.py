@@ -1,7 +1,7 @@
 """Exact solutions of the 2-D experiments and the relative energy-norm error
 of Section 6 (error = ||U - U_h||_{eps,mu} / ||U||_{eps,mu}).
 
-Time-harmonic TM system (Section 5.1): i omega eps e + sigma e + scurl h = j,
+Time-harmonic TM system (Section 5.2.1): i omega eps e + sigma e + scurl h = j,
 i omega mu h - vcurl e = 0, so h = vcurl e / (i omega mu) = (d2 e, -d1 e) /
 (i omega mu), and with eps = mu = 1, sigma = 0: -Lap e - omega^2 e = i omega j.
 

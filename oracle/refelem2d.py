@@ -1,5 +1,5 @@
-"""Reference P_q triangle for the 2-D nodal DG space (Section 5.2, DG
-discretisation on triangles; the transverse-magnetic setting of Section 5.1).
+"""Reference P_q triangle for the 2-D nodal DG space (Section 5.2.2, DG
+discretisation on triangles; the transverse-magnetic setting of Section 5.2.1).
 
 Built like the tetrahedron in ``refelem``, in exact rational arithmetic:
 

@@ -38,6 +38,7 @@ CMCG_ERR_DEVICE = -4
 CMCG_ERR_UNSTABLE = -5
 CMCG_ERR_BREAKDOWN = -6
 CMCG_ERR_STATE = -7
+CMCG_ERR_TOO_LARGE = -8
 CMCG_FP64, CMCG_FP32 = 0, 1
 CMCG_TAG_INTERIOR, CMCG_TAG_PEC, CMCG_TAG_IMPEDANCE = 0, 1, 2
 CMCG_SCHEME_AUTO, CMCG_SCHEME_RK2, CMCG_SCHEME_RK4 = 0, 2, 4
@@ -51,7 +52,7 @@ EXPORTED = [
     "cmcg_problem_create_harmonics", "cmcg_result_harmonics", "cmcg_result_filtered_harmonic_device",
     "cmcg_solve", "cmcg_fw_solve", "cmcg_solve_batch", "cmcg_result_fields", "cmcg_result_filtered_device", "cmcg_result_initial_device",
     "cmcg_result_stats", "cmcg_result_history", "cmcg_result_destroy",
-    "cmcg_debug_rhs", "cmcg_debug_period", "cmcg_debug_dot", "cmcg_tune_stage", "cmcg_tune_get_stage",
+    "cmcg_debug_rhs", "cmcg_debug_period", "cmcg_debug_step", "cmcg_debug_dot", "cmcg_tune_stage", "cmcg_tune_get_stage",
     "cmcg_autotune_stage", "cmcg_mesh_locality_order",
     "cmcg_problem_footprint", "cmcg_engine_create", "cmcg_engine_destroy", "cmcg_engine_admit",
     "cmcg_engine_step", "cmcg_engine_poll", "cmcg_engine_collect", "cmcg_engine_cancel", "cmcg_engine_info",
@@ -99,7 +100,8 @@ _sig = {
                                   C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "cmcg_space_nodes": (C.c_int, [P, P]),
     "cmcg_problem_create": (C.c_int, [P, P, P, P, C.c_double, P, P, P, P, C.POINTER(P)]),
-    "cmcg_problem_create_device": (C.c_int, [P, P, P, P, C.c_double, P, P, P, C.POINTER(P)]),
+    "cmcg_problem_create_device": (C.c_int, [P, P, P, P, C.c_double, P, P, P, P, P, C.POINTER(P)]),
+    "cmcg_debug_step": (C.c_int, [P, C.POINTER(cmcg_options), C.c_int, C.c_int, C.c_int, P, P, P]),
     "cmcg_problem_destroy": (None, [P]),
     "cmcg_problem_steps": (C.c_int, [P, C.POINTER(cmcg_options), C.POINTER(C.c_int), D]),
     "cmcg_solve": (C.c_int, [P, C.POINTER(cmcg_options), P, P, C.POINTER(P)]),
@@ -307,11 +309,13 @@ def cmcg_problem_create(s: Space, eps, mu, sigma=None, omega=2 * np.pi, j=None, 
     return Problem(h, keep=(s,))
 
 
-def cmcg_problem_create_device(s: Space, eps, mu, sigma, omega, j_re_dev, j_im_dev=None, stream=None) -> Problem:
+def cmcg_problem_create_device(s: Space, eps, mu, sigma, omega, j_re_dev, j_im_dev=None, stream=None,
+                               g_re_dev=None, g_im_dev=None) -> Problem:
     eps, mu, sigma = _f64(eps), _f64(mu), _f64(sigma)
     h = P()
     _check(_lib.cmcg_problem_create_device(s.h, _ptr(eps), _ptr(mu), _ptr(sigma), float(omega), _ptr(j_re_dev),
-                                           _ptr(j_im_dev), _stream(stream), C.byref(h)))
+                                           _ptr(j_im_dev), _ptr(g_re_dev), _ptr(g_im_dev), _stream(stream),
+                                           C.byref(h)))
     return Problem(h, keep=(s,))
 
 
@@ -416,6 +420,13 @@ def cmcg_debug_period(p: Problem, u0_dev, ut_dev, direction: int = 1, with_sourc
                                   _ptr(f_re_dev), _ptr(f_im_dev), _stream(stream)))
 
 
+def cmcg_debug_step(p: Problem, u_dev, out_dev, m: int = 0, direction: int = 1, with_source: bool = False,
+                    opts: cmcg_options | None = None, stream=None):
+    o = opts or cmcg_options_default()
+    _check(_lib.cmcg_debug_step(p.h, C.byref(o), int(m), int(direction), int(with_source), _ptr(u_dev),
+                                _ptr(out_dev), _stream(stream)))
+
+
 def cmcg_debug_dot(p: Problem, u_dev, v_dev, stream=None) -> float:
     out = C.c_double()
     _check(_lib.cmcg_debug_dot(p.h, _ptr(u_dev), _ptr(v_dev), C.byref(out), _stream(stream)))
@@ -468,7 +479,8 @@ def cmcg_engine_create(hbm_budget: int, max_slots: int) -> Engine:
 
 
 def cmcg_engine_admit(e: Engine, p: Problem, opts: cmcg_options | None = None):
-    """Slot index, or None when the request does not fit now (keep it queued)."""
+    """Slot index, or None when the request does not fit now (keep it queued).
+    Raises CmcgError with code CMCG_ERR_TOO_LARGE when it never can."""
     o = opts or cmcg_options_default()
     slot = C.c_int(-1)
     rc = _lib.cmcg_engine_admit(e.h, p.h, C.byref(o), C.byref(slot))

@@ -222,7 +222,9 @@ void run_batch_period(Batch& bt, bool src, bool filt, bool use_graph, hipStream_
         enqueue_batch_period(bt, src, filt, st);
         return;
     }
-    const int key = (src ? 2 : 0) | (filt ? 1 : 0);
+    // keyed by the stage variant as well: it is read when the launches are enqueued
+    const int variant = bt.sp->dim == 3 ? get_stage_variant(bt.sp->q, bt.sp->precision) : 0;
+    const int key = (variant << 4) | (src ? 2 : 0) | (filt ? 1 : 0);
     auto it = bt.graphs.find(key);
     if (it == bt.graphs.end()) {
         if (!bt.cap) CMCG_HIP(hipStreamCreateWithFlags(&bt.cap, hipStreamNonBlocking));

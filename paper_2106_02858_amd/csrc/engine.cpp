@@ -118,8 +118,13 @@ int cmcg_engine_admit(cmcg_engine* e, cmcg_problem* p, const cmcg_options* o, in
         if (s.state != 0 && s.p == p) fail(CMCG_ERR_STATE, "engine_admit: problem already held by a slot");
         if (s.state == 0 && free_slot < 0) free_slot = i;
     }
-    if (free_slot < 0) fail(CMCG_ERR_NOMEM, "engine_admit: no free slot");
     const size_t need = footprint(p);
+    // a request larger than the whole budget can never be admitted: tell the
+    // caller so, instead of "not now"
+    if (need > e->budget)
+        fail(CMCG_ERR_TOO_LARGE, "engine_admit: footprint " + std::to_string(need) + " B exceeds the budget " +
+                                     std::to_string(e->budget) + " B");
+    if (free_slot < 0) fail(CMCG_ERR_NOMEM, "engine_admit: no free slot");
     if (e->used + need > e->budget) fail(CMCG_ERR_NOMEM, "engine_admit: over the memory budget");
     auto& s = e->slots[free_slot];
     cmcg_options oe = *o;

@@ -47,7 +47,7 @@ const RefElem& ref_elem(int q);
 // j carries my face local vertex perm3[p][j]
 extern const int perm3[6][3];
 
-// Reference P_q triangle of the 2-D transverse-magnetic space (Section 5.1,
+// Reference P_q triangle of the 2-D transverse-magnetic space (Section 5.2.1,
 // two-dimensional setting): nodes (i, j)/q with j slowest, edge f opposite
 // vertex f, edge nodes listed from the edge's lower-numbered vertex.
 inline int np2_of(int q) { return (q + 1) * (q + 2) / 2; }

@@ -1,5 +1,5 @@
-// Kernels of the 2-D transverse-magnetic path (Section 5.1, two-dimensional
-// setting; Section 5.2 DG scheme on triangles; Section 5.3 Runge-Kutta
+// Kernels of the 2-D transverse-magnetic path (Section 5.2.1, two-dimensional
+// setting; Section 5.2.2 DG scheme on triangles; Section 5.3 Runge-Kutta
 // stages): fields (e, h1, h2), dof layout [K][3][Np].
 //
 // Stage kernel: one 64-lane workgroup per block of 21 triangles, lane =

@@ -1,4 +1,4 @@
-// Mesh validation, face connectivity and affine geometry (Section 5.2:
+// Mesh validation, face connectivity and affine geometry (Section 5.2.2:
 // conforming simplicial mesh, interior / PEC / impedance face sets, outward
 // normals; the insphere diameter rho_K of the CFL rule of Section 5.3).
 //
@@ -204,7 +204,7 @@ std::shared_ptr<MeshData> build_mesh(int64_t nv, const double* xyz, int64_t K, c
     return m;
 }
 
-// Triangle meshes of the 2-D transverse-magnetic setting (Section 5.1): edges
+// Triangle meshes of the 2-D transverse-magnetic setting (Section 5.2.1): edges
 // matched through their sorted vertex pair; normals are the edge directions
 // turned a quarter turn away from the opposite vertex; rho_K = 4 |K| /
 // perimeter, the diameter of the inscribed circle.

@@ -1,6 +1,6 @@
-// Reference P_q tetrahedron for the nodal DG space (Section 5.2, nodal basis
+// Reference P_q tetrahedron for the nodal DG space (Section 5.2.2, nodal basis
 // of P_q(T_h) lifted from triangles to tetrahedra), and the P_q triangle of
-// the 2-D transverse-magnetic space (Section 5.1).
+// the 2-D transverse-magnetic space (Section 5.2.1).
 //
 // Construction (long double): nodal basis from a Cartesian monomial
 // Vandermonde at the equispaced nodes; differentiation matrices from the

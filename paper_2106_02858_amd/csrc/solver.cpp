@@ -420,9 +420,11 @@ static StageArgs base_args(cmcg_problem* p) {
     return a;
 }
 
-// One period of M steps in place on p->U (field precision).  With `filt`,
-// F = (2/T) int U e^{-i w t} is accumulated into Fre / Fim (zeroed here).
-static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool filt, hipStream_t st) {
+// Steps m0 .. m1-1 of a period in place on p->U (field precision).  With
+// `filt` (whole periods only), F = (2/T) int U e^{-i w t} is accumulated into
+// Fre / Fim (zeroed here).
+static void enqueue_steps(cmcg_problem* p, const StepCfg& c, bool src, bool filt, int m0, int m1,
+                          hipStream_t st) {
     const SpaceData& s = *p->sp;
     const int prec = s.precision;
     const int M = c.M;
@@ -458,7 +460,7 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
         (h == 0 ? a.fb_re : a.hfb_re[h]) = wb.real();
         (h == 0 ? a.fb_im : a.hfb_im[h]) = wb.imag();
     };
-    for (int m = 0; m < M; ++m) {
+    for (int m = m0; m < m1; ++m) {
         a.filter = 0;
         if (c.scheme == 2) {
             // stage 1: k1 = Phi(t_m, U); Y1 = U + dt/2 k1
@@ -527,7 +529,7 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
             stage_dim(s, a, st);
         }
     }
-    if (filt) {
+    if (filt && m1 == M) {
         if (c.scheme == 2) {
             // last level t_M = T: e^{-i k_h w T} = 1
             for (int h = 0; h < H; ++h)
@@ -549,12 +551,21 @@ static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool fil
     }
 }
 
+// One period of M steps in place on p->U.
+static void enqueue_period(cmcg_problem* p, const StepCfg& c, bool src, bool filt, hipStream_t st) {
+    enqueue_steps(p, c, src, filt, 0, c.M, st);
+}
+
 static void run_period(cmcg_problem* p, const StepCfg& c, bool src, bool filt, bool use_graph, hipStream_t st) {
     if (!use_graph) {
         enqueue_period(p, c, src, filt, st);
         return;
     }
-    const int64_t key = ((int64_t)c.M << 8) | (c.scheme << 4) | (src ? 2 : 0) | (filt ? 1 : 0);
+    // the stage variant is read when the launches are enqueued, so a graph
+    // captured under one variant must not be replayed after another is chosen
+    const int variant = p->sp->dim == 3 ? get_stage_variant(p->sp->q, p->sp->precision) : 0;
+    const int64_t key =
+        ((int64_t)c.M << 12) | (variant << 8) | (c.scheme << 4) | (src ? 2 : 0) | (filt ? 1 : 0);
     auto it = p->graphs.find(key);
     if (it == p->graphs.end()) {
         if (!p->cap_stream) CMCG_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
@@ -1163,25 +1174,28 @@ int cmcg_problem_create_harmonics(const cmcg_space* s, const double* eps, const 
 }
 
 int cmcg_problem_create_device(const cmcg_space* s, const double* eps, const double* mu, const double* sigma,
-                               double omega, const double* j_re_dev, const double* j_im_dev, hipStream_t stream,
-                               cmcg_problem** out) {
+                               double omega, const double* j_re_dev, const double* j_im_dev, const double* g_re_dev,
+                               const double* g_im_dev, hipStream_t stream, cmcg_problem** out) {
     CMCG_GUARD_BEGIN
     if (!out) fail(CMCG_ERR_ARG, "problem: NULL output");
     *out = nullptr;
     if (!s || !s->d) fail(CMCG_ERR_ARG, "problem: NULL space");
-    const size_t nb = (size_t)s->d->K * s->d->Np * (s->d->dim == 2 ? 1 : 3) * 8;
-    std::vector<double> jr, ji;
-    if (j_re_dev) {
-        jr.resize(nb / 8);
-        CMCG_HIP(hipMemcpyAsync(jr.data(), j_re_dev, nb, hipMemcpyDeviceToHost, stream));
-    }
-    if (j_im_dev) {
-        ji.resize(nb / 8);
-        CMCG_HIP(hipMemcpyAsync(ji.data(), j_im_dev, nb, hipMemcpyDeviceToHost, stream));
-    }
+    const SpaceData& sd = *s->d;
+    const int comps = sd.dim == 2 ? 1 : 3;
+    const size_t nj = (size_t)sd.K * sd.Np * comps, ng = (size_t)sd.K * (sd.dim + 1) * sd.Nfp * comps;
+    // the device arrays are staged through host memory: the source and the
+    // lifted boundary data are assembled on the host as for host inputs
+    std::vector<double> bufs[4];
+    const double* dev[4] = {j_re_dev, j_im_dev, g_re_dev, g_im_dev};
+    const size_t len[4] = {nj, nj, ng, ng};
+    for (int i = 0; i < 4; ++i)
+        if (dev[i]) {
+            bufs[i].resize(len[i]);
+            CMCG_HIP(hipMemcpyAsync(bufs[i].data(), dev[i], len[i] * 8, hipMemcpyDeviceToHost, stream));
+        }
     CMCG_HIP(hipStreamSynchronize(stream));
-    *out = make_problem(s, eps, mu, sigma, omega, j_re_dev ? jr.data() : nullptr, j_im_dev ? ji.data() : nullptr,
-                        nullptr, nullptr);
+    auto host = [&](int i) { return dev[i] ? (const double*)bufs[i].data() : nullptr; };
+    *out = make_problem(s, eps, mu, sigma, omega, host(0), host(1), host(2), host(3));
     return CMCG_OK;
     CMCG_GUARD_END
 }
@@ -1395,6 +1409,28 @@ int cmcg_debug_period(cmcg_problem* p, const cmcg_options* o, int direction, int
     const size_t b = p->sp->ndof * 8;
     if (f_re) CMCG_HIP(hipMemcpyAsync(f_re, p->Fre.p, b, hipMemcpyDeviceToDevice, stream));
     if (f_im) CMCG_HIP(hipMemcpyAsync(f_im, p->Fim.p, b, hipMemcpyDeviceToDevice, stream));
+    CMCG_HIP(hipStreamSynchronize(stream));
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_debug_step(cmcg_problem* p, const cmcg_options* o, int m, int direction, int with_source, const double* u,
+                    double* out, hipStream_t stream) {
+    CMCG_GUARD_BEGIN
+    if (!p || !u || !out) fail(CMCG_ERR_ARG, "debug_step: NULL argument");
+    if (direction != 1 && direction != -1) fail(CMCG_ERR_ARG, "debug_step: direction must be +1 or -1");
+    if (direction < 0 && with_source) fail(CMCG_ERR_ARG, "debug_step: the adjoint step has no source");
+    cmcg_options def;
+    cmcg_options_default(&def);
+    if (!o) o = &def;
+    StepCfg c = step_config(p, o);
+    if (m < 0 || m >= c.M) fail(CMCG_ERR_ARG, "debug_step: step index outside 0 .. M-1");
+    prepare(p, c);
+    const SpaceData& s = *p->sp;
+    const int flip = direction < 0 ? 1 : 0;
+    to_field_dim(s, u, p->U.p, p->Ulo.p, s.ndof, flip, stream);
+    enqueue_steps(p, c, with_source != 0 && direction > 0, false, m, m + 1, stream);
+    from_field_dim(s, p->U.p, p->Ulo.p, out, nullptr, s.ndof, flip, stream);
     CMCG_HIP(hipStreamSynchronize(stream));
     return CMCG_OK;
     CMCG_GUARD_END

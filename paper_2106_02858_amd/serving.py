@@ -3,7 +3,8 @@
 Requests arrive on a wall clock (arrival times in seconds, e.g. a Poisson
 stream).  Arrived requests wait in a FIFO queue; the head is admitted into an
 engine slot as soon as a slot is free and its device footprint fits the
-budget; every engine step advances all running solves (their periods overlap
+budget (a request that cannot fit even an empty engine is rejected and
+listed in the returned "rejected"); every engine step advances all running solves (their periods overlap
 on the device); finished solves are collected and their latency (result
 ready - arrival) recorded.  All numerical work runs in the HIP library; this
 loop only schedules.
@@ -56,6 +57,7 @@ def serve(requests, budget_bytes: int, max_slots: int, precision=cmcg.CMCG_FP32,
     queue = collections.deque()
     slots = {}  # slot -> (request, problem, admit time)
     records = []
+    rejected = []
     results = {}
     t0 = time.perf_counter()
 
@@ -67,14 +69,31 @@ def serve(requests, budget_bytes: int, max_slots: int, precision=cmcg.CMCG_FP32,
         t = now()
         while pending and pending[0]["arrival"] <= t:
             queue.append(pending.popleft())
-        # FIFO admission while the head fits
+        # FIFO admission while the head fits.  A head that can never fit (its
+        # footprint exceeds the whole budget, or it does not fit an engine that
+        # holds nothing else) is rejected and recorded, so the loop neither
+        # spins on it nor holds back the requests behind it.
         while queue:
             req = queue[0]
             prob = req.get("_problem") or build_problem(cache, req)
             req["_problem"] = prob
-            slot = cmcg.cmcg_engine_admit(engine, prob, opts)
+            try:
+                slot = cmcg.cmcg_engine_admit(engine, prob, opts)
+            except cmcg.CmcgError as err:
+                if err.code != cmcg.CMCG_ERR_TOO_LARGE:
+                    raise
+                slot = None
+            else:
+                if slot is None and slots:
+                    break  # fits later, once a running solve has finished
             if slot is None:
-                break
+                queue.popleft()
+                req.pop("_problem", None)
+                rejected.append(dict(id=req["id"], n=req["n"], q=req["q"], arrival=req["arrival"],
+                                     footprint=cmcg.cmcg_problem_footprint(prob)))
+                if log:
+                    log(f"rejected {req['id']} n={req['n']} q={req['q']}: does not fit the budget")
+                continue
             queue.popleft()
             slots[slot] = (req, prob, now())
         if not slots:
@@ -109,7 +128,7 @@ def serve(requests, budget_bytes: int, max_slots: int, precision=cmcg.CMCG_FP32,
                p50=float(np.percentile(lat, 50)) if len(lat) else None,
                p99=float(np.percentile(lat, 99)) if len(lat) else None,
                offered_rate=(len(requests) / max(r["arrival"] for r in requests)) if requests else 0.0,
-               records=records)
+               records=records, rejected=rejected)
     if keep_results:
         out["results"] = results
     return out

@@ -112,7 +112,7 @@ int main(int argc, char** argv) {
     hip_check(hipMemcpy(jd, j, sizeof(double) * ne, hipMemcpyHostToDevice), "copy j");
     cmcg_problem* pd = NULL;
     cmcg_result* rd = NULL;
-    check(cmcg_problem_create_device(sp, eps, mu, NULL, OMEGA, jd, NULL, stream, &pd), "problem_device");
+    check(cmcg_problem_create_device(sp, eps, mu, NULL, OMEGA, jd, NULL, NULL, NULL, stream, &pd), "problem_device");
     check(cmcg_solve(pd, &o, NULL, stream, &rd), "solve_device");
     check(cmcg_result_filtered_device(rd, fre, fim, stream), "filtered_device");
     hip_check(hipStreamSynchronize(stream), "sync");

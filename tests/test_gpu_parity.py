@@ -112,6 +112,64 @@ def test_rhs_centred_flux(lib, q, precision):
     assert np.max(np.abs(host(out) - ref)) / np.max(np.abs(ref)) < TOL[precision]
 
 
+@pytest.mark.parametrize("direction", [1, -1])
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_step_parity(lib, q, precision, direction):
+    """One Runge-Kutta step (Section 5.3: RK2 for P1, RK4 otherwise) through
+    cmcg_debug_step against the oracle's rk2_step / rk4_step, element by
+    element: forward with the source at the stage times of step m, and the
+    adjoint step S R S, on a mesh with PEC and impedance walls, boundary
+    data, conductivity and a ragged last element block."""
+    print(f"step q={q} prec={precision} dir={direction}", flush=True)
+    op, s, lp = pair(lib, n=2, q=q, precision=precision, seed=20 + q, g=True)
+    opts = lib.cmcg_options_default()
+    M, dt = lib.cmcg_problem_steps(lp, opts)
+    assert M == timestep.n_steps(op)
+    m = M // 3
+    U = np.random.default_rng(30 + q).standard_normal((op.K, 6, op.Np))
+    out = dev(np.zeros_like(U))
+    lib.cmcg_debug_step(lp, dev(U), out, m=m, direction=direction, with_source=direction > 0, opts=opts)
+    step = timestep.rk2_step if q == 1 else timestep.rk4_step
+    if direction > 0:
+        ref = step(op, m * dt, U, dt, True)[0]
+    else:
+        ref = dg.flip_H(step(op, m * dt, dg.flip_H(U), dt, False)[0])
+    err = np.max(np.abs(host(out) - ref)) / np.max(np.abs(ref))
+    assert err < TOL[precision], err
+    assert rel_norm(op, host(out), ref) < TOL[precision]
+
+
+def test_step_arguments(lib):
+    op, s, lp = pair(lib, n=1, q=1)
+    U = dev(np.zeros((op.K, 6, op.Np)))
+    M, _ = lib.cmcg_problem_steps(lp)
+    for kw in (dict(m=-1), dict(m=M), dict(direction=0), dict(direction=-1, with_source=True)):
+        with pytest.raises(lib.CmcgError) as err:
+            lib.cmcg_debug_step(lp, U, U, **kw)
+        assert err.value.code == lib.CMCG_ERR_ARG
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_device_problem_with_boundary_data_equals_host_problem(lib, precision):
+    """cmcg_problem_create_device with j and g in device memory builds the
+    same problem as the host-pointer form: equal right-hand sides bit for bit
+    (and both equal the oracle's, boundary-data term included)."""
+    import torch
+    op, s, lp = pair(lib, n=2, q=2, precision=precision, seed=9, g=True)
+    jd = [dev(np.real(op.j)), dev(np.imag(op.j))]
+    gd = [dev(np.real(op.g)), dev(np.imag(op.g))]
+    ld = lib.cmcg_problem_create_device(s, op.eps, op.mu, op.sigma, op.omega, jd[0], jd[1],
+                                        g_re_dev=gd[0], g_im_dev=gd[1])
+    U = dev(np.random.default_rng(3).standard_normal((op.K, 6, op.Np)))
+    a, b = torch.empty_like(U), torch.empty_like(U)
+    lib.cmcg_debug_rhs(lp, U, a, t=0.21, with_source=True)
+    lib.cmcg_debug_rhs(ld, U, b, t=0.21, with_source=True)
+    assert torch.equal(a, b)
+    ref = dg.phi(op, 0.21, host(U), with_source=True)
+    assert np.max(np.abs(host(b) - ref)) / np.max(np.abs(ref)) < TOL[precision]
+
+
 @pytest.mark.parametrize("variant", VARIANTS, indirect=True, ids=lambda t: f"q{t[0]}-p{t[1]}-v{t[2]}")
 def test_period_parity(lib, variant):
     q, precision, v = variant
@@ -291,6 +349,36 @@ def test_two_wave_blocks_equal_one_wave_blocks(lib, q):
             torch.cuda.synchronize()
             outs.append((r.cpu(), UT.cpu()))
         assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    finally:
+        lib.cmcg_tune_stage(q, 1, old)
+
+
+def test_graphed_period_follows_a_stage_variant_change(lib):
+    """A period replayed from a captured graph runs the stage variant chosen
+    when it is replayed: graphs are kept per variant, so after a change of
+    variant the graphed period equals the eager one of the new variant bit for
+    bit (and differs from the old variant's, whose arithmetic differs)."""
+    import torch
+    q = 3
+    old = lib.cmcg_tune_get_stage(q, 1)
+    try:
+        xyz, tet, tags = inputs.cube_mesh(2)
+        K = tet.shape[0]
+        m = lib.cmcg_mesh_create(xyz, tet, tags)
+        s = lib.cmcg_space_create(m, q, 1)
+        Np = lib.cmcg_space_info(s)["Np"]
+        j = inputs.gaussian_current(lib.cmcg_space_nodes(s), (0.5, 0.4, 0.5), 0.3, 1)
+        p = lib.cmcg_problem_create(s, np.ones(K), np.ones(K), None, 2 * np.pi, j)
+        U = dev(np.random.default_rng(5).standard_normal((K, 6, Np)))
+        out = {}
+        for v, graph in ((0, 1), (4, 1), (4, 0)):
+            lib.cmcg_tune_stage(q, 1, v)
+            UT = torch.empty_like(U)
+            lib.cmcg_debug_period(p, U, UT, 1, True, opts=lib.cmcg_options_default(steps=10, use_graph=graph))
+            torch.cuda.synchronize()
+            out[(v, graph)] = UT.cpu()
+        assert torch.equal(out[(4, 1)], out[(4, 0)])
+        assert not torch.equal(out[(4, 1)], out[(0, 1)])
     finally:
         lib.cmcg_tune_stage(q, 1, old)
 

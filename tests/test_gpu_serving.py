@@ -1,13 +1,27 @@
 """Serving engine: requests of different meshes, orders and frequencies are
 admitted by memory, overlap on the device, and each served result equals
 the same request solved alone (bit for bit: a slot runs the launch sequence
-of cmcg_solve)."""
+of cmcg_solve) and the FP64 oracle's CMCG (Algorithms 1-3 and the filter of
+Section 5.4) run for the same number of iterations."""
 import numpy as np
 import pytest
 
+from oracle import dg
 from paper_2106_02858_amd import inputs
 
 pytestmark = pytest.mark.gpu
+
+
+def oracle_solve(req, iters):
+    """The oracle's CMCG on a served request's problem (same seeded recipe)."""
+    from oracle import cmcg as ocmcg
+    w = inputs.serving_request_workload(req)
+    p0 = dg.make_problem(w.xyz, w.tet, w.tags, w.q, w.eps, w.mu, omega=w.omega)
+    j = inputs.gaussian_current(p0.geo.x, w.centre, w.width, w.pol)
+    p = dg.make_problem(w.xyz, w.tet, w.tags, w.q, w.eps, w.mu, omega=w.omega, j=j)
+    r = ocmcg.solve(p, fixed_iters=iters)
+    r.p = p
+    return r
 
 
 def filtered(lib, r, K, Np):
@@ -37,6 +51,10 @@ def test_served_results_equal_solo_solves(lib, precision):
         b = filtered(lib, alone, info["K"], info["Np"])
         assert np.array_equal(a, b), rec
         assert lib.cmcg_result_stats(alone)["iters"] == rec["iters"]
+        # the served result against the oracle at the served iteration count
+        ref = oracle_solve(req, rec["iters"])
+        err = dg.norm(ref.p, a - ref.F) / dg.norm(ref.p, ref.F)
+        assert err <= (1e-11 if precision == 0 else 1e-5), (rec, err)
     lat = [r["latency"] for r in out["records"]]
     assert out["p50"] <= out["p99"] and min(lat) > 0
 
@@ -62,3 +80,27 @@ def test_admission_by_budget_and_state(lib):
     r = lib.cmcg_engine_collect(e, s2, p2)
     assert lib.cmcg_result_stats(r)["iters"] > 0
     assert lib.cmcg_engine_poll(e, s2) == 0
+
+
+def test_request_larger_than_the_budget_is_rejected(lib):
+    """A request whose footprint exceeds the whole budget gets its own error
+    code from the engine, and the serving loop rejects it (instead of waiting
+    for it forever) while serving the requests behind it."""
+    from paper_2106_02858_amd import serving
+    # n = 2 (48 tets), 2, 1 (6 tets): the first two can never fit a budget sized
+    # for the third
+    reqs = inputs.serving_stream(n_requests=3, rate=100.0, seed=9, sizes=(1, 2), orders=(1,))
+    assert [r["n"] for r in reqs] == [2, 2, 1]
+    cache = serving.SpaceCache(1)
+    probs = [serving.build_problem(cache, r) for r in reqs]
+    need = [lib.cmcg_problem_footprint(p) for p in probs]
+    small = need[2]
+    assert need[0] > small
+    e = lib.cmcg_engine_create(small, 2)
+    with pytest.raises(lib.CmcgError) as err:
+        lib.cmcg_engine_admit(e, probs[0])
+    assert err.value.code == lib.CMCG_ERR_TOO_LARGE
+    assert lib.cmcg_engine_info(e)["used"] == 0
+    out = serving.serve(reqs, budget_bytes=small, max_slots=2, precision=1, tol=1e-6)
+    assert out["completed"] == 1 and out["records"][0]["id"] == reqs[2]["id"]
+    assert [r["id"] for r in out["rejected"]] == [reqs[0]["id"], reqs[1]["id"]]

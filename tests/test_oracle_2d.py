@@ -1,5 +1,5 @@
-"""Pins of the 2-D transverse-magnetic oracle (Section 5.1, two-dimensional
-setting; Section 5.2, DG scheme; Section 5.3, CFL rule; Section 6, numerical
+"""Pins of the 2-D transverse-magnetic oracle (Section 5.2.1, two-dimensional
+setting; Section 5.2.2, DG scheme; Section 5.3, CFL rule; Section 6, numerical
 examples).
 
 * reference triangle: exact integrals and derivatives of polynomials;
