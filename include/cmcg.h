@@ -356,6 +356,24 @@ int cmcg_debug_step(cmcg_problem* p, const cmcg_options* o, int m, int direction
 int cmcg_debug_dot(cmcg_problem* p, const double* u_dev, const double* v_dev, double* out,
                    hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the inner
+ * product of cmcg_debug_dot, (U, V)_{eps,mu}, with the same kernels and
+ * summation order (bit-for-bit the same value), written to *out_dev (device
+ * memory, one double) in order on `stream`, without synchronising and
+ * without allocating anything.  Its partial sums go to a fixed device array
+ * of 1024 doubles (8 KB) that the library holds on every GPU it runs on until
+ * the process ends; any K is accepted (the reduction uses at most 1024
+ * partials; a size needing more would be rejected with CMCG_ERR_ARG).  Every
+ * partial is written before it is read, so the array needs no clearing.
+ * All calls on one GPU share that array: calls that may overlap on one GPU
+ * (different streams without ordering between them, several host threads)
+ * race and must be serialised by the caller.  u_dev, v_dev: device dof
+ * vectors of p's space (FP64).  Errors: CMCG_ERR_ARG (NULL argument),
+ * CMCG_ERR_STATE (p's device is not current), CMCG_ERR_DEVICE (launch). */
+int cmcg_debug_dot_noalloc(const cmcg_problem* p, const double* u_dev, const double* v_dev,
+                           double* out_dev, hipStream_t stream);
+
 /* ------------------------------------------------------------ serving -- */
 /* Continuous batching of independent solve requests (any mesh, order,
  * frequency, source).  Each admitted problem occupies a slot with its own

@@ -19,6 +19,7 @@
 //     accumulation run as one coalesced pass over the 10-element chunk.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "internal.h"
@@ -1277,7 +1278,45 @@ void check_launch() {
     if (e != hipSuccess) fail(CMCG_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
 }
 
+// Fixed device array for the partial sums of the allocation-free inner
+// product (one copy per GPU, held until the process ends).  Host code never
+// passes its name to a kernel: the name is a host-side stand-in, and the
+// device address comes from hipGetSymbolAddress, resolved once per device.
+constexpr int kNoallocDoubles = 1024;
+static_assert(kNoallocDoubles >= kDotBlocks, "the scratch array must hold every partial of a dot");
+__device__ __align__(256) double scratch[kNoallocDoubles];
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[64] = {};
+
 }  // namespace
+
+size_t noalloc_scratch_doubles() { return kNoallocDoubles; }
+
+double* noalloc_scratch(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0 || device >= 64) fail(CMCG_ERR_DEVICE, "device index out of range");
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        CMCG_HIP(hipGetDevice(&cur));
+        if (cur != device) fail(CMCG_ERR_STATE, "scratch address requested for a device that is not current");
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            fail(CMCG_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[device] = (double*)ptr;
+    }
+    return g_scratch_ptr[device];
+}
+
+int dot_blocks(int64_t K) {
+    const int64_t rows = 6 * K;
+    int64_t blocks = (rows + kDotThreads - 1) / kDotThreads;
+    if (blocks > kDotBlocks) blocks = kDotBlocks;
+    return (int)(blocks < 1 ? 1 : blocks);
+}
 
 void upload_constants(int q, int precision, const double* D, const double* LIFT, const double* M,
                       const int* fnode, const int* fperm) {
@@ -1425,9 +1464,7 @@ int get_stage_variant(int q, int precision) { return g_variant[q][precision]; }
 
 void launch_dot(int q, const double* U, const double* V, const double* wE, const double* wH, int64_t K,
                 double* partial, double* out_dev, hipStream_t s) {
-    int64_t rows = 6 * K;
-    int blocks = (int)((rows + kDotThreads - 1) / kDotThreads);
-    if (blocks > kDotBlocks) blocks = kDotBlocks;
+    const int blocks = dot_blocks(K);
     if (q == 1)
         hipLaunchKernelGGL(k_dot<1>, dim3(blocks), dim3(kDotThreads), 0, s, U, V, wE, wH, K, partial);
     else if (q == 2)

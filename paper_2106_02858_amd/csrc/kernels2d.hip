@@ -719,6 +719,8 @@ void launch_dot_batch2d(int q, const double* U, const double* V, const double* w
     check2();
 }
 
+int dot2d_partials() { return kDot2Blocks; }
+
 void launch_dot2d(int q, const double* U, const double* V, const double* wE, const double* wH, int64_t K,
                   double* partial, double* out_dev, hipStream_t s) {
     if (q == 1)

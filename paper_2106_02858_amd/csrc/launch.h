@@ -102,6 +102,15 @@ void launch_filter_add(int precision, const void* U, double w_re, double w_im, d
 // Deterministic M-weighted inner product (U, V)_{eps,mu}; result written to
 // out_dev[0] (device).  partial: scratch of dot_partials() doubles.
 int dot_partials();
+// Partials (blocks) a 3-D dot over K elements writes; <= dot_partials().
+int dot_blocks(int64_t K);
+// Allocation-free inner product: device address of this GPU's fixed scratch
+// array (resolved with hipGetSymbolAddress on the first request, with
+// `device` current) and its capacity in doubles.  The 2-D dot writes
+// dot2d_partials() partials.
+double* noalloc_scratch(int device);
+size_t noalloc_scratch_doubles();
+int dot2d_partials();
 void launch_dot(int q, const double* U, const double* V, const double* wE, const double* wH,
                 int64_t K, double* partial, double* out_dev, hipStream_t s);
 // Batched forms: members are consecutive blocks of n entries (K elements).

@@ -275,6 +275,10 @@ static cmcg_problem* make_problem(const cmcg_space* sh, const double* eps, const
     p->wH.alloc(K * 8);
     CMCG_HIP(hipMemcpy(p->wE.p, we.data(), K * 8, hipMemcpyHostToDevice));
     CMCG_HIP(hipMemcpy(p->wH.p, wh.data(), K * 8, hipMemcpyHostToDevice));
+    // per-device set-up that the allocation-free entry point relies on: the
+    // reference matrices of this order and the address of the scratch array
+    ensure_constants(sp->device, sp->q, sp->dim);
+    (void)noalloc_scratch(sp->device);
     if (sp->dim == 2) {
         build_source2d(p.get(), j_re, j_im, g_re, g_im, nh);
         build_geo(p.get(), 1.0);
@@ -1442,6 +1446,27 @@ int cmcg_debug_dot(cmcg_problem* p, const double* u, const double* v, double* ou
     ensure_constants(p->sp->device, p->sp->q, p->sp->dim);
     ensure_work(p);
     *out = dot(p, u, v, stream);
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_debug_dot_noalloc(const cmcg_problem* p, const double* u, const double* v, double* out_dev,
+                           hipStream_t stream) {
+    CMCG_GUARD_BEGIN
+    if (!p || !u || !v || !out_dev) fail(CMCG_ERR_ARG, "debug_dot_noalloc: NULL argument");
+    const SpaceData& s = *p->sp;
+    if (current_device() != s.device) fail(CMCG_ERR_STATE, "debug_dot_noalloc: wrong current device");
+    // the partials the reduction writes must fit the fixed scratch array
+    const size_t need = s.dim == 2 ? (size_t)dot2d_partials() : (size_t)dot_blocks(s.K);
+    if (need > noalloc_scratch_doubles())
+        fail(CMCG_ERR_ARG, "debug_dot_noalloc: " + std::to_string(need) + " partial sums exceed the scratch array of " +
+                               std::to_string(noalloc_scratch_doubles()));
+    // constants and the scratch address were set up when the problem was created
+    double* partial = noalloc_scratch(s.device);
+    if (s.dim == 2)
+        launch_dot2d(s.q, u, v, p->wE.as<double>(), p->wH.as<double>(), s.K, partial, out_dev, stream);
+    else
+        launch_dot(s.q, u, v, p->wE.as<double>(), p->wH.as<double>(), s.K, partial, out_dev, stream);
     return CMCG_OK;
     CMCG_GUARD_END
 }
