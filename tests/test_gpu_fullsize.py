@@ -9,7 +9,11 @@ configuration bench.py times.
 * the 64-member batched configuration: members equal their single solves
   bit for bit;
 * the head of the 2000-request stream through the serving engine: each
-  served result equals the same request solved alone, bit for bit.
+  served result equals the same request solved alone, bit for bit;
+* whole solves at full size: FP32 fields against FP64 fields (the FP64
+  path is itself pinned to the oracle) at the same CG iteration count, on the
+  48000-tet P3 configuration and the 1,572,864-tet P2 scatterer, 1e-5
+  relative in the eps,mu norm.
 """
 import math
 
@@ -110,3 +114,58 @@ def test_serving_stream_head_equal_alone(lib):
         assert lib.cmcg_result_stats(alone)["iters"] == rec["iters"]
         assert np.array_equal(filtered(lib, out["results"][rec["id"]], info["K"], info["Np"]),
                               filtered(lib, alone, info["K"], info["Np"]))
+
+
+def _weighted_rel(lib, p64, a, b):
+    """||a - b|| / ||b|| in the eps,mu norm (complex dof vectors on the
+    device), with the FP64 problem's inner product."""
+    d = a - b
+    num = lib.cmcg_debug_dot(p64, d.real.contiguous(), d.real.contiguous()) + \
+        lib.cmcg_debug_dot(p64, d.imag.contiguous(), d.imag.contiguous())
+    den = lib.cmcg_debug_dot(p64, b.real.contiguous(), b.real.contiguous()) + \
+        lib.cmcg_debug_dot(p64, b.imag.contiguous(), b.imag.contiguous())
+    return math.sqrt(num / den)
+
+
+def _filtered_dev(lib, r, K, Np):
+    import torch
+    fr = torch.zeros((K, 6, Np), dtype=torch.float64, device="cuda")
+    fi = torch.zeros_like(fr)
+    lib.cmcg_result_filtered_device(r, fr, fi)
+    return torch.complex(fr, fi)
+
+
+@pytest.mark.parametrize("name,iters", [("large_single_p3", 0), ("scatterer_p2", 6)])
+def test_fp32_solve_against_fp64_solve_at_full_size(lib, name, iters):
+    """One CMCG solve with FP32 fields (FP64 CG scalars and vectors) against
+    the same solve with FP64 fields at the same iteration count: the FP32
+    error stated per result stays within 1e-5.  48000-tet P3: the FP64
+    solve's own count at 1e-6 (the benchmarked solve); 1,572,864-tet P2
+    scatterer: a fixed count of 6 iterations."""
+    import torch
+    w = inputs.large_single() if name == "large_single_p3" else inputs.scatterer()
+    print(f"full-size solve {name}: K={w.K} q={w.q}", flush=True)
+    m = lib.cmcg_mesh_create(w.xyz, w.tet, w.tags)
+    res = {}
+    for precision in (0, 1):
+        s = lib.cmcg_space_create(m, w.q, precision)
+        jd = torch.tensor(inputs.gaussian_current(lib.cmcg_space_nodes(s), w.centre, w.width, w.pol),
+                          dtype=torch.float64, device="cuda")
+        p = lib.cmcg_problem_create_device(s, w.eps, w.mu, w.sigma, w.omega, jd)
+        del jd
+        if precision == 0 and iters == 0:
+            o = lib.cmcg_options_default(tol=1e-6, max_iter=2000)
+        else:
+            o = lib.cmcg_options_default(fixed_iters=iters)
+        r = lib.cmcg_solve(p, o)
+        st = lib.cmcg_result_stats(r)
+        if precision == 0:
+            iters = st["iters"]
+        info = lib.cmcg_space_info(s)
+        res[precision] = (p, _filtered_dev(lib, r, info["K"], info["Np"]))
+        print(f"  precision {precision}: {st['iters']} iterations, rel res {st['rel_res']:.2e}, "
+              f"{st['seconds']:.2f} s", flush=True)
+        del r
+    err = _weighted_rel(lib, res[0][0], res[1][1], res[0][1])
+    print(f"  FP32 vs FP64 filtered fields: {err:.2e}", flush=True)
+    assert err < 1e-5

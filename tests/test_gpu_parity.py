@@ -275,6 +275,25 @@ def test_cmcg_fixed_iterations_mixed_walls(lib, q, n):
     assert err < max(1e-11, 10 * spread)
 
 
+@pytest.mark.parametrize("q,n", [(1, 2), (2, 2)])
+def test_cmcg_mixed_walls_against_discrete_periodic(lib, q, n):
+    """Mixed PEC / impedance walls, a rounding-independent pin: the FP64 GPU
+    CMCG run to a tight tolerance reaches the exactly periodic orbit of the
+    fully discrete scheme, solved directly by the oracle ((z I - R) U^ = S,
+    filtered by the closed forms of the trapezoid / Hermite rules).  Unlike
+    a fixed-count comparison, this does not depend on the summation order of
+    either side's inner products."""
+    from oracle import fs
+    op, s, lp = pair(lib, n=n, q=q, seed=1, sigma=False, g=(q == 2))
+    r = lib.cmcg_solve(lp, lib.cmcg_options_default(tol=1e-12, max_iter=600))
+    st = lib.cmcg_result_stats(r)
+    _, F = fs.discrete_periodic(op, st["steps"], timestep.default_scheme(q))
+    err = rel_norm_c(op, _filtered(lib, r, op), F)
+    print(f"mixed q={q}: {st['iters']} iterations to {st['rel_res']:.1e}, vs exact orbit {err:.2e}", flush=True)
+    assert st["rel_res"] <= 1e-12
+    assert err <= 1e-9
+
+
 def test_cmcg_plain_fp64_configuration(lib):
     """The 1296-tet P1 configuration (n = 6): FP64 library CMCG at the
     oracle's iteration count matches the oracle's filtered field."""
