@@ -106,8 +106,8 @@ def _lift(p: Problem, fluxE, fluxH):
     fs = geo.fscale[:, :, None, None]
     fE = (fluxE * fs).reshape(K, 4 * Nfp, 3)
     fH = (fluxH * fs).reshape(K, 4 * Nfp, 3)
-    LE = np.einsum("ik,ekc->eci", ref["LIFT"], fE)
-    LH = np.einsum("ik,ekc->eci", ref["LIFT"], fH)
+    LE = np.einsum("ik,ekc->eci", ref["LIFT"], fE, optimize=True)
+    LH = np.einsum("ik,ekc->eci", ref["LIFT"], fH, optimize=True)
     return LE, LH
 
 
@@ -132,8 +132,8 @@ def _rhs(p: Problem, U: np.ndarray, _unused) -> np.ndarray:
     K, Np, Nfp = geo.K, geo.Np, geo.Nfp
     U = U.reshape(K, 6, Np)
     # volume term: reference derivatives, then physical gradient
-    dref = np.einsum("aij,ecj->ecai", ref["D"], U)          # [K,6,3,Np]
-    grad = np.einsum("eak,ecai->ecki", geo.G, dref)         # [K,6,3(x_k),Np]
+    dref = np.einsum("aij,ecj->ecai", ref["D"], U, optimize=True)   # [K,6,3,Np]
+    grad = np.einsum("eak,ecai->ecki", geo.G, dref, optimize=True)  # [K,6,3(x_k),Np]
     E_g, H_g = grad[:, 0:3], grad[:, 3:6]
 
     def curl(gr):  # gr[e, comp, dir, node]
