@@ -70,6 +70,10 @@ def parse():
     ap.add_argument("--serve-precision", choices=["fp32", "fp64"], default="fp32",
                     help="serving: field precision of the served solves (fp64: the plain form, for comparison)")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: engine memory budget")
+    ap.add_argument("--serve-requests", type=int, default=16,
+                    help="default line: requests of the short served stream")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default line: skip the scatterer and batched kernel rooflines and the short served stream")
     return ap.parse_args()
 
 
@@ -128,6 +132,41 @@ def stage_bytes_per_element(q: int, esize: int) -> float:
     else:
         per_dof = 24.0 / 2 if esize == 4 else 40.0 / 2
     return 6 * Np * per_dof + 40 * esize + 16
+
+
+def method_bytes_per_dof_update(q: int, esize: int, members: int = 1) -> float:
+    """The method's minimum HBM bytes per dof-update (one dof advanced one
+    full time step): every field vector the Runge-Kutta form must read or
+    write once per stage -- RK4 16 passes (stage 1 reads Y and writes Y',
+    Acc; stages 2-3 read Y, U, Acc and write Y', Acc; stage 4 reads Y, Acc and
+    writes U), RK2 5 passes -- plus each element's geometry and connectivity
+    once per right-hand side (27 geometry scalars, 4 neighbour ids, 4 face
+    codes: 128 B with FP32 fields, 236 B with FP64), shared by the members of
+    a batched launch; neighbour traces are taken as cache hits.  The 48000-tet
+    P3 FP32 solve: 68.27 B; the 64-member P2 batch: 64.13 B; the
+    1,572,864-tet P2 scatterer: 72.53 B; FP64 P3: 135.87 B."""
+    Np = (q + 1) * (q + 2) * (q + 3) // 6
+    passes, stages = (16, 4) if q >= 2 else (5, 2)
+    geo = 128.0 if esize == 4 else 236.0
+    return passes * esize + stages * geo / (6 * Np) / members
+
+
+def method_bytes_per_launch(q: int, esize: int, K: int, members: int = 1) -> float:
+    """method_bytes_per_dof_update spread over the stage launches of a step
+    (each launch advances 6 Np K dofs of every member by one stage)."""
+    Np = (q + 1) * (q + 2) * (q + 3) // 6
+    stages = 4 if q >= 2 else 2
+    return method_bytes_per_dof_update(q, esize, members) * 6 * Np * K * members / stages
+
+
+def compensation_bytes_per_launch(q: int, K: int, members: int = 1) -> float:
+    """Extra traffic of the compensated FP32 state, beyond the method's
+    minimum, per dof and step: the last stage reads and writes the 2-byte low
+    part, and with RK4 also reads U (4 B) for the two-sum (RK2's last stage
+    reads U anyway)."""
+    Np = (q + 1) * (q + 2) * (q + 3) // 6
+    stages, extra = (4, 8.0) if q >= 2 else (2, 4.0)
+    return extra * 6 * Np * K * members / stages
 
 
 def bytes_per_dof_update(q: int, esize: int, members: int = 1) -> float:
@@ -216,7 +255,7 @@ def batched(a):
            "cmcg": {"iters_min": min(st["iters"] for st in sts), "iters_max": max(st["iters"] for st in sts),
                     "time_to_1e-6_all_members_s": max(st["seconds_to_1e6"] for st in sts),
                     "seconds": sts[0]["seconds"]},
-           "hbm_job": job_roofline(dof / el, bytes_per_dof_update(2, 4, a.members))}
+           "hbm_job": job_roofline(dof / el, method_bytes_per_dof_update(2, 4, a.members))}
     if a.fp64_members > 0:
         # the plain FP64 form on the same problems: one solve after another
         s64 = cmcg.cmcg_space_create(mesh, w0.q, cmcg.CMCG_FP64)
@@ -323,8 +362,8 @@ def scatterer(a):
     ev1.record(stream)
     torch.cuda.synchronize()
     per_launch = ev0.elapsed_time(ev1) / 1e3 / (4 * M)
-    bpe = stage_bytes_per_element(w.q, 4)
-    achieved = bpe * K / per_launch / 1e9
+    bpl = method_bytes_per_launch(w.q, 4, K)
+    achieved = bpl / per_launch / 1e9
     kname = STAGE_KERNEL[cmcg.cmcg_tune_get_stage(w.q, cmcg.CMCG_FP32)].format(q=w.q)
     out = {"metric": "DG dof-updates/s; CMCG time-to-1e-6 residual vs FP64 plain; p50/p99 latency",
            "value": st["dof_updates"] / el, "unit": "dof-updates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
@@ -338,9 +377,9 @@ def scatterer(a):
            "cmcg": {"iters": st["iters"], "periods": st["periods"], "rel_res": st["rel_res"]},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kname,
-                        "avg_launch_us": per_launch * 1e6, "bytes_per_launch": bpe * K,
+                        "avg_launch_us": per_launch * 1e6, "bytes_per_launch": bpl,
                         "copy_GBs": stream_copy_gbs(), "frac_of_copy": achieved / stream_copy_gbs()},
-           "hbm_job": job_roofline(st["dof_updates"] / el, bytes_per_dof_update(w.q, 4))}
+           "hbm_job": job_roofline(st["dof_updates"] / el, method_bytes_per_dof_update(w.q, 4))}
     print(json.dumps(out), flush=True)
 
 
@@ -714,7 +753,7 @@ def served(a):
            "serving": {**{k: out[k] for k in ("completed", "elapsed", "throughput", "p50", "p99", "offered_rate",
                                               "engine_steps")},
                        "service_p50": float(np.percentile(svc, 50)), "service_p99": float(np.percentile(svc, 99))}}
-    byts = sum(r["dof_updates"] * bytes_per_dof_update(r["q"], 8 if fp64 else 4) for r in out["records"])
+    byts = sum(r["dof_updates"] * method_bytes_per_dof_update(r["q"], 8 if fp64 else 4) for r in out["records"])
     res["hbm_job"] = job_roofline(out["dof_updates_per_s"], byts / max(1.0, sum(r["dof_updates"] for r in out["records"])))
     print(json.dumps(res), flush=True)
 
@@ -810,9 +849,9 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     per_launch_s = ev0.elapsed_time(ev1) / 1e3 / (a.kernel_periods * 4 * M)
-    bpe = stage_bytes_per_element(w.q, 4)
+    bpl = method_bytes_per_launch(w.q, 4, K)
     kname = STAGE_KERNEL[cmcg.cmcg_tune_get_stage(w.q, cmcg.CMCG_FP32)].format(q=w.q)
-    achieved = bpe * K / per_launch_s / 1e9
+    achieved = bpl / per_launch_s / 1e9
 
     out = {
         "metric": "DG dof-updates/s; CMCG time-to-1e-6 residual vs FP64 plain; p50/p99 latency",
@@ -840,7 +879,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, K),
                      "kernel": kname,
                      "avg_launch_us": per_launch_s * 1e6,
-                     "bytes_per_launch": bpe * K,
+                     "bytes_per_launch": bpl,
+                     "bytes_per_dof_update": method_bytes_per_dof_update(w.q, 4),
+                     "compensation_overhead_bytes_per_launch": compensation_bytes_per_launch(w.q, K),
+                     "implementation_bytes_per_launch": stage_bytes_per_element(w.q, 4) * K,
                      "copy_GBs": stream_copy_gbs(), "frac_of_copy": achieved / stream_copy_gbs()},
     }
     if not a.no_fp64:
@@ -860,10 +902,130 @@ def main():
         num = sum(cmcg.cmcg_debug_dot(p64, x, x) for x in d)
         den = sum(cmcg.cmcg_debug_dot(p64, x, x) for x in f64)
         out["cmcg"]["fp32_vs_fp64_rel_l2"] = math.sqrt(num / den)
+    del s32, p32, r
+    if not a.no_extra:
+        # the stage kernel where the working set exceeds the on-die caches, the
+        # batched launch with every member active, and a short served stream
+        out["roofline_scatterer"] = scatterer_kernel(a)
+        out["roofline_batched"] = batched_kernel(a)
+        out["serving"] = serving_short(a)
     if not a.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
     print(json.dumps(out), flush=True)
+
+
+def _free_device():
+    import gc
+
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def scatterer_kernel(a) -> dict:
+    """Stage-launch roofline on the 1,572,864-tet P2 scatterer (FP32 fields;
+    its field vectors far exceed the 256 MB Infinity Cache): HIP events around
+    one homogeneous period (4 M launches) on the launch stream."""
+    import torch
+
+    from paper_2106_02858_amd import cmcg, inputs
+    _free_device()
+    dev = torch.device("cuda:0")
+    w = inputs.scatterer()
+    mesh = cmcg.cmcg_mesh_create(w.xyz, w.tet, w.tags)
+    s = cmcg.cmcg_space_create(mesh, w.q, cmcg.CMCG_FP32)
+    jd = torch.tensor(inputs.gaussian_current(cmcg.cmcg_space_nodes(s), w.centre, w.width, w.pol),
+                      dtype=torch.float64, device=dev)
+    p = cmcg.cmcg_problem_create_device(s, w.eps, w.mu, w.sigma, w.omega, jd)
+    del jd
+    K, Np = w.K, 10
+    opts = cmcg.cmcg_options_default()
+    if not a.no_autotune:
+        v, us = cmcg.cmcg_autotune_stage(p, opts)
+        log(f"scatterer: autotuned variant {v}, us per launch {[round(u, 1) for u in us]}")
+    M, _ = cmcg.cmcg_problem_steps(p, opts)
+    U0 = torch.randn((K, 6, Np), dtype=torch.float64, device=dev) * 1e-3
+    UT = torch.empty_like(U0)
+    cmcg.cmcg_debug_period(p, U0, UT, 1, False, opts=opts)  # builds the period's graph
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    cmcg.cmcg_debug_period(p, U0, UT, 1, False, opts=opts)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    per_launch = ev0.elapsed_time(ev1) / 1e3 / (4 * M)
+    bpl = method_bytes_per_launch(w.q, 4, K)
+    achieved = bpl / per_launch / 1e9
+    kname = STAGE_KERNEL[cmcg.cmcg_tune_get_stage(w.q, cmcg.CMCG_FP32)].format(q=w.q)
+    log(f"scatterer stage launch {per_launch * 1e6:.1f} us = {achieved:.0f} GB/s ({kname})")
+    del p, s, mesh, U0, UT
+    _free_device()
+    return {"workload": f"scatterer: 64^3x6 = {K} tets, P2, FP32 fields, one homogeneous period of {M} steps",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "kernel": kname, "avg_launch_us": per_launch * 1e6,
+            "bytes_per_launch": bpl, "bytes_per_dof_update": method_bytes_per_dof_update(w.q, 4),
+            "compensation_overhead_bytes_per_launch": compensation_bytes_per_launch(w.q, K),
+            "traffic": None}
+
+
+def batched_kernel(a) -> dict:
+    """Batched stage-launch roofline: the 64 solves on the 10368-tet P2 mesh,
+    one launch per Runge-Kutta stage for all members, timed by the library's
+    batched autotuner (HIP events on its stream) over 8 homogeneous steps in
+    which every member is active."""
+    from paper_2106_02858_amd import cmcg, inputs
+    _free_device()
+    ws = inputs.batched_members(n=12, q=2, B=a.members)
+    w0 = ws[0]
+    mesh = cmcg.cmcg_mesh_create(w0.xyz, w0.tet, w0.tags)
+    s = cmcg.cmcg_space_create(mesh, w0.q, cmcg.CMCG_FP32)
+    nodes = cmcg.cmcg_space_nodes(s)
+    probs = [cmcg.cmcg_problem_create(s, w.eps, w.mu, None, w.omega,
+                                      inputs.gaussian_current(nodes, w.centre, w.width, w.pol)) for w in ws]
+    old = cmcg.cmcg_tune_get_stage(2, cmcg.CMCG_FP32)
+    v, us = cmcg.cmcg_autotune_batch(probs)
+    if a.no_autotune:
+        cmcg.cmcg_tune_stage(2, cmcg.CMCG_FP32, old)
+        v = old
+    per_launch = us[v] * 1e-6
+    K = w0.K
+    bpl = method_bytes_per_launch(2, 4, K, a.members)
+    achieved = bpl / per_launch / 1e9
+    kname = STAGE_KERNEL[v].format(q=2)
+    log(f"batched stage launch (all {a.members} members active) {us[v]:.1f} us = {achieved:.0f} GB/s ({kname}); "
+        f"variants {[round(u, 1) for u in us]}")
+    del probs, s, mesh
+    _free_device()
+    return {"workload": f"batched: {a.members} members on the {K}-tet P2 mesh, FP32 fields, every member active",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "kernel": kname, "avg_launch_us": us[v],
+            "bytes_per_launch": bpl, "bytes_per_dof_update": method_bytes_per_dof_update(2, 4, a.members),
+            "compensation_overhead_bytes_per_launch": compensation_bytes_per_launch(2, K, a.members),
+            "variant_us": us, "traffic": None}
+
+
+def serving_short(a) -> dict:
+    """The head of the 20 req/s request stream through the serving engine
+    (FP32 fields, CMCG to 1e-6): latency p50 / p99 and throughput."""
+    import numpy as np
+
+    from paper_2106_02858_amd import cmcg, inputs, serving
+    _free_device()
+    reqs = inputs.serving_stream(n_requests=2000, rate=a.rate)[: a.serve_requests]
+    out = serving.serve(reqs, budget_bytes=int(a.budget_gb * 2 ** 30), max_slots=a.slots, tol=a.tol,
+                        precision=cmcg.CMCG_FP32, log=log)
+    svc = np.array([r["done"] - r["admitted"] for r in out["records"]])
+    byts = sum(r["dof_updates"] * method_bytes_per_dof_update(r["q"], 4) for r in out["records"])
+    dofs = max(1.0, sum(r["dof_updates"] for r in out["records"]))
+    _free_device()
+    return {"workload": f"first {a.serve_requests} requests of the 2000-request Poisson stream at {a.rate:g} req/s "
+                        f"(n in 8,12,16,24; q in 1,2,3), {a.slots} slots, FP32 fields, CMCG to {a.tol:g}",
+            **{k: out[k] for k in ("completed", "elapsed", "throughput", "p50", "p99", "offered_rate")},
+            "rejected": len(out["rejected"]), "service_p50": float(np.percentile(svc, 50)),
+            "service_p99": float(np.percentile(svc, 99)), "dof_updates_per_s": out["dof_updates_per_s"],
+            "hbm_job": job_roofline(out["dof_updates_per_s"], byts / dofs)}
 
 
 if __name__ == "__main__":

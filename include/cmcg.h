@@ -441,6 +441,19 @@ int cmcg_tune_get_stage(int q, int precision, int* variant);
  * errors as CMCG_ERR_DEVICE. */
 int cmcg_autotune_stage(cmcg_problem* p, const cmcg_options* o, hipStream_t stream, int* variant,
                         double* us_per_launch);
+/* The same for a batch (the shape cmcg_solve_batch launches): the n problems
+ * must satisfy cmcg_solve_batch's rules; every variant that applies is timed
+ * on up to 8 homogeneous time steps of the batched launch with every member
+ * active (one launch per Runge-Kutta stage covers all members), the fastest
+ * is kept as the process-wide choice for (q, precision) and remembered for
+ * (device, q, precision, K, n), so a later cmcg_solve_batch with
+ * o->autotune = 1 reuses it.  us_per_launch (nullable, CMCG_STAGE_VARIANTS
+ * entries): average microseconds per batched stage launch, 0 where a variant
+ * does not apply.  Allocates the batch's working set for the duration of the
+ * call; does not change the problems' data.  Errors as cmcg_solve_batch;
+ * CMCG_ERR_ARG for 2-D spaces (one 2-D stage kernel). */
+int cmcg_autotune_batch(cmcg_problem* const* problems, int n, const cmcg_options* o, hipStream_t stream,
+                        int* variant, double* us_per_launch);
 
 #ifdef __cplusplus
 }

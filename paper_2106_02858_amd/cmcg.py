@@ -53,7 +53,7 @@ EXPORTED = [
     "cmcg_solve", "cmcg_fw_solve", "cmcg_solve_batch", "cmcg_result_fields", "cmcg_result_filtered_device", "cmcg_result_initial_device",
     "cmcg_result_stats", "cmcg_result_history", "cmcg_result_destroy",
     "cmcg_debug_rhs", "cmcg_debug_period", "cmcg_debug_step", "cmcg_debug_dot", "cmcg_debug_dot_noalloc", "cmcg_tune_stage", "cmcg_tune_get_stage",
-    "cmcg_autotune_stage", "cmcg_mesh_locality_order",
+    "cmcg_autotune_stage", "cmcg_autotune_batch", "cmcg_mesh_locality_order",
     "cmcg_problem_footprint", "cmcg_engine_create", "cmcg_engine_destroy", "cmcg_engine_admit",
     "cmcg_engine_step", "cmcg_engine_poll", "cmcg_engine_collect", "cmcg_engine_cancel", "cmcg_engine_info",
 ]
@@ -133,6 +133,8 @@ _sig = {
     "cmcg_mesh_locality_order": (C.c_int, [C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "cmcg_tune_get_stage": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
     "cmcg_autotune_stage": (C.c_int, [P, C.POINTER(cmcg_options), C.c_void_p, C.POINTER(C.c_int),
+                                      C.POINTER(C.c_double)]),
+    "cmcg_autotune_batch": (C.c_int, [P, C.c_int, C.POINTER(cmcg_options), C.c_void_p, C.POINTER(C.c_int),
                                       C.POINTER(C.c_double)]),
 }
 for _n, (_r, _a) in _sig.items():
@@ -466,6 +468,18 @@ def cmcg_autotune_stage(p: Problem, opts: cmcg_options | None = None, stream=Non
     v = C.c_int()
     us = (C.c_double * CMCG_STAGE_VARIANTS)()
     _check(_lib.cmcg_autotune_stage(p.h, C.byref(o), _stream(stream), C.byref(v), us))
+    return v.value, list(us)
+
+
+def cmcg_autotune_batch(problems, opts: cmcg_options | None = None, stream=None):
+    """(chosen variant, [microseconds per batched stage launch of every
+    variant with all members active, 0 = not applicable])."""
+    o = opts or cmcg_options_default()
+    n = len(problems)
+    arr = (P * n)(*[p.h for p in problems])
+    v = C.c_int()
+    us = (C.c_double * CMCG_STAGE_VARIANTS)()
+    _check(_lib.cmcg_autotune_batch(arr, n, C.byref(o), _stream(stream), C.byref(v), us))
     return v.value, list(us)
 
 

@@ -296,11 +296,10 @@ void set_active(Batch& bt, const std::vector<int>& act, hipStream_t st) {
     CMCG_HIP(hipStreamSynchronize(st));
 }
 
-}  // namespace
-
-void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipStream_t st, cmcg_result** out) {
-    if (!probs || B < 1 || !out) fail(CMCG_ERR_ARG, "solve_batch: NULL argument or empty batch");
-    Batch bt;
+// Validates the members and builds the batch's device state: shared or
+// per-member geometry, sources, field / filter / CG vectors, the member
+// scalar table and step counts; every member active.
+void setup_batch(Batch& bt, cmcg_problem* const* probs, int B, const cmcg_options* o, hipStream_t st) {
     bt.B = B;
     bt.sp = probs[0] ? probs[0]->sp : nullptr;
     if (!bt.sp) fail(CMCG_ERR_ARG, "solve_batch: NULL problem");
@@ -395,24 +394,54 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
     build_table(bt);
     std::vector<int> act(B, 1);
     set_active(bt, act, st);
-    if (o->autotune && s.dim == 3 && !apply_tuned_variant(s.device, s.q, s.precision, K, B)) {
-        // time the stage variants on up to 8 homogeneous steps of the batched launch
-        double us[kStageVariants];
-        const int save = bt.Mmax, Mt = std::min(save, 8);
-        launch_zero(bt.U.p, bt.U.bytes, st);
-        if (bt.Ulo.p) launch_zero(bt.Ulo.p, bt.Ulo.bytes, st);
-        int v;
-        try {
-            v = time_stage_variants(s.q, s.precision, st, [&] {
-                bt.Mmax = Mt;
-                enqueue_batch_period(bt, false, false, st);
-                bt.Mmax = save;
-            }, Mt * bt.S, us);
-        } catch (...) {
+}
+
+// Times the stage variants on up to 8 homogeneous steps of the batched launch
+// (every member active), keeps the fastest as the process-wide choice and
+// remembers it for this shape.
+int tune_batch(Batch& bt, hipStream_t st, double* us) {
+    const SpaceData& s = *bt.sp;
+    const int save = bt.Mmax, Mt = std::min(save, 8);
+    launch_zero(bt.U.p, bt.U.bytes, st);
+    if (bt.Ulo.p) launch_zero(bt.Ulo.p, bt.Ulo.bytes, st);
+    int v;
+    try {
+        v = time_stage_variants(s.q, s.precision, st, [&] {
+            bt.Mmax = Mt;
+            enqueue_batch_period(bt, false, false, st);
             bt.Mmax = save;
-            throw;
-        }
-        remember_tuned_variant(s.device, s.q, s.precision, K, B, v);
+        }, Mt * bt.S, us);
+    } catch (...) {
+        bt.Mmax = save;
+        throw;
+    }
+    remember_tuned_variant(s.device, s.q, s.precision, s.K, bt.B, v);
+    return v;
+}
+
+}  // namespace
+
+int autotune_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipStream_t st, double* us) {
+    if (!probs || B < 1) fail(CMCG_ERR_ARG, "autotune_batch: NULL argument or empty batch");
+    Batch bt;
+    setup_batch(bt, probs, B, o, st);
+    if (bt.sp->dim != 3) fail(CMCG_ERR_ARG, "autotune_batch: the stage variants exist for tetrahedral spaces");
+    double tmp[kStageVariants];
+    const int v = tune_batch(bt, st, us ? us : tmp);
+    CMCG_HIP(hipStreamSynchronize(st));
+    return v;
+}
+
+void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipStream_t st, cmcg_result** out) {
+    if (!probs || B < 1 || !out) fail(CMCG_ERR_ARG, "solve_batch: NULL argument or empty batch");
+    Batch bt;
+    setup_batch(bt, probs, B, o, st);
+    const SpaceData& s = *bt.sp;
+    const int64_t n = s.ndof, K = s.K;
+    std::vector<int> act(B, 1);
+    if (o->autotune && s.dim == 3 && !apply_tuned_variant(s.device, s.q, s.precision, K, B)) {
+        double us[kStageVariants];
+        tune_batch(bt, st, us);
     }
 
     double *U = bt.vu.as<double>(), *R = bt.vr.as<double>(), *D = bt.vd.as<double>(), *A = bt.va.as<double>(),

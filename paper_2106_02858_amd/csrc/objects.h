@@ -195,4 +195,8 @@ void prepare(cmcg_problem* p, const StepCfg& c);
 cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st);
 cmcg_result* fw_solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st);
 void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipStream_t st, cmcg_result** out);
+// Batched stage autotuner: every variant on up to 8 homogeneous steps of the
+// batched launch with all members active; returns the fastest (kept as the
+// process-wide choice), us[v] = microseconds per launch.
+int autotune_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipStream_t st, double* us);
 }  // namespace cmcg

@@ -1499,6 +1499,22 @@ int cmcg_autotune_stage(cmcg_problem* p, const cmcg_options* o, hipStream_t stre
     CMCG_GUARD_END
 }
 
+int cmcg_autotune_batch(cmcg_problem* const* problems, int n, const cmcg_options* o, hipStream_t stream,
+                        int* variant, double* us_per_launch) {
+    CMCG_GUARD_BEGIN
+    if (!problems || n < 1 || !variant) fail(CMCG_ERR_ARG, "autotune_batch: NULL argument or empty batch");
+    if (n > 65535) fail(CMCG_ERR_ARG, "autotune_batch: at most 65535 problems per batch");
+    cmcg_options def;
+    cmcg_options_default(&def);
+    if (!o) o = &def;
+    double us[kStageVariants] = {};
+    *variant = autotune_batch(problems, n, o, stream, us);
+    if (us_per_launch)
+        for (int v = 0; v < kStageVariants; ++v) us_per_launch[v] = us[v];
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
 int cmcg_tune_get_stage(int q, int precision, int* variant) {
     CMCG_GUARD_BEGIN
     if (q < 1 || q > kMaxQ || (precision != CMCG_FP64 && precision != CMCG_FP32) || !variant)

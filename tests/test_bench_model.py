@@ -1,6 +1,8 @@
 """The algorithmic HBM bytes behind ``roofline.achieved``, counted here array
 by array for each Runge-Kutta stage (Section 5.3 schemes, fused stage update)
-and compared with bench.py's closed forms.
+and compared with bench.py's closed forms: the implementation's traffic
+(stage_bytes_per_element) and the method's minimum that roofline.frac uses
+(method_bytes_per_dof_update).
 
 Per dof, with Y the stage input, Y' its output, U the state and Acc the
 stage-combination accumulator (RK4), the launches of one step touch:
@@ -67,3 +69,32 @@ def test_quoted_figures():
     assert bench.bytes_per_dof_update(2, 4, 64) == pytest.approx(72.18, abs=0.01)
     # the 48000-tet P3 FP32 launch
     assert 48000 * bench.stage_bytes_per_element(3, 4) == 112128000
+
+
+def test_method_bytes_count_every_array():
+    """The method's minimum (what roofline.frac is priced with): the field
+    passes of the stage table above without the compensated state's extra
+    traffic, plus 128 B (FP32) or 236 B (FP64) of geometry and connectivity
+    per element and right-hand side, shared by the members of a batch; the
+    compensated state's extra 8 B per dof and step is reported separately."""
+    for q in (1, 2, 3):
+        np3 = (q + 1) * (q + 2) * (q + 3) // 6
+        nst = 4 if q >= 2 else 2
+        for esize, geo in ((4, 128), (8, 236)):
+            plain = sum(esize * (len(r) + len(w)) for r, w in (RK4 if q >= 2 else RK2))
+            for members in (1, 64):
+                assert bench.method_bytes_per_dof_update(q, esize, members) == pytest.approx(
+                    plain + nst * geo / (6 * np3) / members)
+                assert bench.method_bytes_per_launch(q, esize, 1000, members) == pytest.approx(
+                    bench.method_bytes_per_dof_update(q, esize, members) * 6 * np3 * 1000 * members / nst)
+        extra = _field_bytes_per_dof_step(q, 4) - sum(4 * (len(r) + len(w)) for r, w in (RK4 if q >= 2 else RK2))
+        assert bench.compensation_bytes_per_launch(q, 1000) == pytest.approx(extra * 6 * np3 * 1000 / nst)
+
+
+def test_method_figures():
+    assert bench.method_bytes_per_dof_update(3, 4) == pytest.approx(68.27, abs=0.01)     # 48000-tet P3 FP32
+    assert bench.method_bytes_per_dof_update(3, 8) == pytest.approx(135.87, abs=0.01)    # the same, FP64
+    assert bench.method_bytes_per_dof_update(2, 4, 64) == pytest.approx(64.13, abs=0.01)  # 64-member P2 batch
+    assert bench.method_bytes_per_dof_update(2, 4) == pytest.approx(72.53, abs=0.01)     # 1,572,864-tet P2
+    assert bench.method_bytes_per_dof_update(1, 8) == pytest.approx(59.67, abs=0.01)     # 1296-tet P1 FP64
+    assert bench.method_bytes_per_launch(3, 4, 48000) == pytest.approx(98.304e6, rel=1e-6)
