@@ -111,10 +111,11 @@ def measured_traffic(kernel: str, K: int, table=None, source: str = "kernels.hip
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024
 
 
-# single-frequency instantiations (the last template argument selects the several-frequency code)
+# single-frequency instantiations (the MH template argument selects the several-frequency code)
 STAGE_KERNEL = {0: "k_stage<float,{q},false,false>", 1: "k_stage<float,{q},true,false>",
-                2: "k_stage_mfma<{q},false,false,1>", 3: "k_stage_mfma<{q},true,false,1>",
-                4: "k_stage_mfma<{q},true,false,2>"}
+                2: "k_stage_mfma<float,{q},false,false,1>", 3: "k_stage_mfma<float,{q},true,false,1>",
+                4: "k_stage_mfma<float,{q},true,false,2>"}
+STAGE_KERNEL64 = {v: k.replace("float", "double") for v, k in STAGE_KERNEL.items()}
 
 
 def stage_bytes_per_element(q: int, esize: int) -> float:
@@ -902,6 +903,22 @@ def main():
         num = sum(cmcg.cmcg_debug_dot(p64, x, x) for x in d)
         den = sum(cmcg.cmcg_debug_dot(p64, x, x) for x in f64)
         out["cmcg"]["fp32_vs_fp64_rel_l2"] = math.sqrt(num / den)
+        # the plain FP64 path's stage kernel (the variant its autotuned solve kept)
+        ev0.record(stream)
+        for _ in range(a.kernel_periods):
+            cmcg.cmcg_debug_period(p64, U0, UT, 1, False, opts=opts)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        pl64 = ev0.elapsed_time(ev1) / 1e3 / (a.kernel_periods * 4 * M)
+        bpl64 = method_bytes_per_launch(w.q, 8, K)
+        v64 = cmcg.cmcg_tune_get_stage(w.q, cmcg.CMCG_FP64)
+        out["roofline_fp64"] = {"workload": f"the same {K}-tet P{w.q} problem with FP64 fields",
+                                "bound": "hbm", "achieved": bpl64 / pl64 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": bpl64 / pl64 / 1e9 / HBM_PEAK_GBS,
+                                "kernel": STAGE_KERNEL64[v64].format(q=w.q), "avg_launch_us": pl64 * 1e6,
+                                "bytes_per_launch": bpl64, "bytes_per_dof_update": method_bytes_per_dof_update(w.q, 8),
+                                "traffic": None}
+        log(f"fp64 stage launch {pl64 * 1e6:.1f} us ({out['roofline_fp64']['kernel']})")
     del s32, p32, r
     if not a.no_extra:
         # the stage kernel where the working set exceeds the on-die caches, the

@@ -355,6 +355,13 @@ int cmcg_debug_step(cmcg_problem* p, const cmcg_options* o, int m, int direction
                     const double* u_dev, double* out_dev, hipStream_t stream);
 int cmcg_debug_dot(cmcg_problem* p, const double* u_dev, const double* v_dev, double* out,
                    hipStream_t stream);
+/* One 16x16x4 matrix-core product D = A B (v_mfma_f64_16x16x4f64 for
+ * CMCG_FP64, v_mfma_f32_16x16x4f32 for CMCG_FP32 with the inputs rounded to
+ * FP32) through the operand and accumulator lane layout the matrix-core stage
+ * kernels assume.  a_dev [16][4], b_dev [4][16], d_dev [16][16]: row-major
+ * FP64 device arrays; synchronous on return.  Errors: CMCG_ERR_ARG (NULL,
+ * unknown precision). */
+int cmcg_debug_mfma(int precision, const double* a_dev, const double* b_dev, double* d_dev, hipStream_t stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the inner
@@ -418,10 +425,11 @@ int cmcg_engine_info(const cmcg_engine* e, size_t* used, int* n_running, int* n_
 /* Stage-kernel implementation variant for (q, precision): 0 gathers each
  * face's neighbour traces when it is processed, 1 requests them one face
  * ahead (more registers, more latency hiding), 2 runs the volume and lift
- * products on the matrix cores (FP32 fields, q = 2, 3; other combinations
- * fall back to 0), 3 is 2 with the neighbour traces requested one face
- * ahead, 4 is 3 with two waves per 10-element block, each computing half of
- * the output tiles (FP32, q = 2, 3).  All compute the same Phi(t, Y) and stage update.  Process-wide;
+ * products on the matrix cores (q = 2, 3; FP32 fields on
+ * v_mfma_f32_16x16x4f32, FP64 fields on v_mfma_f64_16x16x4f64; q = 1 falls
+ * back to 0), 3 is 2 with the neighbour traces requested one face ahead, 4
+ * is 3 with two waves per 10-element block, each computing half of the
+ * output tiles (q = 2, 3).  All compute the same Phi(t, Y) and stage update.  Process-wide;
  * not thread-safe against concurrent solves.  Returns CMCG_ERR_ARG for an unknown q / precision /
  * variant.  cmcg_tune_get_stage reports the current choice. */
 #define CMCG_STAGE_VARIANTS 5

@@ -52,7 +52,7 @@ EXPORTED = [
     "cmcg_problem_create_harmonics", "cmcg_result_harmonics", "cmcg_result_filtered_harmonic_device",
     "cmcg_solve", "cmcg_fw_solve", "cmcg_solve_batch", "cmcg_result_fields", "cmcg_result_filtered_device", "cmcg_result_initial_device",
     "cmcg_result_stats", "cmcg_result_history", "cmcg_result_destroy",
-    "cmcg_debug_rhs", "cmcg_debug_period", "cmcg_debug_step", "cmcg_debug_dot", "cmcg_debug_dot_noalloc", "cmcg_tune_stage", "cmcg_tune_get_stage",
+    "cmcg_debug_rhs", "cmcg_debug_period", "cmcg_debug_step", "cmcg_debug_dot", "cmcg_debug_dot_noalloc", "cmcg_debug_mfma", "cmcg_tune_stage", "cmcg_tune_get_stage",
     "cmcg_autotune_stage", "cmcg_autotune_batch", "cmcg_mesh_locality_order",
     "cmcg_problem_footprint", "cmcg_engine_create", "cmcg_engine_destroy", "cmcg_engine_admit",
     "cmcg_engine_step", "cmcg_engine_poll", "cmcg_engine_collect", "cmcg_engine_cancel", "cmcg_engine_info",
@@ -103,6 +103,7 @@ _sig = {
     "cmcg_problem_create_device": (C.c_int, [P, P, P, P, C.c_double, P, P, P, P, P, C.POINTER(P)]),
     "cmcg_debug_step": (C.c_int, [P, C.POINTER(cmcg_options), C.c_int, C.c_int, C.c_int, P, P, P]),
     "cmcg_debug_dot_noalloc": (C.c_int, [P, P, P, P, P]),
+    "cmcg_debug_mfma": (C.c_int, [C.c_int, P, P, P, P]),
     "cmcg_problem_destroy": (None, [P]),
     "cmcg_problem_steps": (C.c_int, [P, C.POINTER(cmcg_options), C.POINTER(C.c_int), D]),
     "cmcg_solve": (C.c_int, [P, C.POINTER(cmcg_options), P, P, C.POINTER(P)]),
@@ -440,6 +441,11 @@ def cmcg_debug_dot_noalloc(p: Problem, u_dev, v_dev, out_dev, stream=None):
     """(U, V)_{eps,mu} into out_dev[0] (device), asynchronous on `stream`,
     with no allocation (fixed per-GPU scratch array)."""
     _check(_lib.cmcg_debug_dot_noalloc(p.h, _ptr(u_dev), _ptr(v_dev), _ptr(out_dev), _stream(stream)))
+
+
+def cmcg_debug_mfma(precision: int, a_dev, b_dev, d_dev, stream=None):
+    """D [16,16] = A [16,4] B [4,16] on one matrix-core instruction (device FP64 arrays)."""
+    _check(_lib.cmcg_debug_mfma(int(precision), _ptr(a_dev), _ptr(b_dev), _ptr(d_dev), _stream(stream)))
 
 
 def cmcg_tune_stage(q: int, precision: int, variant: int):

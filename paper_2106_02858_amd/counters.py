@@ -34,6 +34,8 @@ def main() -> int:
     ap.add_argument("--fp64", action="store_true")
     ap.add_argument("--scatterer", action="store_true",
                     help="one homogeneous period of the 1,572,864-tet P2 scatterer (FP32 fields)")
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="stage-kernel variant for the field precision and order (default: the library's choice)")
     ap.add_argument("--batched", action="store_true",
                     help="the batched autotuner on the 64 members of the 10368-tet P2 mesh: every stage variant "
                          "timed on 8 steps with all members active (FP32 fields)")
@@ -73,6 +75,8 @@ def main() -> int:
         torch.cuda.synchronize()
         return copy_calibration(a, dev)
     w = inputs.scatterer() if a.scatterer else inputs.large_single(n=a.n, q=a.q)
+    if a.variant >= 0:
+        cmcg.cmcg_tune_stage(w.q, cmcg.CMCG_FP64 if a.fp64 else cmcg.CMCG_FP32, a.variant)
     if a.scatterer:
         a.periods = 1
     mesh = cmcg.cmcg_mesh_create(w.xyz, w.tet, w.tags)

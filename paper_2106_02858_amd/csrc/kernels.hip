@@ -612,7 +612,7 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
 //   lift:    C[i][n] += sum_{f,k} LIFT[i][f Nfp + k] flux_f[k][n], face by face;
 // with v_mfma_f32_16x16x4f32: A = the reference matrices, held as register
 // fragments (lane l holds A[l % 16][l / 16] of each 16x4 block, read once from a
-// lane-ordered table), B = W or flux values from LDS, D[4 (l/16) + r][l % 16].
+// lane-ordered table), B = W or flux values from LDS, D rows per Mfma<T>::row.
 // The volume's K steps are axis-major: step ks covers axis a = ks / NJ and
 // nodes j = 4 (ks % NJ) + (0..3), so a lane meets the same nodes j = l/16 + 4 t
 // on every axis and reads them once.  Rows i >= Np and nodes j >= Np carry
@@ -630,45 +630,74 @@ __host__ __device__ constexpr int frag_off(int q) {
 }
 constexpr int kFragTotal = 64 * (MfmaDim<2>::NFRAG + MfmaDim<3>::NFRAG);
 __device__ float gFrag[kFragTotal];
+__device__ double gFrag64[kFragTotal];
+template <typename T> __device__ __forceinline__ const T* frags();
+template <> __device__ __forceinline__ const float* frags<float>() { return gFrag; }
+template <> __device__ __forceinline__ const double* frags<double>() { return gFrag64; }
 
-typedef float v4f __attribute__((ext_vector_type(4)));
+// One 16x16x4 matrix-core product D = A B + C in the field precision:
+// v_mfma_f32_16x16x4f32 or v_mfma_f64_16x16x4f64.  Both take A[l % 16][l / 16]
+// and B[l / 16][l % 16] from lane l; their accumulators differ: register r of
+// lane l holds D[row(l / 16, r)][l % 16] with row = 4 (l / 16) + r for FP32
+// and 4 r + l / 16 for FP64 (measured with one-hot operands; checked against
+// numpy through cmcg_debug_mfma).
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int q4, int r) { return 4 * q4 + r; }
+};
+template <> struct Mfma<double> {
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int q4, int r) { return 4 * r + q4; }
+};
 
-template <int Q>
+template <typename T, int Q>
 struct MfmaShared {
     static constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP;
     static constexpr int RS = NP + 1;
     static constexpr int KF = 4 * MfmaDim<Q>::KSF;
     static constexpr int FS = 65;  // flux tile row stride: the face nodes of one column fall in different banks
-    float sY[EPW * 6 * RS];   // stage input, rows (element, component) padded to NP + 1
-    float sF[KF * FS];        // flux tile [face node][column], rows >= NFP stay zero
-    float sG[EPW * kGeo];     // geometry of the chunk
+    T sY[EPW * 6 * RS];       // stage input, rows (element, component) padded to NP + 1
+    T sF[KF * FS];            // flux tile [face node][column], rows >= NFP stay zero
+    T sG[EPW * kGeo];         // geometry of the chunk
     int sC[EPW * 4];          // connectivity codes of the chunk
     uint8_t sT[4 * ft_words(Q)];  // own face nodes [f][k], then neighbour face nodes [nf][perm][k]
 };
 
-// Operands of the coalesced update pass (float4 groups v4 = lane + 64 t of
-// the chunk), all requested before the pass computes: r0 = U (stage 2-4
-// modes) or the stage input (stage-1 modes, filter), r1 = Acc, r2 = the
-// bfloat16 low parts.
-template <int Q, int NTH = 64> struct MfmaUpdateIn {
-    static constexpr int NIT = (EPW * 6 * Dim<Q>::NP / 4 + NTH - 1) / NTH;
-    float4 r0[NIT], r1[NIT];
-    uint2 r2[NIT];
-    __device__ __forceinline__ void fetch(const StageArgs& a, int64_t base, int nv4, int lane) {
+// Operands of the coalesced update pass (16-byte groups v = lane + NTH t of
+// the chunk: 4 FP32 or 2 FP64 values), all requested before the pass
+// computes: r0 = U (modes that combine with the state) or the stage input
+// (stage-1 modes, filter), r1 = Acc, r2 = the bfloat16 low parts (FP32).
+template <typename T, int Q, int NTH = 64> struct MfmaUpdateIn {
+    static constexpr int PV = 16 / (int)sizeof(T);
+    static constexpr bool COMP = std::is_same<T, float>::value;  // compensated state U + Ulo
+    using V = typename std::conditional<COMP, float4, double2>::type;
+    static constexpr int NIT = (EPW * 6 * Dim<Q>::NP / PV + NTH - 1) / NTH;
+    V r0[NIT], r1[NIT];
+    uint2 r2[COMP ? NIT : 1];
+    __device__ __forceinline__ void fetch(const StageArgs& a, int64_t base, int nvv, int lane) {
         const int mode = a.mode;
         const bool s1 = mode == RK2_S1 || mode == RK4_S1 || (mode == RHS && a.filter);
-        const bool needU = mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4;
+        // FP64 stage 4 forms U = Acc + cu k without the state
+        const bool needU = mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || (COMP && mode == RK4_S4);
         const bool needA = mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4;
-        const bool needL = mode == RK2_S2 || mode == RK4_S4;
-        const float* src0 = needU ? (const float*)a.U : (const float*)a.Y;
+        const bool needL = COMP && (mode == RK2_S2 || mode == RK4_S4);
+        const T* src0 = needU ? (const T*)a.U : (const T*)a.Y;
 #pragma unroll
         for (int t = 0; t < NIT; ++t) {
-            const int v4 = lane + NTH * t;
-            if (v4 >= nv4) continue;
-            const int64_t gi = base + 4 * v4;
-            if (s1 || needU) r0[t] = *reinterpret_cast<const float4*>(src0 + gi);
-            if (needA) r1[t] = *reinterpret_cast<const float4*>((const float*)a.Acc + gi);
-            if (needL) r2[t] = *reinterpret_cast<const uint2*>((const uint16_t*)a.Ulo + gi);
+            const int vv = lane + NTH * t;
+            if (vv >= nvv) continue;
+            const int64_t gi = base + PV * vv;
+            if (s1 || needU) r0[t] = *reinterpret_cast<const V*>(src0 + gi);
+            if (needA) r1[t] = *reinterpret_cast<const V*>((const T*)a.Acc + gi);
+            if constexpr (COMP)
+                if (needL) r2[t] = *reinterpret_cast<const uint2*>((const uint16_t*)a.Ulo + gi);
         }
     }
 };
@@ -681,16 +710,19 @@ template <int Q, int NTH = 64> struct MfmaUpdateIn {
 // the MFMAs, the flux items and the update pass are shared by 128 threads.  A
 // block's dependent chain gets shorter at 6 waves per SIMD (76 registers),
 // which pays where the launch ends in a partial round of workgroups.  Register
-// allocation is held to 4 waves per SIMD (128 registers; the LDS tiles of
-// MfmaShared<3> stay under 10 KB so 16 workgroups fit a compute unit).
-// Requesting the update operands earlier (with the staging loads, or before
-// the last face) was measured slower: the registers cost occupancy (P2) or
-// spill (P3).
-template <int Q, bool PIPE, bool MH, int W>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 : 6, 8))) void k_stage_mfma(
-    StageArgs args, int64_t per) {
-    using T = float;
+// allocation is held to 4 waves per SIMD (128 registers; the FP32 LDS tiles
+// of MfmaShared<float, 3> stay under 10 KB so 16 workgroups fit a compute
+// unit).  Requesting the update operands earlier (with the staging loads, or
+// before the last face) was measured slower: the registers cost occupancy
+// (P2) or spill (P3).  T = double runs the same data flow on
+// v_mfma_f64_16x16x4f64 with FP64 fields (no compensated state).
+template <typename T, int Q, bool PIPE, bool MH, int W>
+__global__ __launch_bounds__(64 * W)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (W == 1 ? 4 : 6) : (W == 1 ? 2 : 3), 8)))
+void k_stage_mfma(StageArgs args, int64_t per) {
     using MD = MfmaDim<Q>;
+    using acc_t = typename Mfma<T>::acc_t;
+    constexpr bool COMP = std::is_same<T, float>::value;  // compensated state U + Ulo
     constexpr int NP = MD::NP, NFP = MD::NFP, MT = MD::MT, KSV = MD::KSV, KSF = MD::KSF;
     constexpr int RS = NP + 1;
     constexpr int KF = 4 * KSF;
@@ -702,7 +734,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ?
     constexpr int MW = ROWS ? 1 : MT;   // output row tiles of one wave
     constexpr int NW = COLS ? 2 : 4;    // output column tiles of one wave
     static_assert(W == 1 || ((ROWS || COLS) && RF == 1), "two waves per block need one flux item per thread");
-    __shared__ MfmaShared<Q> sh;
+    __shared__ MfmaShared<T, Q> sh;
 
     StageArgs a;
     if (!member_args<T>(args, a)) return;  // uniform per workgroup
@@ -716,18 +748,19 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ?
     const int nt0 = COLS ? 2 * (tid >> 6) : 0;  // first output column tile of this wave
     const int ne = (int)((a.K - e0) < EPW ? (a.K - e0) : EPW);
     const int64_t base = e0 * 6 * NP;
-    const int nv4 = ne * 6 * NP / 4;  // float4 groups of the chunk (6 NP is even, ne * 6 NP % 4 == 0 for NP even)
+    constexpr int PV = 16 / (int)sizeof(T);  // values per 16-byte group
+    const int nvv = ne * 6 * NP / PV;        // 16-byte groups of the chunk (6 NP ne is a multiple of 4)
 
     // ---- staging: chunk fields, geometry, connectivity, face-node tables
     {
         ChunkIn<T, Q, NTH> in;
         in.fetch(Y, (const T*)a.geo, a.conn, e0, ne, tid);
-        for (int v = tid; v < KF * MfmaShared<Q>::FS; v += NTH) sh.sF[v] = T(0);
+        for (int v = tid; v < KF * MfmaShared<T, Q>::FS; v += NTH) sh.sF[v] = T(0);
         in.put(sh.sY, sh.sG, sh.sC, sh.sT, ne, tid);
     }
 
     // matrix fragments (coalesced: fragment-major, lane-minor)
-    const float* fr = gFrag + frag_off(Q);
+    const T* fr = frags<T>() + frag_off(Q);
     T afV[MW][KSV], afL[MW][KSF], afN[MW][KSF];
 #pragma unroll
     for (int mt = 0; mt < MW; ++mt)
@@ -751,11 +784,11 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ?
 
     const int q4 = lane >> 4;   // K row within a 4-row block / output row group
     const int l16 = lane & 15;  // output column within a 16-column tile
-    v4f acc[MW][NW];
+    acc_t acc[MW][NW];
 #pragma unroll
     for (int mt = 0; mt < MW; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < NW; ++nt) acc[mt][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int nt = 0; nt < NW; ++nt) acc[mt][nt] = acc_t{T(0), T(0), T(0), T(0)};
 
     // ---- volume product: B[(a, j)][n] = sgn (g_a[m1] V_m2(j) - g_a[m2] V_m1(j));
     // padded columns read element 0 (their results are never stored)
@@ -793,7 +826,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ?
                 const T b = g1[ax] * r2[t] - g2[ax] * r1[t];
 #pragma unroll
                 for (int mt = 0; mt < MW; ++mt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(afV[mt][ax * NJ + t], b, acc[mt][nt], 0, 0, 0);
+                    acc[mt][nt] = Mfma<T>::mma(afV[mt][ax * NJ + t], b, acc[mt][nt]);
             }
     }
 
@@ -839,7 +872,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ?
             const T ndH = n0 * dH0 + n1 * dH1 + n2 * dH2;
             const T xH0 = n1 * dH2 - n2 * dH1, xH1 = n2 * dH0 - n0 * dH2, xH2 = n0 * dH1 - n1 * dH0;
             const T xE0 = n1 * dE2 - n2 * dE1, xE1 = n2 * dE0 - n0 * dE2, xE2 = n0 * dE1 - n1 * dE0;
-            T* o = &sh.sF[k * MfmaShared<Q>::FS + fe * 6];
+            T* o = &sh.sF[k * MfmaShared<T, Q>::FS + fe * 6];
             o[0] = cE1 * (dE0 - ndE * n0) - cE2 * xH0;
             o[1] = cE1 * (dE1 - ndE * n1) - cE2 * xH1;
             o[2] = cE1 * (dE2 - ndE * n2) - cE2 * xH2;
@@ -852,12 +885,12 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ?
         for (int ks = 0; ks < KSF; ++ks) {
             T b[NW];
 #pragma unroll
-            for (int nt = 0; nt < NW; ++nt) b[nt] = sh.sF[(ks * 4 + q4) * MfmaShared<Q>::FS + (nt + nt0) * 16 + l16];
+            for (int nt = 0; nt < NW; ++nt) b[nt] = sh.sF[(ks * 4 + q4) * MfmaShared<T, Q>::FS + (nt + nt0) * 16 + l16];
 #pragma unroll
             for (int nt = 0; nt < NW; ++nt)
 #pragma unroll
                 for (int mt = 0; mt < MW; ++mt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(afL[mt][ks], b[nt], acc[mt][nt], 0, 0, 0);
+                    acc[mt][nt] = Mfma<T>::mma(afL[mt][ks], b[nt], acc[mt][nt]);
         }
         __syncthreads();  // the tile is rewritten by the next face
         if (f < 3) {
@@ -884,7 +917,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ?
         for (int mt = 0; mt < MW; ++mt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = (mt + mt0) * 16 + 4 * q4 + r;
+                const int i = (mt + mt0) * 16 + Mfma<T>::row(q4, r);
                 if (i < NP) {
                     T* p = &sh.sY[n * RS + i];
                     *p = fma(inv, acc[mt][nt][r], -sig * *p);
@@ -900,102 +933,137 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ?
     // elements whose source is zero (and H rows of an interior source) read none
     const uint32_t sm = a.smask ? a.smask[blk] : 0xffffffffu;
     auto takes_src = [&](int row) { return row - 6 * (row / 6) < a.src_rows && ((sm >> (row / 6)) & 1u); };
-    MfmaUpdateIn<Q, NTH> upd;
-    upd.fetch(a, base, nv4, tid);
-    auto f4 = [](const void* p, int64_t o) { return reinterpret_cast<const float4*>((const T*)p + o); };
+    using UIn = MfmaUpdateIn<T, Q, NTH>;
+    using V = typename UIn::V;
+    UIn upd;
+    upd.fetch(a, base, nvv, tid);
+    auto ldv = [](const void* p, int64_t o, T (&r)[PV]) {
+        const V v = *reinterpret_cast<const V*>((const T*)p + o);
+        const T* t = reinterpret_cast<const T*>(&v);
 #pragma unroll
-    for (int t = 0; t < MfmaUpdateIn<Q, NTH>::NIT; ++t) {
-        const int v4 = tid + NTH * t;
-        if (v4 >= nv4) continue;
-        const int v = 4 * v4;
+        for (int u = 0; u < PV; ++u) r[u] = t[u];
+    };
+#pragma unroll
+    for (int t = 0; t < UIn::NIT; ++t) {
+        const int vv = tid + NTH * t;
+        if (vv >= nvv) continue;
+        const int v = PV * vv;
         const int64_t gi = base + v;
-        T kv[4];
+        T kv[PV];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) kv[u] = sh.sY[v + u + (v + u) / NP];
-        if (a.src_rows > 0 && (takes_src(v / NP) || takes_src((v + 3) / NP))) {
-            const float4 sr = *f4(a.Sre, gi), si = *f4(a.Sim, gi);
-            const T srv[4] = {sr.x, sr.y, sr.z, sr.w}, siv[4] = {si.x, si.y, si.z, si.w};
+        for (int u = 0; u < PV; ++u) kv[u] = sh.sY[v + u + (v + u) / NP];
+        if (a.src_rows > 0 && (takes_src(v / NP) || takes_src((v + PV - 1) / NP))) {
+            T srv[PV], siv[PV];
+            ldv(a.Sre, gi, srv);
+            ldv(a.Sim, gi, siv);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < PV; ++u) {
                 const int row = (v + u) / NP;
                 if (takes_src(row)) kv[u] += scos * srv[u] - ssin * siv[u];
             }
 #pragma unroll 1
             // further harmonics (tables read from the kernel arguments, as in k_stage)
             for (int h = 1; MH && h < a.nharm; ++h) {
-                const float4 hr = *f4(args.Sre, h * args.hstride + gi), hi = *f4(args.Sim, h * args.hstride + gi);
-                const T hrv[4] = {hr.x, hr.y, hr.z, hr.w}, hiv[4] = {hi.x, hi.y, hi.z, hi.w};
+                T hrv[PV], hiv[PV];
+                ldv(args.Sre, h * args.hstride + gi, hrv);
+                ldv(args.Sim, h * args.hstride + gi, hiv);
                 const T hc = (T)args.hcos[h], hs = (T)args.hsin[h];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < PV; ++u) {
                     const int row = (v + u) / NP;
                     if (takes_src(row)) kv[u] += hc * hrv[u] - hs * hiv[u];
                 }
             }
         }
-        const T x0[4] = {upd.r0[t].x, upd.r0[t].y, upd.r0[t].z, upd.r0[t].w};  // U, or Y in stage-1 modes
-        const T x1[4] = {upd.r1[t].x, upd.r1[t].y, upd.r1[t].z, upd.r1[t].w};  // Acc
-        T lo[4];
-        if (mode == RK2_S2 || mode == RK4_S4) {
-            lo[0] = from_bf16(upd.r2[t].x & 0xffffu);
-            lo[1] = from_bf16(upd.r2[t].x >> 16);
-            lo[2] = from_bf16(upd.r2[t].y & 0xffffu);
-            lo[3] = from_bf16(upd.r2[t].y >> 16);
+        T x0[PV], x1[PV];  // U (or Y in stage-1 modes), Acc
+        {
+            const T* p0 = reinterpret_cast<const T*>(&upd.r0[t]);
+            const T* p1 = reinterpret_cast<const T*>(&upd.r1[t]);
+#pragma unroll
+            for (int u = 0; u < PV; ++u) {
+                x0[u] = p0[u];
+                x1[u] = p1[u];
+            }
         }
-        auto st4 = [&](void* p, const T (&o)[4]) {
-            *reinterpret_cast<float4*>((T*)p + gi) = make_float4(o[0], o[1], o[2], o[3]);
+        T lo[PV];
+        if constexpr (COMP) {
+            if (mode == RK2_S2 || mode == RK4_S4) {
+                lo[0] = from_bf16(upd.r2[t].x & 0xffffu);
+                lo[1] = from_bf16(upd.r2[t].x >> 16);
+                lo[2] = from_bf16(upd.r2[t].y & 0xffffu);
+                lo[3] = from_bf16(upd.r2[t].y >> 16);
+            }
+        }
+        auto stv = [&](void* p, const T (&o)[PV]) {
+            V w;
+            T* q = reinterpret_cast<T*>(&w);
+#pragma unroll
+            for (int u = 0; u < PV; ++u) q[u] = o[u];
+            *reinterpret_cast<V*>((T*)p + gi) = w;
         };
-        auto st_lo = [&](const T (&o)[4]) {
-            uint2 w;
-            w.x = (uint32_t)to_bf16(o[0]) | ((uint32_t)to_bf16(o[1]) << 16);
-            w.y = (uint32_t)to_bf16(o[2]) | ((uint32_t)to_bf16(o[3]) << 16);
-            *reinterpret_cast<uint2*>((uint16_t*)a.Ulo + gi) = w;
-        };
-        T o1[4], o2[4];
+        T o1[PV], o2[PV];
         switch (mode) {
             case RK2_S1:
 #pragma unroll
-                for (int u = 0; u < 4; ++u) o1[u] = fma(cy, kv[u], x0[u]);
-                st4(a.Ynext, o1);
+                for (int u = 0; u < PV; ++u) o1[u] = fma(cy, kv[u], x0[u]);
+                stv(a.Ynext, o1);
                 break;
             case RK2_S2:
+                if constexpr (COMP) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) two_sum(x0[u], fma(cu, kv[u], lo[u]), o1[u], o2[u]);
-                st4(a.Uout, o1);
-                st_lo(o2);
+                    for (int u = 0; u < PV; ++u) two_sum(x0[u], fma(cu, kv[u], lo[u]), o1[u], o2[u]);
+                    stv(a.Uout, o1);
+                    uint2 w;
+                    w.x = (uint32_t)to_bf16(o2[0]) | ((uint32_t)to_bf16(o2[1]) << 16);
+                    w.y = (uint32_t)to_bf16(o2[2]) | ((uint32_t)to_bf16(o2[3]) << 16);
+                    *reinterpret_cast<uint2*>((uint16_t*)a.Ulo + gi) = w;
+                } else {
+#pragma unroll
+                    for (int u = 0; u < PV; ++u) o1[u] = fma(cu, kv[u], x0[u]);
+                    stv(a.Uout, o1);
+                }
                 break;
             case RK4_S1:
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < PV; ++u) {
                     o1[u] = fma(cy, kv[u], x0[u]);
-                    o2[u] = ca * kv[u];
+                    o2[u] = COMP ? ca * kv[u] : fma(ca, kv[u], x0[u]);
                 }
-                st4(a.Ynext, o1);
-                st4(a.Acc, o2);
+                stv(a.Ynext, o1);
+                stv(a.Acc, o2);
                 break;
             case RK4_S2:
             case RK4_S3:
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < PV; ++u) {
                     o1[u] = fma(cy, kv[u], x0[u]);
                     o2[u] = fma(ca, kv[u], x1[u]);
                 }
-                st4(a.Ynext, o1);
-                st4(a.Acc, o2);
+                stv(a.Ynext, o1);
+                stv(a.Acc, o2);
                 break;
             case RK4_S4:
+                if constexpr (COMP) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) two_sum(x0[u], fma(cu, kv[u], x1[u]) + lo[u], o1[u], o2[u]);
-                st4(a.Uout, o1);
-                st_lo(o2);
+                    for (int u = 0; u < PV; ++u) two_sum(x0[u], fma(cu, kv[u], x1[u]) + lo[u], o1[u], o2[u]);
+                    stv(a.Uout, o1);
+                    uint2 w;
+                    w.x = (uint32_t)to_bf16(o2[0]) | ((uint32_t)to_bf16(o2[1]) << 16);
+                    w.y = (uint32_t)to_bf16(o2[2]) | ((uint32_t)to_bf16(o2[3]) << 16);
+                    *reinterpret_cast<uint2*>((uint16_t*)a.Ulo + gi) = w;
+                } else {
+#pragma unroll
+                    for (int u = 0; u < PV; ++u) o1[u] = fma(cu, kv[u], x1[u]);
+                    stv(a.Uout, o1);
+                }
                 break;
             default:
-                st4(a.Kout, kv);
+                stv(a.Kout, kv);
                 break;
         }
         if (a.filter) {  // stage-1 and RHS modes: x0 is the stage input
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < PV; ++u) {
                 const double ud = (double)x0[u], kd = (double)kv[u];
                 a.Fre[gi + u] += a.fa_re * ud + a.fb_re * kd;
                 a.Fim[gi + u] += a.fa_im * ud + a.fb_im * kd;
@@ -1003,13 +1071,28 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W == 1 ?
 #pragma unroll 1
             for (int h = 1; MH && h < a.nharm; ++h)
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < PV; ++u) {
                     const double ud = (double)x0[u], kd = (double)kv[u];
                     args.Fre[h * args.hstride + gi + u] += args.hfa_re[h] * ud + args.hfb_re[h] * kd;
                     args.Fim[h * args.hstride + gi + u] += args.hfa_im[h] * ud + args.hfb_im[h] * kd;
                 }
         }
     }
+}
+
+// One 16x16x4 matrix-core product with the lane layout the stage kernels
+// assume (a single 64-lane wave): lane l takes A[l % 16][l / 16] and
+// B[l / 16][l % 16] and returns D[Mfma<T>::row(l / 16, r)][l % 16], r = 0..3.
+template <typename T>
+__global__ __launch_bounds__(64) void k_mfma_probe(const double* __restrict__ A, const double* __restrict__ B,
+                                                   double* __restrict__ D) {
+    const int l = threadIdx.x;
+    const T a = (T)A[(l % 16) * 4 + l / 16];
+    const T b = (T)B[(l / 16) * 16 + l % 16];
+    typename Mfma<T>::acc_t c = {T(0), T(0), T(0), T(0)};
+    c = Mfma<T>::mma(a, b, c);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) D[Mfma<T>::row(l / 16, r) * 16 + l % 16] = (double)c[r];
 }
 
 template <typename T>
@@ -1222,7 +1305,7 @@ __global__ void k_nonfinite(const double* X, int64_t n, int* flag) {
 }
 
 // Stage-kernel variant per (q, precision): 0 = gather per face, 1 = gathers
-// pipelined one face ahead, 2 / 3 = matrix cores (FP32, q >= 2) without /
+// pipelined one face ahead, 2 / 3 = matrix cores (q >= 2) without /
 // with the one-face-ahead gathers, 4 = 3 with two waves per block.  Chosen
 // from measurements; overridable through cmcg_tune_stage() and the
 // autotuner.  Defaults: FP32 P2 and P3 on the matrix cores with two waves per
@@ -1245,17 +1328,17 @@ void stage_launch_mh(const StageArgs& a, hipStream_t s) {
     const int64_t per = (blocks + 7) / 8;
     const int v = stage_variant(Q, sizeof(T) == 8 ? CMCG_FP64 : CMCG_FP32);
     const dim3 grid((unsigned)(8 * per), (unsigned)(a.nmembers > 1 ? a.nmembers : 1));
-    if constexpr (sizeof(T) == 4 && Q >= 2) {
+    if constexpr (Q >= 2) {
         if (v == 2) {
-            hipLaunchKernelGGL((k_stage_mfma<Q, false, MH, 1>), grid, dim3(64), 0, s, a, per);
+            hipLaunchKernelGGL((k_stage_mfma<T, Q, false, MH, 1>), grid, dim3(64), 0, s, a, per);
             return;
         }
         if (v == 3) {
-            hipLaunchKernelGGL((k_stage_mfma<Q, true, MH, 1>), grid, dim3(64), 0, s, a, per);
+            hipLaunchKernelGGL((k_stage_mfma<T, Q, true, MH, 1>), grid, dim3(64), 0, s, a, per);
             return;
         }
         if (v == 4) {
-            hipLaunchKernelGGL((k_stage_mfma<Q, true, MH, 2>), grid, dim3(128), 0, s, a, per);
+            hipLaunchKernelGGL((k_stage_mfma<T, Q, true, MH, 2>), grid, dim3(128), 0, s, a, per);
             return;
         }
     }
@@ -1352,28 +1435,32 @@ void upload_constants(int q, int precision, const double* D, const double* LIFT,
         // = A[16 mt + lane % 16][4 ks + lane / 16] of the block the fragment names
         const int MT = (NP + 15) / 16, NJ = (NP + 3) / 4, KSV = 3 * NJ, KSF = (NFP + 3) / 4;
         const int nfrag = MT * KSV + 4 * MT * KSF;
-        std::vector<float> fr(64 * nfrag, 0.f);
+        std::vector<double> fr(64 * nfrag, 0.0);
         for (int l = 0; l < 64; ++l) {
             const int i_in = l % 16, k_in = l / 16;
             for (int mt = 0; mt < MT; ++mt) {
                 const int i = 16 * mt + i_in;
                 for (int ks = 0; ks < KSV; ++ks) {
                     const int a = ks / NJ, j = 4 * (ks % NJ) + k_in;  // axis-major K order
-                    float v = 0.f;
-                    if (i < NP && j < NP) v = (float)D[(a * NP + i) * NP + j];
+                    double v = 0.0;
+                    if (i < NP && j < NP) v = D[(a * NP + i) * NP + j];
                     fr[(mt * KSV + ks) * 64 + l] = v;
                 }
                 for (int f = 0; f < 4; ++f)
                     for (int ks = 0; ks < KSF; ++ks) {
                         const int k = 4 * ks + k_in;
-                        float v = 0.f;
-                        if (i < NP && k < NFP) v = (float)LIFT[i * 4 * NFP + f * NFP + k];
+                        double v = 0.0;
+                        if (i < NP && k < NFP) v = LIFT[i * 4 * NFP + f * NFP + k];
                         fr[(MT * KSV + (f * MT + mt) * KSF + ks) * 64 + l] = v;
                     }
             }
         }
-        CMCG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(gFrag), fr.data(), fr.size() * sizeof(float),
+        // FP32 fragments are the rounded FP64 ones
+        std::vector<float> fr32(fr.begin(), fr.end());
+        CMCG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(gFrag), fr32.data(), fr32.size() * sizeof(float),
                                    frag_off(q) * sizeof(float), hipMemcpyHostToDevice));
+        CMCG_HIP(hipMemcpyToSymbol(HIP_SYMBOL(gFrag64), fr.data(), fr.size() * sizeof(double),
+                                   frag_off(q) * sizeof(double), hipMemcpyHostToDevice));
     }
 }
 
@@ -1458,6 +1545,14 @@ void launch_filter_add(int precision, const void* U, double wr, double wi, doubl
 }
 
 int dot_partials() { return kDotBlocks; }
+
+void launch_mfma_probe(int precision, const double* A, const double* B, double* D, hipStream_t s) {
+    if (precision == CMCG_FP64)
+        hipLaunchKernelGGL(k_mfma_probe<double>, dim3(1), dim3(64), 0, s, A, B, D);
+    else
+        hipLaunchKernelGGL(k_mfma_probe<float>, dim3(1), dim3(64), 0, s, A, B, D);
+    check_launch();
+}
 
 void set_stage_variant(int q, int precision, int variant) { g_variant[q][precision] = variant; }
 int get_stage_variant(int q, int precision) { return g_variant[q][precision]; }

@@ -79,10 +79,13 @@ void launch_source_mask(int precision, int Np, const void* Sre, const void* Sim,
 void upload_constants(int q, int precision, const double* D, const double* LIFT, const double* M,
                       const int* fnode, const int* fperm);
 void launch_stage(int q, int precision, const StageArgs& a, hipStream_t s);
+// D[16][16] = A[16][4] B[4][16] on one matrix-core instruction of the field
+// precision, through the lane layout the stage kernels use (FP64 in and out).
+void launch_mfma_probe(int precision, const double* A, const double* B, double* D, hipStream_t s);
 void set_stage_variant(int q, int precision, int variant);
 int get_stage_variant(int q, int precision);
-constexpr int kStageVariants = CMCG_STAGE_VARIANTS;  // 2, 3: matrix cores (FP32, q >= 2; 3 gathers one face
-                                                     // ahead); 4: as 3 with two waves per block (FP32, q >= 2)
+constexpr int kStageVariants = CMCG_STAGE_VARIANTS;  // 2, 3: matrix cores (q >= 2; 3 gathers one face
+                                                     // ahead); 4: as 3 with two waves per block (q >= 2)
 
 // FP64 <-> field precision; flipH negates the magnetic rows (the S of P* = S P S).
 // FP32: Ulo (nullable) receives / contributes the bfloat16 low part.

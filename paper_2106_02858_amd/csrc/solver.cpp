@@ -639,7 +639,8 @@ std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int64_t, int>, int> g_tuned;
 
 bool variant_applies(int q, int precision, int v) {
-    return v <= 1 || (precision == CMCG_FP32 && q >= 2);
+    (void)precision;  // the matrix-core variants exist in both field precisions
+    return v <= 1 || q >= 2;
 }
 
 struct EventPair {
@@ -1467,6 +1468,16 @@ int cmcg_debug_dot_noalloc(const cmcg_problem* p, const double* u, const double*
         launch_dot2d(s.q, u, v, p->wE.as<double>(), p->wH.as<double>(), s.K, partial, out_dev, stream);
     else
         launch_dot(s.q, u, v, p->wE.as<double>(), p->wH.as<double>(), s.K, partial, out_dev, stream);
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_debug_mfma(int precision, const double* a, const double* b, double* d, hipStream_t stream) {
+    CMCG_GUARD_BEGIN
+    if (!a || !b || !d) fail(CMCG_ERR_ARG, "debug_mfma: NULL argument");
+    if (precision != CMCG_FP64 && precision != CMCG_FP32) fail(CMCG_ERR_ARG, "debug_mfma: unknown precision");
+    launch_mfma_probe(precision, a, b, d, stream);
+    CMCG_HIP(hipStreamSynchronize(stream));
     return CMCG_OK;
     CMCG_GUARD_END
 }

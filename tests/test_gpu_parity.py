@@ -44,10 +44,10 @@ def variant(lib, request):
     lib.cmcg_tune_stage(q, prec, old)
 
 
-# 0, 1 run everywhere; the matrix-core variants 2, 3, 4 (4: two waves per block) exist for
-# FP32 fields at q >= 2
+# 0, 1 run everywhere; the matrix-core variants 2, 3, 4 (4: two waves per block) exist at
+# q >= 2 in both field precisions (FP64 on v_mfma_f64_16x16x4f64)
 VARIANTS = [(q, p, v) for q in (1, 2, 3) for p in (0, 1) for v in (0, 1)] + \
-    [(q, 1, v) for q in (2, 3) for v in (2, 3, 4)]
+    [(q, p, v) for q in (2, 3) for p in (0, 1) for v in (2, 3, 4)]
 
 
 @pytest.mark.parametrize("variant", VARIANTS, indirect=True, ids=lambda t: f"q{t[0]}-p{t[1]}-v{t[2]}")
