@@ -114,7 +114,9 @@ def measured_traffic(kernel: str, K: int, table=None, source: str = "kernels.hip
 # single-frequency instantiations (the MH template argument selects the several-frequency code)
 STAGE_KERNEL = {0: "k_stage<float,{q},false,false>", 1: "k_stage<float,{q},true,false>",
                 2: "k_stage_mfma<float,{q},false,false,1>", 3: "k_stage_mfma<float,{q},true,false,1>",
-                4: "k_stage_mfma<float,{q},true,false,2>"}
+                4: "k_stage_mfma<float,{q},true,false,2>", 5: "k_stage_mfma<float,{q},true,false,2,true>",
+                6: "k_stage_mfma<float,{q},true,false,2,false,true>",
+                7: "k_stage_mfma<float,{q},true,false,2,true,true>"}
 STAGE_KERNEL64 = {v: k.replace("float", "double") for v, k in STAGE_KERNEL.items()}
 
 

@@ -429,10 +429,14 @@ int cmcg_engine_info(const cmcg_engine* e, size_t* used, int* n_running, int* n_
  * v_mfma_f32_16x16x4f32, FP64 fields on v_mfma_f64_16x16x4f64; q = 1 falls
  * back to 0), 3 is 2 with the neighbour traces requested one face ahead, 4
  * is 3 with two waves per 10-element block, each computing half of the
- * output tiles (q = 2, 3).  All compute the same Phi(t, Y) and stage update.  Process-wide;
+ * output tiles (q = 2, 3), 5 is 4 with the neighbour traces of all four
+ * faces requested at once and two alternating flux tiles (q = 2, 3), 6 is 4
+ * with the two waves splitting the output by column tiles instead of row
+ * tiles (q = 3), 7 combines 5 and 6 (q = 3); variants that do not exist for
+ * (q, precision) fall back to 0.  All compute the same Phi(t, Y) and stage update.  Process-wide;
  * not thread-safe against concurrent solves.  Returns CMCG_ERR_ARG for an unknown q / precision /
  * variant.  cmcg_tune_get_stage reports the current choice. */
-#define CMCG_STAGE_VARIANTS 5
+#define CMCG_STAGE_VARIANTS 8
 int cmcg_tune_stage(int q, int precision, int variant);
 int cmcg_tune_get_stage(int q, int precision, int* variant);
 

@@ -657,14 +657,14 @@ template <> struct Mfma<double> {
     static __device__ __forceinline__ int row(int q4, int r) { return 4 * r + q4; }
 };
 
-template <typename T, int Q>
+template <typename T, int Q, int NB = 1>
 struct MfmaShared {
     static constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP;
     static constexpr int RS = NP + 1;
     static constexpr int KF = 4 * MfmaDim<Q>::KSF;
     static constexpr int FS = 65;  // flux tile row stride: the face nodes of one column fall in different banks
     T sY[EPW * 6 * RS];       // stage input, rows (element, component) padded to NP + 1
-    T sF[KF * FS];            // flux tile [face node][column], rows >= NFP stay zero
+    T sF[NB * KF * FS];       // NB flux tiles [face node][column], rows >= NFP stay zero
     T sG[EPW * kGeo];         // geometry of the chunk
     int sC[EPW * 4];          // connectivity codes of the chunk
     uint8_t sT[4 * ft_words(Q)];  // own face nodes [f][k], then neighbour face nodes [nf][perm][k]
@@ -716,9 +716,16 @@ template <typename T, int Q, int NTH = 64> struct MfmaUpdateIn {
 // before the last face) was measured slower: the registers cost occupancy
 // (P2) or spill (P3).  T = double runs the same data flow on
 // v_mfma_f64_16x16x4f64 with FP64 fields (no compensated state).
-template <typename T, int Q, bool PIPE, bool MH, int W>
+// EAGER: the neighbour traces of all four faces are requested right after
+// the staging (four faces' loads in flight during the volume product instead
+// of one), and faces alternate between two flux tiles, so a face needs one
+// barrier instead of two.  CSPLIT (P3, two waves): the waves split the output
+// by column tiles, each building only its own B operands and running both
+// row tiles.
+template <typename T, int Q, bool PIPE, bool MH, int W, bool EAGER = false, bool CSPLIT = false>
 __global__ __launch_bounds__(64 * W)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (W == 1 ? 4 : 6) : (W == 1 ? 2 : 3), 8)))
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (W == 1 || (EAGER && Q == 3) ? 4 : (EAGER || CSPLIT ? 5 : 6))
+                                                   : (W == 1 || EAGER || CSPLIT ? 2 : 3), 8)))
 void k_stage_mfma(StageArgs args, int64_t per) {
     using MD = MfmaDim<Q>;
     using acc_t = typename Mfma<T>::acc_t;
@@ -729,12 +736,14 @@ void k_stage_mfma(StageArgs args, int64_t per) {
     constexpr int NTH = 64 * W;                      // threads of the workgroup
     constexpr int RF = (EPW * NFP + NTH - 1) / NTH;  // flux items per thread and face
     // two waves split the output tiles: by rows when there are two row tiles
-    // (P3), by the four 16-column tiles otherwise (P2)
-    constexpr bool ROWS = W == 2 && MT == 2, COLS = W == 2 && MT == 1;
+    // (P3, unless CSPLIT), by the four 16-column tiles otherwise
+    constexpr bool ROWS = W == 2 && MT == 2 && !CSPLIT, COLS = W == 2 && (MT == 1 || CSPLIT);
+    constexpr int NB = EAGER ? 2 : 1;  // flux tiles
+    using Sh = MfmaShared<T, Q, NB>;
     constexpr int MW = ROWS ? 1 : MT;   // output row tiles of one wave
     constexpr int NW = COLS ? 2 : 4;    // output column tiles of one wave
     static_assert(W == 1 || ((ROWS || COLS) && RF == 1), "two waves per block need one flux item per thread");
-    __shared__ MfmaShared<T, Q> sh;
+    __shared__ Sh sh;
 
     StageArgs a;
     if (!member_args<T>(args, a)) return;  // uniform per workgroup
@@ -755,7 +764,7 @@ void k_stage_mfma(StageArgs args, int64_t per) {
     {
         ChunkIn<T, Q, NTH> in;
         in.fetch(Y, (const T*)a.geo, a.conn, e0, ne, tid);
-        for (int v = tid; v < KF * MfmaShared<T, Q>::FS; v += NTH) sh.sF[v] = T(0);
+        for (int v = tid; v < NB * KF * Sh::FS; v += NTH) sh.sF[v] = T(0);
         in.put(sh.sY, sh.sG, sh.sC, sh.sT, ne, tid);
     }
 
@@ -776,11 +785,17 @@ void k_stage_mfma(StageArgs args, int64_t per) {
     lift_frags(0, afL);
     __syncthreads();
 
-    // face 0's neighbour traces in flight during the volume product
+    // face 0's neighbour traces (EAGER: every face's) in flight during the volume product
     FluxItems<Q, RF> itm;
     itm.init(ne, tid);
     TraceGather<T, Q, RF> cur, nxt;
-    cur.issue(Y, sh.sC, sh.sT, itm, 0, e0, ne);
+    TraceGather<T, Q, RF> all[EAGER ? 4 : 1];
+    if constexpr (EAGER) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) all[f].issue(Y, sh.sC, sh.sT, itm, f, e0, ne);
+    } else {
+        cur.issue(Y, sh.sC, sh.sT, itm, 0, e0, ne);
+    }
 
     const int q4 = lane >> 4;   // K row within a 4-row block / output row group
     const int l16 = lane & 15;  // output column within a 16-column tile
@@ -833,8 +848,10 @@ void k_stage_mfma(StageArgs args, int64_t per) {
     // ---- upwind flux and lift, one face at a time
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-        if (PIPE && f < 3) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1, e0, ne);
+        if (!EAGER && PIPE && f < 3) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1, e0, ne);
         if (f < 3) lift_frags(f + 1, afN);
+        T* tile = sh.sF + (EAGER ? (f & 1) * KF * Sh::FS : 0);
+        const TraceGather<T, Q, RF>& gat = EAGER ? all[f] : cur;
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
             if (!itm.on[r]) continue;
@@ -847,9 +864,9 @@ void k_stage_mfma(StageArgs args, int64_t per) {
                 Em[cc] = sh.sY[(fe * 6 + cc) * RS + own];
                 Hm[cc] = sh.sY[(fe * 6 + 3 + cc) * RS + own];
             }
-            const int code = cur.code[r];
+            const int code = gat.code[r];
             if (code >= 0) {
-                cur.values(sh.sY, r, Ep, Hp);
+                gat.values(sh.sY, r, Ep, Hp);
             } else if (code == -1) {  // PEC ghost: E+ = -E-, H+ = H-
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc) {
@@ -872,7 +889,7 @@ void k_stage_mfma(StageArgs args, int64_t per) {
             const T ndH = n0 * dH0 + n1 * dH1 + n2 * dH2;
             const T xH0 = n1 * dH2 - n2 * dH1, xH1 = n2 * dH0 - n0 * dH2, xH2 = n0 * dH1 - n1 * dH0;
             const T xE0 = n1 * dE2 - n2 * dE1, xE1 = n2 * dE0 - n0 * dE2, xE2 = n0 * dE1 - n1 * dE0;
-            T* o = &sh.sF[k * MfmaShared<T, Q>::FS + fe * 6];
+            T* o = &tile[k * Sh::FS + fe * 6];
             o[0] = cE1 * (dE0 - ndE * n0) - cE2 * xH0;
             o[1] = cE1 * (dE1 - ndE * n1) - cE2 * xH1;
             o[2] = cE1 * (dE2 - ndE * n2) - cE2 * xH2;
@@ -885,17 +902,22 @@ void k_stage_mfma(StageArgs args, int64_t per) {
         for (int ks = 0; ks < KSF; ++ks) {
             T b[NW];
 #pragma unroll
-            for (int nt = 0; nt < NW; ++nt) b[nt] = sh.sF[(ks * 4 + q4) * MfmaShared<T, Q>::FS + (nt + nt0) * 16 + l16];
+            for (int nt = 0; nt < NW; ++nt) b[nt] = tile[(ks * 4 + q4) * Sh::FS + (nt + nt0) * 16 + l16];
 #pragma unroll
             for (int nt = 0; nt < NW; ++nt)
 #pragma unroll
                 for (int mt = 0; mt < MW; ++mt)
                     acc[mt][nt] = Mfma<T>::mma(afL[mt][ks], b[nt], acc[mt][nt]);
         }
-        __syncthreads();  // the tile is rewritten by the next face
+        // one tile: it is rewritten by the next face; two tiles: the next face
+        // writes the other one, and the face after it only once every thread
+        // has passed the next face's barrier (so has finished this lift)
+        if (!EAGER) __syncthreads();
         if (f < 3) {
-            if (!PIPE) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1, e0, ne);
-            cur = nxt;
+            if (!EAGER) {
+                if (!PIPE) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1, e0, ne);
+                cur = nxt;
+            }
 #pragma unroll
             for (int mt = 0; mt < MW; ++mt)
 #pragma unroll
@@ -1340,6 +1362,20 @@ void stage_launch_mh(const StageArgs& a, hipStream_t s) {
         if (v == 4) {
             hipLaunchKernelGGL((k_stage_mfma<T, Q, true, MH, 2>), grid, dim3(128), 0, s, a, per);
             return;
+        }
+        if (v == 5) {
+            hipLaunchKernelGGL((k_stage_mfma<T, Q, true, MH, 2, true>), grid, dim3(128), 0, s, a, per);
+            return;
+        }
+        if constexpr (Q == 3) {
+            if (v == 6) {
+                hipLaunchKernelGGL((k_stage_mfma<T, Q, true, MH, 2, false, true>), grid, dim3(128), 0, s, a, per);
+                return;
+            }
+            if (v == 7) {
+                hipLaunchKernelGGL((k_stage_mfma<T, Q, true, MH, 2, true, true>), grid, dim3(128), 0, s, a, per);
+                return;
+            }
         }
     }
     if (v == 1)
