@@ -30,30 +30,47 @@ class Result:
 
 
 class Operators:
-    """P, P*, P_psi for one problem and time discretisation."""
+    """P, P*, P_psi for one problem and time discretisation.  lts = m > 1
+    uses local time stepping (oracle.lts) with m substeps on the fine
+    elements; M then counts coarse steps."""
 
     def __init__(self, p: dg.Problem, M: int | None = None, scheme: int | None = None,
-                 cfl: float | None = None):
+                 cfl: float | None = None, lts: int = 1):
         self.p = p
         self.scheme = timestep.default_scheme(p.geo.q) if scheme is None else scheme
-        self.M = timestep.n_steps(p, cfl) if M is None else M
+        self.lts = lts
+        if lts > 1:
+            from . import lts as olts
+            M_lts, self.fine = olts.lts_steps(p, lts, cfl)
+            self.M = M_lts if M is None else M
+        else:
+            self.M = timestep.n_steps(p, cfl) if M is None else M
         self.periods = 0
+
+    def _fwd(self, U, src, filt=False):
+        if self.lts > 1:
+            from . import lts as olts
+            return olts.forward(self.p, U, self.M, self.lts, self.fine, self.scheme, src, filt=filt)
+        return timestep.forward(self.p, U, self.M, self.scheme, src, filt=filt)
 
     def P(self, U):
         self.periods += 1
-        return timestep.forward(self.p, U, self.M, self.scheme, False)
+        return self._fwd(U, False)
 
     def P_psi(self, U):
         self.periods += 1
-        return timestep.forward(self.p, U, self.M, self.scheme, True)
+        return self._fwd(U, True)
 
     def P_star(self, W):
         self.periods += 1
+        if self.lts > 1:
+            from . import lts as olts
+            return olts.backward(self.p, W, self.M, self.lts, self.fine, self.scheme)
         return timestep.backward(self.p, W, self.M, self.scheme)
 
     def filtered(self, U):
         self.periods += 1
-        return timestep.forward(self.p, U, self.M, self.scheme, True, filt=True)[1]
+        return self._fwd(U, True, filt=True)[1]
 
     def ip(self, U, V):
         return float(timestep.ops_of(self.p).inner(self.p, U, V))
@@ -90,14 +107,17 @@ def functional(ops: Operators, U0, G):
 
 
 def solve(p: dg.Problem, tol: float = 1e-8, max_iter: int = 1000, u0=None, M=None,
-          scheme=None, fixed_iters: int | None = None, cfl=None, filt: bool = True, runup: int = 0) -> Result:
+          scheme=None, fixed_iters: int | None = None, cfl=None, filt: bool = True, runup: int = 0,
+          lts: int = 1) -> Result:
     """Algorithm 3.  Stops when ||R_l|| <= tol ||R_0|| or after ``fixed_iters``
     iterations when that is given (used for parity at a fixed count).
 
     ``runup`` > 0: the run-up phase Section 6 mentions as an accelerator --
     that many limiting-amplitude periods U <- P_psi U from the initial guess
-    (zero or u0) before the first residual; CG then starts from their state."""
-    ops = Operators(p, M, scheme, cfl)
+    (zero or u0) before the first residual; CG then starts from their state.
+    ``lts`` = m > 1: local time stepping with m fine substeps (oracle.lts);
+    the backward periods are the exact adjoint of the LTS forward period."""
+    ops = Operators(p, M, scheme, cfl, lts)
     G, Gstar = initialise(ops)
     U = np.zeros((p.K, p.ncomp, p.Np)) if u0 is None else np.array(u0, dtype=np.float64).reshape(p.K, p.ncomp, p.Np)
     for _ in range(runup):

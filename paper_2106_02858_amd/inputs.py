@@ -67,6 +67,62 @@ def cube_mesh(n: int, boundary_tag: int = TAG_IMPEDANCE):
     return xyz, tet, tags
 
 
+def graded_cube_mesh(xs, ys, zs, boundary_tag: int = TAG_IMPEDANCE):
+    """Kuhn split of the tensor-product grid xs x ys x zs (increasing vertex
+    coordinates per axis) into 6 (len(xs)-1)(len(ys)-1)(len(zs)-1) tetrahedra,
+    cells and tetrahedra numbered as in cube_mesh.  A grid with a few narrow
+    cells is a conforming, locally refined mesh (the narrow cells' elements
+    have small insphere diameters).  Returns (xyz, tet, face_tag)."""
+    xs, ys, zs = (np.asarray(a, dtype=np.float64) for a in (xs, ys, zs))
+    if min(len(xs), len(ys), len(zs)) < 2 or any(np.any(np.diff(a) <= 0) for a in (xs, ys, zs)):
+        raise ValueError("coordinates must be increasing, at least two per axis")
+    nx, ny, nz = len(xs) - 1, len(ys) - 1, len(zs) - 1
+    ii, jj, kk = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij")
+    lat = np.stack([ii.transpose(2, 1, 0).ravel(), jj.transpose(2, 1, 0).ravel(),
+                    kk.transpose(2, 1, 0).ravel()], axis=1)
+    xyz = np.stack([xs[lat[:, 0]], ys[lat[:, 1]], zs[lat[:, 2]]], axis=1)
+
+    def vid(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    ci, cj, ck = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    ci, cj, ck = (a.transpose(2, 1, 0).ravel() for a in (ci, cj, ck))
+    ncube = nx * ny * nz
+    tet = np.empty((ncube, 6, 4), dtype=np.int64)
+    for p, perm in enumerate(_PERMS):
+        off = np.zeros((ncube, 3), dtype=np.int64)
+        corners = [off.copy()]
+        for ax in perm:
+            off = off.copy()
+            off[:, ax] += 1
+            corners.append(off)
+        for v in range(4):
+            tet[:, p, v] = vid(ci + corners[v][:, 0], cj + corners[v][:, 1], ck + corners[v][:, 2])
+    tet = tet.reshape(-1, 4)
+    K = tet.shape[0]
+    tags = np.zeros((K, 4), dtype=np.int8)
+    ext = np.array([nx, ny, nz])
+    for f in range(4):
+        pts = lat[tet[:, [v for v in range(4) if v != f]]]
+        on = np.zeros(K, dtype=bool)
+        for ax in range(3):
+            c = pts[:, :, ax]
+            on |= np.all(c == 0, axis=1) | np.all(c == ext[ax], axis=1)
+        tags[on, f] = boundary_tag
+    return xyz, tet, tags
+
+
+def refined_cube_mesh(n: int, r: int, boundary_tag: int = TAG_IMPEDANCE):
+    """[0,1]^3 with n uniform cells per axis, the middle cell of every axis
+    split into r: a small central region of cells r times finer (and slabs of
+    thin elements through it), the rest at spacing 1/n."""
+    if n < 1 or r < 1:
+        raise ValueError("n, r must be >= 1")
+    c = n // 2
+    axis = np.concatenate([np.arange(c) / n, (c + np.arange(r) / r) / n, np.arange(c + 1, n + 1) / n])
+    return graded_cube_mesh(axis, axis, axis, boundary_tag)
+
+
 def boundary_tags(lat: np.ndarray, tet: np.ndarray, n: int, boundary_tag: int) -> np.ndarray:
     """Tag faces whose three vertices lie on one side of the cube's boundary."""
     K = tet.shape[0]
