@@ -123,11 +123,24 @@ typedef struct cmcg_options {
      * serving engine ignores it (slots run concurrently; tune beforehand).
      * 0 = keep the current choice. */
     int autotune;
+    /* Local time stepping for locally refined meshes (the paper's concluding
+     * remarks), 2..64: every period is M coarse steps of H = T / M, where M is
+     * the smallest count with H / lts_ratio no longer than the smallest
+     * element's CFL step (o->steps forces M); elements whose own CFL step
+     * c_q sqrt(mu eps) rho is shorter than H are fine and take lts_ratio
+     * substeps of the base scheme (RK2 / RK4) per coarse step, the others
+     * enter through the Taylor polynomial of the solution at the coarse step's
+     * start (Runge-Kutta-based local time stepping).  Backward periods are
+     * the exact adjoint of that propagator, so CMCG's gradient stays exact.
+     * Fields stay in the space's precision without the compensated FP32
+     * state; periods run without graph capture.  Tetrahedral spaces, single
+     * frequency; not accepted by cmcg_solve_batch.  0 or 1 = global steps. */
+    int lts_ratio;
 } cmcg_options;
 
 /* Fills *o with defaults: tol 1e-8, max_iter 1000, fixed_iters 0, cfl 0,
  * steps 0, scheme AUTO, flux UPWIND, use_graph 1, residual_refresh 0,
- * progress NULL, runup 0, autotune 0. */
+ * progress NULL, runup 0, autotune 0, lts_ratio 0. */
 void cmcg_options_default(cmcg_options* o);
 
 /* Solve statistics. */
@@ -260,8 +273,12 @@ int cmcg_problem_create_harmonics(const cmcg_space* s, const double* eps, const 
                                   const double* j_re, const double* j_im, cmcg_problem** out);
 void cmcg_problem_destroy(cmcg_problem* p);
 /* Time steps per period M and dt = T / M that `o` selects for this problem
- * (CFL rule of Section 5.3). */
+ * (CFL rule of Section 5.3; with o->lts_ratio > 1 the coarse steps). */
 int cmcg_problem_steps(const cmcg_problem* p, const cmcg_options* o, int* M, double* dt);
+/* Elements that local time stepping with `o` (o->lts_ratio > 1) treats as
+ * fine; fine[K] (host, nullable) receives 1 / 0 per element, *n_fine the
+ * count.  CMCG_ERR_ARG when o asks for no local time stepping. */
+int cmcg_problem_lts_fine(const cmcg_problem* p, const cmcg_options* o, int8_t* fine, int64_t* n_fine);
 
 /* ---------------------------------------------------------------- solve -- */
 /* Algorithm 3 from the zero initial guess (or `u0_dev`, a device dof vector

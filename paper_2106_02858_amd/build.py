@@ -20,7 +20,8 @@ LIB = os.path.join(HERE, "libcmcg.so")
 # 3-D solve and the 2-D transverse-magnetic solve
 C_DEMOS = [os.path.join(ROOT, "tests", "c_abi", name) for name in ("solve_demo", "solve_demo2d")]
 
-SOURCES = ["refelem.cpp", "mesh.cpp", "solver.cpp", "batch.cpp", "engine.cpp", "kernels.hip", "kernels2d.hip"]
+SOURCES = ["refelem.cpp", "mesh.cpp", "solver.cpp", "batch.cpp", "engine.cpp", "lts.cpp", "kernels.hip",
+           "kernels2d.hip"]
 ARCH = os.environ.get("CMCG_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{os.path.join(ROOT, 'include')}"]

@@ -48,7 +48,7 @@ EXPORTED = [
     "cmcg_last_error", "cmcg_version", "cmcg_options_default",
     "cmcg_mesh_create", "cmcg_mesh2d_create", "cmcg_mesh_dim", "cmcg_mesh_destroy", "cmcg_mesh_info",
     "cmcg_space_create", "cmcg_space_destroy", "cmcg_space_info", "cmcg_space_nodes",
-    "cmcg_problem_create", "cmcg_problem_create_device", "cmcg_problem_destroy", "cmcg_problem_steps",
+    "cmcg_problem_create", "cmcg_problem_create_device", "cmcg_problem_destroy", "cmcg_problem_steps", "cmcg_problem_lts_fine",
     "cmcg_problem_create_harmonics", "cmcg_result_harmonics", "cmcg_result_filtered_harmonic_device",
     "cmcg_solve", "cmcg_fw_solve", "cmcg_solve_batch", "cmcg_result_fields", "cmcg_result_filtered_device", "cmcg_result_initial_device",
     "cmcg_result_stats", "cmcg_result_history", "cmcg_result_destroy",
@@ -66,7 +66,7 @@ class cmcg_options(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("cfl", C.c_double),
                 ("steps", C.c_int), ("scheme", C.c_int), ("flux", C.c_int), ("use_graph", C.c_int),
                 ("residual_refresh", C.c_int), ("progress", PROGRESS_FN), ("progress_ctx", C.c_void_p),
-                ("runup", C.c_int), ("autotune", C.c_int)]
+                ("runup", C.c_int), ("autotune", C.c_int), ("lts_ratio", C.c_int)]
 
     def set_progress(self, fn):
         """fn(iter, rel_res) -> bool (True stops the iteration)."""
@@ -104,6 +104,7 @@ _sig = {
     "cmcg_debug_step": (C.c_int, [P, C.POINTER(cmcg_options), C.c_int, C.c_int, C.c_int, P, P, P]),
     "cmcg_debug_dot_noalloc": (C.c_int, [P, P, P, P, P]),
     "cmcg_debug_mfma": (C.c_int, [C.c_int, P, P, P, P]),
+    "cmcg_problem_lts_fine": (C.c_int, [P, C.POINTER(cmcg_options), P, C.POINTER(C.c_int64)]),
     "cmcg_problem_destroy": (None, [P]),
     "cmcg_problem_steps": (C.c_int, [P, C.POINTER(cmcg_options), C.POINTER(C.c_int), D]),
     "cmcg_solve": (C.c_int, [P, C.POINTER(cmcg_options), P, P, C.POINTER(P)]),
@@ -321,6 +322,14 @@ def cmcg_problem_create_device(s: Space, eps, mu, sigma, omega, j_re_dev, j_im_d
                                            _ptr(j_im_dev), _ptr(g_re_dev), _ptr(g_im_dev), _stream(stream),
                                            C.byref(h)))
     return Problem(h, keep=(s,))
+
+
+def cmcg_problem_lts_fine(p: Problem, K: int, opts: cmcg_options):
+    """Boolean [K]: the elements local time stepping with `opts` treats as fine."""
+    f = np.zeros(K, dtype=np.int8)
+    nf = C.c_int64()
+    _check(_lib.cmcg_problem_lts_fine(p.h, C.byref(opts), _ptr(f), C.byref(nf)))
+    return f.astype(bool)
 
 
 def cmcg_problem_steps(p: Problem, opts: cmcg_options | None = None):

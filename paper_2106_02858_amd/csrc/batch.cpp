@@ -304,6 +304,7 @@ void setup_batch(Batch& bt, cmcg_problem* const* probs, int B, const cmcg_option
     bt.sp = probs[0] ? probs[0]->sp : nullptr;
     if (!bt.sp) fail(CMCG_ERR_ARG, "solve_batch: NULL problem");
     if (o->runup < 0) fail(CMCG_ERR_ARG, "options: runup must be >= 0");
+    if (o->lts_ratio > 1) fail(CMCG_ERR_ARG, "solve_batch: local time stepping is for single solves");
     for (int b = 0; b < B; ++b) {
         if (!probs[b]) fail(CMCG_ERR_ARG, "solve_batch: NULL problem");
         if (probs[b]->sp != bt.sp) fail(CMCG_ERR_ARG, "solve_batch: all problems must share one space");

@@ -216,7 +216,9 @@ template <typename T, int Q, int NTH = 64> struct ChunkIn {
             if (lane + NTH * i < ne * kGeo / PV) g[i] = G4[lane + NTH * i];
         cd = lane < ne * 4 ? conn[e0 * 4 + lane] : -3;
     }
-    __device__ __forceinline__ void put(T* sY, T* sG, int* sC, uint8_t* sT, int ne, int lane) const {
+    // keep: bit e clear stages element e's input as zero (an input mask, B P y)
+    __device__ __forceinline__ void put(T* sY, T* sG, int* sC, uint8_t* sT, int ne, int lane,
+                                        uint32_t keep = 0xffffffffu) const {
         uint32_t* sT4 = reinterpret_cast<uint32_t*>(sT);
 #pragma unroll
         for (int i = 0; i < NT; ++i)
@@ -229,7 +231,7 @@ template <typename T, int Q, int NTH = 64> struct ChunkIn {
 #pragma unroll
                 for (int u = 0; u < PV; ++u) {
                     const int v = PV * g4 + u;
-                    sY[v + v / NP] = t[u];
+                    sY[v + v / NP] = ((keep >> (v / (6 * NP))) & 1u) ? t[u] : T(0);
                 }
             }
         }
@@ -274,8 +276,11 @@ template <typename T, int Q, int RF> struct TraceGather {
     static constexpr int RS = Dim<Q>::NP + 1;  // staged row stride
     T v[RF][6];
     int code[RF], loc[RF];
+    // imask (nullable): input mask, one word per element block; a neighbour
+    // whose bit (xor inv) is clear contributes a zero trace
     __device__ __forceinline__ void issue(const T* __restrict__ Y, const int* sC, const uint8_t* sT,
-                                          const FluxItems<Q, RF>& itm, int f, int64_t e0, int ne) {
+                                          const FluxItems<Q, RF>& itm, int f, int64_t e0, int ne,
+                                          const uint32_t* __restrict__ imask = nullptr, int inv = 0) {
         constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP;
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
@@ -290,6 +295,9 @@ template <typename T, int Q, int RF> struct TraceGather {
                     const int64_t d = nb - e0;
                     if (d >= 0 && d < ne) {
                         loc[r] = (int)d * 6 * RS + nn;
+                    } else if (imask && !(((imask[nb / EPW] >> (int)(nb % EPW)) & 1u) ^ (uint32_t)inv)) {
+#pragma unroll
+                        for (int cc = 0; cc < 6; ++cc) v[r][cc] = T(0);
                     } else {
                         const T* q = Y + nb * 6 * NP + nn;
 #pragma unroll
@@ -359,17 +367,18 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     const bool needU = mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || needL;
     const bool needA = mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4;
 
+    const uint32_t keep = a.imask ? (a.imask[blk] ^ (a.imask_inv ? 0xffffffffu : 0u)) : 0xffffffffu;
     {
         ChunkIn<T, Q> in;
         in.fetch(Y, (const T*)a.geo, a.conn, e0, ne, lane);
-        in.put(sY, sG, sC, sT, ne, lane);
+        in.put(sY, sG, sC, sT, ne, lane, keep);
     }
     __syncthreads();
     // neighbour traces of face 0 in flight during the volume work
     FluxItems<Q, RF> itm;
     itm.init(ne, lane);
     TraceGather<T, Q, RF> cur, nxt;
-    if (PIPE) cur.issue(Y, sC, sT, itm, 0, e0, ne);
+    if (PIPE) cur.issue(Y, sC, sT, itm, 0, e0, ne, a.imask, a.imask_inv);
 
     // ---- volume term: D_a y per column, curl terms exchanged between lanes
     T y[NP];
@@ -419,7 +428,7 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     for (int f = 0; f < 4; ++f) {
         if (PIPE) {
             if (f < 3) {
-                nxt.issue(Y, sC, sT, itm, f + 1, e0, ne);
+                nxt.issue(Y, sC, sT, itm, f + 1, e0, ne, a.imask, a.imask_inv);
             } else if (act) {
                 if (needU) Row<T, NP>::load((const T*)a.U + grow, up);
                 if (needA) Row<T, NP>::load((const T*)a.Acc + grow, ap);
@@ -427,7 +436,7 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
                     if (needL) RowH<NP>::load((const uint16_t*)a.Ulo + grow, lo);
             }
         } else {
-            cur.issue(Y, sC, sT, itm, f, e0, ne);
+            cur.issue(Y, sC, sT, itm, f, e0, ne, a.imask, a.imask_inv);
         }
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
@@ -761,11 +770,12 @@ void k_stage_mfma(StageArgs args, int64_t per) {
     const int nvv = ne * 6 * NP / PV;        // 16-byte groups of the chunk (6 NP ne is a multiple of 4)
 
     // ---- staging: chunk fields, geometry, connectivity, face-node tables
+    const uint32_t keep = a.imask ? (a.imask[blk] ^ (a.imask_inv ? 0xffffffffu : 0u)) : 0xffffffffu;
     {
         ChunkIn<T, Q, NTH> in;
         in.fetch(Y, (const T*)a.geo, a.conn, e0, ne, tid);
         for (int v = tid; v < NB * KF * Sh::FS; v += NTH) sh.sF[v] = T(0);
-        in.put(sh.sY, sh.sG, sh.sC, sh.sT, ne, tid);
+        in.put(sh.sY, sh.sG, sh.sC, sh.sT, ne, tid, keep);
     }
 
     // matrix fragments (coalesced: fragment-major, lane-minor)
@@ -792,9 +802,9 @@ void k_stage_mfma(StageArgs args, int64_t per) {
     TraceGather<T, Q, RF> all[EAGER ? 4 : 1];
     if constexpr (EAGER) {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) all[f].issue(Y, sh.sC, sh.sT, itm, f, e0, ne);
+        for (int f = 0; f < 4; ++f) all[f].issue(Y, sh.sC, sh.sT, itm, f, e0, ne, a.imask, a.imask_inv);
     } else {
-        cur.issue(Y, sh.sC, sh.sT, itm, 0, e0, ne);
+        cur.issue(Y, sh.sC, sh.sT, itm, 0, e0, ne, a.imask, a.imask_inv);
     }
 
     const int q4 = lane >> 4;   // K row within a 4-row block / output row group
@@ -848,7 +858,7 @@ void k_stage_mfma(StageArgs args, int64_t per) {
     // ---- upwind flux and lift, one face at a time
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-        if (!EAGER && PIPE && f < 3) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1, e0, ne);
+        if (!EAGER && PIPE && f < 3) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1, e0, ne, a.imask, a.imask_inv);
         if (f < 3) lift_frags(f + 1, afN);
         T* tile = sh.sF + (EAGER ? (f & 1) * KF * Sh::FS : 0);
         const TraceGather<T, Q, RF>& gat = EAGER ? all[f] : cur;
@@ -915,7 +925,7 @@ void k_stage_mfma(StageArgs args, int64_t per) {
         if (!EAGER) __syncthreads();
         if (f < 3) {
             if (!EAGER) {
-                if (!PIPE) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1, e0, ne);
+                if (!PIPE) nxt.issue(Y, sh.sC, sh.sT, itm, f + 1, e0, ne, a.imask, a.imask_inv);
                 cur = nxt;
             }
 #pragma unroll
@@ -1171,6 +1181,62 @@ __global__ __launch_bounds__(64) void k_source_mask(const T* Sre, const T* Sim, 
         }
     for (int o = 32; o > 0; o >>= 1) bits |= (uint32_t)__shfl_xor((int)bits, o, 64);
     if (threadIdx.x == 0) mask[blk] = bits;
+}
+
+// ---- local time stepping: elementwise combinations of field vectors (field
+// precision T, coefficients in FP64).  Row masks use the per-block element
+// words of the stage kernels' masks (bit e of word b: element b EPW + e).
+__device__ __forceinline__ bool lts_row_on(const uint32_t* mask, int inv, int64_t i, int np6) {
+    const int64_t e = i / np6;
+    return ((mask[e / EPW] >> (int)(e % EPW)) & 1u) ^ (uint32_t)inv;
+}
+
+// k = K + sum_{j < nw} w_j W_j;  out1 = base + e acc + c1 k;  out2 = f acc + c2 k
+// (acc nullable = 0; out1 / out2 nullable = not written; out1 may alias base,
+// out2 may alias acc)
+template <typename T>
+__global__ void k_lts_combine(int64_t n, const T* K, const T* W0, const T* W1, const T* W2, const T* W3, int nw,
+                              double w0, double w1, double w2, double w3, const T* base, const T* acc, double e,
+                              double c1, T* out1, double f, double c2, T* out2) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        T k = K[i];
+        if (nw > 0) k += (T)w0 * W0[i];
+        if (nw > 1) k += (T)w1 * W1[i];
+        if (nw > 2) k += (T)w2 * W2[i];
+        if (nw > 3) k += (T)w3 * W3[i];
+        const T ac = acc ? acc[i] : T(0);
+        if (out1) out1[i] = base[i] + (T)e * ac + (T)c1 * k;
+        if (out2) out2[i] = (T)f * ac + (T)c2 * k;
+    }
+}
+
+// Adjoint stage of the homogeneous step (S-flipped variables): A = rows of K
+// on the mask; zbar += A; knext = a0 Z0 + b0 A; wb_j += cw_j kcur (j < nw)
+template <typename T>
+__global__ void k_lts_adjoint(int64_t n, int np6, const uint32_t* mask, int inv, const T* K, T* zbar, const T* Z0,
+                              double a0, double b0, T* knext, const T* kcur, T* wb0, T* wb1, T* wb2, T* wb3, int nw,
+                              double cw0, double cw1, double cw2, double cw3) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const T kc = kcur[i];
+        if (nw > 0) wb0[i] += (T)cw0 * kc;
+        if (nw > 1) wb1[i] += (T)cw1 * kc;
+        if (nw > 2) wb2[i] += (T)cw2 * kc;
+        if (nw > 3) wb3[i] += (T)cw3 * kc;
+        const T A = lts_row_on(mask, inv, i, np6) ? K[i] : T(0);
+        zbar[i] += A;
+        if (knext) knext[i] = (T)a0 * Z0[i] + (T)b0 * A;
+    }
+}
+
+// z = a y + b rows(x), rows(x) = x on the mask's rows (all rows when mask is
+// null), 0 elsewhere; y nullable (= 0); z may alias y
+template <typename T>
+__global__ void k_lts_axpy(int64_t n, int np6, const uint32_t* mask, int inv, double a, const T* y, double b,
+                           const T* x, T* z) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const T xv = (!mask || lts_row_on(mask, inv, i, np6)) ? x[i] : T(0);
+        z[i] = (y ? (T)a * y[i] : T(0)) + (T)b * xv;
+    }
 }
 
 __global__ void k_axpby(double a, const double* x, double b, const double* y, double* z, int64_t n) {
@@ -1581,6 +1647,61 @@ void launch_filter_add(int precision, const void* U, double wr, double wi, doubl
 }
 
 int dot_partials() { return kDotBlocks; }
+
+void launch_lts_combine(int precision, int64_t n, const void* K, const void* const* W, const double* w, int nw,
+                        const void* base, const void* acc, double e, double c1, void* out1, double f, double c2,
+                        void* out2, hipStream_t s) {
+    const void* Wp[4] = {nullptr, nullptr, nullptr, nullptr};
+    double wc[4] = {0, 0, 0, 0};
+    for (int j = 0; j < nw && j < 4; ++j) {
+        Wp[j] = W[j];
+        wc[j] = w[j];
+    }
+    if (precision == CMCG_FP64)
+        hipLaunchKernelGGL(k_lts_combine<double>, dim3(grid_for(n)), dim3(256), 0, s, n, (const double*)K,
+                           (const double*)Wp[0], (const double*)Wp[1], (const double*)Wp[2], (const double*)Wp[3], nw,
+                           wc[0], wc[1], wc[2], wc[3], (const double*)base, (const double*)acc, e, c1, (double*)out1,
+                           f, c2, (double*)out2);
+    else
+        hipLaunchKernelGGL(k_lts_combine<float>, dim3(grid_for(n)), dim3(256), 0, s, n, (const float*)K,
+                           (const float*)Wp[0], (const float*)Wp[1], (const float*)Wp[2], (const float*)Wp[3], nw,
+                           wc[0], wc[1], wc[2], wc[3], (const float*)base, (const float*)acc, e, c1, (float*)out1,
+                           f, c2, (float*)out2);
+    check_launch();
+}
+
+void launch_lts_adjoint(int precision, int64_t n, int np6, const uint32_t* mask, int inv, const void* K, void* zbar,
+                        const void* Z0, double a0, double b0, void* knext, const void* kcur, void* const* wb,
+                        const double* cw, int nw, hipStream_t s) {
+    void* W[4] = {nullptr, nullptr, nullptr, nullptr};
+    double c[4] = {0, 0, 0, 0};
+    for (int j = 0; j < nw && j < 4; ++j) {
+        W[j] = wb[j];
+        c[j] = cw[j];
+    }
+    if (precision == CMCG_FP64)
+        hipLaunchKernelGGL(k_lts_adjoint<double>, dim3(grid_for(n)), dim3(256), 0, s, n, np6, mask, inv,
+                           (const double*)K, (double*)zbar, (const double*)Z0, a0, b0, (double*)knext,
+                           (const double*)kcur, (double*)W[0], (double*)W[1], (double*)W[2], (double*)W[3], nw, c[0],
+                           c[1], c[2], c[3]);
+    else
+        hipLaunchKernelGGL(k_lts_adjoint<float>, dim3(grid_for(n)), dim3(256), 0, s, n, np6, mask, inv,
+                           (const float*)K, (float*)zbar, (const float*)Z0, a0, b0, (float*)knext,
+                           (const float*)kcur, (float*)W[0], (float*)W[1], (float*)W[2], (float*)W[3], nw, c[0],
+                           c[1], c[2], c[3]);
+    check_launch();
+}
+
+void launch_lts_axpy(int precision, int64_t n, int np6, const uint32_t* mask, int inv, double a, const void* y,
+                     double b, const void* x, void* z, hipStream_t s) {
+    if (precision == CMCG_FP64)
+        hipLaunchKernelGGL(k_lts_axpy<double>, dim3(grid_for(n)), dim3(256), 0, s, n, np6, mask, inv, a,
+                           (const double*)y, b, (const double*)x, (double*)z);
+    else
+        hipLaunchKernelGGL(k_lts_axpy<float>, dim3(grid_for(n)), dim3(256), 0, s, n, np6, mask, inv, a,
+                           (const float*)y, b, (const float*)x, (float*)z);
+    check_launch();
+}
 
 void launch_mfma_probe(int precision, const double* A, const double* B, double* D, hipStream_t s) {
     if (precision == CMCG_FP64)

@@ -64,6 +64,11 @@ struct StageArgs {
     int nharm;              // 1 for a single frequency
     int64_t hstride;
     double hcos[8], hsin[8], hfa_re[8], hfa_im[8], hfb_re[8], hfb_im[8];
+    // input mask of a single 3-D launch (nullable): one word per element block
+    // (layout of smask); Phi is evaluated on the input with every element whose
+    // bit xor imask_inv is clear set to zero (B P y for local time stepping)
+    const uint32_t* imask;
+    int imask_inv;
 };
 constexpr int kMaxHarm = 8;
 // per-member scalars of a batched stage: cy, ca, cu, scos, ssin, fa_re, fa_im, fb_re, fb_im
@@ -79,6 +84,19 @@ void launch_source_mask(int precision, int Np, const void* Sre, const void* Sim,
 void upload_constants(int q, int precision, const double* D, const double* LIFT, const double* M,
                       const int* fnode, const int* fperm);
 void launch_stage(int q, int precision, const StageArgs& a, hipStream_t s);
+// Local time stepping (field precision, n values, np6 = 6 Np values per
+// element; masks: one word per element block, bit xor inv selects a row):
+//   combine: k = K + sum_j w_j W_j; out1 = base + e acc + c1 k; out2 = f acc + c2 k
+//   adjoint: A = rows(K); zbar += A; knext = a0 Z0 + b0 A; wb_j += cw_j kcur
+//   axpy:    z = a y + b rows(x)   (mask null: all rows; y null: 0)
+void launch_lts_combine(int precision, int64_t n, const void* K, const void* const* W, const double* w, int nw,
+                        const void* base, const void* acc, double e, double c1, void* out1, double f, double c2,
+                        void* out2, hipStream_t s);
+void launch_lts_adjoint(int precision, int64_t n, int np6, const uint32_t* mask, int inv, const void* K, void* zbar,
+                        const void* Z0, double a0, double b0, void* knext, const void* kcur, void* const* wb,
+                        const double* cw, int nw, hipStream_t s);
+void launch_lts_axpy(int precision, int64_t n, int np6, const uint32_t* mask, int inv, double a, const void* y,
+                     double b, const void* x, void* z, hipStream_t s);
 // D[16][16] = A[16][4] B[4][16] on one matrix-core instruction of the field
 // precision, through the lane layout the stage kernels use (FP64 in and out).
 void launch_mfma_probe(int precision, const double* A, const double* B, double* D, hipStream_t s);

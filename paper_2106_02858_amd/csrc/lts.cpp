@@ -1,0 +1,241 @@
+// Local time stepping (the paper's concluding remarks: locally refined meshes
+// without the global CFL restriction of their smallest elements).
+//
+// One coarse step of size H from t, m fine substeps of size h = H / m
+// (Runge-Kutta-based local time stepping with Taylor-frozen coarse unknowns;
+// P = the unknowns of the fine elements, those whose own CFL step is shorter
+// than H):
+//   D_0 = y, D_{k+1} = B D_k + F^(k)(t)           (k + 1 < p; p = 2 RK2, 4 RK4)
+//   W_k = B (I - P) D_k
+//   z' = B P z + sum_k tau^k / k! W_k + F(t + tau), z(0) = y, m base-RK steps
+//   y(t + H) = z(H)
+// Every application of B is one stage-kernel launch in RHS mode (an input mask
+// zeroes the unknowns outside P or I - P, including neighbour traces); the
+// combinations run as elementwise kernels.  The backward periods of
+// Algorithm 2 need the exact adjoint of this propagator: the step's
+// operations in reverse order, transposed, in S-flipped variables (where
+// B* = S B S becomes B and the masks move to the outputs).  Fields stay in
+// the space's precision without the compensated FP32 state.
+#include <cmath>
+
+#include "objects.h"
+
+namespace cmcg {
+
+namespace {
+
+// fine-element mask (one word per element block) for the coarse step of c
+void ensure_lts_mask(cmcg_problem* p, const StepCfg& c) {
+    const SpaceData& s = *p->sp;
+    if (p->lts_H == c.dt && p->lts_mask.p) return;
+    const MeshData& m = *s.mesh;
+    const int64_t nw = source_mask_words(s.K);
+    std::vector<uint32_t> w(nw, 0u);
+    p->lts_fine = 0;
+    for (int64_t e = 0; e < s.K; ++e) {
+        const double dte = c.cq * std::sqrt(p->mu[e] * p->eps[e]) * m.rho[e];
+        if (dte < c.dt) {
+            w[e / 10] |= 1u << (e % 10);
+            ++p->lts_fine;
+        }
+    }
+    p->lts_mask.alloc(nw * 4);
+    CMCG_HIP(hipMemcpy(p->lts_mask.p, w.data(), nw * 4, hipMemcpyHostToDevice));
+    p->lts_H = c.dt;
+}
+
+double inv_fact(int k) { return k == 0 ? 1.0 : k == 1 ? 1.0 : k == 2 ? 0.5 : 1.0 / 6.0; }
+
+}  // namespace
+
+void ensure_lts(cmcg_problem* p, const StepCfg& c) {
+    const SpaceData& s = *p->sp;
+    if (s.dim != 3) fail(CMCG_ERR_ARG, "local time stepping: tetrahedral spaces only");
+    if (p->nharm != 1) fail(CMCG_ERR_ARG, "local time stepping: single-frequency problems only");
+    ensure_lts_mask(p, c);
+    const size_t fb = s.ndof * s.esize();
+    for (auto& b : p->lD) b.alloc(fb);
+    for (auto& b : p->lW) b.alloc(fb);
+    for (auto& b : p->lWB) b.alloc(fb);
+    p->lZ0.alloc(fb);
+    p->Kbuf.alloc(fb);
+}
+
+void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool filt, hipStream_t st) {
+    const SpaceData& s = *p->sp;
+    const int prec = s.precision;
+    const int64_t n = s.ndof;
+    const int np6 = 6 * s.Np;
+    const int order = c.scheme == 2 ? 2 : 4;
+    const int m = c.lts;
+    const int M = c.M;
+    const double H = c.dt, h = H / m, w = p->omega;
+    const uint32_t* fine = p->lts_mask.as<uint32_t>();
+    void* U = p->U.p;
+    void* Zs = p->Y1.p;
+    void* Zs2 = p->Y2.p;
+    void* Acc = p->Acc.p;
+    void* Kb = p->Kbuf.p;
+    void* D[4] = {U, p->lD[0].p, p->lD[1].p, p->lD[2].p};
+    void* W[4] = {p->lW[0].p, p->lW[1].p, p->lW[2].p, p->lW[3].p};
+    void* WB[4] = {p->lWB[0].p, p->lWB[1].p, p->lWB[2].p, p->lWB[3].p};
+    const bool with_src = src && direction > 0 && p->src_rows;
+
+    StageArgs a{};
+    {
+        // base arguments of the RHS launches
+        a.geo = p->geo.p;
+        a.conn = s.conn.as<int>();
+        a.K = s.K;
+        a.Sre = p->Sre.p;
+        a.Sim = p->Sim.p;
+        a.smask = p->smask.as<uint32_t>();
+        a.nharm = 1;
+        a.hstride = n;
+        a.nmembers = 1;
+        a.mode = RHS;
+    }
+    // Kout = B (mask y) [+ F^(deriv)(tt)]: F^(k)(t) = w^k Re(S e^{i(w t + k pi/2)})
+    auto rhs = [&](const void* Y, void* Kout, bool f, double tt, int deriv, const uint32_t* imask, int inv) {
+        a.Y = Y;
+        a.U = Y;
+        a.Kout = Kout;
+        a.imask = imask;
+        a.imask_inv = inv;
+        a.src_rows = f ? p->src_rows : 0;
+        const double ph = w * tt + deriv * 0.5 * M_PI, amp = std::pow(w, deriv);
+        a.scos = amp * std::cos(ph);
+        a.ssin = amp * std::sin(ph);
+        stage_dim(s, a, st);
+    };
+    // sum_k tau^k / k! W_k coefficients
+    auto poly = [&](double tau, double* cw) {
+        double tk = 1.0;
+        for (int k = 0; k < order; ++k) {
+            cw[k] = tk * inv_fact(k);
+            tk *= tau;
+        }
+    };
+
+    if (direction > 0) {
+        // filter weights (Section 5.4) at the coarse time levels t_nn = nn H
+        std::complex<double> xi[4];
+        if (filt && c.scheme == 4) hermite_weights(w, H, xi);
+        const double twoT = 2.0 / c.T;
+        auto ph = [&](double mm) {
+            const double x = 2.0 * M_PI * mm / M;
+            return std::complex<double>(std::cos(x), -std::sin(x));
+        };
+        if (filt) {
+            launch_zero(p->Fre.p, p->Fre.bytes, st);
+            launch_zero(p->Fim.p, p->Fim.bytes, st);
+        }
+        for (int nn = 0; nn < M; ++nn) {
+            const double t = nn * H;
+            // Taylor coefficients of the solution at t; D_1 = y'(t) is also the
+            // derivative the Hermite filter takes at t_nn
+            for (int k = 1; k < order; ++k) rhs(D[k - 1], D[k], with_src, t, k - 1, nullptr, 0);
+            if (filt) {
+                if (c.scheme == 2) {
+                    const std::complex<double> wa = ph(nn) * ((nn == 0 ? 1.0 : 2.0) / M);
+                    launch_filter_add(prec, U, wa.real(), wa.imag(), p->Fre.as<double>(), p->Fim.as<double>(), n, st);
+                } else {
+                    std::complex<double> wa = twoT * ph(nn) * xi[0], wb = twoT * ph(nn) * xi[2];
+                    if (nn >= 1) {
+                        wa += twoT * ph(nn - 1) * xi[1];
+                        wb += twoT * ph(nn - 1) * xi[3];
+                    }
+                    launch_filter_add(prec, U, wa.real(), wa.imag(), p->Fre.as<double>(), p->Fim.as<double>(), n, st);
+                    launch_filter_add(prec, D[1], wb.real(), wb.imag(), p->Fre.as<double>(), p->Fim.as<double>(), n,
+                                      st);
+                }
+            }
+            // the coarse unknowns' contribution, frozen as a polynomial in tau
+            for (int k = 0; k < order; ++k) rhs(D[k], W[k], false, 0.0, 0, fine, 1);
+            // fine substeps on z (in place on U = D_0)
+            double cw[4];
+            for (int l = 0; l < m; ++l) {
+                const double tau = l * h;
+                if (c.scheme == 2) {
+                    rhs(U, Kb, with_src, t + tau, 0, fine, 0);
+                    poly(tau, cw);
+                    launch_lts_combine(prec, n, Kb, W, cw, order, U, nullptr, 0.0, 0.5 * h, Zs, 0.0, 0.0, nullptr, st);
+                    rhs(Zs, Kb, with_src, t + tau + 0.5 * h, 0, fine, 0);
+                    poly(tau + 0.5 * h, cw);
+                    launch_lts_combine(prec, n, Kb, W, cw, order, U, nullptr, 0.0, h, U, 0.0, 0.0, nullptr, st);
+                } else {
+                    rhs(U, Kb, with_src, t + tau, 0, fine, 0);
+                    poly(tau, cw);
+                    launch_lts_combine(prec, n, Kb, W, cw, order, U, nullptr, 0.0, 0.5 * h, Zs, 0.0, h / 6.0, Acc,
+                                       st);
+                    rhs(Zs, Kb, with_src, t + tau + 0.5 * h, 0, fine, 0);
+                    poly(tau + 0.5 * h, cw);
+                    launch_lts_combine(prec, n, Kb, W, cw, order, U, Acc, 0.0, 0.5 * h, Zs2, 1.0, h / 3.0, Acc, st);
+                    rhs(Zs2, Kb, with_src, t + tau + 0.5 * h, 0, fine, 0);
+                    launch_lts_combine(prec, n, Kb, W, cw, order, U, Acc, 0.0, h, Zs, 1.0, h / 3.0, Acc, st);
+                    rhs(Zs, Kb, with_src, t + tau + h, 0, fine, 0);
+                    poly(tau + h, cw);
+                    launch_lts_combine(prec, n, Kb, W, cw, order, U, Acc, 1.0, h / 6.0, U, 0.0, 0.0, nullptr, st);
+                }
+            }
+        }
+        if (filt) {
+            if (c.scheme == 2) {
+                launch_filter_add(prec, U, 1.0 / M, 0.0, p->Fre.as<double>(), p->Fim.as<double>(), n, st);
+            } else {
+                rhs(U, D[1], with_src, M * H, 0, nullptr, 0);
+                const std::complex<double> wa = twoT * ph(M - 1) * xi[1], wb = twoT * ph(M - 1) * xi[3];
+                launch_filter_add(prec, U, wa.real(), wa.imag(), p->Fre.as<double>(), p->Fim.as<double>(), n, st);
+                launch_filter_add(prec, D[1], wb.real(), wb.imag(), p->Fre.as<double>(), p->Fim.as<double>(), n, st);
+            }
+        }
+        return;
+    }
+
+    // adjoint of the homogeneous step, M times (S-flipped variables: zbar = U)
+    void* KA = Zs;
+    void* KB = Zs2;
+    void* Z0 = p->lZ0.p;
+    for (int nn = 0; nn < M; ++nn) {
+        for (int k = 0; k < order; ++k) launch_zero(WB[k], n * s.esize(), st);
+        double cw[4];
+        for (int l = m - 1; l >= 0; --l) {
+            const double tau = l * h;
+            launch_lts_axpy(prec, n, np6, nullptr, 0, 0.0, nullptr, 1.0, U, Z0, st);  // Z0 = zbar
+            if (c.scheme == 2) {
+                launch_lts_axpy(prec, n, np6, nullptr, 0, 0.0, nullptr, h, Z0, KA, st);  // kbar2 = h zbar
+                poly(tau + 0.5 * h, cw);
+                rhs(KA, Kb, false, 0.0, 0, nullptr, 0);
+                launch_lts_adjoint(prec, n, np6, fine, 0, Kb, U, Z0, 0.0, 0.5 * h, KB, KA, WB, cw, order, st);
+                poly(tau, cw);
+                rhs(KB, Kb, false, 0.0, 0, nullptr, 0);
+                launch_lts_adjoint(prec, n, np6, fine, 0, Kb, U, Z0, 0.0, 0.0, nullptr, KB, WB, cw, order, st);
+            } else {
+                launch_lts_axpy(prec, n, np6, nullptr, 0, 0.0, nullptr, h / 6.0, Z0, KA, st);  // kbar4
+                poly(tau + h, cw);
+                rhs(KA, Kb, false, 0.0, 0, nullptr, 0);
+                launch_lts_adjoint(prec, n, np6, fine, 0, Kb, U, Z0, h / 3.0, h, KB, KA, WB, cw, order, st);
+                poly(tau + 0.5 * h, cw);
+                rhs(KB, Kb, false, 0.0, 0, nullptr, 0);
+                launch_lts_adjoint(prec, n, np6, fine, 0, Kb, U, Z0, h / 3.0, 0.5 * h, KA, KB, WB, cw, order, st);
+                rhs(KA, Kb, false, 0.0, 0, nullptr, 0);
+                launch_lts_adjoint(prec, n, np6, fine, 0, Kb, U, Z0, h / 6.0, 0.5 * h, KB, KA, WB, cw, order, st);
+                poly(tau, cw);
+                rhs(KB, Kb, false, 0.0, 0, nullptr, 0);
+                launch_lts_adjoint(prec, n, np6, fine, 0, Kb, U, Z0, 0.0, 0.0, nullptr, KB, WB, cw, order, st);
+            }
+        }
+        // dbar_k = (I - P) B wbar_k; dbar_{k-1} += B dbar_k; ybar = zbar + dbar_0
+        for (int k = 0; k < order; ++k) {
+            rhs(WB[k], Kb, false, 0.0, 0, nullptr, 0);
+            launch_lts_axpy(prec, n, np6, fine, 1, 0.0, nullptr, 1.0, Kb, WB[k], st);
+        }
+        for (int k = order - 1; k >= 1; --k) {
+            rhs(WB[k], Kb, false, 0.0, 0, nullptr, 0);
+            launch_lts_axpy(prec, n, np6, nullptr, 0, 1.0, WB[k - 1], 1.0, Kb, WB[k - 1], st);
+        }
+        launch_lts_axpy(prec, n, np6, nullptr, 0, 1.0, U, 1.0, WB[0], U, st);
+    }
+}
+
+}  // namespace cmcg

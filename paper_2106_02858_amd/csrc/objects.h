@@ -94,10 +94,12 @@ inline void from_field_dim(const SpaceData& s, const void* U, const void* Ulo, d
 
 // time-stepping configuration of one solve
 struct StepCfg {
-    int M = 0;
+    int M = 0;           // (coarse) steps per period
     int scheme = 2;
     double dt = 0, T = 0;
     double alpha = 1.0;  // flux parameter
+    double cq = 0;       // CFL constant of the step rule
+    int lts = 1;         // > 1: local time stepping with lts fine substeps (lts.cpp)
 };
 
 }  // namespace cmcg
@@ -123,6 +125,11 @@ struct cmcg_problem {
     cmcg::DevBuf Ulo;  // FP32 fields: bfloat16 low parts of U
     cmcg::DevBuf v_u, v_r, v_d, v_a, v_w, v_gs, v_t, v_best;
     cmcg::DevBuf partial, scal;
+    // local time stepping: fine-element mask (per element block) for the coarse
+    // step lts_H, Taylor coefficients, frozen coarse terms, adjoint work vectors
+    cmcg::DevBuf lts_mask, lD[3], lW[4], lWB[4], lZ0;
+    double lts_H = -1;
+    int64_t lts_fine = 0;
     std::unique_ptr<cmcg::HostPinned> pinned;
     hipStream_t cap_stream = nullptr;
     std::map<int64_t, hipGraphExec_t> graphs;
@@ -191,6 +198,11 @@ int current_device();
 StepCfg step_config(const cmcg_problem* p, const cmcg_options* o);
 void hermite_weights(double omega, double dt, std::complex<double> xi[4]);
 void build_geo(cmcg_problem* p, double alpha);
+// local time stepping (lts.cpp): work buffers and fine mask for c, and one
+// period on p->U (direction +1: forward, with source / filter as asked;
+// -1: the adjoint of the homogeneous period, in S-flipped variables)
+void ensure_lts(cmcg_problem* p, const StepCfg& c);
+void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool filt, hipStream_t st);
 void prepare(cmcg_problem* p, const StepCfg& c);
 cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st);
 cmcg_result* fw_solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st);

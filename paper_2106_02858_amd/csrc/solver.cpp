@@ -362,16 +362,23 @@ StepCfg step_config(const cmcg_problem* p, const cmcg_options* o) {
     if (o->flux != CMCG_FLUX_UPWIND && o->flux != CMCG_FLUX_CENTRED) fail(CMCG_ERR_ARG, "options: bad flux");
     c.alpha = o->flux == CMCG_FLUX_UPWIND ? 1.0 : 0.0;
     c.T = 2.0 * M_PI / p->omega;
+    // 3-D: c_1 = 0.20 (readings for tetrahedra); 2-D: the paper's c_1 = 0.24, c_3 = 0.12
+    const double c1 = s.dim == 2 ? 0.24 : 0.20;
+    c.cq = o->cfl > 0 ? o->cfl : (s.q == 1 ? c1 : s.q == 2 ? 0.16 : 0.12);
+    if (o->lts_ratio < 0 || o->lts_ratio > 64) fail(CMCG_ERR_ARG, "options: lts_ratio must be 0..64");
+    c.lts = o->lts_ratio > 1 ? o->lts_ratio : 1;
+    if (c.lts > 1 && (s.dim != 3 || p->nharm != 1))
+        fail(CMCG_ERR_ARG, "options: local time stepping needs a tetrahedral space and one frequency");
     if (o->steps > 0) {
         c.M = o->steps;
     } else {
-        // 3-D: c_1 = 0.20 (readings for tetrahedra); 2-D: the paper's c_1 = 0.24, c_3 = 0.12
-        const double c1 = s.dim == 2 ? 0.24 : 0.20;
-        const double cq = o->cfl > 0 ? o->cfl : (s.q == 1 ? c1 : s.q == 2 ? 0.16 : 0.12);
+        const double cq = c.cq;
         const MeshData& m = *s.mesh;
         double mn = HUGE_VAL;
         for (int64_t e = 0; e < s.K; ++e) mn = std::fmin(mn, std::sqrt(p->mu[e] * p->eps[e]) * m.rho[e]);
-        const double dtmax = cq * mn;
+        // local time stepping: the coarse step may be lts times the smallest
+        // element's step (its m substeps then meet that element's CFL rule)
+        const double dtmax = cq * mn * c.lts;
         long long M = (long long)std::ceil(c.T / dtmax);
         if (M < 1) M = 1;
         while (c.T / (double)M > dtmax) ++M;
@@ -598,6 +605,18 @@ void apply_period(cmcg_problem* p, const StepCfg& c, const cmcg_options* o, cons
                          const double* sub, int direction, bool src, bool filt, hipStream_t st) {
     const SpaceData& s = *p->sp;
     const int flip = direction < 0 ? 1 : 0;
+    if (c.lts > 1) {
+        // local time stepping: plain field-precision state (no FP32 low part),
+        // eager launches
+        ensure_lts(p, c);
+        if (X)
+            to_field_dim(s, X, p->U.p, nullptr, s.ndof, flip, st);
+        else
+            launch_zero(p->U.p, p->U.bytes, st);
+        lts_period(p, c, direction, src && direction > 0, filt, st);
+        if (Yo) from_field_dim(s, p->U.p, nullptr, Yo, sub, s.ndof, flip, st);
+        return;
+    }
     if (X) {
         to_field_dim(s, X, p->U.p, p->Ulo.p, s.ndof, flip, st);
     } else {
@@ -1213,6 +1232,24 @@ int cmcg_problem_steps(const cmcg_problem* p, const cmcg_options* o, int* M, dou
     StepCfg c = step_config(p, o);
     if (M) *M = c.M;
     if (dt) *dt = c.dt;
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_problem_lts_fine(const cmcg_problem* p, const cmcg_options* o, int8_t* fine, int64_t* n_fine) {
+    CMCG_GUARD_BEGIN
+    if (!p || !o) fail(CMCG_ERR_ARG, "problem_lts_fine: NULL argument");
+    StepCfg c = step_config(p, o);
+    if (c.lts <= 1) fail(CMCG_ERR_ARG, "problem_lts_fine: the options ask for no local time stepping");
+    const SpaceData& s = *p->sp;
+    const MeshData& m = *s.mesh;
+    int64_t cnt = 0;
+    for (int64_t e = 0; e < s.K; ++e) {
+        const bool f = c.cq * std::sqrt(p->mu[e] * p->eps[e]) * m.rho[e] < c.dt;
+        if (fine) fine[e] = f ? 1 : 0;
+        cnt += f;
+    }
+    if (n_fine) *n_fine = cnt;
     return CMCG_OK;
     CMCG_GUARD_END
 }

@@ -1,0 +1,142 @@
+"""Local time stepping on the GPU (cmcg_options.lts_ratio) against the
+oracle's LTS scheme (oracle/lts.py), element by element: the fine-element
+mask and coarse step count, one forward period with source and filter, one
+adjoint (backward) period, the adjoint identity, and CMCG on LTS periods at
+a fixed iteration count.  Mesh: a cube with a slab of 4.5x thinner cells
+(96 tetrahedra: ten element blocks, the last one ragged), eps from {1, 2},
+mixed PEC / impedance walls."""
+import numpy as np
+import pytest
+
+from oracle import cmcg as ocmcg
+from oracle import dg, lts
+from paper_2106_02858_amd import inputs
+from tests._pairs import lib_problem, rel_norm, rel_norm_c
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5}
+M_RATIO = 4
+
+
+def dev(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def lts_pair(lib, q, precision, tags=inputs.TAG_IMPEDANCE, seed=0, g=False):
+    axes = ([0, .45, .5, .55, 1.], [0, .5, 1.], [0, .5, 1.])
+    xyz, tet, tg = inputs.graded_cube_mesh(*axes, inputs.TAG_IMPEDANCE if tags == "mixed" else tags)
+    if tags == "mixed":
+        rng = np.random.default_rng(seed)
+        tg = np.where(tg > 0, np.where(rng.random(tg.shape) < 0.5, inputs.TAG_PEC, inputs.TAG_IMPEDANCE), 0)
+        tg = tg.astype(np.int8)
+    K = tet.shape[0]
+    rng = np.random.default_rng(seed + 1)
+    eps = rng.choice([1.0, 2.0], K)
+    p0 = dg.make_problem(xyz, tet, tg, q, eps, np.ones(K), omega=2 * np.pi)
+    j = (inputs.gaussian_current(p0.geo.x, [.5, .5, .5], .3, 2)
+         + 1j * inputs.gaussian_current(p0.geo.x, [.4, .6, .5], .3, 0))
+    gg = rng.standard_normal((K, 4, p0.geo.Nfp, 3)) if g else None
+    op = dg.make_problem(xyz, tet, tg, q, eps, np.ones(K), omega=2 * np.pi, j=j, g=gg)
+    s, lp = lib_problem(lib, op, precision, xyz, tet, tg)
+    return op, s, lp
+
+
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_fine_mask_and_coarse_steps(lib, q):
+    op, s, lp = lts_pair(lib, q, 0)
+    o = lib.cmcg_options_default(lts_ratio=M_RATIO)
+    M, dt = lib.cmcg_problem_steps(lp, o)
+    Mo, fine = lts.lts_steps(op, M_RATIO)
+    assert M == Mo
+    assert np.array_equal(lib.cmcg_problem_lts_fine(lp, op.K, o), fine)
+    assert 0 < fine.sum() < op.K
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_forward_period_with_source_and_filter(lib, q, precision):
+    print(f"lts forward q={q} prec={precision}", flush=True)
+    op, s, lp = lts_pair(lib, q, precision, tags="mixed", seed=q, g=(q == 2))
+    o = lib.cmcg_options_default(lts_ratio=M_RATIO)
+    M, _ = lib.cmcg_problem_steps(lp, o)
+    _, fine = lts.lts_steps(op, M_RATIO)
+    U0 = np.random.default_rng(20 + q).standard_normal((op.K, 6, op.Np))
+    UT, fr, fi = dev(np.zeros_like(U0)), dev(np.zeros_like(U0)), dev(np.zeros_like(U0))
+    lib.cmcg_debug_period(lp, dev(U0), UT, 1, True, fr, fi, opts=o)
+    sch = 2 if q == 1 else 4
+    ref, F = lts.forward(op, U0, M, M_RATIO, fine, sch, True, filt=True)
+    assert rel_norm(op, host(UT), ref) < TOL[precision]
+    assert rel_norm_c(op, host(fr) + 1j * host(fi), F) < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_adjoint_period(lib, q, precision):
+    print(f"lts adjoint q={q} prec={precision}", flush=True)
+    op, s, lp = lts_pair(lib, q, precision, tags="mixed", seed=10 + q)
+    o = lib.cmcg_options_default(lts_ratio=M_RATIO)
+    M, _ = lib.cmcg_problem_steps(lp, o)
+    _, fine = lts.lts_steps(op, M_RATIO)
+    W = np.random.default_rng(30 + q).standard_normal((op.K, 6, op.Np))
+    out = dev(np.zeros_like(W))
+    lib.cmcg_debug_period(lp, dev(W), out, -1, False, opts=o)
+    ref = lts.backward(op, W, M, M_RATIO, fine, 2 if q == 1 else 4)
+    assert rel_norm(op, host(out), ref) < TOL[precision]
+
+
+@pytest.mark.parametrize("q", [1, 3])
+def test_adjoint_identity_on_gpu(lib, q):
+    op, s, lp = lts_pair(lib, q, 0, tags="mixed", seed=40)
+    o = lib.cmcg_options_default(lts_ratio=M_RATIO)
+    rng = np.random.default_rng(41)
+    x, y = dev(rng.standard_normal((op.K, 6, op.Np))), dev(rng.standard_normal((op.K, 6, op.Np)))
+    Px, Psy = dev(np.zeros((op.K, 6, op.Np))), dev(np.zeros((op.K, 6, op.Np)))
+    lib.cmcg_debug_period(lp, x, Px, 1, False, opts=o)
+    lib.cmcg_debug_period(lp, y, Psy, -1, False, opts=o)
+    a, b = lib.cmcg_debug_dot(lp, Px, y), lib.cmcg_debug_dot(lp, x, Psy)
+    nx, ny = lib.cmcg_debug_dot(lp, x, x), lib.cmcg_debug_dot(lp, y, y)
+    assert abs(a - b) <= 1e-13 * np.sqrt(nx * ny)
+
+
+_ORACLE = {}
+
+
+def _oracle_lts_cmcg(q, op):
+    """The oracle's LTS CMCG to 1e-8 (computed once per order)."""
+    if q not in _ORACLE:
+        _ORACLE[q] = ocmcg.solve(op, tol=1e-8, max_iter=300, lts=M_RATIO)
+    return _ORACLE[q]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("q", [1, 2])
+def test_cmcg_with_local_time_stepping(lib, q, precision):
+    """CMCG (Algorithms 1-3 + filter) on LTS periods, impedance walls, at the
+    oracle's iteration count for 1e-8: FP64 within 1e-11 of the oracle's LTS
+    CMCG, FP32 fields within 1e-5."""
+    print(f"lts cmcg q={q} prec={precision}", flush=True)
+    op, s, lp = lts_pair(lib, q, precision, seed=50 + q)
+    ref = _oracle_lts_cmcg(q, op)
+    r = lib.cmcg_solve(lp, lib.cmcg_options_default(fixed_iters=ref.iters, lts_ratio=M_RATIO))
+    st = lib.cmcg_result_stats(r)
+    assert st["iters"] == ref.iters and st["steps"] == ref.M
+    fr, fi = dev(np.zeros((op.K, 6, op.Np))), dev(np.zeros((op.K, 6, op.Np)))
+    lib.cmcg_result_filtered_device(r, fr, fi)
+    err = rel_norm_c(op, host(fr) + 1j * host(fi), ref.F)
+    print(f"  {ref.iters} iterations, M = {ref.M}: {err:.2e}", flush=True)
+    assert err < (1e-11 if precision == 0 else 1e-5)
+
+
+def test_lts_rejected_where_unsupported(lib):
+    op, s, lp = lts_pair(lib, 1, 0)
+    with pytest.raises(lib.CmcgError) as err:
+        lib.cmcg_solve_batch([lp], lib.cmcg_options_default(lts_ratio=M_RATIO))
+    assert err.value.code == lib.CMCG_ERR_ARG
+    with pytest.raises(lib.CmcgError):
+        lib.cmcg_problem_steps(lp, lib.cmcg_options_default(lts_ratio=65))
