@@ -346,7 +346,11 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
 
     StageArgs a;
     if (!member_args<T>(args, a)) return;  // uniform per workgroup
-    const int64_t blk = xcd_block(per);
+    int64_t blk = xcd_block(per);
+    if (a.blist) {  // only the listed element blocks
+        if (blk >= a.nblist) return;
+        blk = a.blist[blk];
+    }
     const int64_t e0 = blk * EPW;
     if (e0 >= a.K) return;
     const T* __restrict__ Y = (const T*)a.Y;
@@ -756,7 +760,11 @@ void k_stage_mfma(StageArgs args, int64_t per) {
 
     StageArgs a;
     if (!member_args<T>(args, a)) return;  // uniform per workgroup
-    const int64_t blk = xcd_block(per);
+    int64_t blk = xcd_block(per);
+    if (a.blist) {  // only the listed element blocks
+        if (blk >= a.nblist) return;
+        blk = a.blist[blk];
+    }
     const int64_t e0 = blk * EPW;
     if (e0 >= a.K) return;  // uniform per workgroup
     const T* __restrict__ Y = (const T*)a.Y;
@@ -1191,14 +1199,31 @@ __device__ __forceinline__ bool lts_row_on(const uint32_t* mask, int inv, int64_
     return ((mask[e / EPW] >> (int)(e % EPW)) & 1u) ^ (uint32_t)inv;
 }
 
+// Values an elementwise LTS kernel visits: all n, or (blist non-null) the
+// rows of the listed element blocks; returns the count and maps a visit
+// index to the value index.
+struct LtsRange {
+    const int* blist;
+    int64_t nb, n, per;  // per = EPW * 6 Np values of a block
+    __device__ __forceinline__ int64_t count() const { return blist ? nb * per : n; }
+    __device__ __forceinline__ int64_t at(int64_t f) const {
+        if (!blist) return f;
+        const int64_t b = f / per;
+        return (int64_t)blist[b] * per + (f - b * per);
+    }
+};
+
 // k = K + sum_{j < nw} w_j W_j;  out1 = base + e acc + c1 k;  out2 = f acc + c2 k
 // (acc nullable = 0; out1 / out2 nullable = not written; out1 may alias base,
 // out2 may alias acc)
 template <typename T>
-__global__ void k_lts_combine(int64_t n, const T* K, const T* W0, const T* W1, const T* W2, const T* W3, int nw,
+__global__ void k_lts_combine(LtsRange rg, const T* K, const T* W0, const T* W1, const T* W2, const T* W3, int nw,
                               double w0, double w1, double w2, double w3, const T* base, const T* acc, double e,
                               double c1, T* out1, double f, double c2, T* out2) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t cnt = rg.count();
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < cnt; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = rg.at(v);
+        if (i >= rg.n) continue;
         T k = K[i];
         if (nw > 0) k += (T)w0 * W0[i];
         if (nw > 1) k += (T)w1 * W1[i];
@@ -1212,17 +1237,24 @@ __global__ void k_lts_combine(int64_t n, const T* K, const T* W0, const T* W1, c
 
 // Adjoint stage of the homogeneous step (S-flipped variables): A = rows of K
 // on the mask; zbar += A; knext = a0 Z0 + b0 A; wb_j += cw_j kcur (j < nw)
+// (wb updated on the mask's rows only: elsewhere the caller holds them in closed form)
 template <typename T>
-__global__ void k_lts_adjoint(int64_t n, int np6, const uint32_t* mask, int inv, const T* K, T* zbar, const T* Z0,
+__global__ void k_lts_adjoint(LtsRange rg, int np6, const uint32_t* mask, int inv, const T* K, T* zbar, const T* Z0,
                               double a0, double b0, T* knext, const T* kcur, T* wb0, T* wb1, T* wb2, T* wb3, int nw,
                               double cw0, double cw1, double cw2, double cw3) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const T kc = kcur[i];
-        if (nw > 0) wb0[i] += (T)cw0 * kc;
-        if (nw > 1) wb1[i] += (T)cw1 * kc;
-        if (nw > 2) wb2[i] += (T)cw2 * kc;
-        if (nw > 3) wb3[i] += (T)cw3 * kc;
-        const T A = lts_row_on(mask, inv, i, np6) ? K[i] : T(0);
+    const int64_t cnt = rg.count();
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < cnt; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = rg.at(v);
+        if (i >= rg.n) continue;
+        const bool on = lts_row_on(mask, inv, i, np6);
+        if (on) {
+            const T kc = kcur[i];
+            if (nw > 0) wb0[i] += (T)cw0 * kc;
+            if (nw > 1) wb1[i] += (T)cw1 * kc;
+            if (nw > 2) wb2[i] += (T)cw2 * kc;
+            if (nw > 3) wb3[i] += (T)cw3 * kc;
+        }
+        const T A = on ? K[i] : T(0);
         zbar[i] += A;
         if (knext) knext[i] = (T)a0 * Z0[i] + (T)b0 * A;
     }
@@ -1231,11 +1263,33 @@ __global__ void k_lts_adjoint(int64_t n, int np6, const uint32_t* mask, int inv,
 // z = a y + b rows(x), rows(x) = x on the mask's rows (all rows when mask is
 // null), 0 elsewhere; y nullable (= 0); z may alias y
 template <typename T>
-__global__ void k_lts_axpy(int64_t n, int np6, const uint32_t* mask, int inv, double a, const T* y, double b,
+__global__ void k_lts_axpy(LtsRange rg, int np6, const uint32_t* mask, int inv, double a, const T* y, double b,
                            const T* x, T* z) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t cnt = rg.count();
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < cnt; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = rg.at(v);
+        if (i >= rg.n) continue;
         const T xv = (!mask || lts_row_on(mask, inv, i, np6)) ? x[i] : T(0);
         z[i] = (y ? (T)a * y[i] : T(0)) + (T)b * xv;
+    }
+}
+
+// Rows outside the mask (the coarse unknowns away from the fine region):
+// z += sum_j al_j W_j + sc Sre - ss Sim (Sre nullable; source rows only where
+// the source mask and the row's component allow)
+template <typename T>
+__global__ void k_lts_closed(int64_t n, int np6, int Np, const uint32_t* mask, const T* W0, const T* W1, const T* W2,
+                             const T* W3, int nw, double a0, double a1, double a2, double a3, const T* Sre,
+                             const T* Sim, int src_rows, double sc, double ss, T* z) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (lts_row_on(mask, 0, i, np6)) continue;
+        T acc = z[i];
+        if (nw > 0) acc += (T)a0 * W0[i];
+        if (nw > 1) acc += (T)a1 * W1[i];
+        if (nw > 2) acc += (T)a2 * W2[i];
+        if (nw > 3) acc += (T)a3 * W3[i];
+        if (Sre && ((i / Np) % 6) < src_rows) acc += (T)sc * Sre[i] - (T)ss * Sim[i];
+        z[i] = acc;
     }
 }
 
@@ -1412,7 +1466,7 @@ inline int grid_for(int64_t n, int threads = 256) {
 
 template <typename T, int Q, bool MH>
 void stage_launch_mh(const StageArgs& a, hipStream_t s) {
-    const int64_t blocks = (a.K + EPW - 1) / EPW;
+    const int64_t blocks = a.blist ? a.nblist : (a.K + EPW - 1) / EPW;
     const int64_t per = (blocks + 7) / 8;
     const int v = stage_variant(Q, sizeof(T) == 8 ? CMCG_FP64 : CMCG_FP32);
     const dim3 grid((unsigned)(8 * per), (unsigned)(a.nmembers > 1 ? a.nmembers : 1));
@@ -1648,58 +1702,96 @@ void launch_filter_add(int precision, const void* U, double wr, double wi, doubl
 
 int dot_partials() { return kDotBlocks; }
 
-void launch_lts_combine(int precision, int64_t n, const void* K, const void* const* W, const double* w, int nw,
-                        const void* base, const void* acc, double e, double c1, void* out1, double f, double c2,
-                        void* out2, hipStream_t s) {
+namespace {
+LtsRange lts_range(int64_t n, int np6, const int* blist, int64_t nb) {
+    LtsRange r;
+    r.blist = blist;
+    r.nb = nb;
+    r.n = n;
+    r.per = (int64_t)EPW * np6;
+    return r;
+}
+int64_t lts_count(const LtsRange& r) { return r.blist ? r.nb * r.per : r.n; }
+}  // namespace
+
+void launch_lts_combine(int precision, int64_t n, int np6, const int* blist, int64_t nb, const void* K,
+                        const void* const* W, const double* w, int nw, const void* base, const void* acc, double e,
+                        double c1, void* out1, double f, double c2, void* out2, hipStream_t s) {
     const void* Wp[4] = {nullptr, nullptr, nullptr, nullptr};
     double wc[4] = {0, 0, 0, 0};
     for (int j = 0; j < nw && j < 4; ++j) {
         Wp[j] = W[j];
         wc[j] = w[j];
     }
+    const LtsRange rg = lts_range(n, np6, blist, nb);
+    const int g = grid_for(lts_count(rg));
     if (precision == CMCG_FP64)
-        hipLaunchKernelGGL(k_lts_combine<double>, dim3(grid_for(n)), dim3(256), 0, s, n, (const double*)K,
+        hipLaunchKernelGGL(k_lts_combine<double>, dim3(g), dim3(256), 0, s, rg, (const double*)K,
                            (const double*)Wp[0], (const double*)Wp[1], (const double*)Wp[2], (const double*)Wp[3], nw,
                            wc[0], wc[1], wc[2], wc[3], (const double*)base, (const double*)acc, e, c1, (double*)out1,
                            f, c2, (double*)out2);
     else
-        hipLaunchKernelGGL(k_lts_combine<float>, dim3(grid_for(n)), dim3(256), 0, s, n, (const float*)K,
+        hipLaunchKernelGGL(k_lts_combine<float>, dim3(g), dim3(256), 0, s, rg, (const float*)K,
                            (const float*)Wp[0], (const float*)Wp[1], (const float*)Wp[2], (const float*)Wp[3], nw,
                            wc[0], wc[1], wc[2], wc[3], (const float*)base, (const float*)acc, e, c1, (float*)out1,
                            f, c2, (float*)out2);
     check_launch();
 }
 
-void launch_lts_adjoint(int precision, int64_t n, int np6, const uint32_t* mask, int inv, const void* K, void* zbar,
-                        const void* Z0, double a0, double b0, void* knext, const void* kcur, void* const* wb,
-                        const double* cw, int nw, hipStream_t s) {
+void launch_lts_adjoint(int precision, int64_t n, int np6, const int* blist, int64_t nb, const uint32_t* mask,
+                        int inv, const void* K, void* zbar, const void* Z0, double a0, double b0, void* knext,
+                        const void* kcur, void* const* wb, const double* cw, int nw, hipStream_t s) {
     void* W[4] = {nullptr, nullptr, nullptr, nullptr};
     double c[4] = {0, 0, 0, 0};
     for (int j = 0; j < nw && j < 4; ++j) {
         W[j] = wb[j];
         c[j] = cw[j];
     }
+    const LtsRange rg = lts_range(n, np6, blist, nb);
+    const int g = grid_for(lts_count(rg));
     if (precision == CMCG_FP64)
-        hipLaunchKernelGGL(k_lts_adjoint<double>, dim3(grid_for(n)), dim3(256), 0, s, n, np6, mask, inv,
-                           (const double*)K, (double*)zbar, (const double*)Z0, a0, b0, (double*)knext,
-                           (const double*)kcur, (double*)W[0], (double*)W[1], (double*)W[2], (double*)W[3], nw, c[0],
-                           c[1], c[2], c[3]);
+        hipLaunchKernelGGL(k_lts_adjoint<double>, dim3(g), dim3(256), 0, s, rg, np6, mask, inv, (const double*)K,
+                           (double*)zbar, (const double*)Z0, a0, b0, (double*)knext, (const double*)kcur,
+                           (double*)W[0], (double*)W[1], (double*)W[2], (double*)W[3], nw, c[0], c[1], c[2], c[3]);
     else
-        hipLaunchKernelGGL(k_lts_adjoint<float>, dim3(grid_for(n)), dim3(256), 0, s, n, np6, mask, inv,
-                           (const float*)K, (float*)zbar, (const float*)Z0, a0, b0, (float*)knext,
-                           (const float*)kcur, (float*)W[0], (float*)W[1], (float*)W[2], (float*)W[3], nw, c[0],
-                           c[1], c[2], c[3]);
+        hipLaunchKernelGGL(k_lts_adjoint<float>, dim3(g), dim3(256), 0, s, rg, np6, mask, inv, (const float*)K,
+                           (float*)zbar, (const float*)Z0, a0, b0, (float*)knext, (const float*)kcur, (float*)W[0],
+                           (float*)W[1], (float*)W[2], (float*)W[3], nw, c[0], c[1], c[2], c[3]);
     check_launch();
 }
 
-void launch_lts_axpy(int precision, int64_t n, int np6, const uint32_t* mask, int inv, double a, const void* y,
-                     double b, const void* x, void* z, hipStream_t s) {
+void launch_lts_axpy(int precision, int64_t n, int np6, const int* blist, int64_t nb, const uint32_t* mask, int inv,
+                     double a, const void* y, double b, const void* x, void* z, hipStream_t s) {
+    const LtsRange rg = lts_range(n, np6, blist, nb);
+    const int g = grid_for(lts_count(rg));
     if (precision == CMCG_FP64)
-        hipLaunchKernelGGL(k_lts_axpy<double>, dim3(grid_for(n)), dim3(256), 0, s, n, np6, mask, inv, a,
-                           (const double*)y, b, (const double*)x, (double*)z);
+        hipLaunchKernelGGL(k_lts_axpy<double>, dim3(g), dim3(256), 0, s, rg, np6, mask, inv, a, (const double*)y,
+                           b, (const double*)x, (double*)z);
     else
-        hipLaunchKernelGGL(k_lts_axpy<float>, dim3(grid_for(n)), dim3(256), 0, s, n, np6, mask, inv, a,
-                           (const float*)y, b, (const float*)x, (float*)z);
+        hipLaunchKernelGGL(k_lts_axpy<float>, dim3(g), dim3(256), 0, s, rg, np6, mask, inv, a, (const float*)y, b,
+                           (const float*)x, (float*)z);
+    check_launch();
+}
+
+void launch_lts_closed(int precision, int64_t n, int np6, int Np, const uint32_t* mask, const void* const* W,
+                       const double* al, int nw, const void* Sre, const void* Sim, int src_rows, double sc, double ss,
+                       void* z, hipStream_t s) {
+    const void* Wp[4] = {nullptr, nullptr, nullptr, nullptr};
+    double c[4] = {0, 0, 0, 0};
+    for (int j = 0; j < nw && j < 4; ++j) {
+        Wp[j] = W[j];
+        c[j] = al[j];
+    }
+    if (precision == CMCG_FP64)
+        hipLaunchKernelGGL(k_lts_closed<double>, dim3(grid_for(n)), dim3(256), 0, s, n, np6, Np, mask,
+                           (const double*)Wp[0], (const double*)Wp[1], (const double*)Wp[2], (const double*)Wp[3], nw,
+                           c[0], c[1], c[2], c[3], (const double*)Sre, (const double*)Sim, src_rows, sc, ss,
+                           (double*)z);
+    else
+        hipLaunchKernelGGL(k_lts_closed<float>, dim3(grid_for(n)), dim3(256), 0, s, n, np6, Np, mask,
+                           (const float*)Wp[0], (const float*)Wp[1], (const float*)Wp[2], (const float*)Wp[3], nw,
+                           c[0], c[1], c[2], c[3], (const float*)Sre, (const float*)Sim, src_rows, sc, ss,
+                           (float*)z);
     check_launch();
 }
 

@@ -69,6 +69,9 @@ struct StageArgs {
     // bit xor imask_inv is clear set to zero (B P y for local time stepping)
     const uint32_t* imask;
     int imask_inv;
+    // single 3-D launches (nullable): run only the element blocks listed
+    const int* blist;
+    int64_t nblist;
 };
 constexpr int kMaxHarm = 8;
 // per-member scalars of a batched stage: cy, ca, cu, scos, ssin, fa_re, fa_im, fb_re, fb_im
@@ -85,18 +88,24 @@ void upload_constants(int q, int precision, const double* D, const double* LIFT,
                       const int* fnode, const int* fperm);
 void launch_stage(int q, int precision, const StageArgs& a, hipStream_t s);
 // Local time stepping (field precision, n values, np6 = 6 Np values per
-// element; masks: one word per element block, bit xor inv selects a row):
+// element; masks: one word per element block, bit xor inv selects a row;
+// blist / nb (nullable): visit only the rows of the listed element blocks):
 //   combine: k = K + sum_j w_j W_j; out1 = base + e acc + c1 k; out2 = f acc + c2 k
-//   adjoint: A = rows(K); zbar += A; knext = a0 Z0 + b0 A; wb_j += cw_j kcur
+//   adjoint: on mask rows wb_j += cw_j kcur and A = K, elsewhere A = 0;
+//            zbar += A; knext = a0 Z0 + b0 A
 //   axpy:    z = a y + b rows(x)   (mask null: all rows; y null: 0)
-void launch_lts_combine(int precision, int64_t n, const void* K, const void* const* W, const double* w, int nw,
-                        const void* base, const void* acc, double e, double c1, void* out1, double f, double c2,
-                        void* out2, hipStream_t s);
-void launch_lts_adjoint(int precision, int64_t n, int np6, const uint32_t* mask, int inv, const void* K, void* zbar,
-                        const void* Z0, double a0, double b0, void* knext, const void* kcur, void* const* wb,
-                        const double* cw, int nw, hipStream_t s);
-void launch_lts_axpy(int precision, int64_t n, int np6, const uint32_t* mask, int inv, double a, const void* y,
-                     double b, const void* x, void* z, hipStream_t s);
+//   closed:  rows off the mask: z += sum_j al_j W_j + sc Sre - ss Sim (source rows)
+void launch_lts_combine(int precision, int64_t n, int np6, const int* blist, int64_t nb, const void* K,
+                        const void* const* W, const double* w, int nw, const void* base, const void* acc, double e,
+                        double c1, void* out1, double f, double c2, void* out2, hipStream_t s);
+void launch_lts_adjoint(int precision, int64_t n, int np6, const int* blist, int64_t nb, const uint32_t* mask,
+                        int inv, const void* K, void* zbar, const void* Z0, double a0, double b0, void* knext,
+                        const void* kcur, void* const* wb, const double* cw, int nw, hipStream_t s);
+void launch_lts_axpy(int precision, int64_t n, int np6, const int* blist, int64_t nb, const uint32_t* mask, int inv,
+                     double a, const void* y, double b, const void* x, void* z, hipStream_t s);
+void launch_lts_closed(int precision, int64_t n, int np6, int Np, const uint32_t* mask, const void* const* W,
+                       const double* al, int nw, const void* Sre, const void* Sim, int src_rows, double sc, double ss,
+                       void* z, hipStream_t s);
 // D[16][16] = A[16][4] B[4][16] on one matrix-core instruction of the field
 // precision, through the lane layout the stage kernels use (FP64 in and out).
 void launch_mfma_probe(int precision, const double* A, const double* B, double* D, hipStream_t s);

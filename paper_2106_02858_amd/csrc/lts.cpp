@@ -16,6 +16,15 @@
 // operations in reverse order, transposed, in S-flipped variables (where
 // B* = S B S becomes B and the masks move to the outputs).  Fields stay in
 // the space's precision without the compensated FP32 state.
+//
+// Only the fine region pays for the substeps: B P z vanishes outside the
+// fine elements and their face neighbours (the halo), so the substeps run
+// on the element blocks that hold halo elements, and every other unknown
+// advances in closed form, z = y + sum_k al_k W_k + (RK quadrature of F) with
+// al_k = sum over the substeps' stages of b_s h tau_s^k / k!.  The adjoint
+// likewise runs its substeps on the fine blocks (outputs) and halo blocks
+// (vectors), the coarse rows' adjoint Taylor weights being al_k times the
+// step's end value.
 #include <cmath>
 
 #include "objects.h"
@@ -24,23 +33,47 @@ namespace cmcg {
 
 namespace {
 
-// fine-element mask (one word per element block) for the coarse step of c
+// fine-element mask (one word per element block) for the coarse step of c,
+// the mask of the element blocks that hold halo elements (fine ones or their
+// face neighbours), and the lists of fine and halo blocks
 void ensure_lts_mask(cmcg_problem* p, const StepCfg& c) {
     const SpaceData& s = *p->sp;
     if (p->lts_H == c.dt && p->lts_mask.p) return;
     const MeshData& m = *s.mesh;
     const int64_t nw = source_mask_words(s.K);
-    std::vector<uint32_t> w(nw, 0u);
+    std::vector<uint32_t> w(nw, 0u), hb(nw, 0u);
+    std::vector<char> halo(s.K, 0);
     p->lts_fine = 0;
     for (int64_t e = 0; e < s.K; ++e) {
         const double dte = c.cq * std::sqrt(p->mu[e] * p->eps[e]) * m.rho[e];
         if (dte < c.dt) {
             w[e / 10] |= 1u << (e % 10);
             ++p->lts_fine;
+            halo[e] = 1;
+            for (int f = 0; f < 4; ++f)
+                if (m.nbr[4 * e + f] >= 0) halo[m.nbr[4 * e + f]] = 1;
+        }
+    }
+    std::vector<int> fb, hbl;
+    for (int64_t b = 0; b < nw; ++b) {
+        bool any_f = w[b] != 0, any_h = false;
+        for (int64_t e = 10 * b; e < std::min<int64_t>(10 * b + 10, s.K); ++e) any_h = any_h || halo[e];
+        if (any_f) fb.push_back((int)b);
+        if (any_h) {
+            hbl.push_back((int)b);
+            hb[b] = 0x3ffu;  // every element of the block
         }
     }
     p->lts_mask.alloc(nw * 4);
+    p->lts_hbmask.alloc(nw * 4);
     CMCG_HIP(hipMemcpy(p->lts_mask.p, w.data(), nw * 4, hipMemcpyHostToDevice));
+    CMCG_HIP(hipMemcpy(p->lts_hbmask.p, hb.data(), nw * 4, hipMemcpyHostToDevice));
+    p->lts_nfb = (int64_t)fb.size();
+    p->lts_nhb = (int64_t)hbl.size();
+    p->lts_fblocks.alloc(std::max<size_t>(1, fb.size()) * 4);
+    p->lts_hblocks.alloc(std::max<size_t>(1, hbl.size()) * 4);
+    if (!fb.empty()) CMCG_HIP(hipMemcpy(p->lts_fblocks.p, fb.data(), fb.size() * 4, hipMemcpyHostToDevice));
+    if (!hbl.empty()) CMCG_HIP(hipMemcpy(p->lts_hblocks.p, hbl.data(), hbl.size() * 4, hipMemcpyHostToDevice));
     p->lts_H = c.dt;
 }
 
@@ -116,6 +149,27 @@ void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool
             tk *= tau;
         }
     };
+    // the base scheme's stages per substep: (offset in the substep, weight b_s)
+    const int ns = c.scheme == 2 ? 1 : 4;
+    const double st_off[4] = {c.scheme == 2 ? 0.5 : 0.0, 0.5, 0.5, 1.0};
+    const double st_b[4] = {c.scheme == 2 ? 1.0 : 1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    // closed-form weights of the unknowns away from the fine region:
+    // al_k = sum_{l,s} b_s h (tau_l + off_s h)^k / k!
+    double al[4] = {0, 0, 0, 0};
+    for (int l = 0; l < m; ++l)
+        for (int si = 0; si < ns; ++si) {
+            double cw[4];
+            poly(l * h + st_off[si] * h, cw);
+            for (int k = 0; k < order; ++k) al[k] += st_b[si] * h * cw[k];
+        }
+    const int* hbl = p->lts_hblocks.as<int>();
+    const int* fbl = p->lts_fblocks.as<int>();
+    const int64_t nhb = p->lts_nhb, nfb = p->lts_nfb;
+    const uint32_t* hbmask = p->lts_hbmask.as<uint32_t>();
+    auto rhs_on = [&](const int* bl, int64_t nb) {
+        a.blist = bl;
+        a.nblist = nb;
+    };
 
     if (direction > 0) {
         // filter weights (Section 5.4) at the coarse time levels t_nn = nn H
@@ -134,6 +188,7 @@ void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool
             const double t = nn * H;
             // Taylor coefficients of the solution at t; D_1 = y'(t) is also the
             // derivative the Hermite filter takes at t_nn
+            rhs_on(nullptr, 0);
             for (int k = 1; k < order; ++k) rhs(D[k - 1], D[k], with_src, t, k - 1, nullptr, 0);
             if (filt) {
                 if (c.scheme == 2) {
@@ -152,33 +207,53 @@ void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool
             }
             // the coarse unknowns' contribution, frozen as a polynomial in tau
             for (int k = 0; k < order; ++k) rhs(D[k], W[k], false, 0.0, 0, fine, 1);
-            // fine substeps on z (in place on U = D_0)
-            double cw[4];
-            for (int l = 0; l < m; ++l) {
-                const double tau = l * h;
-                if (c.scheme == 2) {
-                    rhs(U, Kb, with_src, t + tau, 0, fine, 0);
-                    poly(tau, cw);
-                    launch_lts_combine(prec, n, Kb, W, cw, order, U, nullptr, 0.0, 0.5 * h, Zs, 0.0, 0.0, nullptr, st);
-                    rhs(Zs, Kb, with_src, t + tau + 0.5 * h, 0, fine, 0);
-                    poly(tau + 0.5 * h, cw);
-                    launch_lts_combine(prec, n, Kb, W, cw, order, U, nullptr, 0.0, h, U, 0.0, 0.0, nullptr, st);
-                } else {
-                    rhs(U, Kb, with_src, t + tau, 0, fine, 0);
-                    poly(tau, cw);
-                    launch_lts_combine(prec, n, Kb, W, cw, order, U, nullptr, 0.0, 0.5 * h, Zs, 0.0, h / 6.0, Acc,
-                                       st);
-                    rhs(Zs, Kb, with_src, t + tau + 0.5 * h, 0, fine, 0);
-                    poly(tau + 0.5 * h, cw);
-                    launch_lts_combine(prec, n, Kb, W, cw, order, U, Acc, 0.0, 0.5 * h, Zs2, 1.0, h / 3.0, Acc, st);
-                    rhs(Zs2, Kb, with_src, t + tau + 0.5 * h, 0, fine, 0);
-                    launch_lts_combine(prec, n, Kb, W, cw, order, U, Acc, 0.0, h, Zs, 1.0, h / 3.0, Acc, st);
-                    rhs(Zs, Kb, with_src, t + tau + h, 0, fine, 0);
-                    poly(tau + h, cw);
-                    launch_lts_combine(prec, n, Kb, W, cw, order, U, Acc, 1.0, h / 6.0, U, 0.0, 0.0, nullptr, st);
+            // fine substeps on z (in place on U = D_0), only on the halo blocks
+            if (nhb > 0) {
+                rhs_on(hbl, nhb);
+                double cw[4];
+                for (int l = 0; l < m; ++l) {
+                    const double tau = l * h;
+                    if (c.scheme == 2) {
+                        rhs(U, Kb, with_src, t + tau, 0, fine, 0);
+                        poly(tau, cw);
+                        launch_lts_combine(prec, n, np6, hbl, nhb, Kb, W, cw, order, U, nullptr, 0.0, 0.5 * h, Zs,
+                                           0.0, 0.0, nullptr, st);
+                        rhs(Zs, Kb, with_src, t + tau + 0.5 * h, 0, fine, 0);
+                        poly(tau + 0.5 * h, cw);
+                        launch_lts_combine(prec, n, np6, hbl, nhb, Kb, W, cw, order, U, nullptr, 0.0, h, U, 0.0, 0.0,
+                                           nullptr, st);
+                    } else {
+                        rhs(U, Kb, with_src, t + tau, 0, fine, 0);
+                        poly(tau, cw);
+                        launch_lts_combine(prec, n, np6, hbl, nhb, Kb, W, cw, order, U, nullptr, 0.0, 0.5 * h, Zs,
+                                           0.0, h / 6.0, Acc, st);
+                        rhs(Zs, Kb, with_src, t + tau + 0.5 * h, 0, fine, 0);
+                        poly(tau + 0.5 * h, cw);
+                        launch_lts_combine(prec, n, np6, hbl, nhb, Kb, W, cw, order, U, Acc, 0.0, 0.5 * h, Zs2, 1.0,
+                                           h / 3.0, Acc, st);
+                        rhs(Zs2, Kb, with_src, t + tau + 0.5 * h, 0, fine, 0);
+                        launch_lts_combine(prec, n, np6, hbl, nhb, Kb, W, cw, order, U, Acc, 0.0, h, Zs, 1.0,
+                                           h / 3.0, Acc, st);
+                        rhs(Zs, Kb, with_src, t + tau + h, 0, fine, 0);
+                        poly(tau + h, cw);
+                        launch_lts_combine(prec, n, np6, hbl, nhb, Kb, W, cw, order, U, Acc, 1.0, h / 6.0, U, 0.0, 0.0,
+                                           nullptr, st);
+                    }
                 }
             }
+            // every other unknown: z = y + sum_k al_k W_k + the quadrature of F
+            double sc = 0, ss = 0;
+            if (with_src)
+                for (int l = 0; l < m; ++l)
+                    for (int si = 0; si < ns; ++si) {
+                        const double x = w * (t + l * h + st_off[si] * h);
+                        sc += st_b[si] * h * std::cos(x);
+                        ss += st_b[si] * h * std::sin(x);
+                    }
+            launch_lts_closed(prec, n, np6, s.Np, hbmask, W, al, order, with_src ? p->Sre.p : nullptr, p->Sim.p,
+                              p->src_rows, sc, ss, U, st);
         }
+        rhs_on(nullptr, 0);
         if (filt) {
             if (c.scheme == 2) {
                 launch_filter_add(prec, U, 1.0 / M, 0.0, p->Fre.as<double>(), p->Fim.as<double>(), n, st);
@@ -192,49 +267,65 @@ void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool
         return;
     }
 
-    // adjoint of the homogeneous step, M times (S-flipped variables: zbar = U)
+    // adjoint of the homogeneous step, M times (S-flipped variables: zbar = U);
+    // the substeps' vectors live on the halo blocks, B runs on the fine blocks
+    // (only its fine rows are used), the coarse rows' wbar_k = al_k zbar_end
     void* KA = Zs;
     void* KB = Zs2;
     void* Z0 = p->lZ0.p;
     for (int nn = 0; nn < M; ++nn) {
         for (int k = 0; k < order; ++k) launch_zero(WB[k], n * s.esize(), st);
-        double cw[4];
-        for (int l = m - 1; l >= 0; --l) {
-            const double tau = l * h;
-            launch_lts_axpy(prec, n, np6, nullptr, 0, 0.0, nullptr, 1.0, U, Z0, st);  // Z0 = zbar
-            if (c.scheme == 2) {
-                launch_lts_axpy(prec, n, np6, nullptr, 0, 0.0, nullptr, h, Z0, KA, st);  // kbar2 = h zbar
-                poly(tau + 0.5 * h, cw);
-                rhs(KA, Kb, false, 0.0, 0, nullptr, 0);
-                launch_lts_adjoint(prec, n, np6, fine, 0, Kb, U, Z0, 0.0, 0.5 * h, KB, KA, WB, cw, order, st);
-                poly(tau, cw);
-                rhs(KB, Kb, false, 0.0, 0, nullptr, 0);
-                launch_lts_adjoint(prec, n, np6, fine, 0, Kb, U, Z0, 0.0, 0.0, nullptr, KB, WB, cw, order, st);
-            } else {
-                launch_lts_axpy(prec, n, np6, nullptr, 0, 0.0, nullptr, h / 6.0, Z0, KA, st);  // kbar4
-                poly(tau + h, cw);
-                rhs(KA, Kb, false, 0.0, 0, nullptr, 0);
-                launch_lts_adjoint(prec, n, np6, fine, 0, Kb, U, Z0, h / 3.0, h, KB, KA, WB, cw, order, st);
-                poly(tau + 0.5 * h, cw);
-                rhs(KB, Kb, false, 0.0, 0, nullptr, 0);
-                launch_lts_adjoint(prec, n, np6, fine, 0, Kb, U, Z0, h / 3.0, 0.5 * h, KA, KB, WB, cw, order, st);
-                rhs(KA, Kb, false, 0.0, 0, nullptr, 0);
-                launch_lts_adjoint(prec, n, np6, fine, 0, Kb, U, Z0, h / 6.0, 0.5 * h, KB, KA, WB, cw, order, st);
-                poly(tau, cw);
-                rhs(KB, Kb, false, 0.0, 0, nullptr, 0);
-                launch_lts_adjoint(prec, n, np6, fine, 0, Kb, U, Z0, 0.0, 0.0, nullptr, KB, WB, cw, order, st);
+        if (nhb > 0) {
+            double cw[4];
+            for (int l = m - 1; l >= 0; --l) {
+                const double tau = l * h;
+                launch_lts_axpy(prec, n, np6, hbl, nhb, nullptr, 0, 0.0, nullptr, 1.0, U, Z0, st);  // Z0 = zbar
+                if (c.scheme == 2) {
+                    launch_lts_axpy(prec, n, np6, hbl, nhb, nullptr, 0, 0.0, nullptr, h, Z0, KA, st);  // kbar2
+                    poly(tau + 0.5 * h, cw);
+                    rhs_on(fbl, nfb);
+                    rhs(KA, Kb, false, 0.0, 0, nullptr, 0);
+                    launch_lts_adjoint(prec, n, np6, hbl, nhb, fine, 0, Kb, U, Z0, 0.0, 0.5 * h, KB, KA, WB, cw,
+                                       order, st);
+                    poly(tau, cw);
+                    rhs(KB, Kb, false, 0.0, 0, nullptr, 0);
+                    launch_lts_adjoint(prec, n, np6, hbl, nhb, fine, 0, Kb, U, Z0, 0.0, 0.0, nullptr, KB, WB, cw,
+                                       order, st);
+                } else {
+                    launch_lts_axpy(prec, n, np6, hbl, nhb, nullptr, 0, 0.0, nullptr, h / 6.0, Z0, KA, st);  // kbar4
+                    poly(tau + h, cw);
+                    rhs_on(fbl, nfb);
+                    rhs(KA, Kb, false, 0.0, 0, nullptr, 0);
+                    launch_lts_adjoint(prec, n, np6, hbl, nhb, fine, 0, Kb, U, Z0, h / 3.0, h, KB, KA, WB, cw, order,
+                                       st);
+                    poly(tau + 0.5 * h, cw);
+                    rhs(KB, Kb, false, 0.0, 0, nullptr, 0);
+                    launch_lts_adjoint(prec, n, np6, hbl, nhb, fine, 0, Kb, U, Z0, h / 3.0, 0.5 * h, KA, KB, WB, cw,
+                                       order, st);
+                    rhs(KA, Kb, false, 0.0, 0, nullptr, 0);
+                    launch_lts_adjoint(prec, n, np6, hbl, nhb, fine, 0, Kb, U, Z0, h / 6.0, 0.5 * h, KB, KA, WB, cw,
+                                       order, st);
+                    poly(tau, cw);
+                    rhs(KB, Kb, false, 0.0, 0, nullptr, 0);
+                    launch_lts_adjoint(prec, n, np6, hbl, nhb, fine, 0, Kb, U, Z0, 0.0, 0.0, nullptr, KB, WB, cw,
+                                       order, st);
+                }
+                rhs_on(nullptr, 0);
             }
         }
+        // coarse rows: wbar_k = al_k zbar (zbar there is the step's end value)
+        for (int k = 0; k < order; ++k)
+            launch_lts_axpy(prec, n, np6, nullptr, 0, fine, 1, 1.0, WB[k], al[k], U, WB[k], st);
         // dbar_k = (I - P) B wbar_k; dbar_{k-1} += B dbar_k; ybar = zbar + dbar_0
         for (int k = 0; k < order; ++k) {
             rhs(WB[k], Kb, false, 0.0, 0, nullptr, 0);
-            launch_lts_axpy(prec, n, np6, fine, 1, 0.0, nullptr, 1.0, Kb, WB[k], st);
+            launch_lts_axpy(prec, n, np6, nullptr, 0, fine, 1, 0.0, nullptr, 1.0, Kb, WB[k], st);
         }
         for (int k = order - 1; k >= 1; --k) {
             rhs(WB[k], Kb, false, 0.0, 0, nullptr, 0);
-            launch_lts_axpy(prec, n, np6, nullptr, 0, 1.0, WB[k - 1], 1.0, Kb, WB[k - 1], st);
+            launch_lts_axpy(prec, n, np6, nullptr, 0, nullptr, 0, 1.0, WB[k - 1], 1.0, Kb, WB[k - 1], st);
         }
-        launch_lts_axpy(prec, n, np6, nullptr, 0, 1.0, U, 1.0, WB[0], U, st);
+        launch_lts_axpy(prec, n, np6, nullptr, 0, nullptr, 0, 1.0, U, 1.0, WB[0], U, st);
     }
 }
 
