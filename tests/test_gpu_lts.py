@@ -144,11 +144,11 @@ def test_lts_rejected_where_unsupported(lib):
 
 @pytest.mark.parametrize("direction", [1, -1])
 def test_periods_on_a_refined_cube(lib, direction):
-    """A 768-tet cube with a slab of three thin cells (0.05 against 0.2 and
-    0.25): the fine region and its halo span many element blocks, the rest
-    (about half the elements) advances in closed form.  Forward period with
-    source and adjoint period against the oracle's LTS scheme (P1, FP64)."""
-    xyz, tet, tg = inputs.graded_cube_mesh([0, .2, .4, .45, .5, .55, .6, .8, 1.], [0, .25, .5, .75, 1.],
+    """A 576-tet cube with a slab of two thin cells (0.025 against 0.225 and
+    0.25): the fine elements (192) fill 32 of the 58 element blocks, the rest
+    advances in closed form.  Forward period with source and adjoint period
+    against the oracle's LTS scheme (P1, FP64)."""
+    xyz, tet, tg = inputs.graded_cube_mesh([0, .25, .475, .5, .525, .75, 1.], [0, .25, .5, .75, 1.],
                                            [0, .25, .5, .75, 1.])
     K = tet.shape[0]
     eps = np.ones(K)
