@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=4, help="RK steps of the CPU oracle sample")
     ap.add_argument("--kernel-periods", type=int, default=3)
     ap.add_argument("--workload", choices=["large_single", "batched", "serving", "scatterer", "fw", "trap2d",
-                                           "curves2d"],
+                                           "curves2d", "lts"],
                     default="large_single",
                     help="large_single (default bench line), the 64-member batched configuration, or the "
                          "Poisson request stream through the serving engine")
@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--serve-precision", choices=["fp32", "fp64"], default="fp32",
                     help="serving: field precision of the served solves (fp64: the plain form, for comparison)")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: engine memory budget")
+    ap.add_argument("--lts-n", type=int, default=20, help="lts: cells per axis")
+    ap.add_argument("--lts-r", type=int, default=16, help="lts: the thin layers are 1/r of a cell wide")
+    ap.add_argument("--lts-m", type=int, default=4, help="lts: fine substeps per coarse step")
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="default line: requests of the short served stream")
     ap.add_argument("--no-extra", action="store_true",
@@ -732,6 +735,86 @@ def fw_compare(a):
     print(json.dumps(out), flush=True)
 
 
+def lts_compare(a):
+    """Local time stepping against global stepping on a locally refined mesh:
+    the unit cube with --lts-n cells per axis whose middle x-cell is split so
+    that two of its layers are --lts-r times thinner than a cell (a slab of
+    elements with a much shorter CFL step), P2, eps = mu = 1, omega = 4 pi,
+    impedance walls, Gaussian source at the centre.  Both CMCG solves to --tol with FP64 fields: time per period
+    (forward, HIP events) and per solve, and the difference of the two
+    filtered fields (each carries its own time-discretisation error)."""
+    import numpy as np
+    import torch
+
+    from paper_2106_02858_amd import cmcg, inputs
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    n, r = a.lts_n, a.lts_r
+    c = n // 2
+    # the middle x-cell split into two thin cells of width 1/(r n) around its
+    # centre and two ordinary ones
+    mid = np.array([c, c + 0.5 - 1.0 / r, c + 0.5, c + 0.5 + 1.0 / r]) / n
+    xs = np.concatenate([np.arange(c) / n, mid, np.arange(c + 1, n + 1) / n])
+    ys = np.arange(n + 1) / n
+    xyz, tet, tags = inputs.graded_cube_mesh(xs, ys, ys)
+    K = tet.shape[0]
+    mesh = cmcg.cmcg_mesh_create(xyz, tet, tags)
+    s = cmcg.cmcg_space_create(mesh, 2, cmcg.CMCG_FP64)
+    nodes = cmcg.cmcg_space_nodes(s)
+    omega = 4 * math.pi
+    jd = torch.tensor(inputs.gaussian_current(nodes, (0.5, 0.5, 0.5), 0.1, 2), dtype=torch.float64, device=dev)
+    p = cmcg.cmcg_problem_create_device(s, np.ones(K), np.ones(K), None, omega, jd)
+    info = cmcg.cmcg_space_info(s)
+    Np = info["Np"]
+    stream = torch.cuda.current_stream()
+    U0 = torch.randn((K, 6, Np), dtype=torch.float64, device=dev) * 1e-3
+    UT = torch.empty_like(U0)
+    rows = {}
+    fields = {}
+    for name, ratio in (("global", 0), ("lts", a.lts_m)):
+        o = cmcg.cmcg_options_default(tol=a.tol, max_iter=2000, lts_ratio=ratio, autotune=0 if a.no_autotune else 1)
+        M, dt = cmcg.cmcg_problem_steps(p, o)
+        cmcg.cmcg_debug_period(p, U0, UT, 1, False, opts=o)  # warm-up (graphs, buffers)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        cmcg.cmcg_debug_period(p, U0, UT, 1, False, opts=o)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        per_fwd = ev0.elapsed_time(ev1) / 1e3
+        ev0.record(stream)
+        cmcg.cmcg_debug_period(p, U0, UT, -1, False, opts=o)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        per_bwd = ev0.elapsed_time(ev1) / 1e3
+        res = cmcg.cmcg_solve(p, o)
+        st = cmcg.cmcg_result_stats(res)
+        f = [torch.empty((K, 6, Np), dtype=torch.float64, device=dev) for _ in range(2)]
+        cmcg.cmcg_result_filtered_device(res, *f)
+        fields[name] = f
+        rows[name] = {"steps_per_period": M, "dt": dt, "period_forward_s": per_fwd, "period_backward_s": per_bwd,
+                      "iters": st["iters"], "rel_res": st["rel_res"], "seconds": st["seconds"],
+                      "time_to_1e-6_s": st["seconds_to_1e6"]}
+        if ratio > 1:
+            rows[name]["fine_elements"] = int(cmcg.cmcg_problem_lts_fine(p, K, o).sum())
+            rows[name]["substeps"] = ratio
+        log(f"{name}: M = {M}, period fwd {per_fwd * 1e3:.2f} ms bwd {per_bwd * 1e3:.2f} ms, "
+            f"{st['iters']} iterations, {st['seconds']:.2f} s")
+    d = [x - y for x, y in zip(fields["lts"], fields["global"])]
+    den = sum(cmcg.cmcg_debug_dot(p, x, x) for x in fields["global"])
+    diff = math.sqrt(sum(cmcg.cmcg_debug_dot(p, x, x) for x in d) / den)
+    g, l = rows["global"], rows["lts"]
+    out = {"metric": "CMCG time with local time stepping vs global stepping on a locally refined mesh",
+           "value": g["seconds"] / l["seconds"], "unit": "speedup", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": l["seconds"] * 1e3, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"unit cube, {n} cells per axis, the middle x-cell split into {r} (a thin slab), "
+                                  f"{K} tets, P2, omega = 4 pi, impedance walls; CMCG to {a.tol:g}, FP64 fields",
+                      "K": K, "q": 2},
+           "global": g, "lts": l, "filtered_rel_diff": diff,
+           "period_speedup": g["period_forward_s"] / l["period_forward_s"]}
+    print(json.dumps(out), flush=True)
+
+
 def served(a):
     """The request stream (n in {8,12,16,24}, q in {1,2,3}, omega in [2pi,8pi],
     eps per cube in {1,2,4}, Poisson arrivals) through the serving engine."""
@@ -786,6 +869,9 @@ def main():
         return
     if a.workload == "fw":
         fw_compare(a)
+        return
+    if a.workload == "lts":
+        lts_compare(a)
         return
     import numpy as np
     import torch
