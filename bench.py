@@ -70,6 +70,10 @@ def parse():
     ap.add_argument("--serve-precision", choices=["fp32", "fp64"], default="fp32",
                     help="serving: field precision of the served solves (fp64: the plain form, for comparison)")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: engine memory budget")
+    ap.add_argument("--cobatch", type=int, default=1,
+                    help="serving: queued requests on one space (n, q) that may share a slot and run as one "
+                         "batched solve (1: every request alone); the short served stream of the default run "
+                         "is also measured with 4")
     ap.add_argument("--lts-n", type=int, default=20, help="lts: cells per axis")
     ap.add_argument("--lts-r", type=int, default=16, help="lts: the thin layers are 1/r of a cell wide")
     ap.add_argument("--lts-m", type=int, default=4, help="lts: fine substeps per coarse step")
@@ -826,7 +830,7 @@ def served(a):
     reqs = inputs.serving_stream(n_requests=2000, rate=a.rate)[: a.requests]
     fp64 = a.serve_precision == "fp64"
     out = serving.serve(reqs, budget_bytes=int(a.budget_gb * 2 ** 30), max_slots=a.slots, tol=a.tol,
-                        precision=cmcg.CMCG_FP64 if fp64 else cmcg.CMCG_FP32, log=log)
+                        precision=cmcg.CMCG_FP64 if fp64 else cmcg.CMCG_FP32, log=log, cobatch=a.cobatch)
     svc = np.array([r["done"] - r["admitted"] for r in out["records"]])
     res = {"metric": "DG dof-updates/s; CMCG time-to-1e-6 residual vs FP64 plain; p50/p99 latency",
            "value": out["dof_updates_per_s"], "unit": "dof-updates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
@@ -835,9 +839,10 @@ def served(a):
            "config": {"workload": f"serving: first {a.requests} requests of the 2000-request Poisson stream at "
                                   f"{a.rate:g} req/s (n in 8,12,16,24; q in 1,2,3), {a.slots} slots, "
                                   f"{a.budget_gb:g} GB budget, CMCG to {a.tol:g}, "
-                                  f"{'plain FP64' if fp64 else 'FP32'} fields"},
+                                  f"{'plain FP64' if fp64 else 'FP32'} fields, co-batching up to {a.cobatch}"},
            "serving": {**{k: out[k] for k in ("completed", "elapsed", "throughput", "p50", "p99", "offered_rate",
                                               "engine_steps")},
+                       "co_batched_requests": sum(1 for r in out["records"] if r["members"] > 1),
                        "service_p50": float(np.percentile(svc, 50)), "service_p99": float(np.percentile(svc, 99))}}
     byts = sum(r["dof_updates"] * method_bytes_per_dof_update(r["q"], 8 if fp64 else 4) for r in out["records"])
     res["hbm_job"] = job_roofline(out["dof_updates_per_s"], byts / max(1.0, sum(r["dof_updates"] for r in out["records"])))
@@ -1013,7 +1018,8 @@ def main():
         # batched launch with every member active, and a short served stream
         out["roofline_scatterer"] = scatterer_kernel(a)
         out["roofline_batched"] = batched_kernel(a)
-        out["serving"] = serving_short(a)
+        out["serving"] = serving_short(a, a.cobatch)
+        out["serving_cobatch4"] = serving_short(a, 4)
     if not a.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
@@ -1111,23 +1117,26 @@ def batched_kernel(a) -> dict:
             "variant_us": us, "traffic": None}
 
 
-def serving_short(a) -> dict:
+def serving_short(a, cobatch: int) -> dict:
     """The head of the 20 req/s request stream through the serving engine
-    (FP32 fields, CMCG to 1e-6): latency p50 / p99 and throughput."""
+    (FP32 fields, CMCG to 1e-6): latency p50 / p99 and throughput; up to
+    `cobatch` queued requests on one space share a slot."""
     import numpy as np
 
     from paper_2106_02858_amd import cmcg, inputs, serving
     _free_device()
     reqs = inputs.serving_stream(n_requests=2000, rate=a.rate)[: a.serve_requests]
     out = serving.serve(reqs, budget_bytes=int(a.budget_gb * 2 ** 30), max_slots=a.slots, tol=a.tol,
-                        precision=cmcg.CMCG_FP32, log=log)
+                        precision=cmcg.CMCG_FP32, log=log, cobatch=cobatch)
     svc = np.array([r["done"] - r["admitted"] for r in out["records"]])
     byts = sum(r["dof_updates"] * method_bytes_per_dof_update(r["q"], 4) for r in out["records"])
     dofs = max(1.0, sum(r["dof_updates"] for r in out["records"]))
     _free_device()
     return {"workload": f"first {a.serve_requests} requests of the 2000-request Poisson stream at {a.rate:g} req/s "
-                        f"(n in 8,12,16,24; q in 1,2,3), {a.slots} slots, FP32 fields, CMCG to {a.tol:g}",
+                        f"(n in 8,12,16,24; q in 1,2,3), {a.slots} slots, FP32 fields, CMCG to {a.tol:g}, "
+                        f"co-batching up to {cobatch}",
             **{k: out[k] for k in ("completed", "elapsed", "throughput", "p50", "p99", "offered_rate")},
+            "co_batched_requests": sum(1 for r in out["records"] if r["members"] > 1),
             "rejected": len(out["rejected"]), "service_p50": float(np.percentile(svc, 50)),
             "service_p99": float(np.percentile(svc, 99)), "dof_updates_per_s": out["dof_updates_per_s"],
             "hbm_job": job_roofline(out["dof_updates_per_s"], byts / dofs)}

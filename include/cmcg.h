@@ -437,6 +437,27 @@ int cmcg_engine_poll(const cmcg_engine* e, int slot, int* state);
 int cmcg_engine_collect(cmcg_engine* e, int slot, cmcg_result** out);
 int cmcg_engine_cancel(cmcg_engine* e, int slot);
 int cmcg_engine_info(const cmcg_engine* e, size_t* used, int* n_running, int* n_finished);
+/* Co-batching: n (1..65535) requests on one space (same mesh, order and
+ * field precision) admitted into one slot and solved together by the batched
+ * path of cmcg_solve_batch (one launch per Runge-Kutta stage for every
+ * member), so small requests fill the device together.  Each member's result
+ * equals the one cmcg_solve returns for it alone.  The solve runs on a worker
+ * thread that uses the slot's stream; cmcg_engine_step reports the slot
+ * finished once it has ended.  Admission cost: the members' summed
+ * footprints.  Errors as cmcg_engine_admit, and CMCG_ERR_ARG when the
+ * problems do not share a space, repeat, or ask for local time stepping.
+ * o->progress is not called and o->autotune is ignored.
+ * cmcg_engine_slot_members: members of a slot (0 free, 1 for a single solve).
+ * cmcg_engine_collect_batch: hands over the n results of a finished
+ *   co-batched slot (caller-owned) and frees the slot; returns
+ *   CMCG_NOT_CONVERGED when a member stopped at max_iter, the batched solve's
+ *   error code (no results) when it failed.  cmcg_engine_collect refuses a
+ *   co-batched slot (CMCG_ERR_STATE); cmcg_engine_cancel waits for its solve
+ *   to end. */
+int cmcg_engine_admit_batch(cmcg_engine* e, cmcg_problem* const* problems, int n, const cmcg_options* o,
+                            int* slot);
+int cmcg_engine_slot_members(const cmcg_engine* e, int slot, int* n);
+int cmcg_engine_collect_batch(cmcg_engine* e, int slot, cmcg_result** results, int n);
 
 /* ------------------------------------------------------------- tuning -- */
 /* Stage-kernel implementation variant for (q, precision): 0 gathers each

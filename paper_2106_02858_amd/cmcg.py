@@ -56,6 +56,7 @@ EXPORTED = [
     "cmcg_autotune_stage", "cmcg_autotune_batch", "cmcg_mesh_locality_order",
     "cmcg_problem_footprint", "cmcg_engine_create", "cmcg_engine_destroy", "cmcg_engine_admit",
     "cmcg_engine_step", "cmcg_engine_poll", "cmcg_engine_collect", "cmcg_engine_cancel", "cmcg_engine_info",
+    "cmcg_engine_admit_batch", "cmcg_engine_slot_members", "cmcg_engine_collect_batch",
 ]
 
 
@@ -132,6 +133,9 @@ _sig = {
     "cmcg_engine_collect": (C.c_int, [P, C.c_int, C.POINTER(P)]),
     "cmcg_engine_cancel": (C.c_int, [P, C.c_int]),
     "cmcg_engine_info": (C.c_int, [P, C.POINTER(C.c_size_t), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "cmcg_engine_admit_batch": (C.c_int, [P, P, C.c_int, C.POINTER(cmcg_options), C.POINTER(C.c_int)]),
+    "cmcg_engine_slot_members": (C.c_int, [P, C.c_int, C.POINTER(C.c_int)]),
+    "cmcg_engine_collect_batch": (C.c_int, [P, C.c_int, P, C.c_int]),
     "cmcg_mesh_locality_order": (C.c_int, [C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "cmcg_tune_get_stage": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
     "cmcg_autotune_stage": (C.c_int, [P, C.POINTER(cmcg_options), C.c_void_p, C.POINTER(C.c_int),
@@ -542,6 +546,34 @@ def cmcg_engine_collect(e: Engine, slot: int, problem: Problem | None = None) ->
     h = P()
     _check(_lib.cmcg_engine_collect(e.h, slot, C.byref(h)), allow=(CMCG_OK, CMCG_NOT_CONVERGED))
     return Result(h, keep=(problem,) if problem is not None else ())
+
+
+def cmcg_engine_admit_batch(e: Engine, problems, opts: cmcg_options | None = None):
+    """Slot index of a co-batched slot holding `problems` (one space), or None
+    when it does not fit now.  Raises CmcgError (CMCG_ERR_TOO_LARGE) when it
+    never can."""
+    o = opts or cmcg_options_default()
+    n = len(problems)
+    arr = (P * n)(*[p.h for p in problems])
+    slot = C.c_int(-1)
+    rc = _lib.cmcg_engine_admit_batch(e.h, arr, n, C.byref(o), C.byref(slot))
+    if rc == CMCG_ERR_NOMEM:
+        return None
+    _check(rc)
+    return slot.value
+
+
+def cmcg_engine_slot_members(e: Engine, slot: int) -> int:
+    n = C.c_int()
+    _check(_lib.cmcg_engine_slot_members(e.h, slot, C.byref(n)))
+    return n.value
+
+
+def cmcg_engine_collect_batch(e: Engine, slot: int, problems) -> list:
+    n = len(problems)
+    res = (P * n)()
+    _check(_lib.cmcg_engine_collect_batch(e.h, slot, res, n), allow=(CMCG_OK, CMCG_NOT_CONVERGED))
+    return [Result(P(res[b]), keep=(problems[b],)) for b in range(n)]
 
 
 def cmcg_engine_cancel(e: Engine, slot: int):

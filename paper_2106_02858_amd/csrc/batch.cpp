@@ -45,7 +45,7 @@ struct Batch {
 
 // Stage scalars of every member for every (step, stage), plus one row (step
 // Mmax, stage 0) with the last filter level t = T_b of each member.
-void build_table(Batch& bt) {
+void build_table(Batch& bt, hipStream_t st) {
     const int B = bt.B, S = bt.S;
     std::vector<double> tab((size_t)(bt.Mmax + 1) * S * B * kMemberParams, 0.0);
     std::vector<double> fwr(B), fwi(B);
@@ -118,11 +118,14 @@ void build_table(Batch& bt) {
         fwi[b] = 0.0;
     }
     bt.mtab.alloc(tab.size() * 8);
-    CMCG_HIP(hipMemcpy(bt.mtab.p, tab.data(), tab.size() * 8, hipMemcpyHostToDevice));
     bt.fw_re.alloc(B * 8);
     bt.fw_im.alloc(B * 8);
-    CMCG_HIP(hipMemcpy(bt.fw_re.p, fwr.data(), B * 8, hipMemcpyHostToDevice));
-    CMCG_HIP(hipMemcpy(bt.fw_im.p, fwi.data(), B * 8, hipMemcpyHostToDevice));
+    // stream-ordered copies (no legacy-stream work: a batch may run on a
+    // worker thread while another thread captures a graph)
+    CMCG_HIP(hipMemcpyAsync(bt.mtab.p, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, st));
+    CMCG_HIP(hipMemcpyAsync(bt.fw_re.p, fwr.data(), B * 8, hipMemcpyHostToDevice, st));
+    CMCG_HIP(hipMemcpyAsync(bt.fw_im.p, fwi.data(), B * 8, hipMemcpyHostToDevice, st));
+    CMCG_HIP(hipStreamSynchronize(st));
 }
 
 StageArgs batch_args(Batch& bt) {
@@ -390,9 +393,10 @@ void setup_batch(Batch& bt, cmcg_problem* const* probs, int B, const cmcg_option
     {
         std::vector<int> ms(B);
         for (int b = 0; b < B; ++b) ms[b] = bt.cfg[b].M;
-        CMCG_HIP(hipMemcpy(bt.msteps.p, ms.data(), B * sizeof(int), hipMemcpyHostToDevice));
+        CMCG_HIP(hipMemcpyAsync(bt.msteps.p, ms.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+        CMCG_HIP(hipStreamSynchronize(st));
     }
-    build_table(bt);
+    build_table(bt, st);
     std::vector<int> act(B, 1);
     set_active(bt, act, st);
 }

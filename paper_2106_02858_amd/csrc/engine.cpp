@@ -14,9 +14,27 @@
 // chunk has completed, so a short solve is never held back by a long one on
 // another slot; it blocks (polling) only until at least one slot has
 // advanced.
+#include <atomic>
 #include <thread>
 
 #include "objects.h"
+
+// A co-batched slot: requests on one space solved together by the batched
+// path (cmcg_solve_batch's launches, one per Runge-Kutta stage for every
+// member) on a worker thread that owns the slot's stream.
+struct BatchJob {
+    std::vector<cmcg_problem*> probs;
+    cmcg_options o{};
+    std::vector<cmcg_result*> res;
+    std::atomic<bool> done{false};
+    int code = 0;
+    std::string msg;
+    std::thread th;
+    ~BatchJob() {
+        if (th.joinable()) th.join();
+        for (auto* r : res) delete r;
+    }
+};
 
 struct cmcg_engine {
     struct Slot {
@@ -26,14 +44,23 @@ struct cmcg_engine {
         hipStream_t st = nullptr;
         std::unique_ptr<cmcg::CgRun> run;
         std::unique_ptr<cmcg_result> result;
+        std::unique_ptr<BatchJob> job;  // co-batched slot
         int err = 0;
         std::string msg;
+        bool holds(const cmcg_problem* q) const {
+            if (p == q) return true;
+            if (job)
+                for (auto* b : job->probs)
+                    if (b == q) return true;
+            return false;
+        }
     };
     int device = 0;
     size_t budget = 0, used = 0;
     std::vector<Slot> slots;
     ~cmcg_engine() {
         for (auto& s : slots) {
+            s.job.reset();  // joins a running worker
             if (s.st) {
                 (void)hipStreamSynchronize(s.st);
                 (void)hipStreamDestroy(s.st);
@@ -115,7 +142,7 @@ int cmcg_engine_admit(cmcg_engine* e, cmcg_problem* p, const cmcg_options* o, in
     int free_slot = -1;
     for (int i = 0; i < (int)e->slots.size(); ++i) {
         const auto& s = e->slots[i];
-        if (s.state != 0 && s.p == p) fail(CMCG_ERR_STATE, "engine_admit: problem already held by a slot");
+        if (s.state != 0 && s.holds(p)) fail(CMCG_ERR_STATE, "engine_admit: problem already held by a slot");
         if (s.state == 0 && free_slot < 0) free_slot = i;
     }
     const size_t need = footprint(p);
@@ -142,6 +169,117 @@ int cmcg_engine_admit(cmcg_engine* e, cmcg_problem* p, const cmcg_options* o, in
     ENGINE_GUARD_END
 }
 
+int cmcg_engine_admit_batch(cmcg_engine* e, cmcg_problem* const* problems, int n, const cmcg_options* o,
+                            int* slot) {
+    ENGINE_GUARD_BEGIN
+    if (!e || !problems || !slot || n < 1) fail(CMCG_ERR_ARG, "engine_admit_batch: NULL argument or empty batch");
+    *slot = -1;
+    if (n > 65535) fail(CMCG_ERR_ARG, "engine_admit_batch: at most 65535 problems per batch");
+    if (current_device() != e->device) fail(CMCG_ERR_STATE, "engine_admit_batch: wrong current device");
+    cmcg_options def;
+    cmcg_options_default(&def);
+    if (!o) o = &def;
+    if (o->lts_ratio > 1) fail(CMCG_ERR_ARG, "engine_admit_batch: local time stepping is for single solves");
+    size_t need = 0;
+    for (int b = 0; b < n; ++b) {
+        if (!problems[b]) fail(CMCG_ERR_ARG, "engine_admit_batch: NULL problem");
+        if (problems[b]->sp != problems[0]->sp) fail(CMCG_ERR_ARG, "engine_admit_batch: members must share a space");
+        if (problems[b]->nharm != 1) fail(CMCG_ERR_ARG, "engine_admit_batch: several-frequency problems are single");
+        for (int c = 0; c < b; ++c)
+            if (problems[c] == problems[b]) fail(CMCG_ERR_ARG, "engine_admit_batch: a problem appears twice");
+        need += footprint(problems[b]);
+    }
+    if (need > e->budget)
+        fail(CMCG_ERR_TOO_LARGE, "engine_admit_batch: footprint " + std::to_string(need) + " B exceeds the budget " +
+                                     std::to_string(e->budget) + " B");
+    int free_slot = -1;
+    for (int i = 0; i < (int)e->slots.size(); ++i) {
+        const auto& s = e->slots[i];
+        for (int b = 0; b < n; ++b)
+            if (s.state != 0 && s.holds(problems[b]))
+                fail(CMCG_ERR_STATE, "engine_admit_batch: a problem is already held by a slot");
+        if (s.state == 0 && free_slot < 0) free_slot = i;
+    }
+    if (free_slot < 0) fail(CMCG_ERR_NOMEM, "engine_admit_batch: no free slot");
+    if (e->used + need > e->budget) fail(CMCG_ERR_NOMEM, "engine_admit_batch: over the memory budget");
+    auto& s = e->slots[free_slot];
+    std::unique_ptr<BatchJob> job(new BatchJob());
+    job->probs.assign(problems, problems + n);
+    job->o = *o;
+    job->o.autotune = 0;           // the stage variant is process-wide and slots run concurrently
+    job->o.progress = nullptr;     // no host callbacks from the worker thread
+    // no graph capture on the worker thread: while a stream captures, the
+    // runtime refuses legacy-stream work (synchronous copies, a caller's
+    // default-stream kernels) from every other thread of the process
+    job->o.use_graph = 0;
+    job->res.assign(n, nullptr);
+    BatchJob* jp = job.get();
+    const int dev = e->device;
+    hipStream_t st = s.st;
+    job->th = std::thread([jp, dev, st] {
+        try {
+            CMCG_HIP(hipSetDevice(dev));
+            solve_batch(jp->probs.data(), (int)jp->probs.size(), &jp->o, st, jp->res.data());
+        } catch (const Error& err) {
+            jp->code = err.code;
+            jp->msg = err.msg;
+        } catch (const std::exception& err) {
+            jp->code = CMCG_ERR_ARG;
+            jp->msg = err.what();
+        }
+        jp->done.store(true, std::memory_order_release);
+    });
+    s.job = std::move(job);
+    s.state = 1;
+    s.p = nullptr;
+    s.bytes = need;
+    s.err = 0;
+    s.msg.clear();
+    e->used += need;
+    *slot = free_slot;
+    return CMCG_OK;
+    ENGINE_GUARD_END
+}
+
+int cmcg_engine_slot_members(const cmcg_engine* e, int slot, int* n) {
+    ENGINE_GUARD_BEGIN
+    if (!e || !n || slot < 0 || slot >= (int)e->slots.size()) fail(CMCG_ERR_ARG, "engine_slot_members: bad argument");
+    const auto& s = e->slots[slot];
+    *n = s.state == 0 ? 0 : (s.job ? (int)s.job->probs.size() : 1);
+    return CMCG_OK;
+    ENGINE_GUARD_END
+}
+
+int cmcg_engine_collect_batch(cmcg_engine* e, int slot, cmcg_result** out, int n) {
+    ENGINE_GUARD_BEGIN
+    if (!e || !out || slot < 0 || slot >= (int)e->slots.size()) fail(CMCG_ERR_ARG, "engine_collect_batch: bad argument");
+    auto& s = e->slots[slot];
+    if (!s.job) fail(CMCG_ERR_STATE, "engine_collect_batch: not a co-batched slot");
+    if (s.state != 2 && s.state != 3) fail(CMCG_ERR_STATE, "engine_collect_batch: slot has no finished solve");
+    if (n != (int)s.job->probs.size()) fail(CMCG_ERR_ARG, "engine_collect_batch: wrong member count");
+    const int code = s.state == 3 ? s.err : CMCG_OK;
+    const std::string msg = s.msg;
+    int status = CMCG_OK;
+    for (int b = 0; b < n; ++b) {
+        out[b] = s.job->res[b];
+        if (out[b] && out[b]->st.status != CMCG_OK) status = CMCG_NOT_CONVERGED;
+        s.job->res[b] = nullptr;
+    }
+    e->used -= s.bytes;
+    s.job.reset();
+    s.state = 0;
+    s.bytes = 0;
+    if (code != CMCG_OK) {
+        for (int b = 0; b < n; ++b) {
+            delete out[b];
+            out[b] = nullptr;
+        }
+        fail(code, "engine_collect_batch: the batched solve failed: " + msg);
+    }
+    return status;
+    ENGINE_GUARD_END
+}
+
 int cmcg_engine_step(cmcg_engine* e, int* n_running, int* n_finished) {
     ENGINE_GUARD_BEGIN
     if (!e) fail(CMCG_ERR_ARG, "engine_step: NULL engine");
@@ -151,6 +289,16 @@ int cmcg_engine_step(cmcg_engine* e, int* n_running, int* n_finished) {
         for (auto& s : e->slots) {
             if (s.state != 1) continue;
             any = true;
+            if (s.job) {  // co-batched slot: its worker thread runs the whole solve
+                if (s.job->done.load(std::memory_order_acquire)) {
+                    s.job->th.join();
+                    s.state = s.job->code == 0 ? 2 : 3;
+                    s.err = s.job->code;
+                    s.msg = s.job->msg;
+                    advanced = true;
+                }
+                continue;
+            }
             try {
                 const hipError_t q = hipStreamQuery(s.st);
                 if (q == hipErrorNotReady) {
@@ -202,6 +350,7 @@ int cmcg_engine_collect(cmcg_engine* e, int slot, cmcg_result** out) {
     if (!e || !out || slot < 0 || slot >= (int)e->slots.size()) fail(CMCG_ERR_ARG, "engine_collect: bad argument");
     *out = nullptr;
     auto& s = e->slots[slot];
+    if (s.job) fail(CMCG_ERR_STATE, "engine_collect: a co-batched slot is collected with engine_collect_batch");
     if (s.state != 2 && s.state != 3) fail(CMCG_ERR_STATE, "engine_collect: slot has no finished solve");
     const int code = s.state == 3 ? s.err : CMCG_OK;
     const std::string msg = s.msg;
@@ -223,6 +372,7 @@ int cmcg_engine_cancel(cmcg_engine* e, int slot) {
     if (!e || slot < 0 || slot >= (int)e->slots.size()) fail(CMCG_ERR_ARG, "engine_cancel: bad argument");
     auto& s = e->slots[slot];
     if (s.state == 0) fail(CMCG_ERR_STATE, "engine_cancel: slot is free");
+    s.job.reset();  // a co-batched solve runs to its end first (joins its worker)
     CMCG_HIP(hipStreamSynchronize(s.st));
     e->used -= s.bytes;
     s.run.reset();

@@ -46,9 +46,13 @@ def build_problem(cache: SpaceCache, req):
 
 
 def serve(requests, budget_bytes: int, max_slots: int, precision=cmcg.CMCG_FP32, tol: float = 1e-6,
-          max_iter: int = 2000, time_scale: float = 1.0, log=None, keep_results: bool = False):
+          max_iter: int = 2000, time_scale: float = 1.0, log=None, keep_results: bool = False,
+          cobatch: int = 1):
     """Serve `requests` (dicts with "arrival" and the recipe fields of
     inputs.serving_stream).  time_scale > 1 compresses the arrival clock.
+    cobatch > 1: when the head of the queue has queued requests on the same
+    space (n, q), up to `cobatch` of them share one slot and are solved
+    together by the batched launches (each result equals its solo solve).
     Returns a dict with latencies, throughput and per-request records."""
     engine = cmcg.cmcg_engine_create(budget_bytes, max_slots)
     cache = SpaceCache(precision)
@@ -77,6 +81,25 @@ def serve(requests, budget_bytes: int, max_slots: int, precision=cmcg.CMCG_FP32,
             req = queue[0]
             prob = req.get("_problem") or build_problem(cache, req)
             req["_problem"] = prob
+            if cobatch > 1:
+                group = [r for r in queue if (r["n"], r["q"]) == (req["n"], req["q"])][:cobatch]
+                if len(group) > 1:
+                    for r in group:
+                        r["_problem"] = r.get("_problem") or build_problem(cache, r)
+                    try:
+                        slot = cmcg.cmcg_engine_admit_batch(engine, [r["_problem"] for r in group], opts)
+                    except cmcg.CmcgError as err:
+                        if err.code != cmcg.CMCG_ERR_TOO_LARGE:
+                            raise
+                        slot = None  # too large together: admit the head alone
+                    else:
+                        if slot is None and slots:
+                            break
+                    if slot is not None:
+                        for r in group:
+                            queue.remove(r)
+                        slots[slot] = (group, [r["_problem"] for r in group], now())
+                        continue
             try:
                 slot = cmcg.cmcg_engine_admit(engine, prob, opts)
             except cmcg.CmcgError as err:
@@ -95,7 +118,7 @@ def serve(requests, budget_bytes: int, max_slots: int, precision=cmcg.CMCG_FP32,
                     log(f"rejected {req['id']} n={req['n']} q={req['q']}: does not fit the budget")
                 continue
             queue.popleft()
-            slots[slot] = (req, prob, now())
+            slots[slot] = ([req], [prob], now())
         if not slots:
             if pending:  # idle until the next arrival
                 wait = (pending[0]["arrival"] - now()) / time_scale
@@ -106,20 +129,25 @@ def serve(requests, budget_bytes: int, max_slots: int, precision=cmcg.CMCG_FP32,
         steps += 1
         for slot in list(slots):
             if cmcg.cmcg_engine_poll(engine, slot) >= 2:
-                req, prob, t_adm = slots.pop(slot)
-                res = cmcg.cmcg_engine_collect(engine, slot, prob)
+                reqs_in, probs_in, t_adm = slots.pop(slot)
+                if len(reqs_in) > 1:
+                    res_list = cmcg.cmcg_engine_collect_batch(engine, slot, probs_in)
+                else:
+                    res_list = [cmcg.cmcg_engine_collect(engine, slot, probs_in[0])]
                 t_done = now()
-                st = cmcg.cmcg_result_stats(res)
-                rec = dict(id=req["id"], n=req["n"], q=req["q"], omega=req["omega"], arrival=req["arrival"],
-                           admitted=t_adm, done=t_done, latency=t_done - req["arrival"], iters=st["iters"],
-                           rel_res=st["rel_res"], dof_updates=st["dof_updates"])
-                records.append(rec)
-                if keep_results:
-                    results[req["id"]] = res
-                req.pop("_problem", None)
-                if log:
-                    log(f"done {req['id']} n={req['n']} q={req['q']} iters={st['iters']} "
-                        f"latency={rec['latency']:.2f}s queue={len(queue)} running={len(slots)}")
+                for req, res in zip(reqs_in, res_list):
+                    st = cmcg.cmcg_result_stats(res)
+                    rec = dict(id=req["id"], n=req["n"], q=req["q"], omega=req["omega"], arrival=req["arrival"],
+                               admitted=t_adm, done=t_done, latency=t_done - req["arrival"], iters=st["iters"],
+                               rel_res=st["rel_res"], dof_updates=st["dof_updates"], members=len(reqs_in))
+                    records.append(rec)
+                    if keep_results:
+                        results[req["id"]] = res
+                    req.pop("_problem", None)
+                    if log:
+                        log(f"done {req['id']} n={req['n']} q={req['q']} iters={st['iters']} "
+                            f"members={len(reqs_in)} latency={rec['latency']:.2f}s queue={len(queue)} "
+                            f"running={len(slots)}")
     elapsed = now()
     lat = np.array([r["latency"] for r in records])
     out = dict(completed=len(records), elapsed=elapsed, engine_steps=steps,

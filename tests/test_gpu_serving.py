@@ -104,3 +104,50 @@ def test_request_larger_than_the_budget_is_rejected(lib):
     out = serving.serve(reqs, budget_bytes=small, max_slots=2, precision=1, tol=1e-6)
     assert out["completed"] == 1 and out["records"][0]["id"] == reqs[2]["id"]
     assert [r["id"] for r in out["rejected"]] == [reqs[0]["id"], reqs[1]["id"]]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cobatched_results_equal_solo_solves_and_the_oracle(lib, precision):
+    """Requests on the same space share one slot and run as one batched solve
+    (one launch per Runge-Kutta stage for every member); each served result
+    still equals the request solved alone, bit for bit, and the oracle's CMCG
+    at the served iteration count."""
+    from paper_2106_02858_amd import serving
+    reqs = inputs.serving_stream(n_requests=10, rate=500.0, seed=21, sizes=(1, 2), orders=(1, 2))
+    out = serving.serve(reqs, budget_bytes=1 << 34, max_slots=3, precision=precision, tol=1e-7,
+                        keep_results=True, cobatch=4)
+    assert out["completed"] == len(reqs)
+    assert max(r["members"] for r in out["records"]) > 1
+    cache = serving.SpaceCache(precision)
+    for rec in out["records"]:
+        req = next(r for r in reqs if r["id"] == rec["id"])
+        prob = serving.build_problem(cache, req)
+        alone = lib.cmcg_solve(prob, lib.cmcg_options_default(tol=1e-7, max_iter=2000))
+        s, _ = cache.get(req["n"], req["q"])
+        info = lib.cmcg_space_info(s)
+        a = filtered(lib, out["results"][rec["id"]], info["K"], info["Np"])
+        assert lib.cmcg_result_stats(alone)["iters"] == rec["iters"]
+        assert np.array_equal(a, filtered(lib, alone, info["K"], info["Np"])), rec
+        ref = oracle_solve(req, rec["iters"])
+        assert dg.norm(ref.p, a - ref.F) / dg.norm(ref.p, ref.F) <= (1e-11 if precision == 0 else 1e-5), rec
+
+
+def test_cobatched_slot_interface(lib):
+    from paper_2106_02858_amd import serving
+    reqs = inputs.serving_stream(n_requests=3, rate=10.0, seed=3, sizes=(2,), orders=(2,))
+    cache = serving.SpaceCache(1)
+    probs = [serving.build_problem(cache, r) for r in reqs]
+    e = lib.cmcg_engine_create(1 << 33, 2)
+    slot = lib.cmcg_engine_admit_batch(e, probs[:2])
+    assert lib.cmcg_engine_slot_members(e, slot) == 2
+    with pytest.raises(lib.CmcgError) as err:
+        lib.cmcg_engine_admit(e, probs[0])                 # held by the co-batched slot
+    assert err.value.code == lib.CMCG_ERR_STATE
+    while lib.cmcg_engine_poll(e, slot) == 1:
+        lib.cmcg_engine_step(e)
+    with pytest.raises(lib.CmcgError) as err:
+        lib.cmcg_engine_collect(e, slot, probs[0])        # a co-batched slot is collected as a batch
+    assert err.value.code == lib.CMCG_ERR_STATE
+    res = lib.cmcg_engine_collect_batch(e, slot, probs[:2])
+    assert len(res) == 2 and all(lib.cmcg_result_stats(r)["iters"] > 0 for r in res)
+    assert lib.cmcg_engine_poll(e, slot) == 0 and lib.cmcg_engine_info(e)["used"] == 0
