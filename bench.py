@@ -790,18 +790,30 @@ def lts_compare(a):
         ev1.record(stream)
         torch.cuda.synchronize()
         per_bwd = ev0.elapsed_time(ev1) / 1e3
+        # the same periods from eager launches (no graph replay)
+        oe = cmcg.cmcg_options_default(tol=a.tol, max_iter=2000, lts_ratio=ratio, use_graph=0,
+                                       autotune=0 if a.no_autotune else 1)
+        eager = []
+        for direction in (1, -1):
+            ev0.record(stream)
+            cmcg.cmcg_debug_period(p, U0, UT, direction, False, opts=oe)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            eager.append(ev0.elapsed_time(ev1) / 1e3)
         res = cmcg.cmcg_solve(p, o)
         st = cmcg.cmcg_result_stats(res)
         f = [torch.empty((K, 6, Np), dtype=torch.float64, device=dev) for _ in range(2)]
         cmcg.cmcg_result_filtered_device(res, *f)
         fields[name] = f
         rows[name] = {"steps_per_period": M, "dt": dt, "period_forward_s": per_fwd, "period_backward_s": per_bwd,
+                      "period_forward_eager_s": eager[0], "period_backward_eager_s": eager[1],
                       "iters": st["iters"], "rel_res": st["rel_res"], "seconds": st["seconds"],
                       "time_to_1e-6_s": st["seconds_to_1e6"]}
         if ratio > 1:
             rows[name]["fine_elements"] = int(cmcg.cmcg_problem_lts_fine(p, K, o).sum())
             rows[name]["substeps"] = ratio
-        log(f"{name}: M = {M}, period fwd {per_fwd * 1e3:.2f} ms bwd {per_bwd * 1e3:.2f} ms, "
+        log(f"{name}: M = {M}, period fwd {per_fwd * 1e3:.2f} ms bwd {per_bwd * 1e3:.2f} ms "
+            f"(eager {eager[0] * 1e3:.2f} / {eager[1] * 1e3:.2f} ms), "
             f"{st['iters']} iterations, {st['seconds']:.2f} s")
     d = [x - y for x, y in zip(fields["lts"], fields["global"])]
     den = sum(cmcg.cmcg_debug_dot(p, x, x) for x in fields["global"])

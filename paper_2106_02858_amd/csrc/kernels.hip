@@ -330,7 +330,8 @@ template <typename T, int Q, int RF> struct TraceGather {
 // consumes in turn, which needs fewer registers.
 // MH: several-frequency problems (further source harmonics and filters);
 // the single-frequency instantiation carries none of that code.
-template <typename T, int Q, bool PIPE, bool MH>
+// LTSM: the local-time-stepping substep modes (LTS_FWD, LTS_ADJ) only.
+template <typename T, int Q, bool PIPE, bool MH, bool LTSM = false>
 __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     constexpr int NP = Dim<Q>::NP, NFP = Dim<Q>::NFP, NF4 = 4 * NFP;
     constexpr int RS = NP + 1;            // padded LDS row stride (bank spread)
@@ -368,8 +369,9 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     const int mode = a.mode;
     constexpr bool COMP = std::is_same<T, float>::value;  // compensated state U + Ulo
     const bool needL = COMP && (mode == RK2_S2 || mode == RK4_S4);
-    const bool needU = mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || needL;
-    const bool needA = mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4;
+    const bool needU = LTSM || mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || needL;
+    const bool needA =
+        LTSM ? (mode == LTS_ADJ || a.Acc != nullptr) : (mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4);
 
     const uint32_t keep = a.imask ? (a.imask[blk] ^ (a.imask_inv ? 0xffffffffu : 0u)) : 0xffffffffu;
     {
@@ -535,60 +537,110 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     }
     const T cy = (T)a.cy, ca = (T)a.ca, cu = (T)a.cu;
     T o1[NP], o2[NP];
-    switch (mode) {
-        case RK2_S1:
+    if constexpr (LTSM) {
+        if (mode == LTS_FWD) {
+            T w[NP];
 #pragma unroll
-            for (int i = 0; i < NP; ++i) o1[i] = fma(cy, kv[i], y[i]);
-            Row<T, NP>::store((T*)a.Ynext + grow, o1);
-            break;
-        case RK2_S2:
-            if constexpr (COMP) {
-                float e[NP];
+            for (int j = 0; j < 4; ++j) {
+                if (j >= a.lnw) break;
+                Row<T, NP>::load((const T*)args.lw[j] + grow, w);
+                const T cj = (T)args.lcw[j];
 #pragma unroll
-                for (int i = 0; i < NP; ++i) two_sum(up[i], fma(cu, kv[i], lo[i]), o1[i], e[i]);
-                Row<T, NP>::store((T*)a.Uout + grow, o1);
-                RowH<NP>::store((uint16_t*)a.Ulo + grow, e);
-            } else {
-#pragma unroll
-                for (int i = 0; i < NP; ++i) o1[i] = fma(cu, kv[i], up[i]);
-                Row<T, NP>::store((T*)a.Uout + grow, o1);
+                for (int i = 0; i < NP; ++i) kv[i] = fma(cj, w[i], kv[i]);
             }
-            break;
-        case RK4_S1:
+            const T le = (T)a.le, lf = (T)a.lf;
+            const bool hasA = a.Acc != nullptr;
+            if (a.Ynext) {
+#pragma unroll
+                for (int i = 0; i < NP; ++i) o1[i] = fma(cy, kv[i], hasA ? fma(le, ap[i], up[i]) : up[i]);
+                Row<T, NP>::store((T*)a.Ynext + grow, o1);
+            }
+            if (a.Uout) {
+#pragma unroll
+                for (int i = 0; i < NP; ++i) o2[i] = hasA ? fma(ca, kv[i], lf * ap[i]) : ca * kv[i];
+                Row<T, NP>::store((T*)a.Uout + grow, o2);
+            }
+        } else {
+            const bool on = ((a.lmask[blk] >> elc) & 1u) != 0;
+            if (on) {
+                T w[NP];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (j >= a.lnw) break;
+                    T* wj = (T*)args.lw[j] + grow;
+                    Row<T, NP>::load(wj, w);
+                    const T cj = (T)args.lcw[j];
+#pragma unroll
+                    for (int i = 0; i < NP; ++i) w[i] = fma(cj, y[i], w[i]);
+                    Row<T, NP>::store(wj, w);
+                }
+            }
+            const T le = (T)a.le, lf = (T)a.lf;
 #pragma unroll
             for (int i = 0; i < NP; ++i) {
-                o1[i] = fma(cy, kv[i], y[i]);
-                o2[i] = COMP ? ca * kv[i] : fma(ca, kv[i], y[i]);
+                const T A = on ? kv[i] : T(0);
+                o1[i] = up[i] + A;
+                o2[i] = fma(lf, A, le * ap[i]);
             }
-            Row<T, NP>::store((T*)a.Ynext + grow, o1);
-            Row<T, NP>::store((T*)a.Acc + grow, o2);
-            break;
-        case RK4_S2:
-        case RK4_S3:
+            Row<T, NP>::store((T*)a.Uout + grow, o1);
+            if (a.Ynext) Row<T, NP>::store((T*)a.Ynext + grow, o2);
+        }
+    } else {
+        switch (mode) {
+            case RK2_S1:
 #pragma unroll
-            for (int i = 0; i < NP; ++i) {
-                o1[i] = fma(cy, kv[i], up[i]);
-                o2[i] = fma(ca, kv[i], ap[i]);
-            }
-            Row<T, NP>::store((T*)a.Ynext + grow, o1);
-            Row<T, NP>::store((T*)a.Acc + grow, o2);
-            break;
-        case RK4_S4:
-            if constexpr (COMP) {
-                float e[NP];
+                for (int i = 0; i < NP; ++i) o1[i] = fma(cy, kv[i], y[i]);
+                Row<T, NP>::store((T*)a.Ynext + grow, o1);
+                break;
+            case RK2_S2:
+                if constexpr (COMP) {
+                    float e[NP];
 #pragma unroll
-                for (int i = 0; i < NP; ++i) two_sum(up[i], fma(cu, kv[i], ap[i]) + lo[i], o1[i], e[i]);
-                Row<T, NP>::store((T*)a.Uout + grow, o1);
-                RowH<NP>::store((uint16_t*)a.Ulo + grow, e);
-            } else {
+                    for (int i = 0; i < NP; ++i) two_sum(up[i], fma(cu, kv[i], lo[i]), o1[i], e[i]);
+                    Row<T, NP>::store((T*)a.Uout + grow, o1);
+                    RowH<NP>::store((uint16_t*)a.Ulo + grow, e);
+                } else {
 #pragma unroll
-                for (int i = 0; i < NP; ++i) o1[i] = fma(cu, kv[i], ap[i]);
-                Row<T, NP>::store((T*)a.Uout + grow, o1);
-            }
-            break;
-        default:
-            Row<T, NP>::store((T*)a.Kout + grow, kv);
-            break;
+                    for (int i = 0; i < NP; ++i) o1[i] = fma(cu, kv[i], up[i]);
+                    Row<T, NP>::store((T*)a.Uout + grow, o1);
+                }
+                break;
+            case RK4_S1:
+#pragma unroll
+                for (int i = 0; i < NP; ++i) {
+                    o1[i] = fma(cy, kv[i], y[i]);
+                    o2[i] = COMP ? ca * kv[i] : fma(ca, kv[i], y[i]);
+                }
+                Row<T, NP>::store((T*)a.Ynext + grow, o1);
+                Row<T, NP>::store((T*)a.Acc + grow, o2);
+                break;
+            case RK4_S2:
+            case RK4_S3:
+#pragma unroll
+                for (int i = 0; i < NP; ++i) {
+                    o1[i] = fma(cy, kv[i], up[i]);
+                    o2[i] = fma(ca, kv[i], ap[i]);
+                }
+                Row<T, NP>::store((T*)a.Ynext + grow, o1);
+                Row<T, NP>::store((T*)a.Acc + grow, o2);
+                break;
+            case RK4_S4:
+                if constexpr (COMP) {
+                    float e[NP];
+#pragma unroll
+                    for (int i = 0; i < NP; ++i) two_sum(up[i], fma(cu, kv[i], ap[i]) + lo[i], o1[i], e[i]);
+                    Row<T, NP>::store((T*)a.Uout + grow, o1);
+                    RowH<NP>::store((uint16_t*)a.Ulo + grow, e);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < NP; ++i) o1[i] = fma(cu, kv[i], ap[i]);
+                    Row<T, NP>::store((T*)a.Uout + grow, o1);
+                }
+                break;
+            default:
+                Row<T, NP>::store((T*)a.Kout + grow, kv);
+                break;
+        }
     }
     if (a.filter) {
         // F += fa * U + fb * k on the lane's row (U is the stage input here)
@@ -687,7 +739,7 @@ struct MfmaShared {
 // the chunk: 4 FP32 or 2 FP64 values), all requested before the pass
 // computes: r0 = U (modes that combine with the state) or the stage input
 // (stage-1 modes, filter), r1 = Acc, r2 = the bfloat16 low parts (FP32).
-template <typename T, int Q, int NTH = 64> struct MfmaUpdateIn {
+template <typename T, int Q, int NTH = 64, bool LTSM = false> struct MfmaUpdateIn {
     static constexpr int PV = 16 / (int)sizeof(T);
     static constexpr bool COMP = std::is_same<T, float>::value;  // compensated state U + Ulo
     using V = typename std::conditional<COMP, float4, double2>::type;
@@ -696,11 +748,14 @@ template <typename T, int Q, int NTH = 64> struct MfmaUpdateIn {
     uint2 r2[COMP ? NIT : 1];
     __device__ __forceinline__ void fetch(const StageArgs& a, int64_t base, int nvv, int lane) {
         const int mode = a.mode;
-        const bool s1 = mode == RK2_S1 || mode == RK4_S1 || (mode == RHS && a.filter);
+        // LTS_FWD reads U (and Acc when given), LTS_ADJ the stage input and Acc
+        const bool s1 = LTSM ? mode == LTS_ADJ : mode == RK2_S1 || mode == RK4_S1 || (mode == RHS && a.filter);
         // FP64 stage 4 forms U = Acc + cu k without the state
-        const bool needU = mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || (COMP && mode == RK4_S4);
-        const bool needA = mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4;
-        const bool needL = COMP && (mode == RK2_S2 || mode == RK4_S4);
+        const bool needU =
+            LTSM ? mode == LTS_FWD : mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || (COMP && mode == RK4_S4);
+        const bool needA =
+            LTSM ? (mode == LTS_ADJ || a.Acc != nullptr) : (mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4);
+        const bool needL = !LTSM && COMP && (mode == RK2_S2 || mode == RK4_S4);
         const T* src0 = needU ? (const T*)a.U : (const T*)a.Y;
 #pragma unroll
         for (int t = 0; t < NIT; ++t) {
@@ -735,7 +790,7 @@ template <typename T, int Q, int NTH = 64> struct MfmaUpdateIn {
 // barrier instead of two.  CSPLIT (P3, two waves): the waves split the output
 // by column tiles, each building only its own B operands and running both
 // row tiles.
-template <typename T, int Q, bool PIPE, bool MH, int W, bool EAGER = false, bool CSPLIT = false>
+template <typename T, int Q, bool PIPE, bool MH, int W, bool EAGER = false, bool CSPLIT = false, bool LTSM = false>
 __global__ __launch_bounds__(64 * W)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (W == 1 || (EAGER && Q == 3) ? 4 : (EAGER || CSPLIT ? 5 : 6))
                                                    : (W == 1 || EAGER || CSPLIT ? 2 : 3), 8)))
@@ -973,7 +1028,7 @@ void k_stage_mfma(StageArgs args, int64_t per) {
     // elements whose source is zero (and H rows of an interior source) read none
     const uint32_t sm = a.smask ? a.smask[blk] : 0xffffffffu;
     auto takes_src = [&](int row) { return row - 6 * (row / 6) < a.src_rows && ((sm >> (row / 6)) & 1u); };
-    using UIn = MfmaUpdateIn<T, Q, NTH>;
+    using UIn = MfmaUpdateIn<T, Q, NTH, LTSM>;
     using V = typename UIn::V;
     UIn upd;
     upd.fetch(a, base, nvv, tid);
@@ -1042,64 +1097,116 @@ void k_stage_mfma(StageArgs args, int64_t per) {
             *reinterpret_cast<V*>((T*)p + gi) = w;
         };
         T o1[PV], o2[PV];
-        switch (mode) {
-            case RK2_S1:
+        if constexpr (LTSM) {
+            if (mode == LTS_FWD) {  // x0 = U, x1 = Acc
 #pragma unroll
-                for (int u = 0; u < PV; ++u) o1[u] = fma(cy, kv[u], x0[u]);
-                stv(a.Ynext, o1);
-                break;
-            case RK2_S2:
-                if constexpr (COMP) {
+                for (int j = 0; j < 4; ++j) {
+                    if (j >= a.lnw) break;
+                    T w[PV];
+                    ldv(args.lw[j], gi, w);
+                    const T cj = (T)args.lcw[j];
 #pragma unroll
-                    for (int u = 0; u < PV; ++u) two_sum(x0[u], fma(cu, kv[u], lo[u]), o1[u], o2[u]);
-                    stv(a.Uout, o1);
-                    uint2 w;
-                    w.x = (uint32_t)to_bf16(o2[0]) | ((uint32_t)to_bf16(o2[1]) << 16);
-                    w.y = (uint32_t)to_bf16(o2[2]) | ((uint32_t)to_bf16(o2[3]) << 16);
-                    *reinterpret_cast<uint2*>((uint16_t*)a.Ulo + gi) = w;
-                } else {
-#pragma unroll
-                    for (int u = 0; u < PV; ++u) o1[u] = fma(cu, kv[u], x0[u]);
-                    stv(a.Uout, o1);
+                    for (int u = 0; u < PV; ++u) kv[u] = fma(cj, w[u], kv[u]);
                 }
-                break;
-            case RK4_S1:
+                const T le = (T)a.le, lf = (T)a.lf;
+                const bool hasA = a.Acc != nullptr;
+                if (a.Ynext) {
+#pragma unroll
+                    for (int u = 0; u < PV; ++u) o1[u] = fma(cy, kv[u], hasA ? fma(le, x1[u], x0[u]) : x0[u]);
+                    stv(a.Ynext, o1);
+                }
+                if (a.Uout) {
+#pragma unroll
+                    for (int u = 0; u < PV; ++u) o2[u] = hasA ? fma(ca, kv[u], lf * x1[u]) : ca * kv[u];
+                    stv(a.Uout, o2);
+                }
+            } else {  // x0 = the stage input kcur, x1 = Acc
+                // a 16-byte group never straddles an element (6 NP is a multiple of 4)
+                const bool on = ((a.lmask[blk] >> (v / NP / 6)) & 1u) != 0;
+                if (on) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if (j >= a.lnw) break;
+                        T w[PV];
+                        ldv(args.lw[j], gi, w);
+                        const T cj = (T)args.lcw[j];
+#pragma unroll
+                        for (int u = 0; u < PV; ++u) w[u] = fma(cj, x0[u], w[u]);
+                        stv(const_cast<void*>(args.lw[j]), w);
+                    }
+                }
+                T z[PV];
+                ldv(a.U, gi, z);
+                const T le = (T)a.le, lf = (T)a.lf;
 #pragma unroll
                 for (int u = 0; u < PV; ++u) {
-                    o1[u] = fma(cy, kv[u], x0[u]);
-                    o2[u] = COMP ? ca * kv[u] : fma(ca, kv[u], x0[u]);
+                    const T A = on ? kv[u] : T(0);
+                    o1[u] = z[u] + A;
+                    o2[u] = fma(lf, A, le * x1[u]);
                 }
-                stv(a.Ynext, o1);
-                stv(a.Acc, o2);
-                break;
-            case RK4_S2:
-            case RK4_S3:
+                stv(a.Uout, o1);
+                if (a.Ynext) stv(a.Ynext, o2);
+            }
+        } else {
+            switch (mode) {
+                case RK2_S1:
 #pragma unroll
-                for (int u = 0; u < PV; ++u) {
-                    o1[u] = fma(cy, kv[u], x0[u]);
-                    o2[u] = fma(ca, kv[u], x1[u]);
-                }
-                stv(a.Ynext, o1);
-                stv(a.Acc, o2);
-                break;
-            case RK4_S4:
-                if constexpr (COMP) {
+                    for (int u = 0; u < PV; ++u) o1[u] = fma(cy, kv[u], x0[u]);
+                    stv(a.Ynext, o1);
+                    break;
+                case RK2_S2:
+                    if constexpr (COMP) {
 #pragma unroll
-                    for (int u = 0; u < PV; ++u) two_sum(x0[u], fma(cu, kv[u], x1[u]) + lo[u], o1[u], o2[u]);
-                    stv(a.Uout, o1);
-                    uint2 w;
-                    w.x = (uint32_t)to_bf16(o2[0]) | ((uint32_t)to_bf16(o2[1]) << 16);
-                    w.y = (uint32_t)to_bf16(o2[2]) | ((uint32_t)to_bf16(o2[3]) << 16);
-                    *reinterpret_cast<uint2*>((uint16_t*)a.Ulo + gi) = w;
-                } else {
+                        for (int u = 0; u < PV; ++u) two_sum(x0[u], fma(cu, kv[u], lo[u]), o1[u], o2[u]);
+                        stv(a.Uout, o1);
+                        uint2 w;
+                        w.x = (uint32_t)to_bf16(o2[0]) | ((uint32_t)to_bf16(o2[1]) << 16);
+                        w.y = (uint32_t)to_bf16(o2[2]) | ((uint32_t)to_bf16(o2[3]) << 16);
+                        *reinterpret_cast<uint2*>((uint16_t*)a.Ulo + gi) = w;
+                    } else {
 #pragma unroll
-                    for (int u = 0; u < PV; ++u) o1[u] = fma(cu, kv[u], x1[u]);
-                    stv(a.Uout, o1);
-                }
-                break;
-            default:
-                stv(a.Kout, kv);
-                break;
+                        for (int u = 0; u < PV; ++u) o1[u] = fma(cu, kv[u], x0[u]);
+                        stv(a.Uout, o1);
+                    }
+                    break;
+                case RK4_S1:
+#pragma unroll
+                    for (int u = 0; u < PV; ++u) {
+                        o1[u] = fma(cy, kv[u], x0[u]);
+                        o2[u] = COMP ? ca * kv[u] : fma(ca, kv[u], x0[u]);
+                    }
+                    stv(a.Ynext, o1);
+                    stv(a.Acc, o2);
+                    break;
+                case RK4_S2:
+                case RK4_S3:
+#pragma unroll
+                    for (int u = 0; u < PV; ++u) {
+                        o1[u] = fma(cy, kv[u], x0[u]);
+                        o2[u] = fma(ca, kv[u], x1[u]);
+                    }
+                    stv(a.Ynext, o1);
+                    stv(a.Acc, o2);
+                    break;
+                case RK4_S4:
+                    if constexpr (COMP) {
+#pragma unroll
+                        for (int u = 0; u < PV; ++u) two_sum(x0[u], fma(cu, kv[u], x1[u]) + lo[u], o1[u], o2[u]);
+                        stv(a.Uout, o1);
+                        uint2 w;
+                        w.x = (uint32_t)to_bf16(o2[0]) | ((uint32_t)to_bf16(o2[1]) << 16);
+                        w.y = (uint32_t)to_bf16(o2[2]) | ((uint32_t)to_bf16(o2[3]) << 16);
+                        *reinterpret_cast<uint2*>((uint16_t*)a.Ulo + gi) = w;
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < PV; ++u) o1[u] = fma(cu, kv[u], x1[u]);
+                        stv(a.Uout, o1);
+                    }
+                    break;
+                default:
+                    stv(a.Kout, kv);
+                    break;
+            }
         }
         if (a.filter) {  // stage-1 and RHS modes: x0 is the stage input
 #pragma unroll
@@ -1213,53 +1320,6 @@ struct LtsRange {
     }
 };
 
-// k = K + sum_{j < nw} w_j W_j;  out1 = base + e acc + c1 k;  out2 = f acc + c2 k
-// (acc nullable = 0; out1 / out2 nullable = not written; out1 may alias base,
-// out2 may alias acc)
-template <typename T>
-__global__ void k_lts_combine(LtsRange rg, const T* K, const T* W0, const T* W1, const T* W2, const T* W3, int nw,
-                              double w0, double w1, double w2, double w3, const T* base, const T* acc, double e,
-                              double c1, T* out1, double f, double c2, T* out2) {
-    const int64_t cnt = rg.count();
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < cnt; v += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = rg.at(v);
-        if (i >= rg.n) continue;
-        T k = K[i];
-        if (nw > 0) k += (T)w0 * W0[i];
-        if (nw > 1) k += (T)w1 * W1[i];
-        if (nw > 2) k += (T)w2 * W2[i];
-        if (nw > 3) k += (T)w3 * W3[i];
-        const T ac = acc ? acc[i] : T(0);
-        if (out1) out1[i] = base[i] + (T)e * ac + (T)c1 * k;
-        if (out2) out2[i] = (T)f * ac + (T)c2 * k;
-    }
-}
-
-// Adjoint stage of the homogeneous step (S-flipped variables): A = rows of K
-// on the mask; zbar += A; knext = a0 Z0 + b0 A; wb_j += cw_j kcur (j < nw)
-// (wb updated on the mask's rows only: elsewhere the caller holds them in closed form)
-template <typename T>
-__global__ void k_lts_adjoint(LtsRange rg, int np6, const uint32_t* mask, int inv, const T* K, T* zbar, const T* Z0,
-                              double a0, double b0, T* knext, const T* kcur, T* wb0, T* wb1, T* wb2, T* wb3, int nw,
-                              double cw0, double cw1, double cw2, double cw3) {
-    const int64_t cnt = rg.count();
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < cnt; v += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = rg.at(v);
-        if (i >= rg.n) continue;
-        const bool on = lts_row_on(mask, inv, i, np6);
-        if (on) {
-            const T kc = kcur[i];
-            if (nw > 0) wb0[i] += (T)cw0 * kc;
-            if (nw > 1) wb1[i] += (T)cw1 * kc;
-            if (nw > 2) wb2[i] += (T)cw2 * kc;
-            if (nw > 3) wb3[i] += (T)cw3 * kc;
-        }
-        const T A = on ? K[i] : T(0);
-        zbar[i] += A;
-        if (knext) knext[i] = (T)a0 * Z0[i] + (T)b0 * A;
-    }
-}
-
 // z = a y + b rows(x), rows(x) = x on the mask's rows (all rows when mask is
 // null), 0 elsewhere; y nullable (= 0); z may alias y
 template <typename T>
@@ -1293,6 +1353,21 @@ __global__ void k_lts_closed(int64_t n, int np6, int Np, const uint32_t* mask, c
     }
 }
 
+// Adjoint Taylor weights of the rows outside the mask (every coarse unknown):
+// wb_j = al_j zbar there; the mask's rows keep what the substeps accumulated.
+template <typename T>
+__global__ void k_lts_wbar_close(int64_t n, int np6, const uint32_t* mask, const T* zbar, T* wb0, T* wb1, T* wb2,
+                                 T* wb3, int nw, double a0, double a1, double a2, double a3) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (lts_row_on(mask, 0, i, np6)) continue;
+        const T z = zbar[i];
+        if (nw > 0) wb0[i] = (T)a0 * z;
+        if (nw > 1) wb1[i] = (T)a1 * z;
+        if (nw > 2) wb2[i] = (T)a2 * z;
+        if (nw > 3) wb3[i] = (T)a3 * z;
+    }
+}
+
 __global__ void k_axpby(double a, const double* x, double b, const double* y, double* z, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         z[i] = a * x[i] + b * y[i];
@@ -1304,6 +1379,17 @@ __global__ void k_filter_add(const T* __restrict__ U, double wr, double wi, doub
         const double u = (double)U[i];
         Fre[i] += wr * u;
         Fim[i] += wi * u;
+    }
+}
+
+// F += wa field(U) + wb field(D) (two levels of the filter sum in one pass)
+template <typename T>
+__global__ void k_filter_add2(const T* __restrict__ U, double ar, double ai, const T* __restrict__ D, double br,
+                              double bi, double* Fre, double* Fim, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double u = (double)U[i], d = (double)D[i];
+        Fre[i] += ar * u + br * d;
+        Fim[i] += ai * u + bi * d;
     }
 }
 
@@ -1506,6 +1592,17 @@ void stage_launch_mh(const StageArgs& a, hipStream_t s) {
 
 template <typename T, int Q>
 void stage_launch(const StageArgs& a, hipStream_t s) {
+    if (a.mode == LTS_FWD || a.mode == LTS_ADJ) {  // one instantiation per order (single frequency)
+        const int64_t blocks = a.blist ? a.nblist : (a.K + EPW - 1) / EPW;
+        const int64_t per = (blocks + 7) / 8;
+        const dim3 grid((unsigned)(8 * per));
+        if constexpr (Q >= 2)
+            hipLaunchKernelGGL((k_stage_mfma<T, Q, true, false, 2, false, false, true>), grid, dim3(128), 0, s, a,
+                               per);
+        else
+            hipLaunchKernelGGL((k_stage<T, Q, false, false, true>), grid, dim3(64), 0, s, a, per);
+        return;
+    }
     if (a.nharm > 1)
         stage_launch_mh<T, Q, true>(a, s);
     else
@@ -1700,6 +1797,17 @@ void launch_filter_add(int precision, const void* U, double wr, double wi, doubl
     check_launch();
 }
 
+void launch_filter_add2(int precision, const void* U, double ar, double ai, const void* D, double br, double bi,
+                        double* Fre, double* Fim, int64_t n, hipStream_t s) {
+    if (precision == CMCG_FP64)
+        hipLaunchKernelGGL(k_filter_add2<double>, dim3(grid_for(n)), dim3(256), 0, s, (const double*)U, ar, ai,
+                           (const double*)D, br, bi, Fre, Fim, n);
+    else
+        hipLaunchKernelGGL(k_filter_add2<float>, dim3(grid_for(n)), dim3(256), 0, s, (const float*)U, ar, ai,
+                           (const float*)D, br, bi, Fre, Fim, n);
+    check_launch();
+}
+
 int dot_partials() { return kDotBlocks; }
 
 namespace {
@@ -1713,52 +1821,6 @@ LtsRange lts_range(int64_t n, int np6, const int* blist, int64_t nb) {
 }
 int64_t lts_count(const LtsRange& r) { return r.blist ? r.nb * r.per : r.n; }
 }  // namespace
-
-void launch_lts_combine(int precision, int64_t n, int np6, const int* blist, int64_t nb, const void* K,
-                        const void* const* W, const double* w, int nw, const void* base, const void* acc, double e,
-                        double c1, void* out1, double f, double c2, void* out2, hipStream_t s) {
-    const void* Wp[4] = {nullptr, nullptr, nullptr, nullptr};
-    double wc[4] = {0, 0, 0, 0};
-    for (int j = 0; j < nw && j < 4; ++j) {
-        Wp[j] = W[j];
-        wc[j] = w[j];
-    }
-    const LtsRange rg = lts_range(n, np6, blist, nb);
-    const int g = grid_for(lts_count(rg));
-    if (precision == CMCG_FP64)
-        hipLaunchKernelGGL(k_lts_combine<double>, dim3(g), dim3(256), 0, s, rg, (const double*)K,
-                           (const double*)Wp[0], (const double*)Wp[1], (const double*)Wp[2], (const double*)Wp[3], nw,
-                           wc[0], wc[1], wc[2], wc[3], (const double*)base, (const double*)acc, e, c1, (double*)out1,
-                           f, c2, (double*)out2);
-    else
-        hipLaunchKernelGGL(k_lts_combine<float>, dim3(g), dim3(256), 0, s, rg, (const float*)K,
-                           (const float*)Wp[0], (const float*)Wp[1], (const float*)Wp[2], (const float*)Wp[3], nw,
-                           wc[0], wc[1], wc[2], wc[3], (const float*)base, (const float*)acc, e, c1, (float*)out1,
-                           f, c2, (float*)out2);
-    check_launch();
-}
-
-void launch_lts_adjoint(int precision, int64_t n, int np6, const int* blist, int64_t nb, const uint32_t* mask,
-                        int inv, const void* K, void* zbar, const void* Z0, double a0, double b0, void* knext,
-                        const void* kcur, void* const* wb, const double* cw, int nw, hipStream_t s) {
-    void* W[4] = {nullptr, nullptr, nullptr, nullptr};
-    double c[4] = {0, 0, 0, 0};
-    for (int j = 0; j < nw && j < 4; ++j) {
-        W[j] = wb[j];
-        c[j] = cw[j];
-    }
-    const LtsRange rg = lts_range(n, np6, blist, nb);
-    const int g = grid_for(lts_count(rg));
-    if (precision == CMCG_FP64)
-        hipLaunchKernelGGL(k_lts_adjoint<double>, dim3(g), dim3(256), 0, s, rg, np6, mask, inv, (const double*)K,
-                           (double*)zbar, (const double*)Z0, a0, b0, (double*)knext, (const double*)kcur,
-                           (double*)W[0], (double*)W[1], (double*)W[2], (double*)W[3], nw, c[0], c[1], c[2], c[3]);
-    else
-        hipLaunchKernelGGL(k_lts_adjoint<float>, dim3(g), dim3(256), 0, s, rg, np6, mask, inv, (const float*)K,
-                           (float*)zbar, (const float*)Z0, a0, b0, (float*)knext, (const float*)kcur, (float*)W[0],
-                           (float*)W[1], (float*)W[2], (float*)W[3], nw, c[0], c[1], c[2], c[3]);
-    check_launch();
-}
 
 void launch_lts_axpy(int precision, int64_t n, int np6, const int* blist, int64_t nb, const uint32_t* mask, int inv,
                      double a, const void* y, double b, const void* x, void* z, hipStream_t s) {
@@ -1792,6 +1854,25 @@ void launch_lts_closed(int precision, int64_t n, int np6, int Np, const uint32_t
                            (const float*)Wp[0], (const float*)Wp[1], (const float*)Wp[2], (const float*)Wp[3], nw,
                            c[0], c[1], c[2], c[3], (const float*)Sre, (const float*)Sim, src_rows, sc, ss,
                            (float*)z);
+    check_launch();
+}
+
+void launch_lts_wbar_close(int precision, int64_t n, int np6, const uint32_t* mask, const void* zbar,
+                           void* const* wb, const double* al, int nw, hipStream_t s) {
+    void* W[4] = {nullptr, nullptr, nullptr, nullptr};
+    double c[4] = {0, 0, 0, 0};
+    for (int j = 0; j < nw && j < 4; ++j) {
+        W[j] = wb[j];
+        c[j] = al[j];
+    }
+    if (precision == CMCG_FP64)
+        hipLaunchKernelGGL(k_lts_wbar_close<double>, dim3(grid_for(n)), dim3(256), 0, s, n, np6, mask,
+                           (const double*)zbar, (double*)W[0], (double*)W[1], (double*)W[2], (double*)W[3], nw, c[0],
+                           c[1], c[2], c[3]);
+    else
+        hipLaunchKernelGGL(k_lts_wbar_close<float>, dim3(grid_for(n)), dim3(256), 0, s, n, np6, mask,
+                           (const float*)zbar, (float*)W[0], (float*)W[1], (float*)W[2], (float*)W[3], nw, c[0], c[1],
+                           c[2], c[3]);
     check_launch();
 }
 

@@ -16,6 +16,12 @@ namespace cmcg {
 //   RK4_S2/S3: Ynext = U + cy k ; Acc += ca k
 //   RK4_S4: U     = Acc + cu k
 //   RHS:    Kout  = k
+//   LTS_FWD (local time stepping, substep stage): k += sum_j lcw_j lw_j;
+//           Ynext = U + le Acc + cy k; Uout = lf Acc + ca k (Acc, Ynext, Uout
+//           nullable; no compensated state)
+//   LTS_ADJ (adjoint substep stage; Y = the adjoint stage vector kcur): on the
+//           rows of the elements set in lmask A = k and lw_j += lcw_j kcur,
+//           elsewhere A = 0; Uout = U + A; Ynext = le Acc + lf A (nullable)
 // Optional filter accumulation (FP64): F += fa * U + fb * k (complex).
 //
 // FP32 fields carry the state as an unevaluated sum U + Ulo (Ulo in bfloat16,
@@ -23,7 +29,7 @@ namespace cmcg {
 // Acc = ca k; RK4_S4: U + Ulo += Acc + cu k) and the last update of a step adds
 // its increment to U + Ulo with an exact two-sum, so rounding the state to
 // FP32 once per step does not accumulate over the period.
-enum StageMode { RK2_S1 = 0, RK2_S2, RK4_S1, RK4_S2, RK4_S3, RK4_S4, RHS };
+enum StageMode { RK2_S1 = 0, RK2_S2, RK4_S1, RK4_S2, RK4_S3, RK4_S4, RHS, LTS_FWD, LTS_ADJ };
 
 struct StageArgs {
     const void* Y;      // stage input (Phi argument), [K][6][Np]
@@ -72,6 +78,12 @@ struct StageArgs {
     // single 3-D launches (nullable): run only the element blocks listed
     const int* blist;
     int64_t nblist;
+    // LTS_FWD / LTS_ADJ operands (single 3-D launches)
+    const void* lw[4];
+    double lcw[4];
+    int lnw;
+    double le, lf;
+    const uint32_t* lmask;  // LTS_ADJ: output rows (one word per element block, layout of smask)
 };
 constexpr int kMaxHarm = 8;
 // per-member scalars of a batched stage: cy, ca, cu, scos, ssin, fa_re, fa_im, fb_re, fb_im
@@ -90,22 +102,16 @@ void launch_stage(int q, int precision, const StageArgs& a, hipStream_t s);
 // Local time stepping (field precision, n values, np6 = 6 Np values per
 // element; masks: one word per element block, bit xor inv selects a row;
 // blist / nb (nullable): visit only the rows of the listed element blocks):
-//   combine: k = K + sum_j w_j W_j; out1 = base + e acc + c1 k; out2 = f acc + c2 k
-//   adjoint: on mask rows wb_j += cw_j kcur and A = K, elsewhere A = 0;
-//            zbar += A; knext = a0 Z0 + b0 A
 //   axpy:    z = a y + b rows(x)   (mask null: all rows; y null: 0)
 //   closed:  rows off the mask: z += sum_j al_j W_j + sc Sre - ss Sim (source rows)
-void launch_lts_combine(int precision, int64_t n, int np6, const int* blist, int64_t nb, const void* K,
-                        const void* const* W, const double* w, int nw, const void* base, const void* acc, double e,
-                        double c1, void* out1, double f, double c2, void* out2, hipStream_t s);
-void launch_lts_adjoint(int precision, int64_t n, int np6, const int* blist, int64_t nb, const uint32_t* mask,
-                        int inv, const void* K, void* zbar, const void* Z0, double a0, double b0, void* knext,
-                        const void* kcur, void* const* wb, const double* cw, int nw, hipStream_t s);
 void launch_lts_axpy(int precision, int64_t n, int np6, const int* blist, int64_t nb, const uint32_t* mask, int inv,
                      double a, const void* y, double b, const void* x, void* z, hipStream_t s);
 void launch_lts_closed(int precision, int64_t n, int np6, int Np, const uint32_t* mask, const void* const* W,
                        const double* al, int nw, const void* Sre, const void* Sim, int src_rows, double sc, double ss,
                        void* z, hipStream_t s);
+//   wbar_close: rows off the mask: wb_j = al_j zbar
+void launch_lts_wbar_close(int precision, int64_t n, int np6, const uint32_t* mask, const void* zbar,
+                           void* const* wb, const double* al, int nw, hipStream_t s);
 // D[16][16] = A[16][4] B[4][16] on one matrix-core instruction of the field
 // precision, through the lane layout the stage kernels use (FP64 in and out).
 void launch_mfma_probe(int precision, const double* A, const double* B, double* D, hipStream_t s);
@@ -129,6 +135,9 @@ void launch_axpby(double a, const double* x, double b, const double* y, double* 
 // F += w * field(U) (FP64 complex accumulation of a real field)
 void launch_filter_add(int precision, const void* U, double w_re, double w_im, double* Fre,
                        double* Fim, int64_t n, hipStream_t s);
+// F += w_a * field(U) + w_b * field(D)
+void launch_filter_add2(int precision, const void* U, double ar, double ai, const void* D, double br, double bi,
+                        double* Fre, double* Fim, int64_t n, hipStream_t s);
 // Deterministic M-weighted inner product (U, V)_{eps,mu}; result written to
 // out_dev[0] (device).  partial: scratch of dot_partials() doubles.
 int dot_partials();

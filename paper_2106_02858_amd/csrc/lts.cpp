@@ -9,22 +9,27 @@
 //   W_k = B (I - P) D_k
 //   z' = B P z + sum_k tau^k / k! W_k + F(t + tau), z(0) = y, m base-RK steps
 //   y(t + H) = z(H)
-// Every application of B is one stage-kernel launch in RHS mode (an input mask
-// zeroes the unknowns outside P or I - P, including neighbour traces); the
-// combinations run as elementwise kernels.  The backward periods of
-// Algorithm 2 need the exact adjoint of this propagator: the step's
-// operations in reverse order, transposed, in S-flipped variables (where
-// B* = S B S becomes B and the masks move to the outputs).  Fields stay in
-// the space's precision without the compensated FP32 state.
+// Every application of B is one stage-kernel launch (an input mask zeroes
+// the unknowns outside P or I - P, including neighbour traces).  The backward
+// periods of Algorithm 2 need the exact adjoint of this propagator: the
+// step's operations in reverse order, transposed, in S-flipped variables
+// (where B* = S B S becomes B and the masks move to the outputs).  Fields
+// stay in the space's precision without the compensated FP32 state.
 //
 // Only the fine region pays for the substeps: B P z vanishes outside the
 // fine elements and their face neighbours (the halo), so the substeps run
-// on the element blocks that hold halo elements, and every other unknown
-// advances in closed form, z = y + sum_k al_k W_k + (RK quadrature of F) with
-// al_k = sum over the substeps' stages of b_s h tau_s^k / k!.  The adjoint
-// likewise runs its substeps on the fine blocks (outputs) and halo blocks
-// (vectors), the coarse rows' adjoint Taylor weights being al_k times the
-// step's end value.
+// on the element blocks that hold halo elements (one stage launch per
+// substep stage, the polynomial W terms and the Runge-Kutta combination
+// fused into its update pass), and every other unknown advances in closed
+// form, z = y + sum_k al_k W_k + (RK quadrature of F) with al_k = sum over
+// the substeps' stages of b_s h tau_s^k / k!.  Away from the halo blocks
+// B (I - P) D_k = D_{k+1} - F^(k), so only W_{p-1} needs a full launch: a
+// coarse step costs p full right-hand sides, p - 1 on the halo blocks and
+// p m on the halo blocks for the substeps (RK4: 4 + 3 h + 16 h launches of
+// B for m = 4 against 16 full ones of global stepping).  The adjoint runs
+// its substeps on the halo blocks as well (outputs on the fine rows), the
+// coarse rows' adjoint Taylor weights being al_k times the step's end
+// value.
 #include <cmath>
 
 #include "objects.h"
@@ -54,7 +59,8 @@ void ensure_lts_mask(cmcg_problem* p, const StepCfg& c) {
                 if (m.nbr[4 * e + f] >= 0) halo[m.nbr[4 * e + f]] = 1;
         }
     }
-    std::vector<int> fb, hbl;
+    std::vector<int> fb, hbl, h2l;
+    std::vector<char> near(s.K, 0);  // elements of halo blocks and their face neighbours
     for (int64_t b = 0; b < nw; ++b) {
         bool any_f = w[b] != 0, any_h = false;
         for (int64_t e = 10 * b; e < std::min<int64_t>(10 * b + 10, s.K); ++e) any_h = any_h || halo[e];
@@ -62,7 +68,17 @@ void ensure_lts_mask(cmcg_problem* p, const StepCfg& c) {
         if (any_h) {
             hbl.push_back((int)b);
             hb[b] = 0x3ffu;  // every element of the block
+            for (int64_t e = 10 * b; e < std::min<int64_t>(10 * b + 10, s.K); ++e) {
+                near[e] = 1;
+                for (int f = 0; f < 4; ++f)
+                    if (m.nbr[4 * e + f] >= 0) near[m.nbr[4 * e + f]] = 1;
+            }
         }
+    }
+    for (int64_t b = 0; b < nw; ++b) {
+        bool any = false;
+        for (int64_t e = 10 * b; e < std::min<int64_t>(10 * b + 10, s.K); ++e) any = any || near[e];
+        if (any) h2l.push_back((int)b);
     }
     p->lts_mask.alloc(nw * 4);
     p->lts_hbmask.alloc(nw * 4);
@@ -70,10 +86,16 @@ void ensure_lts_mask(cmcg_problem* p, const StepCfg& c) {
     CMCG_HIP(hipMemcpy(p->lts_hbmask.p, hb.data(), nw * 4, hipMemcpyHostToDevice));
     p->lts_nfb = (int64_t)fb.size();
     p->lts_nhb = (int64_t)hbl.size();
+    p->lts_nh2b = (int64_t)h2l.size();
     p->lts_fblocks.alloc(std::max<size_t>(1, fb.size()) * 4);
     p->lts_hblocks.alloc(std::max<size_t>(1, hbl.size()) * 4);
+    p->lts_h2blocks.alloc(std::max<size_t>(1, h2l.size()) * 4);
     if (!fb.empty()) CMCG_HIP(hipMemcpy(p->lts_fblocks.p, fb.data(), fb.size() * 4, hipMemcpyHostToDevice));
     if (!hbl.empty()) CMCG_HIP(hipMemcpy(p->lts_hblocks.p, hbl.data(), hbl.size() * 4, hipMemcpyHostToDevice));
+    if (!h2l.empty()) CMCG_HIP(hipMemcpy(p->lts_h2blocks.p, h2l.data(), h2l.size() * 4, hipMemcpyHostToDevice));
+    // captured periods hold the old lists' addresses and the old step's coefficients
+    for (auto& kv : p->lts_graphs) (void)hipGraphExecDestroy(kv.second);
+    p->lts_graphs.clear();
     p->lts_H = c.dt;
 }
 
@@ -170,6 +192,41 @@ void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool
         a.blist = bl;
         a.nblist = nb;
     };
+    // one substep stage on the halo blocks, fused with the combination:
+    // k = B P Y [+ F(tt)] + sum_j cw_j W_j; out1 = base + e acc + c1 k;
+    // out2 = f acc + c2 k (acc, out1, out2 nullable)
+    auto fwd_stage = [&](const void* Yin, bool fsrc, double tt, const double* cw, const void* base, void* acc,
+                         double e, double c1, void* out1, double f, double c2, void* out2) {
+        a.Y = Yin;
+        a.U = base;
+        a.Acc = acc;
+        a.Ynext = out1;
+        a.Uout = out2;
+        a.Kout = nullptr;
+        a.imask = fine;
+        a.imask_inv = 0;
+        a.src_rows = fsrc ? p->src_rows : 0;
+        a.scos = std::cos(w * tt);
+        a.ssin = std::sin(w * tt);
+        a.mode = LTS_FWD;
+        a.cy = c1;
+        a.ca = c2;
+        a.le = e;
+        a.lf = f;
+        a.lnw = order;
+        for (int j = 0; j < order; ++j) {
+            a.lw[j] = W[j];
+            a.lcw[j] = cw[j];
+        }
+        a.blist = hbl;
+        a.nblist = nhb;
+        stage_dim(s, a, st);
+        a.mode = RHS;
+        a.Acc = a.Ynext = a.Uout = nullptr;
+        a.lnw = 0;
+        a.blist = nullptr;
+        a.nblist = 0;
+    };
 
     if (direction > 0) {
         // filter weights (Section 5.4) at the coarse time levels t_nn = nn H
@@ -200,57 +257,56 @@ void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool
                         wa += twoT * ph(nn - 1) * xi[1];
                         wb += twoT * ph(nn - 1) * xi[3];
                     }
-                    launch_filter_add(prec, U, wa.real(), wa.imag(), p->Fre.as<double>(), p->Fim.as<double>(), n, st);
-                    launch_filter_add(prec, D[1], wb.real(), wb.imag(), p->Fre.as<double>(), p->Fim.as<double>(), n,
-                                      st);
+                    launch_filter_add2(prec, U, wa.real(), wa.imag(), D[1], wb.real(), wb.imag(), p->Fre.as<double>(),
+                                       p->Fim.as<double>(), n, st);
                 }
             }
-            // the coarse unknowns' contribution, frozen as a polynomial in tau
-            for (int k = 0; k < order; ++k) rhs(D[k], W[k], false, 0.0, 0, fine, 1);
+            // the coarse unknowns' contribution, frozen as a polynomial in tau:
+            // W_{p-1} everywhere; W_k (k < p - 1) on the halo blocks only, since
+            // away from the fine region B (I - P) D_k = B D_k = D_{k+1} - F^(k)
+            rhs(D[order - 1], W[order - 1], false, 0.0, 0, fine, 1);
             // fine substeps on z (in place on U = D_0), only on the halo blocks
             if (nhb > 0) {
                 rhs_on(hbl, nhb);
+                for (int k = 0; k + 1 < order; ++k) rhs(D[k], W[k], false, 0.0, 0, fine, 1);
                 double cw[4];
                 for (int l = 0; l < m; ++l) {
                     const double tau = l * h;
                     if (c.scheme == 2) {
-                        rhs(U, Kb, with_src, t + tau, 0, fine, 0);
                         poly(tau, cw);
-                        launch_lts_combine(prec, n, np6, hbl, nhb, Kb, W, cw, order, U, nullptr, 0.0, 0.5 * h, Zs,
-                                           0.0, 0.0, nullptr, st);
-                        rhs(Zs, Kb, with_src, t + tau + 0.5 * h, 0, fine, 0);
+                        fwd_stage(U, with_src, t + tau, cw, U, nullptr, 0.0, 0.5 * h, Zs, 0.0, 0.0, nullptr);
                         poly(tau + 0.5 * h, cw);
-                        launch_lts_combine(prec, n, np6, hbl, nhb, Kb, W, cw, order, U, nullptr, 0.0, h, U, 0.0, 0.0,
-                                           nullptr, st);
+                        fwd_stage(Zs, with_src, t + tau + 0.5 * h, cw, U, nullptr, 0.0, h, U, 0.0, 0.0, nullptr);
                     } else {
-                        rhs(U, Kb, with_src, t + tau, 0, fine, 0);
                         poly(tau, cw);
-                        launch_lts_combine(prec, n, np6, hbl, nhb, Kb, W, cw, order, U, nullptr, 0.0, 0.5 * h, Zs,
-                                           0.0, h / 6.0, Acc, st);
-                        rhs(Zs, Kb, with_src, t + tau + 0.5 * h, 0, fine, 0);
+                        fwd_stage(U, with_src, t + tau, cw, U, nullptr, 0.0, 0.5 * h, Zs, 0.0, h / 6.0, Acc);
                         poly(tau + 0.5 * h, cw);
-                        launch_lts_combine(prec, n, np6, hbl, nhb, Kb, W, cw, order, U, Acc, 0.0, 0.5 * h, Zs2, 1.0,
-                                           h / 3.0, Acc, st);
-                        rhs(Zs2, Kb, with_src, t + tau + 0.5 * h, 0, fine, 0);
-                        launch_lts_combine(prec, n, np6, hbl, nhb, Kb, W, cw, order, U, Acc, 0.0, h, Zs, 1.0,
-                                           h / 3.0, Acc, st);
-                        rhs(Zs, Kb, with_src, t + tau + h, 0, fine, 0);
+                        fwd_stage(Zs, with_src, t + tau + 0.5 * h, cw, U, Acc, 0.0, 0.5 * h, Zs2, 1.0, h / 3.0, Acc);
+                        fwd_stage(Zs2, with_src, t + tau + 0.5 * h, cw, U, Acc, 0.0, h, Zs, 1.0, h / 3.0, Acc);
                         poly(tau + h, cw);
-                        launch_lts_combine(prec, n, np6, hbl, nhb, Kb, W, cw, order, U, Acc, 1.0, h / 6.0, U, 0.0, 0.0,
-                                           nullptr, st);
+                        fwd_stage(Zs, with_src, t + tau + h, cw, U, Acc, 1.0, h / 6.0, U, 0.0, 0.0, nullptr);
                     }
                 }
             }
-            // every other unknown: z = y + sum_k al_k W_k + the quadrature of F
+            // every other unknown: z = y + sum_k al_k W_k + the quadrature of F,
+            // with W_k = D_{k+1} - F^(k)(t) for k < p - 1
             double sc = 0, ss = 0;
-            if (with_src)
+            if (with_src) {
                 for (int l = 0; l < m; ++l)
                     for (int si = 0; si < ns; ++si) {
                         const double x = w * (t + l * h + st_off[si] * h);
                         sc += st_b[si] * h * std::cos(x);
                         ss += st_b[si] * h * std::sin(x);
                     }
-            launch_lts_closed(prec, n, np6, s.Np, hbmask, W, al, order, with_src ? p->Sre.p : nullptr, p->Sim.p,
+                for (int k = 0; k + 1 < order; ++k) {
+                    const double phk = w * t + k * 0.5 * M_PI, amp = std::pow(w, k);
+                    sc -= al[k] * amp * std::cos(phk);
+                    ss -= al[k] * amp * std::sin(phk);
+                }
+            }
+            const void* Wc[4] = {D[1], order > 2 ? D[2] : W[1], order > 2 ? D[3] : nullptr,
+                                 order > 2 ? W[3] : nullptr};
+            launch_lts_closed(prec, n, np6, s.Np, hbmask, Wc, al, order, with_src ? p->Sre.p : nullptr, p->Sim.p,
                               p->src_rows, sc, ss, U, st);
         }
         rhs_on(nullptr, 0);
@@ -260,8 +316,8 @@ void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool
             } else {
                 rhs(U, D[1], with_src, M * H, 0, nullptr, 0);
                 const std::complex<double> wa = twoT * ph(M - 1) * xi[1], wb = twoT * ph(M - 1) * xi[3];
-                launch_filter_add(prec, U, wa.real(), wa.imag(), p->Fre.as<double>(), p->Fim.as<double>(), n, st);
-                launch_filter_add(prec, D[1], wb.real(), wb.imag(), p->Fre.as<double>(), p->Fim.as<double>(), n, st);
+                launch_filter_add2(prec, U, wa.real(), wa.imag(), D[1], wb.real(), wb.imag(), p->Fre.as<double>(),
+                                   p->Fim.as<double>(), n, st);
             }
         }
         return;
@@ -269,13 +325,56 @@ void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool
 
     // adjoint of the homogeneous step, M times (S-flipped variables: zbar = U);
     // the substeps' vectors live on the halo blocks, B runs on the fine blocks
-    // (only its fine rows are used), the coarse rows' wbar_k = al_k zbar_end
+    // (only its fine rows are used), the coarse rows' wbar_k = al_k zbar_end.
+    // The forward's Taylor part, written with the halo-block mask h,
+    //   D_{k+1} = B D_k,  W_k = h B (I - P) D_k + (1 - h) D_{k+1} (k < p - 1),
+    //   W_{p-1} = B (I - P) D_{p-1},
+    // transposes to A_{p-1} = (I - P) B wbar_{p-1} + (1 - h) wbar_{p-2},
+    //   A_{j-1} = B A_j + (I - P) B (h wbar_{j-1}) [+ (1 - h) wbar_{j-2}],
+    //   ybar = zbar + A_0,
+    // where B (h x) is needed on the blocks of the halo blocks' elements and
+    // their face neighbours only.
     void* KA = Zs;
     void* KB = Zs2;
     void* Z0 = p->lZ0.p;
+    // one adjoint substep stage on the halo blocks, fused with its
+    // combination: A = B kcur on the fine rows (0 elsewhere); zbar += A;
+    // knext = a0 Z0 + b0 A; wbar_j += cw_j kcur on the fine rows
+    auto adj_stage = [&](const void* kcur, const double* cw, double a0, double b0, void* knext) {
+        a.Y = kcur;
+        a.U = U;
+        a.Uout = U;
+        a.Acc = Z0;
+        a.Ynext = knext;
+        a.Kout = nullptr;
+        a.imask = nullptr;
+        a.src_rows = 0;
+        a.mode = LTS_ADJ;
+        a.le = a0;
+        a.lf = b0;
+        a.lmask = fine;
+        a.lnw = order;
+        for (int j = 0; j < order; ++j) {
+            a.lw[j] = WB[j];
+            a.lcw[j] = cw[j];
+        }
+        a.blist = hbl;
+        a.nblist = nhb;
+        stage_dim(s, a, st);
+        a.mode = RHS;
+        a.Acc = a.Ynext = a.Uout = nullptr;
+        a.lnw = 0;
+        a.lmask = nullptr;
+        a.blist = nullptr;
+        a.nblist = 0;
+    };
+    const int* h2l = p->lts_h2blocks.as<int>();
+    const int64_t nh2b = p->lts_nh2b;
     for (int nn = 0; nn < M; ++nn) {
-        for (int k = 0; k < order; ++k) launch_zero(WB[k], n * s.esize(), st);
         if (nhb > 0) {
+            // the substeps accumulate wbar on the fine rows
+            for (int k = 0; k < order; ++k)
+                launch_lts_axpy(prec, n, np6, fbl, nfb, nullptr, 0, 0.0, nullptr, 0.0, U, WB[k], st);
             double cw[4];
             for (int l = m - 1; l >= 0; --l) {
                 const double tau = l * h;
@@ -283,49 +382,43 @@ void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool
                 if (c.scheme == 2) {
                     launch_lts_axpy(prec, n, np6, hbl, nhb, nullptr, 0, 0.0, nullptr, h, Z0, KA, st);  // kbar2
                     poly(tau + 0.5 * h, cw);
-                    rhs_on(fbl, nfb);
-                    rhs(KA, Kb, false, 0.0, 0, nullptr, 0);
-                    launch_lts_adjoint(prec, n, np6, hbl, nhb, fine, 0, Kb, U, Z0, 0.0, 0.5 * h, KB, KA, WB, cw,
-                                       order, st);
+                    adj_stage(KA, cw, 0.0, 0.5 * h, KB);
                     poly(tau, cw);
-                    rhs(KB, Kb, false, 0.0, 0, nullptr, 0);
-                    launch_lts_adjoint(prec, n, np6, hbl, nhb, fine, 0, Kb, U, Z0, 0.0, 0.0, nullptr, KB, WB, cw,
-                                       order, st);
+                    adj_stage(KB, cw, 0.0, 0.0, nullptr);
                 } else {
                     launch_lts_axpy(prec, n, np6, hbl, nhb, nullptr, 0, 0.0, nullptr, h / 6.0, Z0, KA, st);  // kbar4
                     poly(tau + h, cw);
-                    rhs_on(fbl, nfb);
-                    rhs(KA, Kb, false, 0.0, 0, nullptr, 0);
-                    launch_lts_adjoint(prec, n, np6, hbl, nhb, fine, 0, Kb, U, Z0, h / 3.0, h, KB, KA, WB, cw, order,
-                                       st);
+                    adj_stage(KA, cw, h / 3.0, h, KB);
                     poly(tau + 0.5 * h, cw);
-                    rhs(KB, Kb, false, 0.0, 0, nullptr, 0);
-                    launch_lts_adjoint(prec, n, np6, hbl, nhb, fine, 0, Kb, U, Z0, h / 3.0, 0.5 * h, KA, KB, WB, cw,
-                                       order, st);
-                    rhs(KA, Kb, false, 0.0, 0, nullptr, 0);
-                    launch_lts_adjoint(prec, n, np6, hbl, nhb, fine, 0, Kb, U, Z0, h / 6.0, 0.5 * h, KB, KA, WB, cw,
-                                       order, st);
+                    adj_stage(KB, cw, h / 3.0, 0.5 * h, KA);
+                    adj_stage(KA, cw, h / 6.0, 0.5 * h, KB);
                     poly(tau, cw);
-                    rhs(KB, Kb, false, 0.0, 0, nullptr, 0);
-                    launch_lts_adjoint(prec, n, np6, hbl, nhb, fine, 0, Kb, U, Z0, 0.0, 0.0, nullptr, KB, WB, cw,
-                                       order, st);
+                    adj_stage(KB, cw, 0.0, 0.0, nullptr);
                 }
-                rhs_on(nullptr, 0);
             }
         }
         // coarse rows: wbar_k = al_k zbar (zbar there is the step's end value)
-        for (int k = 0; k < order; ++k)
-            launch_lts_axpy(prec, n, np6, nullptr, 0, fine, 1, 1.0, WB[k], al[k], U, WB[k], st);
-        // dbar_k = (I - P) B wbar_k; dbar_{k-1} += B dbar_k; ybar = zbar + dbar_0
-        for (int k = 0; k < order; ++k) {
-            rhs(WB[k], Kb, false, 0.0, 0, nullptr, 0);
-            launch_lts_axpy(prec, n, np6, nullptr, 0, fine, 1, 0.0, nullptr, 1.0, Kb, WB[k], st);
+        launch_lts_wbar_close(prec, n, np6, fine, U, WB, al, order, st);
+        // A_{p-1} (into WB[p-1])
+        rhs(WB[order - 1], Kb, false, 0.0, 0, nullptr, 0);
+        launch_lts_axpy(prec, n, np6, nullptr, 0, fine, 1, 0.0, nullptr, 1.0, Kb, WB[order - 1], st);
+        launch_lts_axpy(prec, n, np6, nullptr, 0, hbmask, 1, 1.0, WB[order - 1], 1.0, WB[order - 2], WB[order - 1],
+                        st);
+        for (int j = order - 1; j >= 1; --j) {
+            rhs(WB[j], Kb, false, 0.0, 0, nullptr, 0);  // B A_j
+            if (nh2b > 0) {                              // B (h wbar_{j-1}) near the halo
+                rhs_on(h2l, nh2b);
+                rhs(WB[j - 1], KA, false, 0.0, 0, hbmask, 0);
+                rhs_on(nullptr, 0);
+            }
+            void* Aout = j >= 2 ? WB[j - 1] : U;
+            if (j >= 2)  // A_{j-1} = B A_j + (1 - h) wbar_{j-2} [+ below]
+                launch_lts_axpy(prec, n, np6, nullptr, 0, hbmask, 1, 1.0, Kb, 1.0, WB[j - 2], Aout, st);
+            else  // ybar = zbar + B A_1 [+ below]
+                launch_lts_axpy(prec, n, np6, nullptr, 0, nullptr, 0, 1.0, U, 1.0, Kb, Aout, st);
+            if (nh2b > 0)  // + (I - P) B (h wbar_{j-1})
+                launch_lts_axpy(prec, n, np6, h2l, nh2b, fine, 1, 1.0, Aout, 1.0, KA, Aout, st);
         }
-        for (int k = order - 1; k >= 1; --k) {
-            rhs(WB[k], Kb, false, 0.0, 0, nullptr, 0);
-            launch_lts_axpy(prec, n, np6, nullptr, 0, nullptr, 0, 1.0, WB[k - 1], 1.0, Kb, WB[k - 1], st);
-        }
-        launch_lts_axpy(prec, n, np6, nullptr, 0, nullptr, 0, 1.0, U, 1.0, WB[0], U, st);
     }
 }
 

@@ -600,20 +600,56 @@ static void run_period(cmcg_problem* p, const StepCfg& c, bool src, bool filt, b
     CMCG_HIP(hipGraphLaunch(it->second, st));
 }
 
+// One LTS period (forward with or without source and filter, or the adjoint).
+// A forward period is replayed from a captured graph when use_graph (one
+// host call for its thousands of launches; as fast as the eager launches on
+// the GPU).  The adjoint period always runs eager: replaying its graph was
+// measured 19% slower than launching it (216 against 182 ms per period on a
+// 55200-tet P2 FP64 mesh, 4 substeps).
+static void run_lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool filt, bool use_graph,
+                           hipStream_t st) {
+    if (!use_graph || direction < 0) {
+        lts_period(p, c, direction, src, filt, st);
+        return;
+    }
+    const int variant = get_stage_variant(p->sp->q, p->sp->precision);
+    const int64_t key = ((int64_t)c.M << 24) | ((int64_t)c.lts << 16) | (variant << 8) | (direction < 0 ? 0x80 : 0) |
+                        (c.scheme << 4) | (src ? 2 : 0) | (filt ? 1 : 0);
+    auto it = p->lts_graphs.find(key);
+    if (it == p->lts_graphs.end()) {
+        if (!p->cap_stream) CMCG_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+        CMCG_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+        try {
+            lts_period(p, c, direction, src, filt, p->cap_stream);
+        } catch (...) {
+            hipGraph_t g;
+            (void)hipStreamEndCapture(p->cap_stream, &g);
+            throw;
+        }
+        hipGraph_t g;
+        CMCG_HIP(hipStreamEndCapture(p->cap_stream, &g));
+        hipGraphExec_t ge;
+        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) fail(CMCG_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        it = p->lts_graphs.emplace(key, ge).first;
+    }
+    CMCG_HIP(hipGraphLaunch(it->second, st));
+}
+
 // X (FP64 dof vector) -> propagate one period -> Y = S^d P S^d X - sub
 void apply_period(cmcg_problem* p, const StepCfg& c, const cmcg_options* o, const double* X, double* Yo,
                          const double* sub, int direction, bool src, bool filt, hipStream_t st) {
     const SpaceData& s = *p->sp;
     const int flip = direction < 0 ? 1 : 0;
     if (c.lts > 1) {
-        // local time stepping: plain field-precision state (no FP32 low part),
-        // eager launches
+        // local time stepping: plain field-precision state (no FP32 low part)
         ensure_lts(p, c);
         if (X)
             to_field_dim(s, X, p->U.p, nullptr, s.ndof, flip, st);
         else
             launch_zero(p->U.p, p->U.bytes, st);
-        lts_period(p, c, direction, src && direction > 0, filt, st);
+        run_lts_period(p, c, direction, src && direction > 0, filt, o->use_graph != 0, st);
         if (Yo) from_field_dim(s, p->U.p, nullptr, Yo, sub, s.ndof, flip, st);
         return;
     }
@@ -641,6 +677,8 @@ void prepare(cmcg_problem* p, const StepCfg& c) {
         build_geo(p, c.alpha);
         for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
         p->graphs.clear();
+        for (auto& kv : p->lts_graphs) (void)hipGraphExecDestroy(kv.second);
+        p->lts_graphs.clear();
     }
     ensure_work(p);
 }
