@@ -72,8 +72,7 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: engine memory budget")
     ap.add_argument("--cobatch", type=int, default=1,
                     help="serving: queued requests on one space (n, q) that may share a slot and run as one "
-                         "batched solve (1: every request alone); the short served stream of the default run "
-                         "is also measured with 4")
+                         "batched solve (1: every request alone)")
     ap.add_argument("--lts-n", type=int, default=20, help="lts: cells per axis")
     ap.add_argument("--lts-r", type=int, default=16, help="lts: the thin layers are 1/r of a cell wide")
     ap.add_argument("--lts-m", type=int, default=4, help="lts: fine substeps per coarse step")
@@ -88,9 +87,17 @@ def parse():
 # 48000-tet P3 FP32 problem, with the scales a 1 GiB copy gives each counter;
 # valid only for the kernel source they were taken on (SHA-256 below).
 MEASURED_TRAFFIC = {
-    "kernels_sha256": "abfd2af7eb55a523de38f4427543a9f2098590ddf924084d5e74d567c74653c4",
-    "kernel": "k_stage_mfma<3,true,false,2>", "K": 48000,
-    "fetch_kib": 42904.72, "fetch_scale": 2.0000, "write_kib": 42195.65, "write_scale": 1.0000,
+    "kernels_sha256": "d4ba8c5c55e148b5aaeeb1aaf31984c53f4b66390ded36d07571a4f8d70cebec",
+    "kernel": "k_stage_mfma<float,3,true,false,2,false,true>", "K": 48000,
+    "fetch_kib": 41476.00, "fetch_scale": 2.0000, "write_kib": 42201.28, "write_scale": 1.0000,
+}
+
+
+# The same for the FP64 stage kernel of the plain FP64 solve (48000 tets, P3).
+MEASURED_TRAFFIC_FP64 = {
+    "kernels_sha256": "d4ba8c5c55e148b5aaeeb1aaf31984c53f4b66390ded36d07571a4f8d70cebec",
+    "kernel": "k_stage_mfma<double,3,true,false,2>", "K": 48000,
+    "fetch_kib": 80723.07, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000,
 }
 
 
@@ -1022,7 +1029,8 @@ def main():
                                 "frac": bpl64 / pl64 / 1e9 / HBM_PEAK_GBS,
                                 "kernel": STAGE_KERNEL64[v64].format(q=w.q), "avg_launch_us": pl64 * 1e6,
                                 "bytes_per_launch": bpl64, "bytes_per_dof_update": method_bytes_per_dof_update(w.q, 8),
-                                "traffic": None}
+                                "traffic": measured_traffic(STAGE_KERNEL64[v64].format(q=w.q), K,
+                                                            MEASURED_TRAFFIC_FP64)}
         log(f"fp64 stage launch {pl64 * 1e6:.1f} us ({out['roofline_fp64']['kernel']})")
     del s32, p32, r
     if not a.no_extra:
@@ -1031,7 +1039,6 @@ def main():
         out["roofline_scatterer"] = scatterer_kernel(a)
         out["roofline_batched"] = batched_kernel(a)
         out["serving"] = serving_short(a, a.cobatch)
-        out["serving_cobatch4"] = serving_short(a, 4)
     if not a.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)

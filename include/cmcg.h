@@ -471,7 +471,8 @@ int cmcg_engine_collect_batch(cmcg_engine* e, int slot, cmcg_result** results, i
  * faces requested at once and two alternating flux tiles (q = 2, 3), 6 is 4
  * with the two waves splitting the output by column tiles instead of row
  * tiles (q = 3), 7 combines 5 and 6 (q = 3); variants that do not exist for
- * (q, precision) fall back to 0.  All compute the same Phi(t, Y) and stage update.  Process-wide;
+ * (q, precision) fall back to 0.  All compute the same Phi(t, Y) and stage update.  Defaults: 4
+ * for q = 2, 3 (both precisions), 0 for q = 1.  Process-wide;
  * not thread-safe against concurrent solves.  Returns CMCG_ERR_ARG for an unknown q / precision /
  * variant.  cmcg_tune_get_stage reports the current choice. */
 #define CMCG_STAGE_VARIANTS 8

@@ -1534,13 +1534,16 @@ __global__ void k_nonfinite(const double* X, int64_t n, int* flag) {
 
 // Stage-kernel variant per (q, precision): 0 = gather per face, 1 = gathers
 // pipelined one face ahead, 2 / 3 = matrix cores (q >= 2) without /
-// with the one-face-ahead gathers, 4 = 3 with two waves per block.  Chosen
-// from measurements; overridable through cmcg_tune_stage() and the
-// autotuner.  Defaults: FP32 P2 and P3 on the matrix cores with two waves per
-// block (P3: 38.2 us vs 41.5 us at 48000 tets, 256 vs 260 us at 384000; P2:
-// 8.6 vs 10.4 us at 10368 tets, 28.8 vs 31.0 us at 82944, but 126 vs 123 us
-// at 384000, where the autotuner keeps one wave), per-face gathers otherwise.
-int g_variant[kMaxQ + 1][2] = {{0, 0}, {0, 0}, {0, 4}, {0, 4}};
+// with the one-face-ahead gathers, 4 = 3 with two waves per block, 5-7 the
+// eager-gather and column-split forms of 4.  Chosen from measurements;
+// overridable through cmcg_tune_stage() and the autotuner.  Defaults: P2 and
+// P3 on the matrix cores with two waves per block, both precisions (FP32 P3:
+// 38.2 us vs 41.5 us at 48000 tets, 256 vs 260 us at 384000; FP32 P2: 8.6 vs
+// 10.4 us at 10368 tets, 28.8 vs 31.0 us at 82944, but 126 vs 123 us at
+// 384000, where the autotuner keeps one wave; FP64 P3: 71.0 us against 112.7
+// us for the VALU form at 48000 tets, FP64 P2: 37.9 against 43.2 us at
+// 55200), per-face gathers for P1.
+int g_variant[kMaxQ + 1][2] = {{0, 0}, {0, 0}, {4, 4}, {4, 4}};
 inline int stage_variant(int q, int precision) { return g_variant[q][precision]; }
 
 inline int grid_for(int64_t n, int threads = 256) {

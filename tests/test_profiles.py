@@ -71,6 +71,7 @@ def _traffic_table(text: str):
 
 @pytest.mark.parametrize("name,table", [
     ("k_stage_mfma_q3_large_single_traffic.md", bench.MEASURED_TRAFFIC),
+    ("k_stage_mfma_q3_fp64_large_single_traffic.md", bench.MEASURED_TRAFFIC_FP64),
     ("k_stage2d_p3_trap_disk_traffic.md", bench.MEASURED_TRAFFIC_2D),
 ])
 def test_traffic_summary_matches_bench_table(name, table):
