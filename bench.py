@@ -130,7 +130,8 @@ STAGE_KERNEL = {0: "k_stage<float,{q},false,false>", 1: "k_stage<float,{q},true,
                 2: "k_stage_mfma<float,{q},false,false,1>", 3: "k_stage_mfma<float,{q},true,false,1>",
                 4: "k_stage_mfma<float,{q},true,false,2>", 5: "k_stage_mfma<float,{q},true,false,2,true>",
                 6: "k_stage_mfma<float,{q},true,false,2,false,true>",
-                7: "k_stage_mfma<float,{q},true,false,2,true,true>"}
+                7: "k_stage_mfma<float,{q},true,false,2,true,true>",
+                8: "k_stage_mfma<float,{q},true,false,4>"}
 STAGE_KERNEL64 = {v: k.replace("float", "double") for v, k in STAGE_KERNEL.items()}
 
 
@@ -219,6 +220,41 @@ def cpu_baseline(w, steps: int):
     return {"value": ndof * steps / el, "unit": "dof-updates/s", "cores": round(cores, 2), "kind": "oracle",
             "sample": f"{steps} RK{'4' if w.q > 1 else '2'} step(s) of the full {p.K}-tet P{w.q} mesh "
                       f"({ndof} dofs), FP64 numpy oracle, {el:.1f} s"}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_baseline_child(args):
+    fn, w, steps = args
+    return fn(w, steps)
+
+
+def cpu_baseline_threads(fn, w, steps: int, threads: int) -> dict:
+    """fn(w, steps) in a fresh process whose BLAS / OpenMP pools hold
+    `threads` threads (the oracle unchanged; only the thread count differs)."""
+    import concurrent.futures as cf
+    import multiprocessing
+    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in keys}
+    os.environ.update({k: str(threads) for k in keys})
+    try:
+        with cf.ProcessPoolExecutor(max_workers=1, mp_context=multiprocessing.get_context("spawn")) as ex:
+            return ex.submit(_cpu_baseline_child, (fn, w, steps)).result()
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
 
 
 def batched(a):
@@ -1042,6 +1078,12 @@ def main():
     if not a.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
+        # the same oracle on one thread (half the sample: the same per-step rate)
+        log("cpu baseline, one thread")
+        one = cpu_baseline_threads(cpu_baseline, w, max(1, a.cpu_steps // 2), 1)
+        out["cpu_baseline"]["single_thread"] = {k: one[k] for k in ("value", "cores", "sample")}
+        out["cpu_baseline"]["cpu_model"] = _cpu_model()
+        out["cpu_baseline"]["host_threads"] = os.cpu_count()
     print(json.dumps(out), flush=True)
 
 

@@ -470,12 +470,14 @@ int cmcg_engine_collect_batch(cmcg_engine* e, int slot, cmcg_result** results, i
  * output tiles (q = 2, 3), 5 is 4 with the neighbour traces of all four
  * faces requested at once and two alternating flux tiles (q = 2, 3), 6 is 4
  * with the two waves splitting the output by column tiles instead of row
- * tiles (q = 3), 7 combines 5 and 6 (q = 3); variants that do not exist for
+ * tiles (q = 3), 7 combines 5 and 6 (q = 3), 8 is 3 with four waves per
+ * block, each computing one row tile and half of the column tiles (q = 3)
+ * or a quarter of them (q = 2); variants that do not exist for
  * (q, precision) fall back to 0.  All compute the same Phi(t, Y) and stage update.  Defaults: 4
  * for q = 2, 3 (both precisions), 0 for q = 1.  Process-wide;
  * not thread-safe against concurrent solves.  Returns CMCG_ERR_ARG for an unknown q / precision /
  * variant.  cmcg_tune_get_stage reports the current choice. */
-#define CMCG_STAGE_VARIANTS 8
+#define CMCG_STAGE_VARIANTS 9
 int cmcg_tune_stage(int q, int precision, int variant);
 int cmcg_tune_get_stage(int q, int precision, int* variant);
 

@@ -789,11 +789,12 @@ template <typename T, int Q, int NTH = 64, bool LTSM = false> struct MfmaUpdateI
 // of one), and faces alternate between two flux tiles, so a face needs one
 // barrier instead of two.  CSPLIT (P3, two waves): the waves split the output
 // by column tiles, each building only its own B operands and running both
-// row tiles.
+// row tiles.  W = 4: each wave one row tile and two column tiles (P3) or one
+// column tile (P2), a quarter of the MFMAs and fewer registers per wave.
 template <typename T, int Q, bool PIPE, bool MH, int W, bool EAGER = false, bool CSPLIT = false, bool LTSM = false>
 __global__ __launch_bounds__(64 * W)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (W == 1 || (EAGER && Q == 3) ? 4 : (EAGER || CSPLIT ? 5 : 6))
-                                                   : (W == 1 || EAGER || CSPLIT ? 2 : 3), 8)))
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (W == 4 ? (Q == 3 ? 7 : 8) : W == 1 || (EAGER && Q == 3) ? 4 : (EAGER || CSPLIT ? 5 : 6))
+                                                   : (W == 4 ? 4 : W == 1 || EAGER || CSPLIT ? 2 : 3), 8)))
 void k_stage_mfma(StageArgs args, int64_t per) {
     using MD = MfmaDim<Q>;
     using acc_t = typename Mfma<T>::acc_t;
@@ -804,13 +805,17 @@ void k_stage_mfma(StageArgs args, int64_t per) {
     constexpr int NTH = 64 * W;                      // threads of the workgroup
     constexpr int RF = (EPW * NFP + NTH - 1) / NTH;  // flux items per thread and face
     // two waves split the output tiles: by rows when there are two row tiles
-    // (P3, unless CSPLIT), by the four 16-column tiles otherwise
-    constexpr bool ROWS = W == 2 && MT == 2 && !CSPLIT, COLS = W == 2 && (MT == 1 || CSPLIT);
+    // (P3, unless CSPLIT), by the four 16-column tiles otherwise; four waves
+    // split by rows (P3) and by columns
+    static_assert(W == 1 || W == 2 || W == 4, "one, two or four waves per block");
+    constexpr bool ROWS = (W == 2 && MT == 2 && !CSPLIT) || (W == 4 && MT == 2);
+    constexpr bool COLS = (W == 2 && (MT == 1 || CSPLIT)) || W == 4;
     constexpr int NB = EAGER ? 2 : 1;  // flux tiles
     using Sh = MfmaShared<T, Q, NB>;
-    constexpr int MW = ROWS ? 1 : MT;   // output row tiles of one wave
-    constexpr int NW = COLS ? 2 : 4;    // output column tiles of one wave
-    static_assert(W == 1 || ((ROWS || COLS) && RF == 1), "two waves per block need one flux item per thread");
+    constexpr int MW = ROWS ? 1 : MT;  // output row tiles of one wave
+    constexpr int CWAVES = COLS ? (ROWS ? W / 2 : W) : 1;  // waves across the column tiles
+    constexpr int NW = 4 / CWAVES;                          // output column tiles of one wave
+    static_assert(W == 1 || ((ROWS || COLS) && RF == 1), "several waves per block need one flux item per thread");
     __shared__ Sh sh;
 
     StageArgs a;
@@ -825,8 +830,9 @@ void k_stage_mfma(StageArgs args, int64_t per) {
     const T* __restrict__ Y = (const T*)a.Y;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int mt0 = ROWS ? tid >> 6 : 0;        // first output row tile of this wave
-    const int nt0 = COLS ? 2 * (tid >> 6) : 0;  // first output column tile of this wave
+    const int wave = tid >> 6;
+    const int mt0 = ROWS ? (wave & 1) : 0;                           // first output row tile of this wave
+    const int nt0 = COLS ? NW * (ROWS ? wave >> 1 : wave) : 0;  // first output column tile of this wave
     const int ne = (int)((a.K - e0) < EPW ? (a.K - e0) : EPW);
     const int64_t base = e0 * 6 * NP;
     constexpr int PV = 16 / (int)sizeof(T);  // values per 16-byte group
@@ -1574,6 +1580,10 @@ void stage_launch_mh(const StageArgs& a, hipStream_t s) {
         }
         if (v == 5) {
             hipLaunchKernelGGL((k_stage_mfma<T, Q, true, MH, 2, true>), grid, dim3(128), 0, s, a, per);
+            return;
+        }
+        if (v == 8) {
+            hipLaunchKernelGGL((k_stage_mfma<T, Q, true, MH, 4>), grid, dim3(256), 0, s, a, per);
             return;
         }
         if constexpr (Q == 3) {

@@ -44,11 +44,11 @@ def variant(lib, request):
     lib.cmcg_tune_stage(q, prec, old)
 
 
-# 0, 1 run everywhere; the matrix-core variants 2-5 (4, 5: two waves per block; 5: all
-# faces' gathers at once) exist at q >= 2 in both field precisions (FP64 on
-# v_mfma_f64_16x16x4f64), 6 and 7 (column split) at q = 3
+# 0, 1 run everywhere; the matrix-core variants 2-5 and 8 (4, 5: two waves per block;
+# 5: all faces' gathers at once; 8: four waves per block) exist at q >= 2 in both field
+# precisions (FP64 on v_mfma_f64_16x16x4f64), 6 and 7 (column split) at q = 3
 VARIANTS = [(q, p, v) for q in (1, 2, 3) for p in (0, 1) for v in (0, 1)] + \
-    [(q, p, v) for q in (2, 3) for p in (0, 1) for v in (2, 3, 4, 5)] + \
+    [(q, p, v) for q in (2, 3) for p in (0, 1) for v in (2, 3, 4, 5, 8)] + \
     [(3, p, v) for p in (0, 1) for v in (6, 7)]
 
 
@@ -365,9 +365,9 @@ def test_cmcg_fixed_iterations_conductive_with_boundary_data(lib, q, n):
 
 @pytest.mark.parametrize("q", [2, 3])
 def test_two_wave_blocks_equal_one_wave_blocks(lib, q):
-    """Variant 4 (two waves per 10-element block, half the output tiles each)
-    does the same arithmetic as variant 3: right-hand side and a period agree
-    bit for bit, also with a partial last block."""
+    """Variants 4 (two waves per 10-element block, half the output tiles each)
+    and 8 (four waves) do the same arithmetic as variant 3: right-hand side and
+    a period agree bit for bit, also with a partial last block."""
     import torch
     old = lib.cmcg_tune_get_stage(q, 1)
     try:
@@ -382,14 +382,15 @@ def test_two_wave_blocks_equal_one_wave_blocks(lib, q):
                                     np.full(K, 0.2), 2 * np.pi, j)
         U = dev(np.random.default_rng(4).standard_normal((K, 6, Np)))
         outs = []
-        for v in (3, 4):
+        for v in (3, 4, 8):
             lib.cmcg_tune_stage(q, 1, v)
             r, UT = torch.empty_like(U), torch.empty_like(U)
             lib.cmcg_debug_rhs(p, U, r, t=0.3, with_source=True)
             lib.cmcg_debug_period(p, U, UT, 1, True, opts=lib.cmcg_options_default(steps=12))
             torch.cuda.synchronize()
             outs.append((r.cpu(), UT.cpu()))
-        assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+        for o in outs[1:]:
+            assert torch.equal(outs[0][0], o[0]) and torch.equal(outs[0][1], o[1])
     finally:
         lib.cmcg_tune_stage(q, 1, old)
 
