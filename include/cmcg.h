@@ -405,7 +405,9 @@ int cmcg_debug_dot_noalloc(const cmcg_problem* p, const double* u_dev, const dou
  * filter period), so its result equals the one cmcg_solve returns.
  *
  * cmcg_problem_footprint: device bytes a solve of p keeps resident (problem
- *   data, field / filter / CG vectors, result) -- the admission cost.
+ *   data, field / filter / CG vectors, result) -- the admission cost; with
+ *   local time stepping (o->lts_ratio > 1) the engine adds 12 field vectors
+ *   and the fine-region masks and block lists.
  * cmcg_engine_create: budget = device bytes the engine may hold for admitted
  *   solves; max_slots = concurrent solves (1..1024).
  * cmcg_engine_admit: starts a solve in a free slot; CMCG_ERR_NOMEM when no

@@ -88,6 +88,17 @@ size_t footprint(const cmcg_problem* p) {
     return b + (size_t)dot_partials() * 8 + 4096;
 }
 
+// footprint with the work buffers local time stepping adds (Taylor
+// coefficients, frozen coarse terms, adjoint vectors; masks and block lists)
+size_t footprint(const cmcg_problem* p, const cmcg_options* o) {
+    size_t b = footprint(p);
+    if (o && o->lts_ratio > 1) {
+        const SpaceData& s = *p->sp;
+        b += 12 * s.ndof * s.esize() + 5 * (size_t)source_mask_words(s.K) * 4;
+    }
+    return b;
+}
+
 }  // namespace cmcg
 
 using namespace cmcg;
@@ -145,7 +156,7 @@ int cmcg_engine_admit(cmcg_engine* e, cmcg_problem* p, const cmcg_options* o, in
         if (s.state != 0 && s.holds(p)) fail(CMCG_ERR_STATE, "engine_admit: problem already held by a slot");
         if (s.state == 0 && free_slot < 0) free_slot = i;
     }
-    const size_t need = footprint(p);
+    const size_t need = footprint(p, o);
     // a request larger than the whole budget can never be admitted: tell the
     // caller so, instead of "not now"
     if (need > e->budget)

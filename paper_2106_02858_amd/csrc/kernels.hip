@@ -369,9 +369,10 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     const int mode = a.mode;
     constexpr bool COMP = std::is_same<T, float>::value;  // compensated state U + Ulo
     const bool needL = COMP && (mode == RK2_S2 || mode == RK4_S4);
-    const bool needU = LTSM || mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || needL;
-    const bool needA =
-        LTSM ? (mode == LTS_ADJ || a.Acc != nullptr) : (mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4);
+    const bool needU =
+        LTSM ? (mode == LTS_FWD || mode == LTS_ADJ) : (mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || needL);
+    const bool needA = LTSM ? (mode == LTS_ADJ || (mode == LTS_FWD && a.Acc != nullptr))
+                            : (mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4);
 
     const uint32_t keep = a.imask ? (a.imask[blk] ^ (a.imask_inv ? 0xffffffffu : 0u)) : 0xffffffffu;
     {
@@ -538,7 +539,24 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
     const T cy = (T)a.cy, ca = (T)a.ca, cu = (T)a.cu;
     T o1[NP], o2[NP];
     if constexpr (LTSM) {
-        if (mode == LTS_FWD) {
+        if (mode == LTS_CHAIN) {
+            auto on = [&](const uint32_t* m, int inv) {
+                return !m || ((((m[blk] >> elc) & 1u) ^ (uint32_t)inv) != 0);
+            };
+            const bool oa = on(a.lmask, a.linv), ob = on(a.lmaskB, a.linvB), oc = on(a.lmaskC, a.linvC);
+#pragma unroll
+            for (int i = 0; i < NP; ++i) o1[i] = oa ? kv[i] : T(0);
+            T x[NP];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const bool use = j == 0 ? ob : j == 1 ? oc : true;
+                if (!args.lw[j] || !use) continue;
+                Row<T, NP>::load((const T*)args.lw[j] + grow, x);
+#pragma unroll
+                for (int i = 0; i < NP; ++i) o1[i] += x[i];
+            }
+            Row<T, NP>::store((T*)a.Uout + grow, o1);
+        } else if (mode == LTS_FWD) {
             T w[NP];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -753,8 +771,8 @@ template <typename T, int Q, int NTH = 64, bool LTSM = false> struct MfmaUpdateI
         // FP64 stage 4 forms U = Acc + cu k without the state
         const bool needU =
             LTSM ? mode == LTS_FWD : mode == RK2_S2 || mode == RK4_S2 || mode == RK4_S3 || (COMP && mode == RK4_S4);
-        const bool needA =
-            LTSM ? (mode == LTS_ADJ || a.Acc != nullptr) : (mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4);
+        const bool needA = LTSM ? (mode == LTS_ADJ || (mode == LTS_FWD && a.Acc != nullptr))
+                                : (mode == RK4_S2 || mode == RK4_S3 || mode == RK4_S4);
         const bool needL = !LTSM && COMP && (mode == RK2_S2 || mode == RK4_S4);
         const T* src0 = needU ? (const T*)a.U : (const T*)a.Y;
 #pragma unroll
@@ -1104,7 +1122,25 @@ void k_stage_mfma(StageArgs args, int64_t per) {
         };
         T o1[PV], o2[PV];
         if constexpr (LTSM) {
-            if (mode == LTS_FWD) {  // x0 = U, x1 = Acc
+            if (mode == LTS_CHAIN) {
+                const int el = v / NP / 6;  // a 16-byte group never straddles an element
+                auto on = [&](const uint32_t* m, int inv) {
+                    return !m || ((((m[blk] >> el) & 1u) ^ (uint32_t)inv) != 0);
+                };
+                const bool oa = on(a.lmask, a.linv), ob = on(a.lmaskB, a.linvB), oc = on(a.lmaskC, a.linvC);
+#pragma unroll
+                for (int u = 0; u < PV; ++u) o1[u] = oa ? kv[u] : T(0);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const bool use = j == 0 ? ob : j == 1 ? oc : true;
+                    if (!args.lw[j] || !use) continue;
+                    T x[PV];
+                    ldv(args.lw[j], gi, x);
+#pragma unroll
+                    for (int u = 0; u < PV; ++u) o1[u] += x[u];
+                }
+                stv(a.Uout, o1);
+            } else if (mode == LTS_FWD) {  // x0 = U, x1 = Acc
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     if (j >= a.lnw) break;
@@ -1605,7 +1641,7 @@ void stage_launch_mh(const StageArgs& a, hipStream_t s) {
 
 template <typename T, int Q>
 void stage_launch(const StageArgs& a, hipStream_t s) {
-    if (a.mode == LTS_FWD || a.mode == LTS_ADJ) {  // one instantiation per order (single frequency)
+    if (a.mode == LTS_FWD || a.mode == LTS_ADJ || a.mode == LTS_CHAIN) {  // one instantiation per order
         const int64_t blocks = a.blist ? a.nblist : (a.K + EPW - 1) / EPW;
         const int64_t per = (blocks + 7) / 8;
         const dim3 grid((unsigned)(8 * per));

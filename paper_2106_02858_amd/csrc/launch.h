@@ -22,6 +22,10 @@ namespace cmcg {
 //   LTS_ADJ (adjoint substep stage; Y = the adjoint stage vector kcur): on the
 //           rows of the elements set in lmask A = k and lw_j += lcw_j kcur,
 //           elsewhere A = 0; Uout = U + A; Ynext = le Acc + lf A (nullable)
+//   LTS_CHAIN (adjoint Taylor chain): Uout = [A] k + [B] lw[0] + [C] lw[1] + lw[2],
+//           [m] x = x on the rows of the elements whose bit of the mask (lmask,
+//           lmaskB, lmaskC) xor its inv flag is set, 0 elsewhere (null mask:
+//           every row); null lw[i]: no term
 // Optional filter accumulation (FP64): F += fa * U + fb * k (complex).
 //
 // FP32 fields carry the state as an unevaluated sum U + Ulo (Ulo in bfloat16,
@@ -29,7 +33,7 @@ namespace cmcg {
 // Acc = ca k; RK4_S4: U + Ulo += Acc + cu k) and the last update of a step adds
 // its increment to U + Ulo with an exact two-sum, so rounding the state to
 // FP32 once per step does not accumulate over the period.
-enum StageMode { RK2_S1 = 0, RK2_S2, RK4_S1, RK4_S2, RK4_S3, RK4_S4, RHS, LTS_FWD, LTS_ADJ };
+enum StageMode { RK2_S1 = 0, RK2_S2, RK4_S1, RK4_S2, RK4_S3, RK4_S4, RHS, LTS_FWD, LTS_ADJ, LTS_CHAIN };
 
 struct StageArgs {
     const void* Y;      // stage input (Phi argument), [K][6][Np]
@@ -84,6 +88,9 @@ struct StageArgs {
     int lnw;
     double le, lf;
     const uint32_t* lmask;  // LTS_ADJ: output rows (one word per element block, layout of smask)
+    const uint32_t* lmaskB;
+    const uint32_t* lmaskC;
+    int linv, linvB, linvC;  // LTS_CHAIN: inversions of lmask, lmaskB, lmaskC
 };
 constexpr int kMaxHarm = 8;
 // per-member scalars of a batched stage: cy, ca, cu, scos, ssin, fa_re, fa_im, fb_re, fb_im

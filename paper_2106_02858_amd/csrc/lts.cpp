@@ -75,13 +75,19 @@ void ensure_lts_mask(cmcg_problem* p, const StepCfg& c) {
             }
         }
     }
+    std::vector<uint32_t> h2nf(nw, 0u);  // rows of those blocks outside the fine elements
     for (int64_t b = 0; b < nw; ++b) {
         bool any = false;
         for (int64_t e = 10 * b; e < std::min<int64_t>(10 * b + 10, s.K); ++e) any = any || near[e];
-        if (any) h2l.push_back((int)b);
+        if (any) {
+            h2l.push_back((int)b);
+            h2nf[b] = ~w[b] & 0x3ffu;
+        }
     }
     p->lts_mask.alloc(nw * 4);
     p->lts_hbmask.alloc(nw * 4);
+    p->lts_h2nf.alloc(nw * 4);
+    CMCG_HIP(hipMemcpy(p->lts_h2nf.p, h2nf.data(), nw * 4, hipMemcpyHostToDevice));
     CMCG_HIP(hipMemcpy(p->lts_mask.p, w.data(), nw * 4, hipMemcpyHostToDevice));
     CMCG_HIP(hipMemcpy(p->lts_hbmask.p, hb.data(), nw * 4, hipMemcpyHostToDevice));
     p->lts_nfb = (int64_t)fb.size();
@@ -368,6 +374,36 @@ void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool
         a.blist = nullptr;
         a.nblist = 0;
     };
+    // out = [rows of maskA ^ invA] B x + [outside the halo blocks] X
+    //       + [near the halo, outside the fine elements] Z + Y  (full launch)
+    const uint32_t* h2nf = p->lts_h2nf.as<uint32_t>();
+    auto chain = [&](const void* x, const uint32_t* maskA, int invA, const void* X, const void* Z, const void* Yadd,
+                     void* out) {
+        a.Y = x;
+        a.U = nullptr;
+        a.Uout = out;
+        a.Acc = a.Ynext = a.Kout = nullptr;
+        a.imask = nullptr;
+        a.src_rows = 0;
+        a.mode = LTS_CHAIN;
+        a.lmask = maskA;
+        a.linv = invA;
+        a.lmaskB = hbmask;
+        a.linvB = 1;
+        a.lmaskC = h2nf;
+        a.linvC = 0;
+        a.lw[0] = X;
+        a.lw[1] = Z;
+        a.lw[2] = Yadd;
+        a.lnw = 0;
+        a.blist = nullptr;
+        a.nblist = 0;
+        stage_dim(s, a, st);
+        a.mode = RHS;
+        a.Uout = nullptr;
+        a.lmask = a.lmaskB = a.lmaskC = nullptr;
+        a.lw[0] = a.lw[1] = a.lw[2] = nullptr;
+    };
     const int* h2l = p->lts_h2blocks.as<int>();
     const int64_t nh2b = p->lts_nh2b;
     for (int nn = 0; nn < M; ++nn) {
@@ -399,25 +435,24 @@ void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool
         }
         // coarse rows: wbar_k = al_k zbar (zbar there is the step's end value)
         launch_lts_wbar_close(prec, n, np6, fine, U, WB, al, order, st);
-        // A_{p-1} (into WB[p-1])
-        rhs(WB[order - 1], Kb, false, 0.0, 0, nullptr, 0);
-        launch_lts_axpy(prec, n, np6, nullptr, 0, fine, 1, 0.0, nullptr, 1.0, Kb, WB[order - 1], st);
-        launch_lts_axpy(prec, n, np6, nullptr, 0, hbmask, 1, 1.0, WB[order - 1], 1.0, WB[order - 2], WB[order - 1],
-                        st);
+        // A_{p-1} = (I - P) B wbar_{p-1} + (1 - h) wbar_{p-2}, then the chain;
+        // each step one right-hand side near the halo and one full launch whose
+        // update pass forms the sum (outputs alternate between Kb and the
+        // consumed wbar vector: a launch never writes its own input)
+        chain(WB[order - 1], fine, 1, WB[order - 2], nullptr, nullptr, Kb);
+        void* Ain = Kb;
         for (int j = order - 1; j >= 1; --j) {
-            rhs(WB[j], Kb, false, 0.0, 0, nullptr, 0);  // B A_j
-            if (nh2b > 0) {                              // B (h wbar_{j-1}) near the halo
+            if (nh2b > 0) {  // B (h wbar_{j-1}) near the halo
                 rhs_on(h2l, nh2b);
                 rhs(WB[j - 1], KA, false, 0.0, 0, hbmask, 0);
                 rhs_on(nullptr, 0);
             }
-            void* Aout = j >= 2 ? WB[j - 1] : U;
-            if (j >= 2)  // A_{j-1} = B A_j + (1 - h) wbar_{j-2} [+ below]
-                launch_lts_axpy(prec, n, np6, nullptr, 0, hbmask, 1, 1.0, Kb, 1.0, WB[j - 2], Aout, st);
-            else  // ybar = zbar + B A_1 [+ below]
-                launch_lts_axpy(prec, n, np6, nullptr, 0, nullptr, 0, 1.0, U, 1.0, Kb, Aout, st);
-            if (nh2b > 0)  // + (I - P) B (h wbar_{j-1})
-                launch_lts_axpy(prec, n, np6, h2l, nh2b, fine, 1, 1.0, Aout, 1.0, KA, Aout, st);
+            void* out = j == 1 ? U : (Ain == Kb ? WB[j] : Kb);
+            // A_{j-1} = B A_j + (1 - h) wbar_{j-2} + (I - P) B (h wbar_{j-1});
+            // ybar = zbar + A_0
+            chain(Ain, nullptr, 0, j >= 2 ? WB[j - 2] : nullptr, nh2b > 0 ? KA : nullptr, j == 1 ? U : nullptr,
+                  out);
+            Ain = out;
         }
     }
 }

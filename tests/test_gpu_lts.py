@@ -28,7 +28,7 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def lts_pair(lib, q, precision, tags=inputs.TAG_IMPEDANCE, seed=0, g=False):
+def lts_pair(lib, q, precision, tags=inputs.TAG_IMPEDANCE, seed=0, g=False, sigma=False):
     axes = ([0, .45, .5, .55, 1.], [0, .5, 1.], [0, .5, 1.])
     xyz, tet, tg = inputs.graded_cube_mesh(*axes, inputs.TAG_IMPEDANCE if tags == "mixed" else tags)
     if tags == "mixed":
@@ -38,11 +38,12 @@ def lts_pair(lib, q, precision, tags=inputs.TAG_IMPEDANCE, seed=0, g=False):
     K = tet.shape[0]
     rng = np.random.default_rng(seed + 1)
     eps = rng.choice([1.0, 2.0], K)
-    p0 = dg.make_problem(xyz, tet, tg, q, eps, np.ones(K), omega=2 * np.pi)
+    sig = np.where(rng.random(K) < 0.5, rng.uniform(0.1, 0.5, K), 0.0) if sigma else None
+    p0 = dg.make_problem(xyz, tet, tg, q, eps, np.ones(K), sig, omega=2 * np.pi)
     j = (inputs.gaussian_current(p0.geo.x, [.5, .5, .5], .3, 2)
          + 1j * inputs.gaussian_current(p0.geo.x, [.4, .6, .5], .3, 0))
     gg = rng.standard_normal((K, 4, p0.geo.Nfp, 3)) if g else None
-    op = dg.make_problem(xyz, tet, tg, q, eps, np.ones(K), omega=2 * np.pi, j=j, g=gg)
+    op = dg.make_problem(xyz, tet, tg, q, eps, np.ones(K), sig, omega=2 * np.pi, j=j, g=gg)
     s, lp = lib_problem(lib, op, precision, xyz, tet, tg)
     return op, s, lp
 
@@ -168,3 +169,49 @@ def test_periods_on_a_refined_cube(lib, direction):
     else:
         ref = lts.backward(op, U, M, 4, fine, 2)
     assert rel_norm(op, host(out), ref) < 1e-12
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_periods_with_conductivity(lib, precision):
+    """Conductive elements (sigma in [0.1, 0.5] on about half of them) with
+    boundary data: forward period with source and filter, adjoint period."""
+    print(f"lts conductive prec={precision}", flush=True)
+    op, s, lp = lts_pair(lib, 2, precision, tags="mixed", seed=70, g=True, sigma=True)
+    o = lib.cmcg_options_default(lts_ratio=M_RATIO)
+    M, _ = lib.cmcg_problem_steps(lp, o)
+    _, fine = lts.lts_steps(op, M_RATIO)
+    U0 = np.random.default_rng(71).standard_normal((op.K, 6, op.Np))
+    UT, fr, fi = dev(np.zeros_like(U0)), dev(np.zeros_like(U0)), dev(np.zeros_like(U0))
+    lib.cmcg_debug_period(lp, dev(U0), UT, 1, True, fr, fi, opts=o)
+    ref, F = lts.forward(op, U0, M, M_RATIO, fine, 4, True, filt=True)
+    assert rel_norm(op, host(UT), ref) < TOL[precision]
+    assert rel_norm_c(op, host(fr) + 1j * host(fi), F) < TOL[precision]
+    out = dev(np.zeros_like(U0))
+    lib.cmcg_debug_period(lp, dev(U0), out, -1, False, opts=o)
+    assert rel_norm(op, host(out), lts.backward(op, U0, M, M_RATIO, fine, 4)) < TOL[precision]
+
+
+def test_served_request_with_local_time_stepping_equals_solo_solve(lib):
+    """An LTS solve admitted to the serving engine (beside a global-stepping
+    one on another slot) returns the fields of the same solve run alone, bit
+    for bit."""
+    op, s, lp = lts_pair(lib, 1, 0, seed=80)
+    op2, s2, lp2 = lts_pair(lib, 2, 1, seed=81)
+    o = lib.cmcg_options_default(tol=1e-8, max_iter=300, lts_ratio=M_RATIO)
+    o2 = lib.cmcg_options_default(tol=1e-6, max_iter=300)
+    e = lib.cmcg_engine_create(1 << 32, 2)
+    s1 = lib.cmcg_engine_admit(e, lp, o)
+    s2_ = lib.cmcg_engine_admit(e, lp2, o2)
+    while lib.cmcg_engine_poll(e, s1) == 1 or lib.cmcg_engine_poll(e, s2_) == 1:
+        lib.cmcg_engine_step(e)
+    served = lib.cmcg_engine_collect(e, s1, lp)
+    lib.cmcg_engine_collect(e, s2_, lp2)
+    alone = lib.cmcg_solve(lp, o)
+    a, b = lib.cmcg_result_stats(served), lib.cmcg_result_stats(alone)
+    assert a["iters"] == b["iters"] and a["steps"] == b["steps"]
+    f = []
+    for r in (served, alone):
+        fr, fi = dev(np.zeros((op.K, 6, op.Np))), dev(np.zeros((op.K, 6, op.Np)))
+        lib.cmcg_result_filtered_device(r, fr, fi)
+        f.append(host(fr) + 1j * host(fi))
+    assert np.array_equal(f[0], f[1])
