@@ -1645,10 +1645,16 @@ void stage_launch(const StageArgs& a, hipStream_t s) {
         const int64_t blocks = a.blist ? a.nblist : (a.K + EPW - 1) / EPW;
         const int64_t per = (blocks + 7) / 8;
         const dim3 grid((unsigned)(8 * per));
-        if constexpr (Q >= 2)
-            hipLaunchKernelGGL((k_stage_mfma<T, Q, true, false, 2, false, false, true>), grid, dim3(128), 0, s, a,
-                               per);
-        else
+        // four waves per block where the autotuner chose them for this order
+        // and precision, two otherwise
+        if constexpr (Q >= 2) {
+            if (stage_variant(Q, sizeof(T) == 8 ? CMCG_FP64 : CMCG_FP32) == 8)
+                hipLaunchKernelGGL((k_stage_mfma<T, Q, true, false, 4, false, false, true>), grid, dim3(256), 0, s,
+                                   a, per);
+            else
+                hipLaunchKernelGGL((k_stage_mfma<T, Q, true, false, 2, false, false, true>), grid, dim3(128), 0, s,
+                                   a, per);
+        } else
             hipLaunchKernelGGL((k_stage<T, Q, false, false, true>), grid, dim3(64), 0, s, a, per);
         return;
     }

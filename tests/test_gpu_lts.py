@@ -215,3 +215,26 @@ def test_served_request_with_local_time_stepping_equals_solo_solve(lib):
         lib.cmcg_result_filtered_device(r, fr, fi)
         f.append(host(fr) + 1j * host(fi))
     assert np.array_equal(f[0], f[1])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("q", [2, 3])
+def test_periods_with_four_wave_blocks(lib, q, precision):
+    """With stage variant 8 chosen the substep launches run four waves per
+    element block: forward and adjoint periods against the oracle."""
+    print(f"lts four waves q={q} prec={precision}", flush=True)
+    old = lib.cmcg_tune_get_stage(q, precision)
+    try:
+        lib.cmcg_tune_stage(q, precision, 8)
+        op, s, lp = lts_pair(lib, q, precision, tags="mixed", seed=90 + q)
+        o = lib.cmcg_options_default(lts_ratio=M_RATIO)
+        M, _ = lib.cmcg_problem_steps(lp, o)
+        _, fine = lts.lts_steps(op, M_RATIO)
+        U0 = np.random.default_rng(91).standard_normal((op.K, 6, op.Np))
+        UT = dev(np.zeros_like(U0))
+        lib.cmcg_debug_period(lp, dev(U0), UT, 1, True, opts=o)
+        assert rel_norm(op, host(UT), lts.forward(op, U0, M, M_RATIO, fine, 4, True)) < TOL[precision]
+        lib.cmcg_debug_period(lp, dev(U0), UT, -1, False, opts=o)
+        assert rel_norm(op, host(UT), lts.backward(op, U0, M, M_RATIO, fine, 4)) < TOL[precision]
+    finally:
+        lib.cmcg_tune_stage(q, precision, old)
