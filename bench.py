@@ -70,9 +70,12 @@ def parse():
     ap.add_argument("--serve-precision", choices=["fp32", "fp64"], default="fp32",
                     help="serving: field precision of the served solves (fp64: the plain form, for comparison)")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: engine memory budget")
-    ap.add_argument("--cobatch", type=int, default=1,
+    ap.add_argument("--cobatch", type=int, default=8,
                     help="serving: queued requests on one space (n, q) that may share a slot and run as one "
                          "batched solve (1: every request alone)")
+    ap.add_argument("--cobatch-max-k", type=int, default=3072,
+                    help="serving: co-batch only spaces of at most this many elements (0: any); the default "
+                         "takes the n = 8 meshes, whose single launches fill an eighth of the chip")
     ap.add_argument("--lts-n", type=int, default=20, help="lts: cells per axis")
     ap.add_argument("--lts-r", type=int, default=16, help="lts: the thin layers are 1/r of a cell wide")
     ap.add_argument("--lts-m", type=int, default=4, help="lts: fine substeps per coarse step")
@@ -885,7 +888,8 @@ def served(a):
     reqs = inputs.serving_stream(n_requests=2000, rate=a.rate)[: a.requests]
     fp64 = a.serve_precision == "fp64"
     out = serving.serve(reqs, budget_bytes=int(a.budget_gb * 2 ** 30), max_slots=a.slots, tol=a.tol,
-                        precision=cmcg.CMCG_FP64 if fp64 else cmcg.CMCG_FP32, log=log, cobatch=a.cobatch)
+                        precision=cmcg.CMCG_FP64 if fp64 else cmcg.CMCG_FP32, log=log, cobatch=a.cobatch,
+                        cobatch_max_elements=a.cobatch_max_k or None)
     svc = np.array([r["done"] - r["admitted"] for r in out["records"]])
     res = {"metric": "DG dof-updates/s; CMCG time-to-1e-6 residual vs FP64 plain; p50/p99 latency",
            "value": out["dof_updates_per_s"], "unit": "dof-updates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
@@ -894,7 +898,8 @@ def served(a):
            "config": {"workload": f"serving: first {a.requests} requests of the 2000-request Poisson stream at "
                                   f"{a.rate:g} req/s (n in 8,12,16,24; q in 1,2,3), {a.slots} slots, "
                                   f"{a.budget_gb:g} GB budget, CMCG to {a.tol:g}, "
-                                  f"{'plain FP64' if fp64 else 'FP32'} fields, co-batching up to {a.cobatch}"},
+                                  f"{'plain FP64' if fp64 else 'FP32'} fields, co-batching up to {a.cobatch}"
+                                  + (f" (spaces of at most {a.cobatch_max_k} elements)" if a.cobatch_max_k else "")},
            "serving": {**{k: out[k] for k in ("completed", "elapsed", "throughput", "p50", "p99", "offered_rate",
                                               "engine_steps")},
                        "co_batched_requests": sum(1 for r in out["records"] if r["members"] > 1),
@@ -1074,7 +1079,7 @@ def main():
         # batched launch with every member active, and a short served stream
         out["roofline_scatterer"] = scatterer_kernel(a)
         out["roofline_batched"] = batched_kernel(a)
-        out["serving"] = serving_short(a, a.cobatch)
+        out["serving"] = serving_short(a, 1)
     if not a.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)

@@ -34,6 +34,7 @@ struct Batch {
     std::unique_ptr<HostPinned> pin;
     hipStream_t cap = nullptr;
     std::map<int, hipGraphExec_t> graphs;
+    bool no_capture = false;  // periods without a captured graph run eagerly
     ~Batch() {
         for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
         if (cap) (void)hipStreamDestroy(cap);
@@ -220,14 +221,15 @@ void enqueue_batch_period(Batch& bt, bool src, bool filt, hipStream_t st) {
     }
 }
 
-void run_batch_period(Batch& bt, bool src, bool filt, bool use_graph, hipStream_t st) {
-    if (!use_graph) {
-        enqueue_batch_period(bt, src, filt, st);
-        return;
-    }
+int batch_graph_key(const Batch& bt, bool src, bool filt) {
     // keyed by the stage variant as well: it is read when the launches are enqueued
     const int variant = bt.sp->dim == 3 ? get_stage_variant(bt.sp->q, bt.sp->precision) : 0;
-    const int key = (variant << 4) | (src ? 2 : 0) | (filt ? 1 : 0);
+    return (variant << 4) | (src ? 2 : 0) | (filt ? 1 : 0);
+}
+
+// the captured period for (src, filt), captured now if missing
+hipGraphExec_t batch_graph(Batch& bt, bool src, bool filt) {
+    const int key = batch_graph_key(bt, src, filt);
     auto it = bt.graphs.find(key);
     if (it == bt.graphs.end()) {
         if (!bt.cap) CMCG_HIP(hipStreamCreateWithFlags(&bt.cap, hipStreamNonBlocking));
@@ -247,7 +249,15 @@ void run_batch_period(Batch& bt, bool src, bool filt, bool use_graph, hipStream_
         if (e != hipSuccess) fail(CMCG_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
         it = bt.graphs.emplace(key, ge).first;
     }
-    CMCG_HIP(hipGraphLaunch(it->second, st));
+    return it->second;
+}
+
+void run_batch_period(Batch& bt, bool src, bool filt, bool use_graph, hipStream_t st) {
+    if (!use_graph || (bt.no_capture && !bt.graphs.count(batch_graph_key(bt, src, filt)))) {
+        enqueue_batch_period(bt, src, filt, st);
+        return;
+    }
+    CMCG_HIP(hipGraphLaunch(batch_graph(bt, src, filt), st));
 }
 
 // Y_b = S^d P_b S^d X_b - sub_b for every member (X == nullptr: zero state)
@@ -437,10 +447,10 @@ int autotune_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hip
     return v;
 }
 
-void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipStream_t st, cmcg_result** out) {
-    if (!probs || B < 1 || !out) fail(CMCG_ERR_ARG, "solve_batch: NULL argument or empty batch");
-    Batch bt;
-    setup_batch(bt, probs, B, o, st);
+namespace {
+
+void solve_prepared(Batch& bt, const cmcg_options* o, hipStream_t st, cmcg_result** out) {
+    const int B = bt.B;
     const SpaceData& s = *bt.sp;
     const int64_t n = s.ndof, K = s.K;
     std::vector<int> act(B, 1);
@@ -618,5 +628,44 @@ void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipSt
     }
     CMCG_HIP(hipStreamSynchronize(st));
 }
+
+}  // namespace
+
+void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipStream_t st, cmcg_result** out) {
+    if (!probs || B < 1 || !out) fail(CMCG_ERR_ARG, "solve_batch: NULL argument or empty batch");
+    Batch bt;
+    setup_batch(bt, probs, B, o, st);
+    solve_prepared(bt, o, st, out);
+}
+
+struct BatchState {
+    Batch bt;
+};
+
+BatchState* batch_prepare(cmcg_problem* const* probs, int B, const cmcg_options* o, hipStream_t st) {
+    if (!probs || B < 1) fail(CMCG_ERR_ARG, "batch_prepare: NULL argument or empty batch");
+    std::unique_ptr<BatchState> bs(new BatchState());
+    setup_batch(bs->bt, probs, B, o, st);
+    if (o->use_graph) {
+        // every period the solve runs: with source (Algorithm 1, run-up), the
+        // homogeneous forward / backward periods, the filter period
+        batch_graph(bs->bt, true, false);
+        batch_graph(bs->bt, false, false);
+        batch_graph(bs->bt, true, true);
+    }
+    bs->bt.no_capture = true;
+    CMCG_HIP(hipStreamSynchronize(st));
+    return bs.release();
+}
+
+void batch_run(BatchState* bs, cmcg_problem* const* probs, int B, const cmcg_options* o, hipStream_t st,
+               cmcg_result** out) {
+    if (!bs || !probs || B != bs->bt.B || !out) fail(CMCG_ERR_ARG, "batch_run: arguments do not match the batch");
+    for (int b = 0; b < B; ++b)
+        if (probs[b] != bs->bt.P[b]) fail(CMCG_ERR_ARG, "batch_run: problems differ from the prepared batch");
+    solve_prepared(bs->bt, o, st, out);
+}
+
+void batch_free(BatchState* bs) { delete bs; }
 
 }  // namespace cmcg

@@ -21,10 +21,12 @@
 
 // A co-batched slot: requests on one space solved together by the batched
 // path (cmcg_solve_batch's launches, one per Runge-Kutta stage for every
-// member) on a worker thread that owns the slot's stream.
+// member) on a worker thread that owns the slot's stream.  The batch is set
+// up and its periods captured on the admitting thread; the worker replays.
 struct BatchJob {
     std::vector<cmcg_problem*> probs;
     cmcg_options o{};
+    cmcg::BatchState* bs = nullptr;
     std::vector<cmcg_result*> res;
     std::atomic<bool> done{false};
     int code = 0;
@@ -33,6 +35,7 @@ struct BatchJob {
     ~BatchJob() {
         if (th.joinable()) th.join();
         for (auto* r : res) delete r;
+        cmcg::batch_free(bs);
     }
 };
 
@@ -219,10 +222,10 @@ int cmcg_engine_admit_batch(cmcg_engine* e, cmcg_problem* const* problems, int n
     job->o = *o;
     job->o.autotune = 0;           // the stage variant is process-wide and slots run concurrently
     job->o.progress = nullptr;     // no host callbacks from the worker thread
-    // no graph capture on the worker thread: while a stream captures, the
-    // runtime refuses legacy-stream work (synchronous copies, a caller's
-    // default-stream kernels) from every other thread of the process
-    job->o.use_graph = 0;
+    // set up and capture here: while a stream captures, the runtime refuses
+    // legacy-stream work (synchronous copies, a caller's default-stream
+    // kernels) from every other thread, so the worker thread never captures
+    job->bs = batch_prepare(job->probs.data(), n, &job->o, s.st);
     job->res.assign(n, nullptr);
     BatchJob* jp = job.get();
     const int dev = e->device;
@@ -230,7 +233,7 @@ int cmcg_engine_admit_batch(cmcg_engine* e, cmcg_problem* const* problems, int n
     job->th = std::thread([jp, dev, st] {
         try {
             CMCG_HIP(hipSetDevice(dev));
-            solve_batch(jp->probs.data(), (int)jp->probs.size(), &jp->o, st, jp->res.data());
+            batch_run(jp->bs, jp->probs.data(), (int)jp->probs.size(), &jp->o, st, jp->res.data());
         } catch (const Error& err) {
             jp->code = err.code;
             jp->msg = err.msg;

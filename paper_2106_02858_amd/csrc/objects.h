@@ -209,6 +209,16 @@ void prepare(cmcg_problem* p, const StepCfg& c);
 cmcg_result* solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st);
 cmcg_result* fw_solve(cmcg_problem* p, const cmcg_options* o, const double* u0, hipStream_t st);
 void solve_batch(cmcg_problem* const* probs, int B, const cmcg_options* o, hipStream_t st, cmcg_result** out);
+// The same in two parts, for a solve run on another thread than the one that
+// prepares it: batch_prepare sets the batch up on st and, when o->use_graph,
+// captures the graphs of its periods (a capture refuses legacy-stream work on
+// every other thread, so it is done here, on the caller's thread); batch_run
+// then only replays graphs (a period without a captured graph runs eagerly).
+struct BatchState;
+BatchState* batch_prepare(cmcg_problem* const* probs, int B, const cmcg_options* o, hipStream_t st);
+void batch_run(BatchState* bs, cmcg_problem* const* probs, int B, const cmcg_options* o, hipStream_t st,
+               cmcg_result** out);
+void batch_free(BatchState* bs);
 // Batched stage autotuner: every variant on up to 8 homogeneous steps of the
 // batched launch with all members active; returns the fastest (kept as the
 // process-wide choice), us[v] = microseconds per launch.

@@ -47,12 +47,14 @@ def build_problem(cache: SpaceCache, req):
 
 def serve(requests, budget_bytes: int, max_slots: int, precision=cmcg.CMCG_FP32, tol: float = 1e-6,
           max_iter: int = 2000, time_scale: float = 1.0, log=None, keep_results: bool = False,
-          cobatch: int = 1):
+          cobatch: int = 1, cobatch_max_elements: int | None = None):
     """Serve `requests` (dicts with "arrival" and the recipe fields of
     inputs.serving_stream).  time_scale > 1 compresses the arrival clock.
     cobatch > 1: when the head of the queue has queued requests on the same
     space (n, q), up to `cobatch` of them share one slot and are solved
-    together by the batched launches (each result equals its solo solve).
+    together by the batched launches (each result equals its solo solve);
+    cobatch_max_elements limits that to spaces of at most that many elements
+    (small meshes, whose single launches leave most of the chip idle).
     Returns a dict with latencies, throughput and per-request records."""
     engine = cmcg.cmcg_engine_create(budget_bytes, max_slots)
     cache = SpaceCache(precision)
@@ -81,7 +83,9 @@ def serve(requests, budget_bytes: int, max_slots: int, precision=cmcg.CMCG_FP32,
             req = queue[0]
             prob = req.get("_problem") or build_problem(cache, req)
             req["_problem"] = prob
-            if cobatch > 1:
+            small = cobatch_max_elements is None or \
+                cmcg.cmcg_space_info(cache.get(req["n"], req["q"])[0])["K"] <= cobatch_max_elements
+            if cobatch > 1 and small:
                 group = [r for r in queue if (r["n"], r["q"]) == (req["n"], req["q"])][:cobatch]
                 if len(group) > 1:
                     for r in group:
