@@ -444,8 +444,11 @@ int cmcg_engine_info(const cmcg_engine* e, size_t* used, int* n_running, int* n_
  * path of cmcg_solve_batch (one launch per Runge-Kutta stage for every
  * member), so small requests fill the device together.  Each member's result
  * equals the one cmcg_solve returns for it alone.  The solve runs on a worker
- * thread that uses the slot's stream; cmcg_engine_step reports the slot
- * finished once it has ended.  Admission cost: the members' summed
+ * thread that uses the slot's stream; the batch is set up and its periods
+ * captured as graphs during this call, on the caller's thread (a capture
+ * would refuse the caller's legacy-stream work from any other thread), and
+ * the worker only replays them.  cmcg_engine_step reports the slot finished
+ * once the solve has ended.  Admission cost: the members' summed
  * footprints.  Errors as cmcg_engine_admit, and CMCG_ERR_ARG when the
  * problems do not share a space, repeat, or ask for local time stepping.
  * o->progress is not called and o->autotune is ignored.
@@ -454,8 +457,9 @@ int cmcg_engine_info(const cmcg_engine* e, size_t* used, int* n_running, int* n_
  *   co-batched slot (caller-owned) and frees the slot; returns
  *   CMCG_NOT_CONVERGED when a member stopped at max_iter, the batched solve's
  *   error code (no results) when it failed.  cmcg_engine_collect refuses a
- *   co-batched slot (CMCG_ERR_STATE); cmcg_engine_cancel waits for its solve
- *   to end. */
+ *   co-batched slot (CMCG_ERR_STATE); cmcg_engine_cancel stops its solve at
+ *   the next CG iteration (after that iteration's periods and one filter
+ *   period) and waits for the worker. */
 int cmcg_engine_admit_batch(cmcg_engine* e, cmcg_problem* const* problems, int n, const cmcg_options* o,
                             int* slot);
 int cmcg_engine_slot_members(const cmcg_engine* e, int slot, int* n);

@@ -29,10 +29,13 @@ struct BatchJob {
     cmcg::BatchState* bs = nullptr;
     std::vector<cmcg_result*> res;
     std::atomic<bool> done{false};
+    std::atomic<bool> stop{false};  // set by a cancel: the solve stops at its next CG iteration
     int code = 0;
     std::string msg;
     std::thread th;
+    static int progress(void* ctx, int, double) { return static_cast<BatchJob*>(ctx)->stop.load() ? 1 : 0; }
     ~BatchJob() {
+        stop.store(true);
         if (th.joinable()) th.join();
         for (auto* r : res) delete r;
         cmcg::batch_free(bs);
@@ -221,7 +224,10 @@ int cmcg_engine_admit_batch(cmcg_engine* e, cmcg_problem* const* problems, int n
     job->probs.assign(problems, problems + n);
     job->o = *o;
     job->o.autotune = 0;           // the stage variant is process-wide and slots run concurrently
-    job->o.progress = nullptr;     // no host callbacks from the worker thread
+    // no callbacks into the caller from the worker thread; the job's own one
+    // lets a cancel stop the solve at its next iteration
+    job->o.progress = &BatchJob::progress;
+    job->o.progress_ctx = job.get();
     // set up and capture here: while a stream captures, the runtime refuses
     // legacy-stream work (synchronous copies, a caller's default-stream
     // kernels) from every other thread, so the worker thread never captures
@@ -386,7 +392,7 @@ int cmcg_engine_cancel(cmcg_engine* e, int slot) {
     if (!e || slot < 0 || slot >= (int)e->slots.size()) fail(CMCG_ERR_ARG, "engine_cancel: bad argument");
     auto& s = e->slots[slot];
     if (s.state == 0) fail(CMCG_ERR_STATE, "engine_cancel: slot is free");
-    s.job.reset();  // a co-batched solve runs to its end first (joins its worker)
+    s.job.reset();  // a co-batched solve stops at its next iteration (joins its worker)
     CMCG_HIP(hipStreamSynchronize(s.st));
     e->used -= s.bytes;
     s.run.reset();

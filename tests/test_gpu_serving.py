@@ -151,3 +151,24 @@ def test_cobatched_slot_interface(lib):
     res = lib.cmcg_engine_collect_batch(e, slot, probs[:2])
     assert len(res) == 2 and all(lib.cmcg_result_stats(r)["iters"] > 0 for r in res)
     assert lib.cmcg_engine_poll(e, slot) == 0 and lib.cmcg_engine_info(e)["used"] == 0
+
+
+def test_cancel_stops_a_cobatched_slot(lib):
+    """A cancel stops a running co-batched solve at its next iteration and
+    frees the slot and its budget; the engine serves the next request."""
+    import time
+    from paper_2106_02858_amd import serving
+    reqs = inputs.serving_stream(n_requests=3, rate=10.0, seed=5, sizes=(2,), orders=(3,))
+    cache = serving.SpaceCache(1)
+    probs = [serving.build_problem(cache, r) for r in reqs]
+    e = lib.cmcg_engine_create(1 << 33, 2)
+    slot = lib.cmcg_engine_admit_batch(e, probs[:2], lib.cmcg_options_default(tol=1e-14, max_iter=20000))
+    assert lib.cmcg_engine_poll(e, slot) == 1
+    t0 = time.perf_counter()
+    lib.cmcg_engine_cancel(e, slot)
+    assert time.perf_counter() - t0 < 30.0
+    assert lib.cmcg_engine_poll(e, slot) == 0 and lib.cmcg_engine_info(e)["used"] == 0
+    s2 = lib.cmcg_engine_admit(e, probs[2])
+    while lib.cmcg_engine_poll(e, s2) == 1:
+        lib.cmcg_engine_step(e)
+    assert lib.cmcg_result_stats(lib.cmcg_engine_collect(e, s2, probs[2]))["iters"] > 0
