@@ -307,7 +307,8 @@ def batched(a):
            "config": {"workload": f"batched: {a.members} solves on the {info['K']}-tet P2 mesh, omega in [2pi,6pi], "
                                   f"FP32 fields, CMCG to {a.tol:g} + filter", "members": a.members, "K": info["K"],
                       "q": 2, "steps_per_period_min": min(Ms), "steps_per_period_max": max(Ms),
-                      "stage_variant": cmcg.cmcg_tune_get_stage(2, cmcg.CMCG_FP32), "autotuned": not a.no_autotune},
+                      "stage_variant": cmcg.cmcg_tune_resolve_stage(2, cmcg.CMCG_FP32, info["K"], len(probs)),
+                      "autotuned": not a.no_autotune},
            "cmcg": {"iters_min": min(st["iters"] for st in sts), "iters_max": max(st["iters"] for st in sts),
                     "time_to_1e-6_all_members_s": max(st["seconds_to_1e6"] for st in sts),
                     "seconds": sts[0]["seconds"]},
@@ -420,7 +421,7 @@ def scatterer(a):
     per_launch = ev0.elapsed_time(ev1) / 1e3 / (4 * M)
     bpl = method_bytes_per_launch(w.q, 4, K)
     achieved = bpl / per_launch / 1e9
-    kname = STAGE_KERNEL[cmcg.cmcg_tune_get_stage(w.q, cmcg.CMCG_FP32)].format(q=w.q)
+    kname = STAGE_KERNEL[cmcg.cmcg_tune_resolve_stage(w.q, cmcg.CMCG_FP32, K)].format(q=w.q)
     out = {"metric": "DG dof-updates/s; CMCG time-to-1e-6 residual vs FP64 plain; p50/p99 latency",
            "value": st["dof_updates"] / el, "unit": "dof-updates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
            "ms_per_step": el * 1e3, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
@@ -428,7 +429,7 @@ def scatterer(a):
            "config": {"workload": f"scatterer: 64^3x6 = {K} tets, P2, eps = 4 in the sphere |x - c| < 1/4 "
                                   f"(103392 tets), omega = 8 pi, source width 0.03 at (0.15,0.5,0.5); "
                                   f"CMCG {a.cg_iters} iterations + filter period", "K": K, "q": w.q,
-                      "steps_per_period": M, "stage_variant": cmcg.cmcg_tune_get_stage(w.q, cmcg.CMCG_FP32),
+                      "steps_per_period": M, "stage_variant": cmcg.cmcg_tune_resolve_stage(w.q, cmcg.CMCG_FP32, K),
                       "autotuned": not a.no_autotune},
            "cmcg": {"iters": st["iters"], "periods": st["periods"], "rel_res": st["rel_res"]},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -1004,7 +1005,7 @@ def main():
     torch.cuda.synchronize()
     per_launch_s = ev0.elapsed_time(ev1) / 1e3 / (a.kernel_periods * 4 * M)
     bpl = method_bytes_per_launch(w.q, 4, K)
-    kname = STAGE_KERNEL[cmcg.cmcg_tune_get_stage(w.q, cmcg.CMCG_FP32)].format(q=w.q)
+    kname = STAGE_KERNEL[cmcg.cmcg_tune_resolve_stage(w.q, cmcg.CMCG_FP32, K)].format(q=w.q)
     achieved = bpl / per_launch_s / 1e9
 
     out = {
@@ -1024,7 +1025,7 @@ def main():
                                f"mu=1, omega=4pi, impedance boundary, Gaussian e_z source width 0.05; "
                                f"CMCG to rel. residual {a.tol:g} + filter period",
                    "K": K, "q": w.q, "ndof": ndof, "steps_per_period": M, "fields": "fp32",
-                   "cg": "fp64", "stage_variant": cmcg.cmcg_tune_get_stage(w.q, cmcg.CMCG_FP32),
+                   "cg": "fp64", "stage_variant": cmcg.cmcg_tune_resolve_stage(w.q, cmcg.CMCG_FP32, K),
                    "autotuned": not a.no_autotune},
         "cmcg": {"iters": stats[-1]["iters"], "periods": stats[-1]["periods"],
                  "rel_res": stats[-1]["rel_res"], "seconds": stats[-1]["seconds"],
@@ -1064,7 +1065,7 @@ def main():
         torch.cuda.synchronize()
         pl64 = ev0.elapsed_time(ev1) / 1e3 / (a.kernel_periods * 4 * M)
         bpl64 = method_bytes_per_launch(w.q, 8, K)
-        v64 = cmcg.cmcg_tune_get_stage(w.q, cmcg.CMCG_FP64)
+        v64 = cmcg.cmcg_tune_resolve_stage(w.q, cmcg.CMCG_FP64, K)
         out["roofline_fp64"] = {"workload": f"the same {K}-tet P{w.q} problem with FP64 fields",
                                 "bound": "hbm", "achieved": bpl64 / pl64 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                 "frac": bpl64 / pl64 / 1e9 / HBM_PEAK_GBS,
@@ -1135,7 +1136,7 @@ def scatterer_kernel(a) -> dict:
     per_launch = ev0.elapsed_time(ev1) / 1e3 / (4 * M)
     bpl = method_bytes_per_launch(w.q, 4, K)
     achieved = bpl / per_launch / 1e9
-    kname = STAGE_KERNEL[cmcg.cmcg_tune_get_stage(w.q, cmcg.CMCG_FP32)].format(q=w.q)
+    kname = STAGE_KERNEL[cmcg.cmcg_tune_resolve_stage(w.q, cmcg.CMCG_FP32, K)].format(q=w.q)
     log(f"scatterer stage launch {per_launch * 1e6:.1f} us = {achieved:.0f} GB/s ({kname})")
     del p, s, mesh, U0, UT
     _free_device()

@@ -479,13 +479,18 @@ int cmcg_engine_collect_batch(cmcg_engine* e, int slot, cmcg_result** results, i
  * tiles (q = 3), 7 combines 5 and 6 (q = 3), 8 is 3 with four waves per
  * block, each computing one row tile and half of the column tiles (q = 3)
  * or a quarter of them (q = 2); variants that do not exist for
- * (q, precision) fall back to 0.  All compute the same Phi(t, Y) and stage update.  Defaults: 4
- * for q = 2, 3 (both precisions), 0 for q = 1.  Process-wide;
+ * (q, precision) fall back to 0; -1 chooses per launch from its size
+ * (workgroups of 10 elements over all members), the form the autotuner's
+ * timings favour there.  All compute the same Phi(t, Y) and stage update.
+ * Defaults: -1 for q = 2, 3, 0 for q = 1.  Process-wide;
  * not thread-safe against concurrent solves.  Returns CMCG_ERR_ARG for an unknown q / precision /
- * variant.  cmcg_tune_get_stage reports the current choice. */
+ * variant.  cmcg_tune_get_stage reports the current choice (possibly -1);
+ * cmcg_tune_resolve_stage the variant a launch over K elements and
+ * `members` members would run under it. */
 #define CMCG_STAGE_VARIANTS 9
 int cmcg_tune_stage(int q, int precision, int variant);
 int cmcg_tune_get_stage(int q, int precision, int* variant);
+int cmcg_tune_resolve_stage(int q, int precision, int64_t K, int members, int* variant);
 
 /* Autotuner: times every stage-kernel variant that applies to p's (q,
  * precision) on p's own launch shape -- up to 8 homogeneous time steps on

@@ -52,7 +52,7 @@ EXPORTED = [
     "cmcg_problem_create_harmonics", "cmcg_result_harmonics", "cmcg_result_filtered_harmonic_device",
     "cmcg_solve", "cmcg_fw_solve", "cmcg_solve_batch", "cmcg_result_fields", "cmcg_result_filtered_device", "cmcg_result_initial_device",
     "cmcg_result_stats", "cmcg_result_history", "cmcg_result_destroy",
-    "cmcg_debug_rhs", "cmcg_debug_period", "cmcg_debug_step", "cmcg_debug_dot", "cmcg_debug_dot_noalloc", "cmcg_debug_mfma", "cmcg_tune_stage", "cmcg_tune_get_stage",
+    "cmcg_debug_rhs", "cmcg_debug_period", "cmcg_debug_step", "cmcg_debug_dot", "cmcg_debug_dot_noalloc", "cmcg_debug_mfma", "cmcg_tune_stage", "cmcg_tune_get_stage", "cmcg_tune_resolve_stage",
     "cmcg_autotune_stage", "cmcg_autotune_batch", "cmcg_mesh_locality_order",
     "cmcg_problem_footprint", "cmcg_engine_create", "cmcg_engine_destroy", "cmcg_engine_admit",
     "cmcg_engine_step", "cmcg_engine_poll", "cmcg_engine_collect", "cmcg_engine_cancel", "cmcg_engine_info",
@@ -138,6 +138,7 @@ _sig = {
     "cmcg_engine_collect_batch": (C.c_int, [P, C.c_int, P, C.c_int]),
     "cmcg_mesh_locality_order": (C.c_int, [C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "cmcg_tune_get_stage": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
+    "cmcg_tune_resolve_stage": (C.c_int, [C.c_int, C.c_int, C.c_int64, C.c_int, C.POINTER(C.c_int)]),
     "cmcg_autotune_stage": (C.c_int, [P, C.POINTER(cmcg_options), C.c_void_p, C.POINTER(C.c_int),
                                       C.POINTER(C.c_double)]),
     "cmcg_autotune_batch": (C.c_int, [P, C.c_int, C.POINTER(cmcg_options), C.c_void_p, C.POINTER(C.c_int),
@@ -466,8 +467,16 @@ def cmcg_tune_stage(q: int, precision: int, variant: int):
 
 
 def cmcg_tune_get_stage(q: int, precision: int) -> int:
+    """The current choice for (q, precision); -1 = chosen per launch from its size."""
     v = C.c_int()
     _check(_lib.cmcg_tune_get_stage(q, precision, C.byref(v)))
+    return v.value
+
+
+def cmcg_tune_resolve_stage(q: int, precision: int, K: int, members: int = 1) -> int:
+    """The variant a launch over K elements and `members` members runs now."""
+    v = C.c_int()
+    _check(_lib.cmcg_tune_resolve_stage(q, precision, int(K), int(members), C.byref(v)))
     return v.value
 
 

@@ -1577,16 +1577,29 @@ __global__ void k_nonfinite(const double* X, int64_t n, int* flag) {
 // Stage-kernel variant per (q, precision): 0 = gather per face, 1 = gathers
 // pipelined one face ahead, 2 / 3 = matrix cores (q >= 2) without /
 // with the one-face-ahead gathers, 4 = 3 with two waves per block, 5-7 the
-// eager-gather and column-split forms of 4.  Chosen from measurements;
-// overridable through cmcg_tune_stage() and the autotuner.  Defaults: P2 and
-// P3 on the matrix cores with two waves per block, both precisions (FP32 P3:
-// 38.2 us vs 41.5 us at 48000 tets, 256 vs 260 us at 384000; FP32 P2: 8.6 vs
-// 10.4 us at 10368 tets, 28.8 vs 31.0 us at 82944, but 126 vs 123 us at
-// 384000, where the autotuner keeps one wave; FP64 P3: 71.0 us against 112.7
-// us for the VALU form at 48000 tets, FP64 P2: 37.9 against 43.2 us at
-// 55200), per-face gathers for P1.
-int g_variant[kMaxQ + 1][2] = {{0, 0}, {0, 0}, {4, 4}, {4, 4}};
-inline int stage_variant(int q, int precision) { return g_variant[q][precision]; }
+// eager-gather and column-split forms of 4, 8 = four waves per block; -1 =
+// chosen per launch from its size.  Overridable through cmcg_tune_stage() and
+// the autotuner.  Defaults: per-face gathers for P1; for P2 and P3 the form
+// the autotuner's timings favour at the launch's size (workgroups over all
+// members).  FP32 P3 (us per launch, forms 4 / 6 / 8): 3072 tets 12.1 / 10.9
+// / 9.0, 10368 tets 15.5 / 14.4 / 13.7, 24576 tets 25.2 / 21.8 / 22.6, 82944
+// tets 57.6 / 56.9 / 57.9, 196608 tets 131.0 / 137.4 / 139.1.  FP32 P2 (forms
+// 3 / 4 / 5 / 8): 3072 tets 8.9 / 7.6 / 7.3 / 6.5, 24576 tets 13.9 / 12.7 /
+// 11.8 / 13.4, 82944 tets 30.3 / 28.3 / 30.4 / 31.2, the 1,572,864-tet mesh
+// 473 / 487 / 525 / -, 64 members of 10368 tets 188 / 199 / 222 / -.  FP64:
+// form 4 (P3 at 48000 tets 69.8 us, against 112.7 us for the VALU form; P2 at
+// 48000 tets 33.3 us against 40.5).
+int g_variant[kMaxQ + 1][2] = {{0, 0}, {0, 0}, {-1, -1}, {-1, -1}};
+inline int variant_by_size(int q, int precision, int64_t blocks) {
+    if (precision == CMCG_FP64) return 4;
+    if (q == 3) return blocks <= 1100 ? 8 : blocks <= 9000 ? 6 : 4;
+    if (q == 2) return blocks <= 1100 ? 8 : blocks <= 3000 ? 5 : blocks <= 12000 ? 4 : 3;
+    return 0;
+}
+inline int stage_variant(int q, int precision, int64_t blocks) {
+    const int v = g_variant[q][precision];
+    return v >= 0 ? v : variant_by_size(q, precision, blocks);
+}
 
 inline int grid_for(int64_t n, int threads = 256) {
     int64_t g = (n + threads - 1) / threads;
@@ -1599,7 +1612,7 @@ template <typename T, int Q, bool MH>
 void stage_launch_mh(const StageArgs& a, hipStream_t s) {
     const int64_t blocks = a.blist ? a.nblist : (a.K + EPW - 1) / EPW;
     const int64_t per = (blocks + 7) / 8;
-    const int v = stage_variant(Q, sizeof(T) == 8 ? CMCG_FP64 : CMCG_FP32);
+    const int v = stage_variant(Q, sizeof(T) == 8 ? CMCG_FP64 : CMCG_FP32, blocks * (a.nmembers > 1 ? a.nmembers : 1));
     const dim3 grid((unsigned)(8 * per), (unsigned)(a.nmembers > 1 ? a.nmembers : 1));
     if constexpr (Q >= 2) {
         if (v == 2) {
@@ -1648,7 +1661,7 @@ void stage_launch(const StageArgs& a, hipStream_t s) {
         // four waves per block where the autotuner chose them for this order
         // and precision, two otherwise
         if constexpr (Q >= 2) {
-            if (stage_variant(Q, sizeof(T) == 8 ? CMCG_FP64 : CMCG_FP32) == 8)
+            if (stage_variant(Q, sizeof(T) == 8 ? CMCG_FP64 : CMCG_FP32, blocks) == 8)
                 hipLaunchKernelGGL((k_stage_mfma<T, Q, true, false, 4, false, false, true>), grid, dim3(256), 0, s,
                                    a, per);
             else
@@ -1941,6 +1954,10 @@ void launch_mfma_probe(int precision, const double* A, const double* B, double* 
 
 void set_stage_variant(int q, int precision, int variant) { g_variant[q][precision] = variant; }
 int get_stage_variant(int q, int precision) { return g_variant[q][precision]; }
+int resolve_stage_variant(int q, int precision, int64_t K, int members) {
+    if (q < 1 || q > kMaxQ) return 0;
+    return stage_variant(q, precision, (K + EPW - 1) / EPW * (members > 1 ? members : 1));
+}
 
 void launch_dot(int q, const double* U, const double* V, const double* wE, const double* wH, int64_t K,
                 double* partial, double* out_dev, hipStream_t s) {

@@ -124,6 +124,8 @@ void launch_lts_wbar_close(int precision, int64_t n, int np6, const uint32_t* ma
 void launch_mfma_probe(int precision, const double* A, const double* B, double* D, hipStream_t s);
 void set_stage_variant(int q, int precision, int variant);
 int get_stage_variant(int q, int precision);
+// the variant a launch over K elements and `members` members runs
+int resolve_stage_variant(int q, int precision, int64_t K, int members);
 constexpr int kStageVariants = CMCG_STAGE_VARIANTS;  // 2, 3: matrix cores (q >= 2; 3 gathers one face
                                                      // ahead); 4: as 3 with two waves per block (q >= 2)
 

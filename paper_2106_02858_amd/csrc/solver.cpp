@@ -1559,7 +1559,7 @@ int cmcg_debug_mfma(int precision, const double* a, const double* b, double* d, 
 
 int cmcg_tune_stage(int q, int precision, int variant) {
     CMCG_GUARD_BEGIN
-    if (q < 1 || q > kMaxQ || (precision != CMCG_FP64 && precision != CMCG_FP32) || variant < 0 ||
+    if (q < 1 || q > kMaxQ || (precision != CMCG_FP64 && precision != CMCG_FP32) || variant < -1 ||
         variant >= kStageVariants)
         fail(CMCG_ERR_ARG, "tune_stage: bad q, precision or variant");
     set_stage_variant(q, precision, variant);
@@ -1606,6 +1606,16 @@ int cmcg_tune_get_stage(int q, int precision, int* variant) {
     if (q < 1 || q > kMaxQ || (precision != CMCG_FP64 && precision != CMCG_FP32) || !variant)
         fail(CMCG_ERR_ARG, "tune_get_stage: bad argument");
     *variant = get_stage_variant(q, precision);
+    return CMCG_OK;
+    CMCG_GUARD_END
+}
+
+int cmcg_tune_resolve_stage(int q, int precision, int64_t K, int members, int* variant) {
+    CMCG_GUARD_BEGIN
+    if (q < 1 || q > kMaxQ || (precision != CMCG_FP64 && precision != CMCG_FP32) || K < 1 || members < 1 ||
+        !variant)
+        fail(CMCG_ERR_ARG, "tune_resolve_stage: bad argument");
+    *variant = resolve_stage_variant(q, precision, K, members);
     return CMCG_OK;
     CMCG_GUARD_END
 }
