@@ -63,10 +63,10 @@ def test_profile_commands_run_committed_files(name):
             assert len(sq) <= 8 and len(tcc) <= 2, argv
 
 
-def _traffic_table(text: str):
+def _traffic_rows(text: str):
     sha = re.search(r"\b([0-9a-f]{64})\b", text).group(1)
-    row = re.search(r"^\| `(k_stage[^`]*)` \| (\d+) \| ([\d.]+) \| ([\d.]+) \|", text, re.M)
-    return sha, row.group(1), float(row.group(3)), float(row.group(4))
+    rows = re.findall(r"^\| `(k_stage[^`]*)` \| (\d+) \| ([\d.]+) \| ([\d.]+) \|", text, re.M)
+    return sha, {k: (float(fe), float(wr)) for k, _, fe, wr in rows}
 
 
 @pytest.mark.parametrize("name,table", [
@@ -75,7 +75,9 @@ def _traffic_table(text: str):
     ("k_stage2d_p3_trap_disk_traffic.md", bench.MEASURED_TRAFFIC_2D),
 ])
 def test_traffic_summary_matches_bench_table(name, table):
-    sha, kernel, fetch, write = _traffic_table(open(os.path.join(PROFILES, name)).read())
-    assert sha == table["kernels_sha256"]
-    assert kernel == table["kernel"]
-    assert fetch == table["fetch_kib"] and write == table["write_kib"]
+    sha, rows = _traffic_rows(open(os.path.join(PROFILES, name)).read())
+    tables = table if isinstance(table, list) else [table]
+    assert len(rows) == len(tables)
+    for t in tables:
+        assert sha == t["kernels_sha256"]
+        assert rows[t["kernel"]] == (t["fetch_kib"], t["write_kib"])
