@@ -77,8 +77,8 @@ def parse():
                     help="serving: co-batch only spaces of at most this many elements (0: any); the default "
                          "takes the n = 8 meshes, whose single launches fill an eighth of the chip")
     ap.add_argument("--lts-n", type=int, default=20, help="lts: cells per axis")
-    ap.add_argument("--lts-r", type=int, default=16, help="lts: the thin layers are 1/r of a cell wide")
-    ap.add_argument("--lts-m", type=int, default=4, help="lts: fine substeps per coarse step")
+    ap.add_argument("--lts-r", type=int, default=32, help="lts: the thin layers are 1/r of a cell wide")
+    ap.add_argument("--lts-m", type=int, default=8, help="lts: fine substeps per coarse step")
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="default line: requests of the short served stream")
     ap.add_argument("--no-extra", action="store_true",
