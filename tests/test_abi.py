@@ -173,3 +173,26 @@ def test_default_stream_does_not_start_torch():
     root = __import__("os").path.dirname(__import__("os").path.dirname(__import__("os").path.abspath(__file__)))
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root, timeout=120)
     assert r.returncode == 0 and r.stdout.strip() == "ok", r.stderr
+
+
+def test_stage_variant_by_launch_size_host_only():
+    """The default stage variant of P2/P3 (-1) resolves by the launch's size
+    (workgroups of 10 elements over all members); an explicit choice wins."""
+    from paper_2106_02858_amd import cmcg
+    FP64, FP32 = cmcg.CMCG_FP64, cmcg.CMCG_FP32
+    assert cmcg.cmcg_tune_get_stage(3, FP32) == -1 and cmcg.cmcg_tune_get_stage(1, FP32) == 0
+    r = cmcg.cmcg_tune_resolve_stage
+    assert r(3, FP32, 3072) == 8 and r(3, FP32, 48000) == 6 and r(3, FP32, 384000) == 4
+    assert r(3, FP32, 3072, 64) == 4                  # 64 members: a large launch
+    assert r(2, FP32, 3072) == 8 and r(2, FP32, 24576) == 5 and r(2, FP32, 82944) == 4
+    assert r(2, FP32, 1572864) == 3 and r(2, FP32, 10368, 64) == 3
+    assert r(3, FP64, 48000) == 4 and r(2, FP64, 3072) == 4 and r(1, FP32, 48000) == 0
+    cmcg.cmcg_tune_stage(3, FP32, 5)
+    try:
+        assert r(3, FP32, 3072) == 5 and r(3, FP32, 384000) == 5
+    finally:
+        cmcg.cmcg_tune_stage(3, FP32, -1)
+    with pytest.raises(cmcg.CmcgError):
+        cmcg.cmcg_tune_stage(3, FP32, -2)
+    with pytest.raises(cmcg.CmcgError):
+        r(3, FP32, 0)
