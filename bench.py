@@ -144,7 +144,7 @@ STAGE_KERNEL = {0: "k_stage<float,{q},false,false>", 1: "k_stage<float,{q},true,
                 4: "k_stage_mfma<float,{q},true,false,2>", 5: "k_stage_mfma<float,{q},true,false,2,true>",
                 6: "k_stage_mfma<float,{q},true,false,2,false,true>",
                 7: "k_stage_mfma<float,{q},true,false,2,true,true>",
-                8: "k_stage_mfma<float,{q},true,false,4>"}
+                8: "k_stage_mfma<float,{q},true,false,4>", 9: "k_stage_mfma<float,{q},true,false,4,true>"}
 STAGE_KERNEL64 = {v: k.replace("float", "double") for v, k in STAGE_KERNEL.items()}
 
 

@@ -478,7 +478,9 @@ int cmcg_engine_collect_batch(cmcg_engine* e, int slot, cmcg_result** results, i
  * with the two waves splitting the output by column tiles instead of row
  * tiles (q = 3), 7 combines 5 and 6 (q = 3), 8 is 3 with four waves per
  * block, each computing one row tile and half of the column tiles (q = 3)
- * or a quarter of them (q = 2); variants that do not exist for
+ * or a quarter of them (q = 2), 9 is 8 with the neighbour traces of all four
+ * faces requested at once (q = 2, 3; more registers per wave: for launches
+ * of a round of workgroups or less); variants that do not exist for
  * (q, precision) fall back to 0; -1 chooses per launch from its size
  * (workgroups of 10 elements over all members), the form the autotuner's
  * timings favour there.  All compute the same Phi(t, Y) and stage update.
@@ -487,7 +489,7 @@ int cmcg_engine_collect_batch(cmcg_engine* e, int slot, cmcg_result** results, i
  * variant.  cmcg_tune_get_stage reports the current choice (possibly -1);
  * cmcg_tune_resolve_stage the variant a launch over K elements and
  * `members` members would run under it. */
-#define CMCG_STAGE_VARIANTS 9
+#define CMCG_STAGE_VARIANTS 10
 int cmcg_tune_stage(int q, int precision, int variant);
 int cmcg_tune_get_stage(int q, int precision, int* variant);
 int cmcg_tune_resolve_stage(int q, int precision, int64_t K, int members, int* variant);

@@ -29,7 +29,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 CMCG_OK = 0
-CMCG_STAGE_VARIANTS = 9  # include/cmcg.h
+CMCG_STAGE_VARIANTS = 10  # include/cmcg.h
 CMCG_NOT_CONVERGED = 1
 CMCG_ERR_ARG = -1
 CMCG_ERR_MESH = -2

@@ -811,8 +811,8 @@ template <typename T, int Q, int NTH = 64, bool LTSM = false> struct MfmaUpdateI
 // column tile (P2), a quarter of the MFMAs and fewer registers per wave.
 template <typename T, int Q, bool PIPE, bool MH, int W, bool EAGER = false, bool CSPLIT = false, bool LTSM = false>
 __global__ __launch_bounds__(64 * W)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (W == 4 ? (Q == 3 ? 7 : 8) : W == 1 || (EAGER && Q == 3) ? 4 : (EAGER || CSPLIT ? 5 : 6))
-                                                   : (W == 4 ? 4 : W == 1 || EAGER || CSPLIT ? 2 : 3), 8)))
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (W == 4 ? (EAGER ? 4 : Q == 3 ? 7 : 8) : W == 1 || (EAGER && Q == 3) ? 4 : (EAGER || CSPLIT ? 5 : 6))
+                                                   : (W == 4 ? (EAGER ? 2 : 4) : W == 1 || EAGER || CSPLIT ? 2 : 3), 8)))
 void k_stage_mfma(StageArgs args, int64_t per) {
     using MD = MfmaDim<Q>;
     using acc_t = typename Mfma<T>::acc_t;
@@ -1577,23 +1577,30 @@ __global__ void k_nonfinite(const double* X, int64_t n, int* flag) {
 // Stage-kernel variant per (q, precision): 0 = gather per face, 1 = gathers
 // pipelined one face ahead, 2 / 3 = matrix cores (q >= 2) without /
 // with the one-face-ahead gathers, 4 = 3 with two waves per block, 5-7 the
-// eager-gather and column-split forms of 4, 8 = four waves per block; -1 =
-// chosen per launch from its size.  Overridable through cmcg_tune_stage() and
-// the autotuner.  Defaults: per-face gathers for P1; for P2 and P3 the form
-// the autotuner's timings favour at the launch's size (workgroups over all
-// members).  FP32 P3 (us per launch, forms 4 / 6 / 8): 3072 tets 12.1 / 10.9
-// / 9.0, 10368 tets 15.5 / 14.4 / 13.7, 24576 tets 25.2 / 21.8 / 22.6, 82944
-// tets 57.6 / 56.9 / 57.9, 196608 tets 131.0 / 137.4 / 139.1.  FP32 P2 (forms
-// 3 / 4 / 5 / 8): 3072 tets 8.9 / 7.6 / 7.3 / 6.5, 24576 tets 13.9 / 12.7 /
-// 11.8 / 13.4, 82944 tets 30.3 / 28.3 / 30.4 / 31.2, the 1,572,864-tet mesh
-// 473 / 487 / 525 / -, 64 members of 10368 tets 188 / 199 / 222 / -.  FP64:
-// form 4 (P3 at 48000 tets 69.8 us, against 112.7 us for the VALU form; P2 at
-// 48000 tets 33.3 us against 40.5).
+// eager-gather and column-split forms of 4, 8 = four waves per block, 9 = 8
+// with every face's gathers at once; -1 = chosen per launch from its size.
+// Overridable through cmcg_tune_stage() and the autotuner.  Defaults:
+// per-face gathers for P1; for P2 and P3 the form the autotuner's timings
+// favour at the launch's size (workgroups over all members).  FP32 P3 (us per
+// launch, forms 4 / 6 / 8 / 9): 3072 tets 12.2 / 10.9 / 8.9 / 8.8, 10368 tets
+// 15.6 / 14.3 / 13.8 / 13.5, 24576 tets 25.2 / 21.8 / 22.7 / 23.6, 48000 tets
+// 38.7 / 37.1 / 36.8 / 39.6, 82944 tets 57.6 / 56.9 / 57.9 / -, 196608 tets
+// 131.0 / 137.4 / 139.1 / -.  FP32 P2 (forms 3 / 4 / 5 / 8 / 9): 3072 tets
+// 9.0 / 7.6 / 7.3 / 6.5 / 6.1, 10368 tets 10.7 / 8.9 / 8.7 / 8.4 / 8.0, 24576
+// tets 14.2 / 13.1 / 12.2 / 13.8 / 13.6, 82944 tets 30.3 / 28.3 / 30.4 / 31.2
+// / -, the 1,572,864-tet mesh 473 / 487 / 525 / - / -, 64 members of 10368
+// tets 188 / 199 / 222 / - / -.  FP64 (forms 4 / 8 / 9): P2 3072 tets 9.4 /
+// 8.1 / 7.8, 10368 tets 12.3 / 11.7 / 13.6, 48000 tets 33.3 / 35.6 / 37.2;
+// P3 3072 tets 17.5 / 12.9 / 12.5, 48000 tets 69.6 / 68.9 / 75.3 (the VALU
+// form: 112.7).
 int g_variant[kMaxQ + 1][2] = {{0, 0}, {0, 0}, {-1, -1}, {-1, -1}};
 inline int variant_by_size(int q, int precision, int64_t blocks) {
-    if (precision == CMCG_FP64) return 4;
-    if (q == 3) return blocks <= 1100 ? 8 : blocks <= 9000 ? 6 : 4;
-    if (q == 2) return blocks <= 1100 ? 8 : blocks <= 3000 ? 5 : blocks <= 12000 ? 4 : 3;
+    if (precision == CMCG_FP64) {
+        if (blocks <= 400) return 9;
+        return blocks <= 1100 || (q == 3 && blocks <= 9000) ? 8 : 4;
+    }
+    if (q == 3) return blocks <= 1100 ? 9 : blocks <= 9000 ? 6 : 4;
+    if (q == 2) return blocks <= 1100 ? 9 : blocks <= 3000 ? 5 : blocks <= 12000 ? 4 : 3;
     return 0;
 }
 inline int stage_variant(int q, int precision, int64_t blocks) {
@@ -1635,6 +1642,10 @@ void stage_launch_mh(const StageArgs& a, hipStream_t s) {
             hipLaunchKernelGGL((k_stage_mfma<T, Q, true, MH, 4>), grid, dim3(256), 0, s, a, per);
             return;
         }
+        if (v == 9) {
+            hipLaunchKernelGGL((k_stage_mfma<T, Q, true, MH, 4, true>), grid, dim3(256), 0, s, a, per);
+            return;
+        }
         if constexpr (Q == 3) {
             if (v == 6) {
                 hipLaunchKernelGGL((k_stage_mfma<T, Q, true, MH, 2, false, true>), grid, dim3(128), 0, s, a, per);
@@ -1658,10 +1669,10 @@ void stage_launch(const StageArgs& a, hipStream_t s) {
         const int64_t blocks = a.blist ? a.nblist : (a.K + EPW - 1) / EPW;
         const int64_t per = (blocks + 7) / 8;
         const dim3 grid((unsigned)(8 * per));
-        // four waves per block where the autotuner chose them for this order
-        // and precision, two otherwise
+        // four waves per block where the chosen form has four (8, 9), two
+        // otherwise
         if constexpr (Q >= 2) {
-            if (stage_variant(Q, sizeof(T) == 8 ? CMCG_FP64 : CMCG_FP32, blocks) == 8)
+            if (stage_variant(Q, sizeof(T) == 8 ? CMCG_FP64 : CMCG_FP32, blocks) >= 8)
                 hipLaunchKernelGGL((k_stage_mfma<T, Q, true, false, 4, false, false, true>), grid, dim3(256), 0, s,
                                    a, per);
             else

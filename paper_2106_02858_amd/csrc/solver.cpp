@@ -697,7 +697,7 @@ std::map<std::tuple<int, int, int, int64_t, int>, int> g_tuned;
 
 bool variant_applies(int q, int precision, int v) {
     (void)precision;  // the matrix-core variants exist in both field precisions
-    return v <= 1 || (v <= 5 && q >= 2) || (v == 8 && q >= 2) || q == 3;
+    return v <= 1 || (v <= 5 && q >= 2) || (v >= 8 && q >= 2) || q == 3;
 }
 
 struct EventPair {

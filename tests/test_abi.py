@@ -182,11 +182,12 @@ def test_stage_variant_by_launch_size_host_only():
     FP64, FP32 = cmcg.CMCG_FP64, cmcg.CMCG_FP32
     assert cmcg.cmcg_tune_get_stage(3, FP32) == -1 and cmcg.cmcg_tune_get_stage(1, FP32) == 0
     r = cmcg.cmcg_tune_resolve_stage
-    assert r(3, FP32, 3072) == 8 and r(3, FP32, 48000) == 6 and r(3, FP32, 384000) == 4
+    assert r(3, FP32, 3072) == 9 and r(3, FP32, 48000) == 6 and r(3, FP32, 384000) == 4
     assert r(3, FP32, 3072, 64) == 4                  # 64 members: a large launch
-    assert r(2, FP32, 3072) == 8 and r(2, FP32, 24576) == 5 and r(2, FP32, 82944) == 4
+    assert r(2, FP32, 3072) == 9 and r(2, FP32, 24576) == 5 and r(2, FP32, 82944) == 4
     assert r(2, FP32, 1572864) == 3 and r(2, FP32, 10368, 64) == 3
-    assert r(3, FP64, 48000) == 4 and r(2, FP64, 3072) == 4 and r(1, FP32, 48000) == 0
+    assert r(3, FP64, 48000) == 8 and r(3, FP64, 384000) == 4 and r(2, FP64, 3072) == 9
+    assert r(2, FP64, 10368) == 8 and r(2, FP64, 48000) == 4 and r(1, FP32, 48000) == 0
     cmcg.cmcg_tune_stage(3, FP32, 5)
     try:
         assert r(3, FP32, 3072) == 5 and r(3, FP32, 384000) == 5

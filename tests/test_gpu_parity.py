@@ -44,11 +44,11 @@ def variant(lib, request):
     lib.cmcg_tune_stage(q, prec, old)
 
 
-# 0, 1 run everywhere; the matrix-core variants 2-5 and 8 (4, 5: two waves per block;
-# 5: all faces' gathers at once; 8: four waves per block) exist at q >= 2 in both field
+# 0, 1 run everywhere; the matrix-core variants 2-5, 8 and 9 (4, 5: two waves per block;
+# 5, 9: all faces' gathers at once; 8, 9: four waves per block) exist at q >= 2 in both field
 # precisions (FP64 on v_mfma_f64_16x16x4f64), 6 and 7 (column split) at q = 3
 VARIANTS = [(q, p, v) for q in (1, 2, 3) for p in (0, 1) for v in (0, 1)] + \
-    [(q, p, v) for q in (2, 3) for p in (0, 1) for v in (2, 3, 4, 5, 8)] + \
+    [(q, p, v) for q in (2, 3) for p in (0, 1) for v in (2, 3, 4, 5, 8, 9)] + \
     [(3, p, v) for p in (0, 1) for v in (6, 7)]
 
 
