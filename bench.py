@@ -90,24 +90,24 @@ def parse():
 # 48000-tet P3 FP32 problem, with the scales a 1 GiB copy gives each counter;
 # valid only for the kernel source they were taken on (SHA-256 below).
 MEASURED_TRAFFIC = [
-    {"kernels_sha256": "de2e0796e302e041dc620da108faa055a8efc936025a3a28c0607e4957ad7159",
+    {"kernels_sha256": "f978b259dffefc31afc3193fcbfae637424e0882aa7580e5489d61a677a0445c",
      "kernel": "k_stage_mfma<float,3,true,false,2,false,true>", "K": 48000,
-     "fetch_kib": 41471.41, "fetch_scale": 2.0000, "write_kib": 42200.79, "write_scale": 1.0000},
-    {"kernels_sha256": "de2e0796e302e041dc620da108faa055a8efc936025a3a28c0607e4957ad7159",
+     "fetch_kib": 41485.02, "fetch_scale": 2.0000, "write_kib": 42200.84, "write_scale": 1.0000},
+    {"kernels_sha256": "f978b259dffefc31afc3193fcbfae637424e0882aa7580e5489d61a677a0445c",
      "kernel": "k_stage_mfma<float,3,true,false,4>", "K": 48000,
-     "fetch_kib": 40943.94, "fetch_scale": 2.0000, "write_kib": 42187.65, "write_scale": 1.0000},
+     "fetch_kib": 40910.61, "fetch_scale": 2.0000, "write_kib": 42187.67, "write_scale": 1.0000},
 ]
 
 
 # The same for the FP64 stage kernel of the plain FP64 solve (48000 tets, P3):
 # the two forms its autotuner keeps (two and four waves per block).
 MEASURED_TRAFFIC_FP64 = [
-    {"kernels_sha256": "de2e0796e302e041dc620da108faa055a8efc936025a3a28c0607e4957ad7159",
+    {"kernels_sha256": "f978b259dffefc31afc3193fcbfae637424e0882aa7580e5489d61a677a0445c",
      "kernel": "k_stage_mfma<double,3,true,false,2>", "K": 48000,
-     "fetch_kib": 80993.40, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000},
-    {"kernels_sha256": "de2e0796e302e041dc620da108faa055a8efc936025a3a28c0607e4957ad7159",
+     "fetch_kib": 80951.04, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000},
+    {"kernels_sha256": "f978b259dffefc31afc3193fcbfae637424e0882aa7580e5489d61a677a0445c",
      "kernel": "k_stage_mfma<double,3,true,false,4>", "K": 48000,
-     "fetch_kib": 75572.02, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000},
+     "fetch_kib": 75561.31, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000},
 ]
 
 
