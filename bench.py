@@ -111,6 +111,28 @@ MEASURED_TRAFFIC_FP64 = [
 ]
 
 
+# The same for the P2 FP32 stage kernels of the large launches: the
+# 1,572,864-tet scatterer (the variant the library resolves for it) and the
+# batched launch of 64 members on the 10368-tet mesh, every member active
+# (K = members x elements; every variant the batched autotuner times).
+_SHA_Q2 = "f978b259dffefc31afc3193fcbfae637424e0882aa7580e5489d61a677a0445c"
+MEASURED_TRAFFIC_Q2 = [
+    {"kernels_sha256": _SHA_Q2, "kernel": "k_stage_mfma<float,2,true,false,1>", "K": 1572864,
+     "fetch_kib": 834159.68, "fetch_scale": 2.0000, "write_kib": 695527.79, "write_scale": 1.0000},
+] + [
+    {"kernels_sha256": _SHA_Q2, "kernel": k, "K": 64 * 10368,
+     "fetch_kib": fe, "fetch_scale": 2.0000, "write_kib": wr, "write_scale": 1.0000}
+    for k, fe, wr in (("k_stage_mfma<float,2,true,false,1>", 262484.87, 292981.22),
+                      ("k_stage_mfma<float,2,false,false,1>", 266357.44, 292878.95),
+                      ("k_stage<float,2,false,false>", 284756.44, 292133.64),
+                      ("k_stage<float,2,true,false>", 252878.53, 291653.58),
+                      ("k_stage_mfma<float,2,true,false,2>", 247272.51, 291723.03),
+                      ("k_stage_mfma<float,2,true,false,2,true>", 245784.44, 291612.68),
+                      ("k_stage_mfma<float,2,true,false,4>", 245632.92, 291602.80),
+                      ("k_stage_mfma<float,2,true,false,4,true>", 245620.27, 291600.10))
+]
+
+
 # The same for the 2-D stage kernel on the 22500-triangle disk trap (P3, FP32).
 MEASURED_TRAFFIC_2D = {
     "kernels_sha256": "2cfab2a02241355bb5ef28a6732137553b93d1adb24d0d1f204160b9cff12150",
@@ -443,7 +465,8 @@ def scatterer(a):
                       "autotuned": not a.no_autotune},
            "cmcg": {"iters": st["iters"], "periods": st["periods"], "rel_res": st["rel_res"]},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kname,
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, K, MEASURED_TRAFFIC_Q2),
+                        "kernel": kname,
                         "avg_launch_us": per_launch * 1e6, "bytes_per_launch": bpl,
                         "copy_GBs": stream_copy_gbs(), "frac_of_copy": achieved / stream_copy_gbs()},
            "hbm_job": job_roofline(st["dof_updates"] / el, method_bytes_per_dof_update(w.q, 4))}
@@ -1155,7 +1178,7 @@ def scatterer_kernel(a) -> dict:
             "frac": achieved / HBM_PEAK_GBS, "kernel": kname, "avg_launch_us": per_launch * 1e6,
             "bytes_per_launch": bpl, "bytes_per_dof_update": method_bytes_per_dof_update(w.q, 4),
             "compensation_overhead_bytes_per_launch": compensation_bytes_per_launch(w.q, K),
-            "traffic": None}
+            "traffic": measured_traffic(kname, K, MEASURED_TRAFFIC_Q2)}
 
 
 def batched_kernel(a) -> dict:
@@ -1191,7 +1214,7 @@ def batched_kernel(a) -> dict:
             "frac": achieved / HBM_PEAK_GBS, "kernel": kname, "avg_launch_us": us[v],
             "bytes_per_launch": bpl, "bytes_per_dof_update": method_bytes_per_dof_update(2, 4, a.members),
             "compensation_overhead_bytes_per_launch": compensation_bytes_per_launch(2, K, a.members),
-            "variant_us": us, "traffic": None}
+            "variant_us": us, "traffic": measured_traffic(kname, K * a.members, MEASURED_TRAFFIC_Q2)}
 
 
 def serving_short(a, cobatch: int) -> dict:

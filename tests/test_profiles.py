@@ -69,14 +69,18 @@ def _traffic_rows(text: str):
     return sha, {k: (float(fe), float(wr)) for k, _, fe, wr in rows}
 
 
-@pytest.mark.parametrize("name,table", [
-    ("k_stage_mfma_q3_large_single_traffic.md", bench.MEASURED_TRAFFIC),
-    ("k_stage_mfma_q3_fp64_large_single_traffic.md", bench.MEASURED_TRAFFIC_FP64),
-    ("k_stage2d_p3_trap_disk_traffic.md", bench.MEASURED_TRAFFIC_2D),
+@pytest.mark.parametrize("name,table,K", [
+    ("k_stage_mfma_q3_large_single_traffic.md", bench.MEASURED_TRAFFIC, None),
+    ("k_stage_mfma_q3_fp64_large_single_traffic.md", bench.MEASURED_TRAFFIC_FP64, None),
+    ("k_stage2d_p3_trap_disk_traffic.md", bench.MEASURED_TRAFFIC_2D, None),
+    ("k_stage_mfma_q2_scatterer.md", bench.MEASURED_TRAFFIC_Q2, 1572864),
+    ("k_stage_mfma_q2_batched_all_active.md", bench.MEASURED_TRAFFIC_Q2, 64 * 10368),
 ])
-def test_traffic_summary_matches_bench_table(name, table):
+def test_traffic_summary_matches_bench_table(name, table, K):
+    """K (when given) selects the table rows that the summary covers."""
     sha, rows = _traffic_rows(open(os.path.join(PROFILES, name)).read())
     tables = table if isinstance(table, list) else [table]
+    tables = [t for t in tables if K is None or t["K"] == K]
     assert len(rows) == len(tables)
     for t in tables:
         assert sha == t["kernels_sha256"]
