@@ -1669,10 +1669,12 @@ void stage_launch(const StageArgs& a, hipStream_t s) {
         const int64_t blocks = a.blist ? a.nblist : (a.K + EPW - 1) / EPW;
         const int64_t per = (blocks + 7) / 8;
         const dim3 grid((unsigned)(8 * per));
-        // four waves per block where the chosen form has four (8, 9), two
+        // four waves per block on the launches restricted to a block list
+        // (the substep stages: a partial round of workgroups, whose time is
+        // one block's chain) and where the chosen form has four (8, 9); two
         // otherwise
         if constexpr (Q >= 2) {
-            if (stage_variant(Q, sizeof(T) == 8 ? CMCG_FP64 : CMCG_FP32, blocks) >= 8)
+            if (a.blist || stage_variant(Q, sizeof(T) == 8 ? CMCG_FP64 : CMCG_FP32, blocks) >= 8)
                 hipLaunchKernelGGL((k_stage_mfma<T, Q, true, false, 4, false, false, true>), grid, dim3(256), 0, s,
                                    a, per);
             else

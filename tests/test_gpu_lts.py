@@ -217,15 +217,17 @@ def test_served_request_with_local_time_stepping_equals_solo_solve(lib):
     assert np.array_equal(f[0], f[1])
 
 
+@pytest.mark.parametrize("variant", [8, 4])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("q", [2, 3])
-def test_periods_with_four_wave_blocks(lib, q, precision):
-    """With stage variant 8 chosen the substep launches run four waves per
-    element block: forward and adjoint periods against the oracle."""
-    print(f"lts four waves q={q} prec={precision}", flush=True)
+def test_periods_with_four_wave_blocks(lib, q, precision, variant):
+    """The substep launches (restricted to the halo blocks) run four waves
+    per element block; the full launches four with stage variant 8 chosen and
+    two with variant 4: forward and adjoint periods against the oracle."""
+    print(f"lts four waves q={q} prec={precision} variant={variant}", flush=True)
     old = lib.cmcg_tune_get_stage(q, precision)
     try:
-        lib.cmcg_tune_stage(q, precision, 8)
+        lib.cmcg_tune_stage(q, precision, variant)
         op, s, lp = lts_pair(lib, q, precision, tags="mixed", seed=90 + q)
         o = lib.cmcg_options_default(lts_ratio=M_RATIO)
         M, _ = lib.cmcg_problem_steps(lp, o)
