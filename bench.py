@@ -90,24 +90,24 @@ def parse():
 # 48000-tet P3 FP32 problem, with the scales a 1 GiB copy gives each counter;
 # valid only for the kernel source they were taken on (SHA-256 below).
 MEASURED_TRAFFIC = [
-    {"kernels_sha256": "f978b259dffefc31afc3193fcbfae637424e0882aa7580e5489d61a677a0445c",
+    {"kernels_sha256": "d96e47bafc3bacf9d0b7259c35cf642053ecaffc4cdf74dfb1a3a9c9f0635163",
      "kernel": "k_stage_mfma<float,3,true,false,2,false,true>", "K": 48000,
-     "fetch_kib": 41485.02, "fetch_scale": 2.0000, "write_kib": 42200.84, "write_scale": 1.0000},
-    {"kernels_sha256": "f978b259dffefc31afc3193fcbfae637424e0882aa7580e5489d61a677a0445c",
+     "fetch_kib": 41487.43, "fetch_scale": 2.0000, "write_kib": 42200.73, "write_scale": 1.0000},
+    {"kernels_sha256": "d96e47bafc3bacf9d0b7259c35cf642053ecaffc4cdf74dfb1a3a9c9f0635163",
      "kernel": "k_stage_mfma<float,3,true,false,4>", "K": 48000,
-     "fetch_kib": 40910.61, "fetch_scale": 2.0000, "write_kib": 42187.67, "write_scale": 1.0000},
+     "fetch_kib": 40911.33, "fetch_scale": 2.0000, "write_kib": 42187.67, "write_scale": 1.0000},
 ]
 
 
 # The same for the FP64 stage kernel of the plain FP64 solve (48000 tets, P3):
 # the two forms its autotuner keeps (two and four waves per block).
 MEASURED_TRAFFIC_FP64 = [
-    {"kernels_sha256": "f978b259dffefc31afc3193fcbfae637424e0882aa7580e5489d61a677a0445c",
+    {"kernels_sha256": "d96e47bafc3bacf9d0b7259c35cf642053ecaffc4cdf74dfb1a3a9c9f0635163",
      "kernel": "k_stage_mfma<double,3,true,false,2>", "K": 48000,
-     "fetch_kib": 80951.04, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000},
-    {"kernels_sha256": "f978b259dffefc31afc3193fcbfae637424e0882aa7580e5489d61a677a0445c",
+     "fetch_kib": 80955.63, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000},
+    {"kernels_sha256": "d96e47bafc3bacf9d0b7259c35cf642053ecaffc4cdf74dfb1a3a9c9f0635163",
      "kernel": "k_stage_mfma<double,3,true,false,4>", "K": 48000,
-     "fetch_kib": 75561.31, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000},
+     "fetch_kib": 75563.54, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000},
 ]
 
 
@@ -115,21 +115,21 @@ MEASURED_TRAFFIC_FP64 = [
 # 1,572,864-tet scatterer (the variant the library resolves for it) and the
 # batched launch of 64 members on the 10368-tet mesh, every member active
 # (K = members x elements; every variant the batched autotuner times).
-_SHA_Q2 = "f978b259dffefc31afc3193fcbfae637424e0882aa7580e5489d61a677a0445c"
+_SHA_Q2 = "d96e47bafc3bacf9d0b7259c35cf642053ecaffc4cdf74dfb1a3a9c9f0635163"
 MEASURED_TRAFFIC_Q2 = [
     {"kernels_sha256": _SHA_Q2, "kernel": "k_stage_mfma<float,2,true,false,1>", "K": 1572864,
-     "fetch_kib": 834159.68, "fetch_scale": 2.0000, "write_kib": 695527.79, "write_scale": 1.0000},
+     "fetch_kib": 827632.77, "fetch_scale": 2.0000, "write_kib": 696250.74, "write_scale": 1.0000},
 ] + [
     {"kernels_sha256": _SHA_Q2, "kernel": k, "K": 64 * 10368,
      "fetch_kib": fe, "fetch_scale": 2.0000, "write_kib": wr, "write_scale": 1.0000}
-    for k, fe, wr in (("k_stage_mfma<float,2,true,false,1>", 262484.87, 292981.22),
-                      ("k_stage_mfma<float,2,false,false,1>", 266357.44, 292878.95),
-                      ("k_stage<float,2,false,false>", 284756.44, 292133.64),
-                      ("k_stage<float,2,true,false>", 252878.53, 291653.58),
-                      ("k_stage_mfma<float,2,true,false,2>", 247272.51, 291723.03),
-                      ("k_stage_mfma<float,2,true,false,2,true>", 245784.44, 291612.68),
-                      ("k_stage_mfma<float,2,true,false,4>", 245632.92, 291602.80),
-                      ("k_stage_mfma<float,2,true,false,4,true>", 245620.27, 291600.10))
+    for k, fe, wr in (("k_stage_mfma<float,2,true,false,1>", 262006.96, 293117.60),
+                      ("k_stage_mfma<float,2,false,false,1>", 265735.77, 293007.60),
+                      ("k_stage<float,2,false,false>", 284607.37, 292228.44),
+                      ("k_stage<float,2,true,false>", 252909.87, 291673.93),
+                      ("k_stage_mfma<float,2,true,false,2>", 247366.78, 291744.54),
+                      ("k_stage_mfma<float,2,true,false,2,true>", 245743.43, 291614.95),
+                      ("k_stage_mfma<float,2,true,false,4>", 245654.32, 291602.79),
+                      ("k_stage_mfma<float,2,true,false,4,true>", 245624.33, 291600.10))
 ]
 
 
