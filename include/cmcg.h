@@ -449,7 +449,10 @@ int cmcg_engine_info(const cmcg_engine* e, size_t* used, int* n_running, int* n_
  * would refuse the caller's legacy-stream work from any other thread), and
  * the worker only replays them.  cmcg_engine_step reports the slot finished
  * once the solve has ended.  Admission cost: the members' summed
- * footprints.  Errors as cmcg_engine_admit, and CMCG_ERR_ARG when the
+ * footprints plus what the batch copies: every member's source and source
+ * mask (when any member has a source) and the geometry and mass weights
+ * (once when the members share their media, else per member).  Errors as
+ * cmcg_engine_admit, and CMCG_ERR_ARG when the
  * problems do not share a space, repeat, or ask for local time stepping.
  * o->progress is not called and o->autotune is ignored.
  * cmcg_engine_slot_members: members of a slot (0 free, 1 for a single solve).

@@ -84,7 +84,7 @@ size_t footprint(const cmcg_problem* p) {
     const SpaceData& s = *p->sp;
     const size_t n = s.ndof, es = s.esize(), K = s.K;
     const size_t H = p->nharm;
-    size_t b = K * kGeo * es + 2 * K * 8;  // geometry, mass weights
+    size_t b = K * geo_values(s) * es + 2 * K * 8;  // geometry, mass weights
     if (p->src_rows) b += 2 * n * es * H + p->smask.bytes;  // source (per harmonic) and its element mask
     b += 5 * n * es;                       // U, Y1, Y2, Acc, RHS buffer
     if (s.precision == CMCG_FP32) b += 2 * n;  // bfloat16 low parts of U
@@ -104,6 +104,30 @@ size_t footprint(const cmcg_problem* p, const cmcg_options* o) {
     }
     return b;
 }
+
+namespace {
+
+// footprint of a co-batched slot: the members' own footprints plus what the
+// batch copies -- every member's source and source mask (when any member has
+// a source) and the geometry and mass weights (once when the members share
+// their media)
+size_t batch_footprint(cmcg_problem* const* probs, int n) {
+    const SpaceData& s = *probs[0]->sp;
+    const size_t nd = s.ndof, es = s.esize(), K = s.K;
+    size_t b = 0;
+    bool shared = true, src = false;
+    for (int i = 0; i < n; ++i) {
+        b += footprint(probs[i]);
+        shared = shared && probs[i]->eps == probs[0]->eps && probs[i]->mu == probs[0]->mu &&
+                 probs[i]->sigma == probs[0]->sigma;
+        src = src || probs[i]->src_rows != 0;
+    }
+    if (src) b += (size_t)n * (2 * nd * es + (size_t)source_mask_words(s.K) * 4);
+    b += (shared ? 1 : (size_t)n) * (K * geo_values(s) * es + 2 * K * 8);
+    return b;
+}
+
+}  // namespace
 
 }  // namespace cmcg
 
@@ -197,15 +221,14 @@ int cmcg_engine_admit_batch(cmcg_engine* e, cmcg_problem* const* problems, int n
     cmcg_options_default(&def);
     if (!o) o = &def;
     if (o->lts_ratio > 1) fail(CMCG_ERR_ARG, "engine_admit_batch: local time stepping is for single solves");
-    size_t need = 0;
     for (int b = 0; b < n; ++b) {
         if (!problems[b]) fail(CMCG_ERR_ARG, "engine_admit_batch: NULL problem");
         if (problems[b]->sp != problems[0]->sp) fail(CMCG_ERR_ARG, "engine_admit_batch: members must share a space");
         if (problems[b]->nharm != 1) fail(CMCG_ERR_ARG, "engine_admit_batch: several-frequency problems are single");
         for (int c = 0; c < b; ++c)
             if (problems[c] == problems[b]) fail(CMCG_ERR_ARG, "engine_admit_batch: a problem appears twice");
-        need += footprint(problems[b]);
     }
+    const size_t need = batch_footprint(problems, n);
     if (need > e->budget)
         fail(CMCG_ERR_TOO_LARGE, "engine_admit_batch: footprint " + std::to_string(need) + " B exceeds the budget " +
                                      std::to_string(e->budget) + " B");

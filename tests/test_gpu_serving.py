@@ -140,6 +140,15 @@ def test_cobatched_slot_interface(lib):
     e = lib.cmcg_engine_create(1 << 33, 2)
     slot = lib.cmcg_engine_admit_batch(e, probs[:2])
     assert lib.cmcg_engine_slot_members(e, slot) == 2
+    # admission cost: the members' footprints plus the batch's copies of their
+    # sources and source masks and of the geometry and mass weights (FP32, 3-D)
+    s, _ = cache.get(reqs[0]["n"], reqs[0]["q"])
+    info = lib.cmcg_space_info(s)
+    K, ndof = info["K"], info["K"] * 6 * info["Np"]
+    base = sum(lib.cmcg_problem_footprint(p) for p in probs[:2])
+    sources = 2 * (2 * ndof * 4 + -(-K // 10) * 4)
+    geo = K * 40 * 4 + 2 * K * 8
+    assert lib.cmcg_engine_info(e)["used"] in (base + sources + geo, base + sources + 2 * geo)
     with pytest.raises(lib.CmcgError) as err:
         lib.cmcg_engine_admit(e, probs[0])                 # held by the co-batched slot
     assert err.value.code == lib.CMCG_ERR_STATE
