@@ -43,7 +43,8 @@ namespace {
 // face neighbours), and the lists of fine and halo blocks
 void ensure_lts_mask(cmcg_problem* p, const StepCfg& c) {
     const SpaceData& s = *p->sp;
-    if (p->lts_H == c.dt && p->lts_mask.p) return;
+    // the fine set depends on the coarse step and the CFL constant
+    if (p->lts_H == c.dt && p->lts_cq == c.cq && p->lts_mask.p) return;
     const MeshData& m = *s.mesh;
     const int64_t nw = source_mask_words(s.K);
     std::vector<uint32_t> w(nw, 0u), hb(nw, 0u);
@@ -103,6 +104,7 @@ void ensure_lts_mask(cmcg_problem* p, const StepCfg& c) {
     for (auto& kv : p->lts_graphs) (void)hipGraphExecDestroy(kv.second);
     p->lts_graphs.clear();
     p->lts_H = c.dt;
+    p->lts_cq = c.cq;
 }
 
 double inv_fact(int k) { return k == 0 ? 1.0 : k == 1 ? 1.0 : k == 2 ? 0.5 : 1.0 / 6.0; }

@@ -574,9 +574,10 @@ static void run_period(cmcg_problem* p, const StepCfg& c, bool src, bool filt, b
     }
     // the stage variant is read when the launches are enqueued, so a graph
     // captured under one variant must not be replayed after another is chosen
+    // (variant + 1: the size-based default is -1, which must not spill into the step count's bits)
     const int variant = p->sp->dim == 3 ? get_stage_variant(p->sp->q, p->sp->precision) : 0;
-    const int64_t key =
-        ((int64_t)c.M << 12) | (variant << 8) | (c.scheme << 4) | (src ? 2 : 0) | (filt ? 1 : 0);
+    const int64_t key = ((int64_t)c.M << 12) | ((int64_t)(variant + 1) << 8) | (c.scheme << 4) | (src ? 2 : 0) |
+                        (filt ? 1 : 0);
     auto it = p->graphs.find(key);
     if (it == p->graphs.end()) {
         if (!p->cap_stream) CMCG_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
@@ -613,8 +614,8 @@ static void run_lts_period(cmcg_problem* p, const StepCfg& c, int direction, boo
         return;
     }
     const int variant = get_stage_variant(p->sp->q, p->sp->precision);
-    const int64_t key = ((int64_t)c.M << 24) | ((int64_t)c.lts << 16) | (variant << 8) | (direction < 0 ? 0x80 : 0) |
-                        (c.scheme << 4) | (src ? 2 : 0) | (filt ? 1 : 0);
+    const int64_t key = ((int64_t)c.M << 24) | ((int64_t)c.lts << 16) | ((int64_t)(variant + 1) << 8) |
+                        (direction < 0 ? 0x80 : 0) | (c.scheme << 4) | (src ? 2 : 0) | (filt ? 1 : 0);
     auto it = p->lts_graphs.find(key);
     if (it == p->lts_graphs.end()) {
         if (!p->cap_stream) CMCG_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));

@@ -240,3 +240,31 @@ def test_periods_with_four_wave_blocks(lib, q, precision, variant):
         assert rel_norm(op, host(UT), lts.backward(op, U0, M, M_RATIO, fine, 4)) < TOL[precision]
     finally:
         lib.cmcg_tune_stage(q, precision, old)
+
+
+def test_graphed_lts_period_follows_a_ratio_change(lib):
+    """Two substep counts at one coarse step count (the same coarse step):
+    each forward period is captured as its own graph and equals the eager
+    one bit for bit, and a change of the CFL constant at the same coarse step
+    rebuilds the fine set (both were once cached on the coarse step alone)."""
+    op, s, lp = lts_pair(lib, 2, 0, seed=7)
+    M, _ = lib.cmcg_problem_steps(lp, lib.cmcg_options_default(lts_ratio=M_RATIO))
+    U0h = np.random.default_rng(8).standard_normal((op.K, 6, op.Np))
+    U0 = dev(U0h)
+    out = {}
+    for ratio, graph in ((M_RATIO, 1), (M_RATIO + 2, 1), (M_RATIO + 2, 0)):
+        UT = dev(np.zeros((op.K, 6, op.Np)))
+        o = lib.cmcg_options_default(lts_ratio=ratio, steps=M, use_graph=graph)
+        lib.cmcg_debug_period(lp, U0, UT, 1, True, opts=o)
+        out[(ratio, graph)] = host(UT)
+    assert np.array_equal(out[(M_RATIO + 2, 1)], out[(M_RATIO + 2, 0)])
+    assert not np.array_equal(out[(M_RATIO + 2, 1)], out[(M_RATIO, 1)])
+    # the first ratio's period built the fine set of the default CFL constant;
+    # a smaller constant at the same coarse step makes more elements fine
+    o2 = lib.cmcg_options_default(lts_ratio=M_RATIO, steps=M, cfl=0.05)
+    f1 = lib.cmcg_problem_lts_fine(lp, op.K, lib.cmcg_options_default(lts_ratio=M_RATIO, steps=M))
+    f2 = lib.cmcg_problem_lts_fine(lp, op.K, o2)
+    assert f2.sum() > f1.sum()
+    UT = dev(np.zeros((op.K, 6, op.Np)))
+    lib.cmcg_debug_period(lp, U0, UT, 1, True, opts=o2)
+    assert rel_norm(op, host(UT), lts.forward(op, U0h, M, M_RATIO, f2.astype(bool), 4, True)) < TOL[0]

@@ -425,6 +425,36 @@ def test_graphed_period_follows_a_stage_variant_change(lib):
         lib.cmcg_tune_stage(q, 1, old)
 
 
+def test_graphed_period_follows_a_step_count_change(lib):
+    """With the size-based default stage form (no variant chosen), periods of
+    one problem at two step counts are captured as two graphs: the second
+    graphed period equals its eager counterpart bit for bit (its graph key
+    once lost the step count for the default form)."""
+    import torch
+    q = 3
+    old = lib.cmcg_tune_get_stage(q, 1)
+    try:
+        lib.cmcg_tune_stage(q, 1, -1)
+        xyz, tet, tags = inputs.cube_mesh(2)
+        K = tet.shape[0]
+        m = lib.cmcg_mesh_create(xyz, tet, tags)
+        s = lib.cmcg_space_create(m, q, 1)
+        Np = lib.cmcg_space_info(s)["Np"]
+        j = inputs.gaussian_current(lib.cmcg_space_nodes(s), (0.5, 0.4, 0.5), 0.3, 1)
+        p = lib.cmcg_problem_create(s, np.ones(K), np.ones(K), None, 2 * np.pi, j)
+        U = dev(np.random.default_rng(6).standard_normal((K, 6, Np)))
+        out = {}
+        for steps, graph in ((60, 1), (64, 1), (64, 0)):
+            UT = torch.empty_like(U)
+            lib.cmcg_debug_period(p, U, UT, 1, True, opts=lib.cmcg_options_default(steps=steps, use_graph=graph))
+            torch.cuda.synchronize()
+            out[(steps, graph)] = UT.cpu()
+        assert torch.equal(out[(64, 1)], out[(64, 0)])
+        assert not torch.equal(out[(64, 1)], out[(60, 1)])
+    finally:
+        lib.cmcg_tune_stage(q, 1, old)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_solves_are_reproducible_bit_for_bit(lib, precision):
     """The same problem solved twice from graphs and once eagerly: identical
