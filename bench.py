@@ -90,24 +90,24 @@ def parse():
 # 48000-tet P3 FP32 problem, with the scales a 1 GiB copy gives each counter;
 # valid only for the kernel source they were taken on (SHA-256 below).
 MEASURED_TRAFFIC = [
-    {"kernels_sha256": "d96e47bafc3bacf9d0b7259c35cf642053ecaffc4cdf74dfb1a3a9c9f0635163",
+    {"kernels_sha256": "e3f11409ed4d0fba0e169ae78fdcfcc2cf1360bfc91b93e0dc41f0e050b95388",
      "kernel": "k_stage_mfma<float,3,true,false,2,false,true>", "K": 48000,
-     "fetch_kib": 41487.43, "fetch_scale": 2.0000, "write_kib": 42200.73, "write_scale": 1.0000},
-    {"kernels_sha256": "d96e47bafc3bacf9d0b7259c35cf642053ecaffc4cdf74dfb1a3a9c9f0635163",
+     "fetch_kib": 41470.71, "fetch_scale": 2.0000, "write_kib": 42200.96, "write_scale": 1.0000},
+    {"kernels_sha256": "e3f11409ed4d0fba0e169ae78fdcfcc2cf1360bfc91b93e0dc41f0e050b95388",
      "kernel": "k_stage_mfma<float,3,true,false,4>", "K": 48000,
-     "fetch_kib": 40911.33, "fetch_scale": 2.0000, "write_kib": 42187.67, "write_scale": 1.0000},
+     "fetch_kib": 40964.72, "fetch_scale": 2.0000, "write_kib": 42187.63, "write_scale": 1.0000},
 ]
 
 
 # The same for the FP64 stage kernel of the plain FP64 solve (48000 tets, P3):
 # the two forms its autotuner keeps (two and four waves per block).
 MEASURED_TRAFFIC_FP64 = [
-    {"kernels_sha256": "d96e47bafc3bacf9d0b7259c35cf642053ecaffc4cdf74dfb1a3a9c9f0635163",
+    {"kernels_sha256": "e3f11409ed4d0fba0e169ae78fdcfcc2cf1360bfc91b93e0dc41f0e050b95388",
      "kernel": "k_stage_mfma<double,3,true,false,2>", "K": 48000,
-     "fetch_kib": 80955.63, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000},
-    {"kernels_sha256": "d96e47bafc3bacf9d0b7259c35cf642053ecaffc4cdf74dfb1a3a9c9f0635163",
+     "fetch_kib": 80986.21, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000},
+    {"kernels_sha256": "e3f11409ed4d0fba0e169ae78fdcfcc2cf1360bfc91b93e0dc41f0e050b95388",
      "kernel": "k_stage_mfma<double,3,true,false,4>", "K": 48000,
-     "fetch_kib": 75563.54, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000},
+     "fetch_kib": 75569.25, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000},
 ]
 
 
@@ -115,21 +115,21 @@ MEASURED_TRAFFIC_FP64 = [
 # 1,572,864-tet scatterer (the variant the library resolves for it) and the
 # batched launch of 64 members on the 10368-tet mesh, every member active
 # (K = members x elements; every variant the batched autotuner times).
-_SHA_Q2 = "d96e47bafc3bacf9d0b7259c35cf642053ecaffc4cdf74dfb1a3a9c9f0635163"
+_SHA_Q2 = "e3f11409ed4d0fba0e169ae78fdcfcc2cf1360bfc91b93e0dc41f0e050b95388"
 MEASURED_TRAFFIC_Q2 = [
     {"kernels_sha256": _SHA_Q2, "kernel": "k_stage_mfma<float,2,true,false,1>", "K": 1572864,
-     "fetch_kib": 827632.77, "fetch_scale": 2.0000, "write_kib": 696250.74, "write_scale": 1.0000},
+     "fetch_kib": 827031.24, "fetch_scale": 2.0000, "write_kib": 696307.63, "write_scale": 1.0000},
 ] + [
     {"kernels_sha256": _SHA_Q2, "kernel": k, "K": 64 * 10368,
      "fetch_kib": fe, "fetch_scale": 2.0000, "write_kib": wr, "write_scale": 1.0000}
-    for k, fe, wr in (("k_stage_mfma<float,2,true,false,1>", 262006.96, 293117.60),
-                      ("k_stage_mfma<float,2,false,false,1>", 265735.77, 293007.60),
-                      ("k_stage<float,2,false,false>", 284607.37, 292228.44),
-                      ("k_stage<float,2,true,false>", 252909.87, 291673.93),
-                      ("k_stage_mfma<float,2,true,false,2>", 247366.78, 291744.54),
-                      ("k_stage_mfma<float,2,true,false,2,true>", 245743.43, 291614.95),
-                      ("k_stage_mfma<float,2,true,false,4>", 245654.32, 291602.79),
-                      ("k_stage_mfma<float,2,true,false,4,true>", 245624.33, 291600.10))
+    for k, fe, wr in (("k_stage_mfma<float,2,true,false,1>", 261893.38, 293125.06),
+                      ("k_stage_mfma<float,2,false,false,1>", 265729.02, 293008.64),
+                      ("k_stage<float,2,false,false>", 284604.15, 292229.89),
+                      ("k_stage<float,2,true,false>", 252912.04, 291676.09),
+                      ("k_stage_mfma<float,2,true,false,2>", 247348.47, 291745.09),
+                      ("k_stage_mfma<float,2,true,false,2,true>", 245738.03, 291615.28),
+                      ("k_stage_mfma<float,2,true,false,4>", 245655.99, 291602.90),
+                      ("k_stage_mfma<float,2,true,false,4,true>", 245623.47, 291600.15))
 ]
 
 

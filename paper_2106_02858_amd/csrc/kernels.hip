@@ -586,7 +586,12 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
                 for (int j = 0; j < 4; ++j) {
                     if (j >= a.lnw) break;
                     T* wj = (T*)args.lw[j] + grow;
-                    Row<T, NP>::load(wj, w);
+                    if (a.linit) {
+#pragma unroll
+                        for (int i = 0; i < NP; ++i) w[i] = T(0);
+                    } else {
+                        Row<T, NP>::load(wj, w);
+                    }
                     const T cj = (T)args.lcw[j];
 #pragma unroll
                     for (int i = 0; i < NP; ++i) w[i] = fma(cj, y[i], w[i]);
@@ -602,6 +607,13 @@ __global__ __launch_bounds__(64) void k_stage(StageArgs args, int64_t per) {
             }
             Row<T, NP>::store((T*)a.Uout + grow, o1);
             if (a.Ynext) Row<T, NP>::store((T*)a.Ynext + grow, o2);
+            if (a.lz) {  // the next substep's starting state and first stage vector
+                Row<T, NP>::store((T*)a.lz + grow, o1);
+                const T kc = (T)a.lkc;
+#pragma unroll
+                for (int i = 0; i < NP; ++i) o2[i] = kc * o1[i];
+                Row<T, NP>::store((T*)a.lk + grow, o2);
+            }
         }
     } else {
         switch (mode) {
@@ -1170,7 +1182,12 @@ void k_stage_mfma(StageArgs args, int64_t per) {
                     for (int j = 0; j < 4; ++j) {
                         if (j >= a.lnw) break;
                         T w[PV];
-                        ldv(args.lw[j], gi, w);
+                        if (a.linit) {
+#pragma unroll
+                            for (int u = 0; u < PV; ++u) w[u] = T(0);
+                        } else {
+                            ldv(args.lw[j], gi, w);
+                        }
                         const T cj = (T)args.lcw[j];
 #pragma unroll
                         for (int u = 0; u < PV; ++u) w[u] = fma(cj, x0[u], w[u]);
@@ -1188,6 +1205,13 @@ void k_stage_mfma(StageArgs args, int64_t per) {
                 }
                 stv(a.Uout, o1);
                 if (a.Ynext) stv(a.Ynext, o2);
+                if (a.lz) {  // the next substep's starting state and first stage vector
+                    stv(a.lz, o1);
+                    const T kc = (T)a.lkc;
+#pragma unroll
+                    for (int u = 0; u < PV; ++u) o2[u] = kc * o1[u];
+                    stv(a.lk, o2);
+                }
             }
         } else {
             switch (mode) {

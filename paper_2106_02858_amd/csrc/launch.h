@@ -20,8 +20,11 @@ namespace cmcg {
 //           Ynext = U + le Acc + cy k; Uout = lf Acc + ca k (Acc, Ynext, Uout
 //           nullable; no compensated state)
 //   LTS_ADJ (adjoint substep stage; Y = the adjoint stage vector kcur): on the
-//           rows of the elements set in lmask A = k and lw_j += lcw_j kcur,
-//           elsewhere A = 0; Uout = U + A; Ynext = le Acc + lf A (nullable)
+//           rows of the elements set in lmask A = k and lw_j += lcw_j kcur
+//           (lw_j = lcw_j kcur when linit), elsewhere A = 0; Uout = U + A;
+//           Ynext = le Acc + lf A (nullable); when lz is set (the last stage
+//           of a substep), also lz = Uout and lk = lkc Uout (the next
+//           substep's starting state and first stage vector)
 //   LTS_CHAIN (adjoint Taylor chain): Uout = [A] k + [B] lw[0] + [C] lw[1] + lw[2],
 //           [m] x = x on the rows of the elements whose bit of the mask (lmask,
 //           lmaskB, lmaskC) xor its inv flag is set, 0 elsewhere (null mask:
@@ -87,6 +90,10 @@ struct StageArgs {
     double lcw[4];
     int lnw;
     double le, lf;
+    void* lz;     // LTS_ADJ: copy of Uout (nullable) ...
+    void* lk;     // ... and lkc Uout
+    double lkc;
+    int linit;    // LTS_ADJ: lw_j = lcw_j kcur instead of lw_j += lcw_j kcur
     const uint32_t* lmask;  // LTS_ADJ: output rows (one word per element block, layout of smask)
     const uint32_t* lmaskB;
     const uint32_t* lmaskC;

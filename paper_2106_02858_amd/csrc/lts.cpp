@@ -40,7 +40,8 @@ namespace {
 
 // fine-element mask (one word per element block) for the coarse step of c,
 // the mask of the element blocks that hold halo elements (fine ones or their
-// face neighbours), and the lists of fine and halo blocks
+// face neighbours), the rows near the halo outside the fine elements, and the
+// lists of halo blocks and of halo blocks with their face neighbours' blocks
 void ensure_lts_mask(cmcg_problem* p, const StepCfg& c) {
     const SpaceData& s = *p->sp;
     // the fine set depends on the coarse step and the CFL constant
@@ -60,12 +61,11 @@ void ensure_lts_mask(cmcg_problem* p, const StepCfg& c) {
                 if (m.nbr[4 * e + f] >= 0) halo[m.nbr[4 * e + f]] = 1;
         }
     }
-    std::vector<int> fb, hbl, h2l;
+    std::vector<int> hbl, h2l;
     std::vector<char> near(s.K, 0);  // elements of halo blocks and their face neighbours
     for (int64_t b = 0; b < nw; ++b) {
-        bool any_f = w[b] != 0, any_h = false;
+        bool any_h = false;
         for (int64_t e = 10 * b; e < std::min<int64_t>(10 * b + 10, s.K); ++e) any_h = any_h || halo[e];
-        if (any_f) fb.push_back((int)b);
         if (any_h) {
             hbl.push_back((int)b);
             hb[b] = 0x3ffu;  // every element of the block
@@ -91,13 +91,10 @@ void ensure_lts_mask(cmcg_problem* p, const StepCfg& c) {
     CMCG_HIP(hipMemcpy(p->lts_h2nf.p, h2nf.data(), nw * 4, hipMemcpyHostToDevice));
     CMCG_HIP(hipMemcpy(p->lts_mask.p, w.data(), nw * 4, hipMemcpyHostToDevice));
     CMCG_HIP(hipMemcpy(p->lts_hbmask.p, hb.data(), nw * 4, hipMemcpyHostToDevice));
-    p->lts_nfb = (int64_t)fb.size();
     p->lts_nhb = (int64_t)hbl.size();
     p->lts_nh2b = (int64_t)h2l.size();
-    p->lts_fblocks.alloc(std::max<size_t>(1, fb.size()) * 4);
     p->lts_hblocks.alloc(std::max<size_t>(1, hbl.size()) * 4);
     p->lts_h2blocks.alloc(std::max<size_t>(1, h2l.size()) * 4);
-    if (!fb.empty()) CMCG_HIP(hipMemcpy(p->lts_fblocks.p, fb.data(), fb.size() * 4, hipMemcpyHostToDevice));
     if (!hbl.empty()) CMCG_HIP(hipMemcpy(p->lts_hblocks.p, hbl.data(), hbl.size() * 4, hipMemcpyHostToDevice));
     if (!h2l.empty()) CMCG_HIP(hipMemcpy(p->lts_h2blocks.p, h2l.data(), h2l.size() * 4, hipMemcpyHostToDevice));
     // captured periods hold the old lists' addresses and the old step's coefficients
@@ -193,8 +190,7 @@ void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool
             for (int k = 0; k < order; ++k) al[k] += st_b[si] * h * cw[k];
         }
     const int* hbl = p->lts_hblocks.as<int>();
-    const int* fbl = p->lts_fblocks.as<int>();
-    const int64_t nhb = p->lts_nhb, nfb = p->lts_nfb;
+    const int64_t nhb = p->lts_nhb;
     const uint32_t* hbmask = p->lts_hbmask.as<uint32_t>();
     auto rhs_on = [&](const int* bl, int64_t nb) {
         a.blist = bl;
@@ -347,8 +343,11 @@ void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool
     void* Z0 = p->lZ0.p;
     // one adjoint substep stage on the halo blocks, fused with its
     // combination: A = B kcur on the fine rows (0 elsewhere); zbar += A;
-    // knext = a0 Z0 + b0 A; wbar_j += cw_j kcur on the fine rows
-    auto adj_stage = [&](const void* kcur, const double* cw, double a0, double b0, void* knext) {
+    // knext = a0 Z0 + b0 A; wbar_j += cw_j kcur on the fine rows (= when
+    // init: the coarse step's first stage); the substep's last stage also
+    // starts the next substep: Z0 = zbar, KA = kc zbar (z0next, knext2)
+    auto adj_stage = [&](const void* kcur, const double* cw, double a0, double b0, void* knext, bool init = false,
+                         void* z0next = nullptr, void* knext2 = nullptr, double kc = 0.0) {
         a.Y = kcur;
         a.U = U;
         a.Uout = U;
@@ -366,6 +365,10 @@ void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool
             a.lw[j] = WB[j];
             a.lcw[j] = cw[j];
         }
+        a.linit = init ? 1 : 0;
+        a.lz = z0next;
+        a.lk = knext2;
+        a.lkc = kc;
         a.blist = hbl;
         a.nblist = nhb;
         stage_dim(s, a, st);
@@ -373,6 +376,9 @@ void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool
         a.Acc = a.Ynext = a.Uout = nullptr;
         a.lnw = 0;
         a.lmask = nullptr;
+        a.linit = 0;
+        a.lz = a.lk = nullptr;
+        a.lkc = 0.0;
         a.blist = nullptr;
         a.nblist = 0;
     };
@@ -410,28 +416,34 @@ void lts_period(cmcg_problem* p, const StepCfg& c, int direction, bool src, bool
     const int64_t nh2b = p->lts_nh2b;
     for (int nn = 0; nn < M; ++nn) {
         if (nhb > 0) {
-            // the substeps accumulate wbar on the fine rows
-            for (int k = 0; k < order; ++k)
-                launch_lts_axpy(prec, n, np6, fbl, nfb, nullptr, 0, 0.0, nullptr, 0.0, U, WB[k], st);
+            // the substeps accumulate wbar on the fine rows (the first stage
+            // sets it); each substep starts from Z0 = zbar and its first
+            // stage vector kc zbar, formed here for the first substep and by
+            // the previous substep's last stage for the others
             double cw[4];
+            const double kc = c.scheme == 2 ? h : h / 6.0;  // kbar2 = h zbar, kbar4 = h/6 zbar
             for (int l = m - 1; l >= 0; --l) {
                 const double tau = l * h;
-                launch_lts_axpy(prec, n, np6, hbl, nhb, nullptr, 0, 0.0, nullptr, 1.0, U, Z0, st);  // Z0 = zbar
+                const bool first = l == m - 1;
+                if (first) {
+                    launch_lts_axpy(prec, n, np6, hbl, nhb, nullptr, 0, 0.0, nullptr, 1.0, U, Z0, st);  // Z0 = zbar
+                    launch_lts_axpy(prec, n, np6, hbl, nhb, nullptr, 0, 0.0, nullptr, kc, Z0, KA, st);
+                }
+                void* zn = l > 0 ? Z0 : nullptr;
+                void* kn = l > 0 ? KA : nullptr;
                 if (c.scheme == 2) {
-                    launch_lts_axpy(prec, n, np6, hbl, nhb, nullptr, 0, 0.0, nullptr, h, Z0, KA, st);  // kbar2
                     poly(tau + 0.5 * h, cw);
-                    adj_stage(KA, cw, 0.0, 0.5 * h, KB);
+                    adj_stage(KA, cw, 0.0, 0.5 * h, KB, first);
                     poly(tau, cw);
-                    adj_stage(KB, cw, 0.0, 0.0, nullptr);
+                    adj_stage(KB, cw, 0.0, 0.0, nullptr, false, zn, kn, kc);
                 } else {
-                    launch_lts_axpy(prec, n, np6, hbl, nhb, nullptr, 0, 0.0, nullptr, h / 6.0, Z0, KA, st);  // kbar4
                     poly(tau + h, cw);
-                    adj_stage(KA, cw, h / 3.0, h, KB);
+                    adj_stage(KA, cw, h / 3.0, h, KB, first);
                     poly(tau + 0.5 * h, cw);
                     adj_stage(KB, cw, h / 3.0, 0.5 * h, KA);
                     adj_stage(KA, cw, h / 6.0, 0.5 * h, KB);
                     poly(tau, cw);
-                    adj_stage(KB, cw, 0.0, 0.0, nullptr);
+                    adj_stage(KB, cw, 0.0, 0.0, nullptr, false, zn, kn, kc);
                 }
             }
         }

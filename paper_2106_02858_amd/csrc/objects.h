@@ -127,9 +127,9 @@ struct cmcg_problem {
     cmcg::DevBuf partial, scal;
     // local time stepping: fine-element mask (per element block) for the coarse
     // step lts_H, Taylor coefficients, frozen coarse terms, adjoint work vectors
-    cmcg::DevBuf lts_mask, lts_hbmask, lts_h2nf, lts_fblocks, lts_hblocks, lts_h2blocks, lD[3], lW[4], lWB[4], lZ0;
+    cmcg::DevBuf lts_mask, lts_hbmask, lts_h2nf, lts_hblocks, lts_h2blocks, lD[3], lW[4], lWB[4], lZ0;
     double lts_H = -1, lts_cq = -1;
-    int64_t lts_fine = 0, lts_nfb = 0, lts_nhb = 0, lts_nh2b = 0;
+    int64_t lts_fine = 0, lts_nhb = 0, lts_nh2b = 0;
     std::map<int64_t, hipGraphExec_t> lts_graphs;  // captured LTS periods
     std::unique_ptr<cmcg::HostPinned> pinned;
     hipStream_t cap_stream = nullptr;
