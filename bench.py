@@ -112,13 +112,15 @@ MEASURED_TRAFFIC_FP64 = [
 
 
 # The same for the P2 FP32 stage kernels of the large launches: the
-# 1,572,864-tet scatterer (the variant the library resolves for it) and the
+# 1,572,864-tet scatterer (variants 3 and 2, the two its autotuner keeps) and the
 # batched launch of 64 members on the 10368-tet mesh, every member active
 # (K = members x elements; every variant the batched autotuner times).
 _SHA_Q2 = "e3f11409ed4d0fba0e169ae78fdcfcc2cf1360bfc91b93e0dc41f0e050b95388"
 MEASURED_TRAFFIC_Q2 = [
     {"kernels_sha256": _SHA_Q2, "kernel": "k_stage_mfma<float,2,true,false,1>", "K": 1572864,
      "fetch_kib": 827031.24, "fetch_scale": 2.0000, "write_kib": 696307.63, "write_scale": 1.0000},
+    {"kernels_sha256": _SHA_Q2, "kernel": "k_stage_mfma<float,2,false,false,1>", "K": 1572864,
+     "fetch_kib": 841317.55, "fetch_scale": 2.0000, "write_kib": 695818.02, "write_scale": 1.0000},
 ] + [
     {"kernels_sha256": _SHA_Q2, "kernel": k, "K": 64 * 10368,
      "fetch_kib": fe, "fetch_scale": 2.0000, "write_kib": wr, "write_scale": 1.0000}
