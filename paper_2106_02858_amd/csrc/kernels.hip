@@ -823,7 +823,7 @@ template <typename T, int Q, int NTH = 64, bool LTSM = false> struct MfmaUpdateI
 // column tile (P2), a quarter of the MFMAs and fewer registers per wave.
 template <typename T, int Q, bool PIPE, bool MH, int W, bool EAGER = false, bool CSPLIT = false, bool LTSM = false>
 __global__ __launch_bounds__(64 * W)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (W == 4 ? (EAGER ? 4 : Q == 3 ? 7 : 8) : W == 1 || (EAGER && Q == 3) ? 4 : (EAGER || CSPLIT ? 5 : 6))
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (W == 4 ? (EAGER ? 5 : Q == 3 ? 7 : 8) : W == 1 || (EAGER && Q == 3) ? 4 : (EAGER || CSPLIT ? 5 : 6))
                                                    : (W == 4 ? (EAGER ? 2 : 4) : W == 1 || EAGER || CSPLIT ? 2 : 3), 8)))
 void k_stage_mfma(StageArgs args, int64_t per) {
     using MD = MfmaDim<Q>;
@@ -868,30 +868,32 @@ void k_stage_mfma(StageArgs args, int64_t per) {
     constexpr int PV = 16 / (int)sizeof(T);  // values per 16-byte group
     const int nvv = ne * 6 * NP / PV;        // 16-byte groups of the chunk (6 NP ne is a multiple of 4)
 
-    // ---- staging: chunk fields, geometry, connectivity, face-node tables
-    const uint32_t keep = a.imask ? (a.imask[blk] ^ (a.imask_inv ? 0xffffffffu : 0u)) : 0xffffffffu;
-    {
-        ChunkIn<T, Q, NTH> in;
-        in.fetch(Y, (const T*)a.geo, a.conn, e0, ne, tid);
-        for (int v = tid; v < NB * KF * Sh::FS; v += NTH) sh.sF[v] = T(0);
-        in.put(sh.sY, sh.sG, sh.sC, sh.sT, ne, tid, keep);
-    }
-
-    // matrix fragments (coalesced: fragment-major, lane-minor)
+    // matrix fragments (coalesced: fragment-major, lane-minor); lift
+    // fragments one face at a time, requested one face ahead
     const T* fr = frags<T>() + frag_off(Q);
     T afV[MW][KSV], afL[MW][KSF], afN[MW][KSF];
-#pragma unroll
-    for (int mt = 0; mt < MW; ++mt)
-#pragma unroll
-        for (int ks = 0; ks < KSV; ++ks) afV[mt][ks] = fr[((mt + mt0) * KSV + ks) * 64 + lane];
-    // lift fragments of one face at a time, requested one face ahead
     auto lift_frags = [&](int f, T (&d)[MW][KSF]) {
 #pragma unroll
         for (int mt = 0; mt < MW; ++mt)
 #pragma unroll
             for (int ks = 0; ks < KSF; ++ks) d[mt][ks] = fr[(MT * KSV + (f * MT + mt + mt0) * KSF + ks) * 64 + lane];
     };
-    lift_frags(0, afL);
+
+    // ---- staging: chunk fields, geometry, connectivity, face-node tables;
+    // the volume and face-0 lift fragments are requested right behind the
+    // chunk's loads, so their latency hides behind the staging wait
+    const uint32_t keep = a.imask ? (a.imask[blk] ^ (a.imask_inv ? 0xffffffffu : 0u)) : 0xffffffffu;
+    {
+        ChunkIn<T, Q, NTH> in;
+        in.fetch(Y, (const T*)a.geo, a.conn, e0, ne, tid);
+#pragma unroll
+        for (int mt = 0; mt < MW; ++mt)
+#pragma unroll
+            for (int ks = 0; ks < KSV; ++ks) afV[mt][ks] = fr[((mt + mt0) * KSV + ks) * 64 + lane];
+        lift_frags(0, afL);
+        for (int v = tid; v < NB * KF * Sh::FS; v += NTH) sh.sF[v] = T(0);
+        in.put(sh.sY, sh.sG, sh.sC, sh.sT, ne, tid, keep);
+    }
     __syncthreads();
 
     // face 0's neighbour traces (EAGER: every face's) in flight during the volume product
