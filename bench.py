@@ -90,24 +90,24 @@ def parse():
 # 48000-tet P3 FP32 problem, with the scales a 1 GiB copy gives each counter;
 # valid only for the kernel source they were taken on (SHA-256 below).
 MEASURED_TRAFFIC = [
-    {"kernels_sha256": "e3f11409ed4d0fba0e169ae78fdcfcc2cf1360bfc91b93e0dc41f0e050b95388",
+    {"kernels_sha256": "95f2693eedc0bcfb1df99161361c7df1cf804e6b22fdb00f46db1035fc9af466",
      "kernel": "k_stage_mfma<float,3,true,false,2,false,true>", "K": 48000,
-     "fetch_kib": 41470.71, "fetch_scale": 2.0000, "write_kib": 42200.96, "write_scale": 1.0000},
-    {"kernels_sha256": "e3f11409ed4d0fba0e169ae78fdcfcc2cf1360bfc91b93e0dc41f0e050b95388",
+     "fetch_kib": 41696.72, "fetch_scale": 2.0000, "write_kib": 42197.84, "write_scale": 1.0000},
+    {"kernels_sha256": "95f2693eedc0bcfb1df99161361c7df1cf804e6b22fdb00f46db1035fc9af466",
      "kernel": "k_stage_mfma<float,3,true,false,4>", "K": 48000,
-     "fetch_kib": 40964.72, "fetch_scale": 2.0000, "write_kib": 42187.63, "write_scale": 1.0000},
+     "fetch_kib": 41006.57, "fetch_scale": 2.0000, "write_kib": 42187.65, "write_scale": 1.0000},
 ]
 
 
 # The same for the FP64 stage kernel of the plain FP64 solve (48000 tets, P3):
 # the two forms its autotuner keeps (two and four waves per block).
 MEASURED_TRAFFIC_FP64 = [
-    {"kernels_sha256": "e3f11409ed4d0fba0e169ae78fdcfcc2cf1360bfc91b93e0dc41f0e050b95388",
+    {"kernels_sha256": "95f2693eedc0bcfb1df99161361c7df1cf804e6b22fdb00f46db1035fc9af466",
      "kernel": "k_stage_mfma<double,3,true,false,2>", "K": 48000,
-     "fetch_kib": 80986.21, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000},
-    {"kernels_sha256": "e3f11409ed4d0fba0e169ae78fdcfcc2cf1360bfc91b93e0dc41f0e050b95388",
+     "fetch_kib": 81060.19, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000},
+    {"kernels_sha256": "95f2693eedc0bcfb1df99161361c7df1cf804e6b22fdb00f46db1035fc9af466",
      "kernel": "k_stage_mfma<double,3,true,false,4>", "K": 48000,
-     "fetch_kib": 75569.25, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000},
+     "fetch_kib": 75600.09, "fetch_scale": 2.0000, "write_kib": 78750.00, "write_scale": 1.0000},
 ]
 
 
@@ -115,23 +115,23 @@ MEASURED_TRAFFIC_FP64 = [
 # 1,572,864-tet scatterer (variants 3 and 2, the two its autotuner keeps) and the
 # batched launch of 64 members on the 10368-tet mesh, every member active
 # (K = members x elements; every variant the batched autotuner times).
-_SHA_Q2 = "e3f11409ed4d0fba0e169ae78fdcfcc2cf1360bfc91b93e0dc41f0e050b95388"
+_SHA_Q2 = "95f2693eedc0bcfb1df99161361c7df1cf804e6b22fdb00f46db1035fc9af466"
 MEASURED_TRAFFIC_Q2 = [
     {"kernels_sha256": _SHA_Q2, "kernel": "k_stage_mfma<float,2,true,false,1>", "K": 1572864,
-     "fetch_kib": 827031.24, "fetch_scale": 2.0000, "write_kib": 696307.63, "write_scale": 1.0000},
+     "fetch_kib": 826087.99, "fetch_scale": 2.0000, "write_kib": 696403.27, "write_scale": 1.0000},
     {"kernels_sha256": _SHA_Q2, "kernel": "k_stage_mfma<float,2,false,false,1>", "K": 1572864,
-     "fetch_kib": 841317.55, "fetch_scale": 2.0000, "write_kib": 695818.02, "write_scale": 1.0000},
+     "fetch_kib": 841445.58, "fetch_scale": 2.0000, "write_kib": 696003.22, "write_scale": 1.0000},
 ] + [
     {"kernels_sha256": _SHA_Q2, "kernel": k, "K": 64 * 10368,
      "fetch_kib": fe, "fetch_scale": 2.0000, "write_kib": wr, "write_scale": 1.0000}
-    for k, fe, wr in (("k_stage_mfma<float,2,true,false,1>", 261893.38, 293125.06),
-                      ("k_stage_mfma<float,2,false,false,1>", 265729.02, 293008.64),
-                      ("k_stage<float,2,false,false>", 284604.15, 292229.89),
-                      ("k_stage<float,2,true,false>", 252912.04, 291676.09),
-                      ("k_stage_mfma<float,2,true,false,2>", 247348.47, 291745.09),
-                      ("k_stage_mfma<float,2,true,false,2,true>", 245738.03, 291615.28),
-                      ("k_stage_mfma<float,2,true,false,4>", 245655.99, 291602.90),
-                      ("k_stage_mfma<float,2,true,false,4,true>", 245623.47, 291600.15))
+    for k, fe, wr in (("k_stage_mfma<float,2,true,false,1>", 261308.21, 293151.86),
+                      ("k_stage_mfma<float,2,false,false,1>", 265477.60, 293033.53),
+                      ("k_stage<float,2,false,false>", 284333.38, 292218.74),
+                      ("k_stage<float,2,true,false>", 252748.48, 291670.07),
+                      ("k_stage_mfma<float,2,true,false,2>", 247271.13, 291747.63),
+                      ("k_stage_mfma<float,2,true,false,2,true>", 245780.23, 291612.83),
+                      ("k_stage_mfma<float,2,true,false,4>", 245653.31, 291603.04),
+                      ("k_stage_mfma<float,2,true,false,4,true>", 245600.44, 291600.09))
 ]
 
 
