@@ -137,9 +137,9 @@ MEASURED_TRAFFIC_Q2 = [
 
 # The same for the 2-D stage kernel on the 22500-triangle disk trap (P3, FP32).
 MEASURED_TRAFFIC_2D = {
-    "kernels_sha256": "2cfab2a02241355bb5ef28a6732137553b93d1adb24d0d1f204160b9cff12150",
+    "kernels_sha256": "1508066633297100c808dafdd5326a30258cc49e8afc20322d497f043203ccde",
     "kernel": "k_stage2d<float,3,true>", "K": 22500,
-    "fetch_kib": 5064.65, "fetch_scale": 2.0000, "write_kib": 4944.12, "write_scale": 1.0000,
+    "fetch_kib": 5064.66, "fetch_scale": 2.0000, "write_kib": 4944.12, "write_scale": 1.0000,
 }
 
 

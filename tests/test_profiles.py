@@ -86,3 +86,20 @@ def test_traffic_summary_matches_bench_table(name, table, K):
     for t in tables:
         assert sha == t["kernels_sha256"]
         assert rows[t["kernel"]] == (t["fetch_kib"], t["write_kib"])
+
+
+@pytest.mark.parametrize("table,source", [
+    (bench.MEASURED_TRAFFIC, "kernels.hip"),
+    (bench.MEASURED_TRAFFIC_FP64, "kernels.hip"),
+    (bench.MEASURED_TRAFFIC_Q2, "kernels.hip"),
+    (bench.MEASURED_TRAFFIC_2D, "kernels2d.hip"),
+])
+def test_traffic_tables_match_the_current_kernel_source(table, source):
+    """Every counter table belongs to the kernel source in the tree: a table
+    left behind by a change of the source would make bench.py report no
+    traffic (it checks the same digest at run time)."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2106_02858_amd", "csrc", source)
+    digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
+    for t in (table if isinstance(table, list) else [table]):
+        assert t["kernels_sha256"] == digest, (source, t["kernel"])
