@@ -15,9 +15,10 @@ exact data G, tests/_manufactured.py).
   magnetic part, or the 1/eps scaling of j (dropped or replaced by 1/mu)
   each break the pin.
 
-The mesh levels are independent solves; they run in worker processes (each
-started fresh, single-threaded BLAS; a planted mistake is made inside the
-worker that computes with it).
+The mesh levels are independent solves; they run in worker processes
+(spawned, single-threaded BLAS; a planted mistake is made inside the worker
+that computes with it, after restoring the oracle's own functions, since a
+pool reuses its workers for several jobs).
 """
 import concurrent.futures as cf
 import dataclasses
@@ -48,10 +49,17 @@ def orders(ns, errs):
     return slope, last
 
 
+# the oracle functions a planted mistake replaces, as imported (a spawned
+# worker imports this module afresh)
+_ORIGINAL = {"_boundary_source": dg._boundary_source, "source": dg.source}
+
+
 def _level(job):
     """(FS error, filtered CMCG error or None, final CG residual) on one mesh,
     with the named planted mistake (or none) in this worker's oracle."""
     q, n, with_cmcg, mutation = job
+    for name, fn in _ORIGINAL.items():  # undo the mistake of this worker's previous job
+        setattr(dg, name, fn)
     if mutation:
         MUTATIONS[mutation](_Patch())
     p, ex = problem(n, q)
@@ -63,7 +71,7 @@ def _level(job):
 
 
 class _Patch:
-    """setattr for a worker process, which exits afterwards."""
+    """setattr in a worker process (undone by its next job)."""
 
     @staticmethod
     def setattr(obj, name, value):
