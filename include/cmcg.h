@@ -487,6 +487,8 @@ int cmcg_engine_collect_batch(cmcg_engine* e, int slot, cmcg_result** results, i
  * (q, precision) fall back to 0; -1 chooses per launch from its size
  * (workgroups of 10 elements over all members), the form the autotuner's
  * timings favour there.  All compute the same Phi(t, Y) and stage update.
+ * Local time stepping's substep launches (restricted to the element blocks
+ * near the fine region) take the four-wave form whatever the choice.
  * Defaults: -1 for q = 2, 3, 0 for q = 1.  Process-wide;
  * not thread-safe against concurrent solves.  Returns CMCG_ERR_ARG for an unknown q / precision /
  * variant.  cmcg_tune_get_stage reports the current choice (possibly -1);
