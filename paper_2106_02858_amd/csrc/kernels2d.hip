@@ -196,29 +196,54 @@ __global__ __launch_bounds__(64) void k_stage2d(StageArgs args, int64_t per) {
     const T* __restrict__ Y = (const T*)a.Y;
     const T* __restrict__ geo = (const T*)a.geo;
     {
-        const int nv = ne * 3 * NP;
-        const T* src = Y + e0 * 3 * NP;
-        if constexpr (Row2<T, NP>::V2) {  // the chunk starts on a pair boundary and holds whole pairs
-            using P2 = typename Row2<T, NP>::P2;
-            const P2* s2 = reinterpret_cast<const P2*>(src);
-            P2* d2 = reinterpret_cast<P2*>(sY);
-            for (int v = lane; v < nv / 2; v += 64) d2[v] = s2[v];
-        } else {
-            for (int v = lane; v < nv; v += 64) sY[v] = src[v];
-        }
-        const int ng = ne * kGeo2;
-        if constexpr (sizeof(T) == 4) {  // records of 28 values: 7 x 16 bytes each
-            const float4* g4 = reinterpret_cast<const float4*>(geo + e0 * kGeo2);
-            float4* d4 = reinterpret_cast<float4*>(sG);
-            for (int v = lane; v < ng / 4; v += 64) d4[v] = g4[v];
-        } else {  // 14 x 16 bytes
-            const double2* g2 = reinterpret_cast<const double2*>(geo + e0 * kGeo2);
-            double2* d2 = reinterpret_cast<double2*>(sG);
-            for (int v = lane; v < ng / 2; v += 64) d2[v] = g2[v];
-        }
-        for (int v = lane; v < ne * 3; v += 64) sC[v] = a.conn[e0 * 3 + v];
+        // every staging load is issued before the first is consumed (loops of
+        // a compile-time trip count; a loop that stored each value as it
+        // arrived waited for one load at a time), then written to LDS.  The
+        // stage input goes in pairs when the chunk starts on a pair boundary
+        // and holds whole pairs, the geometry records (28 values) in 16-byte
+        // groups.
+        constexpr int PV = Row2<T, NP>::V2 ? 2 : 1;
+        constexpr int GV = 16 / (int)sizeof(T);
+        // native vectors: arrays of them stay in registers
+        typedef T VY __attribute__((ext_vector_type(PV)));
+        typedef T VG __attribute__((ext_vector_type(GV)));
+        static_assert(kGeo2 % GV == 0, "geometry records split into 16-byte groups");
+        constexpr int NYL = (EPB * 3 * NP / PV + 63) / 64, NGL = (EPB * kGeo2 / GV + 63) / 64;
+        constexpr int NML = (NM + 63) / 64, NCL = (EPB * 3 + 63) / 64;
+        const int nyl = ne * 3 * NP / PV, ngl = ne * kGeo2 / GV;
+        const VY* ys = reinterpret_cast<const VY*>(Y + e0 * 3 * NP);
+        const VG* gs = reinterpret_cast<const VG*>(geo + e0 * kGeo2);
         const T* gm = mats2<T>() + mat2_off(Q);
-        for (int v = lane; v < NM; v += 64) sM[v] = gm[v];
+        VY ry[NYL];
+        VG rg[NGL];
+        T rm[NML];
+        int rc[NCL];
+#pragma unroll
+        for (int i = 0; i < NYL; ++i)
+            if (lane + 64 * i < nyl) ry[i] = ys[lane + 64 * i];
+#pragma unroll
+        for (int i = 0; i < NGL; ++i)
+            if (lane + 64 * i < ngl) rg[i] = gs[lane + 64 * i];
+#pragma unroll
+        for (int i = 0; i < NCL; ++i)
+            if (lane + 64 * i < ne * 3) rc[i] = a.conn[e0 * 3 + lane + 64 * i];
+#pragma unroll
+        for (int i = 0; i < NML; ++i)
+            if (lane + 64 * i < NM) rm[i] = gm[lane + 64 * i];
+        VY* yd = reinterpret_cast<VY*>(sY);
+        VG* gd = reinterpret_cast<VG*>(sG);
+#pragma unroll
+        for (int i = 0; i < NYL; ++i)
+            if (lane + 64 * i < nyl) yd[lane + 64 * i] = ry[i];
+#pragma unroll
+        for (int i = 0; i < NGL; ++i)
+            if (lane + 64 * i < ngl) gd[lane + 64 * i] = rg[i];
+#pragma unroll
+        for (int i = 0; i < NCL; ++i)
+            if (lane + 64 * i < ne * 3) sC[lane + 64 * i] = rc[i];
+#pragma unroll
+        for (int i = 0; i < NML; ++i)
+            if (lane + 64 * i < NM) sM[lane + 64 * i] = rm[i];
     }
     __syncthreads();
 
